@@ -1,0 +1,186 @@
+/*
+ * mbkk.h - C ABI of the MI355X (gfx950) library for truncated mini-batch
+ * kernel k-means (Jourdan & Schwartzman, "Mini-batch kernel k-means",
+ * ICLR 2025).
+ *
+ * The library runs the per-iteration hot path of the paper's Algorithm 2 on
+ * one GPU: batch-to-center distances in feature space by the kernel trick
+ * (Section 1, "Lloyd's algorithm in feature space"; Section 4), argmin
+ * assignment, the learning-rate update of the implicit centers and their
+ * truncation to a window of recent batches (Section 4.1, Eq. 1 and the
+ * unrolled recursion before it; sliding-window footnote).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named *_dev are device pointers (HIP / torch CUDA tensors on the
+ *    ROCm build); pointers named *_host are host pointers.  Device arrays are
+ *    dense, row-major, caller-owned; the library never frees them.
+ *  - All GPU work is enqueued on the stream given to mbkk_create, in stream
+ *    order.  Calls that write a *_host output synchronise that stream.
+ *  - Return value: MBKK_OK (0) or a negative MBKK_E_* code; no C++ exception
+ *    crosses the ABI.  mbkk_last_error() gives a message for the context (or
+ *    for the last failed mbkk_create when called with NULL).
+ *  - A context is not thread-safe; calls on one context must be serialised.
+ *  - Index arrays are int32 row numbers of X in [0, n).  Out-of-range indices
+ *    are never dereferenced: the row is read as zeros, and when
+ *    config.validate is non-zero the call returns MBKK_E_INDEX (this check
+ *    synchronises the stream).
+ */
+#ifndef MBKK_H
+#define MBKK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Return codes. */
+#define MBKK_OK 0
+#define MBKK_E_INVALID (-1)    /* bad argument or configuration            */
+#define MBKK_E_STATE (-2)      /* call out of order (e.g. step before init) */
+#define MBKK_E_WORKSPACE (-3)  /* workspace missing, too small or misaligned */
+#define MBKK_E_HIP (-4)        /* a HIP runtime call failed                  */
+#define MBKK_E_INDEX (-5)      /* index outside [0, n) (validate only)       */
+#define MBKK_E_NONFINITE (-6)  /* NaN/Inf in gathered rows (validate only)   */
+
+/* Kernel functions K(x, y) (the paper's K; kernel_param is its bandwidth).
+ * GAUSS  : exp(-||x-y||_2^2 / kappa), kernel_param = kappa   (Section 6)
+ * LAPLACE: exp(-||x-y||_1  / sigma), kernel_param = sigma    (abstract)
+ * LINEAR : <x, y>                                             (test kernel)
+ * POLY2  : (<x, y> + c)^2,            kernel_param = c        (test kernel) */
+#define MBKK_GAUSS 0
+#define MBKK_LAPLACE 1
+#define MBKK_LINEAR 2
+#define MBKK_POLY2 3
+
+/* Arithmetic of the cross term <phi(x), C_j>.
+ * FP32  : FP32 kernel values.  Gaussian via ||x||^2 + ||y||^2 - 2 x.y with x.y
+ *         on FP32 MFMA (or direct VALU when cross_impl = DIRECT); the other
+ *         kernels on the VALU.
+ * FP64  : every kernel value and sum in FP64 (VALU).
+ * BF16X3: Gaussian only; x.y on BF16 MFMA as the compensated split product
+ *         hi.hi + hi.lo + lo.hi with FP32 accumulation, norms and the exp
+ *         argument in FP32; rows whose two best distances are closer than
+ *         tie_delta are re-scored in FP64.
+ * BF16X1: as BF16X3 with the single product hi.hi (information only). */
+#define MBKK_FP32 0
+#define MBKK_FP64 1
+#define MBKK_BF16X3 2
+#define MBKK_BF16X1 3
+
+/* Learning-rate rules alpha_i^j (b_i^j = |B_i^j|). */
+#define MBKK_LR_BETA 0     /* sqrt(b_i^j / b)           (Section 5)            */
+#define MBKK_LR_FULL 1     /* 1 if b_i^j > 0, else 0     (b = n gives Lloyd)    */
+#define MBKK_LR_SKLEARN 2  /* b_i^j / sum_{l<=i} b_l^j   (count rate, to 0)     */
+
+/* Cross-term implementation choice. */
+#define MBKK_CROSS_AUTO 0    /* MFMA for Gaussian FP32/BF16 when d >= 16, else direct */
+#define MBKK_CROSS_DIRECT 1  /* VALU kernel, any kernel and precision              */
+#define MBKK_CROSS_MFMA 2    /* MFMA kernel (Gaussian, FP32/BF16 only)             */
+
+typedef struct {
+    int64_t n;           /* rows of X                                            */
+    int32_t d;           /* columns of X                                         */
+    int32_t k;           /* number of centers, 1 <= k <= 65536, k <= n           */
+    int32_t b_max;       /* largest batch or index chunk, 1 <= b_max <= 8192     */
+    int32_t window;      /* W: a center keeps its last W batches, 1 <= W <= 30   */
+    int32_t kernel;      /* MBKK_GAUSS ...                                       */
+    double kernel_param; /* kappa / sigma / c; > 0 for GAUSS and LAPLACE         */
+    int32_t precision;   /* MBKK_FP32 ...                                        */
+    int32_t lr;          /* MBKK_LR_BETA ...                                     */
+    int32_t cross_impl;  /* MBKK_CROSS_AUTO ...                                  */
+    double tie_delta;    /* BF16 forms: FP64 re-scoring threshold; <= 0: 4e-3    */
+    int32_t validate;    /* non-zero: report bad indices / non-finite rows       */
+} mbkk_config;
+
+typedef struct mbkk_ctx mbkk_ctx;
+
+/* Host-side image of the iteration state (all arrays caller-allocated).
+ * Before iteration i the centers are C_i^j = coef[j][0] phi(x_{init_idx[j]})
+ * + sum over live ring slots r of coef[j][1+r] * sum_{p in slot r, center j}
+ * phi(x_p)   (Eq. 1: per-point weight alpha_l^j / b_l^j times the product of
+ * (1 - alpha) of the later iterations).  Slot r holds batch l with
+ * (l - 1) mod W = r; its points are grouped by center, center j occupying
+ * positions slot_off[r][j] .. slot_off[r][j+1]-1.  Slots live before
+ * iteration i: batches max(1, i-W) .. i-1; the initial term is live while
+ * i <= W + 1.  Coefficients of dead slots must be 0. */
+typedef struct {
+    int64_t iteration;  /* i, the index of the next batch (1 after init)    */
+    int32_t k, window, b_max;
+    int32_t *init_idx;  /* [k]                                               */
+    int32_t *slot_b;    /* [W] number of points held by slot r (0 = empty)   */
+    int32_t *slot_idx;  /* [W * b_max] point indices, grouped by center      */
+    int32_t *slot_off;  /* [W * (k + 1)] center offsets within each slot      */
+    double *coef;       /* [k * (W + 1)]                                     */
+    double *cum;        /* [k] running counts (sklearn rate)                 */
+} mbkk_state;
+
+/* Bytes of device workspace that mbkk_create needs for this configuration. */
+int mbkk_workspace_size(const mbkk_config *cfg, size_t *bytes);
+
+/* Creates a context.  workspace_dev: device buffer of at least
+ * mbkk_workspace_size bytes, 256-byte aligned, owned by the caller and kept
+ * alive until mbkk_destroy (all device state lives there; the library does
+ * not allocate device memory).  stream: a hipStream_t (NULL = default). */
+int mbkk_create(const mbkk_config *cfg, void *workspace_dev, size_t bytes, void *stream,
+                mbkk_ctx **out);
+int mbkk_destroy(mbkk_ctx *ctx);
+const char *mbkk_last_error(const mbkk_ctx *ctx);
+
+/* Borrows X_dev (n x d FP32, row stride ld >= d elements, 16-byte aligned
+ * rows when ld % 4 == 0) and caches ||x||^2 for every row.  X_dev must stay
+ * valid and unchanged for the lifetime of the context. */
+int mbkk_set_data(mbkk_ctx *ctx, const float *X_dev, int64_t ld);
+
+/* Initial centers C_1^j = phi(x_{idx[j]}), single points, hence convex
+ * combinations of X as Algorithm 1 requires.  idx_dev: [k] device int32.
+ * Resets the iteration counter to 1. */
+int mbkk_init_centers(mbkk_ctx *ctx, const int32_t *idx_dev);
+
+/* Kernel k-means++ seeding (Section 1: "kernel version of k-means++"), all
+ * on the device in FP64: first pick floor(u[0] n); pick r is the first row p
+ * whose running sum of D2 exceeds u[r] * sum D2, D2(p) = min over chosen c of
+ * K(p,p) - 2K(p,c) + K(c,c).  u_host: [k] uniforms in [0,1).  Writes the picks
+ * to idx_out_dev ([k] int32, may be NULL) and initialises the centers. */
+int mbkk_init_kmeanspp(mbkk_ctx *ctx, const double *u_host, int32_t *idx_out_dev);
+
+/* One iteration of Algorithm 2 on the batch tuple B_i = batch_dev[0..b-1]
+ * (indices, duplicates allowed, 1 <= b <= b_max): distances to C_i, argmin
+ * (lowest center index on ties), counts b_i^j, learning rates, update and
+ * truncation of the centers.  Optional outputs: labels_dev [b] int32,
+ * mind_dev [b] FP32 (distance to the assigned center), fbefore_host (the
+ * batch objective f_{B_i}(C_i), synchronises). */
+int mbkk_step(mbkk_ctx *ctx, const int32_t *batch_dev, int32_t b, int32_t *labels_dev,
+              float *mind_dev, double *fbefore_host);
+
+/* Assignment of m points (any m >= 0, processed in chunks of b_max) to the
+ * current centers, no state change.  Outputs (each may be NULL): labels_dev
+ * [m] int32, mind_dev [m] FP32, margin_dev [m] FP32 (second smallest minus
+ * smallest distance), D_dev [m * k] FP64 (all distances, row-major). */
+int mbkk_assign(mbkk_ctx *ctx, const int32_t *idx_dev, int64_t m, int32_t *labels_dev,
+                float *mind_dev, float *margin_dev, double *D_dev);
+
+/* f_A(C) = (1/m) sum_{x in A} min_j ||phi(x) - C_j||^2 (Section 3) for the m
+ * points idx_dev[0..m-1]; synchronises. */
+int mbkk_objective(mbkk_ctx *ctx, const int32_t *idx_dev, int64_t m, double *out_host);
+
+/* Copies the iteration state to / from host memory (checkpoint, resume,
+ * lock-step comparison).  set_state recomputes the center Gram blocks. */
+int mbkk_get_state(mbkk_ctx *ctx, mbkk_state *out_host);
+int mbkk_set_state(mbkk_ctx *ctx, const mbkk_state *in_host);
+
+/* Self norms <C_j, C_j> of the current centers (FP64, accumulated from the
+ * Gram blocks), N_host [k]; synchronises. */
+int mbkk_center_norms(mbkk_ctx *ctx, double *N_host);
+
+/* Accumulated device time of the cross-term kernel (the dominant kernel) in
+ * milliseconds and the number of launches since the last reset, measured
+ * with HIP events on the context's stream when timing is enabled. */
+int mbkk_set_timing(mbkk_ctx *ctx, int32_t enable);
+int mbkk_get_timing(mbkk_ctx *ctx, double *ms_host, int64_t *launches_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBKK_H */

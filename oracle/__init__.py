@@ -62,6 +62,7 @@ def lib():
         L.orc_update.argtypes = [P, P, I32, P, P, P]
         L.orc_iteration.restype = I64
         L.orc_iteration.argtypes = [P]
+        L.orc_cum.argtypes = [P, P]
         L.orc_state_size.argtypes = [P, P, P]
         L.orc_state_export.argtypes = [P, P, P, P, P, P]
         L.orc_kmeanspp.restype = C.c_int
@@ -209,8 +210,10 @@ class Oracle:
         tn = np.empty(nt.value, dtype=np.int32)
         pts = np.empty(max(ne.value, 1), dtype=np.int32)
         L.orc_state_export(self._m, _p(tc), _p(tt), _p(tw), _p(tn), _p(pts))
+        cum = np.empty(self.k, dtype=np.float64)
+        L.orc_cum(self._m, _p(cum))
         return dict(iteration=self.iteration, term_center=tc, term_tag=tt, term_coef=tw,
-                    term_npts=tn, points=pts[: ne.value])
+                    term_npts=tn, points=pts[: ne.value], cum=cum)
 
     def center_entries(self):
         """Flattened (center, point, coefficient) entries of the current centers."""

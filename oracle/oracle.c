@@ -458,6 +458,12 @@ int orc_step(orc_model *m, const int32_t *batch, int32_t b, int32_t *labels_out,
 
 int64_t orc_iteration(const orc_model *m) { return m->iter; }
 
+/* Running per-center counts used by the count-based (sklearn) rate. */
+void orc_cum(const orc_model *m, double *out)
+{
+    memcpy(out, m->cum, sizeof(double) * (size_t)m->k);
+}
+
 /* Number of terms and of (term, point) entries, to size the export arrays. */
 void orc_state_size(const orc_model *m, int64_t *nterms, int64_t *nentries)
 {

@@ -1,0 +1,42 @@
+// Launch helpers of the mbkk kernels (internal).
+#pragma once
+
+#include "mbkk_internal.h"
+
+namespace mbkk {
+
+void launch_row_sqnorm(const float *X, int64_t n, int d, int64_t ld, float *sqn, hipStream_t st);
+void launch_gather_rows(const float *X, int64_t n, int d, int64_t ld, const int32_t *idx, int64_t cnt,
+                        int dp, float *out32, uint16_t *outhi, uint16_t *outlo, float *outsq,
+                        double *outsq64, int32_t *idx_copy, int32_t *flags, int check_finite,
+                        hipStream_t st);
+void launch_init_state(int k, int W, int kind, double param, int d, int dp, const float *pool32,
+                       double *coef, double *cum, double *G, int fp64, hipStream_t st);
+void launch_support_fill(const Layout &L, const Buffers &B, const SlotList &live, int init_alive,
+                         int pad, hipStream_t st);
+void launch_chunks(const Layout &L, const Buffers &B, int r, hipStream_t st);
+void launch_update(const Layout &L, const Buffers &B, int b, int r_new, int init_alive_before,
+                   int init_keep, const SlotList &live, int lr, hipStream_t st);
+void launch_slot_copy(const Layout &L, const Buffers &B, int b, int r, hipStream_t st);
+void launch_pool_slot_from_X(const Layout &L, const Buffers &B, int r, int cnt, hipStream_t st);
+void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param,
+                 int fp64, hipStream_t st);
+void launch_gram_fold(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, hipStream_t st);
+
+// Cross term P = <phi(x), C_j> for the staged batch rows [0, nb).
+void launch_cross_direct(const Layout &L, const Buffers &B, int nb, int kind, double param, int fp64,
+                         hipStream_t st);
+void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision, double kappa,
+                       hipStream_t st);
+// Distances, argmin, margin (and optionally every distance) of rows [0, nb).
+void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double param, int fp64, int mfma,
+                  double *D_out, int64_t ldD, hipStream_t st);
+void launch_rescore(const Layout &L, const Buffers &B, int nb, int kind, double param, double delta,
+                    hipStream_t st);
+void launch_sum_mind(const Buffers &B, int nb, int accumulate, hipStream_t st);
+
+// k-means++
+void launch_kpp_self(const Layout &L, const Buffers &B, int kind, double param, hipStream_t st);
+void launch_kpp_round(const Layout &L, const Buffers &B, int r, int kind, double param, hipStream_t st);
+
+}  // namespace mbkk

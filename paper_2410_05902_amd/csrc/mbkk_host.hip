@@ -1,0 +1,727 @@
+// Host side of the mbkk C ABI: workspace layout, context, and the order of
+// launches for one iteration of Algorithm 2 (truncated mini-batch kernel
+// k-means).  Every device buffer lives in the caller's workspace; the library
+// allocates no device memory.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace mbkk;
+
+struct mbkk_ctx {
+    mbkk_config cfg;
+    Layout L;
+    Buffers B;
+    hipStream_t stream = nullptr;
+    bool use_mfma = false;
+    bool fp64 = false;
+    bool data_set = false;
+    bool inited = false;
+    int64_t iter = 1;           // index i of the next batch
+    int pending_r = -1;         // ring slot whose Gram partials still have to be folded
+    uint32_t pending_mask = 0;  // their live columns
+    int64_t support_iter = -1;  // iteration for which the support layout is built
+    std::vector<int32_t> slot_b;  // points held by each ring slot
+    // timing of the cross-term kernel
+    bool timing = false;
+    std::vector<hipEvent_t> ev;  // pairs (start, stop)
+    size_t ev_used = 0;
+    double ms_acc = 0.0;
+    int64_t launches = 0;
+    std::string err;
+};
+
+static std::string g_err;
+
+static int fail(mbkk_ctx *c, int code, const std::string &msg)
+{
+    if (c)
+        c->err = msg;
+    else
+        g_err = msg;
+    return code;
+}
+
+#define HIPCHK(c, call)                                                                            \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail((c), MBKK_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+namespace mbkk {
+
+static size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+static bool wants_mfma(const mbkk_config &c)
+{
+    if (c.cross_impl == MBKK_CROSS_MFMA)
+        return true;
+    if (c.cross_impl == MBKK_CROSS_DIRECT)
+        return false;
+    if (c.precision == MBKK_BF16X3 || c.precision == MBKK_BF16X1)
+        return true;
+    return c.kernel == MBKK_GAUSS && c.precision == MBKK_FP32 && c.d >= 16;
+}
+
+Layout make_layout(const mbkk_config &c)
+{
+    Layout L;
+    L.n = c.n;
+    L.d = c.d;
+    L.dp = (int)up((size_t)c.d, kDimAlign);
+    L.k = c.k;
+    L.W = c.window;
+    L.bmax = c.b_max;
+    L.pad = wants_mfma(c) ? kMfmaPad : 1;
+    L.bf16 = c.precision == MBKK_BF16X3 || c.precision == MBKK_BF16X1;
+    L.PR = (int64_t)c.k + (int64_t)c.window * c.b_max;
+    L.Mcap = (int64_t)up((size_t)(L.PR + (int64_t)c.k * (L.pad - 1) + L.pad), 128);
+    L.nblk = L.Mcap / 32;
+    // Gram work items stage their rows in LDS: at most 48 KB of FP32 rows
+    L.gram_rows = (int)(12288 / L.dp);
+    L.gram_rows = L.gram_rows < 1 ? 1 : (L.gram_rows > kGramRowsMax ? kGramRowsMax : L.gram_rows);
+    L.maxchunks = c.b_max / L.gram_rows + c.k + 1;
+    L.kpp_blocks = (c.n + 255) / 256;
+    return L;
+}
+
+// Carves the workspace; with base == nullptr only sizes it (L.bytes).
+void carve(const Layout &Lc, char *base, Buffers &B)
+{
+    Layout &L = const_cast<Layout &>(Lc);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        off = up(off, 256);
+        void *p = base ? base + off : nullptr;
+        off += bytes == 0 ? 1 : bytes;
+        return p;
+    };
+    const int64_t prows = L.PR + 1;
+    const int C = L.W + 1;
+    B.sqn = (float *)take(sizeof(float) * L.n);
+    B.pool32 = (float *)take(sizeof(float) * prows * L.dp);
+    B.poolhi = L.bf16 ? (uint16_t *)take(2 * prows * L.dp) : nullptr;
+    B.poollo = L.bf16 ? (uint16_t *)take(2 * prows * L.dp) : nullptr;
+    B.poolsq = (float *)take(sizeof(float) * prows);
+    B.poolsq64 = (double *)take(sizeof(double) * prows);
+    B.batidx = (int32_t *)take(4 * L.bmax);
+    B.bat32 = (float *)take(sizeof(float) * (size_t)L.bmax * L.dp);
+    B.bathi = L.bf16 ? (uint16_t *)take(2 * (size_t)L.bmax * L.dp) : nullptr;
+    B.batlo = L.bf16 ? (uint16_t *)take(2 * (size_t)L.bmax * L.dp) : nullptr;
+    B.batsq = (float *)take(sizeof(float) * L.bmax);
+    B.batsq64 = (double *)take(sizeof(double) * L.bmax);
+    B.ring_idx = (int32_t *)take(4 * (size_t)L.W * L.bmax);
+    B.ring_off = (int32_t *)take(4 * (size_t)L.W * (L.k + 1));
+    B.init_idx = (int32_t *)take(4 * (size_t)L.k);
+    B.coef = (double *)take(8 * (size_t)L.k * C);
+    B.cum = (double *)take(8 * (size_t)L.k);
+    B.G = (double *)take(8 * (size_t)L.k * C * C);
+    B.N = (double *)take(8 * (size_t)L.k);
+    B.counts = (int32_t *)take(4 * (size_t)L.k);
+    B.alpha = (double *)take(8 * (size_t)L.k);
+    B.chunk_j = (int32_t *)take(4 * L.maxchunks);
+    B.chunk_a0 = (int32_t *)take(4 * L.maxchunks);
+    B.chunk_a1 = (int32_t *)take(4 * L.maxchunks);
+    B.chunk_off = (int32_t *)take(4 * (size_t)(L.k + 1));
+    B.Gpart = (double *)take(8 * L.maxchunks * C);
+    B.seg_off = (int32_t *)take(4 * (size_t)(L.k + 1));
+    B.sup_row = (int32_t *)take(4 * L.Mcap);
+    B.sup_w = (float *)take(4 * L.Mcap);
+    B.sup_w64 = (double *)take(8 * L.Mcap);
+    B.blk_center = (int32_t *)take(4 * L.nblk);
+    size_t part_direct = (size_t)L.k * L.bmax * 8;  // FP64 worst case
+    size_t part_mfma = (size_t)L.nblk * L.bmax * 4;
+    B.part = take(part_direct > part_mfma ? part_direct : part_mfma);
+    B.labels = (int32_t *)take(4 * (size_t)L.bmax);
+    B.mind = (float *)take(4 * (size_t)L.bmax);
+    B.margin = (float *)take(4 * (size_t)L.bmax);
+    B.perm = (int32_t *)take(4 * (size_t)L.bmax);
+    B.obj = (double *)take(8 * 4);
+    B.flags = (int32_t *)take(4 * 4);
+    B.nchunks = (int32_t *)take(4);
+    B.D2 = (double *)take(8 * (size_t)L.n);
+    B.kself = (double *)take(8 * (size_t)L.n);
+    B.bsum = (double *)take(8 * (size_t)L.kpp_blocks);
+    B.picks = (int32_t *)take(4 * (size_t)L.k);
+    B.u = (double *)take(8 * (size_t)L.k);
+    L.bytes = up(off, 256);
+}
+
+}  // namespace mbkk
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+static int check_config(const mbkk_config *c, std::string &why)
+{
+    if (!c) {
+        why = "config is NULL";
+        return MBKK_E_INVALID;
+    }
+    if (c->n <= 0 || c->d <= 0 || c->k <= 0 || c->k > 65536 || c->k > c->n) {
+        why = "need n > 0, d > 0, 0 < k <= min(n, 65536)";
+        return MBKK_E_INVALID;
+    }
+    if (c->n > 2147483647LL) {
+        why = "n must fit in int32 indices";
+        return MBKK_E_INVALID;
+    }
+    if (c->b_max <= 0 || c->b_max > kMaxBatch) {
+        why = "need 1 <= b_max <= 8192";
+        return MBKK_E_INVALID;
+    }
+    if (c->window < 1 || c->window > kMaxWindow) {
+        why = "need 1 <= window <= 30";
+        return MBKK_E_INVALID;
+    }
+    if (c->kernel < MBKK_GAUSS || c->kernel > MBKK_POLY2) {
+        why = "unknown kernel";
+        return MBKK_E_INVALID;
+    }
+    if ((c->kernel == MBKK_GAUSS || c->kernel == MBKK_LAPLACE) && !(c->kernel_param > 0.0)) {
+        why = "bandwidth must be > 0";
+        return MBKK_E_INVALID;
+    }
+    if (c->precision < MBKK_FP32 || c->precision > MBKK_BF16X1) {
+        why = "unknown precision";
+        return MBKK_E_INVALID;
+    }
+    if (c->lr < MBKK_LR_BETA || c->lr > MBKK_LR_SKLEARN) {
+        why = "unknown learning rate";
+        return MBKK_E_INVALID;
+    }
+    if (c->cross_impl < MBKK_CROSS_AUTO || c->cross_impl > MBKK_CROSS_MFMA) {
+        why = "unknown cross_impl";
+        return MBKK_E_INVALID;
+    }
+    const bool bf = c->precision == MBKK_BF16X3 || c->precision == MBKK_BF16X1;
+    if ((bf || c->cross_impl == MBKK_CROSS_MFMA) && c->kernel != MBKK_GAUSS) {
+        why = "the MFMA / BF16 forms exist for the Gaussian kernel only";
+        return MBKK_E_INVALID;
+    }
+    if (bf && c->cross_impl == MBKK_CROSS_DIRECT) {
+        why = "BF16 forms run on MFMA only";
+        return MBKK_E_INVALID;
+    }
+    if (c->cross_impl == MBKK_CROSS_MFMA && c->precision == MBKK_FP64) {
+        why = "no FP64 MFMA form";
+        return MBKK_E_INVALID;
+    }
+    return MBKK_OK;
+}
+
+// Live ring slots of the centers C_i (state before iteration i): batches
+// max(1, i-W) .. i-1, oldest first.
+static SlotList live_before(int64_t i, int W)
+{
+    SlotList s;
+    s.n = 0;
+    int64_t lo = i - W < 1 ? 1 : i - W;
+    for (int64_t l = lo; l <= i - 1; ++l)
+        s.r[s.n++] = (int)((l - 1) % W);
+    return s;
+}
+
+static uint32_t col_mask_of(const SlotList &s, bool init_alive)
+{
+    uint32_t m = init_alive ? 1u : 0u;
+    for (int q = 0; q < s.n; ++q)
+        m |= 1u << (1 + s.r[q]);
+    return m;
+}
+
+static int check_flags(mbkk_ctx *c)
+{
+    int32_t f[2] = {0, 0};
+    HIPCHK(c, hipMemcpyAsync(f, c->B.flags, sizeof(f), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (f[0])
+        return fail(c, MBKK_E_INDEX, "index outside [0, n)");
+    if (f[1])
+        return fail(c, MBKK_E_NONFINITE, "non-finite value in a gathered row");
+    return MBKK_OK;
+}
+
+static int clear_flags(mbkk_ctx *c)
+{
+    HIPCHK(c, hipMemsetAsync(c->B.flags, 0, 4 * sizeof(int32_t), c->stream));
+    return MBKK_OK;
+}
+
+static double tie_delta(const mbkk_config &c) { return c.tie_delta > 0.0 ? c.tie_delta : 4e-3; }
+
+// Gathers rows idx[0..cnt) of X into the batch staging buffers.
+static void stage_rows(mbkk_ctx *c, const int32_t *idx, int64_t cnt)
+{
+    const Layout &L = c->L;
+    Buffers &B = c->B;
+    launch_gather_rows(B.X, L.n, L.d, B.ld, idx, cnt, L.dp, B.bat32, L.bf16 ? B.bathi : nullptr,
+                       L.bf16 ? B.batlo : nullptr, B.batsq, B.batsq64, B.batidx, B.flags, c->cfg.validate,
+                       c->stream);
+}
+
+// Folds pending Gram partials and (re)builds the support of the current
+// centers C_i when needed.
+static void prepare_support(mbkk_ctx *c)
+{
+    const Layout &L = c->L;
+    if (c->pending_r >= 0) {
+        launch_gram_fold(L, c->B, c->pending_r, c->pending_mask, c->stream);
+        c->pending_r = -1;
+    }
+    if (c->support_iter != c->iter) {
+        SlotList live = live_before(c->iter, L.W);
+        const int init_alive = c->iter <= L.W + 1;
+        launch_support_fill(L, c->B, live, init_alive, L.pad, c->stream);
+        c->support_iter = c->iter;
+    }
+}
+
+static int cross_and_score(mbkk_ctx *c, int nb, double *D_out, int64_t ldD)
+{
+    const Layout &L = c->L;
+    const mbkk_config &cf = c->cfg;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        if (c->ev_used + 2 > c->ev.size()) {
+            for (int q = 0; q < 64; ++q) {
+                hipEvent_t e;
+                HIPCHK(c, hipEventCreate(&e));
+                c->ev.push_back(e);
+            }
+        }
+        e0 = c->ev[c->ev_used];
+        e1 = c->ev[c->ev_used + 1];
+        c->ev_used += 2;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+    }
+    if (c->use_mfma)
+        launch_cross_mfma(L, c->B, nb, cf.precision, cf.kernel_param, c->stream);
+    else
+        launch_cross_direct(L, c->B, nb, cf.kernel, cf.kernel_param, c->fp64, c->stream);
+    if (c->timing) {
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        c->launches++;
+    }
+    launch_score(L, c->B, nb, cf.kernel, cf.kernel_param, c->fp64, c->use_mfma, D_out, ldD, c->stream);
+    if (cf.precision == MBKK_BF16X3 || cf.precision == MBKK_BF16X1)
+        launch_rescore(L, c->B, nb, cf.kernel, cf.kernel_param, tie_delta(cf), c->stream);
+    HIPCHK(c, hipGetLastError());
+    return MBKK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int mbkk_workspace_size(const mbkk_config *cfg, size_t *bytes)
+{
+    std::string why;
+    int rc = check_config(cfg, why);
+    if (rc)
+        return fail(nullptr, rc, why);
+    if (!bytes)
+        return fail(nullptr, MBKK_E_INVALID, "bytes is NULL");
+    Layout L = make_layout(*cfg);
+    Buffers B;
+    carve(L, nullptr, B);
+    *bytes = L.bytes;
+    return MBKK_OK;
+}
+
+int mbkk_create(const mbkk_config *cfg, void *workspace, size_t bytes, void *stream, mbkk_ctx **out)
+{
+    std::string why;
+    int rc = check_config(cfg, why);
+    if (rc)
+        return fail(nullptr, rc, why);
+    if (!out)
+        return fail(nullptr, MBKK_E_INVALID, "out is NULL");
+    Layout L = make_layout(*cfg);
+    Buffers B;
+    carve(L, nullptr, B);
+    if (!workspace || bytes < L.bytes || ((uintptr_t)workspace & 255))
+        return fail(nullptr, MBKK_E_WORKSPACE, "workspace missing, smaller than mbkk_workspace_size or not 256-byte aligned");
+    mbkk_ctx *c = new mbkk_ctx();
+    c->cfg = *cfg;
+    c->L = L;
+    carve(c->L, (char *)workspace, c->B);
+    c->stream = (hipStream_t)stream;
+    c->use_mfma = wants_mfma(*cfg);
+    c->fp64 = cfg->precision == MBKK_FP64;
+    c->slot_b.assign(cfg->window, 0);
+    // zero row of the pool (segment padding target) and error flags
+    const int64_t zr = L.PR;
+    hipError_t e = hipMemsetAsync(c->B.pool32 + zr * L.dp, 0, sizeof(float) * L.dp, c->stream);
+    if (e == hipSuccess && L.bf16)
+        e = hipMemsetAsync(c->B.poolhi + zr * L.dp, 0, 2 * L.dp, c->stream);
+    if (e == hipSuccess && L.bf16)
+        e = hipMemsetAsync(c->B.poollo + zr * L.dp, 0, 2 * L.dp, c->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->B.poolsq + zr, 0, sizeof(float), c->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->B.poolsq64 + zr, 0, sizeof(double), c->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->B.flags, 0, 16, c->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->B.ring_off, 0, 4 * (size_t)L.W * (L.k + 1), c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(nullptr, MBKK_E_HIP, std::string("workspace init: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return MBKK_OK;
+}
+
+int mbkk_destroy(mbkk_ctx *c)
+{
+    if (!c)
+        return MBKK_OK;
+    for (hipEvent_t e : c->ev)
+        (void)hipEventDestroy(e);
+    delete c;
+    return MBKK_OK;
+}
+
+const char *mbkk_last_error(const mbkk_ctx *c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+int mbkk_set_data(mbkk_ctx *c, const float *X, int64_t ld)
+{
+    if (!c)
+        return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (!X || ld < c->cfg.d)
+        return fail(c, MBKK_E_INVALID, "X is NULL or ld < d");
+    c->B.X = X;
+    c->B.ld = ld;
+    launch_row_sqnorm(X, c->L.n, c->L.d, ld, c->B.sqn, c->stream);
+    HIPCHK(c, hipGetLastError());
+    c->data_set = true;
+    c->inited = false;
+    return MBKK_OK;
+}
+
+static int init_common(mbkk_ctx *c, const int32_t *idx_dev)
+{
+    const Layout &L = c->L;
+    Buffers &B = c->B;
+    if (c->cfg.validate && clear_flags(c))
+        return MBKK_E_HIP;
+    // pool rows [0, k) <- X[idx]
+    launch_gather_rows(B.X, L.n, L.d, B.ld, idx_dev, L.k, L.dp, B.pool32, L.bf16 ? B.poolhi : nullptr,
+                       L.bf16 ? B.poollo : nullptr, B.poolsq, B.poolsq64, B.init_idx, B.flags, c->cfg.validate,
+                       c->stream);
+    launch_init_state(L.k, L.W, c->cfg.kernel, c->cfg.kernel_param, L.d, L.dp, B.pool32, B.coef, B.cum, B.G,
+                      c->fp64, c->stream);
+    HIPCHK(c, hipMemsetAsync(B.ring_off, 0, 4 * (size_t)L.W * (L.k + 1), c->stream));
+    HIPCHK(c, hipGetLastError());
+    c->iter = 1;
+    c->pending_r = -1;
+    c->support_iter = -1;
+    std::fill(c->slot_b.begin(), c->slot_b.end(), 0);
+    if (c->cfg.validate) {
+        int rc = check_flags(c);
+        if (rc)
+            return rc;
+    }
+    c->inited = true;
+    return MBKK_OK;
+}
+
+int mbkk_init_centers(mbkk_ctx *c, const int32_t *idx_dev)
+{
+    if (!c)
+        return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (!c->data_set)
+        return fail(c, MBKK_E_STATE, "set_data first");
+    if (!idx_dev)
+        return fail(c, MBKK_E_INVALID, "idx is NULL");
+    return init_common(c, idx_dev);
+}
+
+int mbkk_init_kmeanspp(mbkk_ctx *c, const double *u_host, int32_t *idx_out_dev)
+{
+    if (!c)
+        return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (!c->data_set)
+        return fail(c, MBKK_E_STATE, "set_data first");
+    if (!u_host)
+        return fail(c, MBKK_E_INVALID, "u is NULL");
+    const Layout &L = c->L;
+    for (int r = 0; r < L.k; ++r)
+        if (!(u_host[r] >= 0.0 && u_host[r] < 1.0))
+            return fail(c, MBKK_E_INVALID, "uniforms must lie in [0, 1)");
+    HIPCHK(c, hipMemcpyAsync(c->B.u, u_host, sizeof(double) * L.k, hipMemcpyHostToDevice, c->stream));
+    launch_kpp_self(L, c->B, c->cfg.kernel, c->cfg.kernel_param, c->stream);
+    for (int r = 0; r < L.k; ++r)
+        launch_kpp_round(L, c->B, r, c->cfg.kernel, c->cfg.kernel_param, c->stream);
+    HIPCHK(c, hipGetLastError());
+    if (idx_out_dev)
+        HIPCHK(c, hipMemcpyAsync(idx_out_dev, c->B.picks, 4 * (size_t)L.k, hipMemcpyDeviceToDevice, c->stream));
+    return init_common(c, c->B.picks);
+}
+
+int mbkk_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels_dev, float *mind_dev,
+              double *fbefore_host)
+{
+    if (!c)
+        return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (!c->inited)
+        return fail(c, MBKK_E_STATE, "init_centers / init_kmeanspp first");
+    if (!batch || b <= 0 || b > c->L.bmax)
+        return fail(c, MBKK_E_INVALID, "need a batch with 1 <= b <= b_max");
+    const Layout &L = c->L;
+    Buffers &B = c->B;
+    const int64_t i = c->iter;
+    const int W = L.W;
+    if (c->cfg.validate && clear_flags(c))
+        return MBKK_E_HIP;
+    stage_rows(c, batch, b);
+    prepare_support(c);
+    int rc = cross_and_score(c, b, nullptr, 0);
+    if (rc)
+        return rc;
+    // update of the centers
+    const SlotList live = live_before(i, W);
+    const int init_alive_before = i <= W + 1;
+    const int init_keep = i <= W;
+    const int r_new = (int)((i - 1) % W);
+    launch_update(L, B, b, r_new, init_alive_before, init_keep, live, c->cfg.lr, c->stream);
+    launch_slot_copy(L, B, b, r_new, c->stream);
+    const SlotList live_after = live_before(i + 1, W);
+    const uint32_t mask = col_mask_of(live_after, init_keep);
+    launch_gram(L, B, r_new, mask, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->stream);
+    HIPCHK(c, hipGetLastError());
+    c->pending_r = r_new;
+    c->pending_mask = mask;
+    c->slot_b[r_new] = b;
+    c->iter = i + 1;
+    if (labels_dev)
+        HIPCHK(c, hipMemcpyAsync(labels_dev, B.labels, 4 * (size_t)b, hipMemcpyDeviceToDevice, c->stream));
+    if (mind_dev)
+        HIPCHK(c, hipMemcpyAsync(mind_dev, B.mind, 4 * (size_t)b, hipMemcpyDeviceToDevice, c->stream));
+    if (fbefore_host) {
+        double s = 0.0;
+        HIPCHK(c, hipMemcpyAsync(&s, B.obj, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *fbefore_host = s / (double)b;
+    }
+    if (c->cfg.validate)
+        return check_flags(c);
+    return MBKK_OK;
+}
+
+int mbkk_assign(mbkk_ctx *c, const int32_t *idx, int64_t m, int32_t *labels_dev, float *mind_dev,
+                float *margin_dev, double *D_dev)
+{
+    if (!c)
+        return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (!c->inited)
+        return fail(c, MBKK_E_STATE, "init_centers / init_kmeanspp first");
+    if (m < 0 || (m > 0 && !idx))
+        return fail(c, MBKK_E_INVALID, "bad index array");
+    const Layout &L = c->L;
+    Buffers &B = c->B;
+    if (c->cfg.validate && clear_flags(c))
+        return MBKK_E_HIP;
+    prepare_support(c);
+    for (int64_t m0 = 0; m0 < m; m0 += L.bmax) {
+        const int nb = (int)((m - m0) < L.bmax ? (m - m0) : L.bmax);
+        stage_rows(c, idx + m0, nb);
+        int rc = cross_and_score(c, nb, D_dev ? D_dev + m0 * L.k : nullptr, L.k);
+        if (rc)
+            return rc;
+        if (labels_dev)
+            HIPCHK(c, hipMemcpyAsync(labels_dev + m0, B.labels, 4 * (size_t)nb, hipMemcpyDeviceToDevice, c->stream));
+        if (mind_dev)
+            HIPCHK(c, hipMemcpyAsync(mind_dev + m0, B.mind, 4 * (size_t)nb, hipMemcpyDeviceToDevice, c->stream));
+        if (margin_dev)
+            HIPCHK(c, hipMemcpyAsync(margin_dev + m0, B.margin, 4 * (size_t)nb, hipMemcpyDeviceToDevice, c->stream));
+    }
+    if (c->cfg.validate)
+        return check_flags(c);
+    return MBKK_OK;
+}
+
+int mbkk_objective(mbkk_ctx *c, const int32_t *idx, int64_t m, double *out_host)
+{
+    if (!c)
+        return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (!c->inited)
+        return fail(c, MBKK_E_STATE, "init_centers / init_kmeanspp first");
+    if (m <= 0 || !idx || !out_host)
+        return fail(c, MBKK_E_INVALID, "need m > 0 indices and an output");
+    const Layout &L = c->L;
+    if (c->cfg.validate && clear_flags(c))
+        return MBKK_E_HIP;
+    prepare_support(c);
+    for (int64_t m0 = 0; m0 < m; m0 += L.bmax) {
+        const int nb = (int)((m - m0) < L.bmax ? (m - m0) : L.bmax);
+        stage_rows(c, idx + m0, nb);
+        int rc = cross_and_score(c, nb, nullptr, 0);
+        if (rc)
+            return rc;
+        launch_sum_mind(c->B, nb, m0 > 0, c->stream);
+    }
+    double s = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&s, c->B.obj + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *out_host = s / (double)m;
+    if (c->cfg.validate)
+        return check_flags(c);
+    return MBKK_OK;
+}
+
+int mbkk_center_norms(mbkk_ctx *c, double *N_host)
+{
+    if (!c)
+        return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (!c->inited)
+        return fail(c, MBKK_E_STATE, "init_centers / init_kmeanspp first");
+    if (!N_host)
+        return fail(c, MBKK_E_INVALID, "N is NULL");
+    prepare_support(c);
+    HIPCHK(c, hipMemcpyAsync(N_host, c->B.N, 8 * (size_t)c->L.k, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return MBKK_OK;
+}
+
+int mbkk_get_state(mbkk_ctx *c, mbkk_state *s)
+{
+    if (!c)
+        return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (!c->inited)
+        return fail(c, MBKK_E_STATE, "no state yet");
+    const Layout &L = c->L;
+    if (!s || s->k != L.k || s->window != L.W || s->b_max != L.bmax || !s->init_idx || !s->slot_b ||
+        !s->slot_idx || !s->slot_off || !s->coef || !s->cum)
+        return fail(c, MBKK_E_INVALID, "state buffers missing or shaped for another configuration");
+    const int C = L.W + 1;
+    s->iteration = c->iter;
+    for (int r = 0; r < L.W; ++r)
+        s->slot_b[r] = c->slot_b[r];
+    HIPCHK(c, hipMemcpyAsync(s->init_idx, c->B.init_idx, 4 * (size_t)L.k, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(s->slot_idx, c->B.ring_idx, 4 * (size_t)L.W * L.bmax, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(s->slot_off, c->B.ring_off, 4 * (size_t)L.W * (L.k + 1), hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipMemcpyAsync(s->coef, c->B.coef, 8 * (size_t)L.k * C, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(s->cum, c->B.cum, 8 * (size_t)L.k, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return MBKK_OK;
+}
+
+int mbkk_set_state(mbkk_ctx *c, const mbkk_state *s)
+{
+    if (!c)
+        return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (!c->data_set)
+        return fail(c, MBKK_E_STATE, "set_data first");
+    const Layout &L = c->L;
+    if (!s || s->k != L.k || s->window != L.W || s->b_max != L.bmax || !s->init_idx || !s->slot_b ||
+        !s->slot_idx || !s->slot_off || !s->coef || !s->cum || s->iteration < 1)
+        return fail(c, MBKK_E_INVALID, "state buffers missing or shaped for another configuration");
+    const int W = L.W, C = W + 1;
+    const int64_t i = s->iteration;
+    const SlotList live = live_before(i, W);
+    const bool init_alive = i <= W + 1;
+    // host-side validation of the slot contents
+    for (int q = 0; q < live.n; ++q) {
+        const int r = live.r[q];
+        const int32_t *off = s->slot_off + (int64_t)r * (L.k + 1);
+        if (s->slot_b[r] < 1 || s->slot_b[r] > L.bmax || off[0] != 0 || off[L.k] != s->slot_b[r])
+            return fail(c, MBKK_E_INVALID, "slot offsets inconsistent with slot sizes");
+        for (int j = 0; j < L.k; ++j)
+            if (off[j + 1] < off[j])
+                return fail(c, MBKK_E_INVALID, "slot offsets not monotone");
+        for (int p = 0; p < s->slot_b[r]; ++p) {
+            int32_t v = s->slot_idx[(int64_t)r * L.bmax + p];
+            if (v < 0 || v >= L.n)
+                return fail(c, MBKK_E_INDEX, "slot index outside [0, n)");
+        }
+    }
+    for (int j = 0; j < L.k; ++j)
+        if (s->init_idx[j] < 0 || s->init_idx[j] >= L.n)
+            return fail(c, MBKK_E_INDEX, "initial index outside [0, n)");
+    Buffers &B = c->B;
+    // coefficients of dead columns are forced to zero
+    std::vector<double> coef(s->coef, s->coef + (size_t)L.k * C);
+    const uint32_t mask = col_mask_of(live, init_alive);
+    for (int j = 0; j < L.k; ++j)
+        for (int cc = 0; cc < C; ++cc)
+            if (!((mask >> cc) & 1u))
+                coef[(size_t)j * C + cc] = 0.0;
+    std::vector<int32_t> offs(s->slot_off, s->slot_off + (size_t)W * (L.k + 1));
+    for (int r = 0; r < W; ++r) {
+        bool alive = false;
+        for (int q = 0; q < live.n; ++q)
+            alive |= live.r[q] == r;
+        if (!alive)
+            std::fill(offs.begin() + (size_t)r * (L.k + 1), offs.begin() + (size_t)(r + 1) * (L.k + 1), 0);
+    }
+    HIPCHK(c, hipMemcpyAsync(B.ring_idx, s->slot_idx, 4 * (size_t)W * L.bmax, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(B.ring_off, offs.data(), 4 * offs.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(B.cum, s->cum, 8 * (size_t)L.k, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(B.picks, s->init_idx, 4 * (size_t)L.k, hipMemcpyHostToDevice, c->stream));
+    // initial points and G[j][0][0] (init_state also resets coef; uploaded below)
+    launch_gather_rows(B.X, L.n, L.d, B.ld, B.picks, L.k, L.dp, B.pool32, L.bf16 ? B.poolhi : nullptr,
+                       L.bf16 ? B.poollo : nullptr, B.poolsq, B.poolsq64, B.init_idx, B.flags, 0, c->stream);
+    launch_init_state(L.k, W, c->cfg.kernel, c->cfg.kernel_param, L.d, L.dp, B.pool32, B.coef, B.cum, B.G,
+                      c->fp64, c->stream);
+    HIPCHK(c, hipMemcpyAsync(B.coef, coef.data(), 8 * coef.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(B.cum, s->cum, 8 * (size_t)L.k, hipMemcpyHostToDevice, c->stream));
+    for (int q = 0; q < live.n; ++q)
+        launch_pool_slot_from_X(L, B, live.r[q], s->slot_b[live.r[q]], c->stream);
+    // Gram blocks of every live slot against every live column
+    for (int q = 0; q < live.n; ++q) {
+        const int r = live.r[q];
+        launch_chunks(L, B, r, c->stream);
+        launch_gram(L, B, r, mask, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->stream);
+        launch_gram_fold(L, B, r, mask, c->stream);
+    }
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int r = 0; r < W; ++r)
+        c->slot_b[r] = s->slot_b[r];
+    c->iter = i;
+    c->pending_r = -1;
+    c->support_iter = -1;
+    c->inited = true;
+    return MBKK_OK;
+}
+
+int mbkk_set_timing(mbkk_ctx *c, int32_t enable)
+{
+    if (!c)
+        return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    c->timing = enable != 0;
+    c->ev_used = 0;
+    c->ms_acc = 0.0;
+    c->launches = 0;
+    return MBKK_OK;
+}
+
+int mbkk_get_timing(mbkk_ctx *c, double *ms_host, int64_t *launches_host)
+{
+    if (!c)
+        return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double ms = 0.0;
+    for (size_t q = 0; q + 1 < c->ev_used; q += 2) {
+        float t = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&t, c->ev[q], c->ev[q + 1]));
+        ms += t;
+    }
+    if (ms_host)
+        *ms_host = ms;
+    if (launches_host)
+        *launches_host = c->launches;
+    return MBKK_OK;
+}
+
+}  // extern "C"

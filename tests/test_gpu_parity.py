@@ -1,0 +1,318 @@
+"""GPU path against the FP64 oracle, through the C ABI (libmbkk.so).
+
+Lock-step protocol: before every compared iteration the GPU imports the
+oracle's state (mbkk_set_state), so one near-tie cannot make the trajectories
+diverge; the GPU's own update is then compared with the oracle's update of the
+same iteration (slot contents, offsets, coefficients) whenever the labels of
+that iteration agree.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle as O
+from paper_2410_05902_amd import workloads as W
+from tests._parity import agreement, dist_rel_err, oracle_state_to_gpu
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-9, "fp32": 1e-5, "bf16x3": 1e-2, "bf16x1": 1e-2}
+MARGIN = {"fp64": 1e-9, "fp32": 1e-4, "bf16x3": 1e-4, "bf16x1": 1e-2}
+
+
+def _model(X, k, b_max, window, kernel, param, precision, impl="auto", lr="beta", tie=0.0):
+    from paper_2410_05902_amd import Model
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    return Model(Xd, k=k, b_max=b_max, window=window, kernel=kernel, kernel_param=param,
+                 precision=precision, lr=lr, cross_impl=impl, tie_delta=tie)
+
+
+KNAME = {O.GAUSS: "gauss", O.LAPLACE: "laplace", O.LINEAR: "linear", O.POLY2: "poly2"}
+
+
+def lockstep(X, k, window, kind, param, init, batches, precision, impl="auto", lr=W.LR_BETA,
+             b_max=None, check_state=True, threads=4, min_agree=1.0):
+    """Runs the oracle and the GPU in lock-step; returns per-step stats."""
+    b_max = b_max or max(len(B) for B in batches)
+    lrname = {W.LR_BETA: "beta", W.LR_FULL: "full", W.LR_SKLEARN: "sklearn"}[lr]
+    orc = O.Oracle(X, k, window, kind, param, lr)
+    orc.init_centers(init)
+    model = _model(X, k, b_max, window, KNAME[kind], param, precision, impl, lrname)
+    model.init_centers(init)
+    tol, mmin = TOL[precision], MARGIN[precision]
+    stats = []
+    for i, B in enumerate(batches, start=1):
+        model.set_state(oracle_state_to_gpu(orc.state(), init, k, window, b_max))
+        # centers' self norms: GPU Gram blocks vs the oracle's direct quadratic form
+        Ng = model.center_norms()
+        a = model.assign(B, want_D=True)
+        ref = orc.step(B, threads=threads)
+        No = ref["N"]
+        np.testing.assert_allclose(Ng, No, rtol=max(tol, 1e-12), atol=1e-12 + tol * 1e-3)
+        kxx = {O.GAUSS: 1.0, O.LAPLACE: 1.0}.get(kind)
+        if kxx is None:
+            x = X[B].astype(np.float64)
+            sq = (x * x).sum(1)
+            kxx = sq if kind == O.LINEAR else (sq + param) ** 2
+        scale = np.broadcast_to(np.asarray(kxx).reshape(-1, 1), ref["D"].shape) + No[None, :]
+        D = a["D"].cpu().numpy()
+        err = dist_rel_err(D, ref["D"], scale)
+        assert err.max() <= tol, f"step {i}: distance error {err.max():.3e} > {tol}"
+        ag = agreement(a["labels"].cpu().numpy(), ref["labels"], ref["margin"], mmin)
+        assert ag["on_margin"], f"step {i}: label mismatch on rows with margin >= {mmin}: {ag['mismatches'][:8]}"
+        assert ag["all"] >= min_agree, f"step {i}: agreement {ag['all']:.5f}"
+        stats.append(dict(err=float(err.max()), agree=ag["all"]))
+    return orc, model, stats
+
+
+def _step_and_compare_state(X, k, window, kind, param, init, batches, precision, impl="auto",
+                            lr=W.LR_BETA, b_max=None):
+    """Lock-step on full iterations: import the oracle state, run one GPU step
+    and one oracle step on the same batch, compare labels, min distance and the
+    updated state."""
+    b_max = b_max or max(len(B) for B in batches)
+    lrname = {W.LR_BETA: "beta", W.LR_FULL: "full", W.LR_SKLEARN: "sklearn"}[lr]
+    orc = O.Oracle(X, k, window, kind, param, lr)
+    orc.init_centers(init)
+    model = _model(X, k, b_max, window, KNAME[kind], param, precision, impl, lrname)
+    model.init_centers(init)
+    tol, mmin = TOL[precision], MARGIN[precision]
+    compared = 0
+    for i, B in enumerate(batches, start=1):
+        model.set_state(oracle_state_to_gpu(orc.state(), init, k, window, b_max))
+        g = model.step(B, want_objective=True)
+        ref = orc.step(B, threads=4)
+        lab = g["labels"].cpu().numpy()
+        ag = agreement(lab, ref["labels"], ref["margin"], mmin)
+        assert ag["on_margin"], f"step {i}: {ag['mismatches'][:8]}"
+        mind = g["mind"].cpu().numpy().astype(np.float64)
+        scale = 1.0 + ref["N"][ref["labels"]] if kind in (O.GAUSS, O.LAPLACE) else None
+        if scale is not None:
+            same = lab == ref["labels"]
+            e = dist_rel_err(mind[same], ref["mind"][same], scale[same])
+            assert e.max() <= max(tol, 2e-7), f"step {i}: min-distance error {e.max():.3e}"
+            assert g["fbefore"] == pytest.approx(ref["fbefore"], rel=max(tol, 1e-6), abs=1e-9)
+        if (lab == ref["labels"]).all():
+            sg = model.get_state()
+            so = oracle_state_to_gpu(orc.state(), init, k, window, b_max)
+            assert sg["iteration"] == so["iteration"]
+            live = [((l - 1) % window) for l in range(max(1, i - window + 1), i + 1)]
+            for r in live:
+                assert sg["slot_b"][r] == so["slot_b"][r]
+                np.testing.assert_array_equal(sg["slot_off"][r], so["slot_off"][r])
+                np.testing.assert_array_equal(sg["slot_idx"][r, : so["slot_b"][r]],
+                                              so["slot_idx"][r, : so["slot_b"][r]])
+            cols = ([0] if i <= window else []) + [1 + r for r in live]
+            np.testing.assert_allclose(sg["coef"][:, cols], so["coef"][:, cols], rtol=1e-12, atol=1e-15)
+            compared += 1
+    assert compared >= len(batches) // 2
+    return orc, model
+
+
+# ---------------------------------------------------------------------------
+# the 2-D blob workload in full: 20 iterations, k-means++ seeding
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c1():
+    wl = W.c1_blobs(seed=0)
+    init = O.kmeanspp(wl.X, wl.kernel, wl.kernel_param, wl.k, wl.kmeanspp_uniforms())
+    return wl, init
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c1_distances_lockstep(c1, precision):
+    wl, init = c1
+    batches = [wl.batch(i) for i in range(1, wl.iterations + 1)]
+    lockstep(wl.X, wl.k, wl.window, wl.kernel, wl.kernel_param, init, batches, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c1_steps_and_state(c1, precision):
+    wl, init = c1
+    batches = [wl.batch(i) for i in range(1, wl.iterations + 1)]
+    _step_and_compare_state(wl.X, wl.k, wl.window, wl.kernel, wl.kernel_param, init, batches, precision)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_c1_free_running_trajectory(c1, precision):
+    """Without state import: 20 GPU iterations give the oracle's labels on
+    every row whose margin exceeds the precision's threshold."""
+    wl, init = c1
+    orc = O.Oracle(wl.X, wl.k, wl.window, wl.kernel, wl.kernel_param)
+    orc.init_centers(init)
+    model = _model(wl.X, wl.k, wl.b, wl.window, "gauss", wl.kernel_param, precision)
+    model.init_centers(init)
+    for i in range(1, wl.iterations + 1):
+        B = wl.batch(i)
+        ref = orc.step(B)
+        g = model.step(B)
+        lab = g["labels"].cpu().numpy()
+        if precision == "fp64":
+            np.testing.assert_array_equal(lab, ref["labels"])
+        else:
+            ag = agreement(lab, ref["labels"], ref["margin"], MARGIN[precision])
+            assert ag["on_margin"], ag["mismatches"]
+    allidx = np.arange(wl.n, dtype=np.int32)
+    assert model.objective(allidx) == pytest.approx(orc.objective(allidx), rel=TOL[precision] * 10)
+
+
+def test_c1_kmeanspp_picks(c1):
+    wl, init = c1
+    model = _model(wl.X, wl.k, wl.b, wl.window, "gauss", wl.kernel_param, "fp64")
+    picks = model.init_kmeanspp(wl.kmeanspp_uniforms()).cpu().numpy()
+    np.testing.assert_array_equal(picks, init)
+    u = np.random.default_rng(3).random(40)
+    ref = O.kmeanspp(wl.X, wl.kernel, wl.kernel_param, 40, u)
+    model = _model(wl.X, 40, wl.b, wl.window, "gauss", wl.kernel_param, "fp32")
+    np.testing.assert_array_equal(model.init_kmeanspp(u).cpu().numpy(), ref)
+
+
+# ---------------------------------------------------------------------------
+# MFMA and BF16 forms, shapes of the larger workloads at reduced n
+# ---------------------------------------------------------------------------
+
+def _small_gmm(n, d, c, std, seed=0, scale=1.0):
+    rng = np.random.default_rng(seed)
+    means = scale * rng.standard_normal((c, d))
+    comp = rng.integers(0, c, n)
+    return (means[comp] + std * rng.standard_normal((n, d))).astype(np.float32)
+
+
+@pytest.mark.parametrize("precision,impl", [("fp32", "mfma"), ("bf16x3", "mfma"), ("bf16x1", "mfma"),
+                                            ("fp32", "direct"), ("fp64", "direct")])
+def test_gmm128_lockstep(precision, impl):
+    X = _small_gmm(12000, 128, 20, 0.3)
+    sigma = W.median_pairwise_distance(X, 0)
+    k, b, Wn = 20, 300, 3
+    rng = np.random.default_rng(1)
+    init = rng.choice(X.shape[0], k, replace=False).astype(np.int32)
+    batches = [rng.integers(0, X.shape[0], b).astype(np.int32) for _ in range(Wn + 3)]
+    agree = 0.999 if precision.startswith("bf16") else 1.0
+    lockstep(X, k, Wn, O.GAUSS, 2 * sigma * sigma, init, batches, precision, impl,
+             min_agree=agree if precision != "fp32" else 1.0)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_gmm128_steps_and_state(precision):
+    X = _small_gmm(12000, 128, 20, 0.3, seed=2)
+    sigma = W.median_pairwise_distance(X, 0)
+    rng = np.random.default_rng(4)
+    init = rng.choice(X.shape[0], 20, replace=False).astype(np.int32)
+    batches = [rng.integers(0, X.shape[0], 257).astype(np.int32) for _ in range(6)]
+    _step_and_compare_state(X, 20, 3, O.GAUSS, 2 * sigma * sigma, init, batches, precision, "mfma")
+
+
+def test_sparse784_mfma_fp32():
+    """MNIST-shaped rows (d = 784, sparse prototypes in [0,1])."""
+    wl = W.c2_sparse_prototypes(seed=0, n=6000)
+    rng = np.random.default_rng(5)
+    init = rng.choice(wl.n, wl.k, replace=False).astype(np.int32)
+    batches = [rng.integers(0, wl.n, 200).astype(np.int32) for _ in range(5)]
+    lockstep(wl.X, wl.k, 3, wl.kernel, wl.kernel_param, init, batches, "fp32", "mfma")
+
+
+def test_laplace32_direct_lockstep():
+    wl = W.c5_laplace_mixture(seed=0, n=20000, c=100)
+    rng = np.random.default_rng(6)
+    init = rng.choice(wl.n, 100, replace=False).astype(np.int32)
+    batches = [rng.integers(0, wl.n, 700).astype(np.int32) for _ in range(wl.window + 2)]
+    lockstep(wl.X, 100, wl.window, wl.kernel, wl.kernel_param, init, batches, "fp32")
+    _step_and_compare_state(wl.X, 100, wl.window, wl.kernel, wl.kernel_param, init, batches, "fp32")
+
+
+@pytest.mark.parametrize("kind,param", [(O.LINEAR, 0.0), (O.POLY2, 0.7)])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_test_kernels_lockstep(kind, param, precision):
+    X = _small_gmm(3000, 5, 4, 0.4, seed=7)
+    rng = np.random.default_rng(8)
+    init = rng.choice(3000, 4, replace=False).astype(np.int32)
+    batches = [rng.integers(0, 3000, 100).astype(np.int32) for _ in range(6)]
+    lockstep(X, 4, 2, kind, param, init, batches, precision)
+
+
+# ---------------------------------------------------------------------------
+# learning-rate rules, window 1, k = 1, edge cases
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lr", [W.LR_SKLEARN, W.LR_FULL])
+def test_learning_rate_rules(lr):
+    X = _small_gmm(4000, 8, 5, 0.3, seed=9)
+    rng = np.random.default_rng(10)
+    init = rng.choice(4000, 5, replace=False).astype(np.int32)
+    batches = [rng.integers(0, 4000, 128).astype(np.int32) for _ in range(7)]
+    _step_and_compare_state(X, 5, 3, O.GAUSS, 3.0, init, batches, "fp64", lr=lr)
+
+
+def test_window_one_and_single_center():
+    X = _small_gmm(2000, 4, 3, 0.3, seed=11)
+    rng = np.random.default_rng(12)
+    batches = [rng.integers(0, 2000, 64).astype(np.int32) for _ in range(5)]
+    _step_and_compare_state(X, 3, 1, O.GAUSS, 2.0, np.array([0, 1, 2], np.int32), batches, "fp64")
+    _step_and_compare_state(X, 1, 2, O.GAUSS, 2.0, np.array([5], np.int32), batches, "fp64")
+
+
+def test_empty_cluster_and_duplicates():
+    """A far-away initial center receives no points (alpha = 0); batches
+    repeat indices."""
+    X = _small_gmm(1000, 3, 2, 0.2, seed=13)
+    X = np.vstack([X, np.full((1, 3), 50.0, np.float32)])
+    init = np.array([0, 1, 1000], np.int32)
+    base = np.random.default_rng(14).integers(0, 1000, 40).astype(np.int32)
+    batches = [np.concatenate([base, base[:10]]) for _ in range(4)]
+    _step_and_compare_state(X, 3, 2, O.GAUSS, 1.5, init, batches, "fp64")
+
+
+@pytest.mark.parametrize("param", [1e-6, 1e8])
+def test_bandwidth_extremes(param):
+    X = _small_gmm(1500, 6, 3, 0.5, seed=15)
+    rng = np.random.default_rng(16)
+    init = rng.choice(1500, 3, replace=False).astype(np.int32)
+    batches = [rng.integers(0, 1500, 90).astype(np.int32) for _ in range(4)]
+    lockstep(X, 3, 2, O.GAUSS, param, init, batches, "fp64")
+
+
+def test_ragged_batch_sizes_mfma():
+    """Batch sizes that are not multiples of the 128-row tile, down to b = 1."""
+    X = _small_gmm(5000, 64, 10, 0.4, seed=17)
+    rng = np.random.default_rng(18)
+    init = rng.choice(5000, 10, replace=False).astype(np.int32)
+    batches = [rng.integers(0, 5000, b).astype(np.int32) for b in (1, 129, 255, 77, 300)]
+    lockstep(X, 10, 2, O.GAUSS, 40.0, init, batches, "fp32", "mfma", b_max=300)
+
+
+def test_bad_index_and_nonfinite_are_errors():
+    from paper_2410_05902_amd._lib import MbkkError, E_INDEX, E_NONFINITE
+    X = _small_gmm(500, 4, 2, 0.3, seed=19)
+    model = _model(X, 2, 64, 2, "gauss", 1.0, "fp32")
+    model.init_centers([0, 1])
+    with pytest.raises(MbkkError) as e:
+        model.step(np.array([0, 3, 500], np.int32))
+    assert e.value.code == E_INDEX
+    with pytest.raises(MbkkError) as e:
+        model.step(np.array([-1], np.int32))
+    assert e.value.code == E_INDEX
+    Xn = X.copy()
+    Xn[7, 2] = np.nan
+    model = _model(Xn, 2, 64, 2, "gauss", 1.0, "fp32")
+    model.init_centers([0, 1])
+    with pytest.raises(MbkkError) as e:
+        model.step(np.array([3, 7], np.int32))
+    assert e.value.code == E_NONFINITE
+
+
+def test_bit_reproducible():
+    X = _small_gmm(8000, 128, 16, 0.3, seed=20)
+    rng = np.random.default_rng(21)
+    init = rng.choice(8000, 16, replace=False).astype(np.int32)
+    batches = [rng.integers(0, 8000, 512).astype(np.int32) for _ in range(5)]
+    outs = []
+    for _ in range(2):
+        model = _model(X, 16, 512, 2, "gauss", 30.0, "bf16x3")
+        model.init_centers(init)
+        res = [model.step(B)["mind"].cpu().numpy() for B in batches]
+        res.append(model.center_norms())
+        outs.append(res)
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)

@@ -1,0 +1,89 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every entry point declared in include/mbkk.h, and validates configurations
+(mbkk_workspace_size touches no device)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "mbkk.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(mbkk_\w+)\s*\(", text, re.M)))
+
+
+def test_header_declares_the_abi():
+    names = declared_symbols()
+    for n in ["mbkk_create", "mbkk_step", "mbkk_assign", "mbkk_objective", "mbkk_init_centers",
+              "mbkk_init_kmeanspp", "mbkk_get_state", "mbkk_set_state"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2410_05902_amd import _lib
+    L = C.CDLL(_lib.LIB_PATH)
+    missing = [n for n in declared_symbols() if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(declared_symbols()) <= set(_lib.EXPORTS) | {"mbkk_last_error"}
+
+
+def _cfg(**kw):
+    from paper_2410_05902_amd import _lib
+    base = dict(n=1000, d=16, k=8, b_max=256, window=4, kernel=_lib.GAUSS, kernel_param=1.0,
+                precision=_lib.FP32, lr=_lib.LR_BETA, cross_impl=_lib.CROSS_AUTO, tie_delta=0.0, validate=1)
+    base.update(kw)
+    return _lib.Config(**base)
+
+
+def _ws(cfg):
+    from paper_2410_05902_amd import _lib
+    nb = C.c_size_t()
+    rc = _lib.lib().mbkk_workspace_size(C.byref(cfg), C.byref(nb))
+    return rc, nb.value
+
+
+def test_workspace_size_and_validation():
+    from paper_2410_05902_amd import _lib
+    rc, nb = _ws(_cfg())
+    assert rc == _lib.OK and nb > 0 and nb % 256 == 0
+    bad = [dict(k=0), dict(k=2000), dict(n=0), dict(d=0), dict(b_max=0), dict(b_max=20000),
+           dict(window=0), dict(window=31), dict(kernel=9), dict(kernel_param=0.0),
+           dict(precision=7), dict(lr=5), dict(cross_impl=3),
+           dict(kernel=_lib.LAPLACE, precision=_lib.BF16X3),
+           dict(kernel=_lib.LINEAR, cross_impl=_lib.CROSS_MFMA),
+           dict(precision=_lib.BF16X3, cross_impl=_lib.CROSS_DIRECT),
+           dict(precision=_lib.FP64, cross_impl=_lib.CROSS_MFMA)]
+    for b in bad:
+        rc, _ = _ws(_cfg(**b))
+        assert rc == _lib.E_INVALID, b
+        assert _lib.lib().mbkk_last_error(None)
+
+
+def test_workspace_grows_with_the_problem():
+    small = _ws(_cfg())[1]
+    assert _ws(_cfg(b_max=1024))[1] > small
+    assert _ws(_cfg(window=8))[1] > small
+    from paper_2410_05902_amd import _lib
+    assert _ws(_cfg(precision=_lib.BF16X3))[1] > small   # hi/lo copies of the pool
+
+
+def test_create_rejects_missing_workspace():
+    from paper_2410_05902_amd import _lib
+    cfg = _cfg()
+    ctx = C.c_void_p()
+    rc = _lib.lib().mbkk_create(C.byref(cfg), None, 0, None, C.byref(ctx))
+    assert rc == _lib.E_WORKSPACE
+
+
+def test_product_package_does_not_import_the_oracle():
+    """The product path has no route to the oracle (and no CPU fallback)."""
+    pkg = os.path.join(ROOT, "paper_2410_05902_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "liboracle" not in text, f
