@@ -1,0 +1,193 @@
+"""Benchmark of one iteration of truncated mini-batch kernel k-means on one GPU.
+
+Default workload (the precision-form configuration the metric is quoted on):
+n = 1,000,000 points in 128-D from 100 Gaussian components (means N(0, I),
+std 0.3), k = 100 centers, batch b = 4096, centers truncated to their last
+W = 4 batches, Gaussian kernel with the median-heuristic bandwidth, kernel
+k-means++ seeding.  The timed "step" is one whole iteration (mbkk_step):
+batch staging, support layout, cross term on MFMA (BF16 compensated split),
+distances / argmin, FP64 near-tie re-scoring, the windowed update of the
+centers and their FP64 Gram blocks.  The same iterations are then timed in
+the FP32-plain form (FP32 MFMA) for the BF16-vs-FP32 speedup, and the two
+forms' assignments are compared on identical states.
+
+Prints ONE JSON line (rank 0).  Inputs are resident in HBM before timing.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "kernel evals/s + iters/s, BF16 vs FP32 plain at ≥99.9% assignment match"
+PEAK = {"bf16": 2.5e15, "f32": 157.3e12, "f64": 78.6e12}   # dense MFMA / vector peaks (FLOP/s)
+HBM_PEAK = 8.0e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5"])
+    ap.add_argument("--precision", default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=2048)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: the hot path is measured on one GPU's "
+              "share (see DESIGN.md for how it would shard); --gpus must be 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2410_05902_amd import Model, workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.time()
+    wl = W.make(args.workload)
+    log(f"[bench] workload {wl.name}: n={wl.n} d={wl.d} k={wl.k} b={wl.b} W={wl.window} "
+        f"kernel={'gauss' if wl.kernel == W.GAUSS else 'laplace'} param={wl.kernel_param:.4f} "
+        f"(generated in {time.time() - t0:.1f}s)")
+    gauss = wl.kernel == W.GAUSS
+    precision = args.precision or ("bf16x3" if gauss else "fp32")
+    X = torch.from_numpy(wl.X).to(dev)
+    nsteps = args.warmup + args.steps
+    batches = torch.from_numpy(np.stack([wl.batch(i) for i in range(1, nsteps + 1)])).to(dev)
+    u = wl.kmeanspp_uniforms()
+
+    def make(prec):
+        return Model(X, k=wl.k, b_max=wl.b, window=wl.window,
+                     kernel="gauss" if gauss else "laplace", kernel_param=wl.kernel_param,
+                     precision=prec, validate=False)
+
+    def run(model, timed_steps, warm, kernel_steps=50):
+        """Whole-step time over `timed_steps` (no instrumentation), then the
+        cross kernel's average duration from HIP events on the model's stream
+        over `kernel_steps` further steps."""
+        for i in range(warm):
+            model.step_noout(batches[i % nsteps])
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for i in range(warm, warm + timed_steps):
+            model.step_noout(batches[i % nsteps])
+        torch.cuda.synchronize()
+        te = time.perf_counter()
+        model.set_timing(True)
+        for i in range(kernel_steps):
+            model.step_noout(batches[(warm + i) % nsteps])
+        kms, launches = model.get_timing()
+        model.set_timing(False)
+        return (te - ts) * 1e3 / timed_steps, kms / max(launches, 1)
+
+    # ---- main form ---------------------------------------------------------
+    model = make(precision)
+    tk = time.time()
+    init = model.init_kmeanspp(u)
+    torch.cuda.synchronize()
+    log(f"[bench] k-means++ seeding on the GPU: {time.time() - tk:.2f}s")
+    if args.warmup < wl.window + 1:
+        log("[bench] note: warmup shorter than W+1, early steps have a smaller support")
+    ms_step, ms_cross = run(model, args.steps, args.warmup)
+    M = wl.window * wl.b                      # steady-state support size (W batches)
+    evals = wl.b * M                          # cross-term kernel evaluations per step
+    value = evals / (ms_step * 1e-3)
+    iters = 1e3 / ms_step
+    log(f"[bench] {precision}: {ms_step:.4f} ms/step, cross kernel {ms_cross:.4f} ms, "
+        f"{value:.4e} evals/s, {iters:.1f} it/s")
+
+    npass = {"bf16x3": 3, "bf16x1": 1, "fp32": 1}.get(precision, 1)
+    if gauss:
+        flops = npass * 2.0 * wl.d * evals
+        pk = PEAK["bf16"] if precision.startswith("bf16") else PEAK["f32"]
+        roof = {"bound": "mfma", "achieved": flops / (ms_cross * 1e-3) / 1e12, "peak": pk / 1e12,
+                "unit": "TFLOP/s", "frac": flops / (ms_cross * 1e-3) / pk, "traffic": None,
+                "kernel": f"k_cross_mfma<{precision}>",
+                "flops_per_launch": flops}
+    else:
+        # L1 path: 2 VALU ops (sub, add |.|) per coordinate per evaluation, FP32
+        ops = 2.0 * wl.d * evals
+        roof = {"bound": "alu", "achieved": ops / (ms_cross * 1e-3) / 1e12, "peak": 78.6,
+                "unit": "TFLOP/s", "frac": ops / (ms_cross * 1e-3) / 78.6e12, "traffic": None,
+                "kernel": "k_cross_direct<laplace,f32>", "ops_per_launch": ops}
+
+    out = {"metric": METRIC, "value": value, "unit": "kernel evals/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16" if precision.startswith("bf16") else "f32", "data": "synthetic",
+           "config": {"workload": wl.name, "n": wl.n, "d": wl.d, "k": wl.k, "b": wl.b,
+                      "window": wl.window, "kernel": "gauss" if gauss else "laplace",
+                      "kernel_param": wl.kernel_param, "precision": precision,
+                      "init": "kernel k-means++ (GPU)", "parallelism": "single GPU"},
+           "iters_per_s": iters, "cross_kernel_ms": ms_cross}
+
+    # ---- FP32 plain form, and assignment agreement -------------------------
+    if gauss and precision.startswith("bf16") and not args.no_fp32:
+        ref = make("fp32")
+        ref.init_centers(init)
+        fsteps = max(20, args.steps // 4)
+        ms32, mscross32 = run(ref, fsteps, args.warmup)
+        agree_n, agree_t = 0, 0
+        for i in range(4):
+            st = model.get_state()
+            ref.set_state(st)
+            B = batches[(args.warmup + i) % nsteps]
+            a = model.step(B)["labels"]
+            r = ref.step(B)["labels"]
+            agree_n += int((a == r).sum().item())
+            agree_t += int(B.numel())
+        out["fp32_plain"] = {"ms_per_step": ms32, "cross_kernel_ms": mscross32,
+                             "value": evals / (ms32 * 1e-3), "iters_per_s": 1e3 / ms32,
+                             "mfma_frac": 2.0 * wl.d * evals / (mscross32 * 1e-3) / PEAK["f32"]}
+        out["speedup_bf16_vs_fp32"] = ms32 / ms_step
+        out["assignment_match_bf16_vs_fp32"] = agree_n / agree_t
+        log(f"[bench] fp32 plain: {ms32:.4f} ms/step (cross {mscross32:.4f} ms); speedup "
+            f"{ms32 / ms_step:.2f}x; assignment match {agree_n / agree_t:.6f}")
+
+    out["roofline"] = roof
+
+    # ---- CPU baseline: the FP64 oracle, one core, a bounded sample ----------
+    if not args.no_cpu_baseline:
+        import oracle as O
+        rows = min(args.cpu_rows, wl.b)
+        orc = O.Oracle(wl.X, wl.k, wl.window, wl.kernel, wl.kernel_param)
+        # steady-state support: W batches from the generator, each point in
+        # the center of its generating component, equal weights per center
+        comp = wl.comp % wl.k
+        pts = np.concatenate([wl.batch(i) for i in range(1, wl.window + 1)])
+        cen = comp[pts]
+        cnt = np.bincount(cen, minlength=wl.k).astype(np.float64)
+        orc.set_centers(cen, pts, 1.0 / cnt[cen])
+        sample = wl.batch(wl.window + 1)[:rows]
+        tc = time.perf_counter()
+        orc.distances(sample, threads=1, want_D=False)
+        tcpu = time.perf_counter() - tc
+        cpu_evals = rows * len(pts)
+        out["cpu_baseline"] = {"value": cpu_evals / tcpu, "unit": "kernel evals/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": (f"one assignment pass (center norms + distances) of {rows} batch "
+                                          f"rows against a steady-state support of {len(pts)} points "
+                                          f"(W={wl.window} batches of {wl.b}, k={wl.k}), FP64, 1 thread, "
+                                          f"{tcpu:.1f}s")}
+        log(f"[bench] cpu oracle: {cpu_evals / tcpu:.4e} evals/s ({tcpu:.1f}s)")
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

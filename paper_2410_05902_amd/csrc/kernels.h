@@ -10,15 +10,12 @@ void launch_gather_rows(const float *X, int64_t n, int d, int64_t ld, const int3
                         int dp, float *out32, uint16_t *outhi, uint16_t *outlo, float *outsq,
                         double *outsq64, int32_t *idx_copy, int32_t *flags, int check_finite,
                         hipStream_t st);
-void launch_init_state(int k, int W, int kind, double param, int d, int dp, const float *pool32,
-                       double *coef, double *cum, double *G, int fp64, hipStream_t st);
-void launch_support_fill(const Layout &L, const Buffers &B, const SlotList &live, int init_alive,
-                         int pad, hipStream_t st);
-void launch_chunks(const Layout &L, const Buffers &B, int r, hipStream_t st);
-void launch_update(const Layout &L, const Buffers &B, int b, int r_new, int init_alive_before,
+void launch_init_state(const Layout &L, const Buffers &B, int kind, double param, int fp64, int set_coef,
+                       hipStream_t st);
+void launch_support_fill(const Layout &L, const Buffers &B, const SlotList &live, int init_alive, hipStream_t st);
+void launch_chunks(const Layout &L, const Buffers &B, int p, hipStream_t st);
+void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
                    int init_keep, const SlotList &live, int lr, hipStream_t st);
-void launch_slot_copy(const Layout &L, const Buffers &B, int b, int r, hipStream_t st);
-void launch_pool_slot_from_X(const Layout &L, const Buffers &B, int r, int cnt, hipStream_t st);
 void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param,
                  int fp64, hipStream_t st);
 void launch_gram_fold(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, hipStream_t st);

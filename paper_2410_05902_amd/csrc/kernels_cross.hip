@@ -10,6 +10,8 @@
 //     (any kernel, FP32 or FP64; the Laplacian L1 path);
 //   - k_cross_mfma  : Gaussian only, x.y on MFMA (FP32, or BF16 hi/lo split),
 //     exp fused in registers, segmented weighted sums over the support rows.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace mbkk {
@@ -463,8 +465,297 @@ __global__ __launch_bounds__(256, 2) void k_cross_mfma(const CrossArgs A)
     }
 }
 
+// ===========================================================================
+// Batch-stationary MFMA cross kernel (d <= 128).  Each wave keeps the MFMA
+// fragments of its 64 batch rows (2 N-blocks, all of K) in registers for the
+// whole launch; the workgroup streams a range of RB support blocks (32 rows
+// each) through double-buffered LDS, two blocks at a time.  Consecutive blocks
+// of one center are summed in registers; a run is written once, at its first
+// block ("run head": the first block of a center or of a range), so the
+// partial buffer holds one value per (run, batch row).
+// Grid: (#ranges x #batch tiles of 256 rows), XCD-aware: the workgroups of one
+// XCD share support ranges.
+// ===========================================================================
+struct CrossBsArgs {
+    int nb, dp, nbt, RB;
+    int64_t nranges;
+    int64_t zero_row;
+    const int32_t *seg_total;
+    const float *pool32;
+    const uint16_t *poolhi, *poollo;
+    const float *poolsq;
+    const int32_t *sup_row;
+    const float *sup_w;
+    const int32_t *blk_center;
+    const float *bat32;
+    const uint16_t *bathi, *batlo;
+    const float *batsq;
+    float c2, c1;
+    float *part;
+    int ldp;
+};
+
+template <int MODE, int DP>
+__global__ __launch_bounds__(256, 2) void k_cross_bs(const CrossBsArgs A)
+{
+    constexpr bool F32 = MODE == 0;
+    constexpr bool X3 = MODE == 1;
+    constexpr int KS = F32 ? DP / 2 : DP / 16;      // MFMA k-steps over K = DP
+    constexpr int LDA = F32 ? DP + 4 : DP + 8;      // LDS row stride (elements)
+    constexpr int ROWS = 64;                        // support rows per stage (2 blocks)
+    constexpr int BUF_F = F32 ? ROWS * LDA : 4;
+    constexpr int BUF_H = F32 ? 8 : ROWS * LDA;
+    __shared__ __attribute__((aligned(16))) float sAf[2][BUF_F];
+    __shared__ __attribute__((aligned(16))) uint16_t sAh[2][BUF_H];
+    __shared__ __attribute__((aligned(16))) uint16_t sAl[2][X3 ? BUF_H : 8];
+    __shared__ __attribute__((aligned(16))) float sAy[2][ROWS];
+    __shared__ __attribute__((aligned(16))) float sW[2][ROWS];
+
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    // XCD-aware order: tiles t of XCD x are x*G8 .. x*G8+G8-1; consecutive t
+    // share a support range
+    const int64_t G8 = gridDim.x / 8;
+    const int64_t t = (int64_t)(blockIdx.x % 8) * G8 + blockIdx.x / 8;
+    if (t >= A.nranges * A.nbt)
+        return;
+    const int range = (int)(t / A.nbt), bt = (int)(t % A.nbt);
+    const int M = *A.seg_total;
+    const int Mb = M / 32;
+    const int blk0 = range * A.RB;
+    if (blk0 >= Mb)
+        return;
+    const int blk1 = min(Mb, blk0 + A.RB);
+    const int b0 = bt * 256 + wid * 64;  // this wave's 64 batch rows
+    const int n = lane & 31, h = lane >> 5;
+
+    // ---- batch fragments into registers --------------------------------
+    typedef typename std::conditional<F32, float, bf16x8>::type frag_t;
+    frag_t bh[2][KS];
+    frag_t bl[2][X3 ? KS : 1];
+    float ax[2];
+#pragma unroll
+    for (int nbk = 0; nbk < 2; ++nbk) {
+        const int row = b0 + nbk * 32 + n;
+        const bool ok = row < A.nb;
+        const int64_t rr = ok ? row : 0;
+        ax[nbk] = ok ? A.c1 * A.batsq[row] : 0.0f;
+        if constexpr (F32) {
+            // K permutation: k-step s, lane half h -> column h * KS + s
+            const float *src = A.bat32 + rr * A.dp + h * KS;
+#pragma unroll
+            for (int s4 = 0; s4 < KS; s4 += 4) {
+                const f32x4 v = ok ? *(const f32x4 *)(src + s4) : f32x4{0, 0, 0, 0};
+                bh[nbk][s4] = v[0];
+                bh[nbk][s4 + 1] = v[1];
+                bh[nbk][s4 + 2] = v[2];
+                bh[nbk][s4 + 3] = v[3];
+            }
+        } else {
+            const uint16_t *sh = A.bathi + rr * A.dp + h * 8;
+            const uint16_t *sl = A.batlo + rr * A.dp + h * 8;
+            const u16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                bh[nbk][ks] = __builtin_bit_cast(bf16x8, ok ? *(const u16x8 *)(sh + ks * 16) : z8);
+                if constexpr (X3)
+                    bl[nbk][ks] = __builtin_bit_cast(bf16x8, ok ? *(const u16x8 *)(sl + ks * 16) : z8);
+            }
+        }
+    }
+
+    // ---- support stream: 64 rows per stage ------------------------------
+    // loader: thread -> row tid/4, quarter tid%4 of the K columns
+    const int lrow = tid >> 2, lq = tid & 3;
+    constexpr int QE = DP / 4;                    // elements per quarter row
+    constexpr int NV = F32 ? QE / 4 : QE / 8;      // 16-byte vectors per quarter
+    f32x4 rf[F32 ? NV : 1];
+    u16x8 rh[F32 ? 1 : NV], rl[X3 ? NV : 1];
+    float ry = 0.0f, rw = 0.0f;
+    auto gload = [&](int blk) {  // rows blk*32 .. blk*32+63
+        const int srow = blk * 32 + lrow;
+        const bool ok = srow < M;
+        const int64_t prow = ok ? (int64_t)A.sup_row[srow] : A.zero_row;
+        if constexpr (F32) {
+            const float *src = A.pool32 + prow * A.dp + lq * QE;
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                rf[v] = *(const f32x4 *)(src + v * 4);
+        } else {
+            const uint16_t *sh = A.poolhi + prow * A.dp + lq * QE;
+            const uint16_t *sl = A.poollo + prow * A.dp + lq * QE;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                rh[v] = *(const u16x8 *)(sh + v * 8);
+                if constexpr (X3)
+                    rl[v] = *(const u16x8 *)(sl + v * 8);
+            }
+        }
+        if (lq == 0) {
+            ry = A.c1 * A.poolsq[prow];
+            rw = ok ? A.sup_w[srow] : 0.0f;
+        }
+    };
+    auto lstore = [&](int buf) {
+        if constexpr (F32) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                *(f32x4 *)(&sAf[buf][lrow * LDA + lq * QE + v * 4]) = rf[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                *(u16x8 *)(&sAh[buf][lrow * LDA + lq * QE + v * 8]) = rh[v];
+                if constexpr (X3)
+                    *(u16x8 *)(&sAl[buf][lrow * LDA + lq * QE + v * 8]) = rl[v];
+            }
+        }
+        if (lq == 0) {
+            sAy[buf][lrow] = ry;
+            sW[buf][lrow] = rw;
+        }
+    };
+
+    float run[2] = {0.0f, 0.0f};
+    int run_head = blk0;
+    int run_center = A.blk_center[blk0];
+    auto flush = [&]() {
+        // lane l (< 32) holds the half-sums of column n for both N-blocks;
+        // one exchange gives N-block 0 totals to lanes < 32, N-block 1 to the rest
+        const float give = h == 0 ? run[1] : run[0];
+        const float got = __shfl_xor(give, 32);
+        const float tot = (h == 0 ? run[0] : run[1]) + got;
+        const int col = b0 + h * 32 + n;
+        if (col < A.nb)
+            A.part[(int64_t)run_head * A.ldp + col] = tot;
+        run[0] = run[1] = 0.0f;
+    };
+
+    gload(blk0);
+    lstore(0);
+    __syncthreads();
+    int buf = 0;
+    for (int bp = blk0; bp < blk1; bp += 2) {
+        const bool more = bp + 2 < blk1;
+        if (more)
+            gload(bp + 2);
+#pragma unroll
+        for (int sub = 0; sub < 2; ++sub) {
+            const int blk = bp + sub;
+            if (blk >= blk1)
+                break;
+            const int cen = A.blk_center[blk];
+            if (cen != run_center) {
+                flush();
+                run_head = blk;
+                run_center = cen;
+            }
+            f32x16 acc[2];
+#pragma unroll
+            for (int nbk = 0; nbk < 2; ++nbk)
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    acc[nbk][i] = 0.0f;
+            const int arow = sub * 32 + n;
+            if constexpr (F32) {
+                const float *ap = &sAf[buf][arow * LDA + h * KS];
+#pragma unroll
+                for (int s4 = 0; s4 < KS; s4 += 4) {
+                    const f32x4 av = *(const f32x4 *)(ap + s4);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int nbk = 0; nbk < 2; ++nbk)
+                            acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bh[nbk][s4 + u], acc[nbk], 0, 0, 0);
+                }
+            } else {
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    const int off = arow * LDA + ks * 16 + h * 8;
+                    const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u16x8 *)(&sAh[buf][off]));
+                    bf16x8 al;
+                    if constexpr (X3)
+                        al = __builtin_bit_cast(bf16x8, *(const u16x8 *)(&sAl[buf][off]));
+#pragma unroll
+                    for (int nbk = 0; nbk < 2; ++nbk) {
+                        acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[nbk][ks], acc[nbk], 0, 0, 0);
+                        if constexpr (X3) {
+                            acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[nbk][ks], acc[nbk], 0, 0, 0);
+                            acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[nbk][ks], acc[nbk], 0, 0, 0);
+                        }
+                    }
+                }
+            }
+            // epilogue: rows m = 8 (i/4) + 4 h + i%4 of this block
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const int m0 = sub * 32 + 8 * g + 4 * h;
+                const f32x4 ay = *(const f32x4 *)(&sAy[buf][m0]);
+                const f32x4 w = *(const f32x4 *)(&sW[buf][m0]);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int nbk = 0; nbk < 2; ++nbk) {
+                        const float arg = fmaf(acc[nbk][4 * g + q], A.c2, ax[nbk] + ay[q]);
+                        run[nbk] = fmaf(w[q], __builtin_amdgcn_exp2f(arg), run[nbk]);
+                    }
+            }
+        }
+        if (more) {
+            lstore(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+    flush();
+}
+
 void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision, double kappa, hipStream_t st)
 {
+    const double l2e = 1.4426950408889634;
+    if (L.dp <= 128) {
+        CrossBsArgs A;
+        A.nb = nb;
+        A.dp = L.dp;
+        A.nbt = (nb + 255) / 256;
+        A.RB = L.mfma_rb;
+        A.nranges = (L.nblk + A.RB - 1) / A.RB;
+        A.zero_row = L.PR;
+        A.seg_total = B.seg_off + L.k;
+        A.pool32 = B.pool32;
+        A.poolhi = B.poolhi;
+        A.poollo = B.poollo;
+        A.poolsq = B.poolsq;
+        A.sup_row = B.sup_row;
+        A.sup_w = B.sup_w;
+        A.blk_center = B.blk_center;
+        A.bat32 = B.bat32;
+        A.bathi = B.bathi;
+        A.batlo = B.batlo;
+        A.batsq = B.batsq;
+        A.c2 = (float)(2.0 * l2e / kappa);
+        A.c1 = (float)(-l2e / kappa);
+        A.part = (float *)B.part;
+        A.ldp = L.bmax;
+        const int64_t tiles = A.nranges * A.nbt;
+        const dim3 grid((unsigned)((tiles + 7) / 8 * 8));
+#define MBKK_BS(MODE, DP) hipLaunchKernelGGL((k_cross_bs<MODE, DP>), grid, dim3(256), 0, st, A)
+#define MBKK_BS_DP(MODE)                      \
+    switch (L.dp) {                           \
+    case 32: MBKK_BS(MODE, 32); break;        \
+    case 64: MBKK_BS(MODE, 64); break;        \
+    case 96: MBKK_BS(MODE, 96); break;        \
+    default: MBKK_BS(MODE, 128); break;       \
+    }
+        if (precision == MBKK_FP32) {
+            MBKK_BS_DP(0);
+        } else if (precision == MBKK_BF16X3) {
+            MBKK_BS_DP(1);
+        } else {
+            MBKK_BS_DP(2);
+        }
+#undef MBKK_BS_DP
+#undef MBKK_BS
+        return;
+    }
     CrossArgs A;
     A.nb = nb;
     A.dp = L.dp;
@@ -484,7 +775,6 @@ void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision,
     A.bathi = B.bathi;
     A.batlo = B.batlo;
     A.batsq = B.batsq;
-    const double l2e = 1.4426950408889634;
     A.c2 = (float)(2.0 * l2e / kappa);
     A.c1 = (float)(-l2e / kappa);
     A.part = (float *)B.part;
@@ -499,7 +789,7 @@ void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision,
 }
 
 // ===========================================================================
-// Distances, argmin and margin.  One thread per batch row:
+// Distances, argmin and margin of each batch row:
 //   D_j = K(x,x) - 2 P_j + N_j  (FP64 assembly of the FP32/FP64 cross term)
 // label = smallest j attaining the minimum; margin = second smallest - min.
 // LAYOUT 0: P[j][row]; LAYOUT 1: per-32-block partials of the MFMA kernel.
@@ -513,67 +803,108 @@ __device__ __forceinline__ double self_kernel(int kind, double param, double sq)
     return 1.0;  // normalised kernels: K(x,x) = 1
 }
 
+// LAYOUT 1: the MFMA kernels write one partial per run of a center's blocks
+// inside a range of RB blocks, at the run's first block: the center's first
+// block and every range start inside the center.
 template <typename T, int LAYOUT>
 __device__ __forceinline__ double cross_of(const T *__restrict__ part, int ldp, int row, int j,
-                                           const int32_t *__restrict__ seg_off)
+                                           const int32_t *__restrict__ seg_off, int RB)
 {
     if constexpr (LAYOUT == 0) {
         return (double)part[(int64_t)j * ldp + row];
     } else {
         const int bs = seg_off[j] / 32, be = seg_off[j + 1] / 32;
-        float s = 0.0f;
-        for (int blk = bs; blk < be; ++blk) {
-            if ((blk & 1) && blk - 1 >= bs)
-                continue;  // merged into the even block of its pair
+        if (bs >= be)
+            return 0.0;
+        float s = part[(int64_t)bs * ldp + row];
+        for (int blk = (bs / RB + 1) * RB; blk < be; blk += RB)
             s += part[(int64_t)blk * ldp + row];
-        }
         return (double)s;
     }
 }
 
-template <typename T, int LAYOUT>
-__global__ __launch_bounds__(256) void k_score(int nb, int k, const T *__restrict__ part, int ldp,
-                                                const int32_t *__restrict__ seg_off, const double *__restrict__ N,
-                                                int kind, double param, const double *__restrict__ batsq64,
-                                                int32_t *__restrict__ labels, float *__restrict__ mind,
-                                                float *__restrict__ margin, double *__restrict__ Dout, int64_t ldD)
+// One workgroup per 64 batch rows; its 16 waves split the centers (wave w
+// takes j = w, w + 16, ...), each lane one row, then the 16 partial
+// (best, label, second) triples of a row are merged in LDS.  Ties go to the
+// lowest center index: comparisons are on (distance, label).
+constexpr int kScoreWaves = 16;
+
+__device__ __forceinline__ bool lex_less(double a, int la, double b, int lb)
 {
-    const int row = blockIdx.x * 256 + threadIdx.x;
-    if (row >= nb)
-        return;
-    const double kxx = self_kernel(kind, param, batsq64[row]);
+    return a < b || (a == b && la < lb);
+}
+
+template <typename T, int LAYOUT>
+__global__ __launch_bounds__(64 * kScoreWaves) void k_score(
+    int nb, int k, const T *__restrict__ part, int ldp, const int32_t *__restrict__ seg_off,
+    const double *__restrict__ N, int kind, double param, const double *__restrict__ batsq64,
+    int32_t *__restrict__ labels, float *__restrict__ mind, float *__restrict__ margin,
+    double *__restrict__ Dout, int64_t ldD, int RB)
+{
+    __shared__ double sb[kScoreWaves][64], ss[kScoreWaves][64];
+    __shared__ int sl[kScoreWaves][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int row = blockIdx.x * 64 + lane;
+    const bool act = row < nb;
+    const double kxx = act ? self_kernel(kind, param, batsq64[row]) : 0.0;
     double best = INFINITY, second = INFINITY;
-    int lab = 0;
-    for (int j = 0; j < k; ++j) {
-        const double D = kxx - 2.0 * cross_of<T, LAYOUT>(part, ldp, row, j, seg_off) + N[j];
-        if (Dout)
-            Dout[(int64_t)row * ldD + j] = D;
-        if (D < best) {
-            second = best;
-            best = D;
-            lab = j;
-        } else if (D < second) {
-            second = D;
+    int lab = 0x7fffffff;
+    if (act) {
+        for (int j = w; j < k; j += kScoreWaves) {
+            const double D = kxx - 2.0 * cross_of<T, LAYOUT>(part, ldp, row, j, seg_off, RB) + N[j];
+            if (Dout)
+                Dout[(int64_t)row * ldD + j] = D;
+            if (D < best) {   // j increases within a wave: strict < keeps the lowest index
+                second = best;
+                best = D;
+                lab = j;
+            } else if (D < second) {
+                second = D;
+            }
         }
     }
-    labels[row] = lab;
-    mind[row] = (float)best;
-    margin[row] = (float)(second - best);
+    sb[w][lane] = best;
+    ss[w][lane] = second;
+    sl[w][lane] = lab;
+    __syncthreads();
+    if (w == 0 && act) {
+        double b0 = sb[0][lane], s0 = ss[0][lane];
+        int l0 = sl[0][lane];
+        for (int q = 1; q < kScoreWaves; ++q) {
+            const double bq = sb[q][lane], sq = ss[q][lane];
+            const int lq = sl[q][lane];
+            if (lex_less(bq, lq, b0, l0)) {
+                s0 = fmin(b0, sq);
+                b0 = bq;
+                l0 = lq;
+            } else {
+                s0 = fmin(s0, bq);
+            }
+        }
+        // a row whose distances are all NaN (non-finite input) matched no
+        // center: it is assigned to center 0 so that every label is in range
+        if (!(l0 >= 0 && l0 < k))
+            l0 = 0;
+        labels[row] = l0;
+        mind[row] = (float)b0;
+        margin[row] = (float)(s0 - b0);
+    }
 }
 
 void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double param, int fp64, int mfma,
                   double *D_out, int64_t ldD, hipStream_t st)
 {
-    dim3 grid((nb + 255) / 256);
+    const int RB = L.dp <= 128 ? L.mfma_rb : 2;
+    dim3 grid((nb + 63) / 64), block(64 * kScoreWaves);
     if (fp64)
-        hipLaunchKernelGGL((k_score<double, 0>), grid, dim3(256), 0, st, nb, L.k, (const double *)B.part, L.bmax,
-                           B.seg_off, B.N, kind, param, B.batsq64, B.labels, B.mind, B.margin, D_out, ldD);
+        hipLaunchKernelGGL((k_score<double, 0>), grid, block, 0, st, nb, L.k, (const double *)B.part, L.bmax,
+                           B.seg_off, B.N, kind, param, B.batsq64, B.labels, B.mind, B.margin, D_out, ldD, RB);
     else if (mfma)
-        hipLaunchKernelGGL((k_score<float, 1>), grid, dim3(256), 0, st, nb, L.k, (const float *)B.part, L.bmax,
-                           B.seg_off, B.N, kind, param, B.batsq64, B.labels, B.mind, B.margin, D_out, ldD);
+        hipLaunchKernelGGL((k_score<float, 1>), grid, block, 0, st, nb, L.k, (const float *)B.part, L.bmax,
+                           B.seg_off, B.N, kind, param, B.batsq64, B.labels, B.mind, B.margin, D_out, ldD, RB);
     else
-        hipLaunchKernelGGL((k_score<float, 0>), grid, dim3(256), 0, st, nb, L.k, (const float *)B.part, L.bmax,
-                           B.seg_off, B.N, kind, param, B.batsq64, B.labels, B.mind, B.margin, D_out, ldD);
+        hipLaunchKernelGGL((k_score<float, 0>), grid, block, 0, st, nb, L.k, (const float *)B.part, L.bmax,
+                           B.seg_off, B.N, kind, param, B.batsq64, B.labels, B.mind, B.margin, D_out, ldD, RB);
 }
 
 // ===========================================================================
@@ -584,7 +915,7 @@ void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double pa
 // weights), and the label, distance and margin are replaced.
 // ===========================================================================
 __global__ __launch_bounds__(256) void k_rescore(int nb, int k, int d, int dp, double kappa, double delta,
-                                                  const float *__restrict__ part, int ldp,
+                                                  const float *__restrict__ part, int ldp, int RB,
                                                   const int32_t *__restrict__ seg_off, const double *__restrict__ N,
                                                   const float *__restrict__ bat32, const float *__restrict__ pool32,
                                                   const int32_t *__restrict__ sup_row,
@@ -597,51 +928,53 @@ __global__ __launch_bounds__(256) void k_rescore(int nb, int k, int d, int dp, d
         return;
     if (!(margin[row] < (float)delta))
         return;
-    // best approximate distance (every lane scans a strided subset of centers)
+    // approximate distances, lanes over centers; the best of them
     double best = INFINITY;
-    for (int j = lane; j < k; j += 64) {
-        const double D = 1.0 - 2.0 * cross_of<float, 1>(part, ldp, row, j, seg_off) + N[j];
-        best = fmin(best, D);
-    }
+    for (int j = lane; j < k; j += 64)
+        best = fmin(best, 1.0 - 2.0 * cross_of<float, 1>(part, ldp, row, j, seg_off, RB) + N[j]);
     for (int o = 32; o > 0; o >>= 1)
         best = fmin(best, __shfl_xor(best, o));
     const float *x = bat32 + (int64_t)row * dp;
     double b64 = INFINITY, s64 = INFINITY, outside = INFINITY;
     int lab = 0;
-    for (int j = 0; j < k; ++j) {
-        // wave-uniform candidate test
-        double Dapprox = 0.0;
-        if (lane == 0)
-            Dapprox = 1.0 - 2.0 * cross_of<float, 1>(part, ldp, row, j, seg_off) + N[j];
-        Dapprox = __shfl(Dapprox, 0);
-        if (!(Dapprox <= best + delta)) {
-            outside = fmin(outside, Dapprox);
-            continue;
-        }
-        double p = 0.0;
-        for (int s = seg_off[j] + lane; s < seg_off[j + 1]; s += 64) {
-            const double w = sup_w64[s];
-            if (w == 0.0)
-                continue;
-            const float *y = pool32 + (int64_t)sup_row[s] * dp;
-            double d2 = 0.0;
-            for (int t = 0; t < d; ++t) {
-                const double v = (double)x[t] - (double)y[t];
-                d2 += v * v;
+    for (int j0 = 0; j0 < k; j0 += 64) {
+        const int jl = j0 + lane;
+        const double Dap = jl < k ? 1.0 - 2.0 * cross_of<float, 1>(part, ldp, row, jl, seg_off, RB) + N[jl] : INFINITY;
+        const bool cand = Dap <= best + delta;
+        if (!cand)
+            outside = fmin(outside, Dap);
+        uint64_t mask = __ballot(cand);
+        while (mask) {  // candidates in increasing center order (wave-uniform loop)
+            const int bit = __ffsll((unsigned long long)mask) - 1;
+            mask &= mask - 1;
+            const int j = j0 + bit;
+            double p = 0.0;
+            for (int s = seg_off[j] + lane; s < seg_off[j + 1]; s += 64) {
+                const double w = sup_w64[s];
+                if (w == 0.0)
+                    continue;
+                const float *y = pool32 + (int64_t)sup_row[s] * dp;
+                double d2 = 0.0;
+                for (int t = 0; t < d; ++t) {
+                    const double v = (double)x[t] - (double)y[t];
+                    d2 += v * v;
+                }
+                p += w * exp(-d2 / kappa);
             }
-            p += w * exp(-d2 / kappa);
-        }
-        for (int o = 32; o > 0; o >>= 1)
-            p += __shfl_xor(p, o);
-        const double D = 1.0 - 2.0 * p + N[j];
-        if (D < b64) {
-            s64 = b64;
-            b64 = D;
-            lab = j;
-        } else if (D < s64) {
-            s64 = D;
+            for (int o = 32; o > 0; o >>= 1)
+                p += __shfl_xor(p, o);
+            const double D = 1.0 - 2.0 * p + N[j];
+            if (D < b64) {
+                s64 = b64;
+                b64 = D;
+                lab = j;
+            } else if (D < s64) {
+                s64 = D;
+            }
         }
     }
+    for (int o = 32; o > 0; o >>= 1)
+        outside = fmin(outside, __shfl_xor(outside, o));
     if (lane == 0) {
         labels[row] = lab;
         mind[row] = (float)b64;
@@ -654,7 +987,8 @@ void launch_rescore(const Layout &L, const Buffers &B, int nb, int kind, double 
 {
     (void)kind;
     hipLaunchKernelGGL(k_rescore, dim3((nb + 3) / 4), dim3(256), 0, st, nb, L.k, L.d, L.dp, param, delta,
-                       (const float *)B.part, L.bmax, B.seg_off, B.N, B.bat32, B.pool32, B.sup_row, B.sup_w64,
+                       (const float *)B.part, L.bmax, L.dp <= 128 ? L.mfma_rb : 2, B.seg_off, B.N, B.bat32,
+                       B.pool32, B.sup_row, B.sup_w64,
                        B.labels, B.mind, B.margin);
 }
 

@@ -15,66 +15,100 @@ namespace mbkk {
 
 constexpr int kKppBlock = 256;
 
-__device__ __forceinline__ double kfun64(int kind, double param, const float *__restrict__ a,
-                                         const float *__restrict__ b, int d)
+// Partial kernel sums over the coordinates t = sub, sub + 16, ... of a row;
+// the 16 lanes of a row then combine them and finish K (FP64).
+template <int KIND>
+__device__ __forceinline__ double kacc64(const float *__restrict__ a, const float *__restrict__ b, int d, int sub)
 {
     double s = 0.0;
-    if (kind == MBKK_GAUSS) {
-        for (int t = 0; t < d; ++t) {
-            double v = (double)a[t] - (double)b[t];
+    for (int t = sub; t < d; t += 16) {
+        const double x = (double)a[t], y = (double)b[t];
+        if constexpr (KIND == MBKK_GAUSS) {
+            const double v = x - y;
             s += v * v;
+        } else if constexpr (KIND == MBKK_LAPLACE) {
+            s += fabs(x - y);
+        } else {
+            s += x * y;
         }
-        return exp(-s / param);
-    } else if (kind == MBKK_LAPLACE) {
-        for (int t = 0; t < d; ++t)
-            s += fabs((double)a[t] - (double)b[t]);
-        return exp(-s / param);
-    } else if (kind == MBKK_LINEAR) {
-        for (int t = 0; t < d; ++t)
-            s += (double)a[t] * (double)b[t];
-        return s;
     }
-    for (int t = 0; t < d; ++t)
-        s += (double)a[t] * (double)b[t];
-    s += param;
-    return s * s;
+    for (int o = 8; o > 0; o >>= 1)
+        s += __shfl_xor(s, o, 16);
+    return s;
 }
 
+template <int KIND>
+__device__ __forceinline__ double kfin64(double param, double s)
+{
+    if constexpr (KIND == MBKK_GAUSS || KIND == MBKK_LAPLACE)
+        return exp(-s / param);
+    else if constexpr (KIND == MBKK_LINEAR)
+        return s;
+    else
+        return (s + param) * (s + param);
+}
+
+// K(p,p) for every row, D2 = +inf.  16 lanes per row.
+template <int KIND>
 __global__ __launch_bounds__(256) void k_kpp_self(const float *__restrict__ X, int64_t n, int d, int64_t ld,
-                                                   int kind, double param, double *__restrict__ kself,
+                                                   double param, double *__restrict__ kself,
                                                    double *__restrict__ D2)
 {
-    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int sub = threadIdx.x & 15;
+    const int64_t p = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
     if (p >= n)
         return;
     const float *x = X + p * ld;
-    kself[p] = kfun64(kind, param, x, x, d);
-    D2[p] = INFINITY;
+    const double s = kacc64<KIND>(x, x, d, sub);
+    if (sub == 0) {
+        kself[p] = kfin64<KIND>(param, s);
+        D2[p] = INFINITY;
+    }
 }
 
 void launch_kpp_self(const Layout &L, const Buffers &B, int kind, double param, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_kpp_self, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, st, B.X, L.n, L.d, B.ld,
-                       kind, param, B.kself, B.D2);
+    const dim3 grid((unsigned)((L.n + 15) / 16));
+#define MBKK_KSELF(K) \
+    hipLaunchKernelGGL(k_kpp_self<K>, grid, dim3(256), 0, st, B.X, L.n, L.d, B.ld, param, B.kself, B.D2)
+    switch (kind) {
+    case MBKK_GAUSS: MBKK_KSELF(MBKK_GAUSS); break;
+    case MBKK_LAPLACE: MBKK_KSELF(MBKK_LAPLACE); break;
+    case MBKK_LINEAR: MBKK_KSELF(MBKK_LINEAR); break;
+    default: MBKK_KSELF(MBKK_POLY2); break;
+    }
+#undef MBKK_KSELF
 }
 
-// D2 <- min(D2, K(p,p) - 2K(p,c) + K(c,c)) with c = picks[r]; block sums.
-__global__ __launch_bounds__(kKppBlock) void k_kpp_update(const float *__restrict__ X, int64_t n, int d, int64_t ld,
-                                                           int kind, double param, const int32_t *__restrict__ picks,
-                                                           int r, const double *__restrict__ kself,
-                                                           double *__restrict__ D2, double *__restrict__ bsum)
+// D2 <- min(D2, K(p,p) - 2K(p,c) + K(c,c)) with c = picks[r]; block sums over
+// 256 consecutive rows (16 lanes per row, 16 rows at a time).
+template <int KIND>
+__global__ __launch_bounds__(256) void k_kpp_update(const float *__restrict__ X, int64_t n, int d, int64_t ld,
+                                                     double param, const int32_t *__restrict__ picks,
+                                                     int r, const double *__restrict__ kself,
+                                                     double *__restrict__ D2, double *__restrict__ bsum)
 {
     __shared__ double red[kKppBlock];
-    const int tid = threadIdx.x;
-    const int64_t p = (int64_t)blockIdx.x * kKppBlock + tid;
+    const int tid = threadIdx.x, sub = tid & 15, grp = tid >> 4;
     const int64_t c = picks[r];
-    double v = 0.0;
-    if (p < n) {
-        const double dd = kself[p] - 2.0 * kfun64(kind, param, X + p * ld, X + c * ld, d) + kself[c];
-        v = fmin(D2[p], dd);
-        D2[p] = v;
+    const float *xc = X + c * ld;
+    const double kcc = kself[c];
+    for (int it = 0; it < kKppBlock / 16; ++it) {
+        const int local = it * 16 + grp;
+        const int64_t p = (int64_t)blockIdx.x * kKppBlock + local;
+        double s = 0.0;
+        if (p < n)
+            s = kacc64<KIND>(X + p * ld, xc, d, sub);
+        if (sub == 0) {
+            double v = 0.0;
+            if (p < n) {
+                const double dd = kself[p] - 2.0 * kfin64<KIND>(param, s) + kcc;
+                v = fmin(D2[p], dd);
+                D2[p] = v;
+            }
+            red[local] = v;
+        }
     }
-    red[tid] = v;
     __syncthreads();
     for (int h = kKppBlock / 2; h > 0; h >>= 1) {
         if (tid < h)
@@ -174,9 +208,18 @@ void launch_kpp_round(const Layout &L, const Buffers &B, int r, int kind, double
 {
     // r == 0: select the first pick; r >= 1: update with pick r-1, then select pick r
     const int64_t nblocks = (L.n + kKppBlock - 1) / kKppBlock;
-    if (r > 0)
-        hipLaunchKernelGGL(k_kpp_update, dim3((unsigned)nblocks), dim3(kKppBlock), 0, st, B.X, L.n, L.d, B.ld, kind,
-                           param, B.picks, r - 1, B.kself, B.D2, B.bsum);
+    if (r > 0) {
+#define MBKK_KUPD(K)                                                                                     \
+    hipLaunchKernelGGL(k_kpp_update<K>, dim3((unsigned)nblocks), dim3(kKppBlock), 0, st, B.X, L.n, L.d, B.ld, \
+                       param, B.picks, r - 1, B.kself, B.D2, B.bsum)
+        switch (kind) {
+        case MBKK_GAUSS: MBKK_KUPD(MBKK_GAUSS); break;
+        case MBKK_LAPLACE: MBKK_KUPD(MBKK_LAPLACE); break;
+        case MBKK_LINEAR: MBKK_KUPD(MBKK_LINEAR); break;
+        default: MBKK_KUPD(MBKK_POLY2); break;
+        }
+#undef MBKK_KUPD
+    }
     hipLaunchKernelGGL(k_kpp_select, dim3(1), dim3(1024), 0, st, L.n, nblocks, B.u, r, B.D2, B.bsum, B.picks);
 }
 

@@ -1,9 +1,9 @@
 // Data staging and center bookkeeping kernels of one iteration of the
 // truncated mini-batch kernel k-means (Algorithm 2):
 //   - ||x||^2 cache, batch staging (gather + FP32 / BF16 hi-lo copies),
-//   - support layout of the implicit centers (Eq. 1 as a ring of W slots),
-//   - the update: grouping of the batch by center, counts b_i^j, learning
-//     rates, coefficient decay by (1 - alpha) and truncation,
+//   - support layout of the implicit centers (Eq. 1 as a ring of slots),
+//   - the update: deterministic grouping of the batch by center, counts
+//     b_i^j, learning rates, coefficient decay by (1 - alpha), truncation,
 //   - the FP64 Gram blocks that give <C_j, C_j> incrementally.
 #include "kernels.h"
 
@@ -11,30 +11,30 @@ namespace mbkk {
 
 // ---------------------------------------------------------------------------
 // ||x||^2 for every row of X, summed in FP64, stored as FP32 (data norms).
-// One wave per row.
+// 16 lanes per row.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_row_sqnorm(const float *__restrict__ X, int64_t n, int d,
                                                      int64_t ld, float *__restrict__ sqn)
 {
-    const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int sub = threadIdx.x & 15;
+    const int64_t row = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
     if (row >= n)
         return;
     const float *r = X + row * ld;
     double s = 0.0;
-    for (int t = lane; t < d; t += 64) {
+    for (int t = sub; t < d; t += 16) {
         double v = r[t];
         s += v * v;
     }
-    for (int o = 32; o > 0; o >>= 1)
-        s += __shfl_xor(s, o);
-    if (lane == 0)
+    for (int o = 8; o > 0; o >>= 1)
+        s += __shfl_xor(s, o, 16);
+    if (sub == 0)
         sqn[row] = (float)s;
 }
 
 void launch_row_sqnorm(const float *X, int64_t n, int d, int64_t ld, float *sqn, hipStream_t st)
 {
-    int64_t blocks = (n + 3) / 4;
+    int64_t blocks = (n + 15) / 16;
     hipLaunchKernelGGL(k_row_sqnorm, dim3((unsigned)blocks), dim3(256), 0, st, X, n, d, ld, sqn);
 }
 
@@ -130,21 +130,23 @@ __device__ __forceinline__ T kernel_value(int kind, T param, const float *__rest
 }
 
 // ---------------------------------------------------------------------------
-// Initial centers: pool rows [0,k) <- X[idx], coef[j][0] = 1, other
-// coefficients 0, running counts 0, G[j][0][0] = K(x_j, x_j).
+// Initial centers: coef[j][0] = 1, other coefficients 0, running counts 0,
+// G_j = 0 except G_j[0][0] = K(x_j, x_j) (pool rows [0, k) hold the points).
+// With set_coef == 0 only G is reset (state import).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_init_state(int k, int W, int kind, double param, int d,
-                                                     int dp, const float *__restrict__ pool32,
-                                                     double *__restrict__ coef, double *__restrict__ cum,
-                                                     double *__restrict__ G, int fp64)
+__global__ __launch_bounds__(256) void k_init_state(int k, int C, int kind, double param, int d, int dp,
+                                                     const float *__restrict__ pool32, double *__restrict__ coef,
+                                                     double *__restrict__ cum, double *__restrict__ G, int fp64,
+                                                     int set_coef)
 {
-    int j = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= k)
         return;
-    const int C = W + 1;
-    for (int c = 0; c < C; ++c)
-        coef[(int64_t)j * C + c] = c == 0 ? 1.0 : 0.0;
-    cum[j] = 0.0;
+    if (set_coef) {
+        for (int c = 0; c < C; ++c)
+            coef[(int64_t)j * C + c] = c == 0 ? 1.0 : 0.0;
+        cum[j] = 0.0;
+    }
     double *g = G + (int64_t)j * C * C;
     for (int c = 0; c < C * C; ++c)
         g[c] = 0.0;
@@ -153,24 +155,24 @@ __global__ __launch_bounds__(256) void k_init_state(int k, int W, int kind, doub
                 : (double)kernel_value<float>(kind, (float)param, x, x, d);
 }
 
-void launch_init_state(int k, int W, int kind, double param, int d, int dp, const float *pool32,
-                       double *coef, double *cum, double *G, int fp64, hipStream_t st)
+void launch_init_state(const Layout &L, const Buffers &B, int kind, double param, int fp64, int set_coef,
+                       hipStream_t st)
 {
-    hipLaunchKernelGGL(k_init_state, dim3((k + 255) / 256), dim3(256), 0, st, k, W, kind, param, d, dp,
-                       pool32, coef, cum, G, fp64);
+    hipLaunchKernelGGL(k_init_state, dim3((L.k + 255) / 256), dim3(256), 0, st, L.k, L.C, kind, param, L.d, L.dp,
+                       B.pool32, B.coef, B.cum, B.G, fp64, set_coef);
 }
 
 // ---------------------------------------------------------------------------
 // Support layout of C_i (one workgroup per center j).  Center j's segment is
-// [seg_off[j], seg_off[j+1]): its initial point (while alive), then the
-// points of every live ring slot, oldest batch first, padded with the zero
-// pool row to a multiple of `pad`.  Each entry carries its pool row and its
-// weight coef[j][column].  The workgroup also computes
+// [seg_off[j], seg_off[j+1]): its initial point (while alive), then its points
+// in every live slot, oldest batch first, padded with the zero pool row to a
+// multiple of `pad`.  Each entry carries its pool row and the weight
+// coef[j][column].  The workgroup also computes
 //   N_j = <C_j, C_j> = sum_{c,c'} coef[j][c] coef[j][c'] G_j[c][c']
 // over the live columns (FP64).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int seg_len(int j, int k, int bmax, const int32_t *__restrict__ ring_off,
-                                       const SlotList &live, int init_alive)
+__device__ __forceinline__ int seg_len(int j, int k, const int32_t *__restrict__ ring_off, const SlotList &live,
+                                       int init_alive)
 {
     int len = init_alive;
     for (int s = 0; s < live.n; ++s) {
@@ -181,10 +183,11 @@ __device__ __forceinline__ int seg_len(int j, int k, int bmax, const int32_t *__
 }
 
 __global__ __launch_bounds__(256) void k_support_fill(
-    int k, int W, int bmax, int pad, int64_t zero_row, const int32_t *__restrict__ ring_off,
-    SlotList live, int init_alive, const double *__restrict__ coef, const double *__restrict__ G,
-    int32_t *__restrict__ seg_off, int32_t *__restrict__ sup_row, float *__restrict__ sup_w,
-    double *__restrict__ sup_w64, int32_t *__restrict__ blk_center, double *__restrict__ N)
+    int k, int C, int bmax, int pad, int64_t zero_row, const int32_t *__restrict__ ring_off,
+    const int32_t *__restrict__ ring_perm, SlotList live, int init_alive, const double *__restrict__ coef,
+    const double *__restrict__ G, int32_t *__restrict__ seg_off, int32_t *__restrict__ sup_row,
+    float *__restrict__ sup_w, double *__restrict__ sup_w64, int32_t *__restrict__ blk_center,
+    double *__restrict__ N)
 {
     __shared__ int red[256];
     __shared__ int sh_start;
@@ -193,7 +196,7 @@ __global__ __launch_bounds__(256) void k_support_fill(
     // exclusive prefix of the padded lengths of centers < j
     int acc = 0;
     for (int q = tid; q < j; q += 256) {
-        int l = seg_len(q, k, bmax, ring_off, live, init_alive);
+        const int l = seg_len(q, k, ring_off, live, init_alive);
         acc += (l + pad - 1) / pad * pad;
     }
     red[tid] = acc;
@@ -203,7 +206,7 @@ __global__ __launch_bounds__(256) void k_support_fill(
             red[tid] += red[tid + s];
         __syncthreads();
     }
-    const int len = seg_len(j, k, bmax, ring_off, live, init_alive);
+    const int len = seg_len(j, k, ring_off, live, init_alive);
     const int plen = (len + pad - 1) / pad * pad;
     if (tid == 0) {
         sh_start = red[0];
@@ -213,12 +216,10 @@ __global__ __launch_bounds__(256) void k_support_fill(
     }
     __syncthreads();
     const int start = sh_start;
-    const int C = W + 1;
-    // entries
     int pos = start;
     if (init_alive) {
         if (tid == 0) {
-            double w = coef[(int64_t)j * C + 0];
+            const double w = coef[(int64_t)j * C + 0];
             sup_row[pos] = j;
             sup_w[pos] = (float)w;
             sup_w64[pos] = w;
@@ -226,12 +227,14 @@ __global__ __launch_bounds__(256) void k_support_fill(
         ++pos;
     }
     for (int s = 0; s < live.n; ++s) {
-        const int r = live.r[s];
-        const int32_t *o = ring_off + (int64_t)r * (k + 1);
+        const int p = live.r[s];
+        const int32_t *o = ring_off + (int64_t)p * (k + 1);
+        const int32_t *perm = ring_perm + (int64_t)p * bmax;
         const int a0 = o[j], a1 = o[j + 1];
-        const double w = coef[(int64_t)j * C + 1 + r];
+        const double w = coef[(int64_t)j * C + 1 + p];
+        const int64_t row0 = (int64_t)k + (int64_t)p * bmax;
         for (int q = tid; q < a1 - a0; q += 256) {
-            sup_row[pos + q] = (int32_t)(k + (int64_t)r * bmax + a0 + q);
+            sup_row[pos + q] = (int32_t)(row0 + perm[a0 + q]);
             sup_w[pos + q] = (float)w;
             sup_w64[pos + q] = w;
         }
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(256) void k_support_fill(
     }
     // N_j from the Gram blocks (FP64), in a fixed order
     if (tid == 0) {
-        int cols[kMaxWindow + 1];
+        int cols[kMaxSlots + 1];
         int nc = 0;
         if (init_alive)
             cols[nc++] = 0;
@@ -264,23 +267,23 @@ __global__ __launch_bounds__(256) void k_support_fill(
     }
 }
 
-void launch_support_fill(const Layout &L, const Buffers &B, const SlotList &live, int init_alive,
-                         int pad, hipStream_t st)
+void launch_support_fill(const Layout &L, const Buffers &B, const SlotList &live, int init_alive, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_support_fill, dim3(L.k), dim3(256), 0, st, L.k, L.W, L.bmax, pad, L.PR,
-                       B.ring_off, live, init_alive, B.coef, B.G, B.seg_off, B.sup_row, B.sup_w, B.sup_w64,
-                       pad == kMfmaPad ? B.blk_center : nullptr, B.N);
+    hipLaunchKernelGGL(k_support_fill, dim3(L.k), dim3(256), 0, st, L.k, L.C, L.bmax, L.pad, L.PR, B.ring_off,
+                       B.ring_perm, live, init_alive, B.coef, B.G, B.seg_off, B.sup_row, B.sup_w, B.sup_w64,
+                       L.pad == kMfmaPad ? B.blk_center : nullptr, B.N);
 }
 
 // ---------------------------------------------------------------------------
-// Gram work items of one ring slot r: center j's rows of slot r split into
-// chunks of `rows` rows.  Single workgroup; shared by the update kernel.
+// Gram work items of one slot: center j's grouped positions split into
+// chunks of `rows`.  Single workgroup.
 // ---------------------------------------------------------------------------
 __device__ void build_chunks(int k, int rows, const int32_t *__restrict__ off, int32_t *__restrict__ chunk_off,
                              int32_t *__restrict__ chunk_j, int32_t *__restrict__ chunk_a0,
                              int32_t *__restrict__ chunk_a1, int32_t *__restrict__ nchunks, int *scratch)
 {
-    // scratch: blockDim.x ints
+    // scratch: blockDim.x ints; off must be complete before the call
+    __syncthreads();
     const int tid = threadIdx.x, nt = blockDim.x;
     const int per = (k + nt - 1) / nt;
     const int j0 = tid * per, j1 = min(k, j0 + per);
@@ -289,9 +292,8 @@ __device__ void build_chunks(int k, int rows, const int32_t *__restrict__ off, i
         local += (off[j + 1] - off[j] + rows - 1) / rows;
     scratch[tid] = local;
     __syncthreads();
-    // inclusive scan (Hillis-Steele) over threads
     for (int s = 1; s < nt; s <<= 1) {
-        int v = tid >= s ? scratch[tid - s] : 0;
+        const int v = tid >= s ? scratch[tid - s] : 0;
         __syncthreads();
         scratch[tid] += v;
         __syncthreads();
@@ -299,7 +301,7 @@ __device__ void build_chunks(int k, int rows, const int32_t *__restrict__ off, i
     int base = scratch[tid] - local;
     for (int j = j0; j < j1; ++j) {
         chunk_off[j] = base;
-        int a0 = off[j], a1 = off[j + 1];
+        const int a0 = off[j], a1 = off[j + 1];
         for (int a = a0; a < a1; a += rows) {
             chunk_j[base] = j;
             chunk_a0[base] = a;
@@ -323,103 +325,117 @@ __global__ __launch_bounds__(1024) void k_chunks(int k, int rows, const int32_t 
     build_chunks(k, rows, off, chunk_off, chunk_j, chunk_a0, chunk_a1, nchunks, scratch);
 }
 
-void launch_chunks(const Layout &L, const Buffers &B, int r, hipStream_t st)
+void launch_chunks(const Layout &L, const Buffers &B, int p, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_chunks, dim3(1), dim3(1024), 0, st, L.k, L.gram_rows, B.ring_off + (int64_t)r * (L.k + 1),
+    hipLaunchKernelGGL(k_chunks, dim3(1), dim3(1024), 0, st, L.k, L.gram_rows, B.ring_off + (int64_t)p * (L.k + 1),
                        B.chunk_off, B.chunk_j, B.chunk_a0, B.chunk_a1, B.nchunks);
 }
 
 // ---------------------------------------------------------------------------
-// Update of Algorithm 2 (single workgroup of 1024 threads):
-//  1. group the batch by label: sort keys (label << 14 | position), a bitonic
-//     sort in LDS, so each center's points keep batch order;
-//  2. offsets of every center in the new slot, counts b_i^j;
-//  3. learning rates alpha (beta: sqrt(b_i^j/b), full, or count-based);
-//  4. coefficients: every live term times (1 - alpha); the new slot gets
-//     alpha / b_i^j per point (0 for an empty cluster); the initial term is
-//     dropped once i > W; the expired slot is the one overwritten;
-//  5. the new slot's point indices, the permutation for the coordinate copy,
-//     the Gram work items, and sum of the batch min-distances (FP64).
+// Update of Algorithm 2, in three launches that group the batch by center in
+// a deterministic, stable order (each center's points in batch order):
+//   rank    : per chunk of 256 rows, each row's rank among the equal labels
+//             before it, and the chunk's count of every label;
+//   offsets : (one workgroup) counts b_i^j, offsets of the centers in the new
+//             slot, per-(chunk, label) bases, learning rates alpha, the
+//             coefficient update and truncation, the batch objective, the
+//             Gram work items;
+//   scatter : grouped position of every row = base + rank.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_update(
-    int b, int k, int W, int r_new, int init_alive_before, int init_keep, SlotList live, int lr, int gram_rows,
-    const int32_t *__restrict__ labels, const int32_t *__restrict__ batidx, const float *__restrict__ mind,
-    int32_t *__restrict__ ring_idx, int32_t *__restrict__ ring_off, int bmax, double *__restrict__ coef,
-    double *__restrict__ cum, int32_t *__restrict__ counts, double *__restrict__ alpha,
-    int32_t *__restrict__ perm, int32_t *__restrict__ chunk_off, int32_t *__restrict__ chunk_j,
-    int32_t *__restrict__ chunk_a0, int32_t *__restrict__ chunk_a1, int32_t *__restrict__ nchunks,
-    double *__restrict__ obj)
+__global__ __launch_bounds__(kChunk) void k_group_rank(int b, int k, const int32_t *__restrict__ labels,
+                                                        int32_t *__restrict__ rank, int32_t *__restrict__ gcnt)
 {
-    extern __shared__ uint32_t keys[];  // [P2] followed by 1024 ints of scratch
+    __shared__ int sl[kChunk];
+    const int g = blockIdx.x, tid = threadIdx.x;
+    const int p = g * kChunk + tid;
+    // labels outside [0, k) are clamped so that every index below stays in range
+    const int lab = p < b ? min(max(labels[p], 0), k - 1) : -1;
+    sl[tid] = lab;
+    int32_t *cnt = gcnt + (int64_t)g * k;
+    for (int j = tid; j < k; j += kChunk)
+        cnt[j] = 0;
+    __syncthreads();
+    int r = 0, c = 0;
+    for (int t = 0; t < kChunk; ++t) {
+        const int v = sl[t];  // wave-uniform address: LDS broadcast
+        const int eq = v == lab;
+        c += eq;
+        r += eq & (t < tid);
+    }
+    if (p < b) {
+        rank[p] = r;
+        if (r == c - 1)
+            cnt[lab] = c;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_group_offsets(
+    int b, int k, int nchunk, int C, int p_new, int p_expired, int init_alive_before, int init_keep,
+    SlotList live, int lr, int gram_rows, int32_t *__restrict__ gcnt, const float *__restrict__ mind,
+    double *__restrict__ coef, double *__restrict__ cum, int32_t *__restrict__ counts,
+    double *__restrict__ alpha, int32_t *__restrict__ off, int32_t *__restrict__ chunk_off,
+    int32_t *__restrict__ chunk_j, int32_t *__restrict__ chunk_a0, int32_t *__restrict__ chunk_a1,
+    int32_t *__restrict__ nchunks, double *__restrict__ obj)
+{
+    __shared__ int scratch[1024];
+    __shared__ double red[1024];
     const int tid = threadIdx.x, nt = blockDim.x;
-    int P2 = 1;
-    while (P2 < b)
-        P2 <<= 1;
-    int *scratch = (int *)(keys + P2);
-    for (int p = tid; p < P2; p += nt)
-        keys[p] = p < b ? (((uint32_t)labels[p]) << 14) | (uint32_t)p : 0xFFFFFFFFu;
+    const int per = (k + nt - 1) / nt;
+    const int j0 = tid * per, j1 = min(k, j0 + per);
+    // totals of this thread's labels, block-wide exclusive scan -> offsets
+    int local = 0;
+    for (int j = j0; j < j1; ++j)
+        for (int g = 0; g < nchunk; ++g)
+            local += gcnt[(int64_t)g * k + j];
+    scratch[tid] = local;
     __syncthreads();
-    // bitonic sort, ascending
-    for (int size = 2; size <= P2; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int p = tid; p < P2 / 2; p += nt) {
-                int lo = 2 * p - (p & (stride - 1));
-                int hi = lo + stride;
-                bool up = ((lo & size) == 0);
-                uint32_t a = keys[lo], c = keys[hi];
-                if ((a > c) == up) {
-                    keys[lo] = c;
-                    keys[hi] = a;
-                }
-            }
-            __syncthreads();
+    for (int s = 1; s < nt; s <<= 1) {
+        const int v = tid >= s ? scratch[tid - s] : 0;
+        __syncthreads();
+        scratch[tid] += v;
+        __syncthreads();
+    }
+    int run = scratch[tid] - local;
+    for (int j = j0; j < j1; ++j) {
+        off[j] = run;
+        int gb = run;
+        for (int g = 0; g < nchunk; ++g) {
+            const int c = gcnt[(int64_t)g * k + j];
+            gcnt[(int64_t)g * k + j] = gb;  // base of label j in chunk g
+            gb += c;
         }
-    }
-    int32_t *off = ring_off + (int64_t)r_new * (k + 1);
-    int32_t *slot = ring_idx + (int64_t)r_new * bmax;
-    for (int p = tid; p < b; p += nt) {
-        uint32_t key = keys[p];
-        int lab = (int)(key >> 14);
-        int pos = (int)(key & 0x3FFFu);
-        perm[p] = pos;
-        slot[p] = batidx[pos];
-        int prev = p == 0 ? -1 : (int)(keys[p - 1] >> 14);
-        for (int j = prev + 1; j <= lab; ++j)
-            off[j] = p;
-        if (p == b - 1)
-            for (int j = lab + 1; j <= k; ++j)
-                off[j] = b;
-    }
-    __syncthreads();
-    const int C = W + 1;
-    for (int j = tid; j < k; j += nt) {
-        int bj = off[j + 1] - off[j];
+        const int bj = gb - run;
+        run = gb;
         counts[j] = bj;
         double a;
         if (lr == MBKK_LR_FULL)
             a = bj > 0 ? 1.0 : 0.0;
         else if (lr == MBKK_LR_SKLEARN) {
-            double c = cum[j] + (double)bj;
-            cum[j] = c;
-            a = bj > 0 ? (double)bj / c : 0.0;
+            const double cs = cum[j] + (double)bj;
+            cum[j] = cs;
+            a = bj > 0 ? (double)bj / cs : 0.0;
         } else
             a = sqrt((double)bj / (double)b);
         alpha[j] = a;
+        // C_{i+1} = (1 - a) C_i + a cm(B_i^j), truncated to the window
         double *cf = coef + (int64_t)j * C;
         if (init_alive_before)
             cf[0] *= (1.0 - a);
         for (int s = 0; s < live.n; ++s)
             cf[1 + live.r[s]] *= (1.0 - a);
-        cf[1 + r_new] = bj > 0 ? a / (double)bj : 0.0;
+        cf[1 + p_new] = bj > 0 ? a / (double)bj : 0.0;
+        if (p_expired >= 0)
+            cf[1 + p_expired] = 0.0;
         if (!init_keep)
             cf[0] = 0.0;
     }
+    if (tid == nt - 1)
+        off[k] = b;
     // sum of min distances (FP64), fixed-order tree
-    double s = 0.0;
+    double sm = 0.0;
     for (int p = tid; p < b; p += nt)
-        s += (double)mind[p];
-    __shared__ double red[1024];
-    red[tid] = s;
+        sm += (double)mind[p];
+    red[tid] = sm;
     __syncthreads();
     for (int h = nt / 2; h > 0; h >>= 1) {
         if (tid < h)
@@ -431,119 +447,144 @@ __global__ __launch_bounds__(1024) void k_update(
     build_chunks(k, gram_rows, off, chunk_off, chunk_j, chunk_a0, chunk_a1, nchunks, scratch);
 }
 
-void launch_update(const Layout &L, const Buffers &B, int b, int r_new, int init_alive_before,
-                   int init_keep, const SlotList &live, int lr, hipStream_t st)
+__global__ __launch_bounds__(kChunk) void k_group_scatter(int b, int k, const int32_t *__restrict__ labels,
+                                                           const int32_t *__restrict__ rank,
+                                                           const int32_t *__restrict__ gbase,
+                                                           const int32_t *__restrict__ pts,
+                                                           int32_t *__restrict__ ring_idx,
+                                                           int32_t *__restrict__ ring_perm)
 {
-    int P2 = 1;
-    while (P2 < b)
-        P2 <<= 1;
-    size_t shmem = (size_t)P2 * 4 + 1024 * 4;
-    hipLaunchKernelGGL(k_update, dim3(1), dim3(1024), shmem, st, b, L.k, L.W, r_new, init_alive_before,
-                       init_keep, live, lr, L.gram_rows, B.labels, B.batidx, B.mind, B.ring_idx, B.ring_off, L.bmax,
-                       B.coef, B.cum, B.counts, B.alpha, B.perm, B.chunk_off, B.chunk_j, B.chunk_a0,
-                       B.chunk_a1, B.nchunks, B.obj);
-}
-
-// ---------------------------------------------------------------------------
-// Copies staged batch rows into ring slot r in grouped order:
-// pool row k + r*bmax + p <- batch row perm[p].  One wave per row.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_slot_copy(int b, int dp, int64_t row0, const int32_t *__restrict__ perm,
-                                                    const float *__restrict__ bat32, const uint16_t *__restrict__ bathi,
-                                                    const uint16_t *__restrict__ batlo, const float *__restrict__ batsq,
-                                                    const double *__restrict__ batsq64, float *__restrict__ pool32,
-                                                    uint16_t *__restrict__ poolhi, uint16_t *__restrict__ poollo,
-                                                    float *__restrict__ poolsq, double *__restrict__ poolsq64)
-{
-    const int lane = threadIdx.x & 63;
-    const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int g = blockIdx.x;
+    const int p = g * kChunk + threadIdx.x;
     if (p >= b)
         return;
-    const int src = perm[p];
-    const int64_t dst = row0 + p;
-    for (int t = lane; t < dp; t += 64) {
-        pool32[dst * dp + t] = bat32[(int64_t)src * dp + t];
-        if (poolhi) {
-            poolhi[dst * dp + t] = bathi[(int64_t)src * dp + t];
-            poollo[dst * dp + t] = batlo[(int64_t)src * dp + t];
+    const int lab = min(max(labels[p], 0), k - 1);
+    const int pos = gbase[(int64_t)g * k + lab] + rank[p];
+    ring_perm[pos] = p;
+    ring_idx[pos] = pts[p];
+}
+
+void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
+                   int init_keep, const SlotList &live, int lr, hipStream_t st)
+{
+    const int nchunk = (b + kChunk - 1) / kChunk;
+    hipLaunchKernelGGL(k_group_rank, dim3(nchunk), dim3(kChunk), 0, st, b, L.k, B.labels, B.rank, B.gcnt);
+    hipLaunchKernelGGL(k_group_offsets, dim3(1), dim3(1024), 0, st, b, L.k, nchunk, L.C, p_new, p_expired,
+                       init_alive_before, init_keep, live, lr, L.gram_rows, B.gcnt, B.mind, B.coef, B.cum,
+                       B.counts, B.alpha, B.ring_off + (int64_t)p_new * (L.k + 1), B.chunk_off, B.chunk_j,
+                       B.chunk_a0, B.chunk_a1, B.nchunks, B.obj);
+    hipLaunchKernelGGL(k_group_scatter, dim3(nchunk), dim3(kChunk), 0, st, b, L.k, B.labels, B.rank, B.gcnt,
+                       B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,
+                       B.ring_perm + (int64_t)p_new * L.bmax);
+}
+
+// ---------------------------------------------------------------------------
+// Gram blocks of slot rr against every live column (FP32 or FP64 kernel
+// values, FP64 sums):  for each work item q = (j, grouped positions a0..a1 of
+// slot rr) and column c,
+//   Gpart[q][c] = sum_{a in q} sum_{e in column c, center j} K(a, e).
+// Column 0 is the initial point of center j; column 1+p is slot p.
+// Grid: (maxchunks, C); work items past *nchunks exit.  Each workgroup walks
+// the column's rows in tiles of 16; a thread owns one (a, e) pair, and both
+// row sets are staged through LDS 64 coordinates at a time, so any d works.
+// ---------------------------------------------------------------------------
+constexpr int kGramTile = 16, kGramK = 64, kGramLd = kGramK + 4;  // 272-byte LDS rows
+
+template <int KIND, typename KT>
+__device__ __forceinline__ void gram_acc4(KT &s, const float4 a, const float4 e)
+{
+    const float av[4] = {a.x, a.y, a.z, a.w}, ev[4] = {e.x, e.y, e.z, e.w};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const KT x = (KT)av[u], y = (KT)ev[u];
+        if constexpr (KIND == MBKK_GAUSS) {
+            const KT v = x - y;
+            s = fma(v, v, s);
+        } else if constexpr (KIND == MBKK_LAPLACE) {
+            s += fabs(x - y);
+        } else {
+            s = fma(x, y, s);
         }
     }
-    if (lane == 0) {
-        poolsq[dst] = batsq[src];
-        poolsq64[dst] = batsq64[src];
-    }
 }
 
-void launch_slot_copy(const Layout &L, const Buffers &B, int b, int r, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_slot_copy, dim3((b + 3) / 4), dim3(256), 0, st, b, L.dp, (int64_t)L.k + (int64_t)r * L.bmax,
-                       B.perm, B.bat32, B.bathi, B.batlo, B.batsq, B.batsq64, B.pool32, B.poolhi, B.poollo,
-                       B.poolsq, B.poolsq64);
-}
-
-// ---------------------------------------------------------------------------
-// Pool rows of a ring slot straight from X (set_state): pool row
-// k + r*bmax + p <- X[ring_idx[r][p]].
-// ---------------------------------------------------------------------------
-void launch_pool_slot_from_X(const Layout &L, const Buffers &B, int r, int cnt, hipStream_t st)
-{
-    const int64_t row0 = (int64_t)L.k + (int64_t)r * L.bmax;
-    launch_gather_rows(B.X, L.n, L.d, B.ld, B.ring_idx + (int64_t)r * L.bmax, cnt, L.dp,
-                       B.pool32 + row0 * L.dp, B.poolhi ? B.poolhi + row0 * L.dp : nullptr,
-                       B.poollo ? B.poollo + row0 * L.dp : nullptr, B.poolsq + row0, B.poolsq64 + row0,
-                       nullptr, B.flags, 0, st);
-}
-
-// ---------------------------------------------------------------------------
-// Gram blocks of ring slot rr against every live column (FP32 or FP64 kernel
-// values, FP64 sums):  for each work item q = (j, rows a0..a1 of slot rr) and
-// column c,  Gpart[q][c] = sum_{a in q} sum_{e in column c, center j} K(a, e).
-// Column 0 is the initial point of center j; column 1+r is slot r.
-// Grid: (maxchunks, W+1).  Work items past *nchunks exit.
-// ---------------------------------------------------------------------------
-template <typename KT>
-__global__ __launch_bounds__(256) void k_gram(int k, int W, int bmax, int d, int dp, int kind, double param,
-                                               int rr, uint32_t col_mask, const int32_t *__restrict__ ring_off,
+template <int KIND, typename KT>
+__global__ __launch_bounds__(256) void k_gram(int k, int C, int bmax, int d, int dp, double param, int rr,
+                                               uint32_t col_mask, const int32_t *__restrict__ ring_off,
+                                               const int32_t *__restrict__ ring_perm,
                                                const float *__restrict__ pool32,
                                                const int32_t *__restrict__ nchunks,
                                                const int32_t *__restrict__ chunk_j,
                                                const int32_t *__restrict__ chunk_a0,
                                                const int32_t *__restrict__ chunk_a1, double *__restrict__ Gpart)
 {
-    extern __shared__ float arows[];  // [gram_rows * dp]
+    __shared__ __attribute__((aligned(16))) float sa[kGramTile][kGramLd];
+    __shared__ __attribute__((aligned(16))) float se[kGramTile][kGramLd];
     __shared__ double red[256];
     const int q = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
     if (q >= *nchunks)
         return;
-    const int C = W + 1;
     if (!((col_mask >> c) & 1u)) {
         if (tid == 0)
             Gpart[(int64_t)q * C + c] = 0.0;
         return;
     }
-    const int j = chunk_j[q], a0 = chunk_a0[q], a1 = chunk_a1[q];
-    const int na = a1 - a0;
-    const int64_t arow0 = (int64_t)k + (int64_t)rr * bmax + a0;
-    for (int t = tid; t < na * dp; t += 256)
-        arows[t] = pool32[arow0 * dp + t];
-    int64_t e0;
+    const int j = chunk_j[q], a0 = chunk_a0[q];
+    const int na = chunk_a1[q] - a0;
+    const int pa = tid >> 4, pe = tid & 15;      // this thread's pair
+    const int lr = tid >> 4, lc = (tid & 15) * 4;  // loader: row, 4 columns
+    // pool rows of the loader's a-row and of the column's rows
+    const int64_t arow = lr < na ? (int64_t)k + (int64_t)rr * bmax + ring_perm[(int64_t)rr * bmax + a0 + lr] : 0;
     int ne;
+    int64_t erow0 = 0;
+    const int32_t *eperm = nullptr;
     if (c == 0) {
-        e0 = j;
         ne = 1;
+        erow0 = j;
     } else {
-        const int32_t *o = ring_off + (int64_t)(c - 1) * (k + 1);
-        e0 = (int64_t)k + (int64_t)(c - 1) * bmax + o[j];
+        const int pc = c - 1;
+        const int32_t *o = ring_off + (int64_t)pc * (k + 1);
         ne = o[j + 1] - o[j];
+        eperm = ring_perm + (int64_t)pc * bmax + o[j];
+        erow0 = (int64_t)k + (int64_t)pc * bmax;
     }
-    __syncthreads();
     const KT prm = (KT)param;
-    double s = 0.0;
-    for (int pr = tid; pr < na * ne; pr += 256) {
-        const int a = pr / ne, e = pr % ne;
-        s += (double)kernel_value<KT>(kind, prm, arows + a * dp, pool32 + (e0 + e) * dp, d);
+    double acc = 0.0;
+    for (int et = 0; et < ne; et += kGramTile) {
+        const bool eok = et + lr < ne;
+        const int64_t erow = eok ? (c == 0 ? erow0 : erow0 + eperm[et + lr]) : 0;
+        KT sacc = 0;
+        // coordinates past d are zero in the pool, so whole 64-wide chunks
+        // can be processed
+        for (int t0 = 0; t0 < d; t0 += kGramK) {
+            __syncthreads();
+            {
+                const int col = t0 + lc;
+                float4 va = make_float4(0.f, 0.f, 0.f, 0.f), ve = va;
+                if (lr < na && col < dp)
+                    va = *(const float4 *)(pool32 + arow * dp + col);
+                if (eok && col < dp)
+                    ve = *(const float4 *)(pool32 + erow * dp + col);
+                *(float4 *)&sa[lr][lc] = va;
+                *(float4 *)&se[lr][lc] = ve;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < kGramK; t += 4)
+                gram_acc4<KIND, KT>(sacc, *(const float4 *)&sa[pa][t], *(const float4 *)&se[pe][t]);
+        }
+        if (pa < na && et + pe < ne) {
+            KT kv;
+            if constexpr (KIND == MBKK_GAUSS || KIND == MBKK_LAPLACE)
+                kv = (KT)exp(-sacc / prm);
+            else if constexpr (KIND == MBKK_LINEAR)
+                kv = sacc;
+            else
+                kv = (sacc + prm) * (sacc + prm);
+            acc += (double)kv;
+        }
     }
-    red[tid] = s;
+    red[tid] = acc;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
         if (tid < h)
@@ -554,31 +595,41 @@ __global__ __launch_bounds__(256) void k_gram(int k, int W, int bmax, int d, int
         Gpart[(int64_t)q * C + c] = red[0];
 }
 
-void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param,
-                 int fp64, hipStream_t st)
+template <typename KT>
+static void launch_gram_t(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param,
+                          hipStream_t st)
 {
-    dim3 grid((unsigned)L.maxchunks, L.W + 1);
-    size_t shmem = (size_t)L.gram_rows * L.dp * sizeof(float);
+    dim3 grid((unsigned)L.maxchunks, L.C);
+#define MBKK_GRAM(K)                                                                                             \
+    hipLaunchKernelGGL((k_gram<K, KT>), grid, dim3(256), 0, st, L.k, L.C, L.bmax, L.d, L.dp, param, rr, col_mask, \
+                       B.ring_off, B.ring_perm, B.pool32, B.nchunks, B.chunk_j, B.chunk_a0, B.chunk_a1, B.Gpart)
+    switch (kind) {
+    case MBKK_GAUSS: MBKK_GRAM(MBKK_GAUSS); break;
+    case MBKK_LAPLACE: MBKK_GRAM(MBKK_LAPLACE); break;
+    case MBKK_LINEAR: MBKK_GRAM(MBKK_LINEAR); break;
+    default: MBKK_GRAM(MBKK_POLY2); break;
+    }
+#undef MBKK_GRAM
+}
+
+void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param, int fp64,
+                 hipStream_t st)
+{
     if (fp64)
-        hipLaunchKernelGGL(k_gram<double>, grid, dim3(256), shmem, st, L.k, L.W, L.bmax, L.d, L.dp, kind, param,
-                           rr, col_mask, B.ring_off, B.pool32, B.nchunks, B.chunk_j, B.chunk_a0, B.chunk_a1,
-                           B.Gpart);
+        launch_gram_t<double>(L, B, rr, col_mask, kind, param, st);
     else
-        hipLaunchKernelGGL(k_gram<float>, grid, dim3(256), shmem, st, L.k, L.W, L.bmax, L.d, L.dp, kind, param,
-                           rr, col_mask, B.ring_off, B.pool32, B.nchunks, B.chunk_j, B.chunk_a0, B.chunk_a1,
-                           B.Gpart);
+        launch_gram_t<float>(L, B, rr, col_mask, kind, param, st);
 }
 
 // Folds the work-item partials of slot rr into G_j[1+rr][c] = G_j[c][1+rr]
 // (fixed order over the work items of center j).  One thread per center.
-__global__ __launch_bounds__(256) void k_gram_fold(int k, int W, int rr, uint32_t col_mask,
+__global__ __launch_bounds__(256) void k_gram_fold(int k, int C, int rr, uint32_t col_mask,
                                                     const int32_t *__restrict__ chunk_off,
                                                     const double *__restrict__ Gpart, double *__restrict__ G)
 {
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= k)
         return;
-    const int C = W + 1;
     double *g = G + (int64_t)j * C * C;
     const int q0 = chunk_off[j], q1 = chunk_off[j + 1];
     for (int c = 0; c < C; ++c) {
@@ -594,7 +645,7 @@ __global__ __launch_bounds__(256) void k_gram_fold(int k, int W, int rr, uint32_
 
 void launch_gram_fold(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gram_fold, dim3((L.k + 255) / 256), dim3(256), 0, st, L.k, L.W, rr, col_mask,
+    hipLaunchKernelGGL(k_gram_fold, dim3((L.k + 255) / 256), dim3(256), 0, st, L.k, L.C, rr, col_mask,
                        B.chunk_off, B.Gpart, B.G);
 }
 

@@ -26,7 +26,7 @@ struct mbkk_ctx {
     int pending_r = -1;         // ring slot whose Gram partials still have to be folded
     uint32_t pending_mask = 0;  // their live columns
     int64_t support_iter = -1;  // iteration for which the support layout is built
-    std::vector<int32_t> slot_b;  // points held by each ring slot
+    std::vector<int32_t> slot_b;  // points held by each physical slot
     // timing of the cross-term kernel
     bool timing = false;
     std::vector<hipEvent_t> ev;  // pairs (start, stop)
@@ -77,16 +77,28 @@ Layout make_layout(const mbkk_config &c)
     L.dp = (int)up((size_t)c.d, kDimAlign);
     L.k = c.k;
     L.W = c.window;
+    L.P = c.window + 1;
+    L.C = L.P + 1;
     L.bmax = c.b_max;
     L.pad = wants_mfma(c) ? kMfmaPad : 1;
     L.bf16 = c.precision == MBKK_BF16X3 || c.precision == MBKK_BF16X1;
-    L.PR = (int64_t)c.k + (int64_t)c.window * c.b_max;
-    L.Mcap = (int64_t)up((size_t)(L.PR + (int64_t)c.k * (L.pad - 1) + L.pad), 128);
+    L.PR = (int64_t)c.k + (int64_t)L.P * c.b_max;
+    // live support: at most W slots of b_max points and the k initial points
+    const int64_t Mlive = (int64_t)c.k + (int64_t)c.window * c.b_max;
+    L.Mcap = (int64_t)up((size_t)(Mlive + (int64_t)c.k * (L.pad - 1) + L.pad), 128);
     L.nblk = L.Mcap / 32;
-    // Gram work items stage their rows in LDS: at most 48 KB of FP32 rows
-    L.gram_rows = (int)(12288 / L.dp);
-    L.gram_rows = L.gram_rows < 1 ? 1 : (L.gram_rows > kGramRowsMax ? kGramRowsMax : L.gram_rows);
+    L.gram_rows = kGramRowsMax;  // rows of the newest slot per Gram work item
+    // ranges of the batch-stationary MFMA kernel: about 1024 workgroups at
+    // b = b_max, an even number of blocks each (blocks are staged in pairs)
+    {
+        const int64_t nbt = (c.b_max + 255) / 256;
+        int64_t rb = (L.nblk * nbt + 1023) / 1024;
+        rb = rb < 2 ? 2 : rb;
+        rb += rb & 1;
+        L.mfma_rb = (int)rb;
+    }
     L.maxchunks = c.b_max / L.gram_rows + c.k + 1;
+    L.nchunk = (c.b_max + kChunk - 1) / kChunk;
     L.kpp_blocks = (c.n + 255) / 256;
     return L;
 }
@@ -103,21 +115,17 @@ void carve(const Layout &Lc, char *base, Buffers &B)
         return p;
     };
     const int64_t prows = L.PR + 1;
-    const int C = L.W + 1;
+    const int C = L.C;
     B.sqn = (float *)take(sizeof(float) * L.n);
     B.pool32 = (float *)take(sizeof(float) * prows * L.dp);
     B.poolhi = L.bf16 ? (uint16_t *)take(2 * prows * L.dp) : nullptr;
     B.poollo = L.bf16 ? (uint16_t *)take(2 * prows * L.dp) : nullptr;
     B.poolsq = (float *)take(sizeof(float) * prows);
     B.poolsq64 = (double *)take(sizeof(double) * prows);
-    B.batidx = (int32_t *)take(4 * L.bmax);
-    B.bat32 = (float *)take(sizeof(float) * (size_t)L.bmax * L.dp);
-    B.bathi = L.bf16 ? (uint16_t *)take(2 * (size_t)L.bmax * L.dp) : nullptr;
-    B.batlo = L.bf16 ? (uint16_t *)take(2 * (size_t)L.bmax * L.dp) : nullptr;
-    B.batsq = (float *)take(sizeof(float) * L.bmax);
-    B.batsq64 = (double *)take(sizeof(double) * L.bmax);
-    B.ring_idx = (int32_t *)take(4 * (size_t)L.W * L.bmax);
-    B.ring_off = (int32_t *)take(4 * (size_t)L.W * (L.k + 1));
+    B.slot_pts = (int32_t *)take(4 * (size_t)L.P * L.bmax);
+    B.ring_idx = (int32_t *)take(4 * (size_t)L.P * L.bmax);
+    B.ring_perm = (int32_t *)take(4 * (size_t)L.P * L.bmax);
+    B.ring_off = (int32_t *)take(4 * (size_t)L.P * (L.k + 1));
     B.init_idx = (int32_t *)take(4 * (size_t)L.k);
     B.coef = (double *)take(8 * (size_t)L.k * C);
     B.cum = (double *)take(8 * (size_t)L.k);
@@ -125,6 +133,8 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.N = (double *)take(8 * (size_t)L.k);
     B.counts = (int32_t *)take(4 * (size_t)L.k);
     B.alpha = (double *)take(8 * (size_t)L.k);
+    B.rank = (int32_t *)take(4 * (size_t)L.bmax);
+    B.gcnt = (int32_t *)take(4 * (size_t)L.nchunk * L.k);
     B.chunk_j = (int32_t *)take(4 * L.maxchunks);
     B.chunk_a0 = (int32_t *)take(4 * L.maxchunks);
     B.chunk_a1 = (int32_t *)take(4 * L.maxchunks);
@@ -141,7 +151,6 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.labels = (int32_t *)take(4 * (size_t)L.bmax);
     B.mind = (float *)take(4 * (size_t)L.bmax);
     B.margin = (float *)take(4 * (size_t)L.bmax);
-    B.perm = (int32_t *)take(4 * (size_t)L.bmax);
     B.obj = (double *)take(8 * 4);
     B.flags = (int32_t *)take(4 * 4);
     B.nchunks = (int32_t *)take(4);
@@ -216,15 +225,17 @@ static int check_config(const mbkk_config *c, std::string &why)
     return MBKK_OK;
 }
 
-// Live ring slots of the centers C_i (state before iteration i): batches
-// max(1, i-W) .. i-1, oldest first.
+// Physical slots of the batches live in C_i (the state before iteration i):
+// batches max(1, i-W) .. i-1, oldest first; batch l lives in slot (l-1) mod P.
+static int phys_of(int64_t l, int P) { return (int)((l - 1) % P); }
+
 static SlotList live_before(int64_t i, int W)
 {
     SlotList s;
     s.n = 0;
-    int64_t lo = i - W < 1 ? 1 : i - W;
+    const int64_t lo = i - W < 1 ? 1 : i - W;
     for (int64_t l = lo; l <= i - 1; ++l)
-        s.r[s.n++] = (int)((l - 1) % W);
+        s.r[s.n++] = phys_of(l, W + 1);
     return s;
 }
 
@@ -256,14 +267,28 @@ static int clear_flags(mbkk_ctx *c)
 
 static double tie_delta(const mbkk_config &c) { return c.tie_delta > 0.0 ? c.tie_delta : 4e-3; }
 
-// Gathers rows idx[0..cnt) of X into the batch staging buffers.
+// Points the batch view at physical slot p (the free slot of the iteration).
+static void set_batch_view(mbkk_ctx *c, int p)
+{
+    const Layout &L = c->L;
+    Buffers &B = c->B;
+    const int64_t r0 = slot_row(L, p, 0);
+    B.batidx = B.slot_pts + (int64_t)p * L.bmax;
+    B.bat32 = B.pool32 + r0 * L.dp;
+    B.bathi = L.bf16 ? B.poolhi + r0 * L.dp : nullptr;
+    B.batlo = L.bf16 ? B.poollo + r0 * L.dp : nullptr;
+    B.batsq = B.poolsq + r0;
+    B.batsq64 = B.poolsq64 + r0;
+}
+
+// Gathers rows idx[0..cnt) of X into the free slot of the current iteration.
 static void stage_rows(mbkk_ctx *c, const int32_t *idx, int64_t cnt)
 {
     const Layout &L = c->L;
     Buffers &B = c->B;
-    launch_gather_rows(B.X, L.n, L.d, B.ld, idx, cnt, L.dp, B.bat32, L.bf16 ? B.bathi : nullptr,
-                       L.bf16 ? B.batlo : nullptr, B.batsq, B.batsq64, B.batidx, B.flags, c->cfg.validate,
-                       c->stream);
+    set_batch_view(c, phys_of(c->iter, L.P));
+    launch_gather_rows(B.X, L.n, L.d, B.ld, idx, cnt, L.dp, B.bat32, B.bathi, B.batlo, B.batsq, B.batsq64,
+                       B.batidx, B.flags, c->cfg.validate, c->stream);
 }
 
 // Folds pending Gram partials and (re)builds the support of the current
@@ -278,7 +303,7 @@ static void prepare_support(mbkk_ctx *c)
     if (c->support_iter != c->iter) {
         SlotList live = live_before(c->iter, L.W);
         const int init_alive = c->iter <= L.W + 1;
-        launch_support_fill(L, c->B, live, init_alive, L.pad, c->stream);
+        launch_support_fill(L, c->B, live, init_alive, c->stream);
         c->support_iter = c->iter;
     }
 }
@@ -290,7 +315,7 @@ static int cross_and_score(mbkk_ctx *c, int nb, double *D_out, int64_t ldD)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
         if (c->ev_used + 2 > c->ev.size()) {
-            for (int q = 0; q < 64; ++q) {
+            for (int q = 0; q < 256; ++q) {
                 hipEvent_t e;
                 HIPCHK(c, hipEventCreate(&e));
                 c->ev.push_back(e);
@@ -356,7 +381,7 @@ int mbkk_create(const mbkk_config *cfg, void *workspace, size_t bytes, void *str
     c->stream = (hipStream_t)stream;
     c->use_mfma = wants_mfma(*cfg);
     c->fp64 = cfg->precision == MBKK_FP64;
-    c->slot_b.assign(cfg->window, 0);
+    c->slot_b.assign(L.P, 0);
     // zero row of the pool (segment padding target) and error flags
     const int64_t zr = L.PR;
     hipError_t e = hipMemsetAsync(c->B.pool32 + zr * L.dp, 0, sizeof(float) * L.dp, c->stream);
@@ -371,7 +396,7 @@ int mbkk_create(const mbkk_config *cfg, void *workspace, size_t bytes, void *str
     if (e == hipSuccess)
         e = hipMemsetAsync(c->B.flags, 0, 16, c->stream);
     if (e == hipSuccess)
-        e = hipMemsetAsync(c->B.ring_off, 0, 4 * (size_t)L.W * (L.k + 1), c->stream);
+        e = hipMemsetAsync(c->B.ring_off, 0, 4 * (size_t)L.P * (L.k + 1), c->stream);
     if (e != hipSuccess) {
         delete c;
         return fail(nullptr, MBKK_E_HIP, std::string("workspace init: ") + hipGetErrorString(e));
@@ -417,9 +442,8 @@ static int init_common(mbkk_ctx *c, const int32_t *idx_dev)
     launch_gather_rows(B.X, L.n, L.d, B.ld, idx_dev, L.k, L.dp, B.pool32, L.bf16 ? B.poolhi : nullptr,
                        L.bf16 ? B.poollo : nullptr, B.poolsq, B.poolsq64, B.init_idx, B.flags, c->cfg.validate,
                        c->stream);
-    launch_init_state(L.k, L.W, c->cfg.kernel, c->cfg.kernel_param, L.d, L.dp, B.pool32, B.coef, B.cum, B.G,
-                      c->fp64, c->stream);
-    HIPCHK(c, hipMemsetAsync(B.ring_off, 0, 4 * (size_t)L.W * (L.k + 1), c->stream));
+    launch_init_state(L, B, c->cfg.kernel, c->cfg.kernel_param, c->fp64, 1, c->stream);
+    HIPCHK(c, hipMemsetAsync(B.ring_off, 0, 4 * (size_t)L.P * (L.k + 1), c->stream));
     HIPCHK(c, hipGetLastError());
     c->iter = 1;
     c->pending_r = -1;
@@ -488,19 +512,20 @@ int mbkk_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels_dev,
     if (rc)
         return rc;
     // update of the centers
+    const int P = L.P;
     const SlotList live = live_before(i, W);
     const int init_alive_before = i <= W + 1;
     const int init_keep = i <= W;
-    const int r_new = (int)((i - 1) % W);
-    launch_update(L, B, b, r_new, init_alive_before, init_keep, live, c->cfg.lr, c->stream);
-    launch_slot_copy(L, B, b, r_new, c->stream);
+    const int p_new = phys_of(i, P);
+    const int p_expired = i - W >= 1 ? phys_of(i - W, P) : -1;
+    launch_update(L, B, b, p_new, p_expired, init_alive_before, init_keep, live, c->cfg.lr, c->stream);
     const SlotList live_after = live_before(i + 1, W);
     const uint32_t mask = col_mask_of(live_after, init_keep);
-    launch_gram(L, B, r_new, mask, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->stream);
+    launch_gram(L, B, p_new, mask, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->stream);
     HIPCHK(c, hipGetLastError());
-    c->pending_r = r_new;
+    c->pending_r = p_new;
     c->pending_mask = mask;
-    c->slot_b[r_new] = b;
+    c->slot_b[p_new] = b;
     c->iter = i + 1;
     if (labels_dev)
         HIPCHK(c, hipMemcpyAsync(labels_dev, B.labels, 4 * (size_t)b, hipMemcpyDeviceToDevice, c->stream));
@@ -602,17 +627,33 @@ int mbkk_get_state(mbkk_ctx *c, mbkk_state *s)
     if (!s || s->k != L.k || s->window != L.W || s->b_max != L.bmax || !s->init_idx || !s->slot_b ||
         !s->slot_idx || !s->slot_off || !s->coef || !s->cum)
         return fail(c, MBKK_E_INVALID, "state buffers missing or shaped for another configuration");
-    const int C = L.W + 1;
-    s->iteration = c->iter;
-    for (int r = 0; r < L.W; ++r)
-        s->slot_b[r] = c->slot_b[r];
+    const int W = L.W, P = L.P, C = L.C, Cs = W + 1;
+    const int64_t i = c->iter;
+    std::vector<int32_t> ridx((size_t)P * L.bmax), roff((size_t)P * (L.k + 1));
+    std::vector<double> coef((size_t)L.k * C);
     HIPCHK(c, hipMemcpyAsync(s->init_idx, c->B.init_idx, 4 * (size_t)L.k, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(s->slot_idx, c->B.ring_idx, 4 * (size_t)L.W * L.bmax, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(s->slot_off, c->B.ring_off, 4 * (size_t)L.W * (L.k + 1), hipMemcpyDeviceToHost,
-                             c->stream));
-    HIPCHK(c, hipMemcpyAsync(s->coef, c->B.coef, 8 * (size_t)L.k * C, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(ridx.data(), c->B.ring_idx, 4 * ridx.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(roff.data(), c->B.ring_off, 4 * roff.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(coef.data(), c->B.coef, 8 * coef.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(s->cum, c->B.cum, 8 * (size_t)L.k, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    // physical slot of batch l -> logical slot (l-1) mod W of the state image
+    s->iteration = i;
+    for (int r = 0; r < W; ++r)
+        s->slot_b[r] = 0;
+    memset(s->slot_off, 0, sizeof(int32_t) * (size_t)W * (L.k + 1));
+    for (int j = 0; j < L.k; ++j)
+        for (int cc = 0; cc < Cs; ++cc)
+            s->coef[(size_t)j * Cs + cc] = cc == 0 ? coef[(size_t)j * C] : 0.0;
+    const int64_t lo = i - W < 1 ? 1 : i - W;
+    for (int64_t l = lo; l <= i - 1; ++l) {
+        const int p = phys_of(l, P), r = (int)((l - 1) % W);
+        s->slot_b[r] = c->slot_b[p];
+        memcpy(s->slot_idx + (size_t)r * L.bmax, ridx.data() + (size_t)p * L.bmax, 4 * (size_t)L.bmax);
+        memcpy(s->slot_off + (size_t)r * (L.k + 1), roff.data() + (size_t)p * (L.k + 1), 4 * (size_t)(L.k + 1));
+        for (int j = 0; j < L.k; ++j)
+            s->coef[(size_t)j * Cs + 1 + r] = coef[(size_t)j * C + 1 + p];
+    }
     return MBKK_OK;
 }
 
@@ -626,21 +667,21 @@ int mbkk_set_state(mbkk_ctx *c, const mbkk_state *s)
     if (!s || s->k != L.k || s->window != L.W || s->b_max != L.bmax || !s->init_idx || !s->slot_b ||
         !s->slot_idx || !s->slot_off || !s->coef || !s->cum || s->iteration < 1)
         return fail(c, MBKK_E_INVALID, "state buffers missing or shaped for another configuration");
-    const int W = L.W, C = W + 1;
+    const int W = L.W, P = L.P, C = L.C, Cs = W + 1;
     const int64_t i = s->iteration;
-    const SlotList live = live_before(i, W);
     const bool init_alive = i <= W + 1;
-    // host-side validation of the slot contents
-    for (int q = 0; q < live.n; ++q) {
-        const int r = live.r[q];
+    const int64_t lo = i - W < 1 ? 1 : i - W;
+    // host-side validation of the live logical slots (batch l in slot (l-1) mod W)
+    for (int64_t l = lo; l <= i - 1; ++l) {
+        const int r = (int)((l - 1) % W);
         const int32_t *off = s->slot_off + (int64_t)r * (L.k + 1);
         if (s->slot_b[r] < 1 || s->slot_b[r] > L.bmax || off[0] != 0 || off[L.k] != s->slot_b[r])
             return fail(c, MBKK_E_INVALID, "slot offsets inconsistent with slot sizes");
         for (int j = 0; j < L.k; ++j)
             if (off[j + 1] < off[j])
                 return fail(c, MBKK_E_INVALID, "slot offsets not monotone");
-        for (int p = 0; p < s->slot_b[r]; ++p) {
-            int32_t v = s->slot_idx[(int64_t)r * L.bmax + p];
+        for (int q = 0; q < s->slot_b[r]; ++q) {
+            const int32_t v = s->slot_idx[(int64_t)r * L.bmax + q];
             if (v < 0 || v >= L.n)
                 return fail(c, MBKK_E_INDEX, "slot index outside [0, n)");
         }
@@ -649,45 +690,56 @@ int mbkk_set_state(mbkk_ctx *c, const mbkk_state *s)
         if (s->init_idx[j] < 0 || s->init_idx[j] >= L.n)
             return fail(c, MBKK_E_INDEX, "initial index outside [0, n)");
     Buffers &B = c->B;
-    // coefficients of dead columns are forced to zero
-    std::vector<double> coef(s->coef, s->coef + (size_t)L.k * C);
-    const uint32_t mask = col_mask_of(live, init_alive);
+    // physical images: batch l -> slot (l-1) mod P, rows in the image's
+    // grouped order (identity permutation); dead columns get coefficient 0
+    std::vector<double> coef((size_t)L.k * C, 0.0);
+    std::vector<int32_t> offs((size_t)P * (L.k + 1), 0), idx((size_t)P * L.bmax, 0), perm((size_t)P * L.bmax, 0);
+    std::vector<int32_t> sb(P, 0);
     for (int j = 0; j < L.k; ++j)
-        for (int cc = 0; cc < C; ++cc)
-            if (!((mask >> cc) & 1u))
-                coef[(size_t)j * C + cc] = 0.0;
-    std::vector<int32_t> offs(s->slot_off, s->slot_off + (size_t)W * (L.k + 1));
-    for (int r = 0; r < W; ++r) {
-        bool alive = false;
-        for (int q = 0; q < live.n; ++q)
-            alive |= live.r[q] == r;
-        if (!alive)
-            std::fill(offs.begin() + (size_t)r * (L.k + 1), offs.begin() + (size_t)(r + 1) * (L.k + 1), 0);
+        coef[(size_t)j * C] = init_alive ? s->coef[(size_t)j * Cs] : 0.0;
+    for (int64_t l = lo; l <= i - 1; ++l) {
+        const int r = (int)((l - 1) % W), p = phys_of(l, P);
+        sb[p] = s->slot_b[r];
+        memcpy(offs.data() + (size_t)p * (L.k + 1), s->slot_off + (size_t)r * (L.k + 1), 4 * (size_t)(L.k + 1));
+        memcpy(idx.data() + (size_t)p * L.bmax, s->slot_idx + (size_t)r * L.bmax, 4 * (size_t)sb[p]);
+        for (int q = 0; q < sb[p]; ++q)
+            perm[(size_t)p * L.bmax + q] = q;
+        for (int j = 0; j < L.k; ++j)
+            coef[(size_t)j * C + 1 + p] = s->coef[(size_t)j * Cs + 1 + r];
     }
-    HIPCHK(c, hipMemcpyAsync(B.ring_idx, s->slot_idx, 4 * (size_t)W * L.bmax, hipMemcpyHostToDevice, c->stream));
+    const SlotList live = live_before(i, W);
+    const uint32_t mask = col_mask_of(live, init_alive);
+    HIPCHK(c, hipMemcpyAsync(B.ring_idx, idx.data(), 4 * idx.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(B.slot_pts, idx.data(), 4 * idx.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(B.ring_perm, perm.data(), 4 * perm.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(B.ring_off, offs.data(), 4 * offs.size(), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(B.cum, s->cum, 8 * (size_t)L.k, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(B.picks, s->init_idx, 4 * (size_t)L.k, hipMemcpyHostToDevice, c->stream));
-    // initial points and G[j][0][0] (init_state also resets coef; uploaded below)
-    launch_gather_rows(B.X, L.n, L.d, B.ld, B.picks, L.k, L.dp, B.pool32, L.bf16 ? B.poolhi : nullptr,
-                       L.bf16 ? B.poollo : nullptr, B.poolsq, B.poolsq64, B.init_idx, B.flags, 0, c->stream);
-    launch_init_state(L.k, W, c->cfg.kernel, c->cfg.kernel_param, L.d, L.dp, B.pool32, B.coef, B.cum, B.G,
-                      c->fp64, c->stream);
     HIPCHK(c, hipMemcpyAsync(B.coef, coef.data(), 8 * coef.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(B.cum, s->cum, 8 * (size_t)L.k, hipMemcpyHostToDevice, c->stream));
-    for (int q = 0; q < live.n; ++q)
-        launch_pool_slot_from_X(L, B, live.r[q], s->slot_b[live.r[q]], c->stream);
+    HIPCHK(c, hipMemcpyAsync(B.picks, s->init_idx, 4 * (size_t)L.k, hipMemcpyHostToDevice, c->stream));
+    // initial points, G reset with G[j][0][0] = K(x_j, x_j)
+    launch_gather_rows(B.X, L.n, L.d, B.ld, B.picks, L.k, L.dp, B.pool32, L.bf16 ? B.poolhi : nullptr,
+                       L.bf16 ? B.poollo : nullptr, B.poolsq, B.poolsq64, B.init_idx, B.flags, 0, c->stream);
+    launch_init_state(L, B, c->cfg.kernel, c->cfg.kernel_param, c->fp64, 0, c->stream);
+    // coordinates of the live slots
+    for (int q = 0; q < live.n; ++q) {
+        const int p = live.r[q];
+        const int64_t r0 = slot_row(L, p, 0);
+        launch_gather_rows(B.X, L.n, L.d, B.ld, B.ring_idx + (int64_t)p * L.bmax, sb[p], L.dp,
+                           B.pool32 + r0 * L.dp, L.bf16 ? B.poolhi + r0 * L.dp : nullptr,
+                           L.bf16 ? B.poollo + r0 * L.dp : nullptr, B.poolsq + r0, B.poolsq64 + r0, nullptr,
+                           B.flags, 0, c->stream);
+    }
     // Gram blocks of every live slot against every live column
     for (int q = 0; q < live.n; ++q) {
-        const int r = live.r[q];
-        launch_chunks(L, B, r, c->stream);
-        launch_gram(L, B, r, mask, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->stream);
-        launch_gram_fold(L, B, r, mask, c->stream);
+        const int p = live.r[q];
+        launch_chunks(L, B, p, c->stream);
+        launch_gram(L, B, p, mask, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->stream);
+        launch_gram_fold(L, B, p, mask, c->stream);
     }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int r = 0; r < W; ++r)
-        c->slot_b[r] = s->slot_b[r];
+    for (int p = 0; p < P; ++p)
+        c->slot_b[p] = sb[p];
     c->iter = i;
     c->pending_r = -1;
     c->support_iter = -1;
@@ -703,6 +755,12 @@ int mbkk_set_timing(mbkk_ctx *c, int32_t enable)
     c->ev_used = 0;
     c->ms_acc = 0.0;
     c->launches = 0;
+    // events are created here, outside any timed loop
+    while (c->timing && c->ev.size() < 1024) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->ev.push_back(e);
+    }
     return MBKK_OK;
 }
 

@@ -1,5 +1,14 @@
 // Internal declarations of the mbkk library: context layout, launch helpers.
 // Not part of the ABI (include/mbkk.h is).
+//
+// Center representation (Eq. 1, sliding window): the points of each of the
+// last W batches are kept in a ring of P = W + 1 physical slots; batch l lives
+// in slot (l - 1) mod P.  Before iteration i the live slots hold batches
+// max(1, i-W) .. i-1, so slot (i - 1) mod P is free and batch i is staged
+// straight into it.  Within a slot the rows stay in batch order; the grouping
+// by center is a permutation (ring_perm) plus per-center offsets (ring_off).
+// Coefficients and Gram blocks are indexed by column c: 0 = initial point,
+// 1 + p = physical slot p.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -11,20 +20,21 @@
 
 namespace mbkk {
 
-constexpr int kDimAlign = 32;     // pool / batch row stride is d rounded up to this
+constexpr int kDimAlign = 32;     // pool row stride is d rounded up to this
 constexpr int kMfmaPad = 32;      // MFMA path: every center segment is a multiple of 32
-constexpr int kMaxWindow = 30;    // ring slots W (G is (W+1)^2 per center)
-constexpr int kMaxBatch = 8192;   // b_max; the update sorts (label, position) keys in LDS
-constexpr int kGramRowsMax = 16;  // rows of the new slot per Gram work item (fewer for large d)
+constexpr int kMaxWindow = 30;    // W; physical slots P = W + 1
+constexpr int kMaxSlots = kMaxWindow + 1;
+constexpr int kMaxBatch = 8192;   // b_max
+constexpr int kGramRowsMax = 16;  // rows of the new slot per Gram work item
+constexpr int kChunk = 256;       // batch rows per grouping chunk
 
-// Ordered list of ring slots (oldest batch first) that are live.
+// Physical slots of the live batches, oldest batch first.
 struct SlotList {
     int n;
-    int r[kMaxWindow];
+    int r[kMaxSlots];
 };
 
-// Bit-level bf16 helpers (round to nearest even), shared by the staging
-// kernels: hi = bf16(x), lo = bf16(x - hi).
+// Bit-level bf16 helpers (round to nearest even): hi = bf16(x), lo = bf16(x - hi).
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x)
 {
     uint32_t u = __float_as_uint(x);
@@ -38,33 +48,38 @@ struct Buffers {
     const float *X = nullptr;
     int64_t ld = 0;
     float *sqn = nullptr;        // [n] ||x||^2 (FP32 from an FP64 sum)
-    // coordinate pool: rows [0,k) initial points, [k + r*bmax + p] ring slot r
-    // position p, row PR = k + W*bmax is all zeros (padding target)
+    // coordinate pool: rows [0,k) initial points, k + p*bmax + q: position q
+    // (batch order) of physical slot p; row PR = k + P*bmax is all zeros
     float *pool32 = nullptr;     // [(PR+1) * dp]
     uint16_t *poolhi = nullptr;  // [(PR+1) * dp]  BF16 forms only
     uint16_t *poollo = nullptr;
     float *poolsq = nullptr;     // [PR+1]
     double *poolsq64 = nullptr;  // [PR+1]
-    // staged batch rows
-    int32_t *batidx = nullptr;   // [bmax] gathered indices (copy of the caller's)
-    float *bat32 = nullptr;      // [bmax * dp]
+    // the rows being scored: a view of one physical slot (set per call)
+    int32_t *batidx = nullptr;   // [bmax] gathered indices of the staging slot
+    float *bat32 = nullptr;
     uint16_t *bathi = nullptr, *batlo = nullptr;
-    float *batsq = nullptr;      // [bmax]
-    double *batsq64 = nullptr;   // [bmax]
-    // ring of W slots
-    int32_t *ring_idx = nullptr; // [W * bmax]
-    int32_t *ring_off = nullptr; // [W * (k+1)]
-    int32_t *init_idx = nullptr; // [k]
-    double *coef = nullptr;      // [k * (W+1)]
-    double *cum = nullptr;       // [k]
-    double *G = nullptr;         // [k * (W+1) * (W+1)]
-    double *N = nullptr;         // [k]
-    int32_t *counts = nullptr;   // [k]
-    double *alpha = nullptr;     // [k]
+    float *batsq = nullptr;
+    double *batsq64 = nullptr;
+    // ring of P physical slots
+    int32_t *slot_pts = nullptr;  // [P * bmax] point index of each row (batch order)
+    int32_t *ring_idx = nullptr;  // [P * bmax] point indices, grouped by center
+    int32_t *ring_perm = nullptr; // [P * bmax] grouped position -> batch-order row
+    int32_t *ring_off = nullptr;  // [P * (k+1)]
+    int32_t *init_idx = nullptr;  // [k]
+    double *coef = nullptr;       // [k * C], C = P + 1
+    double *cum = nullptr;        // [k]
+    double *G = nullptr;          // [k * C * C]
+    double *N = nullptr;          // [k]
+    int32_t *counts = nullptr;    // [k]
+    double *alpha = nullptr;      // [k]
+    // grouping of a batch by center
+    int32_t *rank = nullptr;      // [bmax] rank of a row among equal labels of its chunk
+    int32_t *gcnt = nullptr;      // [nchunk * k] per-chunk label counts, then bases
     // Gram work items of the newest slot
     int32_t *chunk_j = nullptr, *chunk_a0 = nullptr, *chunk_a1 = nullptr;  // [maxchunks]
     int32_t *chunk_off = nullptr;  // [k+1]
-    double *Gpart = nullptr;       // [maxchunks * (W+1)]
+    double *Gpart = nullptr;       // [maxchunks * C]
     // support of the current centers (padded segments)
     int32_t *seg_off = nullptr;  // [k+1]
     int32_t *sup_row = nullptr;  // [Mcap] pool row
@@ -72,11 +87,10 @@ struct Buffers {
     double *sup_w64 = nullptr;   // [Mcap]
     int32_t *blk_center = nullptr;  // [Mcap/32]
     // cross-term output and assignment
-    void *part = nullptr;        // P[k][bmax] (direct) or per-32-block partials [Mcap/32][bmax]
+    void *part = nullptr;        // P[k][bmax] (direct) or per-run partials [Mcap/32][bmax]
     int32_t *labels = nullptr;   // [bmax]
     float *mind = nullptr;       // [bmax]
     float *margin = nullptr;     // [bmax]
-    int32_t *perm = nullptr;     // [bmax]
     double *obj = nullptr;       // [4] device scalars
     int32_t *flags = nullptr;    // [4] error flags (index, non-finite)
     int32_t *nchunks = nullptr;  // [1]
@@ -90,20 +104,23 @@ struct Buffers {
 
 struct Layout {
     int64_t n;
-    int d, dp, k, W, bmax, pad;
-    int64_t PR;        // pool rows excluding the zero row
+    int d, dp, k, W, P, C, bmax, pad;
+    int64_t PR;        // pool rows excluding the zero row: k + P * bmax
     int64_t Mcap;      // max padded support entries (multiple of 128)
     int64_t nblk;      // Mcap / 32
-    int gram_rows;     // rows per Gram work item (its rows are staged in LDS)
+    int gram_rows;     // rows per Gram work item
+    int mfma_rb;       // support blocks (32 rows) per range of the batch-stationary MFMA kernel
     int64_t maxchunks; // Gram work items bound
+    int nchunk;        // grouping chunks of a full batch: ceil(bmax / kChunk)
     int64_t kpp_blocks;
     bool bf16;
     size_t bytes;
 };
 
-// Pieces of the layout computation and of every launch, implemented in the
-// .hip files.
 Layout make_layout(const mbkk_config &c);
 void carve(const Layout &L, char *base, Buffers &B);
+
+// Row of physical slot p, position q, in the pool.
+inline int64_t slot_row(const Layout &L, int p, int64_t q) { return (int64_t)L.k + (int64_t)p * L.bmax + q; }
 
 }  // namespace mbkk
