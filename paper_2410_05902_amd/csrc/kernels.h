@@ -12,24 +12,23 @@ void launch_gather_rows(const float *X, int64_t n, int d, int64_t ld, const int3
                         hipStream_t st);
 void launch_init_state(const Layout &L, const Buffers &B, int kind, double param, int fp64, int set_coef,
                        hipStream_t st);
-void launch_support_fill(const Layout &L, const Buffers &B, const SlotList &live, int init_alive, hipStream_t st);
-void launch_chunks(const Layout &L, const Buffers &B, int p, hipStream_t st);
+void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const SlotList &live, int init_alive,
+                    const int32_t *idx, int64_t cnt, int check_finite, float ay_scale, hipStream_t st);
 void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
                    int init_keep, const SlotList &live, int lr, hipStream_t st);
 void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param,
                  int fp64, hipStream_t st);
-void launch_gram_fold(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, hipStream_t st);
 
 // Cross term P = <phi(x), C_j> for the staged batch rows [0, nb).
 void launch_cross_direct(const Layout &L, const Buffers &B, int nb, int kind, double param, int fp64,
                          hipStream_t st);
+void launch_gram_mfma(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int precision, double kappa,
+                      hipStream_t st);
 void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision, double kappa,
                        hipStream_t st);
 // Distances, argmin, margin (and optionally every distance) of rows [0, nb).
 void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double param, int fp64, int mfma,
-                  double *D_out, int64_t ldD, hipStream_t st);
-void launch_rescore(const Layout &L, const Buffers &B, int nb, int kind, double param, double delta,
-                    hipStream_t st);
+                  int precision, double tie_delta, double *D_out, int64_t ldD, bool with_rank, hipStream_t st);
 void launch_sum_mind(const Buffers &B, int nb, int accumulate, hipStream_t st);
 
 // k-means++

@@ -469,79 +469,166 @@ __global__ __launch_bounds__(256, 2) void k_cross_mfma(const CrossArgs A)
 // Batch-stationary MFMA cross kernel (d <= 128).  Each wave keeps the MFMA
 // fragments of its 64 batch rows (2 N-blocks, all of K) in registers for the
 // whole launch; the workgroup streams a range of RB support blocks (32 rows
-// each) through double-buffered LDS, two blocks at a time.  Consecutive blocks
-// of one center are summed in registers; a run is written once, at its first
-// block ("run head": the first block of a center or of a range), so the
-// partial buffer holds one value per (run, batch row).
+// each) through two LDS buffers, 64 rows (one stage) at a time.
+//  - Staging is by direct global->LDS loads (16 bytes per lane); each lane
+//    gathers its pool row through sup_row, whose entries for the next stage
+//    are fetched one stage ahead.  LDS rows are padded by one 16-byte chunk
+//    (conflict-free 128-bit fragment reads); the pad positions load a
+//    harmless chunk.
+//  - The accumulator of a block starts at -||x||^2 / 2 (exact), so the
+//    exponent is c2 * acc + ay with ay = -log2(e) ||y||^2 / kappa staged per
+//    row: exp(-||x-y||^2 / kappa) = exp2(c2 * (x.y - ||x||^2/2) + ay).
+//  - The exp epilogue of block b-1 is issued between the MFMAs of block b.
+//  - Consecutive blocks of one center are summed in registers; a run is
+//    written once, at its first block ("run head": the first block of a
+//    center or of a range), so the partial buffer holds one value per
+//    (run, batch row).
 // Grid: (#ranges x #batch tiles of 256 rows), XCD-aware: the workgroups of one
 // XCD share support ranges.
 // ===========================================================================
+// Blocks per range of the batch-stationary kernel for Mb support blocks split
+// over nranges ranges: an even number (blocks are staged in pairs), at least 2.
+__device__ __forceinline__ int bs_range_blocks(int Mb, int nranges)
+{
+    int rb = (Mb + nranges - 1) / nranges;
+    rb = rb < 2 ? 2 : rb;
+    return rb + (rb & 1);
+}
+
+// Ranges of the batch-stationary kernel for nb batch rows: one round of
+// workgroups (kBsOcc per compute unit).
+static int bs_nranges(int nb)
+{
+    const int nbt = (nb + 255) / 256;
+    const int r = kNumCU * kBsOcc / nbt;
+    return r < 1 ? 1 : r;
+}
+
 struct CrossBsArgs {
-    int nb, dp, nbt, RB;
-    int64_t nranges;
-    int64_t zero_row;
+    int nb, nbt, nranges;
+    int32_t sup_cap;      // Mcap: sup_row[Mcap] is the zero pool row
     const int32_t *seg_total;
     const float *pool32;
     const uint16_t *poolhi, *poollo;
-    const float *poolsq;
+    const float *zero_f;  // a float 0 in device memory
     const int32_t *sup_row;
-    const float *sup_w;
+    const float *sup_w, *sup_ay;
     const int32_t *blk_center;
     const float *bat32;
     const uint16_t *bathi, *batlo;
     const float *batsq;
-    float c2, c1;
+    float c2;
     float *part;
     int ldp;
 };
 
+typedef __attribute__((address_space(3))) void lds_void_t;
+
 template <int MODE, int DP>
-__global__ __launch_bounds__(256, 2) void k_cross_bs(const CrossBsArgs A)
+__global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
 {
     constexpr bool F32 = MODE == 0;
     constexpr bool X3 = MODE == 1;
-    constexpr int KS = F32 ? DP / 2 : DP / 16;      // MFMA k-steps over K = DP
-    constexpr int LDA = F32 ? DP + 4 : DP + 8;      // LDS row stride (elements)
-    constexpr int ROWS = 64;                        // support rows per stage (2 blocks)
-    constexpr int BUF_F = F32 ? ROWS * LDA : 4;
-    constexpr int BUF_H = F32 ? 8 : ROWS * LDA;
-    __shared__ __attribute__((aligned(16))) float sAf[2][BUF_F];
-    __shared__ __attribute__((aligned(16))) uint16_t sAh[2][BUF_H];
-    __shared__ __attribute__((aligned(16))) uint16_t sAl[2][X3 ? BUF_H : 8];
-    __shared__ __attribute__((aligned(16))) float sAy[2][ROWS];
-    __shared__ __attribute__((aligned(16))) float sW[2][ROWS];
+    constexpr int KS = F32 ? DP / 2 : DP / 16;     // MFMA k-steps over K = DP
+    constexpr int ES = F32 ? 4 : 2;                // element bytes
+    constexpr int CPR = DP * ES / 16;              // 16-byte chunks per row
+    constexpr int CPS = CPR + 1;                   // chunk positions per LDS row (one pad)
+    constexpr int ROWS = 64;                       // support rows per stage (2 blocks)
+    constexpr int NPOS = ROWS * CPS;               // chunk positions per staged array
+    constexpr int NINS = NPOS / 64;                // DMA instructions per array (= CPS)
+    constexpr int NT = (NINS + 3) / 4;             // per wave (waves take i = w, w+4, ...)
+    constexpr int NARR = X3 ? 2 : 1;
+    constexpr int ABYTES = NPOS * 16;
+    static_assert(NPOS % 64 == 0, "staged array must be whole DMA instructions");
+    __shared__ __attribute__((aligned(16))) char sA[2][NARR][ABYTES];
+    __shared__ __attribute__((aligned(16))) float sAy[3][ROWS];
+    __shared__ __attribute__((aligned(16))) float sW[3][ROWS];
 
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
     // XCD-aware order: tiles t of XCD x are x*G8 .. x*G8+G8-1; consecutive t
     // share a support range
     const int64_t G8 = gridDim.x / 8;
     const int64_t t = (int64_t)(blockIdx.x % 8) * G8 + blockIdx.x / 8;
-    if (t >= A.nranges * A.nbt)
+    if (t >= (int64_t)A.nranges * A.nbt)
         return;
     const int range = (int)(t / A.nbt), bt = (int)(t % A.nbt);
     const int M = *A.seg_total;
     const int Mb = M / 32;
-    const int blk0 = range * A.RB;
+    const int RB = bs_range_blocks(Mb, A.nranges);
+    const int blk0 = range * RB;
     if (blk0 >= Mb)
         return;
-    const int blk1 = min(Mb, blk0 + A.RB);
-    const int b0 = bt * 256 + wid * 64;  // this wave's 64 batch rows
+    const int blk1 = min(Mb, blk0 + RB);
+    const int nst = (blk1 - blk0 + 1) / 2;
+    const int b0 = bt * 256 + wu * 64;  // this wave's 64 batch rows
     const int n = lane & 31, h = lane >> 5;
+
+    // ---- staging ---------------------------------------------------------
+    // DMA slot q of this lane: instruction i = wave + 4 q writes chunk
+    // position 64 i + lane of a staged array: row drow[q], chunk offset dcoff[q]
+    __builtin_assume(wu >= 0 && wu < 4);
+    int drow[NT], dcoff[NT], pidx[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+        const int pos = 64 * (wu + 4 * q) + lane;
+        const int c = pos % CPS;
+        drow[q] = min(pos / CPS, ROWS - 1);
+        dcoff[q] = (c < CPR ? c : 0) * 16;  // the pad position loads any valid chunk
+    }
+    // sup_row[Mcap] holds the zero pool row; entries past the support map there
+    const int sentinel = A.sup_cap;
+    auto load_idx = [&](int s) {  // pool rows of this lane's DMA slots in stage s
+        const int r0 = (blk0 + 2 * s) * 32;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            const int srow = r0 + drow[q];
+            pidx[q] = A.sup_row[srow < M ? srow : sentinel];
+        }
+    };
+    int cen_nxt[2];
+    auto load_cen = [&](int s) {  // centers of the two blocks of stage s
+        const int bp = blk0 + 2 * s;
+        cen_nxt[0] = A.blk_center[bp];
+        cen_nxt[1] = A.blk_center[bp + 1 < blk1 ? bp + 1 : bp];
+    };
+    auto issue = [&](int s, int bufi) {  // DMA of stage s into buffer bufi
+#pragma unroll
+        for (int arr = 0; arr < NARR; ++arr) {
+            const char *gsrc = F32 ? (const char *)A.pool32
+                                   : (arr == 0 ? (const char *)A.poolhi : (const char *)A.poollo);
+#pragma unroll
+            for (int q = 0; q < NT; ++q) {
+                const int i = wu + 4 * q;
+                if (4 * q + 3 < NINS || i < NINS) {
+                    const char *src = gsrc + ((int64_t)pidx[q] * (DP * ES) + dcoff[q]);
+                    __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)&sA[bufi][arr][i * 1024],
+                                                     16, 0, 0);
+                }
+            }
+        }
+        if (wu < 2) {
+            const int srow = (blk0 + 2 * s) * 32 + lane;
+            const float *src = srow < M ? (wu == 0 ? A.sup_ay : A.sup_w) + srow : A.zero_f;
+            float *dst = wu == 0 ? &sAy[s % 3][0] : &sW[s % 3][0];
+            __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)dst, 4, 0, 0);
+        }
+    };
 
     // ---- batch fragments into registers --------------------------------
     typedef typename std::conditional<F32, float, bf16x8>::type frag_t;
     frag_t bh[2][KS];
     frag_t bl[2][X3 ? KS : 1];
-    float ax[2];
+    float hx[2];
 #pragma unroll
     for (int nbk = 0; nbk < 2; ++nbk) {
         const int row = b0 + nbk * 32 + n;
         const bool ok = row < A.nb;
         const int64_t rr = ok ? row : 0;
-        ax[nbk] = ok ? A.c1 * A.batsq[row] : 0.0f;
+        hx[nbk] = ok ? -0.5f * A.batsq[row] : 0.0f;
         if constexpr (F32) {
             // K permutation: k-step s, lane half h -> column h * KS + s
-            const float *src = A.bat32 + rr * A.dp + h * KS;
+            const float *src = A.bat32 + rr * DP + h * KS;
 #pragma unroll
             for (int s4 = 0; s4 < KS; s4 += 4) {
                 const f32x4 v = ok ? *(const f32x4 *)(src + s4) : f32x4{0, 0, 0, 0};
@@ -551,8 +638,8 @@ __global__ __launch_bounds__(256, 2) void k_cross_bs(const CrossBsArgs A)
                 bh[nbk][s4 + 3] = v[3];
             }
         } else {
-            const uint16_t *sh = A.bathi + rr * A.dp + h * 8;
-            const uint16_t *sl = A.batlo + rr * A.dp + h * 8;
+            const uint16_t *sh = A.bathi + rr * DP + h * 8;
+            const uint16_t *sl = A.batlo + rr * DP + h * 8;
             const u16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
@@ -563,60 +650,62 @@ __global__ __launch_bounds__(256, 2) void k_cross_bs(const CrossBsArgs A)
         }
     }
 
-    // ---- support stream: 64 rows per stage ------------------------------
-    // loader: thread -> row tid/4, quarter tid%4 of the K columns
-    const int lrow = tid >> 2, lq = tid & 3;
-    constexpr int QE = DP / 4;                    // elements per quarter row
-    constexpr int NV = F32 ? QE / 4 : QE / 8;      // 16-byte vectors per quarter
-    f32x4 rf[F32 ? NV : 1];
-    u16x8 rh[F32 ? 1 : NV], rl[X3 ? NV : 1];
-    float ry = 0.0f, rw = 0.0f;
-    auto gload = [&](int blk) {  // rows blk*32 .. blk*32+63
-        const int srow = blk * 32 + lrow;
-        const bool ok = srow < M;
-        const int64_t prow = ok ? (int64_t)A.sup_row[srow] : A.zero_row;
-        if constexpr (F32) {
-            const float *src = A.pool32 + prow * A.dp + lq * QE;
+    // ---- block products and epilogue ---------------------------------------
+    // fragment read of row sub*32 + n: byte offset within a staged array
+    const int aoff = n * (CPS * 16) + (F32 ? h * KS * 4 : h * 16);
+    auto mfma_block = [&](f32x16 (&acc)[2], int bufi, int sub) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-                rf[v] = *(const f32x4 *)(src + v * 4);
-        } else {
-            const uint16_t *sh = A.poolhi + prow * A.dp + lq * QE;
-            const uint16_t *sl = A.poollo + prow * A.dp + lq * QE;
+        for (int nbk = 0; nbk < 2; ++nbk)
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                rh[v] = *(const u16x8 *)(sh + v * 8);
-                if constexpr (X3)
-                    rl[v] = *(const u16x8 *)(sl + v * 8);
-            }
-        }
-        if (lq == 0) {
-            ry = A.c1 * A.poolsq[prow];
-            rw = ok ? A.sup_w[srow] : 0.0f;
-        }
-    };
-    auto lstore = [&](int buf) {
+            for (int i = 0; i < 16; ++i)
+                acc[nbk][i] = hx[nbk];
+        const char *base = &sA[bufi][0][sub * 32 * CPS * 16 + aoff];
         if constexpr (F32) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-                *(f32x4 *)(&sAf[buf][lrow * LDA + lq * QE + v * 4]) = rf[v];
+            for (int s4 = 0; s4 < KS; s4 += 4) {
+                const f32x4 av = *(const f32x4 *)(base + s4 * 4);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int nbk = 0; nbk < 2; ++nbk)
+                        acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bh[nbk][s4 + u], acc[nbk], 0, 0, 0);
+            }
         } else {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                *(u16x8 *)(&sAh[buf][lrow * LDA + lq * QE + v * 8]) = rh[v];
+            for (int ks = 0; ks < KS; ++ks) {
+                const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + ks * 32));
+                bf16x8 al;
                 if constexpr (X3)
-                    *(u16x8 *)(&sAl[buf][lrow * LDA + lq * QE + v * 8]) = rl[v];
+                    al = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + ABYTES + ks * 32));
+#pragma unroll
+                for (int nbk = 0; nbk < 2; ++nbk) {
+                    acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[nbk][ks], acc[nbk], 0, 0, 0);
+                    if constexpr (X3) {
+                        acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[nbk][ks], acc[nbk], 0, 0, 0);
+                        acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[nbk][ks], acc[nbk], 0, 0, 0);
+                    }
+                }
             }
         }
-        if (lq == 0) {
-            sAy[buf][lrow] = ry;
-            sW[buf][lrow] = rw;
-        }
     };
-
     float run[2] = {0.0f, 0.0f};
+    const float c2 = A.c2;
+    auto epilogue = [&](const f32x16 (&acc)[2], int e3, int sub) {
+        // rows m = 8 (i/4) + 4 h + i%4 of the block
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const int m0 = sub * 32 + 8 * g + 4 * h;
+            const f32x4 ay = *(const f32x4 *)(&sAy[e3][m0]);
+            const f32x4 w = *(const f32x4 *)(&sW[e3][m0]);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int nbk = 0; nbk < 2; ++nbk)
+                    run[nbk] = fmaf(w[q], __builtin_amdgcn_exp2f(fmaf(acc[nbk][4 * g + q], c2, ay[q])), run[nbk]);
+        }
+    };
     int run_head = blk0;
-    int run_center = A.blk_center[blk0];
+    int run_center = __builtin_amdgcn_readfirstlane(A.blk_center[blk0]);
     auto flush = [&]() {
         // lane l (< 32) holds the half-sums of column n for both N-blocks;
         // one exchange gives N-block 0 totals to lanes < 32, N-block 1 to the rest
@@ -629,82 +718,70 @@ __global__ __launch_bounds__(256, 2) void k_cross_bs(const CrossBsArgs A)
         run[0] = run[1] = 0.0f;
     };
 
-    gload(blk0);
-    lstore(0);
-    __syncthreads();
-    int buf = 0;
-    for (int bp = blk0; bp < blk1; bp += 2) {
-        const bool more = bp + 2 < blk1;
-        if (more)
-            gload(bp + 2);
-#pragma unroll
-        for (int sub = 0; sub < 2; ++sub) {
-            const int blk = bp + sub;
-            if (blk >= blk1)
-                break;
-            const int cen = A.blk_center[blk];
-            if (cen != run_center) {
-                flush();
-                run_head = blk;
-                run_center = cen;
-            }
-            f32x16 acc[2];
-#pragma unroll
-            for (int nbk = 0; nbk < 2; ++nbk)
-#pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    acc[nbk][i] = 0.0f;
-            const int arow = sub * 32 + n;
-            if constexpr (F32) {
-                const float *ap = &sAf[buf][arow * LDA + h * KS];
-#pragma unroll
-                for (int s4 = 0; s4 < KS; s4 += 4) {
-                    const f32x4 av = *(const f32x4 *)(ap + s4);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int nbk = 0; nbk < 2; ++nbk)
-                            acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bh[nbk][s4 + u], acc[nbk], 0, 0, 0);
-                }
-            } else {
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) {
-                    const int off = arow * LDA + ks * 16 + h * 8;
-                    const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u16x8 *)(&sAh[buf][off]));
-                    bf16x8 al;
-                    if constexpr (X3)
-                        al = __builtin_bit_cast(bf16x8, *(const u16x8 *)(&sAl[buf][off]));
-#pragma unroll
-                    for (int nbk = 0; nbk < 2; ++nbk) {
-                        acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[nbk][ks], acc[nbk], 0, 0, 0);
-                        if constexpr (X3) {
-                            acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[nbk][ks], acc[nbk], 0, 0, 0);
-                            acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[nbk][ks], acc[nbk], 0, 0, 0);
-                        }
-                    }
-                }
-            }
-            // epilogue: rows m = 8 (i/4) + 4 h + i%4 of this block
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int m0 = sub * 32 + 8 * g + 4 * h;
-                const f32x4 ay = *(const f32x4 *)(&sAy[buf][m0]);
-                const f32x4 w = *(const f32x4 *)(&sW[buf][m0]);
-#pragma unroll
-                for (int q = 0; q < 4; ++q)
-#pragma unroll
-                    for (int nbk = 0; nbk < 2; ++nbk) {
-                        const float arg = fmaf(acc[nbk][4 * g + q], A.c2, ax[nbk] + ay[q]);
-                        run[nbk] = fmaf(w[q], __builtin_amdgcn_exp2f(arg), run[nbk]);
-                    }
-            }
-        }
-        if (more) {
-            lstore(buf ^ 1);
-            __syncthreads();
-            buf ^= 1;
-        }
+    // ---- pipeline ----------------------------------------------------------
+    // the epilogue of the block before the first one reads weights 0
+    if (tid < ROWS) {
+        sAy[2][tid] = 0.0f;
+        sW[2][tid] = 0.0f;
     }
+    f32x16 accE[2], accO[2];
+#pragma unroll
+    for (int nbk = 0; nbk < 2; ++nbk)
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            accO[nbk][i] = 0.0f;
+    load_idx(0);
+    load_cen(0);
+    issue(0, 0);
+    if (nst > 1)
+        load_idx(1);
+    __syncthreads();
+    for (int s = 0; s < nst; ++s) {
+        const int bufi = s & 1;
+        const int bp = blk0 + 2 * s;
+        const int cenE = __builtin_amdgcn_readfirstlane(cen_nxt[0]);
+        const int cenO = __builtin_amdgcn_readfirstlane(cen_nxt[1]);
+        if (s + 1 < nst) {
+            issue(s + 1, bufi ^ 1);
+            load_cen(s + 1);
+            if (s + 2 < nst)
+                load_idx(s + 2);
+        }
+        if constexpr (kBsPipe) {
+            mfma_block(accE, bufi, 0);
+            epilogue(accO, (s + 2) % 3, 1);  // block bp - 1
+            if (cenE != run_center) {
+                flush();
+                run_head = bp;
+                run_center = cenE;
+            }
+            mfma_block(accO, bufi, 1);
+            epilogue(accE, s % 3, 0);  // block bp
+            if (cenO != run_center) {
+                flush();
+                run_head = bp + 1;
+                run_center = cenO;
+            }
+        } else {
+            if (cenE != run_center) {
+                flush();
+                run_head = bp;
+                run_center = cenE;
+            }
+            mfma_block(accE, bufi, 0);
+            epilogue(accE, s % 3, 0);
+            if (cenO != run_center) {
+                flush();
+                run_head = bp + 1;
+                run_center = cenO;
+            }
+            mfma_block(accE, bufi, 1);
+            epilogue(accE, s % 3, 1);
+        }
+        __syncthreads();
+    }
+    if constexpr (kBsPipe)
+        epilogue(accO, (nst - 1) % 3, 1);
     flush();
 }
 
@@ -714,28 +791,26 @@ void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision,
     if (L.dp <= 128) {
         CrossBsArgs A;
         A.nb = nb;
-        A.dp = L.dp;
         A.nbt = (nb + 255) / 256;
-        A.RB = L.mfma_rb;
-        A.nranges = (L.nblk + A.RB - 1) / A.RB;
-        A.zero_row = L.PR;
+        A.nranges = bs_nranges(nb);
+        A.sup_cap = (int32_t)L.Mcap;
         A.seg_total = B.seg_off + L.k;
         A.pool32 = B.pool32;
         A.poolhi = B.poolhi;
         A.poollo = B.poollo;
-        A.poolsq = B.poolsq;
+        A.zero_f = B.poolsq + L.PR;
         A.sup_row = B.sup_row;
         A.sup_w = B.sup_w;
+        A.sup_ay = B.sup_ay;
         A.blk_center = B.blk_center;
         A.bat32 = B.bat32;
         A.bathi = B.bathi;
         A.batlo = B.batlo;
         A.batsq = B.batsq;
         A.c2 = (float)(2.0 * l2e / kappa);
-        A.c1 = (float)(-l2e / kappa);
         A.part = (float *)B.part;
         A.ldp = L.bmax;
-        const int64_t tiles = A.nranges * A.nbt;
+        const int64_t tiles = (int64_t)A.nranges * A.nbt;
         const dim3 grid((unsigned)((tiles + 7) / 8 * 8));
 #define MBKK_BS(MODE, DP) hipLaunchKernelGGL((k_cross_bs<MODE, DP>), grid, dim3(256), 0, st, A)
 #define MBKK_BS_DP(MODE)                      \
@@ -789,6 +864,147 @@ void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision,
 }
 
 // ===========================================================================
+// Gram blocks on MFMA (Gaussian, d <= 128), same arithmetic as the cross
+// term of the form (FP32 MFMA, or BF16 hi/lo split):
+//   G_j[1+rr][c] = G_j[c][1+rr] = sum_{a in slot rr, center j} sum_{e in column c, center j}
+//                                 exp(-(||a||^2 + ||e||^2 - 2 a.e) / kappa)
+// One workgroup per (center j, column c); rows 64 x 64 at a time, wave w
+// computes the 32 x 32 block (w / 2, w % 2) with fragments loaded straight
+// from the pool into registers; kernel values are summed in FP64.
+// ===========================================================================
+template <int MODE, int DP>
+__global__ __launch_bounds__(256) void k_gram_mfma(int k, int C, int bmax, int rr, uint32_t col_mask,
+                                                    const int32_t *__restrict__ ring_off,
+                                                    const int32_t *__restrict__ ring_perm, int64_t zero_row,
+                                                    const float *__restrict__ pool32,
+                                                    const uint16_t *__restrict__ poolhi,
+                                                    const uint16_t *__restrict__ poollo,
+                                                    const float *__restrict__ poolsq, float c2, float c1,
+                                                    double *__restrict__ G)
+{
+    constexpr bool F32 = MODE == 0;
+    constexpr bool X3 = MODE == 1;
+    constexpr int KS = F32 ? DP / 2 : DP / 16;
+    __shared__ float sqa[64], sqe[64];
+    __shared__ double red[4];
+    const int j = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6, n = lane & 31, h = lane >> 5;
+    if (!((col_mask >> c) & 1u))
+        return;  // block uniform
+    const int32_t *oa = ring_off + (int64_t)rr * (k + 1);
+    const int na = oa[j + 1] - oa[j];
+    const int32_t *pa = ring_perm + (int64_t)rr * bmax + oa[j];
+    const int64_t arow0 = (int64_t)k + (int64_t)rr * bmax;
+    int ne;
+    const int32_t *pe = nullptr;
+    int64_t erow0;
+    if (c == 0) {
+        ne = 1;
+        erow0 = j;
+    } else {
+        const int32_t *oe = ring_off + (int64_t)(c - 1) * (k + 1);
+        ne = oe[j + 1] - oe[j];
+        pe = ring_perm + (int64_t)(c - 1) * bmax + oe[j];
+        erow0 = (int64_t)k + (int64_t)(c - 1) * bmax;
+    }
+    double tot = 0.0;
+    for (int at = 0; at < na; at += 64) {
+        for (int et = 0; et < ne; et += 64) {
+            __syncthreads();
+            if (tid < 64) {
+                const int q = at + tid;
+                sqa[tid] = q < na ? poolsq[arow0 + pa[q]] : 0.0f;
+            } else if (tid < 128) {
+                const int q = et + tid - 64;
+                sqe[tid - 64] = q < ne ? poolsq[c == 0 ? erow0 : erow0 + pe[q]] : 0.0f;
+            }
+            __syncthreads();
+            const int mb = w >> 1, nb = w & 1;
+            if (at + mb * 32 < na && et + nb * 32 < ne) {  // wave uniform
+                const int qa = at + mb * 32 + n, qe = et + nb * 32 + n;
+                const int64_t ra = qa < na ? arow0 + pa[qa] : zero_row;
+                const int64_t re = qe < ne ? (c == 0 ? erow0 : erow0 + pe[qe]) : zero_row;
+                f32x16 acc;
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    acc[i] = 0.0f;
+                if constexpr (F32) {
+                    const float *sa = pool32 + ra * DP + h * KS, *se = pool32 + re * DP + h * KS;
+#pragma unroll
+                    for (int s4 = 0; s4 < KS; s4 += 4) {
+                        const f32x4 av = *(const f32x4 *)(sa + s4), ev = *(const f32x4 *)(se + s4);
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], ev[u], acc, 0, 0, 0);
+                    }
+                } else {
+#pragma unroll
+                    for (int ks = 0; ks < KS; ++ks) {
+                        const int64_t oa16 = ra * DP + ks * 16 + h * 8, oe16 = re * DP + ks * 16 + h * 8;
+                        const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poolhi + oa16));
+                        const bf16x8 eh = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poolhi + oe16));
+                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, eh, acc, 0, 0, 0);
+                        if constexpr (X3) {
+                            const bf16x8 al = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poollo + oa16));
+                            const bf16x8 el = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poollo + oe16));
+                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, el, acc, 0, 0, 0);
+                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, eh, acc, 0, 0, 0);
+                        }
+                    }
+                }
+                // lane: column n (e row), rows m = 8 (i/4) + 4 h + i%4 (a rows)
+                const bool eok = qe < ne;
+                const float se_ = c1 * sqe[nb * 32 + n];
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int m = 8 * (i >> 2) + 4 * h + (i & 3);
+                    if (eok && at + mb * 32 + m < na)
+                        tot += (double)__builtin_amdgcn_exp2f(fmaf(acc[i], c2, c1 * sqa[mb * 32 + m] + se_));
+                }
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        tot += __shfl_xor(tot, o);
+    if (lane == 0)
+        red[w] = tot;
+    __syncthreads();
+    if (tid == 0) {
+        const double g = red[0] + red[1] + red[2] + red[3];
+        double *gj = G + (int64_t)j * C * C;
+        gj[(1 + rr) * C + c] = g;
+        gj[c * C + 1 + rr] = g;
+    }
+}
+
+void launch_gram_mfma(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int precision, double kappa,
+                      hipStream_t st)
+{
+    const double l2e = 1.4426950408889634;
+    const float c2 = (float)(2.0 * l2e / kappa), c1 = (float)(-l2e / kappa);
+    dim3 grid(L.k, L.C);
+#define MBKK_GM(MODE, DP)                                                                                       \
+    hipLaunchKernelGGL((k_gram_mfma<MODE, DP>), grid, dim3(256), 0, st, L.k, L.C, L.bmax, rr, col_mask,         \
+                       B.ring_off, B.ring_perm, L.PR, B.pool32, B.poolhi, B.poollo, B.poolsq, c2, c1, B.G)
+#define MBKK_GM_DP(MODE)                 \
+    switch (L.dp) {                      \
+    case 32: MBKK_GM(MODE, 32); break;   \
+    case 64: MBKK_GM(MODE, 64); break;   \
+    case 96: MBKK_GM(MODE, 96); break;   \
+    default: MBKK_GM(MODE, 128); break;  \
+    }
+    if (precision == MBKK_FP32) {
+        MBKK_GM_DP(0);
+    } else if (precision == MBKK_BF16X3) {
+        MBKK_GM_DP(1);
+    } else {
+        MBKK_GM_DP(2);
+    }
+#undef MBKK_GM_DP
+#undef MBKK_GM
+}
+
+// ===========================================================================
 // Distances, argmin and margin of each batch row:
 //   D_j = K(x,x) - 2 P_j + N_j  (FP64 assembly of the FP32/FP64 cross term)
 // label = smallest j attaining the minimum; margin = second smallest - min.
@@ -834,26 +1050,109 @@ __device__ __forceinline__ bool lex_less(double a, int la, double b, int lb)
     return a < b || (a == b && la < lb);
 }
 
-template <typename T, int LAYOUT>
-__global__ __launch_bounds__(64 * kScoreWaves) void k_score(
-    int nb, int k, const T *__restrict__ part, int ldp, const int32_t *__restrict__ seg_off,
-    const double *__restrict__ N, int kind, double param, const double *__restrict__ batsq64,
-    int32_t *__restrict__ labels, float *__restrict__ mind, float *__restrict__ margin,
-    double *__restrict__ Dout, int64_t ldD, int RB)
+struct ScoreArgs {
+    int nb, k, ldp, RB, kind;
+    int nranges;  // > 0: RB of the batch-stationary kernel, derived from the support size
+    double param;
+    const void *part;
+    const int32_t *seg_off;
+    const double *N;
+    const double *batsq64;
+    int32_t *labels;
+    float *mind, *margin;
+    double *Dout;
+    int64_t ldD;
+    // FP64 re-scoring of near ties (BF16 forms)
+    double delta, kappa;
+    int d, dp;
+    const float *bat32, *pool32;
+    const int32_t *sup_row;
+    const double *sup_w64;
+    // grouping ranks (iteration only): rank of each row among the equal
+    // labels before it in its chunk of 64 rows, and the chunk's label counts
+    int32_t *rank, *gcnt;
+};
+
+// FP64 re-scoring of one batch row by one wave: candidates are the centers
+// whose approximate distance is within delta of the best; for them the cross
+// term is recomputed in FP64 from the FP32 coordinates (direct ||x - y||^2,
+// FP64 exp, FP64 weights).
+__device__ void rescore_row(const ScoreArgs &A, int row, int RB, int &lab_io, float &mind_io, float &margin_io)
+{
+    const int lane = threadIdx.x & 63;
+    const float *part = (const float *)A.part;
+    double best = INFINITY;
+    for (int j = lane; j < A.k; j += 64)
+        best = fmin(best, 1.0 - 2.0 * cross_of<float, 1>(part, A.ldp, row, j, A.seg_off, RB) + A.N[j]);
+    for (int o = 32; o > 0; o >>= 1)
+        best = fmin(best, __shfl_xor(best, o));
+    const float *x = A.bat32 + (int64_t)row * A.dp;
+    double b64 = INFINITY, s64 = INFINITY, outside = INFINITY;
+    int lab = 0;
+    for (int j0 = 0; j0 < A.k; j0 += 64) {
+        const int jl = j0 + lane;
+        const double Dap =
+            jl < A.k ? 1.0 - 2.0 * cross_of<float, 1>(part, A.ldp, row, jl, A.seg_off, RB) + A.N[jl] : INFINITY;
+        const bool cand = Dap <= best + A.delta;
+        if (!cand)
+            outside = fmin(outside, Dap);
+        uint64_t mask = __ballot(cand);
+        while (mask) {  // candidates in increasing center order (wave-uniform loop)
+            const int bit = __ffsll((unsigned long long)mask) - 1;
+            mask &= mask - 1;
+            const int j = j0 + bit;
+            double p = 0.0;
+            for (int s = A.seg_off[j] + lane; s < A.seg_off[j + 1]; s += 64) {
+                const double w = A.sup_w64[s];
+                if (w == 0.0)
+                    continue;
+                const float *y = A.pool32 + (int64_t)A.sup_row[s] * A.dp;
+                double d2 = 0.0;
+                for (int t = 0; t < A.d; ++t) {
+                    const double v = (double)x[t] - (double)y[t];
+                    d2 += v * v;
+                }
+                p += w * exp(-d2 / A.kappa);
+            }
+            for (int o = 32; o > 0; o >>= 1)
+                p += __shfl_xor(p, o);
+            const double D = 1.0 - 2.0 * p + A.N[j];
+            if (D < b64) {
+                s64 = b64;
+                b64 = D;
+                lab = j;
+            } else if (D < s64) {
+                s64 = D;
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        outside = fmin(outside, __shfl_xor(outside, o));
+    lab_io = lab;
+    mind_io = (float)b64;
+    margin_io = (float)(fmin(s64, outside) - b64);
+}
+
+template <typename T, int LAYOUT, bool RESCORE>
+__global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
 {
     __shared__ double sb[kScoreWaves][64], ss[kScoreWaves][64];
     __shared__ int sl[kScoreWaves][64];
+    __shared__ int flab[64];
+    __shared__ float fmin_[64], fmar[64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int row = blockIdx.x * 64 + lane;
-    const bool act = row < nb;
-    const double kxx = act ? self_kernel(kind, param, batsq64[row]) : 0.0;
+    const bool act = row < A.nb;
+    const T *part = (const T *)A.part;
+    const int RB = A.nranges > 0 ? bs_range_blocks(A.seg_off[A.k] / 32, A.nranges) : A.RB;
+    const double kxx = act ? self_kernel(A.kind, A.param, A.batsq64[row]) : 0.0;
     double best = INFINITY, second = INFINITY;
     int lab = 0x7fffffff;
     if (act) {
-        for (int j = w; j < k; j += kScoreWaves) {
-            const double D = kxx - 2.0 * cross_of<T, LAYOUT>(part, ldp, row, j, seg_off, RB) + N[j];
-            if (Dout)
-                Dout[(int64_t)row * ldD + j] = D;
+        for (int j = w; j < A.k; j += kScoreWaves) {
+            const double D = kxx - 2.0 * cross_of<T, LAYOUT>(part, A.ldp, row, j, A.seg_off, RB) + A.N[j];
+            if (A.Dout)
+                A.Dout[(int64_t)row * A.ldD + j] = D;
             if (D < best) {   // j increases within a wave: strict < keeps the lowest index
                 second = best;
                 best = D;
@@ -867,7 +1166,7 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(
     ss[w][lane] = second;
     sl[w][lane] = lab;
     __syncthreads();
-    if (w == 0 && act) {
+    if (w == 0) {
         double b0 = sb[0][lane], s0 = ss[0][lane];
         int l0 = sl[0][lane];
         for (int q = 1; q < kScoreWaves; ++q) {
@@ -883,113 +1182,95 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(
         }
         // a row whose distances are all NaN (non-finite input) matched no
         // center: it is assigned to center 0 so that every label is in range
-        if (!(l0 >= 0 && l0 < k))
+        if (!(l0 >= 0 && l0 < A.k))
             l0 = 0;
-        labels[row] = l0;
-        mind[row] = (float)b0;
-        margin[row] = (float)(s0 - b0);
+        flab[lane] = l0;
+        fmin_[lane] = (float)b0;
+        fmar[lane] = (float)(s0 - b0);
+    }
+    __syncthreads();
+    if constexpr (RESCORE) {
+        for (int r = w; r < 64; r += kScoreWaves) {  // wave-uniform row loop
+            const int rw = blockIdx.x * 64 + r;
+            if (rw < A.nb && fmar[r] < (float)A.delta) {
+                int l;
+                float m, g;
+                rescore_row(A, rw, RB, l, m, g);
+                if (lane == 0) {
+                    flab[r] = l;
+                    fmin_[r] = m;
+                    fmar[r] = g;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (w == 0 && act) {
+        A.labels[row] = flab[lane];
+        A.mind[row] = fmin_[lane];
+        A.margin[row] = fmar[lane];
+    }
+    if (A.rank) {
+        int32_t *cnt = A.gcnt + (int64_t)blockIdx.x * A.k;
+        for (int j = threadIdx.x; j < A.k; j += 64 * kScoreWaves)
+            cnt[j] = 0;
+        __syncthreads();
+        if (w == 0 && act) {
+            const int L = flab[lane];
+            int r = 0, c = 0;
+            const int nrow = min(64, A.nb - blockIdx.x * 64);
+            for (int t = 0; t < nrow; ++t) {
+                const int eq = flab[t] == L;  // wave-uniform address: LDS broadcast
+                c += eq;
+                r += eq & (t < lane);
+            }
+            A.rank[row] = r;
+            if (r == c - 1)
+                cnt[L] = c;
+        }
     }
 }
 
 void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double param, int fp64, int mfma,
-                  double *D_out, int64_t ldD, hipStream_t st)
+                  int precision, double tie_delta, double *D_out, int64_t ldD, bool with_rank, hipStream_t st)
 {
-    const int RB = L.dp <= 128 ? L.mfma_rb : 2;
+    ScoreArgs A;
+    A.nb = nb;
+    A.k = L.k;
+    A.ldp = L.bmax;
+    A.RB = 2;
+    A.nranges = L.dp <= 128 ? bs_nranges(nb) : 0;
+    A.kind = kind;
+    A.param = param;
+    A.part = B.part;
+    A.seg_off = B.seg_off;
+    A.N = B.N;
+    A.batsq64 = B.batsq64;
+    A.labels = B.labels;
+    A.mind = B.mind;
+    A.margin = B.margin;
+    A.Dout = D_out;
+    A.ldD = ldD;
+    A.delta = tie_delta;
+    A.kappa = param;
+    A.d = L.d;
+    A.dp = L.dp;
+    A.bat32 = B.bat32;
+    A.pool32 = B.pool32;
+    A.sup_row = B.sup_row;
+    A.sup_w64 = B.sup_w64;
+    A.rank = with_rank ? B.rank : nullptr;
+    A.gcnt = B.gcnt;
+    const bool rescore = precision == MBKK_BF16X3 || precision == MBKK_BF16X1;
     dim3 grid((nb + 63) / 64), block(64 * kScoreWaves);
     if (fp64)
-        hipLaunchKernelGGL((k_score<double, 0>), grid, block, 0, st, nb, L.k, (const double *)B.part, L.bmax,
-                           B.seg_off, B.N, kind, param, B.batsq64, B.labels, B.mind, B.margin, D_out, ldD, RB);
+        hipLaunchKernelGGL((k_score<double, 0, false>), grid, block, 0, st, A);
+    else if (mfma && rescore)
+        hipLaunchKernelGGL((k_score<float, 1, true>), grid, block, 0, st, A);
     else if (mfma)
-        hipLaunchKernelGGL((k_score<float, 1>), grid, block, 0, st, nb, L.k, (const float *)B.part, L.bmax,
-                           B.seg_off, B.N, kind, param, B.batsq64, B.labels, B.mind, B.margin, D_out, ldD, RB);
+        hipLaunchKernelGGL((k_score<float, 1, false>), grid, block, 0, st, A);
     else
-        hipLaunchKernelGGL((k_score<float, 0>), grid, block, 0, st, nb, L.k, (const float *)B.part, L.bmax,
-                           B.seg_off, B.N, kind, param, B.batsq64, B.labels, B.mind, B.margin, D_out, ldD, RB);
-}
-
-// ===========================================================================
-// FP64 re-scoring of near ties (BF16 forms).  One wave per batch row whose
-// margin is below delta: candidates are the centers whose BF16-form distance
-// is within delta of the best; for those the cross term is recomputed in
-// FP64 from the FP32 coordinates (direct ||x - y||^2, FP64 exp, FP64
-// weights), and the label, distance and margin are replaced.
-// ===========================================================================
-__global__ __launch_bounds__(256) void k_rescore(int nb, int k, int d, int dp, double kappa, double delta,
-                                                  const float *__restrict__ part, int ldp, int RB,
-                                                  const int32_t *__restrict__ seg_off, const double *__restrict__ N,
-                                                  const float *__restrict__ bat32, const float *__restrict__ pool32,
-                                                  const int32_t *__restrict__ sup_row,
-                                                  const double *__restrict__ sup_w64, int32_t *__restrict__ labels,
-                                                  float *__restrict__ mind, float *__restrict__ margin)
-{
-    const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= nb)
-        return;
-    if (!(margin[row] < (float)delta))
-        return;
-    // approximate distances, lanes over centers; the best of them
-    double best = INFINITY;
-    for (int j = lane; j < k; j += 64)
-        best = fmin(best, 1.0 - 2.0 * cross_of<float, 1>(part, ldp, row, j, seg_off, RB) + N[j]);
-    for (int o = 32; o > 0; o >>= 1)
-        best = fmin(best, __shfl_xor(best, o));
-    const float *x = bat32 + (int64_t)row * dp;
-    double b64 = INFINITY, s64 = INFINITY, outside = INFINITY;
-    int lab = 0;
-    for (int j0 = 0; j0 < k; j0 += 64) {
-        const int jl = j0 + lane;
-        const double Dap = jl < k ? 1.0 - 2.0 * cross_of<float, 1>(part, ldp, row, jl, seg_off, RB) + N[jl] : INFINITY;
-        const bool cand = Dap <= best + delta;
-        if (!cand)
-            outside = fmin(outside, Dap);
-        uint64_t mask = __ballot(cand);
-        while (mask) {  // candidates in increasing center order (wave-uniform loop)
-            const int bit = __ffsll((unsigned long long)mask) - 1;
-            mask &= mask - 1;
-            const int j = j0 + bit;
-            double p = 0.0;
-            for (int s = seg_off[j] + lane; s < seg_off[j + 1]; s += 64) {
-                const double w = sup_w64[s];
-                if (w == 0.0)
-                    continue;
-                const float *y = pool32 + (int64_t)sup_row[s] * dp;
-                double d2 = 0.0;
-                for (int t = 0; t < d; ++t) {
-                    const double v = (double)x[t] - (double)y[t];
-                    d2 += v * v;
-                }
-                p += w * exp(-d2 / kappa);
-            }
-            for (int o = 32; o > 0; o >>= 1)
-                p += __shfl_xor(p, o);
-            const double D = 1.0 - 2.0 * p + N[j];
-            if (D < b64) {
-                s64 = b64;
-                b64 = D;
-                lab = j;
-            } else if (D < s64) {
-                s64 = D;
-            }
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1)
-        outside = fmin(outside, __shfl_xor(outside, o));
-    if (lane == 0) {
-        labels[row] = lab;
-        mind[row] = (float)b64;
-        margin[row] = (float)(fmin(s64, outside) - b64);
-    }
-}
-
-void launch_rescore(const Layout &L, const Buffers &B, int nb, int kind, double param, double delta,
-                    hipStream_t st)
-{
-    (void)kind;
-    hipLaunchKernelGGL(k_rescore, dim3((nb + 3) / 4), dim3(256), 0, st, nb, L.k, L.d, L.dp, param, delta,
-                       (const float *)B.part, L.bmax, L.dp <= 128 ? L.mfma_rb : 2, B.seg_off, B.N, B.bat32,
-                       B.pool32, B.sup_row, B.sup_w64,
-                       B.labels, B.mind, B.margin);
+        hipLaunchKernelGGL((k_score<float, 0, false>), grid, block, 0, st, A);
 }
 
 // Sum of min distances of rows [0, nb) in FP64 (fixed order); adds to obj[1]

@@ -45,47 +45,63 @@ void launch_row_sqnorm(const float *X, int64_t n, int d, int64_t ld, float *sqn,
 // zero rows and raise flags[0]; non-finite values raise flags[1] (when
 // check_finite).  One wave per row.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gather_rows(
-    const float *__restrict__ X, int64_t n, int d, int64_t ld, const int32_t *__restrict__ idx,
-    int64_t cnt, int dp, float *__restrict__ out32, uint16_t *__restrict__ outhi,
-    uint16_t *__restrict__ outlo, float *__restrict__ outsq, double *__restrict__ outsq64,
-    int32_t *__restrict__ idx_copy, int32_t *__restrict__ flags, int check_finite)
+struct GatherArgs {
+    const float *X;
+    int64_t n;
+    int d;
+    int64_t ld;
+    const int32_t *idx;
+    int64_t cnt;
+    int dp;
+    float *out32;
+    uint16_t *outhi, *outlo;
+    float *outsq;
+    double *outsq64;
+    int32_t *idx_copy;
+    int32_t *flags;
+    int check_finite;
+};
+
+// One wave per row; `blk` numbers groups of 4 rows.
+__device__ __forceinline__ void gather_rows_body(const GatherArgs &A, int64_t blk)
 {
     const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (row >= cnt)
+    const int64_t row = blk * 4 + (threadIdx.x >> 6);
+    if (row >= A.cnt)
         return;
-    int64_t p = idx ? (int64_t)idx[row] : row;
-    bool ok = p >= 0 && p < n;
+    const int64_t p = A.idx ? (int64_t)A.idx[row] : row;
+    const bool ok = p >= 0 && p < A.n;
     if (!ok && lane == 0)
-        atomicOr(&flags[0], 1);
-    if (idx_copy && lane == 0)
-        idx_copy[row] = (int32_t)p;
-    const float *src = X + (ok ? p : 0) * ld;
+        atomicOr(&A.flags[0], 1);
+    if (A.idx_copy && lane == 0)
+        A.idx_copy[row] = (int32_t)p;
+    const float *src = A.X + (ok ? p : 0) * A.ld;
     double s = 0.0;
     bool finite = true;
-    for (int t = lane; t < dp; t += 64) {
-        float v = (ok && t < d) ? src[t] : 0.0f;
+    for (int t = lane; t < A.dp; t += 64) {
+        const float v = (ok && t < A.d) ? src[t] : 0.0f;
         finite &= isfinite(v);
-        out32[row * dp + t] = v;
-        if (outhi) {
-            uint16_t h = f32_to_bf16_rne(v);
-            uint16_t l = f32_to_bf16_rne(v - bf16_to_f32(h));
-            outhi[row * dp + t] = h;
-            outlo[row * dp + t] = l;
+        A.out32[row * A.dp + t] = v;
+        if (A.outhi) {
+            const uint16_t h = f32_to_bf16_rne(v);
+            const uint16_t l = f32_to_bf16_rne(v - bf16_to_f32(h));
+            A.outhi[row * A.dp + t] = h;
+            A.outlo[row * A.dp + t] = l;
         }
         s += (double)v * (double)v;
     }
-    if (check_finite && !finite)
-        atomicOr(&flags[1], 1);
+    if (A.check_finite && !finite)
+        atomicOr(&A.flags[1], 1);
     for (int o = 32; o > 0; o >>= 1)
         s += __shfl_xor(s, o);
     if (lane == 0) {
-        outsq[row] = (float)s;
-        if (outsq64)
-            outsq64[row] = s;
+        A.outsq[row] = (float)s;
+        if (A.outsq64)
+            A.outsq64[row] = s;
     }
 }
+
+__global__ __launch_bounds__(256) void k_gather_rows(const GatherArgs A) { gather_rows_body(A, blockIdx.x); }
 
 void launch_gather_rows(const float *X, int64_t n, int d, int64_t ld, const int32_t *idx, int64_t cnt,
                         int dp, float *out32, uint16_t *outhi, uint16_t *outlo, float *outsq,
@@ -94,9 +110,9 @@ void launch_gather_rows(const float *X, int64_t n, int d, int64_t ld, const int3
 {
     if (cnt <= 0)
         return;
-    int64_t blocks = (cnt + 3) / 4;
-    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)blocks), dim3(256), 0, st, X, n, d, ld, idx, cnt,
-                       dp, out32, outhi, outlo, outsq, outsq64, idx_copy, flags, check_finite);
+    const GatherArgs A{X, n, d, ld, idx, cnt, dp, out32, outhi, outlo, outsq, outsq64, idx_copy, flags, check_finite};
+    const int64_t blocks = (cnt + 3) / 4;
+    hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)blocks), dim3(256), 0, st, A);
 }
 
 // ---------------------------------------------------------------------------
@@ -182,16 +198,44 @@ __device__ __forceinline__ int seg_len(int j, int k, const int32_t *__restrict__
     return len;
 }
 
-__global__ __launch_bounds__(256) void k_support_fill(
-    int k, int C, int bmax, int pad, int64_t zero_row, const int32_t *__restrict__ ring_off,
-    const int32_t *__restrict__ ring_perm, SlotList live, int init_alive, const double *__restrict__ coef,
-    const double *__restrict__ G, int32_t *__restrict__ seg_off, int32_t *__restrict__ sup_row,
-    float *__restrict__ sup_w, double *__restrict__ sup_w64, int32_t *__restrict__ blk_center,
-    double *__restrict__ N)
+struct SupportArgs {
+    int k, C, bmax, pad;
+    int64_t zero_row;
+    const int32_t *ring_off, *ring_perm;
+    SlotList live;
+    int init_alive;
+    const double *coef, *G;
+    int32_t *seg_off, *sup_row;
+    float *sup_w;
+    double *sup_w64;
+    int32_t *blk_center;
+    double *N;
+    float *sup_ay;        // MFMA path only (else null)
+    const float *poolsq;
+    float ay_scale;       // -log2(e) / kappa
+};
+
+__device__ void support_fill_body(const SupportArgs &A, int j)
 {
+    const int k = A.k, C = A.C, bmax = A.bmax, pad = A.pad;
+    const int64_t zero_row = A.zero_row;
+    const int32_t *__restrict__ ring_off = A.ring_off;
+    const int32_t *__restrict__ ring_perm = A.ring_perm;
+    const SlotList &live = A.live;
+    const int init_alive = A.init_alive;
+    const double *__restrict__ coef = A.coef;
+    const double *__restrict__ G = A.G;
+    int32_t *__restrict__ seg_off = A.seg_off;
+    int32_t *__restrict__ sup_row = A.sup_row;
+    float *__restrict__ sup_w = A.sup_w;
+    double *__restrict__ sup_w64 = A.sup_w64;
+    int32_t *__restrict__ blk_center = A.blk_center;
+    double *__restrict__ N = A.N;
+    float *__restrict__ sup_ay = A.sup_ay;
+    const float *__restrict__ poolsq = A.poolsq;
+    const float ay_scale = A.ay_scale;
     __shared__ int red[256];
     __shared__ int sh_start;
-    const int j = blockIdx.x;
     const int tid = threadIdx.x;
     // exclusive prefix of the padded lengths of centers < j
     int acc = 0;
@@ -223,6 +267,8 @@ __global__ __launch_bounds__(256) void k_support_fill(
             sup_row[pos] = j;
             sup_w[pos] = (float)w;
             sup_w64[pos] = w;
+            if (sup_ay)
+                sup_ay[pos] = ay_scale * poolsq[j];
         }
         ++pos;
     }
@@ -234,9 +280,12 @@ __global__ __launch_bounds__(256) void k_support_fill(
         const double w = coef[(int64_t)j * C + 1 + p];
         const int64_t row0 = (int64_t)k + (int64_t)p * bmax;
         for (int q = tid; q < a1 - a0; q += 256) {
-            sup_row[pos + q] = (int32_t)(row0 + perm[a0 + q]);
+            const int64_t row = row0 + perm[a0 + q];
+            sup_row[pos + q] = (int32_t)row;
             sup_w[pos + q] = (float)w;
             sup_w64[pos + q] = w;
+            if (sup_ay)
+                sup_ay[pos + q] = ay_scale * poolsq[row];
         }
         pos += a1 - a0;
     }
@@ -244,6 +293,8 @@ __global__ __launch_bounds__(256) void k_support_fill(
         sup_row[q] = (int32_t)zero_row;
         sup_w[q] = 0.0f;
         sup_w64[q] = 0.0;
+        if (sup_ay)
+            sup_ay[q] = 0.0f;
     }
     if (blk_center) {
         for (int q = start / 32 + tid; q < (start + plen) / 32; q += 256)
@@ -267,142 +318,137 @@ __global__ __launch_bounds__(256) void k_support_fill(
     }
 }
 
-void launch_support_fill(const Layout &L, const Buffers &B, const SlotList &live, int init_alive, hipStream_t st)
+// One launch prepares an iteration: workgroups [0, nsup) lay out the support
+// of C_i (one per center), the others stage the batch rows (4 per workgroup).
+__global__ __launch_bounds__(256) void k_prepare(const SupportArgs S, int nsup, const GatherArgs Gth)
 {
-    hipLaunchKernelGGL(k_support_fill, dim3(L.k), dim3(256), 0, st, L.k, L.C, L.bmax, L.pad, L.PR, B.ring_off,
-                       B.ring_perm, live, init_alive, B.coef, B.G, B.seg_off, B.sup_row, B.sup_w, B.sup_w64,
-                       L.pad == kMfmaPad ? B.blk_center : nullptr, B.N);
+    if ((int)blockIdx.x < nsup)
+        support_fill_body(S, blockIdx.x);
+    else
+        gather_rows_body(Gth, (int64_t)blockIdx.x - nsup);
+}
+
+void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const SlotList &live, int init_alive,
+                    const int32_t *idx, int64_t cnt, int check_finite, float ay_scale, hipStream_t st)
+{
+    SupportArgs S;
+    S.k = L.k;
+    S.C = L.C;
+    S.bmax = L.bmax;
+    S.pad = L.pad;
+    S.zero_row = L.PR;
+    S.ring_off = B.ring_off;
+    S.ring_perm = B.ring_perm;
+    S.live = live;
+    S.init_alive = init_alive;
+    S.coef = B.coef;
+    S.G = B.G;
+    S.seg_off = B.seg_off;
+    S.sup_row = B.sup_row;
+    S.sup_w = B.sup_w;
+    S.sup_w64 = B.sup_w64;
+    S.blk_center = L.pad == kMfmaPad ? B.blk_center : nullptr;
+    S.N = B.N;
+    S.sup_ay = L.pad == kMfmaPad ? B.sup_ay : nullptr;
+    S.poolsq = B.poolsq;
+    S.ay_scale = ay_scale;
+    const GatherArgs Gth{B.X, L.n, L.d, B.ld, idx, cnt, L.dp, B.bat32, B.bathi, B.batlo, B.batsq, B.batsq64,
+                         B.batidx, B.flags, check_finite};
+    const int nsup = with_support ? L.k : 0;
+    const int64_t ngat = cnt > 0 ? (cnt + 3) / 4 : 0;
+    if (nsup + ngat > 0)
+        hipLaunchKernelGGL(k_prepare, dim3((unsigned)(nsup + ngat)), dim3(256), 0, st, S, nsup, Gth);
 }
 
 // ---------------------------------------------------------------------------
-// Gram work items of one slot: center j's grouped positions split into
-// chunks of `rows`.  Single workgroup.
+// Update of Algorithm 2.  The batch is grouped by center in a deterministic,
+// stable order (each center's points in batch order):
+//   the scoring kernel ranks each row among the equal labels before it in its
+//   chunk of 64 rows and counts the chunk's labels; then one workgroup
+//   computes the counts b_i^j, the offsets of the centers in the new slot,
+//   per-(chunk, label) bases, the learning rates alpha, the coefficient
+//   update and truncation, the batch objective, and scatters every row to
+//   base + rank.
 // ---------------------------------------------------------------------------
-__device__ void build_chunks(int k, int rows, const int32_t *__restrict__ off, int32_t *__restrict__ chunk_off,
-                             int32_t *__restrict__ chunk_j, int32_t *__restrict__ chunk_a0,
-                             int32_t *__restrict__ chunk_a1, int32_t *__restrict__ nchunks, int *scratch)
+// Block-wide exclusive scan of one int per thread (blockDim.x a multiple of
+// 64, at most 1024): wave scans with shuffles, then a scan of the wave totals.
+// `lds` holds at least 16 ints.  Returns the exclusive prefix; *total gets the sum.
+__device__ int block_exclusive_scan(int v, int *lds, int *total)
 {
-    // scratch: blockDim.x ints; off must be complete before the call
-    __syncthreads();
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int per = (k + nt - 1) / nt;
-    const int j0 = tid * per, j1 = min(k, j0 + per);
-    int local = 0;
-    for (int j = j0; j < j1; ++j)
-        local += (off[j + 1] - off[j] + rows - 1) / rows;
-    scratch[tid] = local;
-    __syncthreads();
-    for (int s = 1; s < nt; s <<= 1) {
-        const int v = tid >= s ? scratch[tid - s] : 0;
-        __syncthreads();
-        scratch[tid] += v;
-        __syncthreads();
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o)
+            x += y;
     }
-    int base = scratch[tid] - local;
-    for (int j = j0; j < j1; ++j) {
-        chunk_off[j] = base;
-        const int a0 = off[j], a1 = off[j + 1];
-        for (int a = a0; a < a1; a += rows) {
-            chunk_j[base] = j;
-            chunk_a0[base] = a;
-            chunk_a1[base] = min(a1, a + rows);
-            ++base;
+    if (lane == 63)
+        lds[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        int t = lane < nw ? lds[lane] : 0;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(t, o);
+            if (lane >= o)
+                t += y;
         }
-    }
-    if (tid == nt - 1) {
-        chunk_off[k] = scratch[nt - 1];
-        *nchunks = scratch[nt - 1];
+        if (lane < nw)
+            lds[lane] = t;
     }
     __syncthreads();
-}
-
-__global__ __launch_bounds__(1024) void k_chunks(int k, int rows, const int32_t *__restrict__ off,
-                                                  int32_t *__restrict__ chunk_off, int32_t *__restrict__ chunk_j,
-                                                  int32_t *__restrict__ chunk_a0, int32_t *__restrict__ chunk_a1,
-                                                  int32_t *__restrict__ nchunks)
-{
-    __shared__ int scratch[1024];
-    build_chunks(k, rows, off, chunk_off, chunk_j, chunk_a0, chunk_a1, nchunks, scratch);
-}
-
-void launch_chunks(const Layout &L, const Buffers &B, int p, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_chunks, dim3(1), dim3(1024), 0, st, L.k, L.gram_rows, B.ring_off + (int64_t)p * (L.k + 1),
-                       B.chunk_off, B.chunk_j, B.chunk_a0, B.chunk_a1, B.nchunks);
-}
-
-// ---------------------------------------------------------------------------
-// Update of Algorithm 2, in three launches that group the batch by center in
-// a deterministic, stable order (each center's points in batch order):
-//   rank    : per chunk of 256 rows, each row's rank among the equal labels
-//             before it, and the chunk's count of every label;
-//   offsets : (one workgroup) counts b_i^j, offsets of the centers in the new
-//             slot, per-(chunk, label) bases, learning rates alpha, the
-//             coefficient update and truncation, the batch objective, the
-//             Gram work items;
-//   scatter : grouped position of every row = base + rank.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kChunk) void k_group_rank(int b, int k, const int32_t *__restrict__ labels,
-                                                        int32_t *__restrict__ rank, int32_t *__restrict__ gcnt)
-{
-    __shared__ int sl[kChunk];
-    const int g = blockIdx.x, tid = threadIdx.x;
-    const int p = g * kChunk + tid;
-    // labels outside [0, k) are clamped so that every index below stays in range
-    const int lab = p < b ? min(max(labels[p], 0), k - 1) : -1;
-    sl[tid] = lab;
-    int32_t *cnt = gcnt + (int64_t)g * k;
-    for (int j = tid; j < k; j += kChunk)
-        cnt[j] = 0;
+    const int res = (wid > 0 ? lds[wid - 1] : 0) + x - v;
+    *total = lds[nw - 1];
     __syncthreads();
-    int r = 0, c = 0;
-    for (int t = 0; t < kChunk; ++t) {
-        const int v = sl[t];  // wave-uniform address: LDS broadcast
-        const int eq = v == lab;
-        c += eq;
-        r += eq & (t < tid);
-    }
-    if (p < b) {
-        rank[p] = r;
-        if (r == c - 1)
-            cnt[lab] = c;
-    }
+    return res;
+}
+
+// Block-wide sum of one double per thread, in a fixed order (wave trees,
+// then the wave totals in order).  `lds` holds at least 16 doubles.
+__device__ double block_sum(double v, double *lds)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o);
+    if (lane == 0)
+        lds[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w)
+        t += lds[w];
+    __syncthreads();
+    return t;
 }
 
 __global__ __launch_bounds__(1024) void k_group_offsets(
     int b, int k, int nchunk, int C, int p_new, int p_expired, int init_alive_before, int init_keep,
-    SlotList live, int lr, int gram_rows, int32_t *__restrict__ gcnt, const float *__restrict__ mind,
+    SlotList live, int lr, const int32_t *__restrict__ gcnt, int32_t *__restrict__ gbase,
+    const float *__restrict__ mind,
     double *__restrict__ coef, double *__restrict__ cum, int32_t *__restrict__ counts,
-    double *__restrict__ alpha, int32_t *__restrict__ off, int32_t *__restrict__ chunk_off,
-    int32_t *__restrict__ chunk_j, int32_t *__restrict__ chunk_a0, int32_t *__restrict__ chunk_a1,
-    int32_t *__restrict__ nchunks, double *__restrict__ obj)
+    double *__restrict__ alpha, int32_t *__restrict__ off, double *__restrict__ obj,
+    const int32_t *__restrict__ labels, const int32_t *__restrict__ rank, const int32_t *__restrict__ pts,
+    int32_t *__restrict__ ring_idx, int32_t *__restrict__ ring_perm)
 {
-    __shared__ int scratch[1024];
-    __shared__ double red[1024];
+    __shared__ int sint[16];
+    __shared__ double sdbl[16];
     const int tid = threadIdx.x, nt = blockDim.x;
     const int per = (k + nt - 1) / nt;
     const int j0 = tid * per, j1 = min(k, j0 + per);
     // totals of this thread's labels, block-wide exclusive scan -> offsets
     int local = 0;
-    for (int j = j0; j < j1; ++j)
+    for (int j = j0; j < j1; ++j) {
+#pragma unroll 8
         for (int g = 0; g < nchunk; ++g)
             local += gcnt[(int64_t)g * k + j];
-    scratch[tid] = local;
-    __syncthreads();
-    for (int s = 1; s < nt; s <<= 1) {
-        const int v = tid >= s ? scratch[tid - s] : 0;
-        __syncthreads();
-        scratch[tid] += v;
-        __syncthreads();
     }
-    int run = scratch[tid] - local;
+    int total;
+    int run = block_exclusive_scan(local, sint, &total);
     for (int j = j0; j < j1; ++j) {
         off[j] = run;
         int gb = run;
+#pragma unroll 8
         for (int g = 0; g < nchunk; ++g) {
-            const int c = gcnt[(int64_t)g * k + j];
-            gcnt[(int64_t)g * k + j] = gb;  // base of label j in chunk g
-            gb += c;
+            gbase[(int64_t)g * k + j] = gb;  // base of label j in chunk g
+            gb += gcnt[(int64_t)g * k + j];
         }
         const int bj = gb - run;
         run = gb;
@@ -429,159 +475,150 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
         if (!init_keep)
             cf[0] = 0.0;
     }
-    if (tid == nt - 1)
+    if (tid == 0)
         off[k] = b;
-    // sum of min distances (FP64), fixed-order tree
+    // sum of min distances (FP64), fixed order
     double sm = 0.0;
     for (int p = tid; p < b; p += nt)
         sm += (double)mind[p];
-    red[tid] = sm;
-    __syncthreads();
-    for (int h = nt / 2; h > 0; h >>= 1) {
-        if (tid < h)
-            red[tid] += red[tid + h];
-        __syncthreads();
-    }
+    sm = block_sum(sm, sdbl);  // (its barriers also publish the bases above)
     if (tid == 0)
-        obj[0] = red[0];
-    build_chunks(k, gram_rows, off, chunk_off, chunk_j, chunk_a0, chunk_a1, nchunks, scratch);
-}
-
-__global__ __launch_bounds__(kChunk) void k_group_scatter(int b, int k, const int32_t *__restrict__ labels,
-                                                           const int32_t *__restrict__ rank,
-                                                           const int32_t *__restrict__ gbase,
-                                                           const int32_t *__restrict__ pts,
-                                                           int32_t *__restrict__ ring_idx,
-                                                           int32_t *__restrict__ ring_perm)
-{
-    const int g = blockIdx.x;
-    const int p = g * kChunk + threadIdx.x;
-    if (p >= b)
-        return;
-    const int lab = min(max(labels[p], 0), k - 1);
-    const int pos = gbase[(int64_t)g * k + lab] + rank[p];
-    ring_perm[pos] = p;
-    ring_idx[pos] = pts[p];
+        obj[0] = sm;
+    // scatter: grouped position of every row = base of (chunk, label) + rank
+    for (int p = tid; p < b; p += nt) {
+        const int lab = min(max(labels[p], 0), k - 1);
+        const int pos = gbase[(int64_t)(p / kChunk) * k + lab] + rank[p];
+        ring_perm[pos] = p;
+        ring_idx[pos] = pts[p];
+    }
 }
 
 void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
                    int init_keep, const SlotList &live, int lr, hipStream_t st)
 {
     const int nchunk = (b + kChunk - 1) / kChunk;
-    hipLaunchKernelGGL(k_group_rank, dim3(nchunk), dim3(kChunk), 0, st, b, L.k, B.labels, B.rank, B.gcnt);
     hipLaunchKernelGGL(k_group_offsets, dim3(1), dim3(1024), 0, st, b, L.k, nchunk, L.C, p_new, p_expired,
-                       init_alive_before, init_keep, live, lr, L.gram_rows, B.gcnt, B.mind, B.coef, B.cum,
-                       B.counts, B.alpha, B.ring_off + (int64_t)p_new * (L.k + 1), B.chunk_off, B.chunk_j,
-                       B.chunk_a0, B.chunk_a1, B.nchunks, B.obj);
-    hipLaunchKernelGGL(k_group_scatter, dim3(nchunk), dim3(kChunk), 0, st, b, L.k, B.labels, B.rank, B.gcnt,
+                       init_alive_before, init_keep, live, lr, B.gcnt, B.gbase, B.mind, B.coef, B.cum, B.counts,
+                       B.alpha,
+                       B.ring_off + (int64_t)p_new * (L.k + 1), B.obj, B.labels, B.rank,
                        B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,
                        B.ring_perm + (int64_t)p_new * L.bmax);
 }
 
 // ---------------------------------------------------------------------------
-// Gram blocks of slot rr against every live column (FP32 or FP64 kernel
-// values, FP64 sums):  for each work item q = (j, grouped positions a0..a1 of
-// slot rr) and column c,
-//   Gpart[q][c] = sum_{a in q} sum_{e in column c, center j} K(a, e).
-// Column 0 is the initial point of center j; column 1+p is slot p.
-// Grid: (maxchunks, C); work items past *nchunks exit.  Each workgroup walks
-// the column's rows in tiles of 16; a thread owns one (a, e) pair, and both
-// row sets are staged through LDS 64 coordinates at a time, so any d works.
+// Gram blocks of slot rr (FP32 or FP64 kernel values, FP64 sums):
+//   G_j[1+rr][c] = G_j[c][1+rr] = sum_{a in slot rr, center j} sum_{e in column c, center j} K(a, e)
+// for every live column c (0: the initial point of center j; 1+p: slot p).
+// One workgroup per (center j, column c).  Rows are taken 48 x 48 at a time
+// and coordinates 128 at a time (one load phase when d <= 128); each thread
+// owns a 3 x 3 tile of pairs.
 // ---------------------------------------------------------------------------
-constexpr int kGramTile = 16, kGramK = 64, kGramLd = kGramK + 4;  // 272-byte LDS rows
+constexpr int kGT = 48, kGK = 128, kGLd = kGK + 1;  // odd LDS stride: conflict-free column reads
 
 template <int KIND, typename KT>
-__device__ __forceinline__ void gram_acc4(KT &s, const float4 a, const float4 e)
+__device__ __forceinline__ void gram_term(KT &s, KT x, KT y)
 {
-    const float av[4] = {a.x, a.y, a.z, a.w}, ev[4] = {e.x, e.y, e.z, e.w};
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const KT x = (KT)av[u], y = (KT)ev[u];
-        if constexpr (KIND == MBKK_GAUSS) {
-            const KT v = x - y;
-            s = fma(v, v, s);
-        } else if constexpr (KIND == MBKK_LAPLACE) {
-            s += fabs(x - y);
-        } else {
-            s = fma(x, y, s);
-        }
+    if constexpr (KIND == MBKK_GAUSS) {
+        const KT v = x - y;
+        s = fma(v, v, s);
+    } else if constexpr (KIND == MBKK_LAPLACE) {
+        s += fabs(x - y);
+    } else {
+        s = fma(x, y, s);
     }
+}
+
+template <int KIND, typename KT>
+__device__ __forceinline__ KT gram_finish(KT s, KT prm)
+{
+    if constexpr (KIND == MBKK_GAUSS || KIND == MBKK_LAPLACE)
+        return (KT)exp(-s / prm);
+    else if constexpr (KIND == MBKK_LINEAR)
+        return s;
+    else
+        return (s + prm) * (s + prm);
 }
 
 template <int KIND, typename KT>
 __global__ __launch_bounds__(256) void k_gram(int k, int C, int bmax, int d, int dp, double param, int rr,
                                                uint32_t col_mask, const int32_t *__restrict__ ring_off,
                                                const int32_t *__restrict__ ring_perm,
-                                               const float *__restrict__ pool32,
-                                               const int32_t *__restrict__ nchunks,
-                                               const int32_t *__restrict__ chunk_j,
-                                               const int32_t *__restrict__ chunk_a0,
-                                               const int32_t *__restrict__ chunk_a1, double *__restrict__ Gpart)
+                                               const float *__restrict__ pool32, double *__restrict__ G)
 {
-    __shared__ __attribute__((aligned(16))) float sa[kGramTile][kGramLd];
-    __shared__ __attribute__((aligned(16))) float se[kGramTile][kGramLd];
+    __shared__ float sa[kGT * kGLd], se[kGT * kGLd];
     __shared__ double red[256];
-    const int q = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
-    if (q >= *nchunks)
-        return;
-    if (!((col_mask >> c) & 1u)) {
-        if (tid == 0)
-            Gpart[(int64_t)q * C + c] = 0.0;
-        return;
-    }
-    const int j = chunk_j[q], a0 = chunk_a0[q];
-    const int na = chunk_a1[q] - a0;
-    const int pa = tid >> 4, pe = tid & 15;      // this thread's pair
-    const int lr = tid >> 4, lc = (tid & 15) * 4;  // loader: row, 4 columns
-    // pool rows of the loader's a-row and of the column's rows
-    const int64_t arow = lr < na ? (int64_t)k + (int64_t)rr * bmax + ring_perm[(int64_t)rr * bmax + a0 + lr] : 0;
+    const int j = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
+    if (!((col_mask >> c) & 1u))
+        return;  // block uniform
+    // rows of slot rr for center j
+    const int32_t *oa = ring_off + (int64_t)rr * (k + 1);
+    const int na = oa[j + 1] - oa[j];
+    const int32_t *pa_perm = ring_perm + (int64_t)rr * bmax + oa[j];
+    const int64_t arow0 = (int64_t)k + (int64_t)rr * bmax;
+    // rows of column c for center j
     int ne;
-    int64_t erow0 = 0;
-    const int32_t *eperm = nullptr;
+    const int32_t *pe_perm = nullptr;
+    int64_t erow0;
     if (c == 0) {
         ne = 1;
         erow0 = j;
     } else {
         const int pc = c - 1;
-        const int32_t *o = ring_off + (int64_t)pc * (k + 1);
-        ne = o[j + 1] - o[j];
-        eperm = ring_perm + (int64_t)pc * bmax + o[j];
+        const int32_t *oe = ring_off + (int64_t)pc * (k + 1);
+        ne = oe[j + 1] - oe[j];
+        pe_perm = ring_perm + (int64_t)pc * bmax + oe[j];
         erow0 = (int64_t)k + (int64_t)pc * bmax;
     }
+    const int ty = tid >> 4, tx = tid & 15;  // pairs (ty + 16u, tx + 16v), u, v < 3
+    const int lr = tid >> 5, lc = (tid & 31) * 4;  // loader: rows lr + 8q, 4 coordinates
     const KT prm = (KT)param;
     double acc = 0.0;
-    for (int et = 0; et < ne; et += kGramTile) {
-        const bool eok = et + lr < ne;
-        const int64_t erow = eok ? (c == 0 ? erow0 : erow0 + eperm[et + lr]) : 0;
-        KT sacc = 0;
-        // coordinates past d are zero in the pool, so whole 64-wide chunks
-        // can be processed
-        for (int t0 = 0; t0 < d; t0 += kGramK) {
-            __syncthreads();
-            {
-                const int col = t0 + lc;
-                float4 va = make_float4(0.f, 0.f, 0.f, 0.f), ve = va;
-                if (lr < na && col < dp)
-                    va = *(const float4 *)(pool32 + arow * dp + col);
-                if (eok && col < dp)
-                    ve = *(const float4 *)(pool32 + erow * dp + col);
-                *(float4 *)&sa[lr][lc] = va;
-                *(float4 *)&se[lr][lc] = ve;
-            }
-            __syncthreads();
+    for (int at = 0; at < na; at += kGT) {
+        for (int et = 0; et < ne; et += kGT) {
+            KT sv[3][3];
 #pragma unroll
-            for (int t = 0; t < kGramK; t += 4)
-                gram_acc4<KIND, KT>(sacc, *(const float4 *)&sa[pa][t], *(const float4 *)&se[pe][t]);
-        }
-        if (pa < na && et + pe < ne) {
-            KT kv;
-            if constexpr (KIND == MBKK_GAUSS || KIND == MBKK_LAPLACE)
-                kv = (KT)exp(-sacc / prm);
-            else if constexpr (KIND == MBKK_LINEAR)
-                kv = sacc;
-            else
-                kv = (sacc + prm) * (sacc + prm);
-            acc += (double)kv;
+            for (int u = 0; u < 3; ++u)
+#pragma unroll
+                for (int v = 0; v < 3; ++v)
+                    sv[u][v] = 0;
+            for (int t0 = 0; t0 < d; t0 += kGK) {
+                __syncthreads();
+                const int col = t0 + lc;
+#pragma unroll
+                for (int q = 0; q < kGT / 8; ++q) {
+                    const int r = lr + 8 * q;
+                    float4 va = make_float4(0.f, 0.f, 0.f, 0.f), ve = va;
+                    if (at + r < na && col < dp)
+                        va = *(const float4 *)(pool32 + (arow0 + pa_perm[at + r]) * dp + col);
+                    if (et + r < ne && col < dp)
+                        ve = *(const float4 *)(pool32 + (c == 0 ? erow0 : erow0 + pe_perm[et + r]) * dp + col);
+                    float *da = sa + r * kGLd + lc, *de = se + r * kGLd + lc;
+                    da[0] = va.x; da[1] = va.y; da[2] = va.z; da[3] = va.w;
+                    de[0] = ve.x; de[1] = ve.y; de[2] = ve.z; de[3] = ve.w;
+                }
+                __syncthreads();
+                // coordinates past d (or past dp) are zero in LDS: whole chunks are safe
+#pragma unroll 4
+                for (int t = 0; t < kGK; ++t) {
+                    KT av[3], ev[3];
+#pragma unroll
+                    for (int u = 0; u < 3; ++u) {
+                        av[u] = (KT)sa[(ty + 16 * u) * kGLd + t];
+                        ev[u] = (KT)se[(tx + 16 * u) * kGLd + t];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 3; ++u)
+#pragma unroll
+                        for (int v = 0; v < 3; ++v)
+                            gram_term<KIND, KT>(sv[u][v], av[u], ev[v]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+#pragma unroll
+                for (int v = 0; v < 3; ++v)
+                    if (at + ty + 16 * u < na && et + tx + 16 * v < ne)
+                        acc += (double)gram_finish<KIND, KT>(sv[u][v], prm);
         }
     }
     red[tid] = acc;
@@ -591,18 +628,21 @@ __global__ __launch_bounds__(256) void k_gram(int k, int C, int bmax, int d, int
             red[tid] += red[tid + h];
         __syncthreads();
     }
-    if (tid == 0)
-        Gpart[(int64_t)q * C + c] = red[0];
+    if (tid == 0) {
+        double *g = G + (int64_t)j * C * C;
+        g[(1 + rr) * C + c] = red[0];
+        g[c * C + 1 + rr] = red[0];
+    }
 }
 
 template <typename KT>
 static void launch_gram_t(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param,
                           hipStream_t st)
 {
-    dim3 grid((unsigned)L.maxchunks, L.C);
+    dim3 grid(L.k, L.C);
 #define MBKK_GRAM(K)                                                                                             \
     hipLaunchKernelGGL((k_gram<K, KT>), grid, dim3(256), 0, st, L.k, L.C, L.bmax, L.d, L.dp, param, rr, col_mask, \
-                       B.ring_off, B.ring_perm, B.pool32, B.nchunks, B.chunk_j, B.chunk_a0, B.chunk_a1, B.Gpart)
+                       B.ring_off, B.ring_perm, B.pool32, B.G)
     switch (kind) {
     case MBKK_GAUSS: MBKK_GRAM(MBKK_GAUSS); break;
     case MBKK_LAPLACE: MBKK_GRAM(MBKK_LAPLACE); break;
@@ -619,34 +659,6 @@ void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, i
         launch_gram_t<double>(L, B, rr, col_mask, kind, param, st);
     else
         launch_gram_t<float>(L, B, rr, col_mask, kind, param, st);
-}
-
-// Folds the work-item partials of slot rr into G_j[1+rr][c] = G_j[c][1+rr]
-// (fixed order over the work items of center j).  One thread per center.
-__global__ __launch_bounds__(256) void k_gram_fold(int k, int C, int rr, uint32_t col_mask,
-                                                    const int32_t *__restrict__ chunk_off,
-                                                    const double *__restrict__ Gpart, double *__restrict__ G)
-{
-    const int j = blockIdx.x * 256 + threadIdx.x;
-    if (j >= k)
-        return;
-    double *g = G + (int64_t)j * C * C;
-    const int q0 = chunk_off[j], q1 = chunk_off[j + 1];
-    for (int c = 0; c < C; ++c) {
-        if (!((col_mask >> c) & 1u))
-            continue;
-        double s = 0.0;
-        for (int q = q0; q < q1; ++q)
-            s += Gpart[(int64_t)q * C + c];
-        g[(1 + rr) * C + c] = s;
-        g[c * C + 1 + rr] = s;
-    }
-}
-
-void launch_gram_fold(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_gram_fold, dim3((L.k + 255) / 256), dim3(256), 0, st, L.k, L.C, rr, col_mask,
-                       B.chunk_off, B.Gpart, B.G);
 }
 
 }  // namespace mbkk

@@ -23,8 +23,6 @@ struct mbkk_ctx {
     bool data_set = false;
     bool inited = false;
     int64_t iter = 1;           // index i of the next batch
-    int pending_r = -1;         // ring slot whose Gram partials still have to be folded
-    uint32_t pending_mask = 0;  // their live columns
     int64_t support_iter = -1;  // iteration for which the support layout is built
     std::vector<int32_t> slot_b;  // points held by each physical slot
     // timing of the cross-term kernel
@@ -87,17 +85,6 @@ Layout make_layout(const mbkk_config &c)
     const int64_t Mlive = (int64_t)c.k + (int64_t)c.window * c.b_max;
     L.Mcap = (int64_t)up((size_t)(Mlive + (int64_t)c.k * (L.pad - 1) + L.pad), 128);
     L.nblk = L.Mcap / 32;
-    L.gram_rows = kGramRowsMax;  // rows of the newest slot per Gram work item
-    // ranges of the batch-stationary MFMA kernel: about 1024 workgroups at
-    // b = b_max, an even number of blocks each (blocks are staged in pairs)
-    {
-        const int64_t nbt = (c.b_max + 255) / 256;
-        int64_t rb = (L.nblk * nbt + 1023) / 1024;
-        rb = rb < 2 ? 2 : rb;
-        rb += rb & 1;
-        L.mfma_rb = (int)rb;
-    }
-    L.maxchunks = c.b_max / L.gram_rows + c.k + 1;
     L.nchunk = (c.b_max + kChunk - 1) / kChunk;
     L.kpp_blocks = (c.n + 255) / 256;
     return L;
@@ -135,14 +122,11 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.alpha = (double *)take(8 * (size_t)L.k);
     B.rank = (int32_t *)take(4 * (size_t)L.bmax);
     B.gcnt = (int32_t *)take(4 * (size_t)L.nchunk * L.k);
-    B.chunk_j = (int32_t *)take(4 * L.maxchunks);
-    B.chunk_a0 = (int32_t *)take(4 * L.maxchunks);
-    B.chunk_a1 = (int32_t *)take(4 * L.maxchunks);
-    B.chunk_off = (int32_t *)take(4 * (size_t)(L.k + 1));
-    B.Gpart = (double *)take(8 * L.maxchunks * C);
+    B.gbase = (int32_t *)take(4 * (size_t)L.nchunk * L.k);
     B.seg_off = (int32_t *)take(4 * (size_t)(L.k + 1));
-    B.sup_row = (int32_t *)take(4 * L.Mcap);
+    B.sup_row = (int32_t *)take(4 * (L.Mcap + 1));  // [Mcap] = zero pool row (sentinel)
     B.sup_w = (float *)take(4 * L.Mcap);
+    B.sup_ay = (float *)take(4 * L.Mcap);
     B.sup_w64 = (double *)take(8 * L.Mcap);
     B.blk_center = (int32_t *)take(4 * L.nblk);
     size_t part_direct = (size_t)L.k * L.bmax * 8;  // FP64 worst case
@@ -153,7 +137,6 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.margin = (float *)take(4 * (size_t)L.bmax);
     B.obj = (double *)take(8 * 4);
     B.flags = (int32_t *)take(4 * 4);
-    B.nchunks = (int32_t *)take(4);
     B.D2 = (double *)take(8 * (size_t)L.n);
     B.kself = (double *)take(8 * (size_t)L.n);
     B.bsum = (double *)take(8 * (size_t)L.kpp_blocks);
@@ -247,6 +230,16 @@ static uint32_t col_mask_of(const SlotList &s, bool init_alive)
     return m;
 }
 
+// Gram blocks of slot p against the live columns in `mask`: on MFMA with the
+// form's own arithmetic for the Gaussian MFMA forms (d <= 128), else VALU.
+static void gram(mbkk_ctx *c, int p, uint32_t mask)
+{
+    if (c->use_mfma && c->L.dp <= 128)
+        launch_gram_mfma(c->L, c->B, p, mask, c->cfg.precision, c->cfg.kernel_param, c->stream);
+    else
+        launch_gram(c->L, c->B, p, mask, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->stream);
+}
+
 static int check_flags(mbkk_ctx *c)
 {
     int32_t f[2] = {0, 0};
@@ -281,34 +274,22 @@ static void set_batch_view(mbkk_ctx *c, int p)
     B.batsq64 = B.poolsq64 + r0;
 }
 
-// Gathers rows idx[0..cnt) of X into the free slot of the current iteration.
-static void stage_rows(mbkk_ctx *c, const int32_t *idx, int64_t cnt)
+// One launch: stages rows idx[0..cnt) into the free slot of the current
+// iteration and, when not done yet, lays out the support of C_i.
+static void prepare(mbkk_ctx *c, const int32_t *idx, int64_t cnt)
 {
     const Layout &L = c->L;
-    Buffers &B = c->B;
     set_batch_view(c, phys_of(c->iter, L.P));
-    launch_gather_rows(B.X, L.n, L.d, B.ld, idx, cnt, L.dp, B.bat32, B.bathi, B.batlo, B.batsq, B.batsq64,
-                       B.batidx, B.flags, c->cfg.validate, c->stream);
-}
-
-// Folds pending Gram partials and (re)builds the support of the current
-// centers C_i when needed.
-static void prepare_support(mbkk_ctx *c)
-{
-    const Layout &L = c->L;
-    if (c->pending_r >= 0) {
-        launch_gram_fold(L, c->B, c->pending_r, c->pending_mask, c->stream);
-        c->pending_r = -1;
-    }
-    if (c->support_iter != c->iter) {
-        SlotList live = live_before(c->iter, L.W);
-        const int init_alive = c->iter <= L.W + 1;
-        launch_support_fill(L, c->B, live, init_alive, c->stream);
+    const bool need = c->support_iter != c->iter;
+    const SlotList live = live_before(c->iter, L.W);
+    const int init_alive = c->iter <= L.W + 1;
+    const float ay_scale = (float)(-1.4426950408889634 / c->cfg.kernel_param);
+    launch_prepare(L, c->B, need, live, init_alive, idx, cnt, c->cfg.validate, ay_scale, c->stream);
+    if (need)
         c->support_iter = c->iter;
-    }
 }
 
-static int cross_and_score(mbkk_ctx *c, int nb, double *D_out, int64_t ldD)
+static int cross_and_score(mbkk_ctx *c, int nb, double *D_out, int64_t ldD, bool with_rank)
 {
     const Layout &L = c->L;
     const mbkk_config &cf = c->cfg;
@@ -334,9 +315,8 @@ static int cross_and_score(mbkk_ctx *c, int nb, double *D_out, int64_t ldD)
         HIPCHK(c, hipEventRecord(e1, c->stream));
         c->launches++;
     }
-    launch_score(L, c->B, nb, cf.kernel, cf.kernel_param, c->fp64, c->use_mfma, D_out, ldD, c->stream);
-    if (cf.precision == MBKK_BF16X3 || cf.precision == MBKK_BF16X1)
-        launch_rescore(L, c->B, nb, cf.kernel, cf.kernel_param, tie_delta(cf), c->stream);
+    launch_score(L, c->B, nb, cf.kernel, cf.kernel_param, c->fp64, c->use_mfma, cf.precision, tie_delta(cf), D_out,
+                 ldD, with_rank, c->stream);
     HIPCHK(c, hipGetLastError());
     return MBKK_OK;
 }
@@ -394,6 +374,8 @@ int mbkk_create(const mbkk_config *cfg, void *workspace, size_t bytes, void *str
     if (e == hipSuccess)
         e = hipMemsetAsync(c->B.poolsq64 + zr, 0, sizeof(double), c->stream);
     if (e == hipSuccess)
+        e = hipMemsetD32Async((hipDeviceptr_t)(c->B.sup_row + L.Mcap), (int)L.PR, 1, c->stream);
+    if (e == hipSuccess)
         e = hipMemsetAsync(c->B.flags, 0, 16, c->stream);
     if (e == hipSuccess)
         e = hipMemsetAsync(c->B.ring_off, 0, 4 * (size_t)L.P * (L.k + 1), c->stream);
@@ -446,7 +428,6 @@ static int init_common(mbkk_ctx *c, const int32_t *idx_dev)
     HIPCHK(c, hipMemsetAsync(B.ring_off, 0, 4 * (size_t)L.P * (L.k + 1), c->stream));
     HIPCHK(c, hipGetLastError());
     c->iter = 1;
-    c->pending_r = -1;
     c->support_iter = -1;
     std::fill(c->slot_b.begin(), c->slot_b.end(), 0);
     if (c->cfg.validate) {
@@ -506,9 +487,8 @@ int mbkk_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels_dev,
     const int W = L.W;
     if (c->cfg.validate && clear_flags(c))
         return MBKK_E_HIP;
-    stage_rows(c, batch, b);
-    prepare_support(c);
-    int rc = cross_and_score(c, b, nullptr, 0);
+    prepare(c, batch, b);
+    int rc = cross_and_score(c, b, nullptr, 0, true);
     if (rc)
         return rc;
     // update of the centers
@@ -521,10 +501,8 @@ int mbkk_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels_dev,
     launch_update(L, B, b, p_new, p_expired, init_alive_before, init_keep, live, c->cfg.lr, c->stream);
     const SlotList live_after = live_before(i + 1, W);
     const uint32_t mask = col_mask_of(live_after, init_keep);
-    launch_gram(L, B, p_new, mask, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->stream);
+    gram(c, p_new, mask);
     HIPCHK(c, hipGetLastError());
-    c->pending_r = p_new;
-    c->pending_mask = mask;
     c->slot_b[p_new] = b;
     c->iter = i + 1;
     if (labels_dev)
@@ -555,11 +533,12 @@ int mbkk_assign(mbkk_ctx *c, const int32_t *idx, int64_t m, int32_t *labels_dev,
     Buffers &B = c->B;
     if (c->cfg.validate && clear_flags(c))
         return MBKK_E_HIP;
-    prepare_support(c);
+    if (m == 0)
+        prepare(c, nullptr, 0);
     for (int64_t m0 = 0; m0 < m; m0 += L.bmax) {
         const int nb = (int)((m - m0) < L.bmax ? (m - m0) : L.bmax);
-        stage_rows(c, idx + m0, nb);
-        int rc = cross_and_score(c, nb, D_dev ? D_dev + m0 * L.k : nullptr, L.k);
+        prepare(c, idx + m0, nb);
+        int rc = cross_and_score(c, nb, D_dev ? D_dev + m0 * L.k : nullptr, L.k, false);
         if (rc)
             return rc;
         if (labels_dev)
@@ -585,11 +564,10 @@ int mbkk_objective(mbkk_ctx *c, const int32_t *idx, int64_t m, double *out_host)
     const Layout &L = c->L;
     if (c->cfg.validate && clear_flags(c))
         return MBKK_E_HIP;
-    prepare_support(c);
     for (int64_t m0 = 0; m0 < m; m0 += L.bmax) {
         const int nb = (int)((m - m0) < L.bmax ? (m - m0) : L.bmax);
-        stage_rows(c, idx + m0, nb);
-        int rc = cross_and_score(c, nb, nullptr, 0);
+        prepare(c, idx + m0, nb);
+        int rc = cross_and_score(c, nb, nullptr, 0, false);
         if (rc)
             return rc;
         launch_sum_mind(c->B, nb, m0 > 0, c->stream);
@@ -611,7 +589,7 @@ int mbkk_center_norms(mbkk_ctx *c, double *N_host)
         return fail(c, MBKK_E_STATE, "init_centers / init_kmeanspp first");
     if (!N_host)
         return fail(c, MBKK_E_INVALID, "N is NULL");
-    prepare_support(c);
+    prepare(c, nullptr, 0);
     HIPCHK(c, hipMemcpyAsync(N_host, c->B.N, 8 * (size_t)c->L.k, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return MBKK_OK;
@@ -732,16 +710,13 @@ int mbkk_set_state(mbkk_ctx *c, const mbkk_state *s)
     // Gram blocks of every live slot against every live column
     for (int q = 0; q < live.n; ++q) {
         const int p = live.r[q];
-        launch_chunks(L, B, p, c->stream);
-        launch_gram(L, B, p, mask, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->stream);
-        launch_gram_fold(L, B, p, mask, c->stream);
+        gram(c, p, mask);
     }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     for (int p = 0; p < P; ++p)
         c->slot_b[p] = sb[p];
     c->iter = i;
-    c->pending_r = -1;
     c->support_iter = -1;
     c->inited = true;
     return MBKK_OK;

@@ -25,8 +25,18 @@ constexpr int kMfmaPad = 32;      // MFMA path: every center segment is a multip
 constexpr int kMaxWindow = 30;    // W; physical slots P = W + 1
 constexpr int kMaxSlots = kMaxWindow + 1;
 constexpr int kMaxBatch = 8192;   // b_max
-constexpr int kGramRowsMax = 16;  // rows of the new slot per Gram work item
-constexpr int kChunk = 256;       // batch rows per grouping chunk
+constexpr int kChunk = 64;        // batch rows per grouping chunk (one scoring workgroup)
+// batch-stationary MFMA cross kernel: workgroups per compute unit (waves per
+// SIMD), and whether the exp epilogue of a block overlaps the next block's MFMAs
+#ifndef MBKK_BS_OCC
+#define MBKK_BS_OCC 1
+#endif
+#ifndef MBKK_BS_PIPE
+#define MBKK_BS_PIPE 1
+#endif
+constexpr int kBsOcc = MBKK_BS_OCC;
+constexpr bool kBsPipe = MBKK_BS_PIPE != 0;
+constexpr int kNumCU = 256;
 
 // Physical slots of the live batches, oldest batch first.
 struct SlotList {
@@ -75,15 +85,13 @@ struct Buffers {
     double *alpha = nullptr;      // [k]
     // grouping of a batch by center
     int32_t *rank = nullptr;      // [bmax] rank of a row among equal labels of its chunk
-    int32_t *gcnt = nullptr;      // [nchunk * k] per-chunk label counts, then bases
-    // Gram work items of the newest slot
-    int32_t *chunk_j = nullptr, *chunk_a0 = nullptr, *chunk_a1 = nullptr;  // [maxchunks]
-    int32_t *chunk_off = nullptr;  // [k+1]
-    double *Gpart = nullptr;       // [maxchunks * C]
+    int32_t *gcnt = nullptr;      // [nchunk * k] per-chunk label counts
+    int32_t *gbase = nullptr;     // [nchunk * k] per-chunk label bases in the new slot
     // support of the current centers (padded segments)
     int32_t *seg_off = nullptr;  // [k+1]
-    int32_t *sup_row = nullptr;  // [Mcap] pool row
+    int32_t *sup_row = nullptr;  // [Mcap + 1] pool row; [Mcap] = the zero row
     float *sup_w = nullptr;      // [Mcap]
+    float *sup_ay = nullptr;     // [Mcap] MFMA path: -log2(e) ||y||^2 / kappa of the entry's row
     double *sup_w64 = nullptr;   // [Mcap]
     int32_t *blk_center = nullptr;  // [Mcap/32]
     // cross-term output and assignment
@@ -93,7 +101,6 @@ struct Buffers {
     float *margin = nullptr;     // [bmax]
     double *obj = nullptr;       // [4] device scalars
     int32_t *flags = nullptr;    // [4] error flags (index, non-finite)
-    int32_t *nchunks = nullptr;  // [1]
     // k-means++
     double *D2 = nullptr;        // [n]
     double *kself = nullptr;     // [n]
@@ -108,9 +115,6 @@ struct Layout {
     int64_t PR;        // pool rows excluding the zero row: k + P * bmax
     int64_t Mcap;      // max padded support entries (multiple of 128)
     int64_t nblk;      // Mcap / 32
-    int gram_rows;     // rows per Gram work item
-    int mfma_rb;       // support blocks (32 rows) per range of the batch-stationary MFMA kernel
-    int64_t maxchunks; // Gram work items bound
     int nchunk;        // grouping chunks of a full batch: ceil(bmax / kChunk)
     int64_t kpp_blocks;
     bool bf16;
