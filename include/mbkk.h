@@ -170,6 +170,34 @@ int mbkk_objective(mbkk_ctx *ctx, const int32_t *idx_dev, int64_t m, double *out
 int mbkk_get_state(mbkk_ctx *ctx, mbkk_state *out_host);
 int mbkk_set_state(mbkk_ctx *ctx, const mbkk_state *in_host);
 
+/* Differentiation form, for tuning the bandwidth of the Gaussian kernel
+ * (Section 6 sets it by hand; here it can follow a gradient).  With the
+ * kernel in bandwidth form K_s(x, y) = exp(-||x - y||^2 / (2 s^2)) (kappa =
+ * 2 s^2) and the current centers' support points and weights held constant,
+ * the batch objective of Section 3 as a function of the batch coordinates xb
+ * and of s:
+ *   f(xb, s) = (1/b) sum_x min_j ||phi_s(x) - C_j||^2
+ *            = (1/b) sum_x [1 - 2 sum_{e in C_j} w_e K_s(x, y_e) + <C_j, C_j>_s],
+ * j the argmin (lowest index on ties), <C_j, C_j>_s re-evaluated at s.
+ * Gaussian kernel only; no state change.
+ *
+ * mbkk_objective_fwd: xb_dev [b x d] FP32 row-major dense device array,
+ * 1 <= b <= b_max, sigma > 0.  Writes labels_dev [b] int32 (may be NULL) and
+ * f_host.  The cross term uses the context's precision form.  Returns
+ * MBKK_E_NONFINITE for NaN/Inf coordinates. */
+int mbkk_objective_fwd(mbkk_ctx *ctx, const float *xb_dev, int32_t b, double sigma, int32_t *labels_dev,
+                       double *f_host);
+
+/* mbkk_objective_bwd: gradient of g * f at fixed labels labels_dev [b] (those
+ * of the forward: the hard assignment, a subgradient at ties):
+ *   dX_dev [b x d] FP32 = g (2 / (b s^2)) sum_{e in C_j} w_e K_s(x, y_e) (x - y_e)
+ *   dsigma_host        = g (1/b) sum_x [-2 sum_e w_e K_s(x, y_e) ||x - y_e||^2 / s^3
+ *                                       + d<C_j, C_j>_s / ds].
+ * Kernel values are recomputed (nothing of size b x M is stored); FP64
+ * arithmetic; d <= 1024.  Returns MBKK_E_INVALID for a label outside [0, k). */
+int mbkk_objective_bwd(mbkk_ctx *ctx, const float *xb_dev, int32_t b, double sigma, const int32_t *labels_dev,
+                       double g, float *dX_dev, double *dsigma_host);
+
 /* Self norms <C_j, C_j> of the current centers (FP64, accumulated from the
  * Gram blocks), N_host [k]; synchronises. */
 int mbkk_center_norms(mbkk_ctx *ctx, double *N_host);

@@ -31,6 +31,14 @@ void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double pa
                   int precision, double tie_delta, double *D_out, int64_t ldD, bool with_rank, hipStream_t st);
 void launch_sum_mind(const Buffers &B, int nb, int accumulate, hipStream_t st);
 
+// Differentiation form (Gaussian, bandwidth s): self norms and their
+// s-derivative for every center, and the per-row gradient plus the summed
+// df/ds (written to *out).
+void launch_selfnorm_sigma(const Layout &L, const Buffers &B, double sigma, double *N, double *dN, hipStream_t st);
+void launch_grad_rows(const Layout &L, const Buffers &B, const float *xb, int b, double sigma, const int32_t *labels,
+                      double g, const double *dN, float *dX, double *rowds, double *out, hipStream_t st);
+int grad_max_dim();
+
 // k-means++
 void launch_kpp_self(const Layout &L, const Buffers &B, int kind, double param, hipStream_t st);
 void launch_kpp_round(const Layout &L, const Buffers &B, int r, int kind, double param, hipStream_t st);

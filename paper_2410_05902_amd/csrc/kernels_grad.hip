@@ -1,0 +1,220 @@
+// Differentiation form of the batch objective (Section 3's f_B, Gaussian
+// kernel in the bandwidth form K_s(x, y) = exp(-||x - y||^2 / (2 s^2))):
+//   f(X_B, s) = (1/b) sum_x [1 - 2 P_j(x) + N_j],  j = j*(x) the argmin label,
+//   P_j(x) = sum_{e in C_j} w_e K_s(x, y_e),  N_j = sum_{e, e' in C_j} w_e w_e' K_s(y_e, y_e').
+// With the support points y_e and weights w_e held constant and hard labels:
+//   df/dx   = (2 / (b s^2)) sum_e w_e K_s(x, y_e) (x - y_e)
+//   df/ds   = (1/b) sum_x [-2 sum_e w_e K_s(x, y_e) ||x - y_e||^2 / s^3 + dN_j/ds]
+//   dN_j/ds = sum_{e, e'} w_e w_e' K_s(y_e, y_e') ||y_e - y_e'||^2 / s^3.
+// Kernel values are recomputed here (nothing of size b x M is stored); the
+// arithmetic is FP64 throughout.
+#include "kernels.h"
+
+namespace mbkk {
+
+// ---------------------------------------------------------------------------
+// N_j(s) and dN_j/ds: one workgroup per center, all ordered pairs of its
+// support entries, fixed pair-to-thread assignment and a fixed-order tree
+// reduction (deterministic).
+// ---------------------------------------------------------------------------
+struct SelfNormArgs {
+    int k, d, dp;
+    const int32_t *seg_off, *sup_row;
+    const double *sup_w64;
+    const float *pool32;
+    double inv_kappa;  // 1 / (2 s^2)
+    double inv_s3;     // 1 / s^3
+    double *N, *dN;
+};
+
+__global__ __launch_bounds__(256) void k_selfnorm_sigma(const SelfNormArgs A)
+{
+    __shared__ double rn[256], rd[256];
+    const int j = blockIdx.x, tid = threadIdx.x;
+    const int s0 = A.seg_off[j], L = A.seg_off[j + 1] - s0;
+    double sn = 0.0, sd = 0.0;
+    const int64_t npair = (int64_t)L * L;
+    for (int64_t p = tid; p < npair; p += 256) {
+        const int a = (int)(p / L), e = (int)(p % L);
+        const double wa = A.sup_w64[s0 + a], we = A.sup_w64[s0 + e];
+        if (wa == 0.0 || we == 0.0)
+            continue;
+        const float *ya = A.pool32 + (int64_t)A.sup_row[s0 + a] * A.dp;
+        const float *ye = A.pool32 + (int64_t)A.sup_row[s0 + e] * A.dp;
+        double d2 = 0.0;
+        for (int t = 0; t < A.d; ++t) {
+            const double v = (double)ya[t] - (double)ye[t];
+            d2 = fma(v, v, d2);
+        }
+        const double kv = exp(-d2 * A.inv_kappa);
+        sn = fma(wa * we, kv, sn);
+        sd = fma(wa * we * kv, d2, sd);
+    }
+    rn[tid] = sn;
+    rd[tid] = sd;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) {
+            rn[tid] += rn[tid + s];
+            rd[tid] += rd[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        A.N[j] = rn[0];
+        A.dN[j] = rd[0] * A.inv_s3;
+    }
+}
+
+void launch_selfnorm_sigma(const Layout &L, const Buffers &B, double sigma, double *N, double *dN, hipStream_t st)
+{
+    SelfNormArgs A;
+    A.k = L.k;
+    A.d = L.d;
+    A.dp = L.dp;
+    A.seg_off = B.seg_off;
+    A.sup_row = B.sup_row;
+    A.sup_w64 = B.sup_w64;
+    A.pool32 = B.pool32;
+    A.inv_kappa = 1.0 / (2.0 * sigma * sigma);
+    A.inv_s3 = 1.0 / (sigma * sigma * sigma);
+    A.N = N;
+    A.dN = dN;
+    hipLaunchKernelGGL(k_selfnorm_sigma, dim3((unsigned)L.k), dim3(256), 0, st, A);
+}
+
+// ---------------------------------------------------------------------------
+// Per-row gradient: one wave per batch row x, lane l holds coordinates
+// l + 64 c (c < CH) of x and of the accumulated sum_e w_e K (x - y_e); each
+// support entry of the row's center costs one wave reduction of ||x - y_e||^2.
+// Writes dX (scaled) and the row's term of df/ds.
+// ---------------------------------------------------------------------------
+struct GradRowArgs {
+    int b, d, dp, k;
+    const float *xb;  // [b x d] dense
+    const int32_t *labels;
+    const int32_t *seg_off, *sup_row;
+    const double *sup_w64;
+    const float *pool32;
+    const double *dN;
+    double inv_kappa, inv_s3, cx, cs;  // cx = 2 g / (b s^2), cs = g / b
+    float *dX;
+    double *rowds;   // [b]
+    int32_t *flags;  // flags[2]: a label outside [0, k)
+};
+
+template <int CH>
+__global__ __launch_bounds__(256) void k_grad_rows(const GradRowArgs A)
+{
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= A.b)
+        return;
+    const int j = A.labels[row];
+    if (j < 0 || j >= A.k) {
+        if (lane == 0) {
+            atomicOr(&A.flags[2], 1);
+            A.rowds[row] = 0.0;
+        }
+        for (int t = lane; t < A.d; t += 64)
+            A.dX[(int64_t)row * A.d + t] = 0.0f;
+        return;
+    }
+    double x[CH], acc[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const int t = lane + 64 * c;
+        x[c] = t < A.d ? (double)A.xb[(int64_t)row * A.d + t] : 0.0;
+        acc[c] = 0.0;
+    }
+    double q = 0.0;
+    const int s1 = A.seg_off[j + 1];
+    for (int s = A.seg_off[j]; s < s1; ++s) {
+        const double w = A.sup_w64[s];
+        if (w == 0.0)
+            continue;
+        const float *y = A.pool32 + (int64_t)A.sup_row[s] * A.dp;
+        double diff[CH], part = 0.0;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int t = lane + 64 * c;
+            diff[c] = t < A.d ? x[c] - (double)y[t] : 0.0;
+            part = fma(diff[c], diff[c], part);
+        }
+        for (int o = 32; o > 0; o >>= 1)
+            part += __shfl_xor(part, o);
+        const double wk = w * exp(-part * A.inv_kappa);
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+            acc[c] = fma(wk, diff[c], acc[c]);
+        q = fma(wk, part, q);
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const int t = lane + 64 * c;
+        if (t < A.d)
+            A.dX[(int64_t)row * A.d + t] = (float)(A.cx * acc[c]);
+    }
+    if (lane == 0)
+        A.rowds[row] = A.cs * (-2.0 * q * A.inv_s3 + A.dN[j]);
+}
+
+// Sum of the per-row terms in a fixed order (one workgroup).
+__global__ __launch_bounds__(1024) void k_sum_rows(const double *v, int n, double *out)
+{
+    __shared__ double r[1024];
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    for (int i = tid; i < n; i += 1024)
+        s += v[i];
+    r[tid] = s;
+    __syncthreads();
+    for (int o = 512; o > 0; o >>= 1) {
+        if (tid < o)
+            r[tid] += r[tid + o];
+        __syncthreads();
+    }
+    if (tid == 0)
+        *out = r[0];
+}
+
+int grad_max_dim() { return 64 * 16; }
+
+void launch_grad_rows(const Layout &L, const Buffers &B, const float *xb, int b, double sigma, const int32_t *labels,
+                      double g, const double *dN, float *dX, double *rowds, double *out, hipStream_t st)
+{
+    GradRowArgs A;
+    A.b = b;
+    A.d = L.d;
+    A.dp = L.dp;
+    A.k = L.k;
+    A.xb = xb;
+    A.labels = labels;
+    A.seg_off = B.seg_off;
+    A.sup_row = B.sup_row;
+    A.sup_w64 = B.sup_w64;
+    A.pool32 = B.pool32;
+    A.dN = dN;
+    A.inv_kappa = 1.0 / (2.0 * sigma * sigma);
+    A.inv_s3 = 1.0 / (sigma * sigma * sigma);
+    A.cx = 2.0 * g / ((double)b * sigma * sigma);
+    A.cs = g / (double)b;
+    A.dX = dX;
+    A.rowds = rowds;
+    A.flags = B.flags;
+    const dim3 grid((unsigned)((b + 3) / 4));
+    const int ch = (L.d + 63) / 64;
+    if (ch <= 1)
+        hipLaunchKernelGGL(k_grad_rows<1>, grid, dim3(256), 0, st, A);
+    else if (ch <= 2)
+        hipLaunchKernelGGL(k_grad_rows<2>, grid, dim3(256), 0, st, A);
+    else if (ch <= 4)
+        hipLaunchKernelGGL(k_grad_rows<4>, grid, dim3(256), 0, st, A);
+    else if (ch <= 8)
+        hipLaunchKernelGGL(k_grad_rows<8>, grid, dim3(256), 0, st, A);
+    else
+        hipLaunchKernelGGL(k_grad_rows<16>, grid, dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(1024), 0, st, (const double *)rowds, b, out);
+}
+
+}  // namespace mbkk

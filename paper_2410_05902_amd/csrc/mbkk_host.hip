@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -137,6 +138,9 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.margin = (float *)take(4 * (size_t)L.bmax);
     B.obj = (double *)take(8 * 4);
     B.flags = (int32_t *)take(4 * 4);
+    B.Nsig = (double *)take(8 * (size_t)L.k);
+    B.dNsig = (double *)take(8 * (size_t)L.k);
+    B.rowds = (double *)take(8 * (size_t)L.bmax);
     B.D2 = (double *)take(8 * (size_t)L.n);
     B.kself = (double *)take(8 * (size_t)L.n);
     B.bsum = (double *)take(8 * (size_t)L.kpp_blocks);
@@ -578,6 +582,109 @@ int mbkk_objective(mbkk_ctx *c, const int32_t *idx, int64_t m, double *out_host)
     *out_host = s / (double)m;
     if (c->cfg.validate)
         return check_flags(c);
+    return MBKK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Differentiation form (Gaussian kernel with bandwidth sigma, kappa = 2 sigma^2)
+// ---------------------------------------------------------------------------
+static int grad_args(mbkk_ctx *c, const float *xb, int32_t b, double sigma)
+{
+    if (!c)
+        return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (!c->inited)
+        return fail(c, MBKK_E_STATE, "init_centers / init_kmeanspp first");
+    if (c->cfg.kernel != MBKK_GAUSS)
+        return fail(c, MBKK_E_INVALID, "the differentiation form needs the Gaussian kernel");
+    if (!xb || b < 1 || b > c->L.bmax)
+        return fail(c, MBKK_E_INVALID, "need 1 <= b <= b_max rows of coordinates");
+    if (!(sigma > 0.0) || !std::isfinite(sigma))
+        return fail(c, MBKK_E_INVALID, "sigma must be finite and > 0");
+    return MBKK_OK;
+}
+
+// Lays out the support of C_i with the exponent constants of bandwidth kappa
+// and evaluates the self norms at sigma (N) and their derivative (dN).  The
+// next call that scores at the model's own bandwidth lays the support out again.
+static void support_at_sigma(mbkk_ctx *c, double sigma)
+{
+    const Layout &L = c->L;
+    const double kappa = 2.0 * sigma * sigma;
+    const SlotList live = live_before(c->iter, L.W);
+    const int init_alive = c->iter <= L.W + 1;
+    launch_prepare(L, c->B, true, live, init_alive, nullptr, 0, 0, (float)(-1.4426950408889634 / kappa), c->stream);
+    c->support_iter = -1;
+    launch_selfnorm_sigma(L, c->B, sigma, c->B.Nsig, c->B.dNsig, c->stream);
+}
+
+int mbkk_objective_fwd(mbkk_ctx *c, const float *xb_dev, int32_t b, double sigma, int32_t *labels_dev,
+                       double *f_host)
+{
+    int rc = grad_args(c, xb_dev, b, sigma);
+    if (rc)
+        return rc;
+    const Layout &L = c->L;
+    Buffers &B = c->B;
+    const mbkk_config &cf = c->cfg;
+    const double kappa = 2.0 * sigma * sigma;
+    if (clear_flags(c))
+        return MBKK_E_HIP;
+    // the rows go to the free slot of the current iteration
+    set_batch_view(c, phys_of(c->iter, L.P));
+    launch_gather_rows(xb_dev, b, L.d, L.d, nullptr, b, L.dp, B.bat32, B.bathi, B.batlo, B.batsq, B.batsq64, nullptr,
+                       B.flags, 1, c->stream);
+    support_at_sigma(c, sigma);
+    Buffers Bs = B;
+    Bs.N = B.Nsig;
+    if (c->use_mfma)
+        launch_cross_mfma(L, Bs, b, cf.precision, kappa, c->stream);
+    else
+        launch_cross_direct(L, Bs, b, MBKK_GAUSS, kappa, c->fp64, c->stream);
+    launch_score(L, Bs, b, MBKK_GAUSS, kappa, c->fp64, c->use_mfma, cf.precision, tie_delta(cf), nullptr, 0, false,
+                 c->stream);
+    launch_sum_mind(B, b, 0, c->stream);
+    HIPCHK(c, hipGetLastError());
+    if (labels_dev)
+        HIPCHK(c, hipMemcpyAsync(labels_dev, B.labels, 4 * (size_t)b, hipMemcpyDeviceToDevice, c->stream));
+    double s = 0.0;
+    int32_t f[2] = {0, 0};
+    HIPCHK(c, hipMemcpyAsync(&s, B.obj + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(f, B.flags, sizeof(f), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (f[1])
+        return fail(c, MBKK_E_NONFINITE, "non-finite value in the coordinates");
+    if (f_host)
+        *f_host = s / (double)b;
+    return MBKK_OK;
+}
+
+int mbkk_objective_bwd(mbkk_ctx *c, const float *xb_dev, int32_t b, double sigma, const int32_t *labels_dev,
+                       double g, float *dX_dev, double *dsigma_host)
+{
+    int rc = grad_args(c, xb_dev, b, sigma);
+    if (rc)
+        return rc;
+    if (!labels_dev || !dX_dev || !dsigma_host)
+        return fail(c, MBKK_E_INVALID, "labels, dX and dsigma are required");
+    if (c->L.d > grad_max_dim())
+        return fail(c, MBKK_E_INVALID, "the backward supports d <= " + std::to_string(grad_max_dim()));
+    if (!std::isfinite(g))
+        return fail(c, MBKK_E_INVALID, "g must be finite");
+    const Layout &L = c->L;
+    Buffers &B = c->B;
+    if (clear_flags(c))
+        return MBKK_E_HIP;
+    support_at_sigma(c, sigma);
+    launch_grad_rows(L, B, xb_dev, b, sigma, labels_dev, g, B.dNsig, dX_dev, B.rowds, B.obj + 2, c->stream);
+    HIPCHK(c, hipGetLastError());
+    double s = 0.0;
+    int32_t f[3] = {0, 0, 0};
+    HIPCHK(c, hipMemcpyAsync(&s, B.obj + 2, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(f, B.flags, sizeof(f), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (f[2])
+        return fail(c, MBKK_E_INVALID, "label outside [0, k)");
+    *dsigma_host = s;
     return MBKK_OK;
 }
 

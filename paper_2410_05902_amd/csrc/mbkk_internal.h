@@ -100,7 +100,11 @@ struct Buffers {
     float *mind = nullptr;       // [bmax]
     float *margin = nullptr;     // [bmax]
     double *obj = nullptr;       // [4] device scalars
-    int32_t *flags = nullptr;    // [4] error flags (index, non-finite)
+    int32_t *flags = nullptr;    // [4] error flags (index, non-finite, label)
+    // differentiation form
+    double *Nsig = nullptr;      // [k] self norms at the bandwidth of the call
+    double *dNsig = nullptr;     // [k] their derivative
+    double *rowds = nullptr;     // [bmax] per-row terms of df/dsigma
     // k-means++
     double *D2 = nullptr;        // [n]
     double *kself = nullptr;     // [n]

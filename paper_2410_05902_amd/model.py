@@ -174,3 +174,30 @@ class Model:
         ms, n = C.c_double(), C.c_int64()
         self._chk(L.lib().mbkk_get_timing(self._ctx, C.byref(ms), C.byref(n)))
         return float(ms.value), int(n.value)
+
+    # -- differentiation form (Gaussian kernel, bandwidth sigma) --------------
+    def _coords(self, xb: torch.Tensor) -> torch.Tensor:
+        if not (xb.is_cuda and xb.dtype == torch.float32 and xb.dim() == 2 and xb.shape[1] == self.X.shape[1]):
+            raise ValueError("xb must be a (b, d) float32 CUDA tensor")
+        return xb.contiguous()
+
+    def objective_fwd(self, xb: torch.Tensor, sigma: float):
+        """f(xb, sigma): the batch objective of Section 3 with the bandwidth-form
+        Gaussian kernel exp(-||x-y||^2 / (2 sigma^2)) against the current
+        centers.  Returns (f, labels)."""
+        x = self._coords(xb)
+        labels = torch.empty(x.shape[0], dtype=torch.int32, device=self.device)
+        f = C.c_double()
+        self._chk(L.lib().mbkk_objective_fwd(self._ctx, _ptr(x), x.shape[0], float(sigma), _ptr(labels),
+                                             C.byref(f)))
+        return float(f.value), labels
+
+    def objective_bwd(self, xb: torch.Tensor, sigma: float, labels: torch.Tensor, g: float = 1.0):
+        """Gradient of g * f at fixed labels: (dX (b, d) float32, dsigma float)."""
+        x = self._coords(xb)
+        lab = labels.to(device=self.device, dtype=torch.int32).contiguous()
+        dX = torch.empty_like(x)
+        ds = C.c_double()
+        self._chk(L.lib().mbkk_objective_bwd(self._ctx, _ptr(x), x.shape[0], float(sigma), _ptr(lab), float(g),
+                                             _ptr(dX), C.byref(ds)))
+        return dX, float(ds.value)
