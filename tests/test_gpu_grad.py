@@ -125,7 +125,7 @@ def test_autograd_function():
     f = batch_objective(model, x, s)
     (2.5 * f).backward()
     f2, lab = model.objective_fwd(x.detach(), wl.sigma)
-    assert float(f) == f2
+    assert float(f.detach()) == f2
     dX, ds = model.objective_bwd(x.detach(), wl.sigma, lab, 2.5)
     assert torch.equal(x.grad, dX)
     assert float(s.grad) == ds
