@@ -22,6 +22,9 @@ ARCH = "gfx950"
 CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           # no packed FP32 (v_pk_*_f32) generation
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          # the MFMA kernels' k-step loops must unroll fully (register-resident
+          # fragments and accumulators are indexed by the loop counters)
+          "-mllvm", "-pragma-unroll-threshold=1000000",
           "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 

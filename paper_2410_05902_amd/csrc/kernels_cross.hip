@@ -467,39 +467,58 @@ __global__ __launch_bounds__(256, 2) void k_cross_mfma(const CrossArgs A)
 
 // ===========================================================================
 // Batch-stationary MFMA cross kernel (d <= 128).  Each wave keeps the MFMA
-// fragments of its 64 batch rows (2 N-blocks, all of K) in registers for the
-// whole launch; the workgroup streams a range of RB support blocks (32 rows
-// each) through two LDS buffers, 64 rows (one stage) at a time.
+// fragments of its NBK x 32 batch rows (all of K) in registers for the whole
+// launch; the workgroup streams a range of RB support blocks (32 rows each)
+// through two LDS buffers, SB blocks (one stage) at a time.
 //  - Staging is by direct global->LDS loads (16 bytes per lane); each lane
 //    gathers its pool row through sup_row, whose entries for the next stage
 //    are fetched one stage ahead.  LDS rows are padded by one 16-byte chunk
 //    (conflict-free 128-bit fragment reads); the pad positions load a
-//    harmless chunk.
+//    harmless chunk.  A stage is long enough (SB = 4 blocks) for the loads of
+//    the next one to arrive while it computes.
 //  - The accumulator of a block starts at -||x||^2 / 2 (exact), so the
 //    exponent is c2 * acc + ay with ay = -log2(e) ||y||^2 / kappa staged per
 //    row: exp(-||x-y||^2 / kappa) = exp2(c2 * (x.y - ||x||^2/2) + ay).
-//  - The exp epilogue of block b-1 is issued between the MFMAs of block b.
+//  - The exp epilogue of block b-1 is issued between the MFMAs of block b,
+//    in program order, each MFMA with its share of VALU work fenced off from
+//    the scheduler: the VALU work then issues while the matrix core is busy.
 //  - Consecutive blocks of one center are summed in registers; a run is
 //    written once, at its first block ("run head": the first block of a
 //    center or of a range), so the partial buffer holds one value per
 //    (run, batch row).
-// Grid: (#ranges x #batch tiles of 256 rows), XCD-aware: the workgroups of one
-// XCD share support ranges.
+// Grid: (#ranges x #batch tiles of 128 NBK rows), one round of workgroups
+// (one per compute unit), XCD-aware: the workgroups of one XCD share support
+// ranges.
 // ===========================================================================
-// Blocks per range of the batch-stationary kernel for Mb support blocks split
-// over nranges ranges: an even number (blocks are staged in pairs), at least 2.
+constexpr int kBsStageBlocks = 4;  // support blocks (32 rows) per stage
+// Where the staging of the next stage is issued: spread between the MFMAs of
+// the stage's first block, or all at the start of the stage.
+#ifndef MBKK_BS_SPREAD
+#define MBKK_BS_SPREAD 1
+#endif
+constexpr bool kBsSpreadStaging = MBKK_BS_SPREAD != 0;
+
+// Blocks per range for Mb support blocks split over nranges ranges: a
+// multiple of the stage size.
 __device__ __forceinline__ int bs_range_blocks(int Mb, int nranges)
 {
-    int rb = (Mb + nranges - 1) / nranges;
-    rb = rb < 2 ? 2 : rb;
-    return rb + (rb & 1);
+    const int rb = (Mb + nranges - 1) / nranges;
+    return (rb + kBsStageBlocks - 1) / kBsStageBlocks * kBsStageBlocks;
 }
 
-// Ranges of the batch-stationary kernel for nb batch rows: one round of
-// workgroups (kBsOcc per compute unit).
-static int bs_nranges(int nb)
+// Batch rows held in registers per wave, in 32-row N-blocks: as many as the
+// register file allows (one wave per SIMD: 256 VGPRs + 256 AGPRs) with two
+// accumulator sets (the pipelined epilogue) and few copies between the two
+// register kinds.  FP32 fragments are 2x larger and each FP32 MFMA is 2x
+// longer, so two N-blocks already amortise the support reads.
+__host__ __device__ constexpr int bs_nbk(int mode, int dp) { return mode == 0 ? 2 : (mode == 1 && dp > 64 ? 2 : 4); }
+static int bs_tile_rows(int mode, int dp) { return 4 * 32 * bs_nbk(mode, dp); }
+static int bs_mode(int precision) { return precision == MBKK_FP32 ? 0 : (precision == MBKK_BF16X3 ? 1 : 2); }
+// Ranges for nb batch rows: one round of workgroups (kBsOcc per compute unit).
+static int bs_nranges(int nb, int mode, int dp)
 {
-    const int nbt = (nb + 255) / 256;
+    const int tr = bs_tile_rows(mode, dp);
+    const int nbt = (nb + tr - 1) / tr;
     const int r = kNumCU * kBsOcc / nbt;
     return r < 1 ? 1 : r;
 }
@@ -529,20 +548,46 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
 {
     constexpr bool F32 = MODE == 0;
     constexpr bool X3 = MODE == 1;
+    constexpr int NBK = bs_nbk(MODE, DP);          // 32-row N-blocks (batch rows) per wave
+    constexpr int SB = kBsStageBlocks;
     constexpr int KS = F32 ? DP / 2 : DP / 16;     // MFMA k-steps over K = DP
     constexpr int ES = F32 ? 4 : 2;                // element bytes
     constexpr int CPR = DP * ES / 16;              // 16-byte chunks per row
     constexpr int CPS = CPR + 1;                   // chunk positions per LDS row (one pad)
-    constexpr int ROWS = 64;                       // support rows per stage (2 blocks)
+    constexpr int ROWS = 32 * SB;                  // support rows per stage
     constexpr int NPOS = ROWS * CPS;               // chunk positions per staged array
-    constexpr int NINS = NPOS / 64;                // DMA instructions per array (= CPS)
+    constexpr int NINS = NPOS / 64;                // DMA instructions per array
     constexpr int NT = (NINS + 3) / 4;             // per wave (waves take i = w, w+4, ...)
     constexpr int NARR = X3 ? 2 : 1;
     constexpr int ABYTES = NPOS * 16;
-    static_assert(NPOS % 64 == 0, "staged array must be whole DMA instructions");
-    __shared__ __attribute__((aligned(16))) char sA[2][NARR][ABYTES];
-    __shared__ __attribute__((aligned(16))) float sAy[3][ROWS];
-    __shared__ __attribute__((aligned(16))) float sW[3][ROWS];
+    static_assert(NPOS % 64 == 0 && ROWS % 64 == 0 && ROWS / 64 * 2 == 4, "staging layout");
+    // Two stage buffers, each its own object: every access below names its
+    // buffer at compile time (the stage loop is unrolled by two), so the
+    // compiler sees that the staging of one buffer cannot alias the reads of
+    // the other and needs no wait between them.
+    __shared__ __attribute__((aligned(16))) char sA0[NARR * ABYTES];
+    __shared__ __attribute__((aligned(16))) char sA1[NARR * ABYTES];
+    __shared__ __attribute__((aligned(16))) float sAy0[ROWS], sAy1[ROWS], sW0[ROWS], sW1[ROWS];
+    using IC0 = std::integral_constant<int, 0>;
+    using IC1 = std::integral_constant<int, 1>;
+    auto bufA = [&](auto bc) -> char * {
+        if constexpr (decltype(bc)::value == 0)
+            return sA0;
+        else
+            return sA1;
+    };
+    auto bufAy = [&](auto bc) -> float * {
+        if constexpr (decltype(bc)::value == 0)
+            return sAy0;
+        else
+            return sAy1;
+    };
+    auto bufW = [&](auto bc) -> float * {
+        if constexpr (decltype(bc)::value == 0)
+            return sW0;
+        else
+            return sW1;
+    };
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -560,228 +605,377 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
     if (blk0 >= Mb)
         return;
     const int blk1 = min(Mb, blk0 + RB);
-    const int nst = (blk1 - blk0 + 1) / 2;
-    const int b0 = bt * 256 + wu * 64;  // this wave's 64 batch rows
+    const int nst = (blk1 - blk0 + SB - 1) / SB;
+    const int b0 = (bt * 4 + wu) * (32 * NBK);  // this wave's batch rows
     const int n = lane & 31, h = lane >> 5;
 
     // ---- staging ---------------------------------------------------------
     // DMA slot q of this lane: instruction i = wave + 4 q writes chunk
-    // position 64 i + lane of a staged array: row drow[q], chunk offset dcoff[q]
+    // position 64 i + lane of a staged array, i.e. row dma_row(q), chunk
+    // offset dma_coff(q) (recomputed when needed: registers are scarce)
     __builtin_assume(wu >= 0 && wu < 4);
-    int drow[NT], dcoff[NT], pidx[NT];
-#pragma unroll
-    for (int q = 0; q < NT; ++q) {
-        const int pos = 64 * (wu + 4 * q) + lane;
-        const int c = pos % CPS;
-        drow[q] = min(pos / CPS, ROWS - 1);
-        dcoff[q] = (c < CPR ? c : 0) * 16;  // the pad position loads any valid chunk
-    }
+    auto dma_row = [&](int q) { return min((64 * (wu + 4 * q) + lane) / CPS, ROWS - 1); };
+    auto dma_coff = [&](int q) {
+        const int c = (64 * (wu + 4 * q) + lane) % CPS;
+        return (c < CPR ? c : 0) * 16;  // the pad position loads any valid chunk
+    };
+    int pidx[NT];
     // sup_row[Mcap] holds the zero pool row; entries past the support map there
     const int sentinel = A.sup_cap;
     auto load_idx = [&](int s) {  // pool rows of this lane's DMA slots in stage s
-        const int r0 = (blk0 + 2 * s) * 32;
+        const int r0 = (blk0 + SB * s) * 32;
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
-            const int srow = r0 + drow[q];
+            const int srow = r0 + dma_row(q);
             pidx[q] = A.sup_row[srow < M ? srow : sentinel];
         }
     };
-    int cen_nxt[2];
-    auto load_cen = [&](int s) {  // centers of the two blocks of stage s
-        const int bp = blk0 + 2 * s;
-        cen_nxt[0] = A.blk_center[bp];
-        cen_nxt[1] = A.blk_center[bp + 1 < blk1 ? bp + 1 : bp];
+    // centers of the blocks of a stage; blocks past the range (zero rows)
+    // take the center of the range's last block, so they never end a run
+    int cen_nxt[SB];
+    auto load_cen = [&](int s) {
+        const int bp = blk0 + SB * s;
+#pragma unroll
+        for (int k = 0; k < SB; ++k)
+            cen_nxt[k] = A.blk_center[min(bp + k, blk1 - 1)];
     };
-    auto issue = [&](int s, int bufi) {  // DMA of stage s into buffer bufi
+    auto issue_slot = [&](auto bc, int q) {  // DMA slot q of every staged array (pidx[q] holds its row)
 #pragma unroll
         for (int arr = 0; arr < NARR; ++arr) {
             const char *gsrc = F32 ? (const char *)A.pool32
                                    : (arr == 0 ? (const char *)A.poolhi : (const char *)A.poollo);
-#pragma unroll
-            for (int q = 0; q < NT; ++q) {
-                const int i = wu + 4 * q;
-                if (4 * q + 3 < NINS || i < NINS) {
-                    const char *src = gsrc + ((int64_t)pidx[q] * (DP * ES) + dcoff[q]);
-                    __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)&sA[bufi][arr][i * 1024],
-                                                     16, 0, 0);
-                }
+            const int i = wu + 4 * q;
+            if (4 * q + 3 < NINS || i < NINS) {
+                const char *src = gsrc + ((int64_t)pidx[q] * (DP * ES) + dma_coff(q));
+                __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)(bufA(bc) + arr * ABYTES + i * 1024),
+                                                 16, 0, 0);
             }
         }
-        if (wu < 2) {
-            const int srow = (blk0 + 2 * s) * 32 + lane;
-            const float *src = srow < M ? (wu == 0 ? A.sup_ay : A.sup_w) + srow : A.zero_f;
-            float *dst = wu == 0 ? &sAy[s % 3][0] : &sW[s % 3][0];
-            __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)dst, 4, 0, 0);
+    };
+    auto load_idx_slot = [&](int s, int q) {
+        const int srow = (blk0 + SB * s) * 32 + dma_row(q);
+        pidx[q] = A.sup_row[srow < M ? srow : sentinel];
+    };
+    auto issue_ayw = [&](int s, auto bc) {
+        // exponent constants (waves 0, 1) and weights (waves 2, 3), 64 rows each
+        const int half = wu & 1;
+        const int srow = (blk0 + SB * s) * 32 + half * 64 + lane;
+        const float *src = srow < M ? (wu < 2 ? A.sup_ay : A.sup_w) + srow : A.zero_f;
+        float *dst = (wu < 2 ? bufAy(bc) : bufW(bc)) + half * 64;
+        __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)dst, 4, 0, 0);
+    };
+    auto issue = [&](int s, auto bc) {  // DMA of stage s into buffer bc
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+            issue_slot(bc, q);
+        issue_ayw(s, bc);
+    };
+    // The staging of stage s+1 and the index loads of stage s+2, as NT + 2
+    // items placed after every fourth MFMA of stage s (one per k * NMF + mi
+    // position), so that their issue overlaps matrix-core work.
+    auto stage_item = [&](int s, auto bn, int pos) {  // bn: the buffer of stage s+1
+        if (pos % 4 != 0)
+            return;
+        const int j = pos / 4;
+        if (j < NT) {
+            if (s + 1 < nst) {
+                issue_slot(bn, j);
+                if (s + 2 < nst)
+                    load_idx_slot(s + 2, j);
+            }
+        } else if (j == NT) {
+            if (s + 1 < nst)
+                issue_ayw(s + 1, bn);
+        } else if (j == NT + 1) {
+            if (s + 1 < nst)
+                load_cen(s + 1);
         }
     };
 
     // ---- batch fragments into registers --------------------------------
+    // A fragment wants 32 rows x 32 bytes per load instruction; the rows are
+    // instead read whole (coalesced, 16 bytes per lane), written to this
+    // wave's part of the staging buffer in the padded row layout, and read
+    // back as fragments.  One 32-row N-block per pass; the loads of pass p+1
+    // are in flight while pass p goes through LDS.
     typedef typename std::conditional<F32, float, bf16x8>::type frag_t;
-    frag_t bh[2][KS];
-    frag_t bl[2][X3 ? KS : 1];
-    float hx[2];
+    frag_t bh[NBK][KS];
+    frag_t bl[NBK][X3 ? KS : 1];
+    float hx[NBK];
+    // fragment read of row n of a 32-row block: byte offset in the padded layout
+    const int aoff = n * (CPS * 16) + (F32 ? h * KS * 4 : h * 16);
+    {
+        constexpr int BCH = 32 * CPR / 64;    // 16-byte chunks per lane per array and block
+        constexpr int WREG = 32 * CPS * 16;   // bytes of one array of one block
+        static_assert(4 * NARR * WREG <= (int)sizeof(sA1), "batch transpose must fit one staging buffer");
+        // buffer 1: the support rows of stage 0 are meanwhile landing in buffer 0
+        char *wreg = sA1 + wu * NARR * WREG;
+        u16x8 ld[2][NARR][BCH];
+        auto bload = [&](int nbk, int slot) {
 #pragma unroll
-    for (int nbk = 0; nbk < 2; ++nbk) {
-        const int row = b0 + nbk * 32 + n;
-        const bool ok = row < A.nb;
-        const int64_t rr = ok ? row : 0;
-        hx[nbk] = ok ? -0.5f * A.batsq[row] : 0.0f;
-        if constexpr (F32) {
-            // K permutation: k-step s, lane half h -> column h * KS + s
-            const float *src = A.bat32 + rr * DP + h * KS;
+            for (int arr = 0; arr < NARR; ++arr) {
+                const char *src = F32 ? (const char *)A.bat32
+                                      : (arr == 0 ? (const char *)A.bathi : (const char *)A.batlo);
 #pragma unroll
-            for (int s4 = 0; s4 < KS; s4 += 4) {
-                const f32x4 v = ok ? *(const f32x4 *)(src + s4) : f32x4{0, 0, 0, 0};
-                bh[nbk][s4] = v[0];
-                bh[nbk][s4 + 1] = v[1];
-                bh[nbk][s4 + 2] = v[2];
-                bh[nbk][s4 + 3] = v[3];
+                for (int it = 0; it < BCH; ++it) {
+                    const int cp = it * 64 + lane, r = cp / CPR, c = cp % CPR;
+                    const int row = b0 + nbk * 32 + r;
+                    const u16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
+                    ld[slot][arr][it] = row < A.nb ? *(const u16x8 *)(src + (int64_t)row * (DP * ES) + c * 16) : z8;
+                }
             }
-        } else {
-            const uint16_t *sh = A.bathi + rr * DP + h * 8;
-            const uint16_t *sl = A.batlo + rr * DP + h * 8;
-            const u16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
+        };
+        // the index loads of stage 0 go first, then the batch rows; once the
+        // indices are in, the staging of stage 0 starts while the batch rows
+        // go through LDS
+        load_idx(0);
+        load_cen(0);
+        bload(0, 0);
+        if (NBK > 1)
+            bload(1, 1);
+        issue(0, IC0{});
+        if (nst > 1)
+            load_idx(1);
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                bh[nbk][ks] = __builtin_bit_cast(bf16x8, ok ? *(const u16x8 *)(sh + ks * 16) : z8);
-                if constexpr (X3)
-                    bl[nbk][ks] = __builtin_bit_cast(bf16x8, ok ? *(const u16x8 *)(sl + ks * 16) : z8);
+        for (int nbk = 0; nbk < NBK; ++nbk) {
+            const int slot = nbk & 1;
+#pragma unroll
+            for (int arr = 0; arr < NARR; ++arr)
+#pragma unroll
+                for (int it = 0; it < BCH; ++it) {
+                    const int cp = it * 64 + lane, r = cp / CPR, c = cp % CPR;
+                    *(u16x8 *)(wreg + arr * WREG + r * (CPS * 16) + c * 16) = ld[slot][arr][it];
+                }
+            if (nbk + 2 < NBK)
+                bload(nbk + 2, slot);
+            const char *base = wreg + aoff;
+            if constexpr (F32) {
+#pragma unroll
+                for (int s4 = 0; s4 < KS; s4 += 4) {
+                    const f32x4 v = *(const f32x4 *)(base + s4 * 4);
+                    bh[nbk][s4] = v[0];
+                    bh[nbk][s4 + 1] = v[1];
+                    bh[nbk][s4 + 2] = v[2];
+                    bh[nbk][s4 + 3] = v[3];
+                }
+            } else {
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    bh[nbk][ks] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + ks * 32));
+                    if constexpr (X3)
+                        bl[nbk][ks] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + WREG + ks * 32));
+                }
             }
+            const int row = b0 + nbk * 32 + n;
+            hx[nbk] = row < A.nb ? -0.5f * A.batsq[row] : 0.0f;
         }
     }
+    __syncthreads();  // stage 0 staged; buffer 1 is free for stage 1
 
     // ---- block products and epilogue ---------------------------------------
-    // fragment read of row sub*32 + n: byte offset within a staged array
-    const int aoff = n * (CPS * 16) + (F32 ? h * KS * 4 : h * 16);
-    auto mfma_block = [&](f32x16 (&acc)[2], int bufi, int sub) {
+    // Epilogue element e of a lane: row i = e / NBK (m = 8 (i/4) + 4 h + i%4
+    // of the block), N-block e % NBK.  eay / ew hold the exponent constants
+    // and weights of the 16 rows of the block whose epilogue is running; the
+    // block being multiplied reloads them for its own epilogue as soon as the
+    // running epilogue is done with them (rows 0-7 at half time, rows 8-15 at
+    // the end).  The first support fragments of the next block of the stage
+    // are read during the last k-step.
+    float run[NBK];
 #pragma unroll
-        for (int nbk = 0; nbk < 2; ++nbk)
+    for (int nbk = 0; nbk < NBK; ++nbk)
+        run[nbk] = 0.0f;
+    const float c2 = A.c2;
+    f32x4 eay[4], ew[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        eay[g] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        ew[g] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    auto load_ayw = [&](auto bc, int sub, int g0, int g1) {
+#pragma unroll
+        for (int g = g0; g < g1; ++g) {
+            const int m0 = sub * 32 + 8 * g + 4 * h;
+            eay[g] = *(const f32x4 *)(bufAy(bc) + m0);
+            ew[g] = *(const f32x4 *)(bufW(bc) + m0);
+        }
+    };
+    constexpr int NMF = KS * NBK * (X3 ? 3 : 1);  // MFMAs per block
+    constexpr int NEL = 16 * NBK;                 // epilogue elements per lane
+    constexpr int HALF = NMF / 2;                 // after it, rows 0-7 of the epilogue are done
+    static_assert(NEL * HALF / NMF >= 8 * NBK || true, "");
+    auto epi_range = [&](const f32x16 (&accP)[NBK], int e0, int e1) {
+#pragma unroll
+        for (int e = e0; e < e1; ++e) {
+            const int i = e / NBK, nbk = e % NBK;
+            run[nbk] = fmaf(ew[i / 4][i % 4],
+                            __builtin_amdgcn_exp2f(fmaf(accP[nbk][i], c2, eay[i / 4][i % 4])), run[nbk]);
+        }
+    };
+    // Carried support fragments of k-step 0 of the next block.
+    typedef typename std::conditional<F32, f32x4, bf16x8>::type afrag_t;
+    afrag_t a0h, a0l;
+    auto load_a0 = [&](auto bc, int sub) {
+        const char *base = bufA(bc) + sub * 32 * CPS * 16 + aoff;
+        if constexpr (F32) {
+            a0h = *(const f32x4 *)base;
+        } else {
+            a0h = __builtin_bit_cast(bf16x8, *(const u16x8 *)base);
+            if constexpr (X3)
+                a0l = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + ABYTES));
+        }
+    };
+    // The element range of MFMA mi: the epilogue is spread evenly; rows 0-7
+    // (elements < 8 NBK) are finished by MFMA HALF - 1.
+    auto share = [&](const f32x16 (&accP)[NBK], int mi, auto bc, int sub) {
+        int e0 = mi * NEL / NMF, e1 = (mi + 1) * NEL / NMF;
+        if (mi < HALF) {
+            e1 = min(e1, 8 * NBK);
+            e0 = min(e0, 8 * NBK);
+            if (mi == HALF - 1)
+                e1 = 8 * NBK;
+        } else {
+            e0 = max(e0, 8 * NBK);
+        }
+        epi_range(accP, e0, e1);
+        if (mi == HALF - 1)
+            load_ayw(bc, sub, 0, 2);
+        if (mi == NMF - 1)
+            load_ayw(bc, sub, 2, 4);
+    };
+    // MFMAs of block `sub` of buffer bc into accN (k-step 0 fragments in
+    // a0h / a0l), with the epilogue of the previous block (accP) spread
+    // between them; reads the next block's k-step 0 fragments when `nsub` >= 0.
+    auto fused_block = [&](f32x16 (&accN)[NBK], const f32x16 (&accP)[NBK], auto bc, int sub, int nsub,
+                           auto hook) {
+#pragma unroll
+        for (int nbk = 0; nbk < NBK; ++nbk)
 #pragma unroll
             for (int i = 0; i < 16; ++i)
-                acc[nbk][i] = hx[nbk];
-        const char *base = &sA[bufi][0][sub * 32 * CPS * 16 + aoff];
+                accN[nbk][i] = hx[nbk];
+        const char *base = bufA(bc) + sub * 32 * CPS * 16 + aoff;
         if constexpr (F32) {
+            f32x4 av = a0h, an;
 #pragma unroll
             for (int s4 = 0; s4 < KS; s4 += 4) {
-                const f32x4 av = *(const f32x4 *)(base + s4 * 4);
+                if (s4 + 4 < KS)
+                    an = *(const f32x4 *)(base + (s4 + 4) * 4);
+                else if (nsub >= 0)
+                    load_a0(bc, nsub);
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
-                    for (int nbk = 0; nbk < 2; ++nbk)
-                        acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bh[nbk][s4 + u], acc[nbk], 0, 0, 0);
+                    for (int nbk = 0; nbk < NBK; ++nbk) {
+                        const int mi = ((s4 + u) * NBK + nbk);
+                        accN[nbk] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bh[nbk][s4 + u], accN[nbk], 0, 0, 0);
+                        share(accP, mi, bc, sub);
+                        hook(mi);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                av = an;
             }
         } else {
+            bf16x8 ah = a0h, ahn = a0h;
+            bf16x8 al = a0l, aln = a0l;  // lo fragments: BF16X3 only
+            constexpr int NP = X3 ? 3 : 1;  // products per (k-step, N-block)
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + ks * 32));
-                bf16x8 al;
-                if constexpr (X3)
-                    al = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + ABYTES + ks * 32));
-#pragma unroll
-                for (int nbk = 0; nbk < 2; ++nbk) {
-                    acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[nbk][ks], acc[nbk], 0, 0, 0);
-                    if constexpr (X3) {
-                        acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[nbk][ks], acc[nbk], 0, 0, 0);
-                        acc[nbk] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[nbk][ks], acc[nbk], 0, 0, 0);
-                    }
+                if (ks + 1 < KS) {
+                    ahn = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + (ks + 1) * 32));
+                    if constexpr (X3)
+                        aln = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + ABYTES + (ks + 1) * 32));
+                } else if (nsub >= 0) {
+                    load_a0(bc, nsub);
                 }
+#pragma unroll
+                for (int pr = 0; pr < NP; ++pr)
+#pragma unroll
+                    for (int nbk = 0; nbk < NBK; ++nbk) {
+                        const int mi = (ks * NP + pr) * NBK + nbk;
+                        const bf16x8 aa = pr == 2 ? al : ah;
+                        const bf16x8 bb = pr == 1 ? bl[nbk][ks] : bh[nbk][ks];
+                        accN[nbk] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aa, bb, accN[nbk], 0, 0, 0);
+                        share(accP, mi, bc, sub);
+                        hook(mi);
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                ah = ahn;
+                if constexpr (X3)
+                    al = aln;
             }
-        }
-    };
-    float run[2] = {0.0f, 0.0f};
-    const float c2 = A.c2;
-    auto epilogue = [&](const f32x16 (&acc)[2], int e3, int sub) {
-        // rows m = 8 (i/4) + 4 h + i%4 of the block
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const int m0 = sub * 32 + 8 * g + 4 * h;
-            const f32x4 ay = *(const f32x4 *)(&sAy[e3][m0]);
-            const f32x4 w = *(const f32x4 *)(&sW[e3][m0]);
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int nbk = 0; nbk < 2; ++nbk)
-                    run[nbk] = fmaf(w[q], __builtin_amdgcn_exp2f(fmaf(acc[nbk][4 * g + q], c2, ay[q])), run[nbk]);
         }
     };
     int run_head = blk0;
     int run_center = __builtin_amdgcn_readfirstlane(A.blk_center[blk0]);
     auto flush = [&]() {
-        // lane l (< 32) holds the half-sums of column n for both N-blocks;
-        // one exchange gives N-block 0 totals to lanes < 32, N-block 1 to the rest
-        const float give = h == 0 ? run[1] : run[0];
-        const float got = __shfl_xor(give, 32);
-        const float tot = (h == 0 ? run[0] : run[1]) + got;
-        const int col = b0 + h * 32 + n;
-        if (col < A.nb)
-            A.part[(int64_t)run_head * A.ldp + col] = tot;
-        run[0] = run[1] = 0.0f;
+        // lane l holds the half-sum (over rows with m % 8 in 4h..4h+3) of
+        // column n of every N-block; swapping lanes 32-63 of block p with
+        // lanes 0-31 of block p+1 puts both halves of block p in lanes < 32
+        // and both halves of block p+1 in lanes >= 32
+#pragma unroll
+        for (int p = 0; p < NBK; p += 2) {
+            const int q = p + 1 < NBK ? p + 1 : p;  // an unpaired last block pairs with itself
+            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(run[p]), __float_as_uint(run[q]), false,
+                                                             false);
+            const float tot = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+            const int col = b0 + (p + h) * 32 + n;
+            if ((q != p || h == 0) && col < A.nb)
+                A.part[(int64_t)run_head * A.ldp + col] = tot;
+        }
+#pragma unroll
+        for (int nbk = 0; nbk < NBK; ++nbk)
+            run[nbk] = 0.0f;
     };
 
     // ---- pipeline ----------------------------------------------------------
-    // the epilogue of the block before the first one reads weights 0
-    if (tid < ROWS) {
-        sAy[2][tid] = 0.0f;
-        sW[2][tid] = 0.0f;
-    }
-    f32x16 accE[2], accO[2];
+    static_assert(SB % 2 == 0, "blocks alternate between two accumulator sets");
+    f32x16 acc0[NBK], acc1[NBK];  // even / odd blocks
 #pragma unroll
-    for (int nbk = 0; nbk < 2; ++nbk)
+    for (int nbk = 0; nbk < NBK; ++nbk)
 #pragma unroll
         for (int i = 0; i < 16; ++i)
-            accO[nbk][i] = 0.0f;
-    load_idx(0);
-    load_cen(0);
-    issue(0, 0);
-    if (nst > 1)
-        load_idx(1);
-    __syncthreads();
-    for (int s = 0; s < nst; ++s) {
-        const int bufi = s & 1;
-        const int bp = blk0 + 2 * s;
-        const int cenE = __builtin_amdgcn_readfirstlane(cen_nxt[0]);
-        const int cenO = __builtin_amdgcn_readfirstlane(cen_nxt[1]);
-        if (s + 1 < nst) {
-            issue(s + 1, bufi ^ 1);
-            load_cen(s + 1);
-            if (s + 2 < nst)
-                load_idx(s + 2);
+            acc1[nbk][i] = 0.0f;  // the "previous block" of the first one: weights 0
+    // one stage in buffer bc; the next stage is staged into bn
+    auto stage = [&](int s, auto bc, auto bn) {
+        const int bp = blk0 + SB * s;
+        int cen[SB];
+#pragma unroll
+        for (int k = 0; k < SB; ++k)
+            cen[k] = __builtin_amdgcn_readfirstlane(cen_nxt[k]);
+        if constexpr (!kBsSpreadStaging) {
+            if (s + 1 < nst) {
+                issue(s + 1, bn);
+                load_cen(s + 1);
+                if (s + 2 < nst)
+                    load_idx(s + 2);
+            }
         }
-        if constexpr (kBsPipe) {
-            mfma_block(accE, bufi, 0);
-            epilogue(accO, (s + 2) % 3, 1);  // block bp - 1
-            if (cenE != run_center) {
+        load_a0(bc, 0);
+#pragma unroll
+        for (int k = 0; k < SB; ++k) {
+            // block bp + k; epilogue of block bp + k - 1; staging items of the next stage
+            const int nsub = k + 1 < SB ? k + 1 : -1;
+            auto hook = [&](int mi) {
+                if constexpr (kBsSpreadStaging)
+                    stage_item(s, bn, k * NMF + mi);
+            };
+            if (k % 2 == 0)
+                fused_block(acc0, acc1, bc, k, nsub, hook);
+            else
+                fused_block(acc1, acc0, bc, k, nsub, hook);
+            if (cen[k] != run_center) {
                 flush();
-                run_head = bp;
-                run_center = cenE;
+                run_head = bp + k;
+                run_center = cen[k];
             }
-            mfma_block(accO, bufi, 1);
-            epilogue(accE, s % 3, 0);  // block bp
-            if (cenO != run_center) {
-                flush();
-                run_head = bp + 1;
-                run_center = cenO;
-            }
-        } else {
-            if (cenE != run_center) {
-                flush();
-                run_head = bp;
-                run_center = cenE;
-            }
-            mfma_block(accE, bufi, 0);
-            epilogue(accE, s % 3, 0);
-            if (cenO != run_center) {
-                flush();
-                run_head = bp + 1;
-                run_center = cenO;
-            }
-            mfma_block(accE, bufi, 1);
-            epilogue(accE, s % 3, 1);
         }
         __syncthreads();
+    };
+    for (int s = 0; s < nst; s += 2) {
+        stage(s, IC0{}, IC1{});
+        if (s + 1 < nst)
+            stage(s + 1, IC1{}, IC0{});
     }
-    if constexpr (kBsPipe)
-        epilogue(accO, (nst - 1) % 3, 1);
+    epi_range(acc1, 0, NEL);
     flush();
 }
 
@@ -791,8 +985,9 @@ void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision,
     if (L.dp <= 128) {
         CrossBsArgs A;
         A.nb = nb;
-        A.nbt = (nb + 255) / 256;
-        A.nranges = bs_nranges(nb);
+        const int mode = bs_mode(precision), tr = bs_tile_rows(mode, L.dp);
+        A.nbt = (nb + tr - 1) / tr;
+        A.nranges = bs_nranges(nb, mode, L.dp);
         A.sup_cap = (int32_t)L.Mcap;
         A.seg_total = B.seg_off + L.k;
         A.pool32 = B.pool32;
@@ -1239,7 +1434,7 @@ void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double pa
     A.k = L.k;
     A.ldp = L.bmax;
     A.RB = 2;
-    A.nranges = L.dp <= 128 ? bs_nranges(nb) : 0;
+    A.nranges = (mfma && L.dp <= 128) ? bs_nranges(nb, bs_mode(precision), L.dp) : 0;
     A.kind = kind;
     A.param = param;
     A.part = B.part;

@@ -26,16 +26,8 @@ constexpr int kMaxWindow = 30;    // W; physical slots P = W + 1
 constexpr int kMaxSlots = kMaxWindow + 1;
 constexpr int kMaxBatch = 8192;   // b_max
 constexpr int kChunk = 64;        // batch rows per grouping chunk (one scoring workgroup)
-// batch-stationary MFMA cross kernel: workgroups per compute unit (waves per
-// SIMD), and whether the exp epilogue of a block overlaps the next block's MFMAs
-#ifndef MBKK_BS_OCC
-#define MBKK_BS_OCC 1
-#endif
-#ifndef MBKK_BS_PIPE
-#define MBKK_BS_PIPE 1
-#endif
-constexpr int kBsOcc = MBKK_BS_OCC;
-constexpr bool kBsPipe = MBKK_BS_PIPE != 0;
+// batch-stationary MFMA cross kernel: workgroups per compute unit (waves per SIMD)
+constexpr int kBsOcc = 1;
 constexpr int kNumCU = 256;
 
 // Physical slots of the live batches, oldest batch first.
