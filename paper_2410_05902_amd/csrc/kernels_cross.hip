@@ -496,6 +496,9 @@ constexpr int kBsStageBlocks = 4;  // support blocks (32 rows) per stage
 #ifndef MBKK_BS_SPREAD
 #define MBKK_BS_SPREAD 1
 #endif
+#ifndef MBKK_BS_XCD_BY_TILE
+#define MBKK_BS_XCD_BY_TILE 1
+#endif
 constexpr bool kBsSpreadStaging = MBKK_BS_SPREAD != 0;
 
 // Blocks per range for Mb support blocks split over nranges ranges: a
@@ -568,6 +571,7 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
     __shared__ __attribute__((aligned(16))) char sA0[NARR * ABYTES];
     __shared__ __attribute__((aligned(16))) char sA1[NARR * ABYTES];
     __shared__ __attribute__((aligned(16))) float sAy0[ROWS], sAy1[ROWS], sW0[ROWS], sW1[ROWS];
+    __shared__ __attribute__((aligned(16))) int32_t sIdx0[ROWS], sIdx1[ROWS];  // pool rows of a stage
     using IC0 = std::integral_constant<int, 0>;
     using IC1 = std::integral_constant<int, 1>;
     auto bufA = [&](auto bc) -> char * {
@@ -588,6 +592,12 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
         else
             return sW1;
     };
+    auto bufIdx = [&](auto bc) -> int32_t * {
+        if constexpr (decltype(bc)::value == 0)
+            return sIdx0;
+        else
+            return sIdx1;
+    };
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wu = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -597,7 +607,11 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
     const int64_t t = (int64_t)(blockIdx.x % 8) * G8 + blockIdx.x / 8;
     if (t >= (int64_t)A.nranges * A.nbt)
         return;
+#if MBKK_BS_XCD_BY_TILE
+    const int range = (int)(t % A.nranges), bt = (int)(t / A.nranges);
+#else
     const int range = (int)(t / A.nbt), bt = (int)(t % A.nbt);
+#endif
     const int M = *A.seg_total;
     const int Mb = M / 32;
     const int RB = bs_range_blocks(Mb, A.nranges);
@@ -622,7 +636,7 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
     int pidx[NT];
     // sup_row[Mcap] holds the zero pool row; entries past the support map there
     const int sentinel = A.sup_cap;
-    auto load_idx = [&](int s) {  // pool rows of this lane's DMA slots in stage s
+    auto load_idx = [&](int s) {  // pool rows of this lane's DMA slots in stage s (from global)
         const int r0 = (blk0 + SB * s) * 32;
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
@@ -630,14 +644,25 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
             pidx[q] = A.sup_row[srow < M ? srow : sentinel];
         }
     };
-    // centers of the blocks of a stage; blocks past the range (zero rows)
-    // take the center of the range's last block, so they never end a run
-    int cen_nxt[SB];
-    auto load_cen = [&](int s) {
-        const int bp = blk0 + SB * s;
+    // the pool rows of stage s, staged into index buffer bi by waves 0 and 1
+    auto issue_idx = [&](int s, auto bi) {
+        if (wu < 2) {
+            const int srow = (blk0 + SB * s) * 32 + wu * 64 + lane;
+            const int32_t *src = A.sup_row + (srow < M ? srow : sentinel);
+            __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)(bufIdx(bi) + wu * 64), 4, 0, 0);
+        }
+    };
+    auto read_idx = [&](auto bi) {  // this lane's DMA slot rows from index buffer bi
 #pragma unroll
-        for (int k = 0; k < SB; ++k)
-            cen_nxt[k] = A.blk_center[min(bp + k, blk1 - 1)];
+        for (int q = 0; q < NT; ++q)
+            pidx[q] = bufIdx(bi)[dma_row(q)];
+    };
+    // centers of the range's blocks: lane l of cen_win holds block blk0 + cw0 + l
+    // (blocks past the range take the range's last block: they never end a run)
+    int cw0 = 0, cen_win = 0;
+    auto load_cen_win = [&](int base) {
+        cw0 = base;
+        cen_win = A.blk_center[min(blk0 + base + lane, blk1 - 1)];
     };
     auto issue_slot = [&](auto bc, int q) {  // DMA slot q of every staged array (pidx[q] holds its row)
 #pragma unroll
@@ -651,10 +676,6 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
                                                  16, 0, 0);
             }
         }
-    };
-    auto load_idx_slot = [&](int s, int q) {
-        const int srow = (blk0 + SB * s) * 32 + dma_row(q);
-        pidx[q] = A.sup_row[srow < M ? srow : sentinel];
     };
     auto issue_ayw = [&](int s, auto bc) {
         // exponent constants (waves 0, 1) and weights (waves 2, 3), 64 rows each
@@ -673,22 +694,22 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
     // The staging of stage s+1 and the index loads of stage s+2, as NT + 2
     // items placed after every fourth MFMA of stage s (one per k * NMF + mi
     // position), so that their issue overlaps matrix-core work.
-    auto stage_item = [&](int s, auto bn, int pos) {  // bn: the buffer of stage s+1
+    // The staging of stage s+1 (pool rows already in pidx) and the index
+    // staging of stage s+2, as NT + 2 items placed after every fourth MFMA of
+    // stage s, so that their issue overlaps matrix-core work.
+    auto stage_item = [&](int s, auto bc, auto bn, int pos) {  // bc / bn: the buffers of stages s / s+1
         if (pos % 4 != 0)
             return;
         const int j = pos / 4;
         if (j < NT) {
-            if (s + 1 < nst) {
+            if (s + 1 < nst)
                 issue_slot(bn, j);
-                if (s + 2 < nst)
-                    load_idx_slot(s + 2, j);
-            }
         } else if (j == NT) {
             if (s + 1 < nst)
                 issue_ayw(s + 1, bn);
         } else if (j == NT + 1) {
-            if (s + 1 < nst)
-                load_cen(s + 1);
+            if (s + 2 < nst)
+                issue_idx(s + 2, bc);  // stage s+2 has the parity of stage s
         }
     };
 
@@ -729,13 +750,13 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
         // indices are in, the staging of stage 0 starts while the batch rows
         // go through LDS
         load_idx(0);
-        load_cen(0);
+        load_cen_win(0);
         bload(0, 0);
         if (NBK > 1)
             bload(1, 1);
         issue(0, IC0{});
         if (nst > 1)
-            load_idx(1);
+            issue_idx(1, IC1{});
 #pragma unroll
         for (int nbk = 0; nbk < NBK; ++nbk) {
             const int slot = nbk & 1;
@@ -905,7 +926,7 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
         }
     };
     int run_head = blk0;
-    int run_center = __builtin_amdgcn_readfirstlane(A.blk_center[blk0]);
+    int run_center = __builtin_amdgcn_readlane(cen_win, 0);
     auto flush = [&]() {
         // lane l holds the half-sum (over rows with m % 8 in 4h..4h+3) of
         // column n of every N-block; swapping lanes 32-63 of block p with
@@ -937,16 +958,19 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
     // one stage in buffer bc; the next stage is staged into bn
     auto stage = [&](int s, auto bc, auto bn) {
         const int bp = blk0 + SB * s;
+        if (SB * s + SB - 1 - cw0 >= 64)
+            load_cen_win(SB * s);  // ranges of more than 64 blocks: next window
         int cen[SB];
 #pragma unroll
         for (int k = 0; k < SB; ++k)
-            cen[k] = __builtin_amdgcn_readfirstlane(cen_nxt[k]);
+            cen[k] = __builtin_amdgcn_readlane(cen_win, SB * s + k - cw0);
+        if (s + 1 < nst)
+            read_idx(bn);  // pool rows of stage s+1, staged during stage s-1
         if constexpr (!kBsSpreadStaging) {
             if (s + 1 < nst) {
                 issue(s + 1, bn);
-                load_cen(s + 1);
                 if (s + 2 < nst)
-                    load_idx(s + 2);
+                    issue_idx(s + 2, bc);
             }
         }
         load_a0(bc, 0);
@@ -956,7 +980,7 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
             const int nsub = k + 1 < SB ? k + 1 : -1;
             auto hook = [&](int mi) {
                 if constexpr (kBsSpreadStaging)
-                    stage_item(s, bn, k * NMF + mi);
+                    stage_item(s, bc, bn, k * NMF + mi);
             };
             if (k % 2 == 0)
                 fused_block(acc0, acc1, bc, k, nsub, hook);
@@ -1063,25 +1087,29 @@ void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision,
 // term of the form (FP32 MFMA, or BF16 hi/lo split):
 //   G_j[1+rr][c] = G_j[c][1+rr] = sum_{a in slot rr, center j} sum_{e in column c, center j}
 //                                 exp(-(||a||^2 + ||e||^2 - 2 a.e) / kappa)
-// One workgroup per (center j, column c); rows 64 x 64 at a time, wave w
-// computes the 32 x 32 block (w / 2, w % 2) with fragments loaded straight
-// from the pool into registers; kernel values are summed in FP64.
+// One workgroup per (center j, column c).  The product is cut into 32 x 32
+// blocks (a-block, e-block); each of the 16 waves takes blocks w, w + 16, ...
+// (fragments loaded straight from the pool into registers), so a large
+// cluster's blocks are computed in parallel.  Kernel values are summed in
+// FP64 per wave, then over the waves in a fixed order.
 // ===========================================================================
+constexpr int kGramWaves = 16;
+
 template <int MODE, int DP>
-__global__ __launch_bounds__(256) void k_gram_mfma(int k, int C, int bmax, int rr, uint32_t col_mask,
-                                                    const int32_t *__restrict__ ring_off,
-                                                    const int32_t *__restrict__ ring_perm, int64_t zero_row,
-                                                    const float *__restrict__ pool32,
-                                                    const uint16_t *__restrict__ poolhi,
-                                                    const uint16_t *__restrict__ poollo,
-                                                    const float *__restrict__ poolsq, float c2, float c1,
-                                                    double *__restrict__ G)
+__global__ __launch_bounds__(64 * kGramWaves) void k_gram_mfma(int k, int C, int bmax, int rr, uint32_t col_mask,
+                                                                const int32_t *__restrict__ ring_off,
+                                                                const int32_t *__restrict__ ring_perm,
+                                                                int64_t zero_row, const float *__restrict__ pool32,
+                                                                const uint16_t *__restrict__ poolhi,
+                                                                const uint16_t *__restrict__ poollo,
+                                                                const float *__restrict__ poolsq, float c2, float c1,
+                                                                double *__restrict__ G)
 {
     constexpr bool F32 = MODE == 0;
     constexpr bool X3 = MODE == 1;
     constexpr int KS = F32 ? DP / 2 : DP / 16;
-    __shared__ float sqa[64], sqe[64];
-    __shared__ double red[4];
+    __shared__ float sqa[kGramWaves][32];
+    __shared__ double red[kGramWaves];
     const int j = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6, n = lane & 31, h = lane >> 5;
     if (!((col_mask >> c) & 1u))
@@ -1102,60 +1130,53 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int k, int C, int bmax, int r
         pe = ring_perm + (int64_t)(c - 1) * bmax + oe[j];
         erow0 = (int64_t)k + (int64_t)(c - 1) * bmax;
     }
+    const int nA = (na + 31) / 32, nE = (ne + 31) / 32;
     double tot = 0.0;
-    for (int at = 0; at < na; at += 64) {
-        for (int et = 0; et < ne; et += 64) {
-            __syncthreads();
-            if (tid < 64) {
-                const int q = at + tid;
-                sqa[tid] = q < na ? poolsq[arow0 + pa[q]] : 0.0f;
-            } else if (tid < 128) {
-                const int q = et + tid - 64;
-                sqe[tid - 64] = q < ne ? poolsq[c == 0 ? erow0 : erow0 + pe[q]] : 0.0f;
+    for (int t = w; t < nA * nE; t += kGramWaves) {  // wave-uniform
+        const int ab = t / nE, eb = t % nE;
+        const int qa = ab * 32 + n, qe = eb * 32 + n;
+        const int64_t ra = qa < na ? arow0 + pa[qa] : zero_row;
+        const int64_t re = qe < ne ? (c == 0 ? erow0 : erow0 + pe[qe]) : zero_row;
+        // lane n (h = 0) publishes the norm of a-row n for the output rows m
+        if (h == 0)
+            sqa[w][n] = c1 * poolsq[ra];
+        const float se_ = c1 * poolsq[re];
+        f32x16 acc;
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            acc[i] = 0.0f;
+        if constexpr (F32) {
+            const float *sa = pool32 + ra * DP + h * KS, *se = pool32 + re * DP + h * KS;
+#pragma unroll
+            for (int s4 = 0; s4 < KS; s4 += 4) {
+                const f32x4 av = *(const f32x4 *)(sa + s4), ev = *(const f32x4 *)(se + s4);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], ev[u], acc, 0, 0, 0);
             }
-            __syncthreads();
-            const int mb = w >> 1, nb = w & 1;
-            if (at + mb * 32 < na && et + nb * 32 < ne) {  // wave uniform
-                const int qa = at + mb * 32 + n, qe = et + nb * 32 + n;
-                const int64_t ra = qa < na ? arow0 + pa[qa] : zero_row;
-                const int64_t re = qe < ne ? (c == 0 ? erow0 : erow0 + pe[qe]) : zero_row;
-                f32x16 acc;
+        } else {
 #pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    acc[i] = 0.0f;
-                if constexpr (F32) {
-                    const float *sa = pool32 + ra * DP + h * KS, *se = pool32 + re * DP + h * KS;
-#pragma unroll
-                    for (int s4 = 0; s4 < KS; s4 += 4) {
-                        const f32x4 av = *(const f32x4 *)(sa + s4), ev = *(const f32x4 *)(se + s4);
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], ev[u], acc, 0, 0, 0);
-                    }
-                } else {
-#pragma unroll
-                    for (int ks = 0; ks < KS; ++ks) {
-                        const int64_t oa16 = ra * DP + ks * 16 + h * 8, oe16 = re * DP + ks * 16 + h * 8;
-                        const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poolhi + oa16));
-                        const bf16x8 eh = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poolhi + oe16));
-                        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, eh, acc, 0, 0, 0);
-                        if constexpr (X3) {
-                            const bf16x8 al = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poollo + oa16));
-                            const bf16x8 el = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poollo + oe16));
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, el, acc, 0, 0, 0);
-                            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, eh, acc, 0, 0, 0);
-                        }
-                    }
+            for (int ks = 0; ks < KS; ++ks) {
+                const int64_t oa16 = ra * DP + ks * 16 + h * 8, oe16 = re * DP + ks * 16 + h * 8;
+                const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poolhi + oa16));
+                const bf16x8 eh = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poolhi + oe16));
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, eh, acc, 0, 0, 0);
+                if constexpr (X3) {
+                    const bf16x8 al = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poollo + oa16));
+                    const bf16x8 el = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poollo + oe16));
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, el, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, eh, acc, 0, 0, 0);
                 }
-                // lane: column n (e row), rows m = 8 (i/4) + 4 h + i%4 (a rows)
-                const bool eok = qe < ne;
-                const float se_ = c1 * sqe[nb * 32 + n];
+            }
+        }
+        // lane: column n (e row), rows m = 8 (i/4) + 4 h + i%4 (a rows); the
+        // LDS row norms were written by this wave (in-order LDS access)
+        if (qe < ne) {
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int m = 8 * (i >> 2) + 4 * h + (i & 3);
-                    if (eok && at + mb * 32 + m < na)
-                        tot += (double)__builtin_amdgcn_exp2f(fmaf(acc[i], c2, c1 * sqa[mb * 32 + m] + se_));
-                }
+            for (int i = 0; i < 16; ++i) {
+                const int m = 8 * (i >> 2) + 4 * h + (i & 3);
+                if (ab * 32 + m < na)
+                    tot += (double)__builtin_amdgcn_exp2f(fmaf(acc[i], c2, sqa[w][m] + se_));
             }
         }
     }
@@ -1165,7 +1186,9 @@ __global__ __launch_bounds__(256) void k_gram_mfma(int k, int C, int bmax, int r
         red[w] = tot;
     __syncthreads();
     if (tid == 0) {
-        const double g = red[0] + red[1] + red[2] + red[3];
+        double g = 0.0;
+        for (int q = 0; q < kGramWaves; ++q)
+            g += red[q];
         double *gj = G + (int64_t)j * C * C;
         gj[(1 + rr) * C + c] = g;
         gj[c * C + 1 + rr] = g;
@@ -1179,8 +1202,9 @@ void launch_gram_mfma(const Layout &L, const Buffers &B, int rr, uint32_t col_ma
     const float c2 = (float)(2.0 * l2e / kappa), c1 = (float)(-l2e / kappa);
     dim3 grid(L.k, L.C);
 #define MBKK_GM(MODE, DP)                                                                                       \
-    hipLaunchKernelGGL((k_gram_mfma<MODE, DP>), grid, dim3(256), 0, st, L.k, L.C, L.bmax, rr, col_mask,         \
-                       B.ring_off, B.ring_perm, L.PR, B.pool32, B.poolhi, B.poollo, B.poolsq, c2, c1, B.G)
+    hipLaunchKernelGGL((k_gram_mfma<MODE, DP>), grid, dim3(64 * kGramWaves), 0, st, L.k, L.C, L.bmax, rr,       \
+                       col_mask, B.ring_off, B.ring_perm, L.PR, B.pool32, B.poolhi, B.poollo, B.poolsq, c2, c1,   \
+                       B.G)
 #define MBKK_GM_DP(MODE)                 \
     switch (L.dp) {                      \
     case 32: MBKK_GM(MODE, 32); break;   \
@@ -1344,16 +1368,32 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
     double best = INFINITY, second = INFINITY;
     int lab = 0x7fffffff;
     if (act) {
-        for (int j = w; j < A.k; j += kScoreWaves) {
-            const double D = kxx - 2.0 * cross_of<T, LAYOUT>(part, A.ldp, row, j, A.seg_off, RB) + A.N[j];
-            if (A.Dout)
-                A.Dout[(int64_t)row * A.ldD + j] = D;
-            if (D < best) {   // j increases within a wave: strict < keeps the lowest index
-                second = best;
-                best = D;
-                lab = j;
-            } else if (D < second) {
-                second = D;
+        // the wave's centers j = w, w + 16, ... in batches of 8 whose loads
+        // are all in flight together
+        constexpr int NB = 8;
+        for (int j0 = w; j0 < A.k; j0 += kScoreWaves * NB) {
+            double P[NB], Nj[NB];
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int j = j0 + u * kScoreWaves;
+                P[u] = j < A.k ? cross_of<T, LAYOUT>(part, A.ldp, row, j, A.seg_off, RB) : 0.0;
+                Nj[u] = j < A.k ? A.N[j] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < NB; ++u) {
+                const int j = j0 + u * kScoreWaves;
+                if (j < A.k) {
+                    const double D = kxx - 2.0 * P[u] + Nj[u];
+                    if (A.Dout)
+                        A.Dout[(int64_t)row * A.ldD + j] = D;
+                    if (D < best) {  // j increases within a wave: strict < keeps the lowest index
+                        second = best;
+                        best = D;
+                        lab = j;
+                    } else if (D < second) {
+                        second = D;
+                    }
+                }
             }
         }
     }

@@ -419,6 +419,10 @@ __device__ double block_sum(double v, double *lds)
     return t;
 }
 
+// LDS variant (per-chunk counts held in LDS) when nchunk * k is at most this.
+constexpr int kGroupLdsMax = 8192;
+
+template <bool LDS>
 __global__ __launch_bounds__(1024) void k_group_offsets(
     int b, int k, int nchunk, int C, int p_new, int p_expired, int init_alive_before, int init_keep,
     SlotList live, int lr, const int32_t *__restrict__ gcnt, int32_t *__restrict__ gbase,
@@ -430,7 +434,18 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
 {
     __shared__ int sint[16];
     __shared__ double sdbl[16];
+    __shared__ int scnt[LDS ? kGroupLdsMax : 1], sbase[LDS ? kGroupLdsMax : 1];
     const int tid = threadIdx.x, nt = blockDim.x;
+    // per-(chunk, label) counts: staged in LDS with coalesced loads
+    const int32_t *cnt = gcnt;
+    int32_t *base = gbase;
+    if constexpr (LDS) {
+        for (int i = tid; i < nchunk * k; i += nt)
+            scnt[i] = gcnt[i];
+        __syncthreads();
+        cnt = scnt;
+        base = sbase;
+    }
     const int per = (k + nt - 1) / nt;
     const int j0 = tid * per, j1 = min(k, j0 + per);
     // totals of this thread's labels, block-wide exclusive scan -> offsets
@@ -438,7 +453,7 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
     for (int j = j0; j < j1; ++j) {
 #pragma unroll 8
         for (int g = 0; g < nchunk; ++g)
-            local += gcnt[(int64_t)g * k + j];
+            local += cnt[(int64_t)g * k + j];
     }
     int total;
     int run = block_exclusive_scan(local, sint, &total);
@@ -447,8 +462,8 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
         int gb = run;
 #pragma unroll 8
         for (int g = 0; g < nchunk; ++g) {
-            gbase[(int64_t)g * k + j] = gb;  // base of label j in chunk g
-            gb += gcnt[(int64_t)g * k + j];
+            base[(int64_t)g * k + j] = gb;  // base of label j in chunk g
+            gb += cnt[(int64_t)g * k + j];
         }
         const int bj = gb - run;
         run = gb;
@@ -487,7 +502,7 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
     // scatter: grouped position of every row = base of (chunk, label) + rank
     for (int p = tid; p < b; p += nt) {
         const int lab = min(max(labels[p], 0), k - 1);
-        const int pos = gbase[(int64_t)(p / kChunk) * k + lab] + rank[p];
+        const int pos = base[(int64_t)(p / kChunk) * k + lab] + rank[p];
         ring_perm[pos] = p;
         ring_idx[pos] = pts[p];
     }
@@ -497,12 +512,17 @@ void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_ex
                    int init_keep, const SlotList &live, int lr, hipStream_t st)
 {
     const int nchunk = (b + kChunk - 1) / kChunk;
-    hipLaunchKernelGGL(k_group_offsets, dim3(1), dim3(1024), 0, st, b, L.k, nchunk, L.C, p_new, p_expired,
-                       init_alive_before, init_keep, live, lr, B.gcnt, B.gbase, B.mind, B.coef, B.cum, B.counts,
-                       B.alpha,
-                       B.ring_off + (int64_t)p_new * (L.k + 1), B.obj, B.labels, B.rank,
-                       B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,
-                       B.ring_perm + (int64_t)p_new * L.bmax);
+#define MBKK_GO(LDS)                                                                                             \
+    hipLaunchKernelGGL(k_group_offsets<LDS>, dim3(1), dim3(1024), 0, st, b, L.k, nchunk, L.C, p_new, p_expired,  \
+                       init_alive_before, init_keep, live, lr, B.gcnt, B.gbase, B.mind, B.coef, B.cum, B.counts, \
+                       B.alpha, B.ring_off + (int64_t)p_new * (L.k + 1), B.obj, B.labels, B.rank,                 \
+                       B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,               \
+                       B.ring_perm + (int64_t)p_new * L.bmax)
+    if ((int64_t)nchunk * L.k <= kGroupLdsMax)
+        MBKK_GO(true);
+    else
+        MBKK_GO(false);
+#undef MBKK_GO
 }
 
 // ---------------------------------------------------------------------------
