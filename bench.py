@@ -35,6 +35,73 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+CROSS_SRC = os.path.join(ROOT, "paper_2410_05902_amd", "csrc", "kernels_cross.hip")
+CROSS_KERNEL = {"gauss": "k_cross_bs", "laplace": "k_cross_direct"}
+
+
+def source_sha() -> str:
+    import hashlib
+    with open(CROSS_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _counter_means(d: str, counter: str):
+    """Mean per dispatch of `counter` (summed over its instances), per kernel name."""
+    import glob
+    import re
+    import sqlite3
+    dbs = glob.glob(os.path.join(d, "**", "*.db"), recursive=True)
+    if not dbs:
+        raise SystemExit(f"no rocprofv3 database under {d}")
+    con = sqlite3.connect(dbs[0])
+    rows = con.execute("select kernel_name, dispatch_id, sum(value) from counters_collection "
+                       "where counter_name = ? group by kernel_name, dispatch_id", (counter,)).fetchall()
+    acc = {}
+    for name, _, v in rows:
+        acc.setdefault(re.sub(r"\(.*", "", name), []).append(v)
+    return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+
+def traffic_summary(args):
+    """HBM bytes per launch of the cross kernel from FETCH_SIZE / WRITE_SIZE (KiB
+    per dispatch), each scaled by the ratio of the true bytes of a plain copy of
+    copy_mib MiB to what the same counter reads for that copy."""
+    fdir, wdir, cfdir, cwdir = args.traffic_summary
+    wl = args.workload
+    kern = "k_cross_direct" if wl == "c5" else "k_cross_bs"
+    fetch, write = _counter_means(fdir, "FETCH_SIZE"), _counter_means(wdir, "WRITE_SIZE")
+    cf, cw = _counter_means(cfdir, "FETCH_SIZE"), _counter_means(cwdir, "WRITE_SIZE")
+    pick = lambda m, key: max(((v, n, k) for k, (v, n) in m.items() if key in k), default=None)
+    f, w = pick(fetch, kern), pick(write, kern)
+    copy_f, copy_w = pick(cf, "copy"), pick(cw, "copy")
+    if not (f and w and copy_f and copy_w):
+        raise SystemExit("counters for the cross kernel or the copy kernel not found")
+    true_kib = args.copy_mib * 1024.0
+    sf, sw = true_kib / copy_f[0], true_kib / copy_w[0]
+    out = {"workload": wl, "kernel": f[2], "dispatches": f[1],
+           "fetch_kib_per_dispatch": f[0], "write_kib_per_dispatch": w[0],
+           "copy_mib": args.copy_mib, "copy_fetch_kib": copy_f[0], "copy_write_kib": copy_w[0],
+           "fetch_scale": sf, "write_scale": sw,
+           "traffic_bytes_per_launch": (f[0] * sf + w[0] * sw) * 1024.0,
+           "kernels_cross_sha": source_sha()}
+    path = os.path.join(ROOT, "profiles", f"traffic_{wl}.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
+def measured_traffic(wl: str):
+    """Bytes per launch from profiles/traffic_<wl>.json when it was taken on the
+    current cross-kernel source, else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{wl}.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    return t["traffic_bytes_per_launch"] if t.get("kernels_cross_sha") == source_sha() else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -47,7 +114,14 @@ def main():
     ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run device-to-device copies of MIB MiB (scale for the HBM byte counters)")
+    ap.add_argument("--traffic-summary", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "CAL_FETCH_DIR", "CAL_WRITE_DIR"),
+                    help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE runs of the workload and of the copy "
+                         "calibration into profiles/traffic_<workload>.json (no GPU needed)")
+    ap.add_argument("--copy-mib", type=int, default=256)
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(args)
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the hot path is measured on one GPU's "
@@ -125,19 +199,22 @@ def main():
         f"{value:.4e} evals/s, {iters:.1f} it/s")
 
     npass = {"bf16x3": 3, "bf16x1": 1, "fp32": 1}.get(precision, 1)
+    traffic = measured_traffic(args.workload)   # HBM bytes per launch (rocprofv3 counters), or None
     if gauss:
         flops = npass * 2.0 * wl.d * evals
         pk = PEAK["bf16"] if precision.startswith("bf16") else PEAK["f32"]
         roof = {"bound": "mfma", "achieved": flops / (ms_cross * 1e-3) / 1e12, "peak": pk / 1e12,
-                "unit": "TFLOP/s", "frac": flops / (ms_cross * 1e-3) / pk, "traffic": None,
-                "kernel": f"k_cross_mfma<{precision}>",
-                "flops_per_launch": flops}
+                "unit": "TFLOP/s", "frac": flops / (ms_cross * 1e-3) / pk, "traffic": traffic,
+                "kernel": f"k_cross_bs<{precision}>", "flops_per_launch": flops}
     else:
-        # L1 path: 2 VALU ops (sub, add |.|) per coordinate per evaluation, FP32
+        # L1 path: 2 FP32 VALU lane operations (subtract, add |.|) per coordinate
+        # per evaluation; peak = 157.3 TFLOP/s / 2 lane operations (an FMA counts 2)
         ops = 2.0 * wl.d * evals
-        roof = {"bound": "alu", "achieved": ops / (ms_cross * 1e-3) / 1e12, "peak": 78.6,
-                "unit": "TFLOP/s", "frac": ops / (ms_cross * 1e-3) / 78.6e12, "traffic": None,
+        roof = {"bound": "alu", "achieved": ops / (ms_cross * 1e-3) / 1e12, "peak": PEAK["f32"] / 2e12,
+                "unit": "TOP/s", "frac": ops / (ms_cross * 1e-3) / (PEAK["f32"] / 2), "traffic": traffic,
                 "kernel": "k_cross_direct<laplace,f32>", "ops_per_launch": ops}
+        if traffic:
+            roof["hbm_GBps"] = traffic / (ms_cross * 1e-3) / 1e9
 
     out = {"metric": METRIC, "value": value, "unit": "kernel evals/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,

@@ -1,0 +1,173 @@
+// Device helpers shared by the kernel translation units (internal).
+#pragma once
+
+#include "mbkk_internal.h"
+
+namespace mbkk {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// Block-wide exclusive scan of one int per thread (blockDim.x a multiple of
+// 64, at most 1024): wave scans with shuffles, then a scan of the wave totals.
+// `lds` holds at least 16 ints.  Returns the exclusive prefix; *total gets the sum.
+__device__ __forceinline__ int block_exclusive_scan(int v, int *lds, int *total)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o);
+        if (lane >= o)
+            x += y;
+    }
+    if (lane == 63)
+        lds[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        int t = lane < nw ? lds[lane] : 0;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(t, o);
+            if (lane >= o)
+                t += y;
+        }
+        if (lane < nw)
+            lds[lane] = t;
+    }
+    __syncthreads();
+    const int res = (wid > 0 ? lds[wid - 1] : 0) + x - v;
+    *total = lds[nw - 1];
+    __syncthreads();
+    return res;
+}
+
+// Block-wide sum of one double per thread, in a fixed order (wave trees,
+// then the wave totals in order).  `lds` holds at least 16 doubles.
+__device__ __forceinline__ double block_sum(double v, double *lds)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o);
+    if (lane == 0)
+        lds[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int w = 0; w < nw; ++w)
+        t += lds[w];
+    __syncthreads();
+    return t;
+}
+
+// Smallest i in [0, n) with off[i + 1] > s, for a non-decreasing off[0..n]
+// with off[n] > s: the segment of entry s (empty segments skipped).  A 64-way
+// search by one wave; every lane of the wave calls it with the same s.
+__device__ __forceinline__ int wave_segment_of(const int32_t *__restrict__ off, int n, int s)
+{
+    const int lane = threadIdx.x & 63;
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int step = (hi - lo + 63) / 64;
+        const int q = lo + lane * step;
+        const bool pred = q < hi && off[q + 1] > s;
+        const uint64_t m = __ballot(pred);
+        if (m & 1ull)
+            return lo;  // pred(lo)
+        if (m == 0ull) {
+            const int last = min(63, (hi - 1 - lo) / step);
+            lo = lo + last * step + 1;
+        } else {
+            const int f = __ffsll((unsigned long long)m) - 1;
+            hi = lo + f * step + 1;
+            lo = lo + (f - 1) * step + 1;
+        }
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Gram blocks of one slot, as tasks.  The self-norm of a center held over its
+// support (Section 4.1) is a quadratic form in the blocks
+//   G_j[c][c'] = sum_{a in column c of center j} sum_{e in column c' of center j} K(a, e)
+// (column 0: the initial point, 1 + p: the center's rows of slot p).  The
+// blocks of slot rr against a set of live columns are cut into tasks of
+// kGramTA rows of slot rr by `te` rows of the column:
+//   tasks(j, c) = ceil(na_j / kGramTA) * ceil(ne_jc / te),
+// enumerated over jc = j * C + c with exclusive offsets goff[0 .. k*C].
+// ---------------------------------------------------------------------------
+constexpr int kGramTA = 32;
+
+// Rows of center j in column c: the slot rows through the grouping
+// permutation of their slot, column 0 the initial point (pool row j).
+struct GramCol {
+    int n;                 // rows
+    const int32_t *perm;   // grouped position -> row within the slot (nullptr: column 0)
+    int64_t row0;          // pool row of the slot's first row (column 0: j)
+};
+
+__device__ __forceinline__ GramCol gram_col(int k, int bmax, int j, int c, const int32_t *__restrict__ ring_off,
+                                            const int32_t *__restrict__ ring_perm)
+{
+    GramCol g;
+    if (c == 0) {
+        g.n = 1;
+        g.perm = nullptr;
+        g.row0 = j;
+    } else {
+        const int32_t *o = ring_off + (int64_t)(c - 1) * (k + 1);
+        g.n = o[j + 1] - o[j];
+        g.perm = ring_perm + (int64_t)(c - 1) * bmax + o[j];
+        g.row0 = (int64_t)k + (int64_t)(c - 1) * bmax;
+    }
+    return g;
+}
+
+__device__ __forceinline__ int64_t gram_row(const GramCol &g, int q) { return g.perm ? g.row0 + g.perm[q] : g.row0; }
+
+// Task offsets of the blocks of slot rr against the columns in `mask`, by
+// one workgroup (blockDim.x a multiple of 64, at most 1024).  Thread t owns
+// the centers [t * per, (t + 1) * per), per = ceil(k / blockDim.x); na_own,
+// if given, holds the row counts of slot rr for those centers (written by the
+// same threads), else they come from ring_off of slot rr.  `sint`: 16 ints of LDS.
+__device__ __forceinline__ void gram_plan(int k, int C, int rr, uint32_t mask, int te,
+                                          const int32_t *__restrict__ ring_off, const int32_t *na_own,
+                                          int32_t *__restrict__ goff, int *sint)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int per = (k + nt - 1) / nt;
+    const int j0 = min(k, tid * per), j1 = min(k, j0 + per);
+    const int32_t *orr = ring_off + (int64_t)rr * (k + 1);
+    auto tasks = [&](int j, int c, int na) -> int {
+        if (!((mask >> c) & 1u))
+            return 0;
+        int ne;
+        if (c == 0)
+            ne = 1;
+        else if (c - 1 == rr)
+            ne = na;
+        else {
+            const int32_t *o = ring_off + (int64_t)(c - 1) * (k + 1);
+            ne = o[j + 1] - o[j];
+        }
+        return ((na + kGramTA - 1) / kGramTA) * ((ne + te - 1) / te);
+    };
+    int local = 0;
+    for (int j = j0; j < j1; ++j) {
+        const int na = na_own ? na_own[j] : orr[j + 1] - orr[j];
+        for (int c = 0; c < C; ++c)
+            local += tasks(j, c, na);
+    }
+    int total;
+    int run = block_exclusive_scan(local, sint, &total);
+    for (int j = j0; j < j1; ++j) {
+        const int na = na_own ? na_own[j] : orr[j + 1] - orr[j];
+        for (int c = 0; c < C; ++c) {
+            goff[(int64_t)j * C + c] = run;
+            run += tasks(j, c, na);
+        }
+    }
+    if (tid == 0)
+        goff[(int64_t)k * C] = total;
+}
+
+}  // namespace mbkk

@@ -14,16 +14,22 @@ void launch_init_state(const Layout &L, const Buffers &B, int kind, double param
                        hipStream_t st);
 void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const SlotList &live, int init_alive,
                     const int32_t *idx, int64_t cnt, int check_finite, float ay_scale, hipStream_t st);
+// The update also writes the task plan of the new slot's Gram blocks against
+// the columns in gram_mask (for the Gram form chosen by gram_mfma).
 void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
-                   int init_keep, const SlotList &live, int lr, hipStream_t st);
-void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param,
-                 int fp64, hipStream_t st);
+                   int init_keep, const SlotList &live, int lr, uint32_t gram_mask, int gram_mfma, hipStream_t st);
+
+// Gram blocks of slot rr against the columns in col_mask: plan (when not made
+// by the update), then work and fold.  mfma: the Gaussian MFMA forms, with
+// the product arithmetic of `precision`; else VALU in FP64 or FP32.
+int gram_task_cols(int mfma);
+void launch_gram_plan(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int mfma, hipStream_t st);
+void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param, int fp64,
+                 int mfma, int precision, hipStream_t st);
 
 // Cross term P = <phi(x), C_j> for the staged batch rows [0, nb).
 void launch_cross_direct(const Layout &L, const Buffers &B, int nb, int kind, double param, int fp64,
                          hipStream_t st);
-void launch_gram_mfma(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int precision, double kappa,
-                      hipStream_t st);
 void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision, double kappa,
                        hipStream_t st);
 // Distances, argmin, margin (and optionally every distance) of rows [0, nb).

@@ -12,6 +12,7 @@
 //     exp fused in registers, segmented weighted sums over the support rows.
 #include <type_traits>
 
+#include "dev_common.h"
 #include "kernels.h"
 
 namespace mbkk {
@@ -50,10 +51,18 @@ __device__ __forceinline__ T kval_direct(const T (&x)[DR], const float *__restri
     }
 }
 
-// Register-resident batch row (DR >= d), support rows read with wave-uniform
-// addresses.  Grid: (row blocks of 256, center groups of cpg).
+// Ranges of the direct kernel: the concatenated support is cut into nranges
+// ranges of RR rows (RR from the support size, so the scoring kernel derives
+// the same cut); a run is a range's stretch of one center's segment.  Run id:
+// the center j for the run that starts at the center's first row, k + r for
+// the run that starts at the start of range r inside a center.
+__device__ __forceinline__ int direct_range_rows(int M, int nranges) { return (M + nranges - 1) / nranges; }
+
+// Register-resident batch row (DR >= d, one per lane), support rows of the
+// workgroup's range read with wave-uniform addresses.  Grid: (row tiles of
+// 256) x (ranges).
 template <int KIND, typename T, int DR>
-__global__ __launch_bounds__(256) void k_cross_direct(int nb, int d, int dp, int k, int cpg,
+__global__ __launch_bounds__(256) void k_cross_direct(int nb, int d, int dp, int k, int nranges,
                                                        const float *__restrict__ bat32,
                                                        const float *__restrict__ pool32,
                                                        const int32_t *__restrict__ sup_row,
@@ -64,6 +73,12 @@ __global__ __launch_bounds__(256) void k_cross_direct(int nb, int d, int dp, int
 {
     const int row = blockIdx.x * 256 + threadIdx.x;
     const int rr = row < nb ? row : 0;
+    const int r = blockIdx.y;
+    const int M = seg_off[k];
+    const int RR = direct_range_rows(M, nranges);
+    const int s0 = r * RR, s1 = min(M, s0 + RR);
+    if (s0 >= s1)
+        return;  // block uniform
     const T prm = (T)param;
     const T cneg = (T)(-1.4426950408889634 / param);
     T x[DR > 0 ? DR : 1];
@@ -73,11 +88,15 @@ __global__ __launch_bounds__(256) void k_cross_direct(int nb, int d, int dp, int
         for (int t = 0; t < DR; ++t)
             x[t] = t < d ? (T)bat32[(int64_t)rr * dp + t] : (T)0;
     }
-    const int j0 = blockIdx.y * cpg, j1 = min(k, j0 + cpg);
-    for (int j = j0; j < j1; ++j) {
-        const int s0 = seg_off[j], s1 = seg_off[j + 1];
+    int j = wave_segment_of(seg_off, k, s0);
+    int s = s0;
+    while (s < s1) {  // wave-uniform: one run per center overlapping the range
+        const int cs = seg_off[j];
+        const int e = min(s1, seg_off[j + 1]);
+        const int id = s == cs ? j : k + r;
+        const bool nonempty = s < e;
         T acc = 0;
-        for (int s = s0; s < s1; ++s) {
+        for (; s < e; ++s) {
             const float *y = pool32 + (int64_t)sup_row[s] * dp;
             T kv;
             if constexpr (DR > 0) {
@@ -114,18 +133,19 @@ __global__ __launch_bounds__(256) void k_cross_direct(int nb, int d, int dp, int
             else
                 acc = fma(sup_w64[s], kv, acc);
         }
-        if (row < nb)
-            P[(int64_t)j * ldp + row] = acc;
+        if (nonempty && row < nb)
+            P[(int64_t)id * ldp + row] = acc;
+        ++j;
     }
 }
 
 template <int KIND, typename T>
-static void dispatch_direct_width(const Layout &L, const Buffers &B, int nb, int cpg, double param, T *P,
+static void dispatch_direct_width(const Layout &L, const Buffers &B, int nb, int nranges, double param, T *P,
                                   hipStream_t st)
 {
-    dim3 grid((nb + 255) / 256, (L.k + cpg - 1) / cpg);
+    dim3 grid((nb + 255) / 256, nranges);
 #define MBKK_DIRECT(DR)                                                                                       \
-    hipLaunchKernelGGL((k_cross_direct<KIND, T, DR>), grid, dim3(256), 0, st, nb, L.d, L.dp, L.k, cpg,        \
+    hipLaunchKernelGGL((k_cross_direct<KIND, T, DR>), grid, dim3(256), 0, st, nb, L.d, L.dp, L.k, nranges,    \
                        B.bat32, B.pool32, B.sup_row, B.sup_w, B.sup_w64, B.seg_off, param, P, L.bmax)
     if (L.d <= 4)
         MBKK_DIRECT(4);
@@ -142,28 +162,33 @@ static void dispatch_direct_width(const Layout &L, const Buffers &B, int nb, int
 #undef MBKK_DIRECT
 }
 
+// Ranges of the direct kernel for nb batch rows: about kDirectWGs workgroups.
+static int direct_nranges(int nb)
+{
+    const int tiles = (nb + 255) / 256;
+    const int r = kDirectWGs / tiles;
+    return r < 1 ? 1 : r;
+}
+
 void launch_cross_direct(const Layout &L, const Buffers &B, int nb, int kind, double param, int fp64,
                          hipStream_t st)
 {
-    // enough workgroups to fill the chip: split the centers into groups
-    const int rowblocks = (nb + 255) / 256;
-    int cpg = (int)((int64_t)L.k * rowblocks / 2048);
-    cpg = cpg < 1 ? 1 : cpg;
+    const int nranges = direct_nranges(nb);
     if (fp64) {
         double *P = (double *)B.part;
         switch (kind) {
-        case MBKK_GAUSS: dispatch_direct_width<MBKK_GAUSS, double>(L, B, nb, cpg, param, P, st); break;
-        case MBKK_LAPLACE: dispatch_direct_width<MBKK_LAPLACE, double>(L, B, nb, cpg, param, P, st); break;
-        case MBKK_LINEAR: dispatch_direct_width<MBKK_LINEAR, double>(L, B, nb, cpg, param, P, st); break;
-        default: dispatch_direct_width<MBKK_POLY2, double>(L, B, nb, cpg, param, P, st); break;
+        case MBKK_GAUSS: dispatch_direct_width<MBKK_GAUSS, double>(L, B, nb, nranges, param, P, st); break;
+        case MBKK_LAPLACE: dispatch_direct_width<MBKK_LAPLACE, double>(L, B, nb, nranges, param, P, st); break;
+        case MBKK_LINEAR: dispatch_direct_width<MBKK_LINEAR, double>(L, B, nb, nranges, param, P, st); break;
+        default: dispatch_direct_width<MBKK_POLY2, double>(L, B, nb, nranges, param, P, st); break;
         }
     } else {
         float *P = (float *)B.part;
         switch (kind) {
-        case MBKK_GAUSS: dispatch_direct_width<MBKK_GAUSS, float>(L, B, nb, cpg, param, P, st); break;
-        case MBKK_LAPLACE: dispatch_direct_width<MBKK_LAPLACE, float>(L, B, nb, cpg, param, P, st); break;
-        case MBKK_LINEAR: dispatch_direct_width<MBKK_LINEAR, float>(L, B, nb, cpg, param, P, st); break;
-        default: dispatch_direct_width<MBKK_POLY2, float>(L, B, nb, cpg, param, P, st); break;
+        case MBKK_GAUSS: dispatch_direct_width<MBKK_GAUSS, float>(L, B, nb, nranges, param, P, st); break;
+        case MBKK_LAPLACE: dispatch_direct_width<MBKK_LAPLACE, float>(L, B, nb, nranges, param, P, st); break;
+        case MBKK_LINEAR: dispatch_direct_width<MBKK_LINEAR, float>(L, B, nb, nranges, param, P, st); break;
+        default: dispatch_direct_width<MBKK_POLY2, float>(L, B, nb, nranges, param, P, st); break;
         }
     }
 }
@@ -186,10 +211,6 @@ void launch_cross_direct(const Layout &L, const Buffers &B, int nb, int kind, do
 //   MODE 1: BF16 32x32x16, hi.hi + hi.lo + lo.hi (compensated split)
 //   MODE 2: BF16 32x32x16, hi.hi only
 // ===========================================================================
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
 struct CrossArgs {
     int nb, dp, ntB;
@@ -1083,147 +1104,6 @@ void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision,
 }
 
 // ===========================================================================
-// Gram blocks on MFMA (Gaussian, d <= 128), same arithmetic as the cross
-// term of the form (FP32 MFMA, or BF16 hi/lo split):
-//   G_j[1+rr][c] = G_j[c][1+rr] = sum_{a in slot rr, center j} sum_{e in column c, center j}
-//                                 exp(-(||a||^2 + ||e||^2 - 2 a.e) / kappa)
-// One workgroup per (center j, column c).  The product is cut into 32 x 32
-// blocks (a-block, e-block); each of the 16 waves takes blocks w, w + 16, ...
-// (fragments loaded straight from the pool into registers), so a large
-// cluster's blocks are computed in parallel.  Kernel values are summed in
-// FP64 per wave, then over the waves in a fixed order.
-// ===========================================================================
-constexpr int kGramWaves = 16;
-
-template <int MODE, int DP>
-__global__ __launch_bounds__(64 * kGramWaves) void k_gram_mfma(int k, int C, int bmax, int rr, uint32_t col_mask,
-                                                                const int32_t *__restrict__ ring_off,
-                                                                const int32_t *__restrict__ ring_perm,
-                                                                int64_t zero_row, const float *__restrict__ pool32,
-                                                                const uint16_t *__restrict__ poolhi,
-                                                                const uint16_t *__restrict__ poollo,
-                                                                const float *__restrict__ poolsq, float c2, float c1,
-                                                                double *__restrict__ G)
-{
-    constexpr bool F32 = MODE == 0;
-    constexpr bool X3 = MODE == 1;
-    constexpr int KS = F32 ? DP / 2 : DP / 16;
-    __shared__ float sqa[kGramWaves][32];
-    __shared__ double red[kGramWaves];
-    const int j = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
-    const int lane = tid & 63, w = tid >> 6, n = lane & 31, h = lane >> 5;
-    if (!((col_mask >> c) & 1u))
-        return;  // block uniform
-    const int32_t *oa = ring_off + (int64_t)rr * (k + 1);
-    const int na = oa[j + 1] - oa[j];
-    const int32_t *pa = ring_perm + (int64_t)rr * bmax + oa[j];
-    const int64_t arow0 = (int64_t)k + (int64_t)rr * bmax;
-    int ne;
-    const int32_t *pe = nullptr;
-    int64_t erow0;
-    if (c == 0) {
-        ne = 1;
-        erow0 = j;
-    } else {
-        const int32_t *oe = ring_off + (int64_t)(c - 1) * (k + 1);
-        ne = oe[j + 1] - oe[j];
-        pe = ring_perm + (int64_t)(c - 1) * bmax + oe[j];
-        erow0 = (int64_t)k + (int64_t)(c - 1) * bmax;
-    }
-    const int nA = (na + 31) / 32, nE = (ne + 31) / 32;
-    double tot = 0.0;
-    for (int t = w; t < nA * nE; t += kGramWaves) {  // wave-uniform
-        const int ab = t / nE, eb = t % nE;
-        const int qa = ab * 32 + n, qe = eb * 32 + n;
-        const int64_t ra = qa < na ? arow0 + pa[qa] : zero_row;
-        const int64_t re = qe < ne ? (c == 0 ? erow0 : erow0 + pe[qe]) : zero_row;
-        // lane n (h = 0) publishes the norm of a-row n for the output rows m
-        if (h == 0)
-            sqa[w][n] = c1 * poolsq[ra];
-        const float se_ = c1 * poolsq[re];
-        f32x16 acc;
-#pragma unroll
-        for (int i = 0; i < 16; ++i)
-            acc[i] = 0.0f;
-        if constexpr (F32) {
-            const float *sa = pool32 + ra * DP + h * KS, *se = pool32 + re * DP + h * KS;
-#pragma unroll
-            for (int s4 = 0; s4 < KS; s4 += 4) {
-                const f32x4 av = *(const f32x4 *)(sa + s4), ev = *(const f32x4 *)(se + s4);
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], ev[u], acc, 0, 0, 0);
-            }
-        } else {
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                const int64_t oa16 = ra * DP + ks * 16 + h * 8, oe16 = re * DP + ks * 16 + h * 8;
-                const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poolhi + oa16));
-                const bf16x8 eh = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poolhi + oe16));
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, eh, acc, 0, 0, 0);
-                if constexpr (X3) {
-                    const bf16x8 al = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poollo + oa16));
-                    const bf16x8 el = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poollo + oe16));
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, el, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, eh, acc, 0, 0, 0);
-                }
-            }
-        }
-        // lane: column n (e row), rows m = 8 (i/4) + 4 h + i%4 (a rows); the
-        // LDS row norms were written by this wave (in-order LDS access)
-        if (qe < ne) {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int m = 8 * (i >> 2) + 4 * h + (i & 3);
-                if (ab * 32 + m < na)
-                    tot += (double)__builtin_amdgcn_exp2f(fmaf(acc[i], c2, sqa[w][m] + se_));
-            }
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1)
-        tot += __shfl_xor(tot, o);
-    if (lane == 0)
-        red[w] = tot;
-    __syncthreads();
-    if (tid == 0) {
-        double g = 0.0;
-        for (int q = 0; q < kGramWaves; ++q)
-            g += red[q];
-        double *gj = G + (int64_t)j * C * C;
-        gj[(1 + rr) * C + c] = g;
-        gj[c * C + 1 + rr] = g;
-    }
-}
-
-void launch_gram_mfma(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int precision, double kappa,
-                      hipStream_t st)
-{
-    const double l2e = 1.4426950408889634;
-    const float c2 = (float)(2.0 * l2e / kappa), c1 = (float)(-l2e / kappa);
-    dim3 grid(L.k, L.C);
-#define MBKK_GM(MODE, DP)                                                                                       \
-    hipLaunchKernelGGL((k_gram_mfma<MODE, DP>), grid, dim3(64 * kGramWaves), 0, st, L.k, L.C, L.bmax, rr,       \
-                       col_mask, B.ring_off, B.ring_perm, L.PR, B.pool32, B.poolhi, B.poollo, B.poolsq, c2, c1,   \
-                       B.G)
-#define MBKK_GM_DP(MODE)                 \
-    switch (L.dp) {                      \
-    case 32: MBKK_GM(MODE, 32); break;   \
-    case 64: MBKK_GM(MODE, 64); break;   \
-    case 96: MBKK_GM(MODE, 96); break;   \
-    default: MBKK_GM(MODE, 128); break;  \
-    }
-    if (precision == MBKK_FP32) {
-        MBKK_GM_DP(0);
-    } else if (precision == MBKK_BF16X3) {
-        MBKK_GM_DP(1);
-    } else {
-        MBKK_GM_DP(2);
-    }
-#undef MBKK_GM_DP
-#undef MBKK_GM
-}
-
-// ===========================================================================
 // Distances, argmin and margin of each batch row:
 //   D_j = K(x,x) - 2 P_j + N_j  (FP64 assembly of the FP32/FP64 cross term)
 // label = smallest j attaining the minimum; margin = second smallest - min.
@@ -1241,12 +1121,24 @@ __device__ __forceinline__ double self_kernel(int kind, double param, double sq)
 // LAYOUT 1: the MFMA kernels write one partial per run of a center's blocks
 // inside a range of RB blocks, at the run's first block: the center's first
 // block and every range start inside the center.
+// LAYOUT 0: the direct kernel's runs (ranges of RR rows): run j (the run at
+// the center's first row) plus run k + r of every range r that starts
+// strictly inside the center's segment.
+// LAYOUT 1: the MFMA kernels write one partial per run of a center's blocks
+// inside a range of RB blocks, at the run's first block: the center's first
+// block and every range start inside the center.
 template <typename T, int LAYOUT>
 __device__ __forceinline__ double cross_of(const T *__restrict__ part, int ldp, int row, int j,
-                                           const int32_t *__restrict__ seg_off, int RB)
+                                           const int32_t *__restrict__ seg_off, int RB, int k = 0)
 {
     if constexpr (LAYOUT == 0) {
-        return (double)part[(int64_t)j * ldp + row];
+        const int s0 = seg_off[j], s1 = seg_off[j + 1];
+        if (s0 >= s1)
+            return 0.0;
+        double s = (double)part[(int64_t)j * ldp + row];
+        for (int r = s0 / RB + 1; r * RB < s1; ++r)
+            s += (double)part[(int64_t)(k + r) * ldp + row];
+        return s;
     } else {
         const int bs = seg_off[j] / 32, be = seg_off[j + 1] / 32;
         if (bs >= be)
@@ -1363,7 +1255,8 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
     const int row = blockIdx.x * 64 + lane;
     const bool act = row < A.nb;
     const T *part = (const T *)A.part;
-    const int RB = A.nranges > 0 ? bs_range_blocks(A.seg_off[A.k] / 32, A.nranges) : A.RB;
+    const int RB = LAYOUT == 0 ? direct_range_rows(A.seg_off[A.k], A.nranges)
+                               : (A.nranges > 0 ? bs_range_blocks(A.seg_off[A.k] / 32, A.nranges) : A.RB);
     const double kxx = act ? self_kernel(A.kind, A.param, A.batsq64[row]) : 0.0;
     double best = INFINITY, second = INFINITY;
     int lab = 0x7fffffff;
@@ -1376,7 +1269,7 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
 #pragma unroll
             for (int u = 0; u < NB; ++u) {
                 const int j = j0 + u * kScoreWaves;
-                P[u] = j < A.k ? cross_of<T, LAYOUT>(part, A.ldp, row, j, A.seg_off, RB) : 0.0;
+                P[u] = j < A.k ? cross_of<T, LAYOUT>(part, A.ldp, row, j, A.seg_off, RB, A.k) : 0.0;
                 Nj[u] = j < A.k ? A.N[j] : 0.0;
             }
 #pragma unroll
@@ -1474,7 +1367,7 @@ void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double pa
     A.k = L.k;
     A.ldp = L.bmax;
     A.RB = 2;
-    A.nranges = (mfma && L.dp <= 128) ? bs_nranges(nb, bs_mode(precision), L.dp) : 0;
+    A.nranges = mfma ? (L.dp <= 128 ? bs_nranges(nb, bs_mode(precision), L.dp) : 0) : direct_nranges(nb);
     A.kind = kind;
     A.param = param;
     A.part = B.part;

@@ -1,0 +1,354 @@
+// Gram blocks of the implicit centers (kernel values summed in FP64).
+//
+// A center held over its support (Section 4.1, Eq. 1 with a window of W
+// batches) has self-norm <C_j, C_j> = sum_{c,c'} coef_j[c] coef_j[c'] G_j[c][c'];
+// when batch i enters slot rr only the blocks
+//   G_j[1+rr][c] = G_j[c][1+rr] = sum_{a in slot rr, center j} sum_{e in column c, center j} K(a, e)
+// against the live columns c are new.  Their pairs are cut into tasks of
+// kGramTA rows of the slot by te rows of the column (gram_plan), so that a
+// cluster holding most of the batch is spread over the whole GPU:
+//   plan : task offsets goff over jc = j * C + c (fused into the grouping
+//          kernel of a step, k_gram_plan elsewhere);
+//   work : kGramWaves waves take equal contiguous task ranges; wave w sums
+//          its tasks of one jc in FP64 in task order and stores the sum at
+//          gpart[w + jc].  The (wave, jc) runs of a split into contiguous
+//          ranges form a monotone staircase, so w + jc is distinct per run;
+//   fold : per live (j, c), the partials of its waves in wave order.
+// Every sum has a fixed order, so the blocks are bit-reproducible.
+//   k_gram_valu : any kernel, FP32 or FP64 arithmetic; a task is 32 slot
+//                 rows (wave-uniform) x 64 column rows (one per lane);
+//   k_gram_mfma : Gaussian MFMA forms, the form's own product arithmetic
+//                 (FP32 MFMA, or BF16 hi/lo split) and exp fused in
+//                 registers; a task is one 32 x 32 output block.
+#include "dev_common.h"
+#include "kernels.h"
+
+namespace mbkk {
+
+struct GramWork {
+    int k, C, bmax, rr;
+    const int32_t *ring_off, *ring_perm;
+    const int32_t *goff;  // [k*C + 1] task offsets
+    double *gpart;        // [kGramWaves + k*C] per-run partials
+};
+
+constexpr int kGramWG = 256;  // 4 waves per workgroup
+
+// Runs `task(a, e, ab, eb, lsum)` over this wave's task range; a = the slot's
+// rows of center j, e = column c's rows, (ab, eb) the task's row blocks.
+template <int TE, class Task>
+__device__ __forceinline__ void gram_wave_loop(const GramWork &A, Task &&task)
+{
+    const int lane = threadIdx.x & 63;
+    const int w = blockIdx.x * (kGramWG / 64) + (threadIdx.x >> 6);
+    const int nJC = A.k * A.C;
+    const int T = A.goff[nJC];
+    if (T == 0)
+        return;
+    const int chunk = (T + kGramWaves - 1) / kGramWaves;
+    const int64_t t0l = (int64_t)w * chunk;
+    if (t0l >= T)
+        return;  // wave uniform
+    const int t0 = (int)t0l, t1 = min(T, t0 + chunk);
+    int jc = wave_segment_of(A.goff, nJC, t0);
+    int t = t0;
+    while (t < t1) {  // wave uniform
+        const int g0 = A.goff[jc], g1 = A.goff[jc + 1];
+        const int e = min(t1, g1);
+        if (t < e) {
+            const int j = jc / A.C, c = jc - j * A.C;
+            const GramCol a = gram_col(A.k, A.bmax, j, 1 + A.rr, A.ring_off, A.ring_perm);
+            const GramCol ec = gram_col(A.k, A.bmax, j, c, A.ring_off, A.ring_perm);
+            const int nE = (ec.n + TE - 1) / TE;
+            double lsum = 0.0;
+            for (; t < e; ++t) {
+                const int u = t - g0;
+                const int ab = u / nE, eb = u - ab * nE;
+                task(a, ec, ab, eb, lsum);
+            }
+            for (int o = 32; o > 0; o >>= 1)
+                lsum += __shfl_xor(lsum, o);
+            if (lane == 0)
+                A.gpart[w + jc] = lsum;
+        }
+        ++jc;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// VALU tasks
+// ---------------------------------------------------------------------------
+template <int KIND, typename KT>
+__device__ __forceinline__ void gram_term(KT &s, KT x, KT y)
+{
+    if constexpr (KIND == MBKK_GAUSS) {
+        const KT v = x - y;
+        s = fma(v, v, s);
+    } else if constexpr (KIND == MBKK_LAPLACE) {
+        s += fabs(x - y);
+    } else {
+        s = fma(x, y, s);
+    }
+}
+
+template <int KIND, typename KT>
+__device__ __forceinline__ KT gram_finish(KT s, KT prm)
+{
+    if constexpr (KIND == MBKK_GAUSS || KIND == MBKK_LAPLACE)
+        return (KT)exp(-s / prm);
+    else if constexpr (KIND == MBKK_LINEAR)
+        return s;
+    else
+        return (s + prm) * (s + prm);
+}
+
+constexpr int kGramTEV = 64;  // column rows of a VALU task (one per lane)
+constexpr int kGramDC = 32;   // coordinates per register chunk (the pool stride is a multiple)
+
+// Lane l holds column row eb*64 + l in registers, 32 coordinates at a time;
+// the task's slot rows are read with wave-uniform addresses.  Pairs, sums
+// and the kernel value in KT; the task sum in FP64.
+template <int KIND, typename KT>
+__global__ __launch_bounds__(kGramWG) void k_gram_valu(const GramWork A, int d, int dp, double param,
+                                                       const float *__restrict__ pool32, int zero_row)
+{
+    const int lane = threadIdx.x & 63;
+    const KT prm = (KT)param;
+    gram_wave_loop<kGramTEV>(A, [&](const GramCol &a, const GramCol &ec, int ab, int eb, double &lsum) {
+        const int qe = eb * kGramTEV + lane;
+        const bool eok = qe < ec.n;
+        const int re = eok ? (int)gram_row(ec, qe) : zero_row;
+        const int na = min(kGramTA, a.n - ab * kGramTA);
+        const int ral = lane < na ? (int)gram_row(a, ab * kGramTA + lane) : zero_row;
+        KT acc[kGramTA];
+#pragma unroll
+        for (int i = 0; i < kGramTA; ++i)
+            acc[i] = 0;
+        for (int t0 = 0; t0 < d; t0 += kGramDC) {
+            KT ev[kGramDC];
+            const float *pe = pool32 + (int64_t)re * dp + t0;
+#pragma unroll
+            for (int u = 0; u < kGramDC; u += 4) {
+                const f32x4 v = *(const f32x4 *)(pe + u);
+                ev[u] = (KT)v[0];
+                ev[u + 1] = (KT)v[1];
+                ev[u + 2] = (KT)v[2];
+                ev[u + 3] = (KT)v[3];
+            }
+#pragma unroll
+            for (int i = 0; i < kGramTA; ++i) {
+                if (i < na) {  // wave uniform
+                    const int ra = __builtin_amdgcn_readlane(ral, i);
+                    const float *pa = pool32 + (int64_t)ra * dp + t0;
+#pragma unroll
+                    for (int u = 0; u < kGramDC; ++u)
+                        gram_term<KIND, KT>(acc[i], (KT)pa[u], ev[u]);
+                }
+            }
+        }
+        if (eok) {
+#pragma unroll
+            for (int i = 0; i < kGramTA; ++i)
+                if (i < na)
+                    lsum += (double)gram_finish<KIND, KT>(acc[i], prm);
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// MFMA tasks (Gaussian): exp(-(||a||^2 + ||e||^2 - 2 a.e) / kappa) with a.e
+// in the form's arithmetic; DP = 0 takes the row stride at run time.
+//   MODE 0: FP32 MFMA 32x32x2; MODE 1: BF16 hi.hi + hi.lo + lo.hi; MODE 2: BF16 hi.hi
+// ---------------------------------------------------------------------------
+template <int MODE, int DP>
+__global__ __launch_bounds__(kGramWG) void k_gram_mfma(const GramWork A, int dp_rt, int zero_row,
+                                                       const float *__restrict__ pool32,
+                                                       const uint16_t *__restrict__ poolhi,
+                                                       const uint16_t *__restrict__ poollo,
+                                                       const float *__restrict__ poolsq, float c2, float c1)
+{
+    constexpr bool F32 = MODE == 0;
+    constexpr bool X3 = MODE == 1;
+    const int dp = DP > 0 ? DP : dp_rt;
+    const int KS = F32 ? dp / 2 : dp / 16;
+    __shared__ float sqa[kGramWG / 64][32];
+    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
+    gram_wave_loop<32>(A, [&](const GramCol &a, const GramCol &ec, int ab, int eb, double &lsum) {
+        const int qa = ab * 32 + n, qe = eb * 32 + n;
+        const int64_t ra = qa < a.n ? gram_row(a, qa) : zero_row;
+        const int64_t re = qe < ec.n ? gram_row(ec, qe) : zero_row;
+        // lane n (h = 0) publishes the norm of a-row n for the output rows m
+        if (h == 0)
+            sqa[wl][n] = c1 * poolsq[ra];
+        const float se_ = c1 * poolsq[re];
+        f32x16 acc;
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            acc[i] = 0.0f;
+        if constexpr (F32) {
+            const float *sa = pool32 + ra * dp + h * KS, *se = pool32 + re * dp + h * KS;
+            auto kstep = [&](int s4) {
+                const f32x4 av = *(const f32x4 *)(sa + s4), ev = *(const f32x4 *)(se + s4);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], ev[u], acc, 0, 0, 0);
+            };
+            if constexpr (DP > 0) {
+#pragma unroll
+                for (int s4 = 0; s4 < DP / 2; s4 += 4)
+                    kstep(s4);
+            } else {
+                for (int s4 = 0; s4 < KS; s4 += 4)
+                    kstep(s4);
+            }
+        } else {
+            auto kstep = [&](int ks) {
+                const int64_t oa16 = ra * dp + ks * 16 + h * 8, oe16 = re * dp + ks * 16 + h * 8;
+                const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poolhi + oa16));
+                const bf16x8 eh = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poolhi + oe16));
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, eh, acc, 0, 0, 0);
+                if constexpr (X3) {
+                    const bf16x8 al = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poollo + oa16));
+                    const bf16x8 el = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poollo + oe16));
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, el, acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, eh, acc, 0, 0, 0);
+                }
+            };
+            if constexpr (DP > 0) {
+#pragma unroll
+                for (int ks = 0; ks < DP / 16; ++ks)
+                    kstep(ks);
+            } else {
+                for (int ks = 0; ks < KS; ++ks)
+                    kstep(ks);
+            }
+        }
+        // lane: column n (e row), rows m = 8 (i/4) + 4 h + i%4 (a rows); the
+        // row norms were written by this wave (in-order LDS access)
+        if (qe < ec.n) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int m = 8 * (i >> 2) + 4 * h + (i & 3);
+                if (ab * 32 + m < a.n)
+                    lsum += (double)__builtin_amdgcn_exp2f(fmaf(acc[i], c2, sqa[wl][m] + se_));
+            }
+        }
+    });
+}
+
+// ---------------------------------------------------------------------------
+// plan (outside a step) and fold
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_gram_plan(int k, int C, int rr, uint32_t mask, int te,
+                                                    const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff)
+{
+    __shared__ int sint[16];
+    gram_plan(k, C, rr, mask, te, ring_off, nullptr, goff, sint);
+}
+
+// One wave per jc: the partials of the waves whose ranges met jc, summed
+// lane-strided and then across the wave (a fixed order).
+__global__ __launch_bounds__(256) void k_gram_fold(int k, int C, int rr, uint32_t mask,
+                                                   const int32_t *__restrict__ goff,
+                                                   const double *__restrict__ gpart, double *__restrict__ G)
+{
+    const int lane = threadIdx.x & 63;
+    const int jc = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (jc >= k * C)
+        return;
+    const int j = jc / C, c = jc - j * C;
+    if (!((mask >> c) & 1u))
+        return;
+    const int g0 = goff[jc], g1 = goff[jc + 1];
+    double s = 0.0;
+    if (g1 > g0) {
+        const int T = goff[k * C];
+        const int chunk = (T + kGramWaves - 1) / kGramWaves;
+        const int w0 = g0 / chunk, w1 = (g1 - 1) / chunk;
+        for (int w = w0 + lane; w <= w1; w += 64)
+            s += gpart[w + jc];
+        for (int o = 32; o > 0; o >>= 1)
+            s += __shfl_xor(s, o);
+    }
+    if (lane == 0) {
+        double *g = G + (int64_t)j * C * C;
+        g[(1 + rr) * C + c] = s;
+        g[c * C + 1 + rr] = s;
+    }
+}
+
+int gram_task_cols(int mfma) { return mfma ? 32 : kGramTEV; }
+
+void launch_gram_plan(const Layout &L, const Buffers &B, int rr, uint32_t mask, int mfma, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gram_plan, dim3(1), dim3(1024), 0, st, L.k, L.C, rr, mask, gram_task_cols(mfma),
+                       B.ring_off, B.goff);
+}
+
+template <typename KT>
+static void launch_gram_valu(const Layout &L, const Buffers &B, const GramWork &A, int kind, double param,
+                             hipStream_t st)
+{
+    const dim3 grid(kGramWaves / (kGramWG / 64));
+    const int zr = (int)L.PR;
+#define MBKK_GV(K) \
+    hipLaunchKernelGGL((k_gram_valu<K, KT>), grid, dim3(kGramWG), 0, st, A, L.d, L.dp, param, B.pool32, zr)
+    switch (kind) {
+    case MBKK_GAUSS: MBKK_GV(MBKK_GAUSS); break;
+    case MBKK_LAPLACE: MBKK_GV(MBKK_LAPLACE); break;
+    case MBKK_LINEAR: MBKK_GV(MBKK_LINEAR); break;
+    default: MBKK_GV(MBKK_POLY2); break;
+    }
+#undef MBKK_GV
+}
+
+template <int MODE>
+static void launch_gram_mfma(const Layout &L, const Buffers &B, const GramWork &A, double kappa, hipStream_t st)
+{
+    const double l2e = 1.4426950408889634;
+    const float c2 = (float)(2.0 * l2e / kappa), c1 = (float)(-l2e / kappa);
+    const dim3 grid(kGramWaves / (kGramWG / 64));
+    const int zr = (int)L.PR;
+#define MBKK_GM(DP)                                                                                          \
+    hipLaunchKernelGGL((k_gram_mfma<MODE, DP>), grid, dim3(kGramWG), 0, st, A, L.dp, zr, B.pool32, B.poolhi, \
+                       B.poollo, B.poolsq, c2, c1)
+    switch (L.dp) {
+    case 32: MBKK_GM(32); break;
+    case 64: MBKK_GM(64); break;
+    case 96: MBKK_GM(96); break;
+    case 128: MBKK_GM(128); break;
+    default: MBKK_GM(0); break;
+    }
+#undef MBKK_GM
+}
+
+void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t mask, int kind, double param, int fp64,
+                 int mfma, int precision, hipStream_t st)
+{
+    GramWork A;
+    A.k = L.k;
+    A.C = L.C;
+    A.bmax = L.bmax;
+    A.rr = rr;
+    A.ring_off = B.ring_off;
+    A.ring_perm = B.ring_perm;
+    A.goff = B.goff;
+    A.gpart = B.gpart;
+    if (mfma) {
+        if (precision == MBKK_FP32)
+            launch_gram_mfma<0>(L, B, A, param, st);
+        else if (precision == MBKK_BF16X3)
+            launch_gram_mfma<1>(L, B, A, param, st);
+        else
+            launch_gram_mfma<2>(L, B, A, param, st);
+    } else if (fp64) {
+        launch_gram_valu<double>(L, B, A, kind, param, st);
+    } else {
+        launch_gram_valu<float>(L, B, A, kind, param, st);
+    }
+    const int njc = L.k * L.C;
+    hipLaunchKernelGGL(k_gram_fold, dim3((njc + 3) / 4), dim3(256), 0, st, L.k, L.C, rr, mask, B.goff, B.gpart,
+                       B.G);
+}
+
+}  // namespace mbkk

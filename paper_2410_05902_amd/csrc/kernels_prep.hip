@@ -4,7 +4,9 @@
 //   - support layout of the implicit centers (Eq. 1 as a ring of slots),
 //   - the update: deterministic grouping of the batch by center, counts
 //     b_i^j, learning rates, coefficient decay by (1 - alpha), truncation,
-//   - the FP64 Gram blocks that give <C_j, C_j> incrementally.
+//     and the task plan of the new slot's Gram blocks (computed in
+//     kernels_gram.hip).
+#include "dev_common.h"
 #include "kernels.h"
 
 namespace mbkk {
@@ -367,58 +369,9 @@ void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const 
 //   chunk of 64 rows and counts the chunk's labels; then one workgroup
 //   computes the counts b_i^j, the offsets of the centers in the new slot,
 //   per-(chunk, label) bases, the learning rates alpha, the coefficient
-//   update and truncation, the batch objective, and scatters every row to
-//   base + rank.
+//   update and truncation, the task offsets of the new slot's Gram blocks,
+//   the batch objective, and scatters every row to base + rank.
 // ---------------------------------------------------------------------------
-// Block-wide exclusive scan of one int per thread (blockDim.x a multiple of
-// 64, at most 1024): wave scans with shuffles, then a scan of the wave totals.
-// `lds` holds at least 16 ints.  Returns the exclusive prefix; *total gets the sum.
-__device__ int block_exclusive_scan(int v, int *lds, int *total)
-{
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    int x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o);
-        if (lane >= o)
-            x += y;
-    }
-    if (lane == 63)
-        lds[wid] = x;
-    __syncthreads();
-    if (wid == 0) {
-        int t = lane < nw ? lds[lane] : 0;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(t, o);
-            if (lane >= o)
-                t += y;
-        }
-        if (lane < nw)
-            lds[lane] = t;
-    }
-    __syncthreads();
-    const int res = (wid > 0 ? lds[wid - 1] : 0) + x - v;
-    *total = lds[nw - 1];
-    __syncthreads();
-    return res;
-}
-
-// Block-wide sum of one double per thread, in a fixed order (wave trees,
-// then the wave totals in order).  `lds` holds at least 16 doubles.
-__device__ double block_sum(double v, double *lds)
-{
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int o = 32; o > 0; o >>= 1)
-        v += __shfl_xor(v, o);
-    if (lane == 0)
-        lds[wid] = v;
-    __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < nw; ++w)
-        t += lds[w];
-    __syncthreads();
-    return t;
-}
-
 // LDS variant (per-chunk counts held in LDS) when nchunk * k is at most this.
 constexpr int kGroupLdsMax = 8192;
 
@@ -430,7 +383,8 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
     double *__restrict__ coef, double *__restrict__ cum, int32_t *__restrict__ counts,
     double *__restrict__ alpha, int32_t *__restrict__ off, double *__restrict__ obj,
     const int32_t *__restrict__ labels, const int32_t *__restrict__ rank, const int32_t *__restrict__ pts,
-    int32_t *__restrict__ ring_idx, int32_t *__restrict__ ring_perm)
+    int32_t *__restrict__ ring_idx, int32_t *__restrict__ ring_perm, uint32_t gram_mask, int gram_te,
+    const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff)
 {
     __shared__ int sint[16];
     __shared__ double sdbl[16];
@@ -492,6 +446,9 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
     }
     if (tid == 0)
         off[k] = b;
+    // task offsets of the Gram blocks of the new slot (its counts are this
+    // thread's b_i^j above; the other live slots' offsets are settled)
+    gram_plan(k, C, p_new, gram_mask, gram_te, ring_off, counts, goff, sint);
     // sum of min distances (FP64), fixed order
     double sm = 0.0;
     for (int p = tid; p < b; p += nt)
@@ -509,176 +466,21 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
 }
 
 void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
-                   int init_keep, const SlotList &live, int lr, hipStream_t st)
+                   int init_keep, const SlotList &live, int lr, uint32_t gram_mask, int gram_mfma, hipStream_t st)
 {
     const int nchunk = (b + kChunk - 1) / kChunk;
+    const int gram_te = gram_task_cols(gram_mfma);
 #define MBKK_GO(LDS)                                                                                             \
     hipLaunchKernelGGL(k_group_offsets<LDS>, dim3(1), dim3(1024), 0, st, b, L.k, nchunk, L.C, p_new, p_expired,  \
                        init_alive_before, init_keep, live, lr, B.gcnt, B.gbase, B.mind, B.coef, B.cum, B.counts, \
                        B.alpha, B.ring_off + (int64_t)p_new * (L.k + 1), B.obj, B.labels, B.rank,                 \
                        B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,               \
-                       B.ring_perm + (int64_t)p_new * L.bmax)
+                       B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_te, B.ring_off, B.goff)
     if ((int64_t)nchunk * L.k <= kGroupLdsMax)
         MBKK_GO(true);
     else
         MBKK_GO(false);
 #undef MBKK_GO
-}
-
-// ---------------------------------------------------------------------------
-// Gram blocks of slot rr (FP32 or FP64 kernel values, FP64 sums):
-//   G_j[1+rr][c] = G_j[c][1+rr] = sum_{a in slot rr, center j} sum_{e in column c, center j} K(a, e)
-// for every live column c (0: the initial point of center j; 1+p: slot p).
-// One workgroup per (center j, column c).  Rows are taken 48 x 48 at a time
-// and coordinates 128 at a time (one load phase when d <= 128); each thread
-// owns a 3 x 3 tile of pairs.
-// ---------------------------------------------------------------------------
-constexpr int kGT = 48, kGK = 128, kGLd = kGK + 1;  // odd LDS stride: conflict-free column reads
-
-template <int KIND, typename KT>
-__device__ __forceinline__ void gram_term(KT &s, KT x, KT y)
-{
-    if constexpr (KIND == MBKK_GAUSS) {
-        const KT v = x - y;
-        s = fma(v, v, s);
-    } else if constexpr (KIND == MBKK_LAPLACE) {
-        s += fabs(x - y);
-    } else {
-        s = fma(x, y, s);
-    }
-}
-
-template <int KIND, typename KT>
-__device__ __forceinline__ KT gram_finish(KT s, KT prm)
-{
-    if constexpr (KIND == MBKK_GAUSS || KIND == MBKK_LAPLACE)
-        return (KT)exp(-s / prm);
-    else if constexpr (KIND == MBKK_LINEAR)
-        return s;
-    else
-        return (s + prm) * (s + prm);
-}
-
-template <int KIND, typename KT>
-__global__ __launch_bounds__(256) void k_gram(int k, int C, int bmax, int d, int dp, double param, int rr,
-                                               uint32_t col_mask, const int32_t *__restrict__ ring_off,
-                                               const int32_t *__restrict__ ring_perm,
-                                               const float *__restrict__ pool32, double *__restrict__ G)
-{
-    __shared__ float sa[kGT * kGLd], se[kGT * kGLd];
-    __shared__ double red[256];
-    const int j = blockIdx.x, c = blockIdx.y, tid = threadIdx.x;
-    if (!((col_mask >> c) & 1u))
-        return;  // block uniform
-    // rows of slot rr for center j
-    const int32_t *oa = ring_off + (int64_t)rr * (k + 1);
-    const int na = oa[j + 1] - oa[j];
-    const int32_t *pa_perm = ring_perm + (int64_t)rr * bmax + oa[j];
-    const int64_t arow0 = (int64_t)k + (int64_t)rr * bmax;
-    // rows of column c for center j
-    int ne;
-    const int32_t *pe_perm = nullptr;
-    int64_t erow0;
-    if (c == 0) {
-        ne = 1;
-        erow0 = j;
-    } else {
-        const int pc = c - 1;
-        const int32_t *oe = ring_off + (int64_t)pc * (k + 1);
-        ne = oe[j + 1] - oe[j];
-        pe_perm = ring_perm + (int64_t)pc * bmax + oe[j];
-        erow0 = (int64_t)k + (int64_t)pc * bmax;
-    }
-    const int ty = tid >> 4, tx = tid & 15;  // pairs (ty + 16u, tx + 16v), u, v < 3
-    const int lr = tid >> 5, lc = (tid & 31) * 4;  // loader: rows lr + 8q, 4 coordinates
-    const KT prm = (KT)param;
-    double acc = 0.0;
-    for (int at = 0; at < na; at += kGT) {
-        for (int et = 0; et < ne; et += kGT) {
-            KT sv[3][3];
-#pragma unroll
-            for (int u = 0; u < 3; ++u)
-#pragma unroll
-                for (int v = 0; v < 3; ++v)
-                    sv[u][v] = 0;
-            for (int t0 = 0; t0 < d; t0 += kGK) {
-                __syncthreads();
-                const int col = t0 + lc;
-#pragma unroll
-                for (int q = 0; q < kGT / 8; ++q) {
-                    const int r = lr + 8 * q;
-                    float4 va = make_float4(0.f, 0.f, 0.f, 0.f), ve = va;
-                    if (at + r < na && col < dp)
-                        va = *(const float4 *)(pool32 + (arow0 + pa_perm[at + r]) * dp + col);
-                    if (et + r < ne && col < dp)
-                        ve = *(const float4 *)(pool32 + (c == 0 ? erow0 : erow0 + pe_perm[et + r]) * dp + col);
-                    float *da = sa + r * kGLd + lc, *de = se + r * kGLd + lc;
-                    da[0] = va.x; da[1] = va.y; da[2] = va.z; da[3] = va.w;
-                    de[0] = ve.x; de[1] = ve.y; de[2] = ve.z; de[3] = ve.w;
-                }
-                __syncthreads();
-                // coordinates past d (or past dp) are zero in LDS: whole chunks are safe
-#pragma unroll 4
-                for (int t = 0; t < kGK; ++t) {
-                    KT av[3], ev[3];
-#pragma unroll
-                    for (int u = 0; u < 3; ++u) {
-                        av[u] = (KT)sa[(ty + 16 * u) * kGLd + t];
-                        ev[u] = (KT)se[(tx + 16 * u) * kGLd + t];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 3; ++u)
-#pragma unroll
-                        for (int v = 0; v < 3; ++v)
-                            gram_term<KIND, KT>(sv[u][v], av[u], ev[v]);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 3; ++u)
-#pragma unroll
-                for (int v = 0; v < 3; ++v)
-                    if (at + ty + 16 * u < na && et + tx + 16 * v < ne)
-                        acc += (double)gram_finish<KIND, KT>(sv[u][v], prm);
-        }
-    }
-    red[tid] = acc;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (tid < h)
-            red[tid] += red[tid + h];
-        __syncthreads();
-    }
-    if (tid == 0) {
-        double *g = G + (int64_t)j * C * C;
-        g[(1 + rr) * C + c] = red[0];
-        g[c * C + 1 + rr] = red[0];
-    }
-}
-
-template <typename KT>
-static void launch_gram_t(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param,
-                          hipStream_t st)
-{
-    dim3 grid(L.k, L.C);
-#define MBKK_GRAM(K)                                                                                             \
-    hipLaunchKernelGGL((k_gram<K, KT>), grid, dim3(256), 0, st, L.k, L.C, L.bmax, L.d, L.dp, param, rr, col_mask, \
-                       B.ring_off, B.ring_perm, B.pool32, B.G)
-    switch (kind) {
-    case MBKK_GAUSS: MBKK_GRAM(MBKK_GAUSS); break;
-    case MBKK_LAPLACE: MBKK_GRAM(MBKK_LAPLACE); break;
-    case MBKK_LINEAR: MBKK_GRAM(MBKK_LINEAR); break;
-    default: MBKK_GRAM(MBKK_POLY2); break;
-    }
-#undef MBKK_GRAM
-}
-
-void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param, int fp64,
-                 hipStream_t st)
-{
-    if (fp64)
-        launch_gram_t<double>(L, B, rr, col_mask, kind, param, st);
-    else
-        launch_gram_t<float>(L, B, rr, col_mask, kind, param, st);
 }
 
 }  // namespace mbkk

@@ -118,6 +118,8 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.coef = (double *)take(8 * (size_t)L.k * C);
     B.cum = (double *)take(8 * (size_t)L.k);
     B.G = (double *)take(8 * (size_t)L.k * C * C);
+    B.goff = (int32_t *)take(4 * ((size_t)L.k * C + 1));
+    B.gpart = (double *)take(8 * ((size_t)kGramWaves + (size_t)L.k * C));
     B.N = (double *)take(8 * (size_t)L.k);
     B.counts = (int32_t *)take(4 * (size_t)L.k);
     B.alpha = (double *)take(8 * (size_t)L.k);
@@ -130,7 +132,7 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.sup_ay = (float *)take(4 * L.Mcap);
     B.sup_w64 = (double *)take(8 * L.Mcap);
     B.blk_center = (int32_t *)take(4 * L.nblk);
-    size_t part_direct = (size_t)L.k * L.bmax * 8;  // FP64 worst case
+    size_t part_direct = (size_t)(L.k + kDirectWGs) * L.bmax * 8;  // runs of the direct kernel, FP64 worst case
     size_t part_mfma = (size_t)L.nblk * L.bmax * 4;
     B.part = take(part_direct > part_mfma ? part_direct : part_mfma);
     B.labels = (int32_t *)take(4 * (size_t)L.bmax);
@@ -235,13 +237,14 @@ static uint32_t col_mask_of(const SlotList &s, bool init_alive)
 }
 
 // Gram blocks of slot p against the live columns in `mask`: on MFMA with the
-// form's own arithmetic for the Gaussian MFMA forms (d <= 128), else VALU.
-static void gram(mbkk_ctx *c, int p, uint32_t mask)
+// form's own arithmetic for the Gaussian MFMA forms, else VALU.  `planned`:
+// the update kernel already wrote the task plan.
+static void gram(mbkk_ctx *c, int p, uint32_t mask, bool planned)
 {
-    if (c->use_mfma && c->L.dp <= 128)
-        launch_gram_mfma(c->L, c->B, p, mask, c->cfg.precision, c->cfg.kernel_param, c->stream);
-    else
-        launch_gram(c->L, c->B, p, mask, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->stream);
+    if (!planned)
+        launch_gram_plan(c->L, c->B, p, mask, c->use_mfma, c->stream);
+    launch_gram(c->L, c->B, p, mask, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->use_mfma, c->cfg.precision,
+                c->stream);
 }
 
 static int check_flags(mbkk_ctx *c)
@@ -502,10 +505,11 @@ int mbkk_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels_dev,
     const int init_keep = i <= W;
     const int p_new = phys_of(i, P);
     const int p_expired = i - W >= 1 ? phys_of(i - W, P) : -1;
-    launch_update(L, B, b, p_new, p_expired, init_alive_before, init_keep, live, c->cfg.lr, c->stream);
     const SlotList live_after = live_before(i + 1, W);
     const uint32_t mask = col_mask_of(live_after, init_keep);
-    gram(c, p_new, mask);
+    launch_update(L, B, b, p_new, p_expired, init_alive_before, init_keep, live, c->cfg.lr, mask, c->use_mfma,
+                  c->stream);
+    gram(c, p_new, mask, true);
     HIPCHK(c, hipGetLastError());
     c->slot_b[p_new] = b;
     c->iter = i + 1;
@@ -817,7 +821,7 @@ int mbkk_set_state(mbkk_ctx *c, const mbkk_state *s)
     // Gram blocks of every live slot against every live column
     for (int q = 0; q < live.n; ++q) {
         const int p = live.r[q];
-        gram(c, p, mask);
+        gram(c, p, mask, false);
     }
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));

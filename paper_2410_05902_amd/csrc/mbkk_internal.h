@@ -29,6 +29,8 @@ constexpr int kChunk = 64;        // batch rows per grouping chunk (one scoring 
 // batch-stationary MFMA cross kernel: workgroups per compute unit (waves per SIMD)
 constexpr int kBsOcc = 1;
 constexpr int kNumCU = 256;
+constexpr int kDirectWGs = 1024;  // workgroups of the direct (VALU) cross kernel: ranges x row tiles
+constexpr int kGramWaves = 2048;  // waves of the Gram work kernels (equal contiguous task ranges)
 
 // Physical slots of the live batches, oldest batch first.
 struct SlotList {
@@ -72,6 +74,8 @@ struct Buffers {
     double *coef = nullptr;       // [k * C], C = P + 1
     double *cum = nullptr;        // [k]
     double *G = nullptr;          // [k * C * C]
+    int32_t *goff = nullptr;      // [k * C + 1] task offsets of the Gram blocks being computed
+    double *gpart = nullptr;      // [kGramWaves + k * C] their per-run partial sums
     double *N = nullptr;          // [k]
     int32_t *counts = nullptr;    // [k]
     double *alpha = nullptr;      // [k]
