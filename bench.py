@@ -125,7 +125,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the hot path is measured on one GPU's "
-              "share (see DESIGN.md for how it would shard); --gpus must be 1.", file=sys.stderr)
+              "share of the work; --gpus must be 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
