@@ -40,7 +40,7 @@ __device__ __forceinline__ T kval_direct(const T (&x)[DR], const float *__restri
     }
     if constexpr (KIND == MBKK_GAUSS || KIND == MBKK_LAPLACE) {
         if constexpr (sizeof(T) == 4)
-            return exp2f(s * cneg);  // cneg = -log2(e) / bandwidth
+            return __builtin_amdgcn_exp2f(s * cneg);  // cneg = -log2(e) / bandwidth
         else
             return exp(-s / param);
     } else if constexpr (KIND == MBKK_LINEAR) {
@@ -58,9 +58,24 @@ __device__ __forceinline__ T kval_direct(const T (&x)[DR], const float *__restri
 // the run that starts at the start of range r inside a center.
 __device__ __forceinline__ int direct_range_rows(int M, int nranges) { return (M + nranges - 1) / nranges; }
 
-// Register-resident batch row (DR >= d, one per lane), support rows of the
-// workgroup's range read with wave-uniform addresses.  Grid: (row tiles of
-// 256) x (ranges).
+// Broadcast of lane e's value to the wave (e wave-uniform).
+__device__ __forceinline__ float wave_bcast(float v, int e)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), e));
+}
+__device__ __forceinline__ double wave_bcast(double v, int e)
+{
+    const int64_t b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), e);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), e);
+    return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
+// Register-resident batch row (DR >= d, one per lane).  The workgroup's range
+// of support entries is taken 64 at a time: lane e of every wave loads entry
+// c0 + e's pool row and weight (one coalesced load), and the entries are then
+// broadcast one by one, their rows read with wave-uniform (scalar) loads.
+// A run ends where a center's segment ends.  Grid: (row tiles of 256) x (ranges).
 template <int KIND, typename T, int DR>
 __global__ __launch_bounds__(256) void k_cross_direct(int nb, int d, int dp, int k, int nranges,
                                                        const float *__restrict__ bat32,
@@ -71,6 +86,7 @@ __global__ __launch_bounds__(256) void k_cross_direct(int nb, int d, int dp, int
                                                        const int32_t *__restrict__ seg_off, double param,
                                                        T *__restrict__ P, int ldp)
 {
+    const int lane = threadIdx.x & 63;
     const int row = blockIdx.x * 256 + threadIdx.x;
     const int rr = row < nb ? row : 0;
     const int r = blockIdx.y;
@@ -88,16 +104,33 @@ __global__ __launch_bounds__(256) void k_cross_direct(int nb, int d, int dp, int
         for (int t = 0; t < DR; ++t)
             x[t] = t < d ? (T)bat32[(int64_t)rr * dp + t] : (T)0;
     }
+    // the run being accumulated: center j up to cur_end, stored at id
     int j = wave_segment_of(seg_off, k, s0);
-    int s = s0;
-    while (s < s1) {  // wave-uniform: one run per center overlapping the range
-        const int cs = seg_off[j];
-        const int e = min(s1, seg_off[j + 1]);
-        const int id = s == cs ? j : k + r;
-        const bool nonempty = s < e;
-        T acc = 0;
-        for (; s < e; ++s) {
-            const float *y = pool32 + (int64_t)sup_row[s] * dp;
+    int cur_end = min(s1, seg_off[j + 1]);
+    int id = s0 == seg_off[j] ? j : k + r;
+    T acc = 0;
+    for (int c0 = s0; c0 < s1; c0 += 64) {
+        const int n = min(64, s1 - c0);
+        const int lrow = sup_row[c0 + (lane < n ? lane : 0)];
+        T lw;
+        if constexpr (sizeof(T) == 4)
+            lw = lane < n ? sup_w[c0 + lane] : 0.0f;
+        else
+            lw = lane < n ? sup_w64[c0 + lane] : 0.0;
+        for (int e = 0; e < n; ++e) {  // wave uniform
+            const int s = c0 + e;
+            if (s >= cur_end) {  // the run [.., cur_end) had entries: store it, move to s's center
+                if (row < nb)
+                    P[(int64_t)id * ldp + row] = acc;
+                do {
+                    ++j;
+                } while (seg_off[j + 1] <= s);
+                cur_end = min(s1, seg_off[j + 1]);
+                id = j;
+                acc = 0;
+            }
+            const float *y = pool32 + (int64_t)__builtin_amdgcn_readlane(lrow, e) * dp;
+            const T w = wave_bcast(lw, e);
             T kv;
             if constexpr (DR > 0) {
                 kv = kval_direct<KIND, T, DR>(x, y, cneg, prm);
@@ -118,7 +151,7 @@ __global__ __launch_bounds__(256) void k_cross_direct(int nb, int d, int dp, int
                 }
                 if constexpr (KIND == MBKK_GAUSS || KIND == MBKK_LAPLACE) {
                     if constexpr (sizeof(T) == 4)
-                        kv = exp2f(sacc * cneg);
+                        kv = __builtin_amdgcn_exp2f(sacc * cneg);
                     else
                         kv = exp(-sacc / prm);
                 } else if constexpr (KIND == MBKK_LINEAR) {
@@ -128,15 +161,11 @@ __global__ __launch_bounds__(256) void k_cross_direct(int nb, int d, int dp, int
                     kv = u * u;
                 }
             }
-            if constexpr (sizeof(T) == 4)
-                acc = fma(sup_w[s], kv, acc);
-            else
-                acc = fma(sup_w64[s], kv, acc);
+            acc = fma(w, kv, acc);
         }
-        if (nonempty && row < nb)
-            P[(int64_t)id * ldp + row] = acc;
-        ++j;
     }
+    if (row < nb)
+        P[(int64_t)id * ldp + row] = acc;  // the last run (s0 < s1: it has entries)
 }
 
 template <int KIND, typename T>

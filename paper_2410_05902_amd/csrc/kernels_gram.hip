@@ -265,8 +265,19 @@ __global__ __launch_bounds__(256) void k_gram_fold(int k, int C, int rr, uint32_
         const int T = goff[k * C];
         const int chunk = (T + kGramWaves - 1) / kGramWaves;
         const int w0 = g0 / chunk, w1 = (g1 - 1) / chunk;
-        for (int w = w0 + lane; w <= w1; w += 64)
-            s += gpart[w + jc];
+        // lane-strided over the runs with 8 independent partial sums (loads in
+        // flight together), combined in a fixed order
+        const double *gp = gpart + jc;
+        double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int w = w0 + lane;
+        for (; w + 7 * 64 <= w1; w += 8 * 64) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                q[u] += gp[w + u * 64];
+        }
+        for (; w <= w1; w += 64)
+            q[0] += gp[w];
+        s = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
         for (int o = 32; o > 0; o >>= 1)
             s += __shfl_xor(s, o);
     }

@@ -29,8 +29,8 @@ constexpr int kChunk = 64;        // batch rows per grouping chunk (one scoring 
 // batch-stationary MFMA cross kernel: workgroups per compute unit (waves per SIMD)
 constexpr int kBsOcc = 1;
 constexpr int kNumCU = 256;
-constexpr int kDirectWGs = 1024;  // workgroups of the direct (VALU) cross kernel: ranges x row tiles
-constexpr int kGramWaves = 2048;  // waves of the Gram work kernels (equal contiguous task ranges)
+constexpr int kDirectWGs = 2048;  // workgroups of the direct (VALU) cross kernel: ranges x row tiles (8 waves per SIMD)
+constexpr int kGramWaves = 5120;  // waves of the Gram work kernels (equal contiguous task ranges; 5 per SIMD)
 
 // Physical slots of the live batches, oldest batch first.
 struct SlotList {
