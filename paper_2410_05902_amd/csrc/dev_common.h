@@ -170,4 +170,35 @@ __device__ __forceinline__ void gram_plan(int k, int C, int rr, uint32_t mask, i
         goff[(int64_t)k * C] = total;
 }
 
+// Block (j, c) of the Gram work just done (jc = j * C + c, njc = k * C): the
+// partials of the waves whose task ranges met jc (stored at gpart[w + jc]),
+// lane-strided with eight independent sums, then across the wave; every lane
+// returns the sum.  One fixed order, wherever the fold runs.
+__device__ __forceinline__ double gram_fold_jc(const int32_t *__restrict__ goff, const double *__restrict__ gpart,
+                                               int njc, int jc)
+{
+    const int lane = threadIdx.x & 63;
+    const int g0 = goff[jc], g1 = goff[jc + 1];
+    double s = 0.0;
+    if (g1 > g0) {
+        const int T = goff[njc];
+        const int chunk = (T + kGramWaves - 1) / kGramWaves;
+        const int w0 = g0 / chunk, w1 = (g1 - 1) / chunk;
+        const double *gp = gpart + jc;
+        double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        int w = w0 + lane;
+        for (; w + 7 * 64 <= w1; w += 8 * 64) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                q[u] += gp[w + u * 64];
+        }
+        for (; w <= w1; w += 64)
+            q[0] += gp[w];
+        s = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
+        for (int o = 32; o > 0; o >>= 1)
+            s += __shfl_xor(s, o);
+    }
+    return s;
+}
+
 }  // namespace mbkk

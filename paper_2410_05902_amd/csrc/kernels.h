@@ -12,8 +12,11 @@ void launch_gather_rows(const float *X, int64_t n, int d, int64_t ld, const int3
                         hipStream_t st);
 void launch_init_state(const Layout &L, const Buffers &B, int kind, double param, int fp64, int set_coef,
                        hipStream_t st);
+// fold_rr >= 0: the Gram work of slot fold_rr against fold_mask is folded
+// into G by the support layout (before the self norms use it).
 void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const SlotList &live, int init_alive,
-                    const int32_t *idx, int64_t cnt, int check_finite, float ay_scale, hipStream_t st);
+                    const int32_t *idx, int64_t cnt, int check_finite, float ay_scale, int fold_rr,
+                    uint32_t fold_mask, hipStream_t st);
 // The update also writes the task plan of the new slot's Gram blocks against
 // the columns in gram_mask (for the Gram form chosen by gram_mfma).
 void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
@@ -25,7 +28,8 @@ void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_ex
 int gram_task_cols(int mfma);
 void launch_gram_plan(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int mfma, hipStream_t st);
 void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param, int fp64,
-                 int mfma, int precision, hipStream_t st);
+                 int mfma, int precision, bool fold, hipStream_t st);
+void launch_gram_fold(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, hipStream_t st);
 
 // Cross term P = <phi(x), C_j> for the staged batch rows [0, nb).
 void launch_cross_direct(const Layout &L, const Buffers &B, int nb, int kind, double param, int fp64,

@@ -246,8 +246,8 @@ __global__ __launch_bounds__(1024) void k_gram_plan(int k, int C, int rr, uint32
     gram_plan(k, C, rr, mask, te, ring_off, nullptr, goff, sint);
 }
 
-// One wave per jc: the partials of the waves whose ranges met jc, summed
-// lane-strided and then across the wave (a fixed order).
+// One wave per jc (gram_fold_jc).  In a step the fold runs instead inside
+// the next support layout (k_prepare), with the same summation.
 __global__ __launch_bounds__(256) void k_gram_fold(int k, int C, int rr, uint32_t mask,
                                                    const int32_t *__restrict__ goff,
                                                    const double *__restrict__ gpart, double *__restrict__ G)
@@ -259,28 +259,7 @@ __global__ __launch_bounds__(256) void k_gram_fold(int k, int C, int rr, uint32_
     const int j = jc / C, c = jc - j * C;
     if (!((mask >> c) & 1u))
         return;
-    const int g0 = goff[jc], g1 = goff[jc + 1];
-    double s = 0.0;
-    if (g1 > g0) {
-        const int T = goff[k * C];
-        const int chunk = (T + kGramWaves - 1) / kGramWaves;
-        const int w0 = g0 / chunk, w1 = (g1 - 1) / chunk;
-        // lane-strided over the runs with 8 independent partial sums (loads in
-        // flight together), combined in a fixed order
-        const double *gp = gpart + jc;
-        double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        int w = w0 + lane;
-        for (; w + 7 * 64 <= w1; w += 8 * 64) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                q[u] += gp[w + u * 64];
-        }
-        for (; w <= w1; w += 64)
-            q[0] += gp[w];
-        s = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
-        for (int o = 32; o > 0; o >>= 1)
-            s += __shfl_xor(s, o);
-    }
+    const double s = gram_fold_jc(goff, gpart, k * C, jc);
     if (lane == 0) {
         double *g = G + (int64_t)j * C * C;
         g[(1 + rr) * C + c] = s;
@@ -334,7 +313,7 @@ static void launch_gram_mfma(const Layout &L, const Buffers &B, const GramWork &
 }
 
 void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t mask, int kind, double param, int fp64,
-                 int mfma, int precision, hipStream_t st)
+                 int mfma, int precision, bool fold, hipStream_t st)
 {
     GramWork A;
     A.k = L.k;
@@ -357,6 +336,12 @@ void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t mask, int k
     } else {
         launch_gram_valu<float>(L, B, A, kind, param, st);
     }
+    if (fold)
+        launch_gram_fold(L, B, rr, mask, st);
+}
+
+void launch_gram_fold(const Layout &L, const Buffers &B, int rr, uint32_t mask, hipStream_t st)
+{
     const int njc = L.k * L.C;
     hipLaunchKernelGGL(k_gram_fold, dim3((njc + 3) / 4), dim3(256), 0, st, L.k, L.C, rr, mask, B.goff, B.gpart,
                        B.G);

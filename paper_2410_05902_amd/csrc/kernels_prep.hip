@@ -206,7 +206,12 @@ struct SupportArgs {
     const int32_t *ring_off, *ring_perm;
     SlotList live;
     int init_alive;
-    const double *coef, *G;
+    const double *coef;
+    double *G;
+    int fold_rr;          // >= 0: fold the Gram work of this slot into G first
+    uint32_t fold_mask;
+    const int32_t *goff;
+    const double *gpart;
     int32_t *seg_off, *sup_row;
     float *sup_w;
     double *sup_w64;
@@ -226,7 +231,7 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
     const SlotList &live = A.live;
     const int init_alive = A.init_alive;
     const double *__restrict__ coef = A.coef;
-    const double *__restrict__ G = A.G;
+    double *__restrict__ G = A.G;
     int32_t *__restrict__ seg_off = A.seg_off;
     int32_t *__restrict__ sup_row = A.sup_row;
     float *__restrict__ sup_w = A.sup_w;
@@ -239,6 +244,21 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
     __shared__ int red[256];
     __shared__ int sh_start;
     const int tid = threadIdx.x;
+    // Gram blocks of the last update's slot: one wave per column (the
+    // barriers of the prefix below publish them to the self norm)
+    if (A.fold_rr >= 0) {
+        const int rr = A.fold_rr;
+        for (int c = tid >> 6; c < C; c += 4) {  // wave uniform
+            if ((A.fold_mask >> c) & 1u) {
+                const double g = gram_fold_jc(A.goff, A.gpart, k * C, j * C + c);
+                if ((tid & 63) == 0) {
+                    double *gj = G + (int64_t)j * C * C;
+                    gj[(1 + rr) * C + c] = g;
+                    gj[c * C + 1 + rr] = g;
+                }
+            }
+        }
+    }
     // exclusive prefix of the padded lengths of centers < j
     int acc = 0;
     for (int q = tid; q < j; q += 256) {
@@ -331,7 +351,8 @@ __global__ __launch_bounds__(256) void k_prepare(const SupportArgs S, int nsup, 
 }
 
 void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const SlotList &live, int init_alive,
-                    const int32_t *idx, int64_t cnt, int check_finite, float ay_scale, hipStream_t st)
+                    const int32_t *idx, int64_t cnt, int check_finite, float ay_scale, int fold_rr,
+                    uint32_t fold_mask, hipStream_t st)
 {
     SupportArgs S;
     S.k = L.k;
@@ -345,6 +366,10 @@ void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const 
     S.init_alive = init_alive;
     S.coef = B.coef;
     S.G = B.G;
+    S.fold_rr = with_support ? fold_rr : -1;
+    S.fold_mask = fold_mask;
+    S.goff = B.goff;
+    S.gpart = B.gpart;
     S.seg_off = B.seg_off;
     S.sup_row = B.sup_row;
     S.sup_w = B.sup_w;
@@ -465,6 +490,183 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
     }
 }
 
+// Variant for k <= kGroupSmallK, nchunk * k <= kGroupLdsMax and C <= kGroupSmallC
+// (each thread owns at most one center): every global load that does not
+// depend on a result of this kernel is issued at its start (the rows' labels,
+// ranks, points and distances, the center's coefficient row and the ring
+// offsets the Gram plan needs), so the phases below wait on LDS only.  The
+// chunk sums of the counts are split over kGroupThreads / k slices of chunks.
+constexpr int kGroupSmallK = 512, kGroupSmallC = 8, kGroupThreads = 1024;
+
+__global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
+    int b, int k, int nchunk, int C, int p_new, int p_expired, int init_alive_before, int init_keep,
+    SlotList live, int lr, const int32_t *__restrict__ gcnt, const float *__restrict__ mind,
+    double *__restrict__ coef, double *__restrict__ cum, int32_t *__restrict__ counts,
+    double *__restrict__ alpha, int32_t *__restrict__ off, double *__restrict__ obj,
+    const int32_t *__restrict__ labels, const int32_t *__restrict__ rank, const int32_t *__restrict__ pts,
+    int32_t *__restrict__ ring_idx, int32_t *__restrict__ ring_perm, uint32_t gram_mask, int gram_te,
+    const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff)
+{
+    constexpr int RPT = kMaxBatch / kGroupThreads;  // batch rows per thread
+    __shared__ int sint[16];
+    __shared__ double sdbl[16];
+    __shared__ int scnt[kGroupLdsMax];    // per-(chunk, label) counts, then bases
+    __shared__ int spart[kGroupThreads];  // per-(slice, label) sums, then slice starts
+    __shared__ int soff[kGroupSmallK];
+    const int tid = threadIdx.x, nt = kGroupThreads;
+    // ---- independent loads
+    int r_lab[RPT], r_rank[RPT], r_pt[RPT];
+    float r_md[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int p = tid + i * nt;
+        const bool in = p < b;
+        r_lab[i] = in ? labels[p] : 0;
+        r_rank[i] = in ? rank[p] : 0;
+        r_pt[i] = in ? pts[p] : 0;
+        r_md[i] = in ? mind[p] : 0.0f;
+    }
+    const bool own = tid < k;
+    const int j = tid;
+    double cf[kGroupSmallC];
+    int ne[kGroupSmallC];  // rows of center j in column c (other slots than the new one)
+#pragma unroll
+    for (int c = 0; c < kGroupSmallC; ++c) {
+        cf[c] = own && c < C ? coef[(int64_t)j * C + c] : 0.0;
+        ne[c] = 0;
+        if (own && c >= 1 && c < C && c - 1 != p_new && ((gram_mask >> c) & 1u)) {
+            const int32_t *o = ring_off + (int64_t)(c - 1) * (k + 1);
+            ne[c] = o[j + 1] - o[j];
+        }
+    }
+    const double cumj = own && lr == MBKK_LR_SKLEARN ? cum[j] : 0.0;
+    for (int i = tid; i < nchunk * k; i += nt)
+        scnt[i] = gcnt[i];
+    __syncthreads();
+    // ---- label totals: slice sums over chunks, then per label over slices
+    const int TG = nt / k;  // >= 2
+    const int gs = (nchunk + TG - 1) / TG;
+    if (tid < TG * k) {
+        const int jj = tid % k, sl = tid / k;
+        const int g1 = min(nchunk, (sl + 1) * gs);
+        int sum = 0;
+        for (int g = sl * gs; g < g1; ++g)
+            sum += scnt[g * k + jj];
+        spart[sl * k + jj] = sum;
+    }
+    __syncthreads();
+    int bj = 0;
+    if (own) {
+        for (int sl = 0; sl < TG; ++sl) {
+            const int v = spart[sl * k + j];
+            spart[sl * k + j] = bj;  // start of slice sl within label j
+            bj += v;
+        }
+    }
+    int total;
+    const int offj = block_exclusive_scan(own ? bj : 0, sint, &total);
+    if (own) {
+        soff[j] = offj;
+        off[j] = offj;
+        counts[j] = bj;
+    }
+    if (tid == 0)
+        off[k] = b;
+    __syncthreads();
+    // ---- bases of (chunk, label), in place of the counts
+    if (tid < TG * k) {
+        const int jj = tid % k, sl = tid / k;
+        const int g1 = min(nchunk, (sl + 1) * gs);
+        int gb = soff[jj] + spart[sl * k + jj];
+        for (int g = sl * gs; g < g1; ++g) {
+            const int v = scnt[g * k + jj];
+            scnt[g * k + jj] = gb;
+            gb += v;
+        }
+    }
+    // ---- learning rate and the coefficient update of center j
+    int tasks = 0;
+    if (own) {
+        double a;
+        if (lr == MBKK_LR_FULL)
+            a = bj > 0 ? 1.0 : 0.0;
+        else if (lr == MBKK_LR_SKLEARN) {
+            const double cs = cumj + (double)bj;
+            cum[j] = cs;
+            a = bj > 0 ? (double)bj / cs : 0.0;
+        } else
+            a = sqrt((double)bj / (double)b);
+        alpha[j] = a;
+        uint32_t livem = 0;
+        for (int q = 0; q < live.n; ++q)
+            livem |= 1u << live.r[q];
+        // C_{i+1} = (1 - a) C_i + a cm(B_i^j), truncated to the window
+#pragma unroll
+        for (int c = 0; c < kGroupSmallC; ++c) {
+            if (c >= C)
+                break;
+            double v = cf[c];
+            if (c == 0) {
+                if (init_alive_before)
+                    v *= (1.0 - a);
+                if (!init_keep)
+                    v = 0.0;
+            } else {
+                const int p = c - 1;
+                if ((livem >> p) & 1u)
+                    v *= (1.0 - a);
+                if (p == p_new)
+                    v = bj > 0 ? a / (double)bj : 0.0;
+                if (p == p_expired)
+                    v = 0.0;
+            }
+            coef[(int64_t)j * C + c] = v;
+        }
+        // Gram tasks of the new slot against the live columns
+        const int nA = (bj + kGramTA - 1) / kGramTA;
+#pragma unroll
+        for (int c = 0; c < kGroupSmallC; ++c) {
+            if (c < C && ((gram_mask >> c) & 1u)) {
+                const int nec = c == 0 ? 1 : (c - 1 == p_new ? bj : ne[c]);
+                tasks += nA * ((nec + gram_te - 1) / gram_te);
+            }
+        }
+    }
+    int ttotal;
+    int trun = block_exclusive_scan(tasks, sint, &ttotal);  // (its barriers also publish the bases)
+    if (own) {
+        const int nA = (bj + kGramTA - 1) / kGramTA;
+        for (int c = 0; c < C; ++c) {
+            goff[(int64_t)j * C + c] = trun;
+            if ((gram_mask >> c) & 1u) {
+                const int nec = c == 0 ? 1 : (c - 1 == p_new ? bj : ne[c]);
+                trun += nA * ((nec + gram_te - 1) / gram_te);
+            }
+        }
+    }
+    if (tid == 0)
+        goff[(int64_t)k * C] = ttotal;
+    // ---- sum of min distances (FP64), in the order of the general variant
+    double sm = 0.0;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+        sm += (double)r_md[i];
+    sm = block_sum(sm, sdbl);
+    if (tid == 0)
+        obj[0] = sm;
+    // ---- scatter: grouped position of every row = base of (chunk, label) + rank
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int p = tid + i * nt;
+        if (p < b) {
+            const int lab = min(max(r_lab[i], 0), k - 1);
+            const int pos = scnt[(p / kChunk) * k + lab] + r_rank[i];
+            ring_perm[pos] = p;
+            ring_idx[pos] = r_pt[i];
+        }
+    }
+}
+
 void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
                    int init_keep, const SlotList &live, int lr, uint32_t gram_mask, int gram_mfma, hipStream_t st)
 {
@@ -476,7 +678,13 @@ void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_ex
                        B.alpha, B.ring_off + (int64_t)p_new * (L.k + 1), B.obj, B.labels, B.rank,                 \
                        B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,               \
                        B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_te, B.ring_off, B.goff)
-    if ((int64_t)nchunk * L.k <= kGroupLdsMax)
+    if (L.k <= kGroupSmallK && (int64_t)nchunk * L.k <= kGroupLdsMax && L.C <= kGroupSmallC)
+        hipLaunchKernelGGL(k_group_offsets_small, dim3(1), dim3(kGroupThreads), 0, st, b, L.k, nchunk, L.C, p_new,
+                           p_expired, init_alive_before, init_keep, live, lr, B.gcnt, B.mind, B.coef, B.cum,
+                           B.counts, B.alpha, B.ring_off + (int64_t)p_new * (L.k + 1), B.obj, B.labels, B.rank,
+                           B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,
+                           B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_te, B.ring_off, B.goff);
+    else if ((int64_t)nchunk * L.k <= kGroupLdsMax)
         MBKK_GO(true);
     else
         MBKK_GO(false);

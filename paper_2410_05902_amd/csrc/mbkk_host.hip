@@ -25,6 +25,10 @@ struct mbkk_ctx {
     bool inited = false;
     int64_t iter = 1;           // index i of the next batch
     int64_t support_iter = -1;  // iteration for which the support layout is built
+    // Gram work of the last step whose fold into G is left to the next support
+    // layout (slot, column mask); fold_rr < 0: none pending
+    int fold_rr = -1;
+    uint32_t fold_mask = 0;
     std::vector<int32_t> slot_b;  // points held by each physical slot
     // timing of the cross-term kernel
     bool timing = false;
@@ -237,14 +241,28 @@ static uint32_t col_mask_of(const SlotList &s, bool init_alive)
 }
 
 // Gram blocks of slot p against the live columns in `mask`: on MFMA with the
-// form's own arithmetic for the Gaussian MFMA forms, else VALU.  `planned`:
-// the update kernel already wrote the task plan.
-static void gram(mbkk_ctx *c, int p, uint32_t mask, bool planned)
+// form's own arithmetic for the Gaussian MFMA forms, else VALU.  In a step
+// (`in_step`) the update kernel already wrote the task plan and the fold is
+// left to the next support layout; elsewhere plan, work and fold run here.
+static void gram(mbkk_ctx *c, int p, uint32_t mask, bool in_step)
 {
-    if (!planned)
+    if (!in_step)
         launch_gram_plan(c->L, c->B, p, mask, c->use_mfma, c->stream);
     launch_gram(c->L, c->B, p, mask, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->use_mfma, c->cfg.precision,
-                c->stream);
+                !in_step, c->stream);
+    if (in_step) {
+        c->fold_rr = p;
+        c->fold_mask = mask;
+    }
+}
+
+// Hands the pending fold to the caller's support layout (or runs it alone).
+static int take_fold(mbkk_ctx *c, uint32_t *mask)
+{
+    const int rr = c->fold_rr;
+    *mask = c->fold_mask;
+    c->fold_rr = -1;
+    return rr;
 }
 
 static int check_flags(mbkk_ctx *c)
@@ -291,7 +309,12 @@ static void prepare(mbkk_ctx *c, const int32_t *idx, int64_t cnt)
     const SlotList live = live_before(c->iter, L.W);
     const int init_alive = c->iter <= L.W + 1;
     const float ay_scale = (float)(-1.4426950408889634 / c->cfg.kernel_param);
-    launch_prepare(L, c->B, need, live, init_alive, idx, cnt, c->cfg.validate, ay_scale, c->stream);
+    int fold_rr = -1;
+    uint32_t fold_mask = 0;
+    if (need)
+        fold_rr = take_fold(c, &fold_mask);
+    launch_prepare(L, c->B, need, live, init_alive, idx, cnt, c->cfg.validate, ay_scale, fold_rr, fold_mask,
+                   c->stream);
     if (need)
         c->support_iter = c->iter;
 }
@@ -436,6 +459,7 @@ static int init_common(mbkk_ctx *c, const int32_t *idx_dev)
     HIPCHK(c, hipGetLastError());
     c->iter = 1;
     c->support_iter = -1;
+    c->fold_rr = -1;
     std::fill(c->slot_b.begin(), c->slot_b.end(), 0);
     if (c->cfg.validate) {
         int rc = check_flags(c);
@@ -616,7 +640,10 @@ static void support_at_sigma(mbkk_ctx *c, double sigma)
     const double kappa = 2.0 * sigma * sigma;
     const SlotList live = live_before(c->iter, L.W);
     const int init_alive = c->iter <= L.W + 1;
-    launch_prepare(L, c->B, true, live, init_alive, nullptr, 0, 0, (float)(-1.4426950408889634 / kappa), c->stream);
+    uint32_t fold_mask = 0;
+    const int fold_rr = take_fold(c, &fold_mask);
+    launch_prepare(L, c->B, true, live, init_alive, nullptr, 0, 0, (float)(-1.4426950408889634 / kappa), fold_rr,
+                   fold_mask, c->stream);
     c->support_iter = -1;
     launch_selfnorm_sigma(L, c->B, sigma, c->B.Nsig, c->B.dNsig, c->stream);
 }
@@ -805,7 +832,9 @@ int mbkk_set_state(mbkk_ctx *c, const mbkk_state *s)
     HIPCHK(c, hipMemcpyAsync(B.coef, coef.data(), 8 * coef.size(), hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(B.cum, s->cum, 8 * (size_t)L.k, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(B.picks, s->init_idx, 4 * (size_t)L.k, hipMemcpyHostToDevice, c->stream));
-    // initial points, G reset with G[j][0][0] = K(x_j, x_j)
+    // initial points, G reset with G[j][0][0] = K(x_j, x_j); a fold left by a
+    // step of the replaced state is dropped
+    c->fold_rr = -1;
     launch_gather_rows(B.X, L.n, L.d, B.ld, B.picks, L.k, L.dp, B.pool32, L.bf16 ? B.poolhi : nullptr,
                        L.bf16 ? B.poollo : nullptr, B.poolsq, B.poolsq64, B.init_idx, B.flags, 0, c->stream);
     launch_init_state(L, B, c->cfg.kernel, c->cfg.kernel_param, c->fp64, 0, c->stream);
