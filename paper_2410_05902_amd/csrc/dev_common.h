@@ -129,33 +129,55 @@ __device__ __forceinline__ int64_t gram_row(const GramCol &g, int q) { return g.
 // the centers [t * per, (t + 1) * per), per = ceil(k / blockDim.x); na_own,
 // if given, holds the row counts of slot rr for those centers (written by the
 // same threads), else they come from ring_off of slot rr.  `sint`: 16 ints of LDS.
+// With seg_next, the same pass also writes the segment offsets of the support
+// whose columns are `mask` (each center's rows over those columns, padded to
+// a multiple of pad): the layout of the next iteration when mask holds its
+// live columns.
 __device__ __forceinline__ void gram_plan(int k, int C, int rr, uint32_t mask, int te,
                                           const int32_t *__restrict__ ring_off, const int32_t *na_own,
-                                          int32_t *__restrict__ goff, int *sint)
+                                          int32_t *__restrict__ goff, int *sint, int pad = 1,
+                                          int32_t *__restrict__ seg_next = nullptr)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int per = (k + nt - 1) / nt;
     const int j0 = min(k, tid * per), j1 = min(k, j0 + per);
     const int32_t *orr = ring_off + (int64_t)rr * (k + 1);
-    auto tasks = [&](int j, int c, int na) -> int {
+    auto rows = [&](int j, int c, int na) -> int {  // rows of center j in live column c
         if (!((mask >> c) & 1u))
             return 0;
-        int ne;
         if (c == 0)
-            ne = 1;
-        else if (c - 1 == rr)
-            ne = na;
-        else {
-            const int32_t *o = ring_off + (int64_t)(c - 1) * (k + 1);
-            ne = o[j + 1] - o[j];
-        }
-        return ((na + kGramTA - 1) / kGramTA) * ((ne + te - 1) / te);
+            return 1;
+        if (c - 1 == rr)
+            return na;
+        const int32_t *o = ring_off + (int64_t)(c - 1) * (k + 1);
+        return o[j + 1] - o[j];
     };
-    int local = 0;
+    auto tasks = [&](int j, int c, int na) -> int {
+        return ((na + kGramTA - 1) / kGramTA) * ((rows(j, c, na) + te - 1) / te);
+    };
+    int local = 0, slocal = 0;
     for (int j = j0; j < j1; ++j) {
         const int na = na_own ? na_own[j] : orr[j + 1] - orr[j];
-        for (int c = 0; c < C; ++c)
+        int len = 0;
+        for (int c = 0; c < C; ++c) {
             local += tasks(j, c, na);
+            len += rows(j, c, na);
+        }
+        slocal += (len + pad - 1) / pad * pad;
+    }
+    if (seg_next) {
+        int stotal;
+        int srun = block_exclusive_scan(slocal, sint, &stotal);
+        for (int j = j0; j < j1; ++j) {
+            const int na = na_own ? na_own[j] : orr[j + 1] - orr[j];
+            int len = 0;
+            for (int c = 0; c < C; ++c)
+                len += rows(j, c, na);
+            seg_next[j] = srun;
+            srun += (len + pad - 1) / pad * pad;
+        }
+        if (threadIdx.x == 0)
+            seg_next[k] = stotal;
     }
     int total;
     int run = block_exclusive_scan(local, sint, &total);

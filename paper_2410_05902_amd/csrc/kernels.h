@@ -13,12 +13,14 @@ void launch_gather_rows(const float *X, int64_t n, int d, int64_t ld, const int3
 void launch_init_state(const Layout &L, const Buffers &B, int kind, double param, int fp64, int set_coef,
                        hipStream_t st);
 // fold_rr >= 0: the Gram work of slot fold_rr against fold_mask is folded
-// into G by the support layout (before the self norms use it).
+// into G by the support layout (before the self norms use it).  seg_ready:
+// B.seg_next holds the segment offsets of this support (from the update).
 void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const SlotList &live, int init_alive,
                     const int32_t *idx, int64_t cnt, int check_finite, float ay_scale, int fold_rr,
-                    uint32_t fold_mask, hipStream_t st);
+                    uint32_t fold_mask, bool seg_ready, hipStream_t st);
 // The update also writes the task plan of the new slot's Gram blocks against
-// the columns in gram_mask (for the Gram form chosen by gram_mfma).
+// the columns in gram_mask (for the Gram form chosen by gram_mfma), and the
+// segment offsets of the support over those columns into B.seg_next.
 void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
                    int init_keep, const SlotList &live, int lr, uint32_t gram_mask, int gram_mfma, hipStream_t st);
 

@@ -1273,20 +1273,37 @@ __device__ void rescore_row(const ScoreArgs &A, int row, int RB, int &lab_io, fl
     margin_io = (float)(fmin(s64, outside) - b64);
 }
 
-template <typename T, int LAYOUT, bool RESCORE>
+// LK: the segment offsets and self norms are first copied to LDS (k <= kScoreLdsK).
+constexpr int kScoreLdsK = 2048;
+
+template <typename T, int LAYOUT, bool RESCORE, bool LK>
 __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
 {
     __shared__ double sb[kScoreWaves][64], ss[kScoreWaves][64];
     __shared__ int sl[kScoreWaves][64];
     __shared__ int flab[64];
     __shared__ float fmin_[64], fmar[64];
+    __shared__ int32_t lseg[LK ? kScoreLdsK + 1 : 1];
+    __shared__ double lN[LK ? kScoreLdsK : 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int row = blockIdx.x * 64 + lane;
     const bool act = row < A.nb;
     const T *part = (const T *)A.part;
-    const int RB = LAYOUT == 0 ? direct_range_rows(A.seg_off[A.k], A.nranges)
-                               : (A.nranges > 0 ? bs_range_blocks(A.seg_off[A.k] / 32, A.nranges) : A.RB);
     const double kxx = act ? self_kernel(A.kind, A.param, A.batsq64[row]) : 0.0;
+    const int32_t *seg_off = A.seg_off;
+    const double *Nv = A.N;
+    if constexpr (LK) {
+        for (int i = threadIdx.x; i <= A.k; i += 64 * kScoreWaves) {
+            lseg[i] = A.seg_off[i];
+            if (i < A.k)
+                lN[i] = A.N[i];
+        }
+        __syncthreads();
+        seg_off = lseg;
+        Nv = lN;
+    }
+    const int RB = LAYOUT == 0 ? direct_range_rows(seg_off[A.k], A.nranges)
+                               : (A.nranges > 0 ? bs_range_blocks(seg_off[A.k] / 32, A.nranges) : A.RB);
     double best = INFINITY, second = INFINITY;
     int lab = 0x7fffffff;
     if (act) {
@@ -1298,8 +1315,8 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
 #pragma unroll
             for (int u = 0; u < NB; ++u) {
                 const int j = j0 + u * kScoreWaves;
-                P[u] = j < A.k ? cross_of<T, LAYOUT>(part, A.ldp, row, j, A.seg_off, RB, A.k) : 0.0;
-                Nj[u] = j < A.k ? A.N[j] : 0.0;
+                P[u] = j < A.k ? cross_of<T, LAYOUT>(part, A.ldp, row, j, seg_off, RB, A.k) : 0.0;
+                Nj[u] = j < A.k ? Nv[j] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < NB; ++u) {
@@ -1368,22 +1385,25 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
         A.margin[row] = fmar[lane];
     }
     if (A.rank) {
+        // rank of row r among the rows t < r of the chunk with its label, and
+        // the chunk's count of that label (stored by the label's last row):
+        // one ballot per row, rows spread over the waves
         int32_t *cnt = A.gcnt + (int64_t)blockIdx.x * A.k;
         for (int j = threadIdx.x; j < A.k; j += 64 * kScoreWaves)
             cnt[j] = 0;
         __syncthreads();
-        if (w == 0 && act) {
-            const int L = flab[lane];
-            int r = 0, c = 0;
-            const int nrow = min(64, A.nb - blockIdx.x * 64);
-            for (int t = 0; t < nrow; ++t) {
-                const int eq = flab[t] == L;  // wave-uniform address: LDS broadcast
-                c += eq;
-                r += eq & (t < lane);
+        const int nrow = min(64, A.nb - blockIdx.x * 64);
+        const int Ll = lane < nrow ? flab[lane] : -1;
+        for (int r = w; r < nrow; r += kScoreWaves) {  // wave uniform
+            const int Lr = __builtin_amdgcn_readlane(Ll, r);
+            const uint64_t m = __ballot(Ll == Lr);
+            if (lane == 0) {
+                const int rk = __popcll(m & ((1ull << r) - 1ull));
+                const int c = __popcll(m);
+                A.rank[blockIdx.x * 64 + r] = rk;
+                if (rk == c - 1)
+                    cnt[Lr] = c;
             }
-            A.rank[row] = r;
-            if (r == c - 1)
-                cnt[L] = c;
         }
     }
 }
@@ -1420,14 +1440,22 @@ void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double pa
     A.gcnt = B.gcnt;
     const bool rescore = precision == MBKK_BF16X3 || precision == MBKK_BF16X1;
     dim3 grid((nb + 63) / 64), block(64 * kScoreWaves);
-    if (fp64)
-        hipLaunchKernelGGL((k_score<double, 0, false>), grid, block, 0, st, A);
-    else if (mfma && rescore)
-        hipLaunchKernelGGL((k_score<float, 1, true>), grid, block, 0, st, A);
-    else if (mfma)
-        hipLaunchKernelGGL((k_score<float, 1, false>), grid, block, 0, st, A);
+#define MBKK_SCORE(LK)                                                              \
+    do {                                                                            \
+        if (fp64)                                                                   \
+            hipLaunchKernelGGL((k_score<double, 0, false, LK>), grid, block, 0, st, A); \
+        else if (mfma && rescore)                                                   \
+            hipLaunchKernelGGL((k_score<float, 1, true, LK>), grid, block, 0, st, A);   \
+        else if (mfma)                                                              \
+            hipLaunchKernelGGL((k_score<float, 1, false, LK>), grid, block, 0, st, A);  \
+        else                                                                        \
+            hipLaunchKernelGGL((k_score<float, 0, false, LK>), grid, block, 0, st, A);  \
+    } while (0)
+    if (L.k <= kScoreLdsK)
+        MBKK_SCORE(true);
     else
-        hipLaunchKernelGGL((k_score<float, 0, false>), grid, block, 0, st, A);
+        MBKK_SCORE(false);
+#undef MBKK_SCORE
 }
 
 // Sum of min distances of rows [0, nb) in FP64 (fixed order); adds to obj[1]

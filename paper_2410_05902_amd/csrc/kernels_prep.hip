@@ -208,6 +208,7 @@ struct SupportArgs {
     int init_alive;
     const double *coef;
     double *G;
+    const int32_t *seg_next;  // non-null: segment offsets already computed by the update
     int fold_rr;          // >= 0: fold the Gram work of this slot into G first
     uint32_t fold_mask;
     const int32_t *goff;
@@ -259,29 +260,42 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
             }
         }
     }
-    // exclusive prefix of the padded lengths of centers < j
-    int acc = 0;
-    for (int q = tid; q < j; q += 256) {
-        const int l = seg_len(q, k, ring_off, live, init_alive);
-        acc += (l + pad - 1) / pad * pad;
-    }
-    red[tid] = acc;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s)
-            red[tid] += red[tid + s];
+    int start, plen;
+    if (A.seg_next) {
+        // offsets written by the last update for this support
+        start = A.seg_next[j];
+        plen = A.seg_next[j + 1] - start;
+        if (tid == 0) {
+            seg_off[j] = start;
+            if (j == k - 1)
+                seg_off[k] = start + plen;
+        }
         __syncthreads();
+    } else {
+        // exclusive prefix of the padded lengths of centers < j
+        int acc = 0;
+        for (int q = tid; q < j; q += 256) {
+            const int l = seg_len(q, k, ring_off, live, init_alive);
+            acc += (l + pad - 1) / pad * pad;
+        }
+        red[tid] = acc;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (tid < s)
+                red[tid] += red[tid + s];
+            __syncthreads();
+        }
+        const int len = seg_len(j, k, ring_off, live, init_alive);
+        plen = (len + pad - 1) / pad * pad;
+        if (tid == 0) {
+            sh_start = red[0];
+            seg_off[j] = red[0];
+            if (j == k - 1)
+                seg_off[k] = red[0] + plen;
+        }
+        __syncthreads();
+        start = sh_start;
     }
-    const int len = seg_len(j, k, ring_off, live, init_alive);
-    const int plen = (len + pad - 1) / pad * pad;
-    if (tid == 0) {
-        sh_start = red[0];
-        seg_off[j] = red[0];
-        if (j == k - 1)
-            seg_off[k] = red[0] + plen;
-    }
-    __syncthreads();
-    const int start = sh_start;
     int pos = start;
     if (init_alive) {
         if (tid == 0) {
@@ -352,7 +366,7 @@ __global__ __launch_bounds__(256) void k_prepare(const SupportArgs S, int nsup, 
 
 void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const SlotList &live, int init_alive,
                     const int32_t *idx, int64_t cnt, int check_finite, float ay_scale, int fold_rr,
-                    uint32_t fold_mask, hipStream_t st)
+                    uint32_t fold_mask, bool seg_ready, hipStream_t st)
 {
     SupportArgs S;
     S.k = L.k;
@@ -366,6 +380,7 @@ void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const 
     S.init_alive = init_alive;
     S.coef = B.coef;
     S.G = B.G;
+    S.seg_next = seg_ready ? B.seg_next : nullptr;
     S.fold_rr = with_support ? fold_rr : -1;
     S.fold_mask = fold_mask;
     S.goff = B.goff;
@@ -409,7 +424,7 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
     double *__restrict__ alpha, int32_t *__restrict__ off, double *__restrict__ obj,
     const int32_t *__restrict__ labels, const int32_t *__restrict__ rank, const int32_t *__restrict__ pts,
     int32_t *__restrict__ ring_idx, int32_t *__restrict__ ring_perm, uint32_t gram_mask, int gram_te,
-    const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff)
+    const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff, int pad, int32_t *__restrict__ seg_next)
 {
     __shared__ int sint[16];
     __shared__ double sdbl[16];
@@ -473,7 +488,7 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
         off[k] = b;
     // task offsets of the Gram blocks of the new slot (its counts are this
     // thread's b_i^j above; the other live slots' offsets are settled)
-    gram_plan(k, C, p_new, gram_mask, gram_te, ring_off, counts, goff, sint);
+    gram_plan(k, C, p_new, gram_mask, gram_te, ring_off, counts, goff, sint, pad, seg_next);
     // sum of min distances (FP64), fixed order
     double sm = 0.0;
     for (int p = tid; p < b; p += nt)
@@ -505,7 +520,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
     double *__restrict__ alpha, int32_t *__restrict__ off, double *__restrict__ obj,
     const int32_t *__restrict__ labels, const int32_t *__restrict__ rank, const int32_t *__restrict__ pts,
     int32_t *__restrict__ ring_idx, int32_t *__restrict__ ring_perm, uint32_t gram_mask, int gram_te,
-    const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff)
+    const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff, int pad, int32_t *__restrict__ seg_next)
 {
     constexpr int RPT = kMaxBatch / kGroupThreads;  // batch rows per thread
     __shared__ int sint[16];
@@ -585,7 +600,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
         }
     }
     // ---- learning rate and the coefficient update of center j
-    int tasks = 0;
+    int tasks = 0, slen = 0;
     if (own) {
         double a;
         if (lr == MBKK_LR_FULL)
@@ -622,16 +637,25 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
             }
             coef[(int64_t)j * C + c] = v;
         }
-        // Gram tasks of the new slot against the live columns
+        // Gram tasks of the new slot against the live columns, and the
+        // padded segment of center j in the next iteration's support
         const int nA = (bj + kGramTA - 1) / kGramTA;
 #pragma unroll
         for (int c = 0; c < kGroupSmallC; ++c) {
             if (c < C && ((gram_mask >> c) & 1u)) {
                 const int nec = c == 0 ? 1 : (c - 1 == p_new ? bj : ne[c]);
                 tasks += nA * ((nec + gram_te - 1) / gram_te);
+                slen += nec;
             }
         }
+        slen = (slen + pad - 1) / pad * pad;
     }
+    int stotal;
+    const int srun = block_exclusive_scan(slen, sint, &stotal);
+    if (own)
+        seg_next[j] = srun;
+    if (tid == 0)
+        seg_next[k] = stotal;
     int ttotal;
     int trun = block_exclusive_scan(tasks, sint, &ttotal);  // (its barriers also publish the bases)
     if (own) {
@@ -677,13 +701,15 @@ void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_ex
                        init_alive_before, init_keep, live, lr, B.gcnt, B.gbase, B.mind, B.coef, B.cum, B.counts, \
                        B.alpha, B.ring_off + (int64_t)p_new * (L.k + 1), B.obj, B.labels, B.rank,                 \
                        B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,               \
-                       B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_te, B.ring_off, B.goff)
+                       B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_te, B.ring_off, B.goff, L.pad,  \
+                       B.seg_next)
     if (L.k <= kGroupSmallK && (int64_t)nchunk * L.k <= kGroupLdsMax && L.C <= kGroupSmallC)
         hipLaunchKernelGGL(k_group_offsets_small, dim3(1), dim3(kGroupThreads), 0, st, b, L.k, nchunk, L.C, p_new,
                            p_expired, init_alive_before, init_keep, live, lr, B.gcnt, B.mind, B.coef, B.cum,
                            B.counts, B.alpha, B.ring_off + (int64_t)p_new * (L.k + 1), B.obj, B.labels, B.rank,
                            B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,
-                           B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_te, B.ring_off, B.goff);
+                           B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_te, B.ring_off, B.goff, L.pad,
+                           B.seg_next);
     else if ((int64_t)nchunk * L.k <= kGroupLdsMax)
         MBKK_GO(true);
     else

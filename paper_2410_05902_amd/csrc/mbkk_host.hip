@@ -29,6 +29,8 @@ struct mbkk_ctx {
     // layout (slot, column mask); fold_rr < 0: none pending
     int fold_rr = -1;
     uint32_t fold_mask = 0;
+    // iteration whose support segment offsets the last update wrote to seg_next
+    int64_t seg_next_iter = -1;
     std::vector<int32_t> slot_b;  // points held by each physical slot
     // timing of the cross-term kernel
     bool timing = false;
@@ -131,6 +133,7 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.gcnt = (int32_t *)take(4 * (size_t)L.nchunk * L.k);
     B.gbase = (int32_t *)take(4 * (size_t)L.nchunk * L.k);
     B.seg_off = (int32_t *)take(4 * (size_t)(L.k + 1));
+    B.seg_next = (int32_t *)take(4 * (size_t)(L.k + 1));
     B.sup_row = (int32_t *)take(4 * (L.Mcap + 1));  // [Mcap] = zero pool row (sentinel)
     B.sup_w = (float *)take(4 * L.Mcap);
     B.sup_ay = (float *)take(4 * L.Mcap);
@@ -314,7 +317,7 @@ static void prepare(mbkk_ctx *c, const int32_t *idx, int64_t cnt)
     if (need)
         fold_rr = take_fold(c, &fold_mask);
     launch_prepare(L, c->B, need, live, init_alive, idx, cnt, c->cfg.validate, ay_scale, fold_rr, fold_mask,
-                   c->stream);
+                   c->seg_next_iter == c->iter, c->stream);
     if (need)
         c->support_iter = c->iter;
 }
@@ -460,6 +463,7 @@ static int init_common(mbkk_ctx *c, const int32_t *idx_dev)
     c->iter = 1;
     c->support_iter = -1;
     c->fold_rr = -1;
+    c->seg_next_iter = -1;
     std::fill(c->slot_b.begin(), c->slot_b.end(), 0);
     if (c->cfg.validate) {
         int rc = check_flags(c);
@@ -534,6 +538,7 @@ int mbkk_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels_dev,
     launch_update(L, B, b, p_new, p_expired, init_alive_before, init_keep, live, c->cfg.lr, mask, c->use_mfma,
                   c->stream);
     gram(c, p_new, mask, true);
+    c->seg_next_iter = i + 1;
     HIPCHK(c, hipGetLastError());
     c->slot_b[p_new] = b;
     c->iter = i + 1;
@@ -643,7 +648,7 @@ static void support_at_sigma(mbkk_ctx *c, double sigma)
     uint32_t fold_mask = 0;
     const int fold_rr = take_fold(c, &fold_mask);
     launch_prepare(L, c->B, true, live, init_alive, nullptr, 0, 0, (float)(-1.4426950408889634 / kappa), fold_rr,
-                   fold_mask, c->stream);
+                   fold_mask, c->seg_next_iter == c->iter, c->stream);
     c->support_iter = -1;
     launch_selfnorm_sigma(L, c->B, sigma, c->B.Nsig, c->B.dNsig, c->stream);
 }
@@ -835,6 +840,7 @@ int mbkk_set_state(mbkk_ctx *c, const mbkk_state *s)
     // initial points, G reset with G[j][0][0] = K(x_j, x_j); a fold left by a
     // step of the replaced state is dropped
     c->fold_rr = -1;
+    c->seg_next_iter = -1;
     launch_gather_rows(B.X, L.n, L.d, B.ld, B.picks, L.k, L.dp, B.pool32, L.bf16 ? B.poolhi : nullptr,
                        L.bf16 ? B.poollo : nullptr, B.poolsq, B.poolsq64, B.init_idx, B.flags, 0, c->stream);
     launch_init_state(L, B, c->cfg.kernel, c->cfg.kernel_param, c->fp64, 0, c->stream);

@@ -85,6 +85,7 @@ struct Buffers {
     int32_t *gbase = nullptr;     // [nchunk * k] per-chunk label bases in the new slot
     // support of the current centers (padded segments)
     int32_t *seg_off = nullptr;  // [k+1]
+    int32_t *seg_next = nullptr; // [k+1] segment offsets of the next iteration's support (from the update)
     int32_t *sup_row = nullptr;  // [Mcap + 1] pool row; [Mcap] = the zero row
     float *sup_w = nullptr;      // [Mcap]
     float *sup_ay = nullptr;     // [Mcap] MFMA path: -log2(e) ||y||^2 / kappa of the entry's row
