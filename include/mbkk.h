@@ -62,7 +62,11 @@ extern "C" {
  * BF16X3: Gaussian only; x.y on BF16 MFMA as the compensated split product
  *         hi.hi + hi.lo + lo.hi with FP32 accumulation, norms and the exp
  *         argument in FP32; rows whose two best distances are closer than
- *         tie_delta are re-scored in FP64.
+ *         an error bound of the form are re-scored in FP64 (cross term
+ *         recomputed from the FP32 coordinates).  The bound follows from the
+ *         bf16 split (|x - hi| <= 2^-8 |x|, |x - hi - lo| <= 2^-16 |x|), the
+ *         FP32 sums, ||x||, the largest ||y||^2 of the data and kappa; a
+ *         positive tie_delta replaces it.
  * BF16X1: as BF16X3 with the single product hi.hi (information only). */
 #define MBKK_FP32 0
 #define MBKK_FP64 1
@@ -90,7 +94,7 @@ typedef struct {
     int32_t precision;   /* MBKK_FP32 ...                                        */
     int32_t lr;          /* MBKK_LR_BETA ...                                     */
     int32_t cross_impl;  /* MBKK_CROSS_AUTO ...                                  */
-    double tie_delta;    /* BF16 forms: FP64 re-scoring threshold; <= 0: 4e-3    */
+    double tie_delta;    /* BF16 forms: FP64 re-scoring threshold; <= 0: bound   */
     int32_t validate;    /* non-zero: report bad indices / non-finite rows       */
 } mbkk_config;
 

@@ -5,7 +5,8 @@
 
 namespace mbkk {
 
-void launch_row_sqnorm(const float *X, int64_t n, int d, int64_t ld, float *sqn, hipStream_t st);
+void launch_row_sqnorm(const float *X, int64_t n, int d, int64_t ld, float *sqn, unsigned int *sqmax,
+                       hipStream_t st);
 void launch_gather_rows(const float *X, int64_t n, int d, int64_t ld, const int32_t *idx, int64_t cnt,
                         int dp, float *out32, uint16_t *outhi, uint16_t *outlo, float *outsq,
                         double *outsq64, int32_t *idx_copy, int32_t *flags, int check_finite,
@@ -39,8 +40,12 @@ void launch_cross_direct(const Layout &L, const Buffers &B, int nb, int kind, do
 void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision, double kappa,
                        hipStream_t st);
 // Distances, argmin, margin (and optionally every distance) of rows [0, nb).
+// BF16 forms: rows whose margin is below tie_delta (> 0), or below the
+// per-row error bound of the form (tie_delta <= 0; ymax2 bounds ||y||^2 of
+// every support row), are re-scored in FP64.
 void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double param, int fp64, int mfma,
-                  int precision, double tie_delta, double *D_out, int64_t ldD, bool with_rank, hipStream_t st);
+                  int precision, double tie_delta, double ymax2, double *D_out, int64_t ldD, bool with_rank,
+                  hipStream_t st);
 void launch_sum_mind(const Buffers &B, int nb, int accumulate, hipStream_t st);
 
 // Differentiation form (Gaussian, bandwidth s): self norms and their

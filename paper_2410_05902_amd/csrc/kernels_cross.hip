@@ -1202,8 +1202,9 @@ struct ScoreArgs {
     float *mind, *margin;
     double *Dout;
     int64_t ldD;
-    // FP64 re-scoring of near ties (BF16 forms)
-    double delta, kappa;
+    // FP64 re-scoring of near ties (BF16 forms): a fixed threshold (delta > 0)
+    // or the per-row bound from rel_dot and ymax2
+    double delta, kappa, rel_dot, ymax2;
     int d, dp;
     const float *bat32, *pool32;
     const int32_t *sup_row;
@@ -1217,23 +1218,22 @@ struct ScoreArgs {
 // whose approximate distance is within delta of the best; for them the cross
 // term is recomputed in FP64 from the FP32 coordinates (direct ||x - y||^2,
 // FP64 exp, FP64 weights).
-__device__ void rescore_row(const ScoreArgs &A, int row, int RB, int &lab_io, float &mind_io, float &margin_io)
+// best: the row's smallest approximate distance (from the scoring pass);
+// seg_off / Nv: the segment offsets and self norms (LDS copies when staged).
+__device__ void rescore_row(const ScoreArgs &A, int row, int RB, double delta, double best,
+                            const int32_t *__restrict__ seg_off, const double *__restrict__ Nv, int &lab_io,
+                            float &mind_io, float &margin_io)
 {
     const int lane = threadIdx.x & 63;
     const float *part = (const float *)A.part;
-    double best = INFINITY;
-    for (int j = lane; j < A.k; j += 64)
-        best = fmin(best, 1.0 - 2.0 * cross_of<float, 1>(part, A.ldp, row, j, A.seg_off, RB) + A.N[j]);
-    for (int o = 32; o > 0; o >>= 1)
-        best = fmin(best, __shfl_xor(best, o));
     const float *x = A.bat32 + (int64_t)row * A.dp;
     double b64 = INFINITY, s64 = INFINITY, outside = INFINITY;
     int lab = 0;
     for (int j0 = 0; j0 < A.k; j0 += 64) {
         const int jl = j0 + lane;
         const double Dap =
-            jl < A.k ? 1.0 - 2.0 * cross_of<float, 1>(part, A.ldp, row, jl, A.seg_off, RB) + A.N[jl] : INFINITY;
-        const bool cand = Dap <= best + A.delta;
+            jl < A.k ? 1.0 - 2.0 * cross_of<float, 1>(part, A.ldp, row, jl, seg_off, RB) + Nv[jl] : INFINITY;
+        const bool cand = Dap <= best + delta;
         if (!cand)
             outside = fmin(outside, Dap);
         uint64_t mask = __ballot(cand);
@@ -1242,21 +1242,28 @@ __device__ void rescore_row(const ScoreArgs &A, int row, int RB, int &lab_io, fl
             mask &= mask - 1;
             const int j = j0 + bit;
             double p = 0.0;
-            for (int s = A.seg_off[j] + lane; s < A.seg_off[j + 1]; s += 64) {
+            for (int s = seg_off[j] + lane; s < seg_off[j + 1]; s += 64) {
                 const double w = A.sup_w64[s];
                 if (w == 0.0)
                     continue;
-                const float *y = A.pool32 + (int64_t)A.sup_row[s] * A.dp;
+                // rows are zero past d up to the padded stride: 16-byte loads over dp
+                const f32x4 *y4 = (const f32x4 *)(A.pool32 + (int64_t)A.sup_row[s] * A.dp);
+                const f32x4 *x4 = (const f32x4 *)x;
                 double d2 = 0.0;
-                for (int t = 0; t < A.d; ++t) {
-                    const double v = (double)x[t] - (double)y[t];
-                    d2 += v * v;
+#pragma unroll 4
+                for (int t4 = 0; t4 < A.dp / 4; ++t4) {
+                    const f32x4 a = x4[t4], c = y4[t4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const double v = (double)a[u] - (double)c[u];
+                        d2 = fma(v, v, d2);
+                    }
                 }
                 p += w * exp(-d2 / A.kappa);
             }
             for (int o = 32; o > 0; o >>= 1)
                 p += __shfl_xor(p, o);
-            const double D = 1.0 - 2.0 * p + A.N[j];
+            const double D = 1.0 - 2.0 * p + Nv[j];
             if (D < b64) {
                 s64 = b64;
                 b64 = D;
@@ -1283,6 +1290,8 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
     __shared__ int sl[kScoreWaves][64];
     __shared__ int flab[64];
     __shared__ float fmin_[64], fmar[64];
+    __shared__ double fdel[64], fbest[64];
+    __shared__ int smax_seg;
     __shared__ int32_t lseg[LK ? kScoreLdsK + 1 : 1];
     __shared__ double lN[LK ? kScoreLdsK : 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1304,6 +1313,19 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
     }
     const int RB = LAYOUT == 0 ? direct_range_rows(seg_off[A.k], A.nranges)
                                : (A.nranges > 0 ? bs_range_blocks(seg_off[A.k] / 32, A.nranges) : A.RB);
+    if constexpr (RESCORE) {
+        // longest center segment: the length of the FP32 sums in the error bound
+        if (threadIdx.x == 0)
+            smax_seg = 0;
+        __syncthreads();
+        int m = 0;
+        for (int i = threadIdx.x; i < A.k; i += 64 * kScoreWaves)
+            m = max(m, seg_off[i + 1] - seg_off[i]);
+        for (int o = 32; o > 0; o >>= 1)
+            m = max(m, __shfl_xor(m, o));
+        if (lane == 0)
+            atomicMax(&smax_seg, m);
+    }
     double best = INFINITY, second = INFINITY;
     int lab = 0x7fffffff;
     if (act) {
@@ -1361,15 +1383,38 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
         flab[lane] = l0;
         fmin_[lane] = (float)b0;
         fmar[lane] = (float)(s0 - b0);
+        if constexpr (RESCORE) {
+            // Error bound of an approximate distance D_j (Gaussian, BF16 form):
+            // the exponent a = (2 x.y - |x|^2 - |y|^2) / kappa has
+            // |da| <= (2 rel_dot |x||y| + 2^-22 (|x|^2 + |y|^2)) / kappa = e(x, y)
+            // (rel_dot: relative error of x.y against sum |x_t y_t| <= |x||y|;
+            // 2^-22: the FP32 roundings of the norms and of the FMA), so a
+            // kernel value has relative error <= e, and with weights summing
+            // to at most 1 and kernel values at most 1
+            //   |dP_j| <= e(x, Y) + S 2^-24,  |dN_j| <= e(Y, Y) + S 2^-24
+            // (Y^2 = max |y|^2 over the data, S = longest segment: the FP32
+            // sums).  A margin above 2 (2 |dP| + |dN|) cannot hide a swap.
+            double dl = A.delta;
+            if (!(dl > 0.0)) {
+                const double x2 = act ? A.batsq64[row] : 0.0, y2 = A.ymax2;
+                const double xn = sqrt(x2), yn = sqrt(y2);
+                const double gS = (double)smax_seg * 0x1p-24;
+                const double eP = (2.0 * A.rel_dot * xn * yn + 0x1p-22 * (x2 + y2)) / A.kappa + gS;
+                const double eN = (2.0 * A.rel_dot * y2 + 0x1p-22 * 2.0 * y2) / A.kappa + gS;
+                dl = 2.0 * (2.0 * eP + eN);
+            }
+            fdel[lane] = dl;
+            fbest[lane] = b0;
+        }
     }
     __syncthreads();
     if constexpr (RESCORE) {
         for (int r = w; r < 64; r += kScoreWaves) {  // wave-uniform row loop
             const int rw = blockIdx.x * 64 + r;
-            if (rw < A.nb && fmar[r] < (float)A.delta) {
+            if (rw < A.nb && (double)fmar[r] < fdel[r]) {
                 int l;
                 float m, g;
-                rescore_row(A, rw, RB, l, m, g);
+                rescore_row(A, rw, RB, fdel[r], fbest[r], seg_off, Nv, l, m, g);
                 if (lane == 0) {
                     flab[r] = l;
                     fmin_[r] = m;
@@ -1409,7 +1454,8 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
 }
 
 void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double param, int fp64, int mfma,
-                  int precision, double tie_delta, double *D_out, int64_t ldD, bool with_rank, hipStream_t st)
+                  int precision, double tie_delta, double ymax2, double *D_out, int64_t ldD, bool with_rank,
+                  hipStream_t st)
 {
     ScoreArgs A;
     A.nb = nb;
@@ -1430,6 +1476,14 @@ void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double pa
     A.ldD = ldD;
     A.delta = tie_delta;
     A.kappa = param;
+    // relative error of the split product x.y against sum_t |x_t y_t|: bf16
+    // rounding leaves |x - hi| <= 2^-8 |x| and |x - hi - lo| <= 2^-16 |x|;
+    // hi.hi + hi.lo + lo.hi misses at most 3 * 2^-16 per term, hi.hi alone
+    // 2^-7 + 2^-16; FP32 accumulation of the dp-long (x3: 3 dp) sum adds
+    // n 2^-24
+    A.rel_dot = precision == MBKK_BF16X1 ? 0x1p-7 + 0x1p-16 + (double)L.dp * 0x1p-24
+                                         : 3.0 * 0x1p-16 + 3.0 * (double)L.dp * 0x1p-24;
+    A.ymax2 = ymax2;
     A.d = L.d;
     A.dp = L.dp;
     A.bat32 = B.bat32;

@@ -12,32 +12,48 @@
 namespace mbkk {
 
 // ---------------------------------------------------------------------------
-// ||x||^2 for every row of X, summed in FP64, stored as FP32 (data norms).
-// 16 lanes per row.
+// ||x||^2 for every row of X, summed in FP64, stored as FP32 (data norms),
+// and their maximum over the finite ones (as FP32 bits in *sqmax, which the
+// caller zeroes first; non-negative floats order like their bit patterns).
+// 16 lanes per row, rows grid-strided; one atomic per workgroup.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_row_sqnorm(const float *__restrict__ X, int64_t n, int d,
-                                                     int64_t ld, float *__restrict__ sqn)
+                                                     int64_t ld, float *__restrict__ sqn,
+                                                     unsigned int *__restrict__ sqmax)
 {
+    __shared__ float wmax[4];
     const int sub = threadIdx.x & 15;
-    const int64_t row = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
-    if (row >= n)
-        return;
-    const float *r = X + row * ld;
-    double s = 0.0;
-    for (int t = sub; t < d; t += 16) {
-        double v = r[t];
-        s += v * v;
+    float m = 0.0f;
+    for (int64_t row = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4); row < n; row += (int64_t)gridDim.x * 16) {
+        const float *r = X + row * ld;
+        double s = 0.0;
+        for (int t = sub; t < d; t += 16) {
+            double v = r[t];
+            s += v * v;
+        }
+        for (int o = 8; o > 0; o >>= 1)
+            s += __shfl_xor(s, o, 16);
+        const float f = (float)s;
+        if (sub == 0)
+            sqn[row] = f;
+        if (isfinite(f))
+            m = fmaxf(m, f);
     }
-    for (int o = 8; o > 0; o >>= 1)
-        s += __shfl_xor(s, o, 16);
-    if (sub == 0)
-        sqn[row] = (float)s;
+    for (int o = 32; o > 0; o >>= 1)
+        m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0)
+        wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(sqmax, __float_as_uint(fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]))));
 }
 
-void launch_row_sqnorm(const float *X, int64_t n, int d, int64_t ld, float *sqn, hipStream_t st)
+void launch_row_sqnorm(const float *X, int64_t n, int d, int64_t ld, float *sqn, unsigned int *sqmax,
+                       hipStream_t st)
 {
     int64_t blocks = (n + 15) / 16;
-    hipLaunchKernelGGL(k_row_sqnorm, dim3((unsigned)blocks), dim3(256), 0, st, X, n, d, ld, sqn);
+    blocks = blocks < 4096 ? blocks : 4096;
+    hipLaunchKernelGGL(k_row_sqnorm, dim3((unsigned)blocks), dim3(256), 0, st, X, n, d, ld, sqn, sqmax);
 }
 
 // ---------------------------------------------------------------------------

@@ -22,6 +22,7 @@ struct mbkk_ctx {
     bool use_mfma = false;
     bool fp64 = false;
     bool data_set = false;
+    double ymax2 = 0.0;         // max ||x||^2 over the data (bounds every support row)
     bool inited = false;
     int64_t iter = 1;           // index i of the next batch
     int64_t support_iter = -1;  // iteration for which the support layout is built
@@ -111,6 +112,7 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     const int64_t prows = L.PR + 1;
     const int C = L.C;
     B.sqn = (float *)take(sizeof(float) * L.n);
+    B.sqmax = (unsigned int *)take(sizeof(unsigned int));
     B.pool32 = (float *)take(sizeof(float) * prows * L.dp);
     B.poolhi = L.bf16 ? (uint16_t *)take(2 * prows * L.dp) : nullptr;
     B.poollo = L.bf16 ? (uint16_t *)take(2 * prows * L.dp) : nullptr;
@@ -286,7 +288,8 @@ static int clear_flags(mbkk_ctx *c)
     return MBKK_OK;
 }
 
-static double tie_delta(const mbkk_config &c) { return c.tie_delta > 0.0 ? c.tie_delta : 4e-3; }
+// A positive tie_delta replaces the per-row error bound of the BF16 forms.
+static double tie_delta(const mbkk_config &c) { return c.tie_delta > 0.0 ? c.tie_delta : 0.0; }
 
 // Points the batch view at physical slot p (the free slot of the iteration).
 static void set_batch_view(mbkk_ctx *c, int p)
@@ -348,8 +351,8 @@ static int cross_and_score(mbkk_ctx *c, int nb, double *D_out, int64_t ldD, bool
         HIPCHK(c, hipEventRecord(e1, c->stream));
         c->launches++;
     }
-    launch_score(L, c->B, nb, cf.kernel, cf.kernel_param, c->fp64, c->use_mfma, cf.precision, tie_delta(cf), D_out,
-                 ldD, with_rank, c->stream);
+    launch_score(L, c->B, nb, cf.kernel, cf.kernel_param, c->fp64, c->use_mfma, cf.precision, tie_delta(cf), c->ymax2,
+                 D_out, ldD, with_rank, c->stream);
     HIPCHK(c, hipGetLastError());
     return MBKK_OK;
 }
@@ -440,8 +443,15 @@ int mbkk_set_data(mbkk_ctx *c, const float *X, int64_t ld)
         return fail(c, MBKK_E_INVALID, "X is NULL or ld < d");
     c->B.X = X;
     c->B.ld = ld;
-    launch_row_sqnorm(X, c->L.n, c->L.d, ld, c->B.sqn, c->stream);
+    HIPCHK(c, hipMemsetAsync(c->B.sqmax, 0, sizeof(unsigned int), c->stream));
+    launch_row_sqnorm(X, c->L.n, c->L.d, ld, c->B.sqn, c->B.sqmax, c->stream);
     HIPCHK(c, hipGetLastError());
+    unsigned int bits = 0;
+    HIPCHK(c, hipMemcpyAsync(&bits, c->B.sqmax, sizeof(bits), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    float f;
+    memcpy(&f, &bits, sizeof(f));
+    c->ymax2 = (double)f;
     c->data_set = true;
     c->inited = false;
     return MBKK_OK;
@@ -676,8 +686,8 @@ int mbkk_objective_fwd(mbkk_ctx *c, const float *xb_dev, int32_t b, double sigma
         launch_cross_mfma(L, Bs, b, cf.precision, kappa, c->stream);
     else
         launch_cross_direct(L, Bs, b, MBKK_GAUSS, kappa, c->fp64, c->stream);
-    launch_score(L, Bs, b, MBKK_GAUSS, kappa, c->fp64, c->use_mfma, cf.precision, tie_delta(cf), nullptr, 0, false,
-                 c->stream);
+    launch_score(L, Bs, b, MBKK_GAUSS, kappa, c->fp64, c->use_mfma, cf.precision, tie_delta(cf), c->ymax2, nullptr, 0,
+                 false, c->stream);
     launch_sum_mind(B, b, 0, c->stream);
     HIPCHK(c, hipGetLastError());
     if (labels_dev)

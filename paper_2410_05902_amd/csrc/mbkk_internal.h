@@ -52,6 +52,7 @@ struct Buffers {
     const float *X = nullptr;
     int64_t ld = 0;
     float *sqn = nullptr;        // [n] ||x||^2 (FP32 from an FP64 sum)
+    unsigned int *sqmax = nullptr;  // [1] max of sqn over the finite rows (FP32 bits)
     // coordinate pool: rows [0,k) initial points, k + p*bmax + q: position q
     // (batch order) of physical slot p; row PR = k + P*bmax is all zeros
     float *pool32 = nullptr;     // [(PR+1) * dp]
