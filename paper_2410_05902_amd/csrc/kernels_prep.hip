@@ -450,8 +450,19 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
     const int32_t *cnt = gcnt;
     int32_t *base = gbase;
     if constexpr (LDS) {
-        for (int i = tid; i < nchunk * k; i += nt)
-            scnt[i] = gcnt[i];
+        constexpr int CPT = kGroupLdsMax / 1024;  // blockDim.x == 1024
+        int v[CPT];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int i = tid + q * nt;
+            v[q] = i < nchunk * k ? gcnt[i] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int i = tid + q * nt;
+            if (i < nchunk * k)
+                scnt[i] = v[q];
+        }
         __syncthreads();
         cnt = scnt;
         base = sbase;
@@ -571,8 +582,22 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
         }
     }
     const double cumj = own && lr == MBKK_LR_SKLEARN ? cum[j] : 0.0;
-    for (int i = tid; i < nchunk * k; i += nt)
-        scnt[i] = gcnt[i];
+    {
+        // every count load in flight before the first LDS store
+        constexpr int CPT = kGroupLdsMax / kGroupThreads;
+        int v[CPT];
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int i = tid + q * nt;
+            v[q] = i < nchunk * k ? gcnt[i] : 0;
+        }
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+            const int i = tid + q * nt;
+            if (i < nchunk * k)
+                scnt[i] = v[q];
+        }
+    }
     __syncthreads();
     // ---- label totals: slice sums over chunks, then per label over slices
     const int TG = nt / k;  // >= 2
