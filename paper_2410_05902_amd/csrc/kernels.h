@@ -7,10 +7,12 @@ namespace mbkk {
 
 void launch_row_sqnorm(const float *X, int64_t n, int d, int64_t ld, float *sqn, unsigned int *sqmax,
                        hipStream_t st);
+// frag_mode 1 / 2: also write the rows (as batch rows 0..cnt-1) in MFMA
+// fragment order into frag (BF16 hi, then lo at byte offset frag_lo / FP32).
 void launch_gather_rows(const float *X, int64_t n, int d, int64_t ld, const int32_t *idx, int64_t cnt,
                         int dp, float *out32, uint16_t *outhi, uint16_t *outlo, float *outsq,
                         double *outsq64, int32_t *idx_copy, int32_t *flags, int check_finite,
-                        hipStream_t st);
+                        hipStream_t st, int frag_mode = 0, char *frag = nullptr, int64_t frag_lo = 0);
 void launch_init_state(const Layout &L, const Buffers &B, int kind, double param, int fp64, int set_coef,
                        hipStream_t st);
 // fold_rr >= 0: the Gram work of slot fold_rr against fold_mask is folded

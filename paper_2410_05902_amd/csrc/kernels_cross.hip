@@ -586,8 +586,8 @@ struct CrossBsArgs {
     const int32_t *sup_row;
     const float *sup_w, *sup_ay;
     const int32_t *blk_center;
-    const float *bat32;
-    const uint16_t *bathi, *batlo;
+    const char *batfrag;  // the batch in fragment order (see gather_rows_body), hi then lo
+    int64_t frag_lo;      // byte offset of the lo fragments
     const float *batsq;
     float c2;
     float *part;
@@ -764,83 +764,53 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
     };
 
     // ---- batch fragments into registers --------------------------------
-    // A fragment wants 32 rows x 32 bytes per load instruction; the rows are
-    // instead read whole (coalesced, 16 bytes per lane), written to this
-    // wave's part of the staging buffer in the padded row layout, and read
-    // back as fragments.  One 32-row N-block per pass; the loads of pass p+1
-    // are in flight while pass p goes through LDS.
+    // The batch was written in fragment order when it was staged: the 16
+    // bytes lane l = 32 h + n needs for k-step ks of a 32-row block are at
+    // ((block * QPB + ks) * 64 + l) * 16 (QPB = KS, or KS / 4 in FP32), so
+    // every fragment is one coalesced 1 KB load straight into its register,
+    // and all of them are in flight together with the staging of stage 0.
     typedef typename std::conditional<F32, float, bf16x8>::type frag_t;
     frag_t bh[NBK][KS];
     frag_t bl[NBK][X3 ? KS : 1];
     float hx[NBK];
-    // fragment read of row n of a 32-row block: byte offset in the padded layout
-    const int aoff = n * (CPS * 16) + (F32 ? h * KS * 4 : h * 16);
     {
-        constexpr int BCH = 32 * CPR / 64;    // 16-byte chunks per lane per array and block
-        constexpr int WREG = 32 * CPS * 16;   // bytes of one array of one block
-        static_assert(4 * NARR * WREG <= (int)sizeof(sA1), "batch transpose must fit one staging buffer");
-        // buffer 1: the support rows of stage 0 are meanwhile landing in buffer 0
-        char *wreg = sA1 + wu * NARR * WREG;
-        u16x8 ld[2][NARR][BCH];
-        auto bload = [&](int nbk, int slot) {
-#pragma unroll
-            for (int arr = 0; arr < NARR; ++arr) {
-                const char *src = F32 ? (const char *)A.bat32
-                                      : (arr == 0 ? (const char *)A.bathi : (const char *)A.batlo);
-#pragma unroll
-                for (int it = 0; it < BCH; ++it) {
-                    const int cp = it * 64 + lane, r = cp / CPR, c = cp % CPR;
-                    const int row = b0 + nbk * 32 + r;
-                    const u16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
-                    ld[slot][arr][it] = row < A.nb ? *(const u16x8 *)(src + (int64_t)row * (DP * ES) + c * 16) : z8;
-                }
-            }
-        };
-        // the index loads of stage 0 go first, then the batch rows; once the
-        // indices are in, the staging of stage 0 starts while the batch rows
-        // go through LDS
+        constexpr int QPB = F32 ? KS / 4 : KS;
         load_idx(0);
         load_cen_win(0);
-        bload(0, 0);
-        if (NBK > 1)
-            bload(1, 1);
+#pragma unroll
+        for (int nbk = 0; nbk < NBK; ++nbk) {
+            const int row = b0 + nbk * 32 + n;
+            const bool ok = row < A.nb;
+            const int64_t blk = (b0 >> 5) + nbk;
+            const char *src = A.batfrag + ((blk * QPB) * 64 + lane) * 16;
+            if constexpr (F32) {
+#pragma unroll
+                for (int q = 0; q < QPB; ++q) {
+                    const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+                    const f32x4 v = ok ? *(const f32x4 *)(src + q * 1024) : z;
+                    bh[nbk][4 * q] = v[0];
+                    bh[nbk][4 * q + 1] = v[1];
+                    bh[nbk][4 * q + 2] = v[2];
+                    bh[nbk][4 * q + 3] = v[3];
+                }
+            } else {
+                const u16x8 z8 = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks) {
+                    bh[nbk][ks] = __builtin_bit_cast(bf16x8, ok ? *(const u16x8 *)(src + ks * 1024) : z8);
+                    if constexpr (X3)
+                        bl[nbk][ks] =
+                            __builtin_bit_cast(bf16x8, ok ? *(const u16x8 *)(src + A.frag_lo + ks * 1024) : z8);
+                }
+            }
+            hx[nbk] = ok ? -0.5f * A.batsq[row] : 0.0f;
+        }
         issue(0, IC0{});
         if (nst > 1)
             issue_idx(1, IC1{});
-#pragma unroll
-        for (int nbk = 0; nbk < NBK; ++nbk) {
-            const int slot = nbk & 1;
-#pragma unroll
-            for (int arr = 0; arr < NARR; ++arr)
-#pragma unroll
-                for (int it = 0; it < BCH; ++it) {
-                    const int cp = it * 64 + lane, r = cp / CPR, c = cp % CPR;
-                    *(u16x8 *)(wreg + arr * WREG + r * (CPS * 16) + c * 16) = ld[slot][arr][it];
-                }
-            if (nbk + 2 < NBK)
-                bload(nbk + 2, slot);
-            const char *base = wreg + aoff;
-            if constexpr (F32) {
-#pragma unroll
-                for (int s4 = 0; s4 < KS; s4 += 4) {
-                    const f32x4 v = *(const f32x4 *)(base + s4 * 4);
-                    bh[nbk][s4] = v[0];
-                    bh[nbk][s4 + 1] = v[1];
-                    bh[nbk][s4 + 2] = v[2];
-                    bh[nbk][s4 + 3] = v[3];
-                }
-            } else {
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks) {
-                    bh[nbk][ks] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + ks * 32));
-                    if constexpr (X3)
-                        bl[nbk][ks] = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + WREG + ks * 32));
-                }
-            }
-            const int row = b0 + nbk * 32 + n;
-            hx[nbk] = row < A.nb ? -0.5f * A.batsq[row] : 0.0f;
-        }
     }
+    // fragment read of row n of a staged 32-row support block: byte offset in the padded layout
+    const int aoff = n * (CPS * 16) + (F32 ? h * KS * 4 : h * 16);
     __syncthreads();  // stage 0 staged; buffer 1 is free for stage 1
 
     // ---- block products and epilogue ---------------------------------------
@@ -1072,9 +1042,8 @@ void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision,
         A.sup_w = B.sup_w;
         A.sup_ay = B.sup_ay;
         A.blk_center = B.blk_center;
-        A.bat32 = B.bat32;
-        A.bathi = B.bathi;
-        A.batlo = B.batlo;
+        A.batfrag = (const char *)B.batfrag;
+        A.frag_lo = 2 * (int64_t)frag_rows(L) * L.dp;
         A.batsq = B.batsq;
         A.c2 = (float)(2.0 * l2e / kappa);
         A.part = (float *)B.part;

@@ -78,6 +78,9 @@ struct GatherArgs {
     int32_t *idx_copy;
     int32_t *flags;
     int check_finite;
+    int frag_mode;    // 1: BF16 hi/lo fragments, 2: FP32 fragments, 0: none
+    char *frag;
+    int64_t frag_lo;  // byte offset of the lo fragments
 };
 
 // One wave per row; `blk` numbers groups of 4 rows.
@@ -105,6 +108,22 @@ __device__ __forceinline__ void gather_rows_body(const GatherArgs &A, int64_t bl
             const uint16_t l = f32_to_bf16_rne(v - bf16_to_f32(h));
             A.outhi[row * A.dp + t] = h;
             A.outlo[row * A.dp + t] = l;
+            if (A.frag_mode == 1) {
+                // 32x32x16 BF16 fragment order: k-step ks = t / 16 of block
+                // row / 32; lane 32 (t / 8 % 2) + row % 32, element t % 8
+                const int64_t f = ((((row >> 5) * (A.dp >> 4) + (t >> 4)) * 64 + ((t >> 3) & 1) * 32 + (row & 31))
+                                   << 3) + (t & 7);
+                ((uint16_t *)A.frag)[f] = h;
+                ((uint16_t *)(A.frag + A.frag_lo))[f] = l;
+            }
+        }
+        if (A.frag_mode == 2) {
+            // 32x32x2 FP32 fragment order: lane half hh = t / (dp/2) holds the
+            // coordinates hh dp/2 + 4 q + e of row row % 32, chunk q
+            const int ks = A.dp >> 1, hh = t / ks, r2 = t - hh * ks;
+            const int64_t f =
+                ((((row >> 5) * (ks >> 2) + (r2 >> 2)) * 64 + hh * 32 + (row & 31)) << 2) + (r2 & 3);
+            ((float *)A.frag)[f] = v;
         }
         s += (double)v * (double)v;
     }
@@ -124,11 +143,13 @@ __global__ __launch_bounds__(256) void k_gather_rows(const GatherArgs A) { gathe
 void launch_gather_rows(const float *X, int64_t n, int d, int64_t ld, const int32_t *idx, int64_t cnt,
                         int dp, float *out32, uint16_t *outhi, uint16_t *outlo, float *outsq,
                         double *outsq64, int32_t *idx_copy, int32_t *flags, int check_finite,
-                        hipStream_t st)
+                        hipStream_t st, int frag_mode, char *frag, int64_t frag_lo)
 {
     if (cnt <= 0)
         return;
-    const GatherArgs A{X, n, d, ld, idx, cnt, dp, out32, outhi, outlo, outsq, outsq64, idx_copy, flags, check_finite};
+    const GatherArgs A{X,        n,     d,         ld,    idx,          cnt,       dp,   out32,
+                       outhi,    outlo, outsq,     outsq64, idx_copy,   flags,     check_finite,
+                       frag_mode, frag, frag_lo};
     const int64_t blocks = (cnt + 3) / 4;
     hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)blocks), dim3(256), 0, st, A);
 }
@@ -410,8 +431,10 @@ void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const 
     S.sup_ay = L.pad == kMfmaPad ? B.sup_ay : nullptr;
     S.poolsq = B.poolsq;
     S.ay_scale = ay_scale;
-    const GatherArgs Gth{B.X, L.n, L.d, B.ld, idx, cnt, L.dp, B.bat32, B.bathi, B.batlo, B.batsq, B.batsq64,
-                         B.batidx, B.flags, check_finite};
+    const GatherArgs Gth{B.X,       L.n,       L.d,       B.ld,      idx,       cnt,
+                         L.dp,      B.bat32,   B.bathi,   B.batlo,   B.batsq,   B.batsq64,
+                         B.batidx,  B.flags,   check_finite, L.frag_mode, B.batfrag,
+                         2 * (int64_t)frag_rows(L) * L.dp};
     const int nsup = with_support ? L.k : 0;
     const int64_t ngat = cnt > 0 ? (cnt + 3) / 4 : 0;
     if (nsup + ngat > 0)

@@ -88,6 +88,9 @@ Layout make_layout(const mbkk_config &c)
     L.bmax = c.b_max;
     L.pad = wants_mfma(c) ? kMfmaPad : 1;
     L.bf16 = c.precision == MBKK_BF16X3 || c.precision == MBKK_BF16X1;
+    // the batch-stationary MFMA cross kernel (row stride <= 128) reads the
+    // batch from a fragment-order copy
+    L.frag_mode = wants_mfma(c) && L.dp <= 128 ? (L.bf16 ? 1 : 2) : 0;
     L.PR = (int64_t)c.k + (int64_t)L.P * c.b_max;
     // live support: at most W slots of b_max points and the k initial points
     const int64_t Mlive = (int64_t)c.k + (int64_t)c.window * c.b_max;
@@ -118,6 +121,7 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.poollo = L.bf16 ? (uint16_t *)take(2 * prows * L.dp) : nullptr;
     B.poolsq = (float *)take(sizeof(float) * prows);
     B.poolsq64 = (double *)take(sizeof(double) * prows);
+    B.batfrag = L.frag_mode ? (char *)take(4 * (size_t)frag_rows(L) * L.dp) : nullptr;
     B.slot_pts = (int32_t *)take(4 * (size_t)L.P * L.bmax);
     B.ring_idx = (int32_t *)take(4 * (size_t)L.P * L.bmax);
     B.ring_perm = (int32_t *)take(4 * (size_t)L.P * L.bmax);
@@ -678,7 +682,7 @@ int mbkk_objective_fwd(mbkk_ctx *c, const float *xb_dev, int32_t b, double sigma
     // the rows go to the free slot of the current iteration
     set_batch_view(c, phys_of(c->iter, L.P));
     launch_gather_rows(xb_dev, b, L.d, L.d, nullptr, b, L.dp, B.bat32, B.bathi, B.batlo, B.batsq, B.batsq64, nullptr,
-                       B.flags, 1, c->stream);
+                       B.flags, 1, c->stream, L.frag_mode, B.batfrag, 2 * (int64_t)frag_rows(L) * L.dp);
     support_at_sigma(c, sigma);
     Buffers Bs = B;
     Bs.N = B.Nsig;

@@ -66,6 +66,9 @@ struct Buffers {
     uint16_t *bathi = nullptr, *batlo = nullptr;
     float *batsq = nullptr;
     double *batsq64 = nullptr;
+    // the staged batch again in MFMA fragment order (batch-stationary cross
+    // kernel): BF16 forms hi then lo (2 bytes each), FP32 form floats
+    char *batfrag = nullptr;     // [frag_rows * dp * 4 bytes]
     // ring of P physical slots
     int32_t *slot_pts = nullptr;  // [P * bmax] point index of each row (batch order)
     int32_t *ring_idx = nullptr;  // [P * bmax] point indices, grouped by center
@@ -120,8 +123,12 @@ struct Layout {
     int nchunk;        // grouping chunks of a full batch: ceil(bmax / kChunk)
     int64_t kpp_blocks;
     bool bf16;
+    int frag_mode;     // batch fragment copy: 0 none, 1 BF16 hi/lo, 2 FP32
     size_t bytes;
 };
+
+// Rows of the batch fragment copy (whole 32-row blocks).
+inline int frag_rows(const Layout &L) { return (L.bmax + 31) / 32 * 32; }
 
 Layout make_layout(const mbkk_config &c);
 void carve(const Layout &L, char *base, Buffers &B);
