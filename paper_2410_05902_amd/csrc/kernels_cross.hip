@@ -23,6 +23,51 @@ namespace mbkk {
 // K(x, y) with x held in registers.  The loop runs over all DR entries: both
 // the register row and the pool row are zero past d (DR <= padded stride), so
 // the padding adds nothing, and the fixed trip count keeps x in registers.
+template <int KIND, typename T>
+__device__ __forceinline__ T kfinish_direct(T s, T cneg, T param)
+{
+    if constexpr (KIND == MBKK_GAUSS || KIND == MBKK_LAPLACE) {
+        if constexpr (sizeof(T) == 4)
+            return __builtin_amdgcn_exp2f(s * cneg);  // cneg = -log2(e) / bandwidth
+        else
+            return exp(-s / param);
+    } else if constexpr (KIND == MBKK_LINEAR) {
+        return s;
+    } else {
+        T u = s + param;
+        return u * u;
+    }
+}
+
+// K(x_q, y) for RPL register rows at once: each coordinate of y is read once.
+template <int KIND, typename T, int DR, int RPL>
+__device__ __forceinline__ void kval_direct_rows(const T (&x)[RPL][DR], const float *__restrict__ y, T cneg,
+                                                 T param, T (&kv)[RPL])
+{
+    T s[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q)
+        s[q] = 0;
+#pragma unroll
+    for (int t = 0; t < DR; ++t) {
+        const T yt = (T)y[t];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            if constexpr (KIND == MBKK_GAUSS) {
+                T v = x[q][t] - yt;
+                s[q] = fma(v, v, s[q]);
+            } else if constexpr (KIND == MBKK_LAPLACE) {
+                s[q] += fabs(x[q][t] - yt);
+            } else {
+                s[q] = fma(x[q][t], yt, s[q]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RPL; ++q)
+        kv[q] = kfinish_direct<KIND, T>(s[q], cneg, param);
+}
+
 template <int KIND, typename T, int DR>
 __device__ __forceinline__ T kval_direct(const T (&x)[DR], const float *__restrict__ y, T cneg, T param)
 {
@@ -71,12 +116,13 @@ __device__ __forceinline__ double wave_bcast(double v, int e)
     return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
 }
 
-// Register-resident batch row (DR >= d, one per lane).  The workgroup's range
-// of support entries is taken 64 at a time: lane e of every wave loads entry
-// c0 + e's pool row and weight (one coalesced load), and the entries are then
-// broadcast one by one, their rows read with wave-uniform (scalar) loads.
-// A run ends where a center's segment ends.  Grid: (row tiles of 256) x (ranges).
-template <int KIND, typename T, int DR>
+// Register-resident batch rows (DR >= d; RPL rows per lane, 256 apart).  The
+// workgroup's range of support entries is taken 64 at a time: lane e of
+// every wave loads entry c0 + e's pool row and weight (one coalesced load),
+// and the entries are then broadcast one by one, their rows read with
+// wave-uniform (scalar) loads, each used for the lane's RPL batch rows.  A
+// run ends where a center's segment ends.  Grid: (row tiles of 256 RPL) x (ranges).
+template <int KIND, typename T, int DR, int RPL>
 __global__ __launch_bounds__(256) void k_cross_direct(int nb, int d, int dp, int k, int nranges,
                                                        const float *__restrict__ bat32,
                                                        const float *__restrict__ pool32,
@@ -86,9 +132,14 @@ __global__ __launch_bounds__(256) void k_cross_direct(int nb, int d, int dp, int
                                                        const int32_t *__restrict__ seg_off, double param,
                                                        T *__restrict__ P, int ldp)
 {
+    static_assert(RPL == 1 || DR > 0, "two rows per lane need a register-resident width");
     const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * 256 + threadIdx.x;
-    const int rr = row < nb ? row : 0;
+    int row[RPL], rr[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        row[q] = blockIdx.x * 256 * RPL + q * 256 + threadIdx.x;
+        rr[q] = row[q] < nb ? row[q] : 0;
+    }
     const int r = blockIdx.y;
     const int M = seg_off[k];
     const int RR = direct_range_rows(M, nranges);
@@ -97,18 +148,23 @@ __global__ __launch_bounds__(256) void k_cross_direct(int nb, int d, int dp, int
         return;  // block uniform
     const T prm = (T)param;
     const T cneg = (T)(-1.4426950408889634 / param);
-    T x[DR > 0 ? DR : 1];
+    T x[RPL][DR > 0 ? DR : 1];
     static_assert(DR <= kDimAlign || DR % kDimAlign == 0, "register row must fit the padded stride");
     if constexpr (DR > 0) {
 #pragma unroll
-        for (int t = 0; t < DR; ++t)
-            x[t] = t < d ? (T)bat32[(int64_t)rr * dp + t] : (T)0;
+        for (int q = 0; q < RPL; ++q)
+#pragma unroll
+            for (int t = 0; t < DR; ++t)
+                x[q][t] = t < d ? (T)bat32[(int64_t)rr[q] * dp + t] : (T)0;
     }
     // the run being accumulated: center j up to cur_end, stored at id
     int j = wave_segment_of(seg_off, k, s0);
     int cur_end = min(s1, seg_off[j + 1]);
     int id = s0 == seg_off[j] ? j : k + r;
-    T acc = 0;
+    T acc[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q)
+        acc[q] = 0;
     for (int c0 = s0; c0 < s1; c0 += 64) {
         const int n = min(64, s1 - c0);
         const int lrow = sup_row[c0 + (lane < n ? lane : 0)];
@@ -120,24 +176,34 @@ __global__ __launch_bounds__(256) void k_cross_direct(int nb, int d, int dp, int
         for (int e = 0; e < n; ++e) {  // wave uniform
             const int s = c0 + e;
             if (s >= cur_end) {  // the run [.., cur_end) had entries: store it, move to s's center
-                if (row < nb)
-                    P[(int64_t)id * ldp + row] = acc;
+#pragma unroll
+                for (int q = 0; q < RPL; ++q) {
+                    if (row[q] < nb)
+                        P[(int64_t)id * ldp + row[q]] = acc[q];
+                    acc[q] = 0;
+                }
                 do {
                     ++j;
                 } while (seg_off[j + 1] <= s);
                 cur_end = min(s1, seg_off[j + 1]);
                 id = j;
-                acc = 0;
             }
             const float *y = pool32 + (int64_t)__builtin_amdgcn_readlane(lrow, e) * dp;
             const T w = wave_bcast(lw, e);
-            T kv;
             if constexpr (DR > 0) {
-                kv = kval_direct<KIND, T, DR>(x, y, cneg, prm);
+                if constexpr (RPL == 1) {
+                    acc[0] = fma(w, kval_direct<KIND, T, DR>(x[0], y, cneg, prm), acc[0]);
+                } else {
+                    T kv[RPL];
+                    kval_direct_rows<KIND, T, DR, RPL>(x, y, cneg, prm, kv);
+#pragma unroll
+                    for (int q = 0; q < RPL; ++q)
+                        acc[q] = fma(w, kv[q], acc[q]);
+                }
             } else {
                 // generic width: the batch row is re-read from memory
                 T sacc = 0;
-                const float *xr = bat32 + (int64_t)rr * dp;
+                const float *xr = bat32 + (int64_t)rr[0] * dp;
                 for (int t = 0; t < d; ++t) {
                     T xv = (T)xr[t], yv = (T)y[t];
                     if constexpr (KIND == MBKK_GAUSS) {
@@ -149,6 +215,7 @@ __global__ __launch_bounds__(256) void k_cross_direct(int nb, int d, int dp, int
                         sacc = fma(xv, yv, sacc);
                     }
                 }
+                T kv;
                 if constexpr (KIND == MBKK_GAUSS || KIND == MBKK_LAPLACE) {
                     if constexpr (sizeof(T) == 4)
                         kv = __builtin_amdgcn_exp2f(sacc * cneg);
@@ -160,22 +227,31 @@ __global__ __launch_bounds__(256) void k_cross_direct(int nb, int d, int dp, int
                     T u = sacc + prm;
                     kv = u * u;
                 }
+                acc[0] = fma(w, kv, acc[0]);
             }
-            acc = fma(w, kv, acc);
         }
     }
-    if (row < nb)
-        P[(int64_t)id * ldp + row] = acc;  // the last run (s0 < s1: it has entries)
+#pragma unroll
+    for (int q = 0; q < RPL; ++q)
+        if (row[q] < nb)
+            P[(int64_t)id * ldp + row[q]] = acc[q];  // the last run (s0 < s1: it has entries)
 }
+
+// Batch rows per lane of the direct kernel: two for FP32 rows of at most 32
+// coordinates (each broadcast support row then feeds two evaluations).
+static int direct_rpl(int d, bool fp64) { return !fp64 && d <= 32 ? 2 : 1; }
 
 template <int KIND, typename T>
 static void dispatch_direct_width(const Layout &L, const Buffers &B, int nb, int nranges, double param, T *P,
                                   hipStream_t st)
 {
-    dim3 grid((nb + 255) / 256, nranges);
-#define MBKK_DIRECT(DR)                                                                                       \
-    hipLaunchKernelGGL((k_cross_direct<KIND, T, DR>), grid, dim3(256), 0, st, nb, L.d, L.dp, L.k, nranges,    \
+    constexpr int R2 = sizeof(T) == 4 ? 2 : 1;  // rows per lane for d <= 32 (direct_rpl)
+    const int rpl = direct_rpl(L.d, sizeof(T) == 8);
+    dim3 grid((nb + 256 * rpl - 1) / (256 * rpl), nranges);
+#define MBKK_DIRECT_R(DR, RPL)                                                                                 \
+    hipLaunchKernelGGL((k_cross_direct<KIND, T, DR, RPL>), grid, dim3(256), 0, st, nb, L.d, L.dp, L.k, nranges, \
                        B.bat32, B.pool32, B.sup_row, B.sup_w, B.sup_w64, B.seg_off, param, P, L.bmax)
+#define MBKK_DIRECT(DR) MBKK_DIRECT_R(DR, (DR > 0 && DR <= 32 ? R2 : 1))
     if (L.d <= 4)
         MBKK_DIRECT(4);
     else if (L.d <= 8)
@@ -189,20 +265,23 @@ static void dispatch_direct_width(const Layout &L, const Buffers &B, int nb, int
     else
         MBKK_DIRECT(0);
 #undef MBKK_DIRECT
+#undef MBKK_DIRECT_R
 }
 
-// Ranges of the direct kernel for nb batch rows: about kDirectWGs workgroups.
-static int direct_nranges(int nb)
+// Ranges of the direct kernel for nb batch rows: about kDirectWGs workgroups
+// (one round at 8 waves per SIMD), 3/4 of that with two rows per lane (whose
+// registers allow 6 waves per SIMD).
+static int direct_nranges(int nb, int rpl)
 {
-    const int tiles = (nb + 255) / 256;
-    const int r = kDirectWGs / tiles;
+    const int tiles = (nb + 256 * rpl - 1) / (256 * rpl);
+    const int r = (rpl == 2 ? kDirectWGs * 3 / 4 : kDirectWGs) / tiles;
     return r < 1 ? 1 : r;
 }
 
 void launch_cross_direct(const Layout &L, const Buffers &B, int nb, int kind, double param, int fp64,
                          hipStream_t st)
 {
-    const int nranges = direct_nranges(nb);
+    const int nranges = direct_nranges(nb, direct_rpl(L.d, fp64));
     if (fp64) {
         double *P = (double *)B.part;
         switch (kind) {
@@ -1431,7 +1510,8 @@ void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double pa
     A.k = L.k;
     A.ldp = L.bmax;
     A.RB = 2;
-    A.nranges = mfma ? (L.dp <= 128 ? bs_nranges(nb, bs_mode(precision), L.dp) : 0) : direct_nranges(nb);
+    A.nranges = mfma ? (L.dp <= 128 ? bs_nranges(nb, bs_mode(precision), L.dp) : 0)
+                     : direct_nranges(nb, direct_rpl(L.d, fp64));
     A.kind = kind;
     A.param = param;
     A.part = B.part;
