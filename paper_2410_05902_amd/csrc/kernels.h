@@ -22,16 +22,16 @@ void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const 
                     const int32_t *idx, int64_t cnt, int check_finite, float ay_scale, int fold_rr,
                     uint32_t fold_mask, bool seg_ready, hipStream_t st);
 // The update also writes the task plan of the new slot's Gram blocks against
-// the columns in gram_mask (for the Gram form chosen by gram_mfma), and the
+// the columns in gram_mask (tasks gram_te column rows wide), and the
 // segment offsets of the support over those columns into B.seg_next.
 void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
-                   int init_keep, const SlotList &live, int lr, uint32_t gram_mask, int gram_mfma, hipStream_t st);
+                   int init_keep, const SlotList &live, int lr, uint32_t gram_mask, int gram_te, hipStream_t st);
 
 // Gram blocks of slot rr against the columns in col_mask: plan (when not made
 // by the update), then work and fold.  mfma: the Gaussian MFMA forms, with
 // the product arithmetic of `precision`; else VALU in FP64 or FP32.
-int gram_task_cols(int mfma);
-void launch_gram_plan(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int mfma, hipStream_t st);
+int gram_task_cols(int mfma, int fp64);  // te of the plan for the chosen Gram form
+void launch_gram_plan(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int te, hipStream_t st);
 void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param, int fp64,
                  int mfma, int precision, bool fold, hipStream_t st);
 void launch_gram_fold(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, hipStream_t st);

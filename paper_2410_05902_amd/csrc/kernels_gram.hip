@@ -102,38 +102,57 @@ __device__ __forceinline__ KT gram_finish(KT s, KT prm)
         return (s + prm) * (s + prm);
 }
 
-constexpr int kGramTEV = 64;  // column rows of a VALU task (one per lane)
-constexpr int kGramDC = 32;   // coordinates per register chunk (the pool stride is a multiple)
+// VALU tasks: RPL column rows per lane (two in FP32, one in FP64), so a
+// task is 32 slot rows by 64 RPL column rows, and coordinates are held in
+// registers 32 / RPL at a time (the pool stride is a multiple of 32).
+template <typename KT>
+__host__ __device__ constexpr int gram_valu_rpl()
+{
+    return sizeof(KT) == 4 ? 2 : 1;
+}
 
-// Lane l holds column row eb*64 + l in registers, 32 coordinates at a time;
-// the task's slot rows are read with wave-uniform addresses.  Pairs, sums
-// and the kernel value in KT; the task sum in FP64.
+// Column rows eb*64 RPL + 64 q + l (q < RPL) of lane l are held in registers,
+// 32 / RPL coordinates at a time; the task's slot rows are read with
+// wave-uniform addresses and each coordinate serves the RPL rows.  Pairs,
+// sums and the kernel value in KT; the task sum in FP64.
 template <int KIND, typename KT>
 __global__ __launch_bounds__(kGramWG) void k_gram_valu(const GramWork A, int d, int dp, double param,
                                                        const float *__restrict__ pool32, int zero_row)
 {
+    constexpr int RPL = gram_valu_rpl<KT>();
+    constexpr int DC = 32 / RPL;
     const int lane = threadIdx.x & 63;
     const KT prm = (KT)param;
-    gram_wave_loop<kGramTEV>(A, [&](const GramCol &a, const GramCol &ec, int ab, int eb, double &lsum) {
-        const int qe = eb * kGramTEV + lane;
-        const bool eok = qe < ec.n;
-        const int re = eok ? (int)gram_row(ec, qe) : zero_row;
+    gram_wave_loop<64 * RPL>(A, [&](const GramCol &a, const GramCol &ec, int ab, int eb, double &lsum) {
+        bool eok[RPL];
+        int re[RPL];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const int qe = eb * 64 * RPL + q * 64 + lane;
+            eok[q] = qe < ec.n;
+            re[q] = eok[q] ? (int)gram_row(ec, qe) : zero_row;
+        }
         const int na = min(kGramTA, a.n - ab * kGramTA);
         const int ral = lane < na ? (int)gram_row(a, ab * kGramTA + lane) : zero_row;
-        KT acc[kGramTA];
+        KT acc[RPL][kGramTA];
 #pragma unroll
-        for (int i = 0; i < kGramTA; ++i)
-            acc[i] = 0;
-        for (int t0 = 0; t0 < d; t0 += kGramDC) {
-            KT ev[kGramDC];
-            const float *pe = pool32 + (int64_t)re * dp + t0;
+        for (int q = 0; q < RPL; ++q)
 #pragma unroll
-            for (int u = 0; u < kGramDC; u += 4) {
-                const f32x4 v = *(const f32x4 *)(pe + u);
-                ev[u] = (KT)v[0];
-                ev[u + 1] = (KT)v[1];
-                ev[u + 2] = (KT)v[2];
-                ev[u + 3] = (KT)v[3];
+            for (int i = 0; i < kGramTA; ++i)
+                acc[q][i] = 0;
+        for (int t0 = 0; t0 < d; t0 += DC) {
+            KT ev[RPL][DC];
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+                const float *pe = pool32 + (int64_t)re[q] * dp + t0;
+#pragma unroll
+                for (int u = 0; u < DC; u += 4) {
+                    const f32x4 v = *(const f32x4 *)(pe + u);
+                    ev[q][u] = (KT)v[0];
+                    ev[q][u + 1] = (KT)v[1];
+                    ev[q][u + 2] = (KT)v[2];
+                    ev[q][u + 3] = (KT)v[3];
+                }
             }
 #pragma unroll
             for (int i = 0; i < kGramTA; ++i) {
@@ -141,16 +160,23 @@ __global__ __launch_bounds__(kGramWG) void k_gram_valu(const GramWork A, int d, 
                     const int ra = __builtin_amdgcn_readlane(ral, i);
                     const float *pa = pool32 + (int64_t)ra * dp + t0;
 #pragma unroll
-                    for (int u = 0; u < kGramDC; ++u)
-                        gram_term<KIND, KT>(acc[i], (KT)pa[u], ev[u]);
+                    for (int u = 0; u < DC; ++u) {
+                        const KT au = (KT)pa[u];
+#pragma unroll
+                        for (int q = 0; q < RPL; ++q)
+                            gram_term<KIND, KT>(acc[q][i], au, ev[q][u]);
+                    }
                 }
             }
         }
-        if (eok) {
 #pragma unroll
-            for (int i = 0; i < kGramTA; ++i)
-                if (i < na)
-                    lsum += (double)gram_finish<KIND, KT>(acc[i], prm);
+        for (int q = 0; q < RPL; ++q) {
+            if (eok[q]) {
+#pragma unroll
+                for (int i = 0; i < kGramTA; ++i)
+                    if (i < na)
+                        lsum += (double)gram_finish<KIND, KT>(acc[q][i], prm);
+            }
         }
     });
 }
@@ -267,12 +293,14 @@ __global__ __launch_bounds__(256) void k_gram_fold(int k, int C, int rr, uint32_
     }
 }
 
-int gram_task_cols(int mfma) { return mfma ? 32 : kGramTEV; }
-
-void launch_gram_plan(const Layout &L, const Buffers &B, int rr, uint32_t mask, int mfma, hipStream_t st)
+int gram_task_cols(int mfma, int fp64)
 {
-    hipLaunchKernelGGL(k_gram_plan, dim3(1), dim3(1024), 0, st, L.k, L.C, rr, mask, gram_task_cols(mfma),
-                       B.ring_off, B.goff);
+    return mfma ? 32 : 64 * (fp64 ? gram_valu_rpl<double>() : gram_valu_rpl<float>());
+}
+
+void launch_gram_plan(const Layout &L, const Buffers &B, int rr, uint32_t mask, int te, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gram_plan, dim3(1), dim3(1024), 0, st, L.k, L.C, rr, mask, te, B.ring_off, B.goff);
 }
 
 template <typename KT>

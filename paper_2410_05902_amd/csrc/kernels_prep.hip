@@ -756,10 +756,9 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
 }
 
 void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
-                   int init_keep, const SlotList &live, int lr, uint32_t gram_mask, int gram_mfma, hipStream_t st)
+                   int init_keep, const SlotList &live, int lr, uint32_t gram_mask, int gram_te, hipStream_t st)
 {
     const int nchunk = (b + kChunk - 1) / kChunk;
-    const int gram_te = gram_task_cols(gram_mfma);
 #define MBKK_GO(LDS)                                                                                             \
     hipLaunchKernelGGL(k_group_offsets<LDS>, dim3(1), dim3(1024), 0, st, b, L.k, nchunk, L.C, p_new, p_expired,  \
                        init_alive_before, init_keep, live, lr, B.gcnt, B.gbase, B.mind, B.coef, B.cum, B.counts, \

@@ -256,7 +256,7 @@ static uint32_t col_mask_of(const SlotList &s, bool init_alive)
 static void gram(mbkk_ctx *c, int p, uint32_t mask, bool in_step)
 {
     if (!in_step)
-        launch_gram_plan(c->L, c->B, p, mask, c->use_mfma, c->stream);
+        launch_gram_plan(c->L, c->B, p, mask, gram_task_cols(c->use_mfma, c->fp64), c->stream);
     launch_gram(c->L, c->B, p, mask, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->use_mfma, c->cfg.precision,
                 !in_step, c->stream);
     if (in_step) {
@@ -549,8 +549,8 @@ int mbkk_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels_dev,
     const int p_expired = i - W >= 1 ? phys_of(i - W, P) : -1;
     const SlotList live_after = live_before(i + 1, W);
     const uint32_t mask = col_mask_of(live_after, init_keep);
-    launch_update(L, B, b, p_new, p_expired, init_alive_before, init_keep, live, c->cfg.lr, mask, c->use_mfma,
-                  c->stream);
+    launch_update(L, B, b, p_new, p_expired, init_alive_before, init_keep, live, c->cfg.lr, mask,
+                  gram_task_cols(c->use_mfma, c->fp64), c->stream);
     gram(c, p_new, mask, true);
     c->seg_next_iter = i + 1;
     HIPCHK(c, hipGetLastError());

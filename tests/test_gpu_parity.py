@@ -173,11 +173,18 @@ def test_c1_kmeanspp_picks(c1):
 # MFMA and BF16 forms, shapes of the larger workloads at reduced n
 # ---------------------------------------------------------------------------
 
-def _small_gmm(n, d, c, std, seed=0, scale=1.0):
+def _small_gmm(n, d, c, std, seed=0, scale=1.0, with_comp=False):
     rng = np.random.default_rng(seed)
     means = scale * rng.standard_normal((c, d))
     comp = rng.integers(0, c, n)
-    return (means[comp] + std * rng.standard_normal((n, d))).astype(np.float32)
+    X = (means[comp] + std * rng.standard_normal((n, d))).astype(np.float32)
+    return (X, comp) if with_comp else X
+
+
+def _one_per_component(comp, c):
+    """The first point of every component: initial centers without shared or
+    empty components, so that no exact tie decides a label."""
+    return np.array([np.flatnonzero(comp == j)[0] for j in range(c)], np.int32)
 
 
 @pytest.mark.parametrize("precision,impl", [("fp32", "mfma"), ("bf16x3", "mfma"), ("bf16x1", "mfma"),
@@ -280,6 +287,73 @@ def test_ragged_batch_sizes_mfma():
     init = rng.choice(5000, 10, replace=False).astype(np.int32)
     batches = [rng.integers(0, 5000, b).astype(np.int32) for b in (1, 129, 255, 77, 300)]
     lockstep(X, 10, 2, O.GAUSS, 40.0, init, batches, "fp32", "mfma", b_max=300)
+
+
+# ---------------------------------------------------------------------------
+# free-running steps: the paths that only consecutive iterations take (the
+# update writes the next segment offsets and the Gram task plan; the Gram
+# work is folded into G by the next support layout), for the VALU Gram with
+# two column rows per lane, both update kernels (k <= 512 and larger), the
+# MFMA Gram and FP64
+# ---------------------------------------------------------------------------
+
+def free_run(X, k, window, kind, param, init, batches, precision, impl="auto", threads=4):
+    """GPU and oracle from the same initial centers, no state import: labels
+    agree on rows with margin; while all labels agree, the self norms of the
+    centers after the last step agree with the oracle's.  Returns the number
+    of steps with identical labels."""
+    orc = O.Oracle(X, k, window, kind, param)
+    orc.init_centers(init)
+    model = _model(X, k, max(len(B) for B in batches), window, KNAME[kind], param, precision, impl)
+    model.init_centers(init)
+    same = 0
+    for B in batches:
+        ref = orc.step(B, threads=threads)
+        lab = model.step(B)["labels"].cpu().numpy()
+        ag = agreement(lab, ref["labels"], ref["margin"], MARGIN[precision])
+        assert ag["on_margin"], f"step {same + 1}: {ag['mismatches'][:8]}"
+        if not (lab == ref["labels"]).all():
+            return same  # a near tie parted the trajectories
+        same += 1
+    np.testing.assert_allclose(model.center_norms(), orc.norms(), rtol=max(TOL[precision], 1e-12),
+                               atol=1e-12 + TOL[precision] * 1e-3)
+    return same
+
+
+def test_free_running_laplace_two_rows_per_lane():
+    """d = 16 Laplacian FP32: direct cross kernel and VALU Gram with two rows per lane, k <= 512."""
+    wl = W.c5_laplace_mixture(seed=1, n=12000, d=16, c=20)
+    init = _one_per_component(wl.comp, 20)
+    rng = np.random.default_rng(30)
+    batches = [rng.integers(0, wl.n, 700).astype(np.int32) for _ in range(8)]
+    assert free_run(wl.X, 20, 3, wl.kernel, 8.0, init, batches, "fp32") == 8
+
+
+def test_free_running_large_k_general_update():
+    """k = 600 with 32 chunks per batch: the general update kernel (counts in global memory)."""
+    wl = W.c5_laplace_mixture(seed=2, n=30000, d=32, c=600)
+    init = _one_per_component(wl.comp, 600)
+    rng = np.random.default_rng(31)
+    batches = [rng.integers(0, wl.n, 2048).astype(np.int32) for _ in range(4)]
+    assert free_run(wl.X, 600, 2, wl.kernel, 20.0, init, batches, "fp32") == 4
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "fp32"])
+def test_free_running_mfma(precision):
+    X, comp = _small_gmm(8000, 64, 12, 0.3, seed=32, with_comp=True)
+    sigma = W.median_pairwise_distance(X, 0)
+    rng = np.random.default_rng(33)
+    batches = [rng.integers(0, 8000, 512).astype(np.int32) for _ in range(8)]
+    same = free_run(X, 12, 3, O.GAUSS, 2 * sigma * sigma, _one_per_component(comp, 12), batches, precision,
+                    "mfma")
+    assert same == 8
+
+
+def test_free_running_fp64_direct():
+    X, comp = _small_gmm(3000, 8, 6, 0.4, seed=34, with_comp=True)
+    rng = np.random.default_rng(35)
+    batches = [rng.integers(0, 3000, 200).astype(np.int32) for _ in range(8)]
+    assert free_run(X, 6, 3, O.GAUSS, 4.0, _one_per_component(comp, 6), batches, "fp64", "direct") == 8
 
 
 def test_bad_index_and_nonfinite_are_errors():
