@@ -931,9 +931,11 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
                             __builtin_amdgcn_exp2f(fmaf(accP[nbk][i], c2, eay[i / 4][i % 4])), run[nbk]);
         }
     };
-    // Carried support fragments of k-step 0 of the next block.
+    // Carried support fragments of the next block: k-step 0 (a0h / a0l) and,
+    // in the BF16 forms, k-step 1 (a1h / a1l): the BF16 fragments are read two
+    // k-steps ahead of their MFMAs.
     typedef typename std::conditional<F32, f32x4, bf16x8>::type afrag_t;
-    afrag_t a0h, a0l;
+    afrag_t a0h, a0l, a1h, a1l;
     auto load_a0 = [&](auto bc, int sub) {
         const char *base = bufA(bc) + sub * 32 * CPS * 16 + aoff;
         if constexpr (F32) {
@@ -942,6 +944,14 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
             a0h = __builtin_bit_cast(bf16x8, *(const u16x8 *)base);
             if constexpr (X3)
                 a0l = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + ABYTES));
+        }
+    };
+    auto load_a1 = [&](auto bc, int sub) {  // BF16: k-step 1 of block sub
+        if constexpr (!F32) {
+            const char *base = bufA(bc) + sub * 32 * CPS * 16 + aoff + 32;
+            a1h = __builtin_bit_cast(bf16x8, *(const u16x8 *)base);
+            if constexpr (X3)
+                a1l = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + ABYTES));
         }
     };
     // The element range of MFMA mi: the epilogue is spread evenly; rows 0-7
@@ -994,17 +1004,21 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
                 av = an;
             }
         } else {
-            bf16x8 ah = a0h, ahn = a0h;
-            bf16x8 al = a0l, aln = a0l;  // lo fragments: BF16X3 only
+            static_assert(F32 || KS >= 2, "BF16 fragments are read two k-steps ahead");
+            bf16x8 ah = a0h, ah1 = a1h, ahn = a0h;
+            bf16x8 al = a0l, al1 = a1l, aln = a0l;  // lo fragments: BF16X3 only
             constexpr int NP = X3 ? 3 : 1;  // products per (k-step, N-block)
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                if (ks + 1 < KS) {
-                    ahn = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + (ks + 1) * 32));
+                if (ks + 2 < KS) {
+                    ahn = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + (ks + 2) * 32));
                     if constexpr (X3)
-                        aln = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + ABYTES + (ks + 1) * 32));
+                        aln = __builtin_bit_cast(bf16x8, *(const u16x8 *)(base + ABYTES + (ks + 2) * 32));
                 } else if (nsub >= 0) {
-                    load_a0(bc, nsub);
+                    if (ks + 2 == KS)
+                        load_a0(bc, nsub);
+                    else
+                        load_a1(bc, nsub);
                 }
 #pragma unroll
                 for (int pr = 0; pr < NP; ++pr)
@@ -1018,9 +1032,12 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
                         hook(mi);
                         __builtin_amdgcn_sched_barrier(0);
                     }
-                ah = ahn;
-                if constexpr (X3)
-                    al = aln;
+                ah = ah1;
+                ah1 = ahn;
+                if constexpr (X3) {
+                    al = al1;
+                    al1 = aln;
+                }
             }
         }
     };
@@ -1073,6 +1090,8 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
             }
         }
         load_a0(bc, 0);
+        if constexpr (!F32)
+            load_a1(bc, 0);
 #pragma unroll
         for (int k = 0; k < SB; ++k) {
             // block bp + k; epilogue of block bp + k - 1; staging items of the next stage
