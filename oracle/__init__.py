@@ -47,6 +47,8 @@ def lib():
         L.orc_create.restype = P
         L.orc_create.argtypes = [P, I64, I32, I32, I32, I32, D, I32]
         L.orc_destroy.argtypes = [P]
+        L.orc_set_tau.restype = C.c_int
+        L.orc_set_tau.argtypes = [P, I32]
         L.orc_init_centers.restype = C.c_int
         L.orc_init_centers.argtypes = [P, P]
         L.orc_set_centers.restype = C.c_int
@@ -103,13 +105,16 @@ class Oracle:
     """One run of truncated mini-batch kernel k-means, in FP64 on one core."""
 
     def __init__(self, X: np.ndarray, k: int, window: int, kernel: int, param: float,
-                 lr: int = LR_BETA):
+                 lr: int = LR_BETA, tau: int = 0):
         self.X = np.ascontiguousarray(X, dtype=np.float32)   # kept alive: borrowed by C
         self.k, self.window, self.kernel, self.param, self.lr = k, window, kernel, param, lr
+        self.tau = tau
         self._m = lib().orc_create(_p(self.X), self.X.shape[0], self.X.shape[1], k, window,
                                    kernel, param, lr)
         if not self._m:
             raise ValueError("invalid oracle configuration")
+        if tau and lib().orc_set_tau(self._m, tau) != 0:
+            raise ValueError("invalid tau")
 
     def __del__(self):
         m, self._m = getattr(self, "_m", None), None

@@ -32,6 +32,11 @@
  * Readings of the paper that this file fixes (each listed in the design notes):
  *   window W >= 1: after iteration i a center keeps batches
  *     max(1, i-W+1) .. i, plus the initial term while i <= W; W = 0 keeps all.
+ *   tau > 0 (the rule of Section 4.1, applied within the window): Q_i^j runs
+ *     from batch i down to the newest batch l at which the counts
+ *     b_i^j + ... + b_l^j (the paper's sum over Q, read with b_l^j) reach tau;
+ *     batches older than l and the initial term are dropped when l > 1; if the
+ *     counts reach tau only at batch 1, or never, the center is untruncated.
  *   no renormalisation after truncation (Eq. 1 drops terms, nothing rescales).
  *   empty cluster: b_i^j = 0 gives alpha = 0 and adds no term.
  *   batches are tuples: a point drawn twice counts twice.
@@ -111,6 +116,7 @@ typedef struct {
     const float *X;   /* borrowed (n x d) row-major FP32 */
     int64_t n;
     int32_t d, k, W, kind, lr;
+    int32_t tau;      /* 0: window only; > 0: the per-center rule of Section 4.1 */
     double param;
     int64_t iter;     /* index i of the next batch (starts at 1) */
     orc_center *c;
@@ -151,6 +157,15 @@ static void center_push(orc_center *c, int64_t tag, double coef, int32_t npts, c
     t->npts = npts;
     t->pts = (int32_t *)malloc(sizeof(int32_t) * (size_t)(npts > 0 ? npts : 1));
     memcpy(t->pts, pts, sizeof(int32_t) * (size_t)npts);
+}
+
+/* The count threshold tau of Section 4.1 (0: the window alone truncates). */
+int orc_set_tau(orc_model *m, int32_t tau)
+{
+    if (!m || tau < 0)
+        return -1;
+    m->tau = tau;
+    return 0;
 }
 
 orc_model *orc_create(const float *X, int64_t n, int32_t d, int32_t k, int32_t W,
@@ -415,6 +430,31 @@ int orc_update(orc_model *m, const int32_t *batch, int32_t b, const int32_t *lab
                     free(c->t[g].pts);
             }
             c->nterms = w;
+        }
+        /* Truncation by count (Section 4.1): Q_i^j = {i, i-1, ..., lmin} with
+         * lmin the newest batch at which b_i^j + ... + b_lmin^j >= tau.  When
+         * lmin > 1 the terms of batches older than lmin and the initial term
+         * go; otherwise (lmin = 1, or the counts never reach tau) nothing. */
+        if (m->tau > 0) {
+            int64_t lmin = 0;  /* 0: tau not reached */
+            int64_t sum = 0;
+            for (int64_t l = i; l >= 1 && lmin == 0; --l) {
+                for (int g = 0; g < c->nterms; ++g)
+                    if (c->t[g].tag == l)
+                        sum += c->t[g].npts;
+                if (sum >= m->tau)
+                    lmin = l;
+            }
+            if (lmin > 1) {
+                int w = 0;
+                for (int g = 0; g < c->nterms; ++g) {
+                    if (c->t[g].tag >= lmin)
+                        c->t[w++] = c->t[g];
+                    else
+                        free(c->t[g].pts);
+                }
+                c->nterms = w;
+            }
         }
     }
     m->iter = i + 1;

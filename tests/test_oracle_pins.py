@@ -482,6 +482,54 @@ def test_window_one_keeps_only_last_batch():
         assert set(s["term_tag"].tolist()) <= ({0, 1} if i == 1 else {i})
 
 
+def test_tau_truncation_rule():
+    """Section 4.1: after iteration i a center keeps Q_i^j = {i, ..., lmin},
+    lmin the newest batch at which b_i^j + ... + b_lmin^j >= tau, and drops the
+    older batches and the initial term when lmin > 1; reaching tau only at
+    batch 1, or not at all, leaves the center untruncated.  The kept terms
+    keep their untruncated coefficients (nothing is renormalised).  Counts
+    scripted through the labels; the expected sets are derived by hand."""
+    X = small_data(seed=40, n=60, d=2)
+    tau = 5
+    counts0 = [3, 1, 2, 4, 0, 5, 1, 1, 1, 2]
+    expect0 = [{0, 1}, {0, 1, 2}, {0, 1, 2, 3}, {3, 4}, {3, 4}, {6}, {6, 7}, {6, 7, 8}, {6, 7, 8, 9},
+               {7, 8, 9, 10}]
+    with_tau = O.Oracle(X, 2, 20, O.GAUSS, 1.0, tau=tau)
+    plain = O.Oracle(X, 2, 20, O.GAUSS, 1.0)
+    for o in (with_tau, plain):
+        o.init_centers(np.array([0, 1], np.int32))
+    rng = np.random.default_rng(41)
+    for i, c0 in enumerate(counts0, start=1):
+        B = rng.integers(2, 60, c0 + 3).astype(np.int32)
+        lab = np.array([0] * c0 + [1] * 3, np.int32)
+        with_tau.update(B, lab)
+        plain.update(B, lab)
+        st, sp = with_tau.state(), plain.state()
+        tags = set(st["term_tag"][st["term_center"] == 0].tolist())
+        assert tags == expect0[i - 1], (i, tags)
+        ref = {t: c for t, c, j in zip(sp["term_tag"], sp["term_coef"], sp["term_center"]) if j == 0}
+        for t, cf, j in zip(st["term_tag"], st["term_coef"], st["term_center"]):
+            if j == 0:
+                assert cf == ref[t]
+        # center 1 gets 3 points per batch: at i = 2 the counts reach tau only
+        # at batch 1 (untruncated); from i = 3 on at batch i - 1
+        tags1 = set(st["term_tag"][st["term_center"] == 1].tolist())
+        assert tags1 == ({0, 1} if i == 1 else {0, 1, 2} if i == 2 else {i - 1, i}), (i, tags1)
+
+
+def test_tau_huge_is_untruncated_and_window_caps():
+    """tau above every count total: the run equals the window rule alone."""
+    X = small_data(seed=42, n=50, d=3)
+    a = O.Oracle(X, 3, 3, O.GAUSS, 2.0, tau=10 ** 6)
+    b = O.Oracle(X, 3, 3, O.GAUSS, 2.0)
+    for o in (a, b):
+        o.init_centers(np.array([0, 1, 2], np.int32))
+    for B in batches_for(50, 7, 6, seed=43):
+        ra, rb = a.step(B), b.step(B)
+        np.testing.assert_array_equal(ra["labels"], rb["labels"])
+        np.testing.assert_array_equal(ra["D"], rb["D"])
+
+
 # --------------------------------------------------------------------------
 # kernel k-means++ (first pick uniform, then proportional to D^2)
 # --------------------------------------------------------------------------
