@@ -96,6 +96,11 @@ typedef struct {
     int32_t cross_impl;  /* MBKK_CROSS_AUTO ...                                  */
     double tie_delta;    /* BF16 forms: FP64 re-scoring threshold; <= 0: bound   */
     int32_t validate;    /* non-zero: report bad indices / non-finite rows       */
+    int32_t tau;         /* 0: the window alone truncates; > 0: also the count   */
+                         /* rule of Section 4.1: a center keeps its newest       */
+                         /* batches (within the window) up to the one at which   */
+                         /* its counts reach tau, and drops the older ones and   */
+                         /* its initial point unless that is batch 1             */
 } mbkk_config;
 
 typedef struct mbkk_ctx mbkk_ctx;

@@ -36,7 +36,7 @@ class Config(C.Structure):
         ("n", C.c_int64), ("d", C.c_int32), ("k", C.c_int32), ("b_max", C.c_int32),
         ("window", C.c_int32), ("kernel", C.c_int32), ("kernel_param", C.c_double),
         ("precision", C.c_int32), ("lr", C.c_int32), ("cross_impl", C.c_int32),
-        ("tie_delta", C.c_double), ("validate", C.c_int32),
+        ("tie_delta", C.c_double), ("validate", C.c_int32), ("tau", C.c_int32),
     ]
 
 

@@ -128,23 +128,24 @@ __device__ __forceinline__ int64_t gram_row(const GramCol &g, int q) { return g.
 // one workgroup (blockDim.x a multiple of 64, at most 1024).  Thread t owns
 // the centers [t * per, (t + 1) * per), per = ceil(k / blockDim.x); na_own,
 // if given, holds the row counts of slot rr for those centers (written by the
-// same threads), else they come from ring_off of slot rr.  `sint`: 16 ints of LDS.
+// same threads), else they come from ring_off of slot rr; coef: the centers'
+// column weights, columns of weight 0 having no tasks.  `sint`: 16 ints of LDS.
 // With seg_next, the same pass also writes the segment offsets of the support
 // whose columns are `mask` (each center's rows over those columns, padded to
 // a multiple of pad): the layout of the next iteration when mask holds its
 // live columns.
 __device__ __forceinline__ void gram_plan(int k, int C, int rr, uint32_t mask, int te,
                                           const int32_t *__restrict__ ring_off, const int32_t *na_own,
-                                          int32_t *__restrict__ goff, int *sint, int pad = 1,
-                                          int32_t *__restrict__ seg_next = nullptr)
+                                          const double *coef, int32_t *__restrict__ goff, int *sint,
+                                          int pad = 1, int32_t *__restrict__ seg_next = nullptr)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int per = (k + nt - 1) / nt;
     const int j0 = min(k, tid * per), j1 = min(k, j0 + per);
     const int32_t *orr = ring_off + (int64_t)rr * (k + 1);
     auto rows = [&](int j, int c, int na) -> int {  // rows of center j in live column c
-        if (!((mask >> c) & 1u))
-            return 0;
+        if (!((mask >> c) & 1u) || coef[(int64_t)j * C + c] == 0.0)
+            return 0;  // (a column of weight 0 is left out of the support)
         if (c == 0)
             return 1;
         if (c - 1 == rr)

@@ -24,8 +24,11 @@ void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const 
 // The update also writes the task plan of the new slot's Gram blocks against
 // the columns in gram_mask (tasks gram_te column rows wide), and the
 // segment offsets of the support over those columns into B.seg_next.
+// win: the window after the update and tau (> 0: the count truncation of
+// each center, whose dropped columns get coefficient 0).
 void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
-                   int init_keep, const SlotList &live, int lr, uint32_t gram_mask, int gram_te, hipStream_t st);
+                   int init_keep, const SlotList &live, const WindowRank &win, int lr, uint32_t gram_mask,
+                   int gram_te, hipStream_t st);
 
 // Gram blocks of slot rr against the columns in col_mask: plan (when not made
 // by the update), then work and fold.  mfma: the Gaussian MFMA forms, with

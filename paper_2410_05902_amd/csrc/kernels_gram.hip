@@ -266,10 +266,11 @@ __global__ __launch_bounds__(kGramWG) void k_gram_mfma(const GramWork A, int dp_
 // plan (outside a step) and fold
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_gram_plan(int k, int C, int rr, uint32_t mask, int te,
-                                                    const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff)
+                                                    const int32_t *__restrict__ ring_off,
+                                                    const double *__restrict__ coef, int32_t *__restrict__ goff)
 {
     __shared__ int sint[16];
-    gram_plan(k, C, rr, mask, te, ring_off, nullptr, goff, sint);
+    gram_plan(k, C, rr, mask, te, ring_off, nullptr, coef, goff, sint);
 }
 
 // One wave per jc (gram_fold_jc).  In a step the fold runs instead inside
@@ -300,7 +301,8 @@ int gram_task_cols(int mfma, int fp64)
 
 void launch_gram_plan(const Layout &L, const Buffers &B, int rr, uint32_t mask, int te, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gram_plan, dim3(1), dim3(1024), 0, st, L.k, L.C, rr, mask, te, B.ring_off, B.goff);
+    hipLaunchKernelGGL(k_gram_plan, dim3(1), dim3(1024), 0, st, L.k, L.C, rr, mask, te, B.ring_off, B.coef,
+                       B.goff);
 }
 
 template <typename KT>

@@ -226,11 +226,16 @@ void launch_init_state(const Layout &L, const Buffers &B, int kind, double param
 //   N_j = <C_j, C_j> = sum_{c,c'} coef[j][c] coef[j][c'] G_j[c][c']
 // over the live columns (FP64).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int seg_len(int j, int k, const int32_t *__restrict__ ring_off, const SlotList &live,
-                                       int init_alive)
+// Rows of center j's support: the initial point while alive and the center's
+// rows of every live slot, columns of weight 0 left out (their terms are zero).
+__device__ __forceinline__ int seg_len(int j, int k, int C, const int32_t *__restrict__ ring_off,
+                                       const double *__restrict__ coef, const SlotList &live, int init_alive)
 {
-    int len = init_alive;
+    const double *cf = coef + (int64_t)j * C;
+    int len = init_alive && cf[0] != 0.0 ? 1 : 0;
     for (int s = 0; s < live.n; ++s) {
+        if (cf[1 + live.r[s]] == 0.0)
+            continue;
         const int32_t *o = ring_off + (int64_t)live.r[s] * (k + 1);
         len += o[j + 1] - o[j];
     }
@@ -312,7 +317,7 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
         // exclusive prefix of the padded lengths of centers < j
         int acc = 0;
         for (int q = tid; q < j; q += 256) {
-            const int l = seg_len(q, k, ring_off, live, init_alive);
+            const int l = seg_len(q, k, C, ring_off, coef, live, init_alive);
             acc += (l + pad - 1) / pad * pad;
         }
         red[tid] = acc;
@@ -322,7 +327,7 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
                 red[tid] += red[tid + s];
             __syncthreads();
         }
-        const int len = seg_len(j, k, ring_off, live, init_alive);
+        const int len = seg_len(j, k, C, ring_off, coef, live, init_alive);
         plen = (len + pad - 1) / pad * pad;
         if (tid == 0) {
             sh_start = red[0];
@@ -334,7 +339,7 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
         start = sh_start;
     }
     int pos = start;
-    if (init_alive) {
+    if (init_alive && coef[(int64_t)j * C + 0] != 0.0) {
         if (tid == 0) {
             const double w = coef[(int64_t)j * C + 0];
             sup_row[pos] = j;
@@ -349,8 +354,10 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
         const int p = live.r[s];
         const int32_t *o = ring_off + (int64_t)p * (k + 1);
         const int32_t *perm = ring_perm + (int64_t)p * bmax;
-        const int a0 = o[j], a1 = o[j + 1];
         const double w = coef[(int64_t)j * C + 1 + p];
+        if (w == 0.0)
+            continue;  // (block uniform)
+        const int a0 = o[j], a1 = o[j + 1];
         const int64_t row0 = (int64_t)k + (int64_t)p * bmax;
         for (int q = tid; q < a1 - a0; q += 256) {
             const int64_t row = row0 + perm[a0 + q];
@@ -457,7 +464,7 @@ constexpr int kGroupLdsMax = 8192;
 template <bool LDS>
 __global__ __launch_bounds__(1024) void k_group_offsets(
     int b, int k, int nchunk, int C, int p_new, int p_expired, int init_alive_before, int init_keep,
-    SlotList live, int lr, const int32_t *__restrict__ gcnt, int32_t *__restrict__ gbase,
+    SlotList live, WindowRank win, int lr, const int32_t *__restrict__ gcnt, int32_t *__restrict__ gbase,
     const float *__restrict__ mind,
     double *__restrict__ coef, double *__restrict__ cum, int32_t *__restrict__ counts,
     double *__restrict__ alpha, int32_t *__restrict__ off, double *__restrict__ obj,
@@ -533,12 +540,32 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
             cf[1 + p_expired] = 0.0;
         if (!init_keep)
             cf[0] = 0.0;
+        // and by count (Section 4.1), as in the small variant
+        if (win.tau > 0) {
+            int sum = 0, q0 = -1;
+            for (int q = win.n - 1; q >= 0 && q0 < 0; --q) {
+                for (int p = 0; p < C - 1; ++p) {
+                    if (win.rank[p] == q) {
+                        const int32_t *o = ring_off + (int64_t)p * (k + 1);
+                        sum += p == p_new ? bj : o[j + 1] - o[j];
+                    }
+                }
+                if (sum >= win.tau)
+                    q0 = q;
+            }
+            if (q0 >= 0 && win.first + q0 > 1) {
+                cf[0] = 0.0;
+                for (int p = 0; p < C - 1; ++p)
+                    if (win.rank[p] >= 0 && win.rank[p] < q0)
+                        cf[1 + p] = 0.0;
+            }
+        }
     }
     if (tid == 0)
         off[k] = b;
     // task offsets of the Gram blocks of the new slot (its counts are this
     // thread's b_i^j above; the other live slots' offsets are settled)
-    gram_plan(k, C, p_new, gram_mask, gram_te, ring_off, counts, goff, sint, pad, seg_next);
+    gram_plan(k, C, p_new, gram_mask, gram_te, ring_off, counts, coef, goff, sint, pad, seg_next);
     // sum of min distances (FP64), fixed order
     double sm = 0.0;
     for (int p = tid; p < b; p += nt)
@@ -565,7 +592,7 @@ constexpr int kGroupSmallK = 512, kGroupSmallC = 8, kGroupThreads = 1024;
 
 __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
     int b, int k, int nchunk, int C, int p_new, int p_expired, int init_alive_before, int init_keep,
-    SlotList live, int lr, const int32_t *__restrict__ gcnt, const float *__restrict__ mind,
+    SlotList live, WindowRank win, int lr, const int32_t *__restrict__ gcnt, const float *__restrict__ mind,
     double *__restrict__ coef, double *__restrict__ cum, int32_t *__restrict__ counts,
     double *__restrict__ alpha, int32_t *__restrict__ off, double *__restrict__ obj,
     const int32_t *__restrict__ labels, const int32_t *__restrict__ rank, const int32_t *__restrict__ pts,
@@ -699,14 +726,40 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
                 if (p == p_expired)
                     v = 0.0;
             }
-            coef[(int64_t)j * C + c] = v;
+            cf[c] = v;
         }
-        // Gram tasks of the new slot against the live columns, and the
-        // padded segment of center j in the next iteration's support
+        // and by count (Section 4.1): the newest batches up to the one at
+        // which the counts reach tau stay; older ones and the initial point
+        // go when that batch is not the first
+        if (win.tau > 0) {
+            int sum = 0, q0 = -1;
+            for (int q = win.n - 1; q >= 0 && q0 < 0; --q) {
+                int cq = 0;
+#pragma unroll
+                for (int c = 1; c < kGroupSmallC; ++c)
+                    if (c < C && win.rank[c - 1] == q)
+                        cq = c - 1 == p_new ? bj : ne[c];
+                sum += cq;
+                if (sum >= win.tau)
+                    q0 = q;
+            }
+            if (q0 >= 0 && win.first + q0 > 1) {
+#pragma unroll
+                for (int c = 0; c < kGroupSmallC; ++c)
+                    if (c < C && (c == 0 || win.rank[c - 1] < q0))
+                        cf[c] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < kGroupSmallC; ++c)
+            if (c < C)
+                coef[(int64_t)j * C + c] = cf[c];
+        // Gram tasks of the new slot against the live columns that keep a
+        // weight, and the padded segment of center j in the next support
         const int nA = (bj + kGramTA - 1) / kGramTA;
 #pragma unroll
         for (int c = 0; c < kGroupSmallC; ++c) {
-            if (c < C && ((gram_mask >> c) & 1u)) {
+            if (c < C && ((gram_mask >> c) & 1u) && cf[c] != 0.0) {
                 const int nec = c == 0 ? 1 : (c - 1 == p_new ? bj : ne[c]);
                 tasks += nA * ((nec + gram_te - 1) / gram_te);
                 slen += nec;
@@ -724,11 +777,14 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
     int trun = block_exclusive_scan(tasks, sint, &ttotal);  // (its barriers also publish the bases)
     if (own) {
         const int nA = (bj + kGramTA - 1) / kGramTA;
-        for (int c = 0; c < C; ++c) {
-            goff[(int64_t)j * C + c] = trun;
-            if ((gram_mask >> c) & 1u) {
-                const int nec = c == 0 ? 1 : (c - 1 == p_new ? bj : ne[c]);
-                trun += nA * ((nec + gram_te - 1) / gram_te);
+#pragma unroll
+        for (int c = 0; c < kGroupSmallC; ++c) {
+            if (c < C) {
+                goff[(int64_t)j * C + c] = trun;
+                if (((gram_mask >> c) & 1u) && cf[c] != 0.0) {
+                    const int nec = c == 0 ? 1 : (c - 1 == p_new ? bj : ne[c]);
+                    trun += nA * ((nec + gram_te - 1) / gram_te);
+                }
             }
         }
     }
@@ -756,19 +812,21 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
 }
 
 void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
-                   int init_keep, const SlotList &live, int lr, uint32_t gram_mask, int gram_te, hipStream_t st)
+                   int init_keep, const SlotList &live, const WindowRank &win, int lr, uint32_t gram_mask,
+                   int gram_te, hipStream_t st)
 {
     const int nchunk = (b + kChunk - 1) / kChunk;
 #define MBKK_GO(LDS)                                                                                             \
     hipLaunchKernelGGL(k_group_offsets<LDS>, dim3(1), dim3(1024), 0, st, b, L.k, nchunk, L.C, p_new, p_expired,  \
-                       init_alive_before, init_keep, live, lr, B.gcnt, B.gbase, B.mind, B.coef, B.cum, B.counts, \
+                       init_alive_before, init_keep, live, win, lr, B.gcnt, B.gbase, B.mind, B.coef, B.cum,      \
+                       B.counts,                                                                                 \
                        B.alpha, B.ring_off + (int64_t)p_new * (L.k + 1), B.obj, B.labels, B.rank,                 \
                        B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,               \
                        B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_te, B.ring_off, B.goff, L.pad,  \
                        B.seg_next)
     if (L.k <= kGroupSmallK && (int64_t)nchunk * L.k <= kGroupLdsMax && L.C <= kGroupSmallC)
         hipLaunchKernelGGL(k_group_offsets_small, dim3(1), dim3(kGroupThreads), 0, st, b, L.k, nchunk, L.C, p_new,
-                           p_expired, init_alive_before, init_keep, live, lr, B.gcnt, B.mind, B.coef, B.cum,
+                           p_expired, init_alive_before, init_keep, live, win, lr, B.gcnt, B.mind, B.coef, B.cum,
                            B.counts, B.alpha, B.ring_off + (int64_t)p_new * (L.k + 1), B.obj, B.labels, B.rank,
                            B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,
                            B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_te, B.ring_off, B.goff, L.pad,

@@ -187,6 +187,10 @@ static int check_config(const mbkk_config *c, std::string &why)
         why = "need 1 <= b_max <= 8192";
         return MBKK_E_INVALID;
     }
+    if (c->tau < 0) {
+        why = "need tau >= 0";
+        return MBKK_E_INVALID;
+    }
     if (c->window < 1 || c->window > kMaxWindow) {
         why = "need 1 <= window <= 30";
         return MBKK_E_INVALID;
@@ -549,7 +553,15 @@ int mbkk_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels_dev,
     const int p_expired = i - W >= 1 ? phys_of(i - W, P) : -1;
     const SlotList live_after = live_before(i + 1, W);
     const uint32_t mask = col_mask_of(live_after, init_keep);
-    launch_update(L, B, b, p_new, p_expired, init_alive_before, init_keep, live, c->cfg.lr, mask,
+    WindowRank win;
+    win.n = live_after.n;
+    win.tau = c->cfg.tau;
+    win.first = i + 1 - W < 1 ? 1 : i + 1 - W;  // batch of live_after.r[0]
+    for (int p = 0; p < kMaxSlots; ++p)
+        win.rank[p] = -1;
+    for (int q = 0; q < live_after.n; ++q)
+        win.rank[live_after.r[q]] = q;
+    launch_update(L, B, b, p_new, p_expired, init_alive_before, init_keep, live, win, c->cfg.lr, mask,
                   gram_task_cols(c->use_mfma, c->fp64), c->stream);
     gram(c, p_new, mask, true);
     c->seg_next_iter = i + 1;
@@ -810,7 +822,9 @@ int mbkk_set_state(mbkk_ctx *c, const mbkk_state *s)
     for (int64_t l = lo; l <= i - 1; ++l) {
         const int r = (int)((l - 1) % W);
         const int32_t *off = s->slot_off + (int64_t)r * (L.k + 1);
-        if (s->slot_b[r] < 1 || s->slot_b[r] > L.bmax || off[0] != 0 || off[L.k] != s->slot_b[r])
+        // (a live slot may hold no points: with tau every center can have
+        // dropped that batch)
+        if (s->slot_b[r] < 0 || s->slot_b[r] > L.bmax || off[0] != 0 || off[L.k] != s->slot_b[r])
             return fail(c, MBKK_E_INVALID, "slot offsets inconsistent with slot sizes");
         for (int j = 0; j < L.k; ++j)
             if (off[j + 1] < off[j])

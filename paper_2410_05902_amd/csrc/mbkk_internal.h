@@ -38,6 +38,15 @@ struct SlotList {
     int r[kMaxSlots];
 };
 
+// The window after an update, for the count truncation (tau > 0): the rank
+// (0 = oldest) of each physical slot in it, -1 outside; rank q holds batch
+// first + q.
+struct WindowRank {
+    int n, tau;
+    int64_t first;
+    int rank[kMaxSlots];
+};
+
 // Bit-level bf16 helpers (round to nearest even): hi = bf16(x), lo = bf16(x - hi).
 __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x)
 {

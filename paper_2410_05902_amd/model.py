@@ -34,7 +34,8 @@ class Model:
 
     def __init__(self, X: torch.Tensor, k: int, b_max: int, window: int, kernel="gauss",
                  kernel_param: float = 1.0, precision="fp32", lr="beta", cross_impl="auto",
-                 tie_delta: float = 0.0, validate: bool = True, stream: Optional[torch.cuda.Stream] = None):
+                 tie_delta: float = 0.0, validate: bool = True, stream: Optional[torch.cuda.Stream] = None,
+                 tau: int = 0):
         if not (X.is_cuda and X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1):
             raise ValueError("X must be a row-major float32 CUDA tensor")
         self.X = X
@@ -44,7 +45,7 @@ class Model:
                             kernel=_code(_KERNELS, kernel), kernel_param=float(kernel_param),
                             precision=_code(_PREC, precision), lr=_code(_LR, lr),
                             cross_impl=_code(_IMPL, cross_impl), tie_delta=float(tie_delta),
-                            validate=1 if validate else 0)
+                            validate=1 if validate else 0, tau=int(tau))
         lib = L.lib()
         nbytes = C.c_size_t()
         L.check(lib.mbkk_workspace_size(C.byref(self.cfg), C.byref(nbytes)))

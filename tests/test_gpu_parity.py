@@ -21,11 +21,11 @@ TOL = {"fp64": 1e-9, "fp32": 1e-5, "bf16x3": 1e-2, "bf16x1": 1e-2}
 MARGIN = {"fp64": 1e-9, "fp32": 1e-4, "bf16x3": 1e-4, "bf16x1": 1e-2}
 
 
-def _model(X, k, b_max, window, kernel, param, precision, impl="auto", lr="beta", tie=0.0):
+def _model(X, k, b_max, window, kernel, param, precision, impl="auto", lr="beta", tie=0.0, tau=0):
     from paper_2410_05902_amd import Model
     Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
     return Model(Xd, k=k, b_max=b_max, window=window, kernel=kernel, kernel_param=param,
-                 precision=precision, lr=lr, cross_impl=impl, tie_delta=tie)
+                 precision=precision, lr=lr, cross_impl=impl, tie_delta=tie, tau=tau)
 
 
 KNAME = {O.GAUSS: "gauss", O.LAPLACE: "laplace", O.LINEAR: "linear", O.POLY2: "poly2"}
@@ -67,15 +67,15 @@ def lockstep(X, k, window, kind, param, init, batches, precision, impl="auto", l
 
 
 def _step_and_compare_state(X, k, window, kind, param, init, batches, precision, impl="auto",
-                            lr=W.LR_BETA, b_max=None):
+                            lr=W.LR_BETA, b_max=None, tau=0):
     """Lock-step on full iterations: import the oracle state, run one GPU step
     and one oracle step on the same batch, compare labels, min distance and the
     updated state."""
     b_max = b_max or max(len(B) for B in batches)
     lrname = {W.LR_BETA: "beta", W.LR_FULL: "full", W.LR_SKLEARN: "sklearn"}[lr]
-    orc = O.Oracle(X, k, window, kind, param, lr)
+    orc = O.Oracle(X, k, window, kind, param, lr, tau=tau)
     orc.init_centers(init)
-    model = _model(X, k, b_max, window, KNAME[kind], param, precision, impl, lrname)
+    model = _model(X, k, b_max, window, KNAME[kind], param, precision, impl, lrname, tau=tau)
     model.init_centers(init)
     tol, mmin = TOL[precision], MARGIN[precision]
     compared = 0
@@ -98,11 +98,21 @@ def _step_and_compare_state(X, k, window, kind, param, init, batches, precision,
             so = oracle_state_to_gpu(orc.state(), init, k, window, b_max)
             assert sg["iteration"] == so["iteration"]
             live = [((l - 1) % window) for l in range(max(1, i - window + 1), i + 1)]
-            for r in live:
-                assert sg["slot_b"][r] == so["slot_b"][r]
-                np.testing.assert_array_equal(sg["slot_off"][r], so["slot_off"][r])
-                np.testing.assert_array_equal(sg["slot_idx"][r, : so["slot_b"][r]],
-                                              so["slot_idx"][r, : so["slot_b"][r]])
+            if tau == 0:
+                for r in live:
+                    assert sg["slot_b"][r] == so["slot_b"][r]
+                    np.testing.assert_array_equal(sg["slot_off"][r], so["slot_off"][r])
+                    np.testing.assert_array_equal(sg["slot_idx"][r, : so["slot_b"][r]],
+                                                  so["slot_idx"][r, : so["slot_b"][r]])
+            else:
+                # the oracle drops a truncated center's points, the ring keeps
+                # them at weight 0: compare each center's weighted points
+                for r in live:
+                    for c in range(k):
+                        if so["coef"][c, 1 + r] != 0.0:
+                            a = sg["slot_idx"][r, sg["slot_off"][r][c]: sg["slot_off"][r][c + 1]]
+                            b = so["slot_idx"][r, so["slot_off"][r][c]: so["slot_off"][r][c + 1]]
+                            np.testing.assert_array_equal(a, b)
             cols = ([0] if i <= window else []) + [1 + r for r in live]
             np.testing.assert_allclose(sg["coef"][:, cols], so["coef"][:, cols], rtol=1e-12, atol=1e-15)
             compared += 1
@@ -297,14 +307,14 @@ def test_ragged_batch_sizes_mfma():
 # MFMA Gram and FP64
 # ---------------------------------------------------------------------------
 
-def free_run(X, k, window, kind, param, init, batches, precision, impl="auto", threads=4):
+def free_run(X, k, window, kind, param, init, batches, precision, impl="auto", threads=4, tau=0):
     """GPU and oracle from the same initial centers, no state import: labels
     agree on rows with margin; while all labels agree, the self norms of the
     centers after the last step agree with the oracle's.  Returns the number
     of steps with identical labels."""
-    orc = O.Oracle(X, k, window, kind, param)
+    orc = O.Oracle(X, k, window, kind, param, tau=tau)
     orc.init_centers(init)
-    model = _model(X, k, max(len(B) for B in batches), window, KNAME[kind], param, precision, impl)
+    model = _model(X, k, max(len(B) for B in batches), window, KNAME[kind], param, precision, impl, tau=tau)
     model.init_centers(init)
     same = 0
     for B in batches:
@@ -354,6 +364,41 @@ def test_free_running_fp64_direct():
     rng = np.random.default_rng(35)
     batches = [rng.integers(0, 3000, 200).astype(np.int32) for _ in range(8)]
     assert free_run(X, 6, 3, O.GAUSS, 4.0, _one_per_component(comp, 6), batches, "fp64", "direct") == 8
+
+
+# ---------------------------------------------------------------------------
+# the count truncation of Section 4.1 (tau) within the window
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("precision,impl", [("fp32", "mfma"), ("bf16x3", "mfma"), ("fp32", "direct")])
+def test_tau_free_running(precision, impl):
+    """tau = 60 with about 21 points per center and batch: centers drop their
+    older batches (and the initial point) well inside the 8-batch window."""
+    X, comp = _small_gmm(6000, 32, 12, 0.3, seed=50, with_comp=True)
+    sigma = W.median_pairwise_distance(X, 0)
+    rng = np.random.default_rng(51)
+    batches = [rng.integers(0, 6000, 256).astype(np.int32) for _ in range(10)]
+    same = free_run(X, 12, 8, O.GAUSS, 2 * sigma * sigma, _one_per_component(comp, 12), batches, precision,
+                    impl, tau=60)
+    assert same == 10
+
+
+def test_tau_state_lockstep():
+    """Imported states and one step at a time: the coefficients after the
+    count truncation equal the oracle's (dropped columns at 0)."""
+    X, comp = _small_gmm(3000, 6, 5, 0.4, seed=52, with_comp=True)
+    rng = np.random.default_rng(53)
+    batches = [rng.integers(0, 3000, 90).astype(np.int32) for _ in range(8)]
+    _step_and_compare_state(X, 5, 6, O.GAUSS, 3.0, _one_per_component(comp, 5), batches, "fp64", tau=40)
+
+
+def test_tau_large_k_general_update():
+    """k = 600: the general update kernel applies the count truncation."""
+    wl = W.c5_laplace_mixture(seed=3, n=30000, d=32, c=600)
+    init = _one_per_component(wl.comp, 600)
+    rng = np.random.default_rng(54)
+    batches = [rng.integers(0, wl.n, 2048).astype(np.int32) for _ in range(5)]
+    assert free_run(wl.X, 600, 4, wl.kernel, 20.0, init, batches, "fp32", tau=6) == 5
 
 
 def test_bad_index_and_nonfinite_are_errors():
