@@ -174,6 +174,28 @@ int mbkk_assign(mbkk_ctx *ctx, const int32_t *idx_dev, int64_t m, int32_t *label
  * points idx_dev[0..m-1]; synchronises. */
 int mbkk_objective(mbkk_ctx *ctx, const int32_t *idx_dev, int64_t m, double *out_host);
 
+/* f_{B_i}(C_{i+1}): the objective of the last step's batch B_i (its tuple of
+ * points, duplicates included) on the centers after that step's update: the
+ * second term of the early-stopping test of Algorithms 1 and 2, whose first
+ * term f_{B_i}(C_i) is mbkk_step's fbefore.  Scores the batch again (one
+ * assignment pass); synchronises.  MBKK_E_STATE before the first step. */
+int mbkk_last_batch_objective(mbkk_ctx *ctx, double *f_host);
+
+/* Agreement of a labeling with reference labels, the two quality scores of
+ * Section 6: the adjusted Rand index (pair counting, corrected for chance)
+ * and the normalised mutual information I(U; V) / ((H(U) + H(V)) / 2),
+ * natural logarithms.  labels_dev [m] int32 in [0, k) (e.g. from
+ * mbkk_assign), truth_dev [m] int32 in [0, c), 2 <= m < 2^40, 1 <= c,
+ * k * c <= 2^26; table_dev [k x c] int64 row-major device array owned by the
+ * caller, overwritten with the contingency table (cell (i, j) = rows with
+ * label i and truth j).  Writes ari_host and nmi_host (FP64, computed on the
+ * host from the table).  Conventions: ARI = 1 when both labelings are one
+ * cluster, or both all singletons; NMI = 1 when both are one cluster.
+ * Returns MBKK_E_INVALID for a value outside its range (the table then holds
+ * the in-range rows only).  Synchronises. */
+int mbkk_agreement(mbkk_ctx *ctx, const int32_t *labels_dev, const int32_t *truth_dev, int64_t m, int32_t c,
+                   int64_t *table_dev, double *ari_host, double *nmi_host);
+
 /* Copies the iteration state to / from host memory (checkpoint, resume,
  * lock-step comparison).  set_state recomputes the center Gram blocks. */
 int mbkk_get_state(mbkk_ctx *ctx, mbkk_state *out_host);

@@ -21,7 +21,7 @@ EXPORTS = [
     "mbkk_workspace_size", "mbkk_create", "mbkk_destroy", "mbkk_last_error", "mbkk_set_data",
     "mbkk_init_centers", "mbkk_init_kmeanspp", "mbkk_step", "mbkk_assign", "mbkk_objective",
     "mbkk_get_state", "mbkk_set_state", "mbkk_center_norms", "mbkk_set_timing", "mbkk_get_timing",
-    "mbkk_objective_fwd", "mbkk_objective_bwd",
+    "mbkk_objective_fwd", "mbkk_objective_bwd", "mbkk_last_batch_objective", "mbkk_agreement",
 ]
 
 
@@ -72,6 +72,8 @@ def lib():
         L.mbkk_step.argtypes = [P, P, I32, P, P, C.POINTER(D)]
         L.mbkk_assign.argtypes = [P, P, I64, P, P, P, P]
         L.mbkk_objective.argtypes = [P, P, I64, C.POINTER(D)]
+        L.mbkk_last_batch_objective.argtypes = [P, C.POINTER(D)]
+        L.mbkk_agreement.argtypes = [P, P, P, I64, I32, P, C.POINTER(D), C.POINTER(D)]
         L.mbkk_get_state.argtypes = [P, C.POINTER(State)]
         L.mbkk_set_state.argtypes = [P, C.POINTER(State)]
         L.mbkk_center_norms.argtypes = [P, P]

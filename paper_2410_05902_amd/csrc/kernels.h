@@ -61,6 +61,11 @@ void launch_grad_rows(const Layout &L, const Buffers &B, const float *xb, int b,
                       double g, const double *dN, float *dX, double *rowds, double *out, hipStream_t st);
 int grad_max_dim();
 
+// Contingency table [k x c] (int64, zeroed by the caller) of labels in [0, k)
+// against truth in [0, c); an out-of-range row raises flags[2].
+void launch_contingency(const int32_t *labels, const int32_t *truth, int64_t m, int k, int c, int64_t *table,
+                        int32_t *flags, hipStream_t st);
+
 // k-means++
 void launch_kpp_self(const Layout &L, const Buffers &B, int kind, double param, hipStream_t st);
 void launch_kpp_round(const Layout &L, const Buffers &B, int r, int kind, double param, hipStream_t st);

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -333,22 +334,31 @@ static void prepare(mbkk_ctx *c, const int32_t *idx, int64_t cnt)
         c->support_iter = c->iter;
 }
 
+// The next (start, stop) pair of timing events.
+static int timing_pair(mbkk_ctx *c, hipEvent_t *e0, hipEvent_t *e1)
+{
+    if (c->ev_used + 2 > c->ev.size()) {
+        for (int q = 0; q < 256; ++q) {
+            hipEvent_t e;
+            HIPCHK(c, hipEventCreate(&e));
+            c->ev.push_back(e);
+        }
+    }
+    *e0 = c->ev[c->ev_used];
+    *e1 = c->ev[c->ev_used + 1];
+    c->ev_used += 2;
+    return MBKK_OK;
+}
+
 static int cross_and_score(mbkk_ctx *c, int nb, double *D_out, int64_t ldD, bool with_rank)
 {
     const Layout &L = c->L;
     const mbkk_config &cf = c->cfg;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (c->timing) {
-        if (c->ev_used + 2 > c->ev.size()) {
-            for (int q = 0; q < 256; ++q) {
-                hipEvent_t e;
-                HIPCHK(c, hipEventCreate(&e));
-                c->ev.push_back(e);
-            }
-        }
-        e0 = c->ev[c->ev_used];
-        e1 = c->ev[c->ev_used + 1];
-        c->ev_used += 2;
+        int rc = timing_pair(c, &e0, &e1);
+        if (rc)
+            return rc;
         HIPCHK(c, hipEventRecord(e0, c->stream));
     }
     if (c->use_mfma)
@@ -641,6 +651,90 @@ int mbkk_objective(mbkk_ctx *c, const int32_t *idx, int64_t m, double *out_host)
     *out_host = s / (double)m;
     if (c->cfg.validate)
         return check_flags(c);
+    return MBKK_OK;
+}
+
+int mbkk_last_batch_objective(mbkk_ctx *c, double *f_host)
+{
+    if (!c)
+        return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (!c->inited || c->iter < 2)
+        return fail(c, MBKK_E_STATE, "no step yet");
+    if (!f_host)
+        return fail(c, MBKK_E_INVALID, "f is NULL");
+    // batch i-1 lives in its ring slot with its point indices in slot_pts
+    const int p = phys_of(c->iter - 1, c->L.P);
+    const int b = c->slot_b[p];
+    if (b < 1)
+        return fail(c, MBKK_E_STATE, "the last batch's slot holds no points");
+    return mbkk_objective(c, c->B.slot_pts + (int64_t)p * c->L.bmax, b, f_host);
+}
+
+// Adjusted Rand index and normalised mutual information (arithmetic-mean
+// normalisation) of a contingency table n[k x c], in FP64 (each pair count
+// C(n, 2) is exact for cells below 2^26 rows).
+static void agreement_scores(const std::vector<int64_t> &n, int k, int c, double *ari, double *nmi)
+{
+    std::vector<double> a(k, 0.0), b(c, 0.0);
+    double N = 0.0, sij = 0.0;
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < c; ++j) {
+            const double v = (double)n[(size_t)i * c + j];
+            a[i] += v;
+            b[j] += v;
+            N += v;
+            sij += v * (v - 1.0) * 0.5;
+        }
+    double sa = 0.0, sb = 0.0, hu = 0.0, hv = 0.0;
+    for (int i = 0; i < k; ++i) {
+        sa += a[i] * (a[i] - 1.0) * 0.5;
+        if (a[i] > 0.0)
+            hu -= a[i] / N * std::log(a[i] / N);
+    }
+    for (int j = 0; j < c; ++j) {
+        sb += b[j] * (b[j] - 1.0) * 0.5;
+        if (b[j] > 0.0)
+            hv -= b[j] / N * std::log(b[j] / N);
+    }
+    // ARI: (index - expected index) / (max index - expected index), pairs
+    const double expct = sa * sb / (N * (N - 1.0) * 0.5);
+    const double den = 0.5 * (sa + sb) - expct;
+    *ari = den == 0.0 ? 1.0 : (sij - expct) / den;
+    double mi = 0.0;
+    for (int i = 0; i < k; ++i)
+        for (int j = 0; j < c; ++j) {
+            const double v = (double)n[(size_t)i * c + j];
+            if (v > 0.0)
+                mi += v / N * (std::log(v) + std::log(N) - std::log(a[i]) - std::log(b[j]));
+        }
+    if (hu == 0.0 && hv == 0.0)
+        *nmi = 1.0;  // one cluster on both sides: identical partitions
+    else
+        *nmi = std::max(0.0, mi) / (0.5 * (hu + hv));
+}
+
+int mbkk_agreement(mbkk_ctx *c, const int32_t *labels_dev, const int32_t *truth_dev, int64_t m, int32_t nc,
+                   int64_t *table_dev, double *ari_host, double *nmi_host)
+{
+    if (!c)
+        return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (m < 2 || m >= ((int64_t)1 << 40) || !labels_dev || !truth_dev || !table_dev || !ari_host || !nmi_host)
+        return fail(c, MBKK_E_INVALID, "need 2 <= m < 2^40 rows, both labelings, a table and two outputs");
+    const int k = c->L.k;
+    if (nc < 1 || (int64_t)k * nc > ((int64_t)1 << 26))
+        return fail(c, MBKK_E_INVALID, "need 1 <= c and k * c <= 2^26");
+    HIPCHK(c, hipMemsetAsync(c->B.flags, 0, 4 * sizeof(int32_t), c->stream));
+    HIPCHK(c, hipMemsetAsync(table_dev, 0, sizeof(int64_t) * (size_t)k * nc, c->stream));
+    launch_contingency(labels_dev, truth_dev, m, k, nc, table_dev, c->B.flags, c->stream);
+    HIPCHK(c, hipGetLastError());
+    std::vector<int64_t> n((size_t)k * nc);
+    int32_t f[3] = {0, 0, 0};
+    HIPCHK(c, hipMemcpyAsync(n.data(), table_dev, sizeof(int64_t) * n.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(f, c->B.flags, sizeof(f), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (f[2])
+        return fail(c, MBKK_E_INVALID, "label outside [0, k) or truth outside [0, c)");
+    agreement_scores(n, k, nc, ari_host, nmi_host);
     return MBKK_OK;
 }
 

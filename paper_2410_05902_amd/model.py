@@ -127,6 +127,41 @@ class Model:
         self._chk(L.lib().mbkk_objective(self._ctx, _ptr(t), t.numel(), C.byref(f)))
         return float(f.value)
 
+    def last_batch_objective(self) -> float:
+        """f of the most recent batch under the centers after its update."""
+        f = C.c_double()
+        self._chk(L.lib().mbkk_last_batch_objective(self._ctx, C.byref(f)))
+        return float(f.value)
+
+    def fit(self, batches, eps: float):
+        """Run steps over `batches` (an iterable of index tensors) until the
+        early-stopping test of Algorithms 1 and 2 fires: the objective of the
+        batch just used drops by less than eps across its update, i.e.
+        f_B(C_i) - f_B(C_{i+1}) < eps.  Returns the number of steps taken and
+        the per-step improvements."""
+        gains = []
+        for batch in batches:
+            fb = self.step(batch, want_objective=True)["fbefore"]
+            gains.append(fb - self.last_batch_objective())
+            if gains[-1] < eps:
+                break
+        return len(gains), gains
+
+    def agreement(self, labels, truth, c: int):
+        """Adjusted Rand index and normalised mutual information of `labels`
+        (in [0, k)) against reference labels `truth` (in [0, c)); returns
+        (ari, nmi, contingency table [k x c])."""
+        lab = self._idx(labels)
+        tru = self._idx(truth)
+        if lab.numel() != tru.numel():
+            raise ValueError("labels and truth differ in length")
+        table = torch.empty((self.k, c), dtype=torch.int64, device=self.device)
+        ari, nmi = C.c_double(), C.c_double()
+        self._chk(L.lib().mbkk_agreement(self._ctx, _ptr(lab), _ptr(tru), lab.numel(), c, _ptr(table),
+                                         C.byref(ari), C.byref(nmi)))
+        self._keep = (lab, tru)
+        return float(ari.value), float(nmi.value), table
+
     def center_norms(self) -> np.ndarray:
         N = np.empty(self.k, dtype=np.float64)
         self._chk(L.lib().mbkk_center_norms(self._ctx, N.ctypes.data_as(C.c_void_p)))

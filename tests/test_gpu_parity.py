@@ -94,6 +94,8 @@ def _step_and_compare_state(X, k, window, kind, param, init, batches, precision,
             assert e.max() <= max(tol, 2e-7), f"step {i}: min-distance error {e.max():.3e}"
             assert g["fbefore"] == pytest.approx(ref["fbefore"], rel=max(tol, 1e-6), abs=1e-9)
         if (lab == ref["labels"]).all():
+            # second term of the early-stopping test: the batch under the updated centers
+            assert model.last_batch_objective() == pytest.approx(orc.objective(B), rel=max(tol, 1e-6), abs=1e-9)
             sg = model.get_state()
             so = oracle_state_to_gpu(orc.state(), init, k, window, b_max)
             assert sg["iteration"] == so["iteration"]
@@ -399,6 +401,75 @@ def test_tau_large_k_general_update():
     rng = np.random.default_rng(54)
     batches = [rng.integers(0, wl.n, 2048).astype(np.int32) for _ in range(5)]
     assert free_run(wl.X, 600, 4, wl.kernel, 20.0, init, batches, "fp32", tau=6) == 5
+
+
+@pytest.mark.parametrize("precision,impl", [("fp32", "mfma"), ("fp32", "direct"), ("bf16x3", "mfma")])
+def test_early_stopping_fit(precision, impl):
+    """Algorithm 2's stopping test: the improvement f_B(C_i) - f_B(C_{i+1}) of
+    each batch agrees with the oracle's, and fit stops at the first step whose
+    improvement falls below eps."""
+    X, comp = _small_gmm(6000, 32, 12, 0.3, seed=60, with_comp=True)
+    sigma = W.median_pairwise_distance(X, 0)
+    kappa = 2 * sigma * sigma
+    init = _one_per_component(comp, 12)
+    rng = np.random.default_rng(61)
+    batches = [rng.integers(0, 6000, 256).astype(np.int32) for _ in range(12)]
+    orc = O.Oracle(X, 12, 4, O.GAUSS, kappa)
+    orc.init_centers(init)
+    gains_o = []
+    for B in batches:
+        ref = orc.step(B, threads=4)
+        gains_o.append(ref["fbefore"] - orc.objective(B))
+    gains_o = np.array(gains_o)
+    # eps halfway between two improvements far apart, so rounding cannot move the stop
+    order = np.sort(gains_o[2:8])
+    gap = np.argmax(np.diff(order))
+    eps = 0.5 * (order[gap] + order[gap + 1])
+    stop_o = int(np.flatnonzero(gains_o < eps)[0]) + 1
+    model = _model(X, 12, 256, 4, "gauss", kappa, precision, impl)
+    model.init_centers(init)
+    n, gains = model.fit([torch.from_numpy(B) for B in batches], eps)
+    tol = max(TOL[precision], 1e-6)
+    np.testing.assert_allclose(gains, gains_o[:n], rtol=0, atol=tol * 2.0)
+    assert n == stop_o, (n, stop_o, gains, gains_o)
+    # after the stop the entry point still scores the last batch used
+    assert model.last_batch_objective() == pytest.approx(model.objective(batches[n - 1]), rel=1e-12)
+
+
+def test_last_batch_objective_before_any_step_is_an_error():
+    from paper_2410_05902_amd._lib import MbkkError
+    X = _small_gmm(500, 8, 4, 0.4)
+    model = _model(X, 4, 64, 2, "gauss", 4.0, "fp32")
+    model.init_centers(np.arange(4, dtype=np.int32))
+    with pytest.raises(MbkkError):
+        model.last_batch_objective()
+
+
+def test_agreement_scores():
+    """Contingency table bit-exact, ARI and NMI of Section 6 against the oracle:
+    assignments of a Gaussian mixture against its components (LDS table), many
+    rows in many workgroups, and a table too large for LDS."""
+    from oracle import scores
+    from paper_2410_05902_amd._lib import MbkkError
+    X, comp = _small_gmm(20000, 16, 10, 0.5, seed=70, with_comp=True)
+    model = _model(X, 10, 4096, 2, "gauss", 8.0, "fp32")
+    model.init_centers(_one_per_component(comp, 10))
+    lab = model.assign(np.arange(20000))["labels"].cpu().numpy()
+    rng = np.random.default_rng(71)
+    big_u = rng.integers(0, 10, 3_000_000).astype(np.int32)
+    cases = [(lab, comp, 10), (lab, comp % 3, 3), (big_u, (big_u * 7 + rng.integers(0, 3, big_u.size)) % 13, 13),
+             (lab, rng.integers(0, 4000, lab.size), 4000), (lab[:2], comp[:2], 10)]
+    for u, v, c in cases:
+        ari, nmi, table = model.agreement(u, v, c)
+        n = scores.contingency(u, v, 10, c)
+        np.testing.assert_array_equal(table.cpu().numpy(), n)
+        assert ari == pytest.approx(scores.ari(n), rel=1e-12, abs=1e-12)
+        assert nmi == pytest.approx(scores.nmi(n), rel=1e-12, abs=1e-12)
+    assert model.agreement(lab, comp, 10)[0] > 0.5
+    bad = comp.copy()
+    bad[5] = 10
+    with pytest.raises(MbkkError):
+        model.agreement(lab, bad, 10)
 
 
 def test_bad_index_and_nonfinite_are_errors():

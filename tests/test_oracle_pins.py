@@ -611,3 +611,60 @@ def test_exact_ties_go_to_lowest_index():
         np.testing.assert_array_equal(out["labels"], expect)
         tied = out["labels"] == 0
         assert (out["margin"][tied] == 0.0).all()
+
+
+# --------------------------------------------------------------------------
+# agreement scores of Section 6 (ARI, NMI)
+# --------------------------------------------------------------------------
+
+def _ari_pairs_brute(u, v):
+    """ARI from pair counts taken one pair at a time (no contingency table)."""
+    m = len(u)
+    both = su = sv = 0
+    for a in range(m):
+        for b in range(a + 1, m):
+            tu, tv = u[a] == u[b], v[a] == v[b]
+            both += tu and tv
+            su += tu
+            sv += tv
+    pairs = m * (m - 1) / 2
+    exp = su * sv / pairs
+    top = 0.5 * (su + sv)
+    return 1.0 if top == exp else (both - exp) / (top - exp)
+
+
+def test_scores_against_sklearn_and_brute_force():
+    from oracle import scores
+    from sklearn.metrics import adjusted_rand_score, normalized_mutual_info_score
+    rng = np.random.default_rng(70)
+    for trial in range(40):
+        m = int(rng.integers(2, 40))
+        k, c = int(rng.integers(1, 7)), int(rng.integers(1, 7))
+        u = rng.integers(0, k, m)
+        v = (u + rng.integers(0, 2, m) * rng.integers(0, c, m)) % c if trial % 2 else rng.integers(0, c, m)
+        n = scores.contingency(u, v, k, c)
+        assert n.sum() == m and n[u[0], v[0]] >= 1
+        assert scores.ari(n) == pytest.approx(_ari_pairs_brute(list(u), list(v)), abs=1e-12)
+        assert scores.ari(n) == pytest.approx(adjusted_rand_score(v, u), abs=1e-12)
+        assert scores.nmi(n) == pytest.approx(normalized_mutual_info_score(v, u), abs=1e-12)
+
+
+def test_scores_closed_forms():
+    from oracle import scores
+    # the same partition under renamed labels: both scores 1
+    u = np.array([0, 0, 1, 1, 2, 2, 2])
+    n = scores.contingency(u, (u + 1) % 3, 3, 3)
+    assert scores.ari(n) == pytest.approx(1.0) and scores.nmi(n) == pytest.approx(1.0)
+    # two independent halvings of four rows: no shared information, and the
+    # index falls below its expectation: ARI = (0 - 2/3) / (2 - 2/3) = -1/2
+    n = scores.contingency([0, 1, 0, 1], [0, 0, 1, 1], 2, 2)
+    assert scores.ari(n) == pytest.approx(-0.5, abs=1e-15)
+    assert scores.nmi(n) == pytest.approx(0.0, abs=1e-15)
+    # one cluster against one cluster: 1; one cluster against a split: ARI 0, NMI 0
+    assert scores.ari(scores.contingency([0] * 5, [0] * 5, 1, 1)) == 1.0
+    assert scores.nmi(scores.contingency([0] * 5, [0] * 5, 1, 1)) == 1.0
+    n = scores.contingency([0] * 4, [0, 0, 1, 1], 1, 2)
+    assert scores.ari(n) == pytest.approx(0.0, abs=1e-15) and scores.nmi(n) == pytest.approx(0.0, abs=1e-15)
+    # NMI of a refinement: H(V) = log 2, H(U) = log 4, I = log 2 -> 2 log 2 / (3 log 2) = 2/3
+    n = scores.contingency([0, 1, 2, 3], [0, 0, 1, 1], 4, 2)
+    assert scores.nmi(n) == pytest.approx(2.0 / 3.0, abs=1e-15)
