@@ -11,6 +11,11 @@ centers and their FP64 Gram blocks.  The same iterations are then timed in
 the FP32-plain form (FP32 MFMA) for the BF16-vs-FP32 speedup, and the two
 forms' assignments are compared on identical states.
 
+With --untruncated the same workload runs untruncated (Algorithm 1, window
+0) on the table of cross terms of every point (Appendix A): a step scores the
+batch from the table and updates the n x k table with n * b kernel
+evaluations (FP32, VALU).
+
 Prints ONE JSON line (rank 0).  Inputs are resident in HBM before timing.
 """
 from __future__ import annotations
@@ -37,11 +42,12 @@ def log(*a):
 
 CROSS_SRC = os.path.join(ROOT, "paper_2410_05902_amd", "csrc", "kernels_cross.hip")
 CROSS_KERNEL = {"gauss": "k_cross_bs", "laplace": "k_cross_direct"}
+DP_SRC = os.path.join(ROOT, "paper_2410_05902_amd", "csrc", "kernels_dp.hip")
 
 
-def source_sha() -> str:
+def source_sha(path: str = CROSS_SRC) -> str:
     import hashlib
-    with open(CROSS_SRC, "rb") as f:
+    with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
@@ -67,8 +73,9 @@ def traffic_summary(args):
     per dispatch), each scaled by the ratio of the true bytes of a plain copy of
     copy_mib MiB to what the same counter reads for that copy."""
     fdir, wdir, cfdir, cwdir = args.traffic_summary
-    wl = args.workload
-    kern = "k_cross_direct" if wl == "c5" else "k_cross_bs"
+    wl = args.workload + ("u" if args.untruncated else "")
+    kern = "k_dp_table" if args.untruncated else ("k_cross_direct" if wl == "c5" else "k_cross_bs")
+    src = DP_SRC if args.untruncated else CROSS_SRC
     fetch, write = _counter_means(fdir, "FETCH_SIZE"), _counter_means(wdir, "WRITE_SIZE")
     cf, cw = _counter_means(cfdir, "FETCH_SIZE"), _counter_means(cwdir, "WRITE_SIZE")
     pick = lambda m, key: max(((v, n, k) for k, (v, n) in m.items() if key in k), default=None)
@@ -83,23 +90,24 @@ def traffic_summary(args):
            "copy_mib": args.copy_mib, "copy_fetch_kib": copy_f[0], "copy_write_kib": copy_w[0],
            "fetch_scale": sf, "write_scale": sw,
            "traffic_bytes_per_launch": (f[0] * sf + w[0] * sw) * 1024.0,
-           "kernels_cross_sha": source_sha()}
+           "source": os.path.basename(src), "source_sha": source_sha(src)}
     path = os.path.join(ROOT, "profiles", f"traffic_{wl}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out))
 
 
-def measured_traffic(wl: str):
+def measured_traffic(wl: str, src: str = CROSS_SRC):
     """Bytes per launch from profiles/traffic_<wl>.json when it was taken on the
-    current cross-kernel source, else None."""
+    current source of the kernel, else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{wl}.json")
     try:
         with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    return t["traffic_bytes_per_launch"] if t.get("kernels_cross_sha") == source_sha() else None
+    sha = t.get("source_sha", t.get("kernels_cross_sha"))
+    return t["traffic_bytes_per_launch"] if sha == source_sha(src) else None
 
 
 def main():
@@ -118,6 +126,8 @@ def main():
                     help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE runs of the workload and of the copy "
                          "calibration into profiles/traffic_<workload>.json (no GPU needed)")
     ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--untruncated", action="store_true",
+                    help="run the workload untruncated (window 0) on the table of cross terms")
     args = ap.parse_args()
     if args.traffic_summary:
         traffic_summary(args)
@@ -152,16 +162,20 @@ def main():
         f"kernel={'gauss' if wl.kernel == W.GAUSS else 'laplace'} param={wl.kernel_param:.4f} "
         f"(generated in {time.time() - t0:.1f}s)")
     gauss = wl.kernel == W.GAUSS
-    precision = args.precision or ("bf16x3" if gauss else "fp32")
+    untrunc = args.untruncated
+    window = 0 if untrunc else wl.window
+    precision = args.precision or ("bf16x3" if gauss and not untrunc else "fp32")
     X = torch.from_numpy(wl.X).to(dev)
     nsteps = args.warmup + args.steps
     batches = torch.from_numpy(np.stack([wl.batch(i) for i in range(1, nsteps + 1)])).to(dev)
     u = wl.kmeanspp_uniforms()
 
     def make(prec):
-        return Model(X, k=wl.k, b_max=wl.b, window=wl.window,
+        return Model(X, k=wl.k, b_max=wl.b, window=window,
                      kernel="gauss" if gauss else "laplace", kernel_param=wl.kernel_param,
                      precision=prec, validate=False)
+
+    active = []  # untruncated form: centers with batch points in each kernel-timed step
 
     def run(model, timed_steps, warm, kernel_steps=50):
         """Whole-step time over `timed_steps` (no instrumentation), then the
@@ -177,7 +191,11 @@ def main():
         te = time.perf_counter()
         model.set_timing(True)
         for i in range(kernel_steps):
-            model.step_noout(batches[(warm + i) % nsteps])
+            if untrunc:
+                lab = model.step(batches[(warm + i) % nsteps])["labels"]
+                active.append(int(torch.unique(lab).numel()))
+            else:
+                model.step_noout(batches[(warm + i) % nsteps])
         kms, launches = model.get_timing()
         model.set_timing(False)
         return (te - ts) * 1e3 / timed_steps, kms / max(launches, 1)
@@ -188,19 +206,39 @@ def main():
     init = model.init_kmeanspp(u)
     torch.cuda.synchronize()
     log(f"[bench] k-means++ seeding on the GPU: {time.time() - tk:.2f}s")
-    if args.warmup < wl.window + 1:
+    if args.warmup < wl.window + 1 and not untrunc:
         log("[bench] note: warmup shorter than W+1, early steps have a smaller support")
     ms_step, ms_cross = run(model, args.steps, args.warmup)
-    M = wl.window * wl.b                      # steady-state support size (W batches)
-    evals = wl.b * M                          # cross-term kernel evaluations per step
+    if untrunc:
+        evals = wl.n * wl.b                   # table update: every point of X against the batch
+    else:
+        M = wl.window * wl.b                  # steady-state support size (W batches)
+        evals = wl.b * M                      # cross-term kernel evaluations per step
     value = evals / (ms_step * 1e-3)
     iters = 1e3 / ms_step
     log(f"[bench] {precision}: {ms_step:.4f} ms/step, cross kernel {ms_cross:.4f} ms, "
         f"{value:.4e} evals/s, {iters:.1f} it/s")
 
     npass = {"bf16x3": 3, "bf16x1": 1, "fp32": 1}.get(precision, 1)
-    traffic = measured_traffic(args.workload)   # HBM bytes per launch (rocprofv3 counters), or None
-    if gauss:
+    # HBM bytes per launch (rocprofv3 counters), or None
+    traffic = measured_traffic(args.workload + ("u" if untrunc else ""), DP_SRC if untrunc else CROSS_SRC)
+    if untrunc:
+        # the table kernel: 2 FP32 VALU lane operations per coordinate per
+        # evaluation (subtract and add |.|; the Gaussian product form does one
+        # FMA, counted as 2 as well), peak as for the direct kernel; its
+        # algorithmic HBM bytes: the table entries of the centers that the
+        # batch touched read and written once, X read once
+        ops = 2.0 * wl.d * evals
+        kact = float(np.mean(active)) if active else float(wl.k)
+        tbytes = 2.0 * 4 * wl.n * kact + 4.0 * wl.n * wl.d
+        roof = {"bound": "alu", "achieved": ops / (ms_cross * 1e-3) / 1e12, "peak": PEAK["f32"] / 2e12,
+                "unit": "TOP/s", "frac": ops / (ms_cross * 1e-3) / (PEAK["f32"] / 2), "traffic": traffic,
+                "kernel": f"k_dp_table<{'gauss' if gauss else 'laplace'},f32>", "ops_per_launch": ops,
+                "table_bytes_per_launch": tbytes, "table_GBps": tbytes / (ms_cross * 1e-3) / 1e9,
+                "centers_touched_per_step": kact}
+        if traffic:
+            roof["hbm_GBps"] = traffic / (ms_cross * 1e-3) / 1e9
+    elif gauss:
         flops = npass * 2.0 * wl.d * evals
         pk = PEAK["bf16"] if precision.startswith("bf16") else PEAK["f32"]
         roof = {"bound": "mfma", "achieved": flops / (ms_cross * 1e-3) / 1e12, "peak": pk / 1e12,
@@ -220,14 +258,14 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "bf16" if precision.startswith("bf16") else "f32", "data": "synthetic",
-           "config": {"workload": wl.name, "n": wl.n, "d": wl.d, "k": wl.k, "b": wl.b,
-                      "window": wl.window, "kernel": "gauss" if gauss else "laplace",
+           "config": {"workload": wl.name + ("_untruncated" if untrunc else ""), "n": wl.n, "d": wl.d,
+                      "k": wl.k, "b": wl.b, "window": window, "kernel": "gauss" if gauss else "laplace",
                       "kernel_param": wl.kernel_param, "precision": precision,
                       "init": "kernel k-means++ (GPU)", "parallelism": "single GPU"},
-           "iters_per_s": iters, "cross_kernel_ms": ms_cross}
+           "iters_per_s": iters, ("table_kernel_ms" if untrunc else "cross_kernel_ms"): ms_cross}
 
     # ---- FP32 plain form, and assignment agreement -------------------------
-    if gauss and precision.startswith("bf16") and not args.no_fp32:
+    if gauss and precision.startswith("bf16") and not args.no_fp32 and not untrunc:
         ref = make("fp32")
         ref.init_centers(init)
         fsteps = max(20, args.steps // 4)

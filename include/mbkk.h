@@ -10,6 +10,17 @@
  * truncation to a window of recent batches (Section 4.1, Eq. 1 and the
  * unrolled recursion before it; sliding-window footnote).
  *
+ * window = 0 selects the untruncated Algorithm 1 instead, run on the table
+ * of cross terms that Appendix A describes: the context keeps
+ * <phi(x), C_j> for every row x of X and every center j (a k x n table in the
+ * workspace, FP32 or FP64 by the precision) and <C_j, C_j>, and each step
+ * updates both by the recursion of Section 4 (O(n b) kernel evaluations and
+ * one pass over the table).  In that form tau must be 0, the precision FP32
+ * or FP64, cross_impl AUTO or DIRECT and d <= 128; mbkk_get_state,
+ * mbkk_set_state and the differentiation form return MBKK_E_STATE; an
+ * out-of-range index in mbkk_step / mbkk_assign / mbkk_objective is scored
+ * as row 0 (and reported under validate).
+ *
  * Conventions for every entry point:
  *  - Pointers named *_dev are device pointers (HIP / torch CUDA tensors on the
  *    ROCm build); pointers named *_host are host pointers.  Device arrays are
@@ -88,7 +99,8 @@ typedef struct {
     int32_t d;           /* columns of X                                         */
     int32_t k;           /* number of centers, 1 <= k <= 65536, k <= n           */
     int32_t b_max;       /* largest batch or index chunk, 1 <= b_max <= 8192     */
-    int32_t window;      /* W: a center keeps its last W batches, 1 <= W <= 30   */
+    int32_t window;      /* W: a center keeps its last W batches, 1 <= W <= 30;  */
+                         /* 0: untruncated, on the table of cross terms          */
     int32_t kernel;      /* MBKK_GAUSS ...                                       */
     double kernel_param; /* kappa / sigma / c; > 0 for GAUSS and LAPLACE         */
     int32_t precision;   /* MBKK_FP32 ...                                        */

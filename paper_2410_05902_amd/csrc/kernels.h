@@ -61,6 +61,23 @@ void launch_grad_rows(const Layout &L, const Buffers &B, const float *xb, int b,
                       double g, const double *dN, float *dX, double *rowds, double *out, hipStream_t st);
 int grad_max_dim();
 
+// Untruncated form on the table of cross terms (window 0).  init: N and the
+// table of the initial centers (pool rows 0..k-1).  score: distances of rows
+// idx[0..m) from the table into labels / mind / margin (step: also the old
+// table value of the winner and the counts).  update: plan, grouping, pair
+// sums, N and weights of batch rows [0, b) (staged in slot 0).  table: the
+// update of T over all of X.
+int dp_max_dim();
+// dot: the Gaussian FP32 table update takes the squared distance from the
+// norms and the dot product (else from the coordinate differences).
+void launch_dp_init(const Layout &L, const Buffers &B, int kind, double param, int fp64, bool dot, hipStream_t st);
+void launch_dp_score(const Layout &L, const Buffers &B, int kind, double param, int fp64, const int32_t *idx, int m,
+                     bool step, double *D_out, int64_t ldD, int32_t *flags, hipStream_t st);
+void launch_dp_update(const Layout &L, const Buffers &B, int b, int kind, double param, int fp64, int lr,
+                      hipStream_t st);
+void launch_dp_table(const Layout &L, const Buffers &B, int kind, double param, int fp64, int init, bool dot,
+                     hipStream_t st);
+
 // Contingency table [k x c] (int64, zeroed by the caller) of labels in [0, k)
 // against truth in [0, c); an out-of-range row raises flags[2].
 void launch_contingency(const int32_t *labels, const int32_t *truth, int64_t m, int k, int c, int64_t *table,

@@ -67,6 +67,8 @@ static size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
 static bool wants_mfma(const mbkk_config &c)
 {
+    if (c.window == 0)
+        return false;  // the table form runs on the VALU
     if (c.cross_impl == MBKK_CROSS_MFMA)
         return true;
     if (c.cross_impl == MBKK_CROSS_DIRECT)
@@ -93,8 +95,12 @@ Layout make_layout(const mbkk_config &c)
     // batch from a fragment-order copy
     L.frag_mode = wants_mfma(c) && L.dp <= 128 ? (L.bf16 ? 1 : 2) : 0;
     L.PR = (int64_t)c.k + (int64_t)L.P * c.b_max;
+    L.untrunc = c.window == 0;
+    L.ldT = (int64_t)up((size_t)c.n, 64);
+    L.tbytes = c.precision == MBKK_FP64 ? 8 : 4;
     // live support: at most W slots of b_max points and the k initial points
-    const int64_t Mlive = (int64_t)c.k + (int64_t)c.window * c.b_max;
+    // (the table form: the grouped batch, or the k initial points)
+    const int64_t Mlive = L.untrunc ? std::max<int64_t>(c.k, c.b_max) : (int64_t)c.k + (int64_t)c.window * c.b_max;
     L.Mcap = (int64_t)up((size_t)(Mlive + (int64_t)c.k * (L.pad - 1) + L.pad), 128);
     L.nblk = L.Mcap / 32;
     L.nchunk = (c.b_max + kChunk - 1) / kChunk;
@@ -148,7 +154,19 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.blk_center = (int32_t *)take(4 * L.nblk);
     size_t part_direct = (size_t)(L.k + kDirectWGs) * L.bmax * 8;  // runs of the direct kernel, FP64 worst case
     size_t part_mfma = (size_t)L.nblk * L.bmax * 4;
-    B.part = take(part_direct > part_mfma ? part_direct : part_mfma);
+    B.part = take(L.untrunc ? 0 : (part_direct > part_mfma ? part_direct : part_mfma));
+    if (L.untrunc) {
+        B.dp_T = take((size_t)L.tbytes * (size_t)L.k * (size_t)L.ldT);
+        B.dp_tsel = take(8 * (size_t)L.bmax);
+        B.dp_gsel = take(8 * (size_t)L.bmax);
+        B.dp_gctr = (int32_t *)take(4 * (size_t)L.bmax);
+        B.dp_pair = (double *)take(8 * (size_t)L.bmax);
+        B.dp_toff = (int32_t *)take(4 * ((size_t)L.k + 1));
+        B.dp_pp = (double *)take(8 * (size_t)((L.bmax + 63) / 64) * L.bmax);
+        B.dp_w = (double *)take(8 * (size_t)L.k);
+        B.dp_iseg = (int32_t *)take(4 * ((size_t)L.k + 1));
+        B.dp_irow = (int32_t *)take(4 * (size_t)L.k);
+    }
     B.labels = (int32_t *)take(4 * (size_t)L.bmax);
     B.mind = (float *)take(4 * (size_t)L.bmax);
     B.margin = (float *)take(4 * (size_t)L.bmax);
@@ -192,9 +210,32 @@ static int check_config(const mbkk_config *c, std::string &why)
         why = "need tau >= 0";
         return MBKK_E_INVALID;
     }
-    if (c->window < 1 || c->window > kMaxWindow) {
-        why = "need 1 <= window <= 30";
+    if (c->window < 0 || c->window > kMaxWindow) {
+        why = "need 0 <= window <= 30";
         return MBKK_E_INVALID;
+    }
+    if (c->window == 0) {
+        if (c->tau != 0) {
+            why = "window 0 (untruncated) takes no tau";
+            return MBKK_E_INVALID;
+        }
+        if (c->precision != MBKK_FP32 && c->precision != MBKK_FP64) {
+            why = "window 0 (untruncated) runs in FP32 or FP64";
+            return MBKK_E_INVALID;
+        }
+        if (c->cross_impl == MBKK_CROSS_MFMA) {
+            why = "window 0 (untruncated) has no MFMA form";
+            return MBKK_E_INVALID;
+        }
+        if (c->d > dp_max_dim()) {
+            why = "window 0 (untruncated) needs d <= 128";
+            return MBKK_E_INVALID;
+        }
+        const double tb = (double)(c->precision == MBKK_FP64 ? 8 : 4) * (double)c->k * (double)(c->n + 63);
+        if (tb > (double)((int64_t)1 << 42)) {
+            why = "window 0 (untruncated): the n x k table exceeds 4 TiB";
+            return MBKK_E_INVALID;
+        }
     }
     if (c->kernel < MBKK_GAUSS || c->kernel > MBKK_POLY2) {
         why = "unknown kernel";
@@ -475,6 +516,14 @@ int mbkk_set_data(mbkk_ctx *c, const float *X, int64_t ld)
     return MBKK_OK;
 }
 
+// The Gaussian FP32 table update in product form (norms and dot product), as
+// the cross term of the truncated form in FP32 with cross_impl AUTO / MFMA
+// (d >= 16); cross_impl DIRECT keeps the coordinate differences.
+static bool dp_dot(const mbkk_config &c)
+{
+    return c.kernel == MBKK_GAUSS && c.precision == MBKK_FP32 && c.cross_impl != MBKK_CROSS_DIRECT && c.d >= 16;
+}
+
 static int init_common(mbkk_ctx *c, const int32_t *idx_dev)
 {
     const Layout &L = c->L;
@@ -485,8 +534,12 @@ static int init_common(mbkk_ctx *c, const int32_t *idx_dev)
     launch_gather_rows(B.X, L.n, L.d, B.ld, idx_dev, L.k, L.dp, B.pool32, L.bf16 ? B.poolhi : nullptr,
                        L.bf16 ? B.poollo : nullptr, B.poolsq, B.poolsq64, B.init_idx, B.flags, c->cfg.validate,
                        c->stream);
-    launch_init_state(L, B, c->cfg.kernel, c->cfg.kernel_param, c->fp64, 1, c->stream);
-    HIPCHK(c, hipMemsetAsync(B.ring_off, 0, 4 * (size_t)L.P * (L.k + 1), c->stream));
+    if (L.untrunc) {
+        launch_dp_init(L, B, c->cfg.kernel, c->cfg.kernel_param, c->fp64, dp_dot(c->cfg), c->stream);
+    } else {
+        launch_init_state(L, B, c->cfg.kernel, c->cfg.kernel_param, c->fp64, 1, c->stream);
+        HIPCHK(c, hipMemsetAsync(B.ring_off, 0, 4 * (size_t)L.P * (L.k + 1), c->stream));
+    }
     HIPCHK(c, hipGetLastError());
     c->iter = 1;
     c->support_iter = -1;
@@ -535,6 +588,54 @@ int mbkk_init_kmeanspp(mbkk_ctx *c, const double *u_host, int32_t *idx_out_dev)
     return init_common(c, c->B.picks);
 }
 
+// One iteration of Algorithm 1 on the table of cross terms (window 0): the
+// batch is staged in slot 0 (pool rows for the pair sums and the table
+// update, its indices for the last batch's objective), scored from the
+// table, grouped, and T and N updated.
+static int dp_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels_dev, float *mind_dev,
+                   double *fbefore_host)
+{
+    const Layout &L = c->L;
+    Buffers &B = c->B;
+    const mbkk_config &cf = c->cfg;
+    if (cf.validate && clear_flags(c))
+        return MBKK_E_HIP;
+    set_batch_view(c, 0);
+    launch_gather_rows(B.X, L.n, L.d, B.ld, batch, b, L.dp, B.bat32, nullptr, nullptr, B.batsq, B.batsq64, B.batidx,
+                       B.flags, cf.validate, c->stream);
+    launch_dp_score(L, B, cf.kernel, cf.kernel_param, c->fp64, B.batidx, b, true, nullptr, 0, nullptr, c->stream);
+    launch_sum_mind(B, b, 0, c->stream);
+    launch_dp_update(L, B, b, cf.kernel, cf.kernel_param, c->fp64, cf.lr, c->stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        int rc = timing_pair(c, &e0, &e1);
+        if (rc)
+            return rc;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+    }
+    launch_dp_table(L, B, cf.kernel, cf.kernel_param, c->fp64, 0, dp_dot(cf), c->stream);
+    if (c->timing) {
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        c->launches++;
+    }
+    HIPCHK(c, hipGetLastError());
+    c->slot_b[0] = b;
+    c->iter += 1;
+    if (labels_dev)
+        HIPCHK(c, hipMemcpyAsync(labels_dev, B.labels, 4 * (size_t)b, hipMemcpyDeviceToDevice, c->stream));
+    if (mind_dev)
+        HIPCHK(c, hipMemcpyAsync(mind_dev, B.mind, 4 * (size_t)b, hipMemcpyDeviceToDevice, c->stream));
+    if (fbefore_host) {
+        double s = 0.0;
+        HIPCHK(c, hipMemcpyAsync(&s, B.obj + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        *fbefore_host = s / (double)b;
+    }
+    if (cf.validate)
+        return check_flags(c);
+    return MBKK_OK;
+}
+
 int mbkk_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels_dev, float *mind_dev,
               double *fbefore_host)
 {
@@ -544,6 +645,8 @@ int mbkk_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels_dev,
         return fail(c, MBKK_E_STATE, "init_centers / init_kmeanspp first");
     if (!batch || b <= 0 || b > c->L.bmax)
         return fail(c, MBKK_E_INVALID, "need a batch with 1 <= b <= b_max");
+    if (c->L.untrunc)
+        return dp_step(c, batch, b, labels_dev, mind_dev, fbefore_host);
     const Layout &L = c->L;
     Buffers &B = c->B;
     const int64_t i = c->iter;
@@ -606,14 +709,19 @@ int mbkk_assign(mbkk_ctx *c, const int32_t *idx, int64_t m, int32_t *labels_dev,
     Buffers &B = c->B;
     if (c->cfg.validate && clear_flags(c))
         return MBKK_E_HIP;
-    if (m == 0)
+    if (m == 0 && !L.untrunc)
         prepare(c, nullptr, 0);
     for (int64_t m0 = 0; m0 < m; m0 += L.bmax) {
         const int nb = (int)((m - m0) < L.bmax ? (m - m0) : L.bmax);
-        prepare(c, idx + m0, nb);
-        int rc = cross_and_score(c, nb, D_dev ? D_dev + m0 * L.k : nullptr, L.k, false);
-        if (rc)
-            return rc;
+        if (L.untrunc) {
+            launch_dp_score(L, B, c->cfg.kernel, c->cfg.kernel_param, c->fp64, idx + m0, nb, false,
+                            D_dev ? D_dev + m0 * L.k : nullptr, L.k, c->cfg.validate ? B.flags : nullptr, c->stream);
+        } else {
+            prepare(c, idx + m0, nb);
+            int rc = cross_and_score(c, nb, D_dev ? D_dev + m0 * L.k : nullptr, L.k, false);
+            if (rc)
+                return rc;
+        }
         if (labels_dev)
             HIPCHK(c, hipMemcpyAsync(labels_dev + m0, B.labels, 4 * (size_t)nb, hipMemcpyDeviceToDevice, c->stream));
         if (mind_dev)
@@ -639,10 +747,15 @@ int mbkk_objective(mbkk_ctx *c, const int32_t *idx, int64_t m, double *out_host)
         return MBKK_E_HIP;
     for (int64_t m0 = 0; m0 < m; m0 += L.bmax) {
         const int nb = (int)((m - m0) < L.bmax ? (m - m0) : L.bmax);
-        prepare(c, idx + m0, nb);
-        int rc = cross_and_score(c, nb, nullptr, 0, false);
-        if (rc)
-            return rc;
+        if (L.untrunc) {
+            launch_dp_score(L, c->B, c->cfg.kernel, c->cfg.kernel_param, c->fp64, idx + m0, nb, false, nullptr, 0,
+                            c->cfg.validate ? c->B.flags : nullptr, c->stream);
+        } else {
+            prepare(c, idx + m0, nb);
+            int rc = cross_and_score(c, nb, nullptr, 0, false);
+            if (rc)
+                return rc;
+        }
         launch_sum_mind(c->B, nb, m0 > 0, c->stream);
     }
     double s = 0.0;
@@ -745,6 +858,8 @@ static int grad_args(mbkk_ctx *c, const float *xb, int32_t b, double sigma)
 {
     if (!c)
         return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (c->L.untrunc)
+        return fail(c, MBKK_E_STATE, "the differentiation form needs the centers' support (window >= 1)");
     if (!c->inited)
         return fail(c, MBKK_E_STATE, "init_centers / init_kmeanspp first");
     if (c->cfg.kernel != MBKK_GAUSS)
@@ -852,7 +967,8 @@ int mbkk_center_norms(mbkk_ctx *c, double *N_host)
         return fail(c, MBKK_E_STATE, "init_centers / init_kmeanspp first");
     if (!N_host)
         return fail(c, MBKK_E_INVALID, "N is NULL");
-    prepare(c, nullptr, 0);
+    if (!c->L.untrunc)
+        prepare(c, nullptr, 0);
     HIPCHK(c, hipMemcpyAsync(N_host, c->B.N, 8 * (size_t)c->L.k, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return MBKK_OK;
@@ -862,6 +978,8 @@ int mbkk_get_state(mbkk_ctx *c, mbkk_state *s)
 {
     if (!c)
         return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (c->L.untrunc)
+        return fail(c, MBKK_E_STATE, "window 0 keeps the centers as the table of cross terms: no state image");
     if (!c->inited)
         return fail(c, MBKK_E_STATE, "no state yet");
     const Layout &L = c->L;
@@ -902,6 +1020,8 @@ int mbkk_set_state(mbkk_ctx *c, const mbkk_state *s)
 {
     if (!c)
         return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (c->L.untrunc)
+        return fail(c, MBKK_E_STATE, "window 0 keeps the centers as the table of cross terms: no state image");
     if (!c->data_set)
         return fail(c, MBKK_E_STATE, "set_data first");
     const Layout &L = c->L;

@@ -115,6 +115,17 @@ struct Buffers {
     double *Nsig = nullptr;      // [k] self norms at the bandwidth of the call
     double *dNsig = nullptr;     // [k] their derivative
     double *rowds = nullptr;     // [bmax] per-row terms of df/dsigma
+    // untruncated form (window 0): the table of cross terms of every point
+    void *dp_T = nullptr;        // [k * ldT] T[j][x] = <phi(x), C_j>, FP32 or FP64
+    void *dp_tsel = nullptr;     // [bmax] old T[label][x] of the batch rows
+    void *dp_gsel = nullptr;     // [bmax] the same, grouped by center
+    int32_t *dp_gctr = nullptr;  // [bmax] center of each grouped entry
+    double *dp_pair = nullptr;   // [bmax] sum of K(y, y') over the entry's center
+    int32_t *dp_toff = nullptr;  // [k+1] offsets of the centers' pair tasks
+    double *dp_pp = nullptr;     // [ceil(bmax/64) * bmax] row sums of the pair tasks by column tile
+    double *dp_w = nullptr;      // [k] alpha_j / b_j of the update (1 at init)
+    int32_t *dp_iseg = nullptr;  // [k+1] one-entry segments of the initial centers
+    int32_t *dp_irow = nullptr;  // [k] their pool rows
     // k-means++
     double *D2 = nullptr;        // [n]
     double *kself = nullptr;     // [n]
@@ -133,6 +144,9 @@ struct Layout {
     int64_t kpp_blocks;
     bool bf16;
     int frag_mode;     // batch fragment copy: 0 none, 1 BF16 hi/lo, 2 FP32
+    bool untrunc;      // window 0: untruncated, on the table of cross terms
+    int64_t ldT;       // its row stride (n rounded up to 64)
+    int tbytes;        // bytes of a table entry (4 or 8)
     size_t bytes;
 };
 

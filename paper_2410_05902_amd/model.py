@@ -28,6 +28,8 @@ def _ptr(t: Optional[torch.Tensor]):
 class Model:
     """Implicit centers held as weights over the points of their last
     `window` batches (Eq. 1), updated one batch at a time (Algorithm 2).
+    window = 0: untruncated (Algorithm 1), with the centers held as the table
+    of cross terms <phi(x), C_j> of every point (Appendix A).
 
     X: (n, d) float32 CUDA tensor, borrowed for the lifetime of the model.
     """

@@ -50,12 +50,15 @@ def test_workspace_size_and_validation():
     rc, nb = _ws(_cfg())
     assert rc == _lib.OK and nb > 0 and nb % 256 == 0
     bad = [dict(k=0), dict(k=2000), dict(n=0), dict(d=0), dict(b_max=0), dict(b_max=20000),
-           dict(window=0), dict(window=31), dict(kernel=9), dict(kernel_param=0.0),
+           dict(window=-1), dict(window=31), dict(kernel=9), dict(kernel_param=0.0),
            dict(precision=7), dict(lr=5), dict(cross_impl=3),
            dict(kernel=_lib.LAPLACE, precision=_lib.BF16X3),
            dict(kernel=_lib.LINEAR, cross_impl=_lib.CROSS_MFMA),
            dict(precision=_lib.BF16X3, cross_impl=_lib.CROSS_DIRECT),
-           dict(precision=_lib.FP64, cross_impl=_lib.CROSS_MFMA)]
+           dict(precision=_lib.FP64, cross_impl=_lib.CROSS_MFMA),
+           # the untruncated table form: no tau, FP32 / FP64 on the VALU, d <= 128
+           dict(window=0, tau=5), dict(window=0, precision=_lib.BF16X3),
+           dict(window=0, cross_impl=_lib.CROSS_MFMA), dict(window=0, d=129)]
     for b in bad:
         rc, _ = _ws(_cfg(**b))
         assert rc == _lib.E_INVALID, b
@@ -68,6 +71,19 @@ def test_workspace_grows_with_the_problem():
     assert _ws(_cfg(window=8))[1] > small
     from paper_2410_05902_amd import _lib
     assert _ws(_cfg(precision=_lib.BF16X3))[1] > small   # hi/lo copies of the pool
+
+
+def test_untruncated_workspace_holds_the_table():
+    """window 0: the workspace holds the k x n table of cross terms (n padded
+    to 64), 4 bytes an entry in FP32 and 8 in FP64."""
+    from paper_2410_05902_amd import _lib
+    a = _ws(_cfg(window=0, n=100_000))
+    b = _ws(_cfg(window=0, n=200_000))
+    assert a[0] == _lib.OK and b[0] == _lib.OK
+    k = _cfg().k
+    assert b[1] - a[1] >= 4 * k * 100_000
+    c = _ws(_cfg(window=0, n=100_000, precision=_lib.FP64))
+    assert c[1] - a[1] >= 4 * k * 100_000
 
 
 def test_create_rejects_missing_workspace():
