@@ -74,7 +74,7 @@ def traffic_summary(args):
     copy_mib MiB to what the same counter reads for that copy."""
     fdir, wdir, cfdir, cwdir = args.traffic_summary
     wl = args.workload + ("u" if args.untruncated else "")
-    kern = "k_dp_table" if args.untruncated else ("k_cross_direct" if wl == "c5" else "k_cross_bs")
+    kern = ("k_dp_mfma" if args.workload == "c3" else "k_dp_table") if args.untruncated else ("k_cross_direct" if wl == "c5" else "k_cross_bs")
     src = DP_SRC if args.untruncated else CROSS_SRC
     fetch, write = _counter_means(fdir, "FETCH_SIZE"), _counter_means(wdir, "WRITE_SIZE")
     cf, cw = _counter_means(cfdir, "FETCH_SIZE"), _counter_means(cwdir, "WRITE_SIZE")
@@ -224,18 +224,23 @@ def main():
     traffic = measured_traffic(args.workload + ("u" if untrunc else ""), DP_SRC if untrunc else CROSS_SRC)
     if untrunc:
         # the table kernel: 2 FP32 VALU lane operations per coordinate per
-        # evaluation (subtract and add |.|; the Gaussian product form does one
-        # FMA, counted as 2 as well), peak as for the direct kernel; its
+        # evaluation (subtract and add |.|), peak as for the direct kernel; its
         # algorithmic HBM bytes: the table entries of the centers that the
         # batch touched read and written once, X read once
         ops = 2.0 * wl.d * evals
         kact = float(np.mean(active)) if active else float(wl.k)
         tbytes = 2.0 * 4 * wl.n * kact + 4.0 * wl.n * wl.d
-        roof = {"bound": "alu", "achieved": ops / (ms_cross * 1e-3) / 1e12, "peak": PEAK["f32"] / 2e12,
-                "unit": "TOP/s", "frac": ops / (ms_cross * 1e-3) / (PEAK["f32"] / 2), "traffic": traffic,
-                "kernel": f"k_dp_table<{'gauss' if gauss else 'laplace'},f32>", "ops_per_launch": ops,
-                "table_bytes_per_launch": tbytes, "table_GBps": tbytes / (ms_cross * 1e-3) / 1e9,
-                "centers_touched_per_step": kact}
+        if gauss and precision == "fp32" and wl.d >= 16:
+            # the Gaussian table update on FP32 MFMA: 2 d flops per evaluation
+            roof = {"bound": "mfma", "achieved": ops / (ms_cross * 1e-3) / 1e12, "peak": PEAK["f32"] / 1e12,
+                    "unit": "TFLOP/s", "frac": ops / (ms_cross * 1e-3) / PEAK["f32"], "traffic": traffic,
+                    "kernel": "k_dp_mfma + k_dp_blend (gauss, f32)", "flops_per_launch": ops}
+        else:
+            roof = {"bound": "alu", "achieved": ops / (ms_cross * 1e-3) / 1e12, "peak": PEAK["f32"] / 2e12,
+                    "unit": "TOP/s", "frac": ops / (ms_cross * 1e-3) / (PEAK["f32"] / 2), "traffic": traffic,
+                    "kernel": f"k_dp_table<{'gauss' if gauss else 'laplace'},f32>", "ops_per_launch": ops}
+        roof.update({"table_bytes_per_launch": tbytes, "table_GBps": tbytes / (ms_cross * 1e-3) / 1e9,
+                     "centers_touched_per_step": kact})
         if traffic:
             roof["hbm_GBps"] = traffic / (ms_cross * 1e-3) / 1e9
     elif gauss:

@@ -68,14 +68,13 @@ int grad_max_dim();
 // sums, N and weights of batch rows [0, b) (staged in slot 0).  table: the
 // update of T over all of X.
 int dp_max_dim();
-// dot: the Gaussian FP32 table update takes the squared distance from the
-// norms and the dot product (else from the coordinate differences).
-void launch_dp_init(const Layout &L, const Buffers &B, int kind, double param, int fp64, bool dot, hipStream_t st);
+void launch_dp_init(const Layout &L, const Buffers &B, int kind, double param, int fp64, hipStream_t st);
 void launch_dp_score(const Layout &L, const Buffers &B, int kind, double param, int fp64, const int32_t *idx, int m,
                      bool step, double *D_out, int64_t ldD, int32_t *flags, hipStream_t st);
 void launch_dp_update(const Layout &L, const Buffers &B, int b, int kind, double param, int fp64, int lr,
                       hipStream_t st);
-void launch_dp_table(const Layout &L, const Buffers &B, int kind, double param, int fp64, int init, bool dot,
+// L.dp_mfma: the Gaussian FP32 form on MFMA (k_dp_mfma + k_dp_blend).
+void launch_dp_table(const Layout &L, const Buffers &B, int kind, double param, int fp64, int init,
                      hipStream_t st);
 
 // Contingency table [k x c] (int64, zeroed by the caller) of labels in [0, k)

@@ -25,7 +25,9 @@
 //   k_dp_gram  : the pair tasks: partial sums of K(y, y') over 64 columns;
 //   k_dp_rowsum: sum over B_i^j of K(y, y') for each grouped row y;
 //   k_dp_norms : the N update and the per-center weights a / b_i^j;
-//   k_dp_table : the table update over all of X (the O(n b) term).
+//   k_dp_table : the table update over all of X (the O(n b) term) on the
+//                VALU; the Gaussian in FP32 runs it on MFMA instead
+//                (k_dp_mfma, then k_dp_blend).
 #include "dev_common.h"
 #include "kernels.h"
 
@@ -368,10 +370,8 @@ __global__ __launch_bounds__(256) void k_dp_norms(int k, const int32_t *__restri
 }
 
 // ---------------------------------------------------------------------------
-// Table update over all of X.  DOT (Gaussian, FP32): the squared distance is
-// taken from the expansion |x|^2 + |y|^2 - 2 x.y, one FMA per coordinate
-// instead of a subtraction and an FMA, with the norms' exponent terms per row
-// and per entry (the FP32 product form of the Gaussian cross kernels).  Lane = RPL rows of X (256 apart), held in
+// Table update over all of X on the VALU (every kernel; the Gaussian in FP64,
+// with cross_impl DIRECT, or at d < 16).  Lane = RPL rows of X (256 apart), held in
 // registers; every workgroup runs over all grouped entries, 64 at a time
 // (lane e loads entry e's pool row, then the entries are broadcast one by
 // one and their coordinates read with wave-uniform loads).  At the end of a
@@ -379,10 +379,9 @@ __global__ __launch_bounds__(256) void k_dp_norms(int k, const int32_t *__restri
 //     T[j][x] <- (1 - alpha_j) T[j][x] + (alpha_j / b_j) * sum,
 // or, when init is set, T[j][x] <- wgt_j * sum without reading T.
 // ---------------------------------------------------------------------------
-template <int KIND, typename TT, int DR, int RPL, bool DOT>
+template <int KIND, typename TT, int DR, int RPL>
 __global__ __launch_bounds__(kDpTableWG) void k_dp_table(int64_t n, int d, int64_t ld, const float *__restrict__ X,
-                                                         int dp, const float *__restrict__ pool32,
-                                                         const float *__restrict__ poolsq, int k,
+                                                         int dp, const float *__restrict__ pool32, int k,
                                                          const int32_t *__restrict__ seg,
                                                          const int32_t *__restrict__ sup_row,
                                                          const double *__restrict__ alpha,
@@ -404,20 +403,6 @@ __global__ __launch_bounds__(kDpTableWG) void k_dp_table(int64_t n, int d, int64
 #pragma unroll
         for (int t = 0; t < DR; ++t)
             x[q][t] = t < d ? (TT)X[rr[q] * ld + t] : (TT)0;
-    // DOT: exponent log2(e) (2 x.y - |x|^2 - |y|^2) / kappa = c2 x.y - cx - cy
-    const TT c2 = (TT)(2.0 * 1.4426950408889634 / param);
-    TT cx[RPL];
-#pragma unroll
-    for (int q = 0; q < RPL; ++q) {
-        cx[q] = 0;
-        if constexpr (DOT) {
-            TT xx = 0;
-#pragma unroll
-            for (int t = 0; t < DR; ++t)
-                xx = fma(x[q][t], x[q][t], xx);
-            cx[q] = xx * (TT)0.5 * c2;
-        }
-    }
     const int M = seg[k];
     if (M == 0)
         return;
@@ -443,9 +428,6 @@ __global__ __launch_bounds__(kDpTableWG) void k_dp_table(int64_t n, int d, int64
     for (int c0 = 0; c0 < M; c0 += 64) {
         const int cnt = min(64, M - c0);
         const int lrow = sup_row[c0 + (lane < cnt ? lane : 0)];
-        TT lcy = 0;
-        if constexpr (DOT)
-            lcy = (TT)poolsq[lrow] * (TT)0.5 * c2;
         for (int e = 0; e < cnt; ++e) {  // wave uniform
             const int s = c0 + e;
             if (s >= cur_end) {
@@ -464,26 +446,233 @@ __global__ __launch_bounds__(kDpTableWG) void k_dp_table(int64_t n, int d, int64
             for (int t = 0; t < DR; ++t) {
                 const TT yt = (TT)y[t];
 #pragma unroll
-                for (int q = 0; q < RPL; ++q) {
-                    if constexpr (DOT)
-                        sacc[q] = fma(x[q][t], yt, sacc[q]);
-                    else
-                        sacc[q] = dp_kstep<KIND, TT>(x[q][t], yt, sacc[q]);
-                }
-            }
-            if constexpr (DOT) {
-                const TT cy = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lcy), e));
-#pragma unroll
                 for (int q = 0; q < RPL; ++q)
-                    acc[q] += __builtin_amdgcn_exp2f(fma(sacc[q], c2, -(cx[q] + cy)));
-            } else {
-#pragma unroll
-                for (int q = 0; q < RPL; ++q)
-                    acc[q] += dp_kfinish<KIND, TT>(sacc[q], cneg, prm);
+                    sacc[q] = dp_kstep<KIND, TT>(x[q][t], yt, sacc[q]);
             }
+#pragma unroll
+            for (int q = 0; q < RPL; ++q)
+                acc[q] += dp_kfinish<KIND, TT>(sacc[q], cneg, prm);
         }
     }
     flush(j);
+}
+
+// ---------------------------------------------------------------------------
+// Table update of the Gaussian on MFMA (FP32 products, v_mfma_f32_32x32x2f32).
+// The product form S = x.y - |x|^2 / 2 is a dense contraction over the
+// coordinates: A = 32 grouped batch entries (rows m), B = 32 points of X
+// (columns n), K(x, y) = exp2(c2 S + ay) with c2 = 2 log2(e) / kappa and
+// ay = -log2(e) |y|^2 / kappa.  Lane l = 32 h + n holds point n's column of a
+// 32 x 32 tile: entries m(i) = 8 (i / 4) + 4 h + i % 4, i = 0..15.  Lane half
+// h contracts the coordinates h KS .. h KS + KS - 1 (KS = DP / 2), so each lane
+// reads consecutive coordinates of its rows.
+//
+// A wave holds two 32-point blocks of X in registers (64 points, 256 per
+// workgroup) and runs over all grouped entries, staged 64 at a time through
+// LDS (double-buffered; rows padded by 4 floats so that the 16-byte reads of
+// 16 lanes fall in distinct banks).  After each 32-entry tile the lane sums
+// its kernel values per center segment (masks on m); at the end of a segment
+// the two lane halves are combined (permlane32 swap) and
+//     S[j][x] = (alpha_j / b_j) sum_{y in B^j} K(x, y)
+// is stored; k_dp_blend then forms T <- (1 - alpha) T + S for the touched
+// centers.  Entries past the support are zero rows outside every segment.
+// ---------------------------------------------------------------------------
+constexpr int kDpMfmaStage = 64;  // grouped entries per LDS stage
+
+// (two workgroups per compute unit up to DP = 96; at DP = 128 the two
+// register-resident blocks of X take one wave per SIMD)
+template <int DP>
+__global__ __launch_bounds__(256, DP == 128 ? 1 : 2) void k_dp_mfma(int64_t n, int d, int64_t ld, const float *__restrict__ X,
+                                                    const float *__restrict__ pool32,
+                                                    const float *__restrict__ poolsq, int k,
+                                                    const int32_t *__restrict__ seg,
+                                                    const int32_t *__restrict__ sup_row,
+                                                    const double *__restrict__ wgt, float c2,
+                                                    float *__restrict__ S, int64_t ldT)
+{
+    constexpr int KS = DP / 2;   // MFMA k-steps
+    constexpr int RS = DP + 4;   // LDS row stride (floats)
+    constexpr int NE = kDpMfmaStage;
+    constexpr int FPT = NE * DP / 256;  // floats staged per thread and stage
+    static_assert(FPT % 4 == 0 && KS % 4 == 0, "staging in 16-byte pieces");
+    __shared__ __attribute__((aligned(16))) float sY[2][NE * RS];
+    __shared__ __attribute__((aligned(16))) float sAy[2][NE];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nn = lane & 31, h = lane >> 5;
+    const int M = seg[k];
+    if (M == 0)
+        return;
+    const float ayc = -0.5f * c2;  // ay = ayc |y|^2
+    // ---- the wave's two blocks of X in registers ----------------------------
+    const int64_t x0 = (int64_t)blockIdx.x * 256 + w * 64;
+    float bx[2][KS];
+    float hx[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int64_t row = x0 + q * 32 + nn;
+        const float *xr = X + (row < n ? row : 0) * ld;
+        float ss = 0.0f;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int t = h * KS + s;
+            bx[q][s] = t < d ? xr[t] : 0.0f;
+            ss = fmaf(bx[q][s], bx[q][s], ss);
+        }
+        ss += __shfl_xor(ss, 32);
+        hx[q] = -0.5f * ss;
+    }
+    // ---- staging of grouped entries [e0, e0 + 64) into buffer bb ------------
+    // thread t stages entry t / 4, floats (t % 4) * FPT .. + FPT of its row
+    const int se = tid >> 2, sq = tid & 3;
+    f32x4 pre[FPT / 4];
+    float pay = 0.0f;
+    auto fetch = [&](int e0) {
+        const int e = e0 + se;
+        const int row = e < M ? sup_row[e] : -1;
+        const float *src = pool32 + (int64_t)(row < 0 ? 0 : row) * DP + sq * FPT;
+#pragma unroll
+        for (int u = 0; u < FPT / 4; ++u)
+            pre[u] = row < 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : *(const f32x4 *)(src + 4 * u);
+        pay = row < 0 ? 0.0f : ayc * poolsq[row];
+    };
+    auto commit = [&](int bb) {
+        float *dst = &sY[bb][se * RS + sq * FPT];
+#pragma unroll
+        for (int u = 0; u < FPT / 4; ++u)
+            *(f32x4 *)(dst + 4 * u) = pre[u];
+        if (sq == 0)
+            sAy[bb][se] = pay;
+    };
+    // ---- segment bookkeeping (wave uniform) ---------------------------------
+    int j = wave_segment_of(seg, k, 0);
+    float run[2] = {0.0f, 0.0f};
+    auto store = [&](int jj) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(run[0]), __float_as_uint(run[1]), false,
+                                                         false);
+        const float tot = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+        const int64_t col = x0 + h * 32 + nn;  // lanes < 32: block 0, lanes >= 32: block 1
+        if (col < n)
+            S[(int64_t)jj * ldT + col] = (float)wgt[jj] * tot;
+        run[0] = run[1] = 0.0f;
+    };
+    const int nst = (M + NE - 1) / NE;
+    fetch(0);
+    commit(0);
+    __syncthreads();
+    for (int st = 0; st < nst; ++st) {
+        const int bb = st & 1;
+        if (st + 1 < nst)
+            fetch((st + 1) * NE);
+#pragma unroll
+        for (int t32 = 0; t32 < NE / 32; ++t32) {
+            const int B0 = st * NE + t32 * 32;
+            if (B0 >= M)
+                break;  // wave uniform
+            f32x16 acc[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    acc[q][i] = hx[q];
+            const float *arow = &sY[bb][(t32 * 32 + nn) * RS + h * KS];
+            f32x4 av = *(const f32x4 *)arow, an;
+#pragma unroll
+            for (int s4 = 0; s4 < KS; s4 += 4) {
+                if (s4 + 4 < KS)
+                    an = *(const f32x4 *)(arow + s4 + 4);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+                        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bx[q][s4 + u], acc[q], 0, 0, 0);
+                av = an;
+            }
+            // kernel values of the tile, in place
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                const f32x4 a4 = *(const f32x4 *)&sAy[bb][t32 * 32 + 8 * g + 4 * h];
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+                        acc[q][4 * g + r] = __builtin_amdgcn_exp2f(fmaf(acc[q][4 * g + r], c2, a4[r]));
+            }
+            // segment sums over the tile's entries [B0, B0 + 32)
+            int lo = B0;
+            const int top = min(B0 + 32, M);
+            while (lo < top) {  // wave uniform
+                const int end = seg[j + 1];
+                const int hi = min(end, top);
+                const int mlo = lo - B0, mhi = hi - B0;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int m = 8 * (i >> 2) + 4 * h + (i & 3);
+                    const bool in = m >= mlo && m < mhi;
+                    run[0] += in ? acc[0][i] : 0.0f;
+                    run[1] += in ? acc[1][i] : 0.0f;
+                }
+                if (end <= top) {
+                    store(j);
+                    if (end < M) {
+                        do {
+                            ++j;
+                        } while (seg[j + 1] <= end);
+                    }
+                }
+                lo = hi;
+            }
+        }
+        if (st + 1 < nst)
+            commit(bb ^ 1);
+        __syncthreads();
+    }
+}
+
+// T[j][x] <- (1 - alpha_j) T[j][x] + S[j][x] for the centers with batch points
+// (init: T <- S).  Grid: (point chunks of 1024) x centers.
+__global__ __launch_bounds__(256) void k_dp_blend(int64_t n, const int32_t *__restrict__ seg,
+                                                  const double *__restrict__ alpha, const float *__restrict__ S,
+                                                  float *__restrict__ T, int64_t ldT, int init)
+{
+    const int j = blockIdx.y;
+    if (seg[j + 1] == seg[j])
+        return;
+    const float keep = (float)(1.0 - alpha[j]);
+    const int64_t x = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+    if (x >= n)
+        return;
+    const f32x4 sv = *(const f32x4 *)(S + (int64_t)j * ldT + x);
+    f32x4 *tp = (f32x4 *)(T + (int64_t)j * ldT + x);  // ldT is a multiple of 64: whole vectors
+    if (init) {
+        *tp = sv;
+    } else {
+        const f32x4 tv = *tp;
+        f32x4 r;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            r[u] = fmaf(keep, tv[u], sv[u]);
+        *tp = r;
+    }
+}
+
+static void launch_dp_mfma(const Layout &L, const Buffers &B, const int32_t *seg, const int32_t *sup_row,
+                           double kappa, int init, hipStream_t st)
+{
+    const float c2 = (float)(2.0 * 1.4426950408889634 / kappa);
+    const dim3 grid((unsigned)((L.n + 255) / 256));
+#define MBKK_DP_MFMA(DPV)                                                                                        \
+    hipLaunchKernelGGL(k_dp_mfma<DPV>, grid, dim3(256), 0, st, L.n, L.d, B.ld, B.X, B.pool32, B.poolsq, L.k, seg, \
+                       sup_row, B.dp_w, c2, B.dp_S, L.ldT)
+    switch (L.dp) {
+    case 32: MBKK_DP_MFMA(32); break;
+    case 64: MBKK_DP_MFMA(64); break;
+    case 96: MBKK_DP_MFMA(96); break;
+    default: MBKK_DP_MFMA(128); break;
+    }
+#undef MBKK_DP_MFMA
+    const dim3 gb((unsigned)((L.n + 1023) / 1024), (unsigned)L.k);
+    hipLaunchKernelGGL(k_dp_blend, gb, dim3(256), 0, st, L.n, seg, B.alpha, B.dp_S, (float *)B.dp_T, L.ldT, init);
 }
 
 // Rows per lane of the table update: two for FP32 rows of at most 32
@@ -494,7 +683,7 @@ static int dp_rpl(int d, bool fp64) { return !fp64 && d <= 32 ? 2 : 1; }
 
 int dp_max_dim() { return 128; }
 
-template <int KIND, typename TT, bool DOT>
+template <int KIND, typename TT>
 static void dispatch_dp_table(const Layout &L, const Buffers &B, const int32_t *seg, const int32_t *sup_row,
                               double param, int init, hipStream_t st)
 {
@@ -502,8 +691,8 @@ static void dispatch_dp_table(const Layout &L, const Buffers &B, const int32_t *
     const dim3 grid((unsigned)((L.n + (int64_t)kDpTableWG * rpl - 1) / ((int64_t)kDpTableWG * rpl)));
     TT *T = (TT *)B.dp_T;
 #define MBKK_DP_TABLE(DR, RPL)                                                                                   \
-    hipLaunchKernelGGL((k_dp_table<KIND, TT, DR, RPL, DOT>), grid, dim3(kDpTableWG), 0, st, L.n, L.d, B.ld, B.X,  \
-                       L.dp, B.pool32, B.poolsq, L.k, seg, sup_row, B.alpha, B.dp_w, param, init, T, L.ldT)
+    hipLaunchKernelGGL((k_dp_table<KIND, TT, DR, RPL>), grid, dim3(kDpTableWG), 0, st, L.n, L.d, B.ld, B.X, L.dp, \
+                       B.pool32, L.k, seg, sup_row, B.alpha, B.dp_w, param, init, T, L.ldT)
     constexpr int R2 = sizeof(TT) == 4 ? 2 : 1;
     if (L.d <= 4)
         MBKK_DP_TABLE(4, R2);
@@ -525,34 +714,30 @@ static void dispatch_dp_table(const Layout &L, const Buffers &B, const int32_t *
 
 template <typename TT>
 static void dp_table_kind(const Layout &L, const Buffers &B, int kind, const int32_t *seg, const int32_t *sup_row,
-                          double param, int init, bool dot, hipStream_t st)
+                          double param, int init, hipStream_t st)
 {
     switch (kind) {
-    case MBKK_GAUSS:
-        if constexpr (sizeof(TT) == 4) {
-            if (dot) {
-                dispatch_dp_table<MBKK_GAUSS, TT, true>(L, B, seg, sup_row, param, init, st);
-                break;
-            }
-        }
-        dispatch_dp_table<MBKK_GAUSS, TT, false>(L, B, seg, sup_row, param, init, st);
-        break;
-    case MBKK_LAPLACE: dispatch_dp_table<MBKK_LAPLACE, TT, false>(L, B, seg, sup_row, param, init, st); break;
-    case MBKK_LINEAR: dispatch_dp_table<MBKK_LINEAR, TT, false>(L, B, seg, sup_row, param, init, st); break;
-    default: dispatch_dp_table<MBKK_POLY2, TT, false>(L, B, seg, sup_row, param, init, st); break;
+    case MBKK_GAUSS: dispatch_dp_table<MBKK_GAUSS, TT>(L, B, seg, sup_row, param, init, st); break;
+    case MBKK_LAPLACE: dispatch_dp_table<MBKK_LAPLACE, TT>(L, B, seg, sup_row, param, init, st); break;
+    case MBKK_LINEAR: dispatch_dp_table<MBKK_LINEAR, TT>(L, B, seg, sup_row, param, init, st); break;
+    default: dispatch_dp_table<MBKK_POLY2, TT>(L, B, seg, sup_row, param, init, st); break;
     }
 }
 
-void launch_dp_table(const Layout &L, const Buffers &B, int kind, double param, int fp64, int init, bool dot,
+void launch_dp_table(const Layout &L, const Buffers &B, int kind, double param, int fp64, int init,
                      hipStream_t st)
 {
     // init: one entry per center, the initial points (pool rows 0..k-1)
     const int32_t *seg = init ? B.dp_iseg : B.seg_off;
     const int32_t *sup = init ? B.dp_irow : B.sup_row;
+    if (L.dp_mfma) {
+        launch_dp_mfma(L, B, seg, sup, param, init, st);
+        return;
+    }
     if (fp64)
-        dp_table_kind<double>(L, B, kind, seg, sup, param, init, false, st);
+        dp_table_kind<double>(L, B, kind, seg, sup, param, init, st);
     else
-        dp_table_kind<float>(L, B, kind, seg, sup, param, init, dot, st);
+        dp_table_kind<float>(L, B, kind, seg, sup, param, init, st);
 }
 
 template <int KIND, typename TT>
@@ -682,7 +867,7 @@ __global__ __launch_bounds__(256) void k_dp_init(int k, int d, int dp, const flo
     N[j] = v;
 }
 
-void launch_dp_init(const Layout &L, const Buffers &B, int kind, double param, int fp64, bool dot, hipStream_t st)
+void launch_dp_init(const Layout &L, const Buffers &B, int kind, double param, int fp64, hipStream_t st)
 {
     const dim3 g((unsigned)((L.k + 1 + 255) / 256));
     switch (kind) {
@@ -703,7 +888,7 @@ void launch_dp_init(const Layout &L, const Buffers &B, int kind, double param, i
                            B.dp_w, B.alpha, B.cum, B.dp_iseg, B.dp_irow, B.counts);
         break;
     }
-    launch_dp_table(L, B, kind, param, fp64, 1, dot, st);
+    launch_dp_table(L, B, kind, param, fp64, 1, st);
 }
 
 }  // namespace mbkk

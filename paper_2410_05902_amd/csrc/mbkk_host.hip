@@ -98,6 +98,10 @@ Layout make_layout(const mbkk_config &c)
     L.untrunc = c.window == 0;
     L.ldT = (int64_t)up((size_t)c.n, 64);
     L.tbytes = c.precision == MBKK_FP64 ? 8 : 4;
+    // the Gaussian FP32 table update on MFMA (product form), as the FP32 cross
+    // term of the truncated form with cross_impl AUTO / MFMA (d >= 16)
+    L.dp_mfma = L.untrunc && c.kernel == MBKK_GAUSS && c.precision == MBKK_FP32 &&
+                (c.cross_impl == MBKK_CROSS_MFMA || (c.cross_impl == MBKK_CROSS_AUTO && c.d >= 16));
     // live support: at most W slots of b_max points and the k initial points
     // (the table form: the grouped batch, or the k initial points)
     const int64_t Mlive = L.untrunc ? std::max<int64_t>(c.k, c.b_max) : (int64_t)c.k + (int64_t)c.window * c.b_max;
@@ -163,6 +167,7 @@ void carve(const Layout &Lc, char *base, Buffers &B)
         B.dp_pair = (double *)take(8 * (size_t)L.bmax);
         B.dp_toff = (int32_t *)take(4 * ((size_t)L.k + 1));
         B.dp_pp = (double *)take(8 * (size_t)((L.bmax + 63) / 64) * L.bmax);
+        B.dp_S = L.dp_mfma ? (float *)take(4 * (size_t)L.k * (size_t)L.ldT) : nullptr;
         B.dp_w = (double *)take(8 * (size_t)L.k);
         B.dp_iseg = (int32_t *)take(4 * ((size_t)L.k + 1));
         B.dp_irow = (int32_t *)take(4 * (size_t)L.k);
@@ -221,10 +226,6 @@ static int check_config(const mbkk_config *c, std::string &why)
         }
         if (c->precision != MBKK_FP32 && c->precision != MBKK_FP64) {
             why = "window 0 (untruncated) runs in FP32 or FP64";
-            return MBKK_E_INVALID;
-        }
-        if (c->cross_impl == MBKK_CROSS_MFMA) {
-            why = "window 0 (untruncated) has no MFMA form";
             return MBKK_E_INVALID;
         }
         if (c->d > dp_max_dim()) {
@@ -516,14 +517,6 @@ int mbkk_set_data(mbkk_ctx *c, const float *X, int64_t ld)
     return MBKK_OK;
 }
 
-// The Gaussian FP32 table update in product form (norms and dot product), as
-// the cross term of the truncated form in FP32 with cross_impl AUTO / MFMA
-// (d >= 16); cross_impl DIRECT keeps the coordinate differences.
-static bool dp_dot(const mbkk_config &c)
-{
-    return c.kernel == MBKK_GAUSS && c.precision == MBKK_FP32 && c.cross_impl != MBKK_CROSS_DIRECT && c.d >= 16;
-}
-
 static int init_common(mbkk_ctx *c, const int32_t *idx_dev)
 {
     const Layout &L = c->L;
@@ -535,7 +528,7 @@ static int init_common(mbkk_ctx *c, const int32_t *idx_dev)
                        L.bf16 ? B.poollo : nullptr, B.poolsq, B.poolsq64, B.init_idx, B.flags, c->cfg.validate,
                        c->stream);
     if (L.untrunc) {
-        launch_dp_init(L, B, c->cfg.kernel, c->cfg.kernel_param, c->fp64, dp_dot(c->cfg), c->stream);
+        launch_dp_init(L, B, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->stream);
     } else {
         launch_init_state(L, B, c->cfg.kernel, c->cfg.kernel_param, c->fp64, 1, c->stream);
         HIPCHK(c, hipMemsetAsync(B.ring_off, 0, 4 * (size_t)L.P * (L.k + 1), c->stream));
@@ -613,7 +606,7 @@ static int dp_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels
             return rc;
         HIPCHK(c, hipEventRecord(e0, c->stream));
     }
-    launch_dp_table(L, B, cf.kernel, cf.kernel_param, c->fp64, 0, dp_dot(cf), c->stream);
+    launch_dp_table(L, B, cf.kernel, cf.kernel_param, c->fp64, 0, c->stream);
     if (c->timing) {
         HIPCHK(c, hipEventRecord(e1, c->stream));
         c->launches++;

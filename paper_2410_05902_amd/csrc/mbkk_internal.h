@@ -123,6 +123,7 @@ struct Buffers {
     double *dp_pair = nullptr;   // [bmax] sum of K(y, y') over the entry's center
     int32_t *dp_toff = nullptr;  // [k+1] offsets of the centers' pair tasks
     double *dp_pp = nullptr;     // [ceil(bmax/64) * bmax] row sums of the pair tasks by column tile
+    float *dp_S = nullptr;       // [k * ldT] MFMA form: (alpha_j / b_j) sum_y K(x, y) of the touched centers
     double *dp_w = nullptr;      // [k] alpha_j / b_j of the update (1 at init)
     int32_t *dp_iseg = nullptr;  // [k+1] one-entry segments of the initial centers
     int32_t *dp_irow = nullptr;  // [k] their pool rows
@@ -147,6 +148,7 @@ struct Layout {
     bool untrunc;      // window 0: untruncated, on the table of cross terms
     int64_t ldT;       // its row stride (n rounded up to 64)
     int tbytes;        // bytes of a table entry (4 or 8)
+    bool dp_mfma;      // the table update on MFMA (Gaussian FP32, d >= 16)
     size_t bytes;
 };
 

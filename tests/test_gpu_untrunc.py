@@ -99,11 +99,12 @@ def test_laplace_d32_two_rows_per_lane():
     assert run_untrunc(wl.X, 24, wl.kernel, 20.0, init, batches, "fp32") == 6
 
 
-@pytest.mark.parametrize("d,impl", [(8, "auto"), (64, "auto"), (72, "auto"), (100, "auto"), (64, "direct"),
-                                    (128, "auto")])
+@pytest.mark.parametrize("d,impl", [(8, "auto"), (8, "mfma"), (20, "auto"), (64, "auto"), (72, "auto"), (100, "auto"),
+                                    (64, "direct"), (128, "auto")])
 def test_gauss_fp32_widths(d, impl):
-    """d >= 16 with cross_impl auto: the product form (norms and dot product);
-    d < 16 or cross_impl direct: coordinate differences."""
+    """d >= 16 with cross_impl auto, or cross_impl mfma: the table update on
+    MFMA (product form); d < 16 with auto, or direct: the VALU kernel with
+    coordinate differences."""
     X, comp, init = _gmm(5000, d, 10, 0.3, seed=41 + d)
     sigma = W.median_pairwise_distance(X, 0)
     rng = np.random.default_rng(42)
@@ -176,7 +177,9 @@ def test_errors_of_the_table_form():
     with pytest.raises(MbkkError):
         Model(Xd, k=3, b_max=64, window=0, precision="bf16x3")
     with pytest.raises(MbkkError):
-        Model(Xd, k=3, b_max=64, window=0, cross_impl="mfma")
+        Model(Xd, k=3, b_max=64, window=0, precision="fp64", cross_impl="mfma")
+    with pytest.raises(MbkkError):
+        Model(Xd, k=3, b_max=64, window=0, kernel="laplace", cross_impl="mfma")
     model = Model(Xd, k=3, b_max=64, window=0, kernel_param=2.0)
     model.init_centers(init)
     with pytest.raises(MbkkError):
@@ -216,6 +219,38 @@ def test_full_size_sampled_rows():
             np.testing.assert_array_equal(lab, ref["labels"])  # every margin is wide at step 1
         elif not (lab == ref["labels"]).all():
             break  # a near tie parted the trajectories after the compared state
+        N = orc.norms()
+        D = orc.distances(sample, threads=8)["D"]
+        a = model.assign(sample, want_D=True)
+        err = dist_rel_err(a["D"].cpu().numpy(), D, 1.0 + N[None, :])
+        assert err.max() <= TOL["fp32"], f"after step {i}: {err.max():.3e}"
+        np.testing.assert_allclose(model.center_norms(), N, rtol=1e-5, atol=1e-8)
+
+
+def test_full_size_gaussian_mfma_sampled_rows():
+    """The Gaussian mixture at n = 1,000,000, d = 128, k = 100, b = 4096, window
+    0 (the table update on MFMA): after two steps, the distances of sampled
+    points to every center equal the oracle's."""
+    wl = W.c3_gaussian_mixture(seed=0)
+    first = np.full(wl.k, -1, np.int64)
+    rows = np.arange(wl.n)
+    first[wl.comp[::-1]] = rows[::-1]
+    init = first.astype(np.int32)
+    assert (init >= 0).all()
+    orc = O.Oracle(wl.X, wl.k, 0, wl.kernel, wl.kernel_param)
+    orc.init_centers(init)
+    model = _model(wl.X, wl.k, wl.b, wl.kernel, wl.kernel_param, "fp32")
+    model.init_centers(init)
+    rng = np.random.default_rng(56)
+    sample = np.concatenate([rng.integers(0, wl.n, 500), [0, wl.n - 1]]).astype(np.int32)
+    for i in (1, 2):
+        B = wl.batch(i)
+        ref = orc.step(B, threads=8)
+        lab = model.step(B)["labels"].cpu().numpy()
+        ag = agreement(lab, ref["labels"], ref["margin"], MARGIN["fp32"])
+        assert ag["on_margin"], ag["mismatches"][:8]
+        if not (lab == ref["labels"]).all():
+            break
         N = orc.norms()
         D = orc.distances(sample, threads=8)["D"]
         a = model.assign(sample, want_D=True)

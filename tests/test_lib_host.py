@@ -58,7 +58,8 @@ def test_workspace_size_and_validation():
            dict(precision=_lib.FP64, cross_impl=_lib.CROSS_MFMA),
            # the untruncated table form: no tau, FP32 / FP64 on the VALU, d <= 128
            dict(window=0, tau=5), dict(window=0, precision=_lib.BF16X3),
-           dict(window=0, cross_impl=_lib.CROSS_MFMA), dict(window=0, d=129)]
+           dict(window=0, precision=_lib.FP64, cross_impl=_lib.CROSS_MFMA),
+           dict(window=0, kernel=_lib.LAPLACE, cross_impl=_lib.CROSS_MFMA), dict(window=0, d=129)]
     for b in bad:
         rc, _ = _ws(_cfg(**b))
         assert rc == _lib.E_INVALID, b
@@ -77,13 +78,17 @@ def test_untruncated_workspace_holds_the_table():
     """window 0: the workspace holds the k x n table of cross terms (n padded
     to 64), 4 bytes an entry in FP32 and 8 in FP64."""
     from paper_2410_05902_amd import _lib
-    a = _ws(_cfg(window=0, n=100_000))
-    b = _ws(_cfg(window=0, n=200_000))
+    a = _ws(_cfg(window=0, n=100_000, cross_impl=_lib.CROSS_DIRECT))
+    b = _ws(_cfg(window=0, n=200_000, cross_impl=_lib.CROSS_DIRECT))
     assert a[0] == _lib.OK and b[0] == _lib.OK
     k = _cfg().k
     assert b[1] - a[1] >= 4 * k * 100_000
-    c = _ws(_cfg(window=0, n=100_000, precision=_lib.FP64))
+    c = _ws(_cfg(window=0, n=100_000, precision=_lib.FP64, cross_impl=_lib.CROSS_DIRECT))
     assert c[1] - a[1] >= 4 * k * 100_000
+    # the Gaussian FP32 table update on MFMA also holds the k x n sums of the step
+    e = _ws(_cfg(window=0, n=100_000, cross_impl=_lib.CROSS_MFMA))
+    f = _ws(_cfg(window=0, n=100_000, cross_impl=_lib.CROSS_DIRECT))
+    assert e[0] == _lib.OK and e[1] - f[1] >= 4 * k * 100_000
 
 
 def test_create_rejects_missing_workspace():
