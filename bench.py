@@ -230,11 +230,15 @@ def main():
         ops = 2.0 * wl.d * evals
         kact = float(np.mean(active)) if active else float(wl.k)
         tbytes = 2.0 * 4 * wl.n * kact + 4.0 * wl.n * wl.d
-        if gauss and precision == "fp32" and wl.d >= 16:
-            # the Gaussian table update on FP32 MFMA: 2 d flops per evaluation
-            roof = {"bound": "mfma", "achieved": ops / (ms_cross * 1e-3) / 1e12, "peak": PEAK["f32"] / 1e12,
-                    "unit": "TFLOP/s", "frac": ops / (ms_cross * 1e-3) / PEAK["f32"], "traffic": traffic,
-                    "kernel": "k_dp_mfma + k_dp_blend (gauss, f32)", "flops_per_launch": ops}
+        if gauss and (precision == "bf16x3" or (precision == "fp32" and wl.d >= 16)):
+            # the Gaussian table update on MFMA: 2 d flops per evaluation and
+            # product pass (three passes in BF16X3), at the peak of the MFMA dtype
+            npass_t = 3 if precision == "bf16x3" else 1
+            flops_t = npass_t * ops
+            pk = PEAK["bf16"] if precision == "bf16x3" else PEAK["f32"]
+            roof = {"bound": "mfma", "achieved": flops_t / (ms_cross * 1e-3) / 1e12, "peak": pk / 1e12,
+                    "unit": "TFLOP/s", "frac": flops_t / (ms_cross * 1e-3) / pk, "traffic": traffic,
+                    "kernel": f"k_dp_mfma + k_dp_blend (gauss, {precision})", "flops_per_launch": flops_t}
         else:
             roof = {"bound": "alu", "achieved": ops / (ms_cross * 1e-3) / 1e12, "peak": PEAK["f32"] / 2e12,
                     "unit": "TOP/s", "frac": ops / (ms_cross * 1e-3) / (PEAK["f32"] / 2), "traffic": traffic,

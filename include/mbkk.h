@@ -15,10 +15,11 @@
  * <phi(x), C_j> for every row x of X and every center j (a k x n table in the
  * workspace, FP32 or FP64 by the precision) and <C_j, C_j>, and each step
  * updates both by the recursion of Section 4 (O(n b) kernel evaluations and
- * one pass over the table).  In that form tau must be 0, the precision FP32
- * or FP64 and d <= 128; the Gaussian in FP32 runs the update on MFMA (with
- * cross_impl AUTO and d >= 16, or MFMA; the workspace then also holds a
- * k x n FP32 array of the step's sums), else on the VALU; mbkk_get_state,
+ * one pass over the table).  In that form tau must be 0, the precision FP32,
+ * FP64 or BF16X3 (Gaussian) and d <= 128; the Gaussian runs the update on
+ * MFMA in BF16X3, and in FP32 with cross_impl AUTO and d >= 16 or MFMA (the
+ * workspace then also holds a k x n FP32 array of the step's sums), else on
+ * the VALU; BF16X3 has no FP64 re-scoring in this form; mbkk_get_state,
  * mbkk_set_state and the differentiation form return MBKK_E_STATE; an
  * out-of-range index in mbkk_step / mbkk_assign / mbkk_objective is scored
  * as row 0 (and reported under validate).

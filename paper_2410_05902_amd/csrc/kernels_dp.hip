@@ -28,6 +28,8 @@
 //   k_dp_table : the table update over all of X (the O(n b) term) on the
 //                VALU; the Gaussian in FP32 runs it on MFMA instead
 //                (k_dp_mfma, then k_dp_blend).
+#include <type_traits>
+
 #include "dev_common.h"
 #include "kernels.h"
 
@@ -458,18 +460,22 @@ __global__ __launch_bounds__(kDpTableWG) void k_dp_table(int64_t n, int d, int64
 }
 
 // ---------------------------------------------------------------------------
-// Table update of the Gaussian on MFMA (FP32 products, v_mfma_f32_32x32x2f32).
+// Table update of the Gaussian on MFMA.  FP32 form: v_mfma_f32_32x32x2f32;
+// BF16X3 form: v_mfma_f32_32x32x16_bf16 on the compensated split
+// x = hi + lo (hi = bf16(x), lo = bf16(x - hi)), x.y ~ hi.hi + hi.lo + lo.hi,
+// the batch entries' hi / lo from the pool and the points' split in registers.
 // The product form S = x.y - |x|^2 / 2 is a dense contraction over the
 // coordinates: A = 32 grouped batch entries (rows m), B = 32 points of X
 // (columns n), K(x, y) = exp2(c2 S + ay) with c2 = 2 log2(e) / kappa and
 // ay = -log2(e) |y|^2 / kappa.  Lane l = 32 h + n holds point n's column of a
 // 32 x 32 tile: entries m(i) = 8 (i / 4) + 4 h + i % 4, i = 0..15.  Lane half
-// h contracts the coordinates h KS .. h KS + KS - 1 (KS = DP / 2), so each lane
-// reads consecutive coordinates of its rows.
+// h contracts the coordinates h DP/2 .. (h + 1) DP/2 - 1 (k-step s: the next
+// one (FP32) or eight (BF16) of them), so each lane reads consecutive
+// coordinates of its rows.
 //
 // A wave holds two 32-point blocks of X in registers (64 points, 256 per
 // workgroup) and runs over all grouped entries, staged 64 at a time through
-// LDS (double-buffered; rows padded by 4 floats so that the 16-byte reads of
+// LDS (double-buffered; rows padded by 16 bytes so that the 16-byte reads of
 // 16 lanes fall in distinct banks).  After each 32-entry tile the lane sums
 // its kernel values per center segment (masks on m); at the end of a segment
 // the two lane halves are combined (permlane32 swap) and
@@ -481,21 +487,27 @@ constexpr int kDpMfmaStage = 64;  // grouped entries per LDS stage
 
 // (two workgroups per compute unit up to DP = 96; at DP = 128 the two
 // register-resident blocks of X take one wave per SIMD)
-template <int DP>
+template <int DP, bool X3>
 __global__ __launch_bounds__(256, DP == 128 ? 1 : 2) void k_dp_mfma(int64_t n, int d, int64_t ld, const float *__restrict__ X,
                                                     const float *__restrict__ pool32,
+                                                    const uint16_t *__restrict__ poolhi,
+                                                    const uint16_t *__restrict__ poollo,
                                                     const float *__restrict__ poolsq, int k,
                                                     const int32_t *__restrict__ seg,
                                                     const int32_t *__restrict__ sup_row,
                                                     const double *__restrict__ wgt, float c2,
                                                     float *__restrict__ S, int64_t ldT)
 {
-    constexpr int KS = DP / 2;   // MFMA k-steps
-    constexpr int RS = DP + 4;   // LDS row stride (floats)
+    constexpr int HD = DP / 2;              // coordinates per lane half
+    constexpr int KS = X3 ? DP / 16 : HD;   // MFMA k-steps
+    constexpr int ES = X3 ? 2 : 4;          // element bytes in LDS
+    constexpr int RS = DP + 16 / ES;        // LDS row stride (elements): 16 bytes of padding
     constexpr int NE = kDpMfmaStage;
-    constexpr int FPT = NE * DP / 256;  // floats staged per thread and stage
-    static_assert(FPT % 4 == 0 && KS % 4 == 0, "staging in 16-byte pieces");
-    __shared__ __attribute__((aligned(16))) float sY[2][NE * RS];
+    constexpr int UPT = NE * DP * ES / 256 / 16;  // 16-byte pieces per array staged per thread and stage
+    constexpr int NARR = X3 ? 2 : 1;
+    static_assert(UPT >= 1 && (X3 || KS % 4 == 0), "staging in 16-byte pieces");
+    typedef typename std::conditional<X3, uint16_t, float>::type elem_t;
+    __shared__ __attribute__((aligned(16))) elem_t sY[2][NARR][NE * RS];
     __shared__ __attribute__((aligned(16))) float sAy[2][NE];
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -506,41 +518,69 @@ __global__ __launch_bounds__(256, DP == 128 ? 1 : 2) void k_dp_mfma(int64_t n, i
     const float ayc = -0.5f * c2;  // ay = ayc |y|^2
     // ---- the wave's two blocks of X in registers ----------------------------
     const int64_t x0 = (int64_t)blockIdx.x * 256 + w * 64;
-    float bx[2][KS];
+    typedef typename std::conditional<X3, bf16x8, float>::type bfrag_t;
+    bfrag_t bxh[2][KS], bxl[2][X3 ? KS : 1];
     float hx[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int64_t row = x0 + q * 32 + nn;
         const float *xr = X + (row < n ? row : 0) * ld;
         float ss = 0.0f;
+        if constexpr (X3) {
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            const int t = h * KS + s;
-            bx[q][s] = t < d ? xr[t] : 0.0f;
-            ss = fmaf(bx[q][s], bx[q][s], ss);
+            for (int s = 0; s < KS; ++s) {
+                u16x8 vh, vl;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int t = h * HD + 8 * s + u;
+                    const float v = t < d ? xr[t] : 0.0f;
+                    ss = fmaf(v, v, ss);
+                    const uint16_t hb = f32_to_bf16_rne(v);
+                    vh[u] = hb;
+                    vl[u] = f32_to_bf16_rne(v - bf16_to_f32(hb));
+                }
+                bxh[q][s] = __builtin_bit_cast(bf16x8, vh);
+                bxl[q][s] = __builtin_bit_cast(bf16x8, vl);
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const int t = h * HD + s;
+                bxh[q][s] = t < d ? xr[t] : 0.0f;
+                ss = fmaf(bxh[q][s], bxh[q][s], ss);
+            }
         }
         ss += __shfl_xor(ss, 32);
         hx[q] = -0.5f * ss;
     }
     // ---- staging of grouped entries [e0, e0 + 64) into buffer bb ------------
-    // thread t stages entry t / 4, floats (t % 4) * FPT .. + FPT of its row
+    // thread t stages entry t / 4, 16-byte pieces (t % 4) * UPT .. + UPT of its
+    // row in every array (FP32 row, or the BF16 hi and lo rows)
     const int se = tid >> 2, sq = tid & 3;
-    f32x4 pre[FPT / 4];
+    f32x4 pre[NARR][UPT];
     float pay = 0.0f;
     auto fetch = [&](int e0) {
         const int e = e0 + se;
         const int row = e < M ? sup_row[e] : -1;
-        const float *src = pool32 + (int64_t)(row < 0 ? 0 : row) * DP + sq * FPT;
+        const int64_t r0 = (int64_t)(row < 0 ? 0 : row) * DP;
 #pragma unroll
-        for (int u = 0; u < FPT / 4; ++u)
-            pre[u] = row < 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : *(const f32x4 *)(src + 4 * u);
+        for (int a = 0; a < NARR; ++a) {
+            const char *src = X3 ? (const char *)((a == 0 ? poolhi : poollo) + r0)
+                                 : (const char *)(pool32 + r0);
+#pragma unroll
+            for (int u = 0; u < UPT; ++u)
+                pre[a][u] = row < 0 ? f32x4{0.f, 0.f, 0.f, 0.f} : *(const f32x4 *)(src + (sq * UPT + u) * 16);
+        }
         pay = row < 0 ? 0.0f : ayc * poolsq[row];
     };
     auto commit = [&](int bb) {
-        float *dst = &sY[bb][se * RS + sq * FPT];
 #pragma unroll
-        for (int u = 0; u < FPT / 4; ++u)
-            *(f32x4 *)(dst + 4 * u) = pre[u];
+        for (int a = 0; a < NARR; ++a) {
+            char *dst = (char *)&sY[bb][a][se * RS];
+#pragma unroll
+            for (int u = 0; u < UPT; ++u)
+                *(f32x4 *)(dst + (sq * UPT + u) * 16) = pre[a][u];
+        }
         if (sq == 0)
             sAy[bb][se] = pay;
     };
@@ -575,18 +615,34 @@ __global__ __launch_bounds__(256, DP == 128 ? 1 : 2) void k_dp_mfma(int64_t n, i
 #pragma unroll
                 for (int i = 0; i < 16; ++i)
                     acc[q][i] = hx[q];
-            const float *arow = &sY[bb][(t32 * 32 + nn) * RS + h * KS];
-            f32x4 av = *(const f32x4 *)arow, an;
+            if constexpr (X3) {
+                const uint16_t *arh = &sY[bb][0][(t32 * 32 + nn) * RS + h * HD];
+                const uint16_t *arl = &sY[bb][1][(t32 * 32 + nn) * RS + h * HD];
 #pragma unroll
-            for (int s4 = 0; s4 < KS; s4 += 4) {
-                if (s4 + 4 < KS)
-                    an = *(const f32x4 *)(arow + s4 + 4);
+                for (int s = 0; s < KS; ++s) {
+                    const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u16x8 *)(arh + 8 * s));
+                    const bf16x8 al = __builtin_bit_cast(bf16x8, *(const u16x8 *)(arl + 8 * s));
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                    for (int q = 0; q < 2; ++q) {
+                        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bxh[q][s], acc[q], 0, 0, 0);
+                        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bxl[q][s], acc[q], 0, 0, 0);
+                        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bxh[q][s], acc[q], 0, 0, 0);
+                    }
+                }
+            } else {
+                const float *arow = &sY[bb][0][(t32 * 32 + nn) * RS + h * HD];
+                f32x4 av = *(const f32x4 *)arow, an;
 #pragma unroll
-                    for (int q = 0; q < 2; ++q)
-                        acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bx[q][s4 + u], acc[q], 0, 0, 0);
-                av = an;
+                for (int s4 = 0; s4 < KS; s4 += 4) {
+                    if (s4 + 4 < KS)
+                        an = *(const f32x4 *)(arow + s4 + 4);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int q = 0; q < 2; ++q)
+                            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bxh[q][s4 + u], acc[q], 0, 0, 0);
+                    av = an;
+                }
             }
             // kernel values of the tile, in place
 #pragma unroll
@@ -605,12 +661,23 @@ __global__ __launch_bounds__(256, DP == 128 ? 1 : 2) void k_dp_mfma(int64_t n, i
                 const int end = seg[j + 1];
                 const int hi = min(end, top);
                 const int mlo = lo - B0, mhi = hi - B0;
+                if (mlo == 0 && mhi == 32) {  // the whole tile in one segment: no masks
+                    float s0 = 0.0f, s1 = 0.0f;
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const int m = 8 * (i >> 2) + 4 * h + (i & 3);
-                    const bool in = m >= mlo && m < mhi;
-                    run[0] += in ? acc[0][i] : 0.0f;
-                    run[1] += in ? acc[1][i] : 0.0f;
+                    for (int i = 0; i < 16; ++i) {
+                        s0 += acc[0][i];
+                        s1 += acc[1][i];
+                    }
+                    run[0] += s0;
+                    run[1] += s1;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const int m = 8 * (i >> 2) + 4 * h + (i & 3);
+                        const bool in = m >= mlo && m < mhi;
+                        run[0] += in ? acc[0][i] : 0.0f;
+                        run[1] += in ? acc[1][i] : 0.0f;
+                    }
                 }
                 if (end <= top) {
                     store(j);
@@ -661,15 +728,22 @@ static void launch_dp_mfma(const Layout &L, const Buffers &B, const int32_t *seg
 {
     const float c2 = (float)(2.0 * 1.4426950408889634 / kappa);
     const dim3 grid((unsigned)((L.n + 255) / 256));
-#define MBKK_DP_MFMA(DPV)                                                                                        \
-    hipLaunchKernelGGL(k_dp_mfma<DPV>, grid, dim3(256), 0, st, L.n, L.d, B.ld, B.X, B.pool32, B.poolsq, L.k, seg, \
-                       sup_row, B.dp_w, c2, B.dp_S, L.ldT)
-    switch (L.dp) {
-    case 32: MBKK_DP_MFMA(32); break;
-    case 64: MBKK_DP_MFMA(64); break;
-    case 96: MBKK_DP_MFMA(96); break;
-    default: MBKK_DP_MFMA(128); break;
+#define MBKK_DP_MFMA(DPV, X3)                                                                                     \
+    hipLaunchKernelGGL((k_dp_mfma<DPV, X3>), grid, dim3(256), 0, st, L.n, L.d, B.ld, B.X, B.pool32, B.poolhi,       \
+                       B.poollo, B.poolsq, L.k, seg, sup_row, B.dp_w, c2, B.dp_S, L.ldT)
+#define MBKK_DP_MFMA_W(X3)                  \
+    switch (L.dp) {                          \
+    case 32: MBKK_DP_MFMA(32, X3); break;    \
+    case 64: MBKK_DP_MFMA(64, X3); break;    \
+    case 96: MBKK_DP_MFMA(96, X3); break;    \
+    default: MBKK_DP_MFMA(128, X3); break;   \
     }
+    if (L.bf16) {
+        MBKK_DP_MFMA_W(true)
+    } else {
+        MBKK_DP_MFMA_W(false)
+    }
+#undef MBKK_DP_MFMA_W
 #undef MBKK_DP_MFMA
     const dim3 gb((unsigned)((L.n + 1023) / 1024), (unsigned)L.k);
     hipLaunchKernelGGL(k_dp_blend, gb, dim3(256), 0, st, L.n, seg, B.alpha, B.dp_S, (float *)B.dp_T, L.ldT, init);

@@ -100,8 +100,10 @@ Layout make_layout(const mbkk_config &c)
     L.tbytes = c.precision == MBKK_FP64 ? 8 : 4;
     // the Gaussian FP32 table update on MFMA (product form), as the FP32 cross
     // term of the truncated form with cross_impl AUTO / MFMA (d >= 16)
-    L.dp_mfma = L.untrunc && c.kernel == MBKK_GAUSS && c.precision == MBKK_FP32 &&
-                (c.cross_impl == MBKK_CROSS_MFMA || (c.cross_impl == MBKK_CROSS_AUTO && c.d >= 16));
+    L.dp_mfma = L.untrunc && c.kernel == MBKK_GAUSS &&
+                (c.precision == MBKK_BF16X3 ||
+                 (c.precision == MBKK_FP32 &&
+                  (c.cross_impl == MBKK_CROSS_MFMA || (c.cross_impl == MBKK_CROSS_AUTO && c.d >= 16))));
     // live support: at most W slots of b_max points and the k initial points
     // (the table form: the grouped batch, or the k initial points)
     const int64_t Mlive = L.untrunc ? std::max<int64_t>(c.k, c.b_max) : (int64_t)c.k + (int64_t)c.window * c.b_max;
@@ -224,8 +226,8 @@ static int check_config(const mbkk_config *c, std::string &why)
             why = "window 0 (untruncated) takes no tau";
             return MBKK_E_INVALID;
         }
-        if (c->precision != MBKK_FP32 && c->precision != MBKK_FP64) {
-            why = "window 0 (untruncated) runs in FP32 or FP64";
+        if (c->precision == MBKK_BF16X1) {
+            why = "window 0 (untruncated) runs in FP32, FP64 or BF16X3";
             return MBKK_E_INVALID;
         }
         if (c->d > dp_max_dim()) {
@@ -594,7 +596,7 @@ static int dp_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels
     if (cf.validate && clear_flags(c))
         return MBKK_E_HIP;
     set_batch_view(c, 0);
-    launch_gather_rows(B.X, L.n, L.d, B.ld, batch, b, L.dp, B.bat32, nullptr, nullptr, B.batsq, B.batsq64, B.batidx,
+    launch_gather_rows(B.X, L.n, L.d, B.ld, batch, b, L.dp, B.bat32, B.bathi, B.batlo, B.batsq, B.batsq64, B.batidx,
                        B.flags, cf.validate, c->stream);
     launch_dp_score(L, B, cf.kernel, cf.kernel_param, c->fp64, B.batidx, b, true, nullptr, 0, nullptr, c->stream);
     launch_sum_mind(B, b, 0, c->stream);

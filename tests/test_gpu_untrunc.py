@@ -18,8 +18,8 @@ from tests._parity import agreement, dist_rel_err
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-9, "fp32": 1e-5}
-MARGIN = {"fp64": 1e-9, "fp32": 1e-4}
+TOL = {"fp64": 1e-9, "fp32": 1e-5, "bf16x3": 1e-2}
+MARGIN = {"fp64": 1e-9, "fp32": 1e-4, "bf16x3": 1e-4}
 KNAME = {O.GAUSS: "gauss", O.LAPLACE: "laplace", O.LINEAR: "linear", O.POLY2: "poly2"}
 LRNAME = {W.LR_BETA: "beta", W.LR_FULL: "full", W.LR_SKLEARN: "sklearn"}
 
@@ -175,7 +175,7 @@ def test_errors_of_the_table_form():
     with pytest.raises(MbkkError):
         Model(Xd, k=3, b_max=64, window=0, tau=10)
     with pytest.raises(MbkkError):
-        Model(Xd, k=3, b_max=64, window=0, precision="bf16x3")
+        Model(Xd, k=3, b_max=64, window=0, precision="bf16x1")
     with pytest.raises(MbkkError):
         Model(Xd, k=3, b_max=64, window=0, precision="fp64", cross_impl="mfma")
     with pytest.raises(MbkkError):
@@ -227,10 +227,11 @@ def test_full_size_sampled_rows():
         np.testing.assert_allclose(model.center_norms(), N, rtol=1e-5, atol=1e-8)
 
 
-def test_full_size_gaussian_mfma_sampled_rows():
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_full_size_gaussian_mfma_sampled_rows(precision):
     """The Gaussian mixture at n = 1,000,000, d = 128, k = 100, b = 4096, window
-    0 (the table update on MFMA): after two steps, the distances of sampled
-    points to every center equal the oracle's."""
+    0 (the table update on MFMA, FP32 or BF16X3): after two steps, the
+    distances of sampled points to every center equal the oracle's."""
     wl = W.c3_gaussian_mixture(seed=0)
     first = np.full(wl.k, -1, np.int64)
     rows = np.arange(wl.n)
@@ -239,7 +240,7 @@ def test_full_size_gaussian_mfma_sampled_rows():
     assert (init >= 0).all()
     orc = O.Oracle(wl.X, wl.k, 0, wl.kernel, wl.kernel_param)
     orc.init_centers(init)
-    model = _model(wl.X, wl.k, wl.b, wl.kernel, wl.kernel_param, "fp32")
+    model = _model(wl.X, wl.k, wl.b, wl.kernel, wl.kernel_param, precision)
     model.init_centers(init)
     rng = np.random.default_rng(56)
     sample = np.concatenate([rng.integers(0, wl.n, 500), [0, wl.n - 1]]).astype(np.int32)
@@ -247,13 +248,27 @@ def test_full_size_gaussian_mfma_sampled_rows():
         B = wl.batch(i)
         ref = orc.step(B, threads=8)
         lab = model.step(B)["labels"].cpu().numpy()
-        ag = agreement(lab, ref["labels"], ref["margin"], MARGIN["fp32"])
+        ag = agreement(lab, ref["labels"], ref["margin"], MARGIN[precision])
         assert ag["on_margin"], ag["mismatches"][:8]
+        assert ag["all"] >= 0.999
         if not (lab == ref["labels"]).all():
             break
         N = orc.norms()
         D = orc.distances(sample, threads=8)["D"]
         a = model.assign(sample, want_D=True)
         err = dist_rel_err(a["D"].cpu().numpy(), D, 1.0 + N[None, :])
-        assert err.max() <= TOL["fp32"], f"after step {i}: {err.max():.3e}"
+        assert err.max() <= TOL[precision], f"after step {i}: {err.max():.3e}"
         np.testing.assert_allclose(model.center_norms(), N, rtol=1e-5, atol=1e-8)
+
+
+@pytest.mark.parametrize("d", [24, 64, 128])
+def test_gauss_bf16x3_table(d):
+    """BF16X3 (compensated split on MFMA) table update: distances within the
+    BF16 tolerance (in practice far inside it) and the labels of every step
+    equal the oracle's wherever the margin exceeds the form's error."""
+    X, comp, init = _gmm(6000, d, 10, 0.3, seed=70 + d)
+    sigma = W.median_pairwise_distance(X, 0)
+    rng = np.random.default_rng(71)
+    batches = [rng.integers(0, 6000, 400).astype(np.int32) for _ in range(6)]
+    same = run_untrunc(X, 10, O.GAUSS, 2 * sigma * sigma, init, batches, "bf16x3")
+    assert same >= 4

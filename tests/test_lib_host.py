@@ -56,8 +56,8 @@ def test_workspace_size_and_validation():
            dict(kernel=_lib.LINEAR, cross_impl=_lib.CROSS_MFMA),
            dict(precision=_lib.BF16X3, cross_impl=_lib.CROSS_DIRECT),
            dict(precision=_lib.FP64, cross_impl=_lib.CROSS_MFMA),
-           # the untruncated table form: no tau, FP32 / FP64 on the VALU, d <= 128
-           dict(window=0, tau=5), dict(window=0, precision=_lib.BF16X3),
+           # the untruncated table form: no tau, FP32 / FP64 / BF16X3, d <= 128
+           dict(window=0, tau=5), dict(window=0, precision=_lib.BF16X1),
            dict(window=0, precision=_lib.FP64, cross_impl=_lib.CROSS_MFMA),
            dict(window=0, kernel=_lib.LAPLACE, cross_impl=_lib.CROSS_MFMA), dict(window=0, d=129)]
     for b in bad:
