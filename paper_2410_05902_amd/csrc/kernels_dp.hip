@@ -468,7 +468,9 @@ __global__ __launch_bounds__(kDpTableWG) void k_dp_table(int64_t n, int d, int64
 // coordinates: A = 32 grouped batch entries (rows m), B = 32 points of X
 // (columns n), K(x, y) = exp2(c2 S + ay) with c2 = 2 log2(e) / kappa and
 // ay = -log2(e) |y|^2 / kappa.  Lane l = 32 h + n holds point n's column of a
-// 32 x 32 tile: entries m(i) = 8 (i / 4) + 4 h + i % 4, i = 0..15.  Lane half
+// 32 x 32 tile: output rows 8 (i / 4) + 4 h + i % 4, i = 0..15, which the
+// staging fills with the tile's entries 16 h + i (so a lane's 16 values are
+// consecutive entries, and a segment is a range of them per lane half).  Lane half
 // h contracts the coordinates h DP/2 .. (h + 1) DP/2 - 1 (k-step s: the next
 // one (FP32) or eight (BF16) of them), so each lane reads consecutive
 // coordinates of its rows.
@@ -477,7 +479,7 @@ __global__ __launch_bounds__(kDpTableWG) void k_dp_table(int64_t n, int d, int64
 // workgroup) and runs over all grouped entries, staged 64 at a time through
 // LDS (double-buffered; rows padded by 16 bytes so that the 16-byte reads of
 // 16 lanes fall in distinct banks).  After each 32-entry tile the lane sums
-// its kernel values per center segment (masks on m); at the end of a segment
+// its kernel values per center segment (masks on i); at the end of a segment
 // the two lane halves are combined (permlane32 swap) and
 //     S[j][x] = (alpha_j / b_j) sum_{y in B^j} K(x, y)
 // is stored; k_dp_blend then forms T <- (1 - alpha) T + S for the touched
@@ -485,10 +487,11 @@ __global__ __launch_bounds__(kDpTableWG) void k_dp_table(int64_t n, int d, int64
 // ---------------------------------------------------------------------------
 constexpr int kDpMfmaStage = 64;  // grouped entries per LDS stage
 
-// (two workgroups per compute unit up to DP = 96; at DP = 128 the two
-// register-resident blocks of X take one wave per SIMD)
+// (two workgroups per compute unit up to DP = 64; from DP = 96 the two
+// register-resident blocks of X and the two accumulator sets take one wave
+// per SIMD)
 template <int DP, bool X3>
-__global__ __launch_bounds__(256, DP == 128 ? 1 : 2) void k_dp_mfma(int64_t n, int d, int64_t ld, const float *__restrict__ X,
+__global__ __launch_bounds__(256, DP >= 96 ? 1 : 2) void k_dp_mfma(int64_t n, int d, int64_t ld, const float *__restrict__ X,
                                                     const float *__restrict__ pool32,
                                                     const uint16_t *__restrict__ poolhi,
                                                     const uint16_t *__restrict__ poollo,
@@ -573,153 +576,237 @@ __global__ __launch_bounds__(256, DP == 128 ? 1 : 2) void k_dp_mfma(int64_t n, i
         }
         pay = row < 0 ? 0.0f : ayc * poolsq[row];
     };
+    // Entry e of a 32-entry tile goes to LDS row 8 ((e % 16) / 4) + 4 (e / 16)
+    // + e % 4: the MFMA output row of element i of lane half h is then entry
+    // 16 h + i, so each lane holds 16 consecutive entries of the tile.
+    const int srow = (se & ~31) + 8 * ((se & 15) >> 2) + 4 * ((se >> 4) & 1) + (se & 3);
     auto commit = [&](int bb) {
 #pragma unroll
         for (int a = 0; a < NARR; ++a) {
-            char *dst = (char *)&sY[bb][a][se * RS];
+            char *dst = (char *)&sY[bb][a][srow * RS];
 #pragma unroll
             for (int u = 0; u < UPT; ++u)
                 *(f32x4 *)(dst + (sq * UPT + u) * 16) = pre[a][u];
         }
         if (sq == 0)
-            sAy[bb][se] = pay;
+            sAy[bb][srow] = pay;
     };
     // ---- segment bookkeeping (wave uniform) ---------------------------------
+    // The current center j, the end of its segment and its weight are held in
+    // registers, loaded when j becomes current (a segment usually spans
+    // tiles), so that the epilogue does not wait on memory.
     int j = wave_segment_of(seg, k, 0);
+    int cur_end = seg[j + 1];
+    float cur_w = (float)wgt[j];
     float run[2] = {0.0f, 0.0f};
-    auto store = [&](int jj) {
+    auto store = [&]() {
         const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(run[0]), __float_as_uint(run[1]), false,
                                                          false);
         const float tot = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
         const int64_t col = x0 + h * 32 + nn;  // lanes < 32: block 0, lanes >= 32: block 1
         if (col < n)
-            S[(int64_t)jj * ldT + col] = (float)wgt[jj] * tot;
+            S[(int64_t)j * ldT + col] = cur_w * tot;
         run[0] = run[1] = 0.0f;
+    };
+    // segment sums of a tile of kernel values (entries [t0, t0 + 32))
+    auto segments = [&](const f32x16 (&kv)[2], int t0) {
+        int lo = t0;
+        const int top = min(t0 + 32, M);
+        while (lo < top) {  // wave uniform
+            const int end = cur_end;
+            const int hi = min(end, top);
+            const int mlo = lo - t0, mhi = hi - t0;
+            if (mlo == 0 && mhi == 32) {  // the whole tile in one segment: no masks
+                float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    s0 += kv[0][i];
+                    s1 += kv[1][i];
+                }
+                run[0] += s0;
+                run[1] += s1;
+            } else {
+                // element i of lane half h is entry 16 h + i: the segment's
+                // elements are [a_h, b_h) with wave-uniform bounds per half
+                const int a0 = min(max(mlo, 0), 16), b0 = min(max(mhi, 0), 16);
+                const int a1 = min(max(mlo - 16, 0), 16), b1 = min(max(mhi - 16, 0), 16);
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const bool in = h == 0 ? (i >= a0 && i < b0) : (i >= a1 && i < b1);
+                    run[0] += in ? kv[0][i] : 0.0f;
+                    run[1] += in ? kv[1][i] : 0.0f;
+                }
+            }
+            if (end <= top) {
+                store();
+                if (end < M) {
+                    int e1;
+                    do {
+                        ++j;
+                        e1 = seg[j + 1];
+                    } while (e1 <= end);
+                    cur_end = e1;
+                    cur_w = (float)wgt[j];
+                }
+            }
+            lo = hi;
+        }
+    };
+    // Software pipeline over tiles: the MFMAs of tile t go into one
+    // accumulator set while the exponentials of tile t - 1 (the other set,
+    // exponent constants in eay) are spread between them (BF16X3; FP32 takes
+    // them after the MFMAs); the segment sums of tile t - 1 follow.  Tiles alternate between the sets by the
+    // parity of t (two tiles per stage).
+    constexpr int NMF = X3 ? 6 * KS : 2 * KS;  // MFMAs per tile
+    f32x16 accA[2], accB[2];
+    float eay[16];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            accB[q][i] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        eay[i] = 0.0f;
+    int prev = -1;  // first entry of the tile whose epilogue is pending
+    // the exponentials due after MFMA mi of a tile, fenced from the scheduler
+    // so that they issue while the matrix core is busy (MFMAs without a share
+    // carry no fence)
+    auto exp_share = [&](f32x16 (&kv)[2], int mi) {
+        const int e0 = mi * 32 / NMF, e1 = (mi + 1) * 32 / NMF;
+        if (e1 > e0) {
+#pragma unroll
+            for (int e = e0; e < e1; ++e)
+                kv[e & 1][e >> 1] = __builtin_amdgcn_exp2f(fmaf(kv[e & 1][e >> 1], c2, eay[e >> 1]));
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    auto tile = [&](f32x16 (&accN)[2], f32x16 (&accP)[2], int bb, int t32) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                accN[q][i] = hx[q];
+        if constexpr (X3) {
+            const uint16_t *arh = &sY[bb][0][(t32 * 32 + nn) * RS + h * HD];
+            const uint16_t *arl = &sY[bb][1][(t32 * 32 + nn) * RS + h * HD];
+            bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u16x8 *)arh);
+            bf16x8 al = __builtin_bit_cast(bf16x8, *(const u16x8 *)arl);
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                bf16x8 ahn = ah, aln = al;
+                if (s + 1 < KS) {
+                    ahn = __builtin_bit_cast(bf16x8, *(const u16x8 *)(arh + 8 * (s + 1)));
+                    aln = __builtin_bit_cast(bf16x8, *(const u16x8 *)(arl + 8 * (s + 1)));
+                }
+                // products hi.hi, hi.lo, lo.hi; the two point blocks alternate, so
+                // consecutive MFMAs never wait on each other's accumulator
+#pragma unroll
+                for (int pr = 0; pr < 3; ++pr)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const bf16x8 aa = pr == 2 ? al : ah;
+                        const bf16x8 bv = pr == 1 ? bxl[q][s] : bxh[q][s];
+                        accN[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aa, bv, accN[q], 0, 0, 0);
+                        exp_share(accP, (s * 3 + pr) * 2 + q);
+                    }
+                ah = ahn;
+                al = aln;
+            }
+        } else {
+            const float *arow = &sY[bb][0][(t32 * 32 + nn) * RS + h * HD];
+            f32x4 av = *(const f32x4 *)arow, an;
+#pragma unroll
+            for (int s4 = 0; s4 < KS; s4 += 4) {
+                if (s4 + 4 < KS)
+                    an = *(const f32x4 *)(arow + s4 + 4);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        accN[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bxh[q][s4 + u], accN[q], 0, 0, 0);
+                    }
+                av = an;
+            }
+        }
+        if constexpr (!X3) {
+            // FP32: a tile's MFMAs take 4x longer than in BF16; its
+            // exponentials run in one piece (fences would only constrain the
+            // scheduling of the fragment reads)
+#pragma unroll
+            for (int mi = 0; mi < NMF; ++mi)
+                exp_share(accP, mi);
+        }
+        if (prev >= 0)
+            segments(accP, prev);
+        // the new tile's exponent constants, for its epilogue during the next tile
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            const f32x4 a4 = *(const f32x4 *)&sAy[bb][t32 * 32 + 8 * g + 4 * h];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                eay[4 * g + r] = a4[r];
+        }
     };
     const int nst = (M + NE - 1) / NE;
     fetch(0);
     commit(0);
     __syncthreads();
+    static_assert(NE == 64, "two tiles per stage: the tile parity selects the accumulator set");
     for (int st = 0; st < nst; ++st) {
         const int bb = st & 1;
         if (st + 1 < nst)
             fetch((st + 1) * NE);
-#pragma unroll
-        for (int t32 = 0; t32 < NE / 32; ++t32) {
-            const int B0 = st * NE + t32 * 32;
-            if (B0 >= M)
-                break;  // wave uniform
-            f32x16 acc[2];
-#pragma unroll
-            for (int q = 0; q < 2; ++q)
-#pragma unroll
-                for (int i = 0; i < 16; ++i)
-                    acc[q][i] = hx[q];
-            if constexpr (X3) {
-                const uint16_t *arh = &sY[bb][0][(t32 * 32 + nn) * RS + h * HD];
-                const uint16_t *arl = &sY[bb][1][(t32 * 32 + nn) * RS + h * HD];
-#pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u16x8 *)(arh + 8 * s));
-                    const bf16x8 al = __builtin_bit_cast(bf16x8, *(const u16x8 *)(arl + 8 * s));
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) {
-                        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bxh[q][s], acc[q], 0, 0, 0);
-                        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bxl[q][s], acc[q], 0, 0, 0);
-                        acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bxh[q][s], acc[q], 0, 0, 0);
-                    }
-                }
-            } else {
-                const float *arow = &sY[bb][0][(t32 * 32 + nn) * RS + h * HD];
-                f32x4 av = *(const f32x4 *)arow, an;
-#pragma unroll
-                for (int s4 = 0; s4 < KS; s4 += 4) {
-                    if (s4 + 4 < KS)
-                        an = *(const f32x4 *)(arow + s4 + 4);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int q = 0; q < 2; ++q)
-                            acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bxh[q][s4 + u], acc[q], 0, 0, 0);
-                    av = an;
-                }
-            }
-            // kernel values of the tile, in place
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const f32x4 a4 = *(const f32x4 *)&sAy[bb][t32 * 32 + 8 * g + 4 * h];
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int q = 0; q < 2; ++q)
-                        acc[q][4 * g + r] = __builtin_amdgcn_exp2f(fmaf(acc[q][4 * g + r], c2, a4[r]));
-            }
-            // segment sums over the tile's entries [B0, B0 + 32)
-            int lo = B0;
-            const int top = min(B0 + 32, M);
-            while (lo < top) {  // wave uniform
-                const int end = seg[j + 1];
-                const int hi = min(end, top);
-                const int mlo = lo - B0, mhi = hi - B0;
-                if (mlo == 0 && mhi == 32) {  // the whole tile in one segment: no masks
-                    float s0 = 0.0f, s1 = 0.0f;
-#pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        s0 += acc[0][i];
-                        s1 += acc[1][i];
-                    }
-                    run[0] += s0;
-                    run[1] += s1;
-                } else {
-#pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        const int m = 8 * (i >> 2) + 4 * h + (i & 3);
-                        const bool in = m >= mlo && m < mhi;
-                        run[0] += in ? acc[0][i] : 0.0f;
-                        run[1] += in ? acc[1][i] : 0.0f;
-                    }
-                }
-                if (end <= top) {
-                    store(j);
-                    if (end < M) {
-                        do {
-                            ++j;
-                        } while (seg[j + 1] <= end);
-                    }
-                }
-                lo = hi;
-            }
+        tile(accA, accB, bb, 0);
+        prev = st * NE;
+        if (st * NE + 32 < M) {  // wave uniform
+            tile(accB, accA, bb, 1);
+            prev = st * NE + 32;
         }
         if (st + 1 < nst)
             commit(bb ^ 1);
         __syncthreads();
     }
+    // epilogue of the last tile
+    if ((prev - (nst - 1) * NE) == 0) {
+#pragma unroll
+        for (int mi = 0; mi < NMF; ++mi)
+            exp_share(accA, mi);
+        segments(accA, prev);
+    } else {
+#pragma unroll
+        for (int mi = 0; mi < NMF; ++mi)
+            exp_share(accB, mi);
+        segments(accB, prev);
+    }
 }
 
 // T[j][x] <- (1 - alpha_j) T[j][x] + S[j][x] for the centers with batch points
-// (init: T <- S).  Grid: (point chunks of 1024) x centers.
-__global__ __launch_bounds__(256) void k_dp_blend(int64_t n, const int32_t *__restrict__ seg,
+// (init: T <- S).  A thread owns 4 consecutive points and runs over the
+// centers, skipping (wave uniform) those the batch did not touch.
+__global__ __launch_bounds__(256) void k_dp_blend(int64_t n, int k, const int32_t *__restrict__ seg,
                                                   const double *__restrict__ alpha, const float *__restrict__ S,
                                                   float *__restrict__ T, int64_t ldT, int init)
 {
-    const int j = blockIdx.y;
-    if (seg[j + 1] == seg[j])
-        return;
-    const float keep = (float)(1.0 - alpha[j]);
     const int64_t x = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
     if (x >= n)
         return;
-    const f32x4 sv = *(const f32x4 *)(S + (int64_t)j * ldT + x);
-    f32x4 *tp = (f32x4 *)(T + (int64_t)j * ldT + x);  // ldT is a multiple of 64: whole vectors
-    if (init) {
-        *tp = sv;
-    } else {
-        const f32x4 tv = *tp;
-        f32x4 r;
+    for (int j = 0; j < k; ++j) {
+        if (seg[j + 1] == seg[j])
+            continue;
+        const f32x4 sv = *(const f32x4 *)(S + (int64_t)j * ldT + x);
+        f32x4 *tp = (f32x4 *)(T + (int64_t)j * ldT + x);  // ldT is a multiple of 64: whole vectors
+        if (init) {
+            *tp = sv;
+        } else {
+            const float keep = (float)(1.0 - alpha[j]);
+            const f32x4 tv = *tp;
+            f32x4 r;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            r[u] = fmaf(keep, tv[u], sv[u]);
-        *tp = r;
+            for (int u = 0; u < 4; ++u)
+                r[u] = fmaf(keep, tv[u], sv[u]);
+            *tp = r;
+        }
     }
 }
 
@@ -745,8 +832,8 @@ static void launch_dp_mfma(const Layout &L, const Buffers &B, const int32_t *seg
     }
 #undef MBKK_DP_MFMA_W
 #undef MBKK_DP_MFMA
-    const dim3 gb((unsigned)((L.n + 1023) / 1024), (unsigned)L.k);
-    hipLaunchKernelGGL(k_dp_blend, gb, dim3(256), 0, st, L.n, seg, B.alpha, B.dp_S, (float *)B.dp_T, L.ldT, init);
+    hipLaunchKernelGGL(k_dp_blend, dim3((unsigned)((L.n + 1023) / 1024)), dim3(256), 0, st, L.n, L.k, seg, B.alpha,
+                       B.dp_S, (float *)B.dp_T, L.ldT, init);
 }
 
 // Rows per lane of the table update: two for FP32 rows of at most 32
