@@ -408,16 +408,24 @@ __global__ __launch_bounds__(kDpTableWG) void k_dp_table(int64_t n, int d, int64
     const int M = seg[k];
     if (M == 0)
         return;
+    // The current center j: the end of its segment, its weight and rate are
+    // loaded when j becomes current (the rows' old table values are read at
+    // the blend: holding them would cost the registers of a wave per SIMD).
     int j = wave_segment_of(seg, k, 0);
-    int cur_end = seg[j + 1];
+    int cur_end;
+    TT wj, keep;
+    auto begin = [&]() {
+        cur_end = seg[j + 1];
+        wj = (TT)wgt[j];
+        keep = (TT)(1.0 - alpha[j]);
+    };
+    begin();
     TT acc[RPL];
 #pragma unroll
     for (int q = 0; q < RPL; ++q)
         acc[q] = 0;
-    auto flush = [&](int jj) {
-        const TT wj = (TT)wgt[jj];
-        const TT keep = (TT)(1.0 - alpha[jj]);
-        TT *__restrict__ Tj = T + (int64_t)jj * ldT;
+    auto flush = [&]() {
+        TT *__restrict__ Tj = T + (int64_t)j * ldT;
 #pragma unroll
         for (int q = 0; q < RPL; ++q) {
             if (row[q] < n) {
@@ -433,11 +441,11 @@ __global__ __launch_bounds__(kDpTableWG) void k_dp_table(int64_t n, int d, int64
         for (int e = 0; e < cnt; ++e) {  // wave uniform
             const int s = c0 + e;
             if (s >= cur_end) {
-                flush(j);
+                flush();
                 do {
                     ++j;
                 } while (seg[j + 1] <= s);
-                cur_end = seg[j + 1];
+                begin();
             }
             const float *__restrict__ y = pool32 + (int64_t)__builtin_amdgcn_readlane(lrow, e) * dp;
             TT sacc[RPL];
@@ -456,7 +464,7 @@ __global__ __launch_bounds__(kDpTableWG) void k_dp_table(int64_t n, int d, int64
                 acc[q] += dp_kfinish<KIND, TT>(sacc[q], cneg, prm);
         }
     }
-    flush(j);
+    flush();
 }
 
 // ---------------------------------------------------------------------------
