@@ -71,3 +71,23 @@ def agreement(lab_gpu, lab_ref, margin_ref, min_margin):
     return dict(all=float((lab_gpu == lab_ref).mean()),
                 on_margin=bool((lab_gpu[sel] == lab_ref[sel]).all()),
                 n_margin=int(sel.sum()), mismatches=np.nonzero(lab_gpu != lab_ref)[0])
+
+
+def oracle_from_gpu_state(orc, st, k, window):
+    """Loads a truncated-form state image (mbkk_get_state) into the oracle as
+    explicit centers: every live term of every center, one entry per point."""
+    coef, off, sidx = st["coef"], st["slot_off"], st["slot_idx"]
+    cen, pts, wts = [], [], []
+    j0 = np.flatnonzero(coef[:, 0] != 0.0)
+    cen.append(j0)
+    pts.append(st["init_idx"][j0])
+    wts.append(coef[j0, 0])
+    for r in range(window):
+        cnt = np.diff(off[r])
+        cj = np.repeat(np.arange(k), cnt)
+        keep = coef[cj, 1 + r] != 0.0
+        cen.append(cj[keep])
+        pts.append(sidx[r, : off[r][-1]][keep])
+        wts.append(coef[cj[keep], 1 + r])
+    orc.set_centers(np.concatenate(cen), np.concatenate(pts), np.concatenate(wts))
+    return int(sum(len(p) for p in pts))
