@@ -26,7 +26,8 @@
 //   k_dp_rowsum: sum over B_i^j of K(y, y') for each grouped row y;
 //   k_dp_norms : the N update and the per-center weights a / b_i^j;
 //   k_dp_table : the table update over all of X (the O(n b) term) on the
-//                VALU; the Gaussian in FP32 runs it on MFMA instead
+//                VALU; the Gaussian in BF16X3, and in FP32 unless the
+//                difference form is asked for, runs it on MFMA instead
 //                (k_dp_mfma, then k_dp_blend).
 #include <type_traits>
 
@@ -878,7 +879,6 @@ static void dispatch_dp_table(const Layout &L, const Buffers &B, const int32_t *
     else
         MBKK_DP_TABLE(128, 1);
 #undef MBKK_DP_TABLE
-    (void)rpl;
 }
 
 template <typename TT>
