@@ -117,6 +117,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c3", choices=["c3", "c2", "c4", "c5"])
     ap.add_argument("--precision", default=None)
+    ap.add_argument("--lr", default="beta", choices=["beta", "sklearn", "full"],
+                    help="learning rate (Section 5 beta rate, or the count rate)")
+    ap.add_argument("--tau", type=int, default=0,
+                    help="count truncation of Section 4.1 within the window (0: the window alone)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--cpu-rows", type=int, default=2048)
@@ -173,9 +177,18 @@ def main():
     def make(prec):
         return Model(X, k=wl.k, b_max=wl.b, window=window,
                      kernel="gauss" if gauss else "laplace", kernel_param=wl.kernel_param,
-                     precision=prec, validate=False)
+                     precision=prec, validate=False, lr=args.lr, tau=args.tau)
 
     active = []  # untruncated form: centers with batch points in each kernel-timed step
+    live = []    # truncated form: support entries with a nonzero weight in each kernel-timed step
+
+    def live_entries(st):
+        """Support entries the cross kernel evaluates (weight != 0), from the state."""
+        coef, off = st["coef"], st["slot_off"]
+        m = int((coef[:, 0] != 0.0).sum())
+        for r in range(coef.shape[1] - 1):
+            m += int((np.diff(off[r]) * (coef[:, 1 + r] != 0.0)).sum())
+        return m
 
     def run(model, timed_steps, warm, kernel_steps=50):
         """Whole-step time over `timed_steps` (no instrumentation), then the
@@ -195,6 +208,7 @@ def main():
                 lab = model.step(batches[(warm + i) % nsteps])["labels"]
                 active.append(int(torch.unique(lab).numel()))
             else:
+                live.append(live_entries(model.get_state()))  # the support of the next step
                 model.step_noout(batches[(warm + i) % nsteps])
         kms, launches = model.get_timing()
         model.set_timing(False)
@@ -212,7 +226,10 @@ def main():
     if untrunc:
         evals = wl.n * wl.b                   # table update: every point of X against the batch
     else:
-        M = wl.window * wl.b                  # steady-state support size (W batches)
+        # support entries with a nonzero weight (at most W batches; fewer where a
+        # learning rate of 1 or the count rule has zeroed a center's older
+        # batches), averaged over the kernel-timed steps
+        M = float(np.mean(live))
         evals = wl.b * M                      # cross-term kernel evaluations per step
     value = evals / (ms_step * 1e-3)
     iters = 1e3 / ms_step
@@ -269,7 +286,8 @@ def main():
            "dtype": "bf16" if precision.startswith("bf16") else "f32", "data": "synthetic",
            "config": {"workload": wl.name + ("_untruncated" if untrunc else ""), "n": wl.n, "d": wl.d,
                       "k": wl.k, "b": wl.b, "window": window, "kernel": "gauss" if gauss else "laplace",
-                      "kernel_param": wl.kernel_param, "precision": precision,
+                      "kernel_param": wl.kernel_param, "precision": precision, "lr": args.lr,
+                      "tau": args.tau, "support_entries": None if untrunc else M,
                       "init": "kernel k-means++ (GPU)", "parallelism": "single GPU"},
            "iters_per_s": iters, ("table_kernel_ms" if untrunc else "cross_kernel_ms"): ms_cross}
 
