@@ -458,7 +458,10 @@ def test_agreement_scores():
     rng = np.random.default_rng(71)
     big_u = rng.integers(0, 10, 3_000_000).astype(np.int32)
     cases = [(lab, comp, 10), (lab, comp % 3, 3), (big_u, (big_u * 7 + rng.integers(0, 3, big_u.size)) % 13, 13),
-             (lab, rng.integers(0, 4000, lab.size), 4000), (lab[:2], comp[:2], 10)]
+             (lab, rng.integers(0, 4000, lab.size), 4000), (lab[:2], comp[:2], 10),
+             # one reference class; a table of k c = 32760 cells (counted in LDS) and of 32770 (global)
+             (lab, np.zeros_like(comp), 1), (lab, rng.integers(0, 3276, lab.size), 3276),
+             (lab, rng.integers(0, 3277, lab.size), 3277)]
     for u, v, c in cases:
         ari, nmi, table = model.agreement(u, v, c)
         n = scores.contingency(u, v, 10, c)

@@ -272,3 +272,27 @@ def test_gauss_bf16x3_table(d):
     batches = [rng.integers(0, 6000, 400).astype(np.int32) for _ in range(6)]
     same = run_untrunc(X, 10, O.GAUSS, 2 * sigma * sigma, init, batches, "bf16x3")
     assert same >= 4
+
+
+@pytest.mark.parametrize("precision,impl", [("fp32", "auto"), ("fp32", "mfma"), ("fp64", "auto"), ("bf16x3", "auto")])
+def test_tiny_data_and_single_point_batches(precision, impl):
+    """n = 7 points (one partial row tile, table rows padded to 64), k = 2,
+    batches of one point and of repeated points."""
+    rng = np.random.default_rng(90)
+    X = rng.standard_normal((7, 5)).astype(np.float32)
+    init = np.array([0, 3], np.int32)
+    orc = O.Oracle(X, 2, 0, O.GAUSS, 3.0)
+    orc.init_centers(init)
+    model = _model(X, 2, 4, O.GAUSS, 3.0, precision, impl=impl)
+    model.init_centers(init)
+    for B in ([6], [1, 1, 1], [2, 5, 6, 0], [4]):
+        B = np.array(B, np.int32)
+        ref = orc.step(B)
+        lab = model.step(B)["labels"].cpu().numpy()
+        ag = agreement(lab, ref["labels"], ref["margin"], MARGIN[precision])
+        assert ag["on_margin"]
+    allidx = np.arange(7, dtype=np.int32)
+    ref = orc.distances(allidx)
+    D = model.assign(allidx, want_D=True)["D"].cpu().numpy()
+    err = dist_rel_err(D, ref["D"], 1.0 + ref["N"][None, :])
+    assert err.max() <= TOL[precision]
