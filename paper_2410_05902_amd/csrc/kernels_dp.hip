@@ -496,11 +496,11 @@ __global__ __launch_bounds__(kDpTableWG) void k_dp_table(int64_t n, int d, int64
 // ---------------------------------------------------------------------------
 constexpr int kDpMfmaStage = 64;  // grouped entries per LDS stage
 
-// (two workgroups per compute unit up to DP = 64; from DP = 96 the two
-// register-resident blocks of X and the two accumulator sets take one wave
-// per SIMD)
-template <int DP, bool X3>
-__global__ __launch_bounds__(256, DP >= 96 ? 1 : 2) void k_dp_mfma(int64_t n, int d, int64_t ld, const float *__restrict__ X,
+// NBX blocks of 32 points per wave: two (four waves per workgroup) up to
+// DP = 64, one (eight waves) from DP = 96, so that two waves share each SIMD
+// and one wave's epilogue runs beside the other's matrix work.
+template <int DP, bool X3, int NBX>
+__global__ __launch_bounds__(NBX == 2 ? 256 : 512, 2) void k_dp_mfma(int64_t n, int d, int64_t ld, const float *__restrict__ X,
                                                     const float *__restrict__ pool32,
                                                     const uint16_t *__restrict__ poolhi,
                                                     const uint16_t *__restrict__ poollo,
@@ -515,7 +515,9 @@ __global__ __launch_bounds__(256, DP >= 96 ? 1 : 2) void k_dp_mfma(int64_t n, in
     constexpr int ES = X3 ? 2 : 4;          // element bytes in LDS
     constexpr int RS = DP + 16 / ES;        // LDS row stride (elements): 16 bytes of padding
     constexpr int NE = kDpMfmaStage;
-    constexpr int UPT = NE * DP * ES / 256 / 16;  // 16-byte pieces per array staged per thread and stage
+    constexpr int NTH = 64 * 8 / NBX;       // threads of a workgroup (256 points)
+    constexpr int TPE = NTH / kDpMfmaStage; // staging threads per entry
+    constexpr int UPT = NE * DP * ES / NTH / 16;  // 16-byte pieces per array staged per thread and stage
     constexpr int NARR = X3 ? 2 : 1;
     static_assert(UPT >= 1 && (X3 || KS % 4 == 0), "staging in 16-byte pieces");
     typedef typename std::conditional<X3, uint16_t, float>::type elem_t;
@@ -528,13 +530,13 @@ __global__ __launch_bounds__(256, DP >= 96 ? 1 : 2) void k_dp_mfma(int64_t n, in
     if (M == 0)
         return;
     const float ayc = -0.5f * c2;  // ay = ayc |y|^2
-    // ---- the wave's two blocks of X in registers ----------------------------
-    const int64_t x0 = (int64_t)blockIdx.x * 256 + w * 64;
+    // ---- the wave's blocks of X in registers ---------------------------------
+    const int64_t x0 = (int64_t)blockIdx.x * 256 + w * (32 * NBX);
     typedef typename std::conditional<X3, bf16x8, float>::type bfrag_t;
-    bfrag_t bxh[2][KS], bxl[2][X3 ? KS : 1];
-    float hx[2];
+    bfrag_t bxh[NBX][KS], bxl[NBX][X3 ? KS : 1];
+    float hx[NBX];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < NBX; ++q) {
         const int64_t row = x0 + q * 32 + nn;
         const float *xr = X + (row < n ? row : 0) * ld;
         float ss = 0.0f;
@@ -566,9 +568,9 @@ __global__ __launch_bounds__(256, DP >= 96 ? 1 : 2) void k_dp_mfma(int64_t n, in
         hx[q] = -0.5f * ss;
     }
     // ---- staging of grouped entries [e0, e0 + 64) into buffer bb ------------
-    // thread t stages entry t / 4, 16-byte pieces (t % 4) * UPT .. + UPT of its
+    // thread t stages entry t / TPE, 16-byte pieces (t % TPE) * UPT .. + UPT of its
     // row in every array (FP32 row, or the BF16 hi and lo rows)
-    const int se = tid >> 2, sq = tid & 3;
+    const int se = tid / TPE, sq = tid % TPE;
     f32x4 pre[NARR][UPT];
     float pay = 0.0f;
     auto fetch = [&](int e0) {
@@ -607,18 +609,30 @@ __global__ __launch_bounds__(256, DP >= 96 ? 1 : 2) void k_dp_mfma(int64_t n, in
     int j = wave_segment_of(seg, k, 0);
     int cur_end = seg[j + 1];
     float cur_w = (float)wgt[j];
-    float run[2] = {0.0f, 0.0f};
+    float run[NBX];
+#pragma unroll
+    for (int q = 0; q < NBX; ++q)
+        run[q] = 0.0f;
     auto store = [&]() {
-        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(run[0]), __float_as_uint(run[1]), false,
-                                                         false);
-        const float tot = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
-        const int64_t col = x0 + h * 32 + nn;  // lanes < 32: block 0, lanes >= 32: block 1
-        if (col < n)
-            S[(int64_t)j * ldT + col] = cur_w * tot;
-        run[0] = run[1] = 0.0f;
+        if constexpr (NBX == 2) {
+            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(run[0]), __float_as_uint(run[1]),
+                                                             false, false);
+            const float tot = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
+            const int64_t col = x0 + h * 32 + nn;  // lanes < 32: block 0, lanes >= 32: block 1
+            if (col < n)
+                S[(int64_t)j * ldT + col] = cur_w * tot;
+        } else {
+            const float tot = run[0] + __shfl_xor(run[0], 32);
+            const int64_t col = x0 + nn;
+            if (h == 0 && col < n)
+                S[(int64_t)j * ldT + col] = cur_w * tot;
+        }
+#pragma unroll
+        for (int q = 0; q < NBX; ++q)
+            run[q] = 0.0f;
     };
     // segment sums of a tile of kernel values (entries [t0, t0 + 32))
-    auto segments = [&](const f32x16 (&kv)[2], int t0) {
+    auto segments = [&](const f32x16 (&kv)[NBX], int t0) {
         int lo = t0;
         const int top = min(t0 + 32, M);
         while (lo < top) {  // wave uniform
@@ -626,14 +640,14 @@ __global__ __launch_bounds__(256, DP >= 96 ? 1 : 2) void k_dp_mfma(int64_t n, in
             const int hi = min(end, top);
             const int mlo = lo - t0, mhi = hi - t0;
             if (mlo == 0 && mhi == 32) {  // the whole tile in one segment: no masks
-                float s0 = 0.0f, s1 = 0.0f;
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    s0 += kv[0][i];
-                    s1 += kv[1][i];
+                for (int q = 0; q < NBX; ++q) {
+                    float sq_ = 0.0f;
+#pragma unroll
+                    for (int i = 0; i < 16; ++i)
+                        sq_ += kv[q][i];
+                    run[q] += sq_;
                 }
-                run[0] += s0;
-                run[1] += s1;
             } else {
                 // element i of lane half h is entry 16 h + i: the segment's
                 // elements are [a_h, b_h) with wave-uniform bounds per half
@@ -642,8 +656,9 @@ __global__ __launch_bounds__(256, DP >= 96 ? 1 : 2) void k_dp_mfma(int64_t n, in
 #pragma unroll
                 for (int i = 0; i < 16; ++i) {
                     const bool in = h == 0 ? (i >= a0 && i < b0) : (i >= a1 && i < b1);
-                    run[0] += in ? kv[0][i] : 0.0f;
-                    run[1] += in ? kv[1][i] : 0.0f;
+#pragma unroll
+                    for (int q = 0; q < NBX; ++q)
+                        run[q] += in ? kv[q][i] : 0.0f;
                 }
             }
             if (end <= top) {
@@ -666,11 +681,12 @@ __global__ __launch_bounds__(256, DP >= 96 ? 1 : 2) void k_dp_mfma(int64_t n, in
     // exponent constants in eay) are spread between them (BF16X3; FP32 takes
     // them after the MFMAs); the segment sums of tile t - 1 follow.  Tiles alternate between the sets by the
     // parity of t (two tiles per stage).
-    constexpr int NMF = X3 ? 6 * KS : 2 * KS;  // MFMAs per tile
-    f32x16 accA[2], accB[2];
+    constexpr int NMF = (X3 ? 3 : 1) * NBX * KS;  // MFMAs per tile
+    constexpr int NEL = 16 * NBX;                 // kernel values per lane and tile
+    f32x16 accA[NBX], accB[NBX];
     float eay[16];
 #pragma unroll
-    for (int q = 0; q < 2; ++q)
+    for (int q = 0; q < NBX; ++q)
 #pragma unroll
         for (int i = 0; i < 16; ++i)
             accB[q][i] = 0.0f;
@@ -681,18 +697,18 @@ __global__ __launch_bounds__(256, DP >= 96 ? 1 : 2) void k_dp_mfma(int64_t n, in
     // the exponentials due after MFMA mi of a tile, fenced from the scheduler
     // so that they issue while the matrix core is busy (MFMAs without a share
     // carry no fence)
-    auto exp_share = [&](f32x16 (&kv)[2], int mi) {
-        const int e0 = mi * 32 / NMF, e1 = (mi + 1) * 32 / NMF;
+    auto exp_share = [&](f32x16 (&kv)[NBX], int mi) {
+        const int e0 = mi * NEL / NMF, e1 = (mi + 1) * NEL / NMF;
         if (e1 > e0) {
 #pragma unroll
             for (int e = e0; e < e1; ++e)
-                kv[e & 1][e >> 1] = __builtin_amdgcn_exp2f(fmaf(kv[e & 1][e >> 1], c2, eay[e >> 1]));
+                kv[e % NBX][e / NBX] = __builtin_amdgcn_exp2f(fmaf(kv[e % NBX][e / NBX], c2, eay[e / NBX]));
             __builtin_amdgcn_sched_barrier(0);
         }
     };
-    auto tile = [&](f32x16 (&accN)[2], f32x16 (&accP)[2], int bb, int t32) {
+    auto tile = [&](f32x16 (&accN)[NBX], f32x16 (&accP)[NBX], int bb, int t32) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < NBX; ++q)
 #pragma unroll
             for (int i = 0; i < 16; ++i)
                 accN[q][i] = hx[q];
@@ -713,11 +729,11 @@ __global__ __launch_bounds__(256, DP >= 96 ? 1 : 2) void k_dp_mfma(int64_t n, in
 #pragma unroll
                 for (int pr = 0; pr < 3; ++pr)
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) {
+                    for (int q = 0; q < NBX; ++q) {
                         const bf16x8 aa = pr == 2 ? al : ah;
                         const bf16x8 bv = pr == 1 ? bxl[q][s] : bxh[q][s];
                         accN[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aa, bv, accN[q], 0, 0, 0);
-                        exp_share(accP, (s * 3 + pr) * 2 + q);
+                        exp_share(accP, (s * 3 + pr) * NBX + q);
                     }
                 ah = ahn;
                 al = aln;
@@ -732,7 +748,7 @@ __global__ __launch_bounds__(256, DP >= 96 ? 1 : 2) void k_dp_mfma(int64_t n, in
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
-                    for (int q = 0; q < 2; ++q) {
+                    for (int q = 0; q < NBX; ++q) {
                         accN[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bxh[q][s4 + u], accN[q], 0, 0, 0);
                     }
                 av = an;
@@ -824,15 +840,15 @@ static void launch_dp_mfma(const Layout &L, const Buffers &B, const int32_t *seg
 {
     const float c2 = (float)(2.0 * 1.4426950408889634 / kappa);
     const dim3 grid((unsigned)((L.n + 255) / 256));
-#define MBKK_DP_MFMA(DPV, X3)                                                                                     \
-    hipLaunchKernelGGL((k_dp_mfma<DPV, X3>), grid, dim3(256), 0, st, L.n, L.d, B.ld, B.X, B.pool32, B.poolhi,       \
-                       B.poollo, B.poolsq, L.k, seg, sup_row, B.dp_w, c2, B.dp_S, L.ldT)
-#define MBKK_DP_MFMA_W(X3)                  \
-    switch (L.dp) {                          \
-    case 32: MBKK_DP_MFMA(32, X3); break;    \
-    case 64: MBKK_DP_MFMA(64, X3); break;    \
-    case 96: MBKK_DP_MFMA(96, X3); break;    \
-    default: MBKK_DP_MFMA(128, X3); break;   \
+#define MBKK_DP_MFMA(DPV, X3, NBX)                                                                                \
+    hipLaunchKernelGGL((k_dp_mfma<DPV, X3, NBX>), grid, dim3(NBX == 2 ? 256 : 512), 0, st, L.n, L.d, B.ld, B.X,    \
+                       B.pool32, B.poolhi, B.poollo, B.poolsq, L.k, seg, sup_row, B.dp_w, c2, B.dp_S, L.ldT)
+#define MBKK_DP_MFMA_W(X3)                     \
+    switch (L.dp) {                             \
+    case 32: MBKK_DP_MFMA(32, X3, 2); break;    \
+    case 64: MBKK_DP_MFMA(64, X3, 2); break;    \
+    case 96: MBKK_DP_MFMA(96, X3, 1); break;    \
+    default: MBKK_DP_MFMA(128, X3, 1); break;   \
     }
     if (L.bf16) {
         MBKK_DP_MFMA_W(true)
