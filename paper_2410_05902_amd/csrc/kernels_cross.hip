@@ -657,11 +657,11 @@ static int bs_nranges(int nb, int mode, int dp)
 
 struct CrossBsArgs {
     int nb, nbt, nranges;
-    int32_t sup_cap;      // Mcap: sup_row[Mcap] is the zero pool row
+    int32_t sup_cap;      // Mcap: sup_row[Mcap] is the zero pool row, sup_w[Mcap] = sup_ay[Mcap] = 0
+    int32_t pool_bytes;   // bytes of the pool in the staged form (the bound of its buffer resource)
     const int32_t *seg_total;
     const float *pool32;
     const uint16_t *poolhi, *poollo;
-    const float *zero_f;  // a float 0 in device memory
     const int32_t *sup_row;
     const float *sup_w, *sup_ay;
     const int32_t *blk_center;
@@ -678,6 +678,8 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 template <int MODE, int DP>
 __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
 {
+    // buffer resources exist in the device pass only; the host pass keeps the launch stub
+#if defined(__HIP_DEVICE_COMPILE__)
     constexpr bool F32 = MODE == 0;
     constexpr bool X3 = MODE == 1;
     constexpr int NBK = bs_nbk(MODE, DP);          // 32-row N-blocks (batch rows) per wave
@@ -765,6 +767,24 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
     int pidx[NT];
     // sup_row[Mcap] holds the zero pool row; entries past the support map there
     const int sentinel = A.sup_cap;
+    // The staging goes through buffer resources (MUBUF loads into LDS) rather
+    // than global_load_lds: the compiler treats a FLAT load that writes LDS as
+    // touching both counters, and while one is outstanding every wait on LDS
+    // reads becomes a full drain, which serialises the fragment reads that are
+    // meant to run two k-steps ahead of their MFMAs.  A MUBUF load into LDS is
+    // tracked on the vector-memory counter alone.
+    constexpr int kRsrcWord3 = 0x00020000;  // raw buffer, 32-bit data format (gfx9)
+    const int sup_bytes = 4 * (A.sup_cap + 1);
+    const __amdgpu_buffer_rsrc_t rs_row =
+        __builtin_amdgcn_make_buffer_rsrc((void *)A.sup_row, (short)0, sup_bytes, kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t rs_ay =
+        __builtin_amdgcn_make_buffer_rsrc((void *)A.sup_ay, (short)0, sup_bytes, kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t rs_w =
+        __builtin_amdgcn_make_buffer_rsrc((void *)A.sup_w, (short)0, sup_bytes, kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t rs_p0 = __builtin_amdgcn_make_buffer_rsrc(
+        F32 ? (void *)A.pool32 : (void *)A.poolhi, (short)0, A.pool_bytes, kRsrcWord3);
+    const __amdgpu_buffer_rsrc_t rs_p1 = __builtin_amdgcn_make_buffer_rsrc(
+        F32 ? (void *)A.pool32 : (void *)A.poollo, (short)0, A.pool_bytes, kRsrcWord3);
     auto load_idx = [&](int s) {  // pool rows of this lane's DMA slots in stage s (from global)
         const int r0 = (blk0 + SB * s) * 32;
 #pragma unroll
@@ -777,8 +797,8 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
     auto issue_idx = [&](int s, auto bi) {
         if (wu < 2) {
             const int srow = (blk0 + SB * s) * 32 + wu * 64 + lane;
-            const int32_t *src = A.sup_row + (srow < M ? srow : sentinel);
-            __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)(bufIdx(bi) + wu * 64), 4, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs_row, (lds_void_t *)(bufIdx(bi) + wu * 64), 4,
+                                                     4 * (srow < M ? srow : sentinel), 0, 0, 0);
         }
     };
     auto read_idx = [&](auto bi) {  // this lane's DMA slot rows from index buffer bi
@@ -796,23 +816,20 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
     auto issue_slot = [&](auto bc, int q) {  // DMA slot q of every staged array (pidx[q] holds its row)
 #pragma unroll
         for (int arr = 0; arr < NARR; ++arr) {
-            const char *gsrc = F32 ? (const char *)A.pool32
-                                   : (arr == 0 ? (const char *)A.poolhi : (const char *)A.poollo);
             const int i = wu + 4 * q;
-            if (4 * q + 3 < NINS || i < NINS) {
-                const char *src = gsrc + ((int64_t)pidx[q] * (DP * ES) + dma_coff(q));
-                __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)(bufA(bc) + arr * ABYTES + i * 1024),
-                                                 16, 0, 0);
-            }
+            if (4 * q + 3 < NINS || i < NINS)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(arr == 0 ? rs_p0 : rs_p1,
+                                                         (lds_void_t *)(bufA(bc) + arr * ABYTES + i * 1024), 16,
+                                                         pidx[q] * (DP * ES) + dma_coff(q), 0, 0, 0);
         }
     };
     auto issue_ayw = [&](int s, auto bc) {
         // exponent constants (waves 0, 1) and weights (waves 2, 3), 64 rows each
         const int half = wu & 1;
         const int srow = (blk0 + SB * s) * 32 + half * 64 + lane;
-        const float *src = srow < M ? (wu < 2 ? A.sup_ay : A.sup_w) + srow : A.zero_f;
         float *dst = (wu < 2 ? bufAy(bc) : bufW(bc)) + half * 64;
-        __builtin_amdgcn_global_load_lds((const void *)src, (lds_void_t *)dst, 4, 0, 0);
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(wu < 2 ? rs_ay : rs_w, (lds_void_t *)dst, 4,
+                                                 4 * (srow < M ? srow : sentinel), 0, 0, 0);
     };
     auto issue = [&](int s, auto bc) {  // DMA of stage s into buffer bc
 #pragma unroll
@@ -1119,6 +1136,7 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
     }
     epi_range(acc1, 0, NEL);
     flush();
+#endif
 }
 
 void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision, double kappa, hipStream_t st)
@@ -1135,7 +1153,7 @@ void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision,
         A.pool32 = B.pool32;
         A.poolhi = B.poolhi;
         A.poollo = B.poollo;
-        A.zero_f = B.poolsq + L.PR;
+        A.pool_bytes = (int32_t)((L.PR + 1) * L.dp * (precision == MBKK_FP32 ? 4 : 2));
         A.sup_row = B.sup_row;
         A.sup_w = B.sup_w;
         A.sup_ay = B.sup_ay;

@@ -154,8 +154,8 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.seg_off = (int32_t *)take(4 * (size_t)(L.k + 1));
     B.seg_next = (int32_t *)take(4 * (size_t)(L.k + 1));
     B.sup_row = (int32_t *)take(4 * (L.Mcap + 1));  // [Mcap] = zero pool row (sentinel)
-    B.sup_w = (float *)take(4 * L.Mcap);
-    B.sup_ay = (float *)take(4 * L.Mcap);
+    B.sup_w = (float *)take(4 * (L.Mcap + 1));   // [Mcap] = 0 (sentinel)
+    B.sup_ay = (float *)take(4 * (L.Mcap + 1));  // [Mcap] = 0 (sentinel)
     B.sup_w64 = (double *)take(8 * L.Mcap);
     B.blk_center = (int32_t *)take(4 * L.nblk);
     size_t part_direct = (size_t)(L.k + kDirectWGs) * L.bmax * 8;  // runs of the direct kernel, FP64 worst case
@@ -473,6 +473,10 @@ int mbkk_create(const mbkk_config *cfg, void *workspace, size_t bytes, void *str
         e = hipMemsetAsync(c->B.poolsq64 + zr, 0, sizeof(double), c->stream);
     if (e == hipSuccess)
         e = hipMemsetD32Async((hipDeviceptr_t)(c->B.sup_row + L.Mcap), (int)L.PR, 1, c->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->B.sup_w + L.Mcap, 0, sizeof(float), c->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(c->B.sup_ay + L.Mcap, 0, sizeof(float), c->stream);
     if (e == hipSuccess)
         e = hipMemsetAsync(c->B.flags, 0, 16, c->stream);
     if (e == hipSuccess)

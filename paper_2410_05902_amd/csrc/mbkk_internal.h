@@ -100,8 +100,8 @@ struct Buffers {
     int32_t *seg_off = nullptr;  // [k+1]
     int32_t *seg_next = nullptr; // [k+1] segment offsets of the next iteration's support (from the update)
     int32_t *sup_row = nullptr;  // [Mcap + 1] pool row; [Mcap] = the zero row
-    float *sup_w = nullptr;      // [Mcap]
-    float *sup_ay = nullptr;     // [Mcap] MFMA path: -log2(e) ||y||^2 / kappa of the entry's row
+    float *sup_w = nullptr;      // [Mcap + 1]; [Mcap] = 0
+    float *sup_ay = nullptr;     // [Mcap + 1], [Mcap] = 0; MFMA path: -log2(e) ||y||^2 / kappa of the entry's row
     double *sup_w64 = nullptr;   // [Mcap]
     int32_t *blk_center = nullptr;  // [Mcap/32]
     // cross-term output and assignment
