@@ -1153,6 +1153,8 @@ void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision,
         A.pool32 = B.pool32;
         A.poolhi = B.poolhi;
         A.poollo = B.poollo;
+        // at most (65536 + 31 * 8192 + 1) rows of 128 FP32 coordinates (164 MB): the
+        // configuration limits on k, the window and b_max keep it within 31 bits
         A.pool_bytes = (int32_t)((L.PR + 1) * L.dp * (precision == MBKK_FP32 ? 4 : 2));
         A.sup_row = B.sup_row;
         A.sup_w = B.sup_w;
