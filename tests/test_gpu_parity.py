@@ -292,13 +292,17 @@ def test_bandwidth_extremes(param):
     lockstep(X, 3, 2, O.GAUSS, param, init, batches, "fp64")
 
 
-def test_ragged_batch_sizes_mfma():
-    """Batch sizes that are not multiples of the 128-row tile, down to b = 1."""
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_ragged_batch_sizes_mfma(precision):
+    """Batch sizes that are not multiples of the 128-row tile, down to b = 1
+    (waves whose rows all lie past the batch still stage their share of the
+    support)."""
     X = _small_gmm(5000, 64, 10, 0.4, seed=17)
     rng = np.random.default_rng(18)
     init = rng.choice(5000, 10, replace=False).astype(np.int32)
     batches = [rng.integers(0, 5000, b).astype(np.int32) for b in (1, 129, 255, 77, 300)]
-    lockstep(X, 10, 2, O.GAUSS, 40.0, init, batches, "fp32", "mfma", b_max=300)
+    lockstep(X, 10, 2, O.GAUSS, 40.0, init, batches, precision, "mfma", b_max=300,
+             min_agree=0.999 if precision == "bf16x3" else 1.0)
 
 
 # ---------------------------------------------------------------------------
