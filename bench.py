@@ -16,6 +16,12 @@ With --untruncated the same workload runs untruncated (Algorithm 1, window
 batch from the table and updates the n x k table with n * b kernel
 evaluations (FP32, VALU).
 
+With --differentiation (default workload for it: the 64-D mixture) the
+differentiation form is timed instead: the objective of a batch of
+coordinates at a bandwidth (forward, with its assignment) and its gradient
+with respect to the coordinates and the bandwidth (backward, tiles
+recomputed), against the centers after a full window of steps.
+
 Prints ONE JSON line (rank 0).  Inputs are resident in HBM before timing.
 """
 from __future__ import annotations
@@ -110,6 +116,61 @@ def measured_traffic(wl: str, src: str = CROSS_SRC):
     return t["traffic_bytes_per_launch"] if sha == source_sha(src) else None
 
 
+def differentiation(args, wl, X, batches, u, make, window, nsteps):
+    """Times the differentiation form: forward (objective and assignment of a
+    batch of coordinates at bandwidth sigma) and backward (gradient with
+    respect to the coordinates and sigma at the forward's labels), against the
+    centers after window + 2 steps of the FP32 form.  Both calls return host
+    scalars, so each is timed whole (launches and the read-back included)."""
+    import torch
+    model = make("fp32")
+    model.init_kmeanspp(u)
+    for i in range(window + 2):
+        model.step_noout(batches[i % nsteps])
+    torch.cuda.synchronize()
+    live = live_support(model.get_state())
+    xs = [X[batches[(window + 2 + i) % nsteps].long()].contiguous() for i in range(4)]
+    sigma = float(wl.sigma)
+    for i in range(args.warmup):
+        _, lab = model.objective_fwd(xs[i % 4], sigma)
+        model.objective_bwd(xs[i % 4], sigma, lab)
+    torch.cuda.synchronize()
+    tf = tb = 0.0
+    for i in range(args.steps):
+        x = xs[i % 4]
+        t0 = time.perf_counter()
+        _, lab = model.objective_fwd(x, sigma)
+        t1 = time.perf_counter()
+        dX, ds = model.objective_bwd(x, sigma, lab)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tf += t1 - t0
+        tb += t2 - t1
+    ms_f, ms_b = tf * 1e3 / args.steps, tb * 1e3 / args.steps
+    b = xs[0].shape[0]
+    log(f"[bench] differentiation form: forward {ms_f:.4f} ms, backward {ms_b:.4f} ms, "
+        f"b={b}, support {live} entries")
+    print(json.dumps({
+        "metric": "differentiation form: objective and gradient (coordinates, bandwidth) per batch",
+        "value": b / ((ms_f + ms_b) * 1e-3), "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_f + ms_b, "ms_forward": ms_f, "ms_backward": ms_b,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name + "_differentiation", "n": wl.n, "d": wl.d, "k": wl.k, "b": b,
+                   "window": window, "kernel": "gauss", "sigma": sigma, "support_entries": live,
+                   "parallelism": "single GPU"},
+        "roofline": None, "cpu_baseline": None}), flush=True)
+
+
+def live_support(st):
+    """Support entries with a nonzero weight, from a state image."""
+    coef, off = st["coef"], st["slot_off"]
+    m = int((coef[:, 0] != 0.0).sum())
+    for r in range(coef.shape[1] - 1):
+        m += int((np.diff(off[r]) * (coef[:, 1 + r] != 0.0)).sum())
+    return m
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,6 +191,8 @@ def main():
                     help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE runs of the workload and of the copy "
                          "calibration into profiles/traffic_<workload>.json (no GPU needed)")
     ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--differentiation", action="store_true",
+                    help="time the differentiation form (objective and gradient) on the 64-D mixture")
     ap.add_argument("--untruncated", action="store_true",
                     help="run the workload untruncated (window 0) on the table of cross terms")
     args = ap.parse_args()
@@ -160,6 +223,8 @@ def main():
         print(json.dumps({"copy_calibration_mib": args.copy_calibration, "launches": 5}), flush=True)
         return
 
+    if args.differentiation and args.workload == "c3":
+        args.workload = "c4"  # the workload the differentiation form is specified on
     t0 = time.time()
     wl = W.make(args.workload)
     log(f"[bench] workload {wl.name}: n={wl.n} d={wl.d} k={wl.k} b={wl.b} W={wl.window} "
@@ -178,6 +243,12 @@ def main():
         return Model(X, k=wl.k, b_max=wl.b, window=window,
                      kernel="gauss" if gauss else "laplace", kernel_param=wl.kernel_param,
                      precision=prec, validate=False, lr=args.lr, tau=args.tau)
+
+    if args.differentiation:
+        if not gauss or untrunc:
+            raise SystemExit("the differentiation form takes a Gaussian workload in the windowed form")
+        differentiation(args, wl, X, batches, u, make, window, nsteps)
+        return
 
     active = []  # untruncated form: centers with batch points in each kernel-timed step
     live = []    # truncated form: support entries with a nonzero weight in each kernel-timed step

@@ -13,9 +13,16 @@
 namespace mbkk {
 
 // ---------------------------------------------------------------------------
-// N_j(s) and dN_j/ds: one workgroup per center, all ordered pairs of its
-// support entries, fixed pair-to-thread assignment and a fixed-order tree
-// reduction (deterministic).
+// N_j(s) and dN_j/ds over all ordered pairs of center j's support entries,
+// split over kSnSplit workgroups per center (workgroup g takes the a tiles
+// g, g + kSnSplit, ...), so that one large center is spread over the chip.
+// Each writes its partial sums; k_selfnorm_fold adds them in workgroup order.
+// The pairs are taken in tiles of 16 rows a by 64 rows e
+// whose coordinates are staged in LDS (128 coordinates per pass), so each
+// coordinate is read from global memory once per tile instead of once per
+// pair; thread (ta, te) of a tile owns the pairs (ta, te + 16 q), q < 4.
+// Every thread sums its pairs in a fixed order, and the tree reduction is
+// fixed as well (deterministic).
 // ---------------------------------------------------------------------------
 struct SelfNormArgs {
     int k, d, dp;
@@ -24,31 +31,60 @@ struct SelfNormArgs {
     const float *pool32;
     double inv_kappa;  // 1 / (2 s^2)
     double inv_s3;     // 1 / s^3
+    double *part;      // [k][kSnSplit][2]
     double *N, *dN;
 };
 
+constexpr int kSnTA = 16, kSnTE = 64, kSnDim = 128;
+
 __global__ __launch_bounds__(256) void k_selfnorm_sigma(const SelfNormArgs A)
 {
+    __shared__ float sa[kSnTA][kSnDim + 1], se[kSnTE][kSnDim + 1];
     __shared__ double rn[256], rd[256];
-    const int j = blockIdx.x, tid = threadIdx.x;
+    const int j = blockIdx.x, g = blockIdx.y, tid = threadIdx.x;
+    const int ta = tid / kSnTA, te = tid % kSnTA;  // a row of the tile, first e row (then +16 q)
     const int s0 = A.seg_off[j], L = A.seg_off[j + 1] - s0;
     double sn = 0.0, sd = 0.0;
-    const int64_t npair = (int64_t)L * L;
-    for (int64_t p = tid; p < npair; p += 256) {
-        const int a = (int)(p / L), e = (int)(p % L);
-        const double wa = A.sup_w64[s0 + a], we = A.sup_w64[s0 + e];
-        if (wa == 0.0 || we == 0.0)
-            continue;
-        const float *ya = A.pool32 + (int64_t)A.sup_row[s0 + a] * A.dp;
-        const float *ye = A.pool32 + (int64_t)A.sup_row[s0 + e] * A.dp;
-        double d2 = 0.0;
-        for (int t = 0; t < A.d; ++t) {
-            const double v = (double)ya[t] - (double)ye[t];
-            d2 = fma(v, v, d2);
+    for (int a0 = g * kSnTA; a0 < L; a0 += kSnSplit * kSnTA) {
+        for (int e0 = 0; e0 < L; e0 += kSnTE) {
+            double d2[4] = {0.0, 0.0, 0.0, 0.0};
+            for (int t0 = 0; t0 < A.d; t0 += kSnDim) {
+                const int nt = min(kSnDim, A.d - t0);
+                __syncthreads();  // the previous pass is done with the tiles
+                for (int i = tid; i < (kSnTA + kSnTE) * kSnDim; i += 256) {
+                    const int r = i / kSnDim, t = i % kSnDim;
+                    const int row = r < kSnTA ? a0 + r : e0 + (r - kSnTA);
+                    float v = 0.0f;
+                    if (row < L && t < nt)
+                        v = A.pool32[(int64_t)A.sup_row[s0 + row] * A.dp + t0 + t];
+                    if (r < kSnTA)
+                        sa[r][t] = v;
+                    else
+                        se[r - kSnTA][t] = v;
+                }
+                __syncthreads();
+                for (int t = 0; t < nt; ++t) {
+                    const double x = (double)sa[ta][t];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const double v = x - (double)se[te + 16 * q][t];
+                        d2[q] = fma(v, v, d2[q]);
+                    }
+                }
+            }
+            const int a = a0 + ta;
+            const double wa = a < L ? A.sup_w64[s0 + a] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = e0 + te + 16 * q;
+                const double we = e < L ? A.sup_w64[s0 + e] : 0.0;
+                if (wa != 0.0 && we != 0.0) {
+                    const double kv = exp(-d2[q] * A.inv_kappa);
+                    sn = fma(wa * we, kv, sn);
+                    sd = fma(wa * we * kv, d2[q], sd);
+                }
+            }
         }
-        const double kv = exp(-d2 * A.inv_kappa);
-        sn = fma(wa * we, kv, sn);
-        sd = fma(wa * we * kv, d2, sd);
     }
     rn[tid] = sn;
     rd[tid] = sd;
@@ -61,9 +97,24 @@ __global__ __launch_bounds__(256) void k_selfnorm_sigma(const SelfNormArgs A)
         __syncthreads();
     }
     if (tid == 0) {
-        A.N[j] = rn[0];
-        A.dN[j] = rd[0] * A.inv_s3;
+        A.part[((int64_t)j * kSnSplit + g) * 2] = rn[0];
+        A.part[((int64_t)j * kSnSplit + g) * 2 + 1] = rd[0];
     }
+}
+
+// N_j and dN_j/ds from the kSnSplit partial sums of center j, in order.
+__global__ __launch_bounds__(256) void k_selfnorm_fold(const SelfNormArgs A)
+{
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= A.k)
+        return;
+    double sn = 0.0, sd = 0.0;
+    for (int g = 0; g < kSnSplit; ++g) {
+        sn += A.part[((int64_t)j * kSnSplit + g) * 2];
+        sd += A.part[((int64_t)j * kSnSplit + g) * 2 + 1];
+    }
+    A.N[j] = sn;
+    A.dN[j] = sd * A.inv_s3;
 }
 
 void launch_selfnorm_sigma(const Layout &L, const Buffers &B, double sigma, double *N, double *dN, hipStream_t st)
@@ -78,9 +129,11 @@ void launch_selfnorm_sigma(const Layout &L, const Buffers &B, double sigma, doub
     A.pool32 = B.pool32;
     A.inv_kappa = 1.0 / (2.0 * sigma * sigma);
     A.inv_s3 = 1.0 / (sigma * sigma * sigma);
+    A.part = B.sn_part;
     A.N = N;
     A.dN = dN;
-    hipLaunchKernelGGL(k_selfnorm_sigma, dim3((unsigned)L.k), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_selfnorm_sigma, dim3((unsigned)L.k, kSnSplit), dim3(256), 0, st, A);
+    hipLaunchKernelGGL(k_selfnorm_fold, dim3((unsigned)((L.k + 255) / 256)), dim3(256), 0, st, A);
 }
 
 // ---------------------------------------------------------------------------

@@ -157,6 +157,7 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.sup_w = (float *)take(4 * (L.Mcap + 1));   // [Mcap] = 0 (sentinel)
     B.sup_ay = (float *)take(4 * (L.Mcap + 1));  // [Mcap] = 0 (sentinel)
     B.sup_w64 = (double *)take(8 * L.Mcap);
+    B.sn_part = (double *)take(8 * 2 * (size_t)L.k * kSnSplit);
     B.blk_center = (int32_t *)take(4 * L.nblk);
     size_t part_direct = (size_t)(L.k + kDirectWGs) * L.bmax * 8;  // runs of the direct kernel, FP64 worst case
     size_t part_mfma = (size_t)L.nblk * L.bmax * 4;

@@ -30,6 +30,7 @@ constexpr int kChunk = 64;        // batch rows per grouping chunk (one scoring 
 constexpr int kBsOcc = 1;
 constexpr int kNumCU = 256;
 constexpr int kDirectWGs = 2048;  // workgroups of the direct (VALU) cross kernel: ranges x row tiles (8 waves per SIMD)
+constexpr int kSnSplit = 64;      // workgroups per center of the self norms at a bandwidth (differentiation form)
 constexpr int kGramWaves = 5120;  // waves of the Gram work kernels (equal contiguous task ranges; 5 per SIMD)
 
 // Physical slots of the live batches, oldest batch first.
@@ -103,6 +104,7 @@ struct Buffers {
     float *sup_w = nullptr;      // [Mcap + 1]; [Mcap] = 0
     float *sup_ay = nullptr;     // [Mcap + 1], [Mcap] = 0; MFMA path: -log2(e) ||y||^2 / kappa of the entry's row
     double *sup_w64 = nullptr;   // [Mcap]
+    double *sn_part = nullptr;   // [k][kSnSplit][2] partial sums of the self norms at a bandwidth
     int32_t *blk_center = nullptr;  // [Mcap/32]
     // cross-term output and assignment
     void *part = nullptr;        // P[k][bmax] (direct) or per-run partials [Mcap/32][bmax]
