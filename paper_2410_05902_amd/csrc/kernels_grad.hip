@@ -181,26 +181,38 @@ __global__ __launch_bounds__(256) void k_grad_rows(const GradRowArgs A)
         acc[c] = 0.0;
     }
     double q = 0.0;
+    // U entries at a time: their loads and wave reductions are independent
+    // and overlap; the sums still take the entries in order, one by one
+    constexpr int U = 4;
     const int s1 = A.seg_off[j + 1];
-    for (int s = A.seg_off[j]; s < s1; ++s) {
-        const double w = A.sup_w64[s];
-        if (w == 0.0)
-            continue;
-        const float *y = A.pool32 + (int64_t)A.sup_row[s] * A.dp;
-        double diff[CH], part = 0.0;
+    for (int s = A.seg_off[j]; s < s1; s += U) {
+        double w[U], part[U], diff[U][CH];
 #pragma unroll
-        for (int c = 0; c < CH; ++c) {
-            const int t = lane + 64 * c;
-            diff[c] = t < A.d ? x[c] - (double)y[t] : 0.0;
-            part = fma(diff[c], diff[c], part);
+        for (int u = 0; u < U; ++u) {
+            w[u] = s + u < s1 ? A.sup_w64[s + u] : 0.0;
+            part[u] = 0.0;
+            const float *y = A.pool32 + (int64_t)A.sup_row[s + u < s1 ? s + u : s] * A.dp;
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const int t = lane + 64 * c;
+                diff[u][c] = t < A.d ? x[c] - (double)y[t] : 0.0;
+                part[u] = fma(diff[u][c], diff[u][c], part[u]);
+            }
         }
         for (int o = 32; o > 0; o >>= 1)
-            part += __shfl_xor(part, o);
-        const double wk = w * exp(-part * A.inv_kappa);
 #pragma unroll
-        for (int c = 0; c < CH; ++c)
-            acc[c] = fma(wk, diff[c], acc[c]);
-        q = fma(wk, part, q);
+            for (int u = 0; u < U; ++u)
+                part[u] += __shfl_xor(part[u], o);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (w[u] == 0.0)
+                continue;  // (wave uniform)
+            const double wk = w[u] * exp(-part[u] * A.inv_kappa);
+#pragma unroll
+            for (int c = 0; c < CH; ++c)
+                acc[c] = fma(wk, diff[u][c], acc[c]);
+            q = fma(wk, part[u], q);
+        }
     }
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
