@@ -8,6 +8,7 @@
 //   dN_j/ds = sum_{e, e'} w_e w_e' K_s(y_e, y_e') ||y_e - y_e'||^2 / s^3.
 // Kernel values are recomputed here (nothing of size b x M is stored); the
 // arithmetic is FP64 throughout.
+#include "dev_common.h"
 #include "kernels.h"
 
 namespace mbkk {
@@ -48,19 +49,36 @@ __global__ __launch_bounds__(256) void k_selfnorm_sigma(const SelfNormArgs A)
     for (int a0 = g * kSnTA; a0 < L; a0 += kSnSplit * kSnTA) {
         for (int e0 = 0; e0 < L; e0 += kSnTE) {
             double d2[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int t0 = 0; t0 < A.d; t0 += kSnDim) {
-                const int nt = min(kSnDim, A.d - t0);
-                __syncthreads();  // the previous pass is done with the tiles
-                for (int i = tid; i < (kSnTA + kSnTE) * kSnDim; i += 256) {
-                    const int r = i / kSnDim, t = i % kSnDim;
+            // pool rows are zero from d up to the stride dp, so passes run over dp
+            for (int t0 = 0; t0 < A.dp; t0 += kSnDim) {
+                const int nt = min(kSnDim, A.dp - t0);
+                // this thread's 16-byte chunks of the tiles: all pool-row indices
+                // first, then all coordinate loads, so each pass waits on two
+                // rounds of independent loads
+                constexpr int CPRow = kSnDim / 4, Q = (kSnTA + kSnTE) * CPRow / 256;
+                int ridx[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int i = tid + 256 * q, r = i / CPRow, c4 = i % CPRow;
                     const int row = r < kSnTA ? a0 + r : e0 + (r - kSnTA);
-                    float v = 0.0f;
-                    if (row < L && t < nt)
-                        v = A.pool32[(int64_t)A.sup_row[s0 + row] * A.dp + t0 + t];
-                    if (r < kSnTA)
-                        sa[r][t] = v;
-                    else
-                        se[r - kSnTA][t] = v;
+                    ridx[q] = row < L && 4 * c4 < nt ? A.sup_row[s0 + row] : -1;
+                }
+                f32x4 v[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int c4 = (tid + 256 * q) % CPRow;
+                    const f32x4 z = {0.0f, 0.0f, 0.0f, 0.0f};
+                    v[q] = ridx[q] >= 0 ? *(const f32x4 *)(A.pool32 + (int64_t)ridx[q] * A.dp + t0 + 4 * c4) : z;
+                }
+                __syncthreads();  // the previous pass is done with the tiles
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int i = tid + 256 * q, r = i / CPRow, c4 = i % CPRow;
+                    float *dst = r < kSnTA ? &sa[r][4 * c4] : &se[r - kSnTA][4 * c4];
+                    dst[0] = v[q][0];
+                    dst[1] = v[q][1];
+                    dst[2] = v[q][2];
+                    dst[3] = v[q][3];
                 }
                 __syncthreads();
                 for (int t = 0; t < nt; ++t) {
