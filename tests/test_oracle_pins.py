@@ -668,3 +668,46 @@ def test_scores_closed_forms():
     # NMI of a refinement: H(V) = log 2, H(U) = log 4, I = log 2 -> 2 log 2 / (3 log 2) = 2/3
     n = scores.contingency([0, 1, 2, 3], [0, 0, 1, 1], 4, 2)
     assert scores.nmi(n) == pytest.approx(2.0 / 3.0, abs=1e-15)
+
+
+# --------------------------------------------------------------------------
+# differentiation form: the objective at free coordinates is the objective of
+# Section 3 on the pinned distance path, and the explicit feature map's
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("window,tau,steps", [(2, 0, 5), (3, 0, 2), (3, 9, 6)])
+def test_fobj_coords_is_the_batch_objective(window, tau, steps):
+    """f(x_B, sigma) written over coordinates equals f_B(C) of Section 3 from
+    the assignment path at kappa = 2 sigma^2 (value and argmin), on states whose
+    window (and count rule) has dropped terms and the initial points, and at
+    several bandwidths, so the sigma-dependence of the self norms is pinned
+    too.  The explicit Taylor feature map of the Gaussian gives the same value
+    with the centers formed as vectors (no kernel trick)."""
+    X = small_data(seed=41, n=64, d=2, spread=0.3, scale=1.0)
+    sigma0 = 1.0
+    kappa0 = 2.0 * sigma0 * sigma0
+    orc = O.Oracle(X, 3, window, O.GAUSS, kappa0, tau=tau)
+    orc.init_centers(np.array([1, 20, 47], np.int32))
+    for B in batches_for(64, 12, steps, seed=42):
+        orc.step(B)
+    cen, pts, wts = orc.center_entries()
+    if steps > window:
+        # the window has dropped the initial term of every center
+        assert orc.state()["term_tag"].min() >= 1
+    B = batches_for(64, 20, 1, seed=43)[0]
+    for sigma in (0.6, 1.0, 1.7):
+        kappa = 2.0 * sigma * sigma
+        ref = O.Oracle(X, 3, window, O.GAUSS, kappa)
+        ref.set_centers(cen, pts, wts)
+        out = ref.distances(B)
+        f_path = ref.objective(B)
+        f, lab = orc.fobj_coords(X[B].astype(np.float64), sigma)
+        assert f == pytest.approx(f_path, rel=1e-13, abs=1e-15)
+        np.testing.assert_array_equal(lab, out["labels"])
+        # explicit feature vectors: C_j = sum_e w_e F(y_e)
+        F = gauss_taylor_features(X.astype(np.float64), kappa)
+        Cx = np.zeros((3, F.shape[1]))
+        np.add.at(Cx, cen, wts[:, None] * F[pts])
+        Dx = ((F[B][:, None, :] - Cx[None, :, :]) ** 2).sum(-1)
+        assert f == pytest.approx(Dx.min(1).mean(), rel=1e-9)
+        np.testing.assert_array_equal(lab, Dx.argmin(1))
