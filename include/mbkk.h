@@ -22,7 +22,7 @@
  * the VALU; BF16X3 has no FP64 re-scoring in this form; mbkk_get_state,
  * mbkk_set_state and the differentiation form return MBKK_E_STATE; an
  * out-of-range index in mbkk_step / mbkk_assign / mbkk_objective is scored
- * as row 0 (and reported under validate).
+ * as row 0 (and reported under validate), see the conventions below.
  *
  * Conventions for every entry point:
  *  - Pointers named *_dev are device pointers (HIP / torch CUDA tensors on the
@@ -35,9 +35,12 @@
  *    for the last failed mbkk_create when called with NULL).
  *  - A context is not thread-safe; calls on one context must be serialised.
  *  - Index arrays are int32 row numbers of X in [0, n).  Out-of-range indices
- *    are never dereferenced: the row is read as zeros, and when
- *    config.validate is non-zero the call returns MBKK_E_INDEX (this check
- *    synchronises the stream).
+ *    are never dereferenced, and when config.validate is non-zero the call
+ *    returns MBKK_E_INDEX (this check synchronises the stream).  Without
+ *    validate the result for such an entry is defined but meaningless, and
+ *    differs between the forms: the truncated forms (window >= 1) score a
+ *    row of zeros in its place; the table form (window = 0), which holds
+ *    cross terms only for rows of X, scores row 0.
  */
 #ifndef MBKK_H
 #define MBKK_H
@@ -73,14 +76,19 @@ extern "C" {
  *         on FP32 MFMA (or direct VALU when cross_impl = DIRECT); the other
  *         kernels on the VALU.
  * FP64  : every kernel value and sum in FP64 (VALU).
- * BF16X3: Gaussian only; x.y on BF16 MFMA as the compensated split product
- *         hi.hi + hi.lo + lo.hi with FP32 accumulation, norms and the exp
- *         argument in FP32; rows whose two best distances are closer than
- *         an error bound of the form are re-scored in FP64 (cross term
- *         recomputed from the FP32 coordinates).  The bound follows from the
- *         bf16 split (|x - hi| <= 2^-8 |x|, |x - hi - lo| <= 2^-16 |x|), the
- *         FP32 sums, ||x||, the largest ||y||^2 of the data and kappa; a
- *         positive tie_delta replaces it.
+ * BF16X3: Gaussian only; x.y of the cross term on BF16 MFMA as the
+ *         compensated split product hi.hi + hi.lo + lo.hi with FP32
+ *         accumulation, norms and the exp argument in FP32; the centers' self
+ *         norms from FP32 MFMA kernel values summed in FP64.  Rows whose two
+ *         best distances are closer than an error bound of the form are
+ *         re-scored in FP64: the cross term of every candidate center (those
+ *         within the bound of the best) is recomputed from the FP32
+ *         coordinates, so a re-scored distance carries only the error of N_j
+ *         (mbkk_selfnorm_error_bound).  The bound follows from the bf16 split
+ *         (|x - hi| <= 2^-8 |x|, |x - hi - lo| <= 2^-16 |x|), the FP32 sums,
+ *         ||x||, the largest ||y||^2 of the data and kappa; a positive
+ *         tie_delta replaces it.  Ties are broken arbitrarily in Section 5;
+ *         here, as in every form, by the lowest center index.
  * BF16X1: as BF16X3 with the single product hi.hi (information only). */
 #define MBKK_FP32 0
 #define MBKK_FP64 1
@@ -152,6 +160,7 @@ int mbkk_create(const mbkk_config *cfg, void *workspace_dev, size_t bytes, void 
 int mbkk_destroy(mbkk_ctx *ctx);
 const char *mbkk_last_error(const mbkk_ctx *ctx);
 
+
 /* Borrows X_dev (n x d FP32, row stride ld >= d elements, 16-byte aligned
  * rows when ld % 4 == 0) and caches ||x||^2 for every row.  X_dev must stay
  * valid and unchanged for the lifetime of the context. */
@@ -181,7 +190,8 @@ int mbkk_step(mbkk_ctx *ctx, const int32_t *batch_dev, int32_t b, int32_t *label
 /* Assignment of m points (any m >= 0, processed in chunks of b_max) to the
  * current centers, no state change.  Outputs (each may be NULL): labels_dev
  * [m] int32, mind_dev [m] FP32, margin_dev [m] FP32 (second smallest minus
- * smallest distance), D_dev [m * k] FP64 (all distances, row-major). */
+ * smallest distance), D_dev [m * k] FP64 (all distances, row-major; in the
+ * BF16 forms the candidates of a re-scored row hold their FP64 values). */
 int mbkk_assign(mbkk_ctx *ctx, const int32_t *idx_dev, int64_t m, int32_t *labels_dev,
                 float *mind_dev, float *margin_dev, double *D_dev);
 
@@ -247,6 +257,19 @@ int mbkk_objective_bwd(mbkk_ctx *ctx, const float *xb_dev, int32_t b, double sig
 /* Self norms <C_j, C_j> of the current centers (FP64, accumulated from the
  * Gram blocks), N_host [k]; synchronises. */
 int mbkk_center_norms(mbkk_ctx *ctx, double *N_host);
+
+/* Near-tie re-scoring of the BF16 forms (the assignment step of Algorithm 2,
+ * whose ties Section 5 leaves arbitrary).  mbkk_rescore_count: the number
+ * of rows re-scored in FP64 by every scoring pass (step, assign, objective,
+ * objective_fwd) since mbkk_create or the last reset; reset != 0 clears the
+ * count after reading it; synchronises.  Always 0 in the FP32 and FP64
+ * forms.  mbkk_selfnorm_error_bound: the bound on |N_j - <C_j, C_j>| of the
+ * Gaussian MFMA forms (FP32 kernel values summed in FP64), from d, the
+ * largest ||x||^2 of the data and kappa; after re-scoring, a row's label is
+ * the exact argmin wherever the exact margin exceeds twice this bound.
+ * MBKK_E_STATE before mbkk_set_data or for another form. */
+int mbkk_rescore_count(mbkk_ctx *ctx, int64_t *rows_host, int32_t reset);
+int mbkk_selfnorm_error_bound(mbkk_ctx *ctx, double *bound_host);
 
 /* Accumulated device time of the cross-term kernel (the dominant kernel) in
  * milliseconds and the number of launches since the last reset, measured

@@ -67,6 +67,8 @@ def lib():
         L.orc_cum.argtypes = [P, P]
         L.orc_state_size.argtypes = [P, P, P]
         L.orc_state_export.argtypes = [P, P, P, P, P, P]
+        L.orc_set_terms.restype = C.c_int
+        L.orc_set_terms.argtypes = [P, I64, I64, P, P, P, P, P, P]
         L.orc_kmeanspp.restype = C.c_int
         L.orc_kmeanspp.argtypes = [P, I64, I32, I32, D, I32, P, P]
         L.orc_fobj_coords.restype = D
@@ -219,6 +221,20 @@ class Oracle:
         L.orc_cum(self._m, _p(cum))
         return dict(iteration=self.iteration, term_center=tc, term_tag=tt, term_coef=tw,
                     term_npts=tn, points=pts[: ne.value], cum=cum)
+
+    def set_state(self, st: dict):
+        """Resumes from a state in the layout of state(): the iteration counter,
+        every term of every center with its batch tag, and the running counts."""
+        tc = _i32(st["term_center"])
+        tt = np.ascontiguousarray(st["term_tag"], dtype=np.int64)
+        tw = np.ascontiguousarray(st["term_coef"], dtype=np.float64)
+        tn = _i32(st["term_npts"])
+        pts = _i32(st["points"])
+        cum = np.ascontiguousarray(st["cum"], dtype=np.float64)
+        assert tc.shape == tt.shape == tw.shape == tn.shape and int(tn.sum()) == pts.shape[0]
+        if lib().orc_set_terms(self._m, int(st["iteration"]), tc.shape[0], _p(tc), _p(tt), _p(tw), _p(tn),
+                               _p(pts), _p(cum)) != 0:
+            raise ValueError("bad state")
 
     def center_entries(self):
         """Flattened (center, point, coefficient) entries of the current centers."""

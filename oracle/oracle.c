@@ -240,6 +240,41 @@ int orc_set_centers(orc_model *m, int64_t nent, const int32_t *ent_center,
     return 0;
 }
 
+/* A whole iteration state: the counter i of the next batch, every term of
+ * every center (the layout orc_state_export writes: term_center, term_tag
+ * (0: the initial point, l >= 1: the part of batch B_l), term_coef,
+ * term_npts, and the points of all terms concatenated) and the running
+ * counts.  Resuming from an exported state continues the same run: the window
+ * and the count rule act on the tags.  Returns -1 on a bad entry. */
+int orc_set_terms(orc_model *m, int64_t iteration, int64_t nterms, const int32_t *term_center,
+                  const int64_t *term_tag, const double *term_coef, const int32_t *term_npts,
+                  const int32_t *points, const double *cum)
+{
+    if (iteration < 1)
+        return -1;
+    int64_t e = 0;
+    for (int64_t a = 0; a < nterms; ++a) {
+        if (term_center[a] < 0 || term_center[a] >= m->k || term_npts[a] < 1 || term_tag[a] < 0 ||
+            term_tag[a] >= iteration)
+            return -1;
+        for (int32_t q = 0; q < term_npts[a]; ++q)
+            if (points[e + q] < 0 || points[e + q] >= m->n)
+                return -1;
+        e += term_npts[a];
+    }
+    for (int j = 0; j < m->k; ++j) {
+        center_clear(&m->c[j]);
+        m->cum[j] = cum ? cum[j] : 0.0;
+    }
+    e = 0;
+    for (int64_t a = 0; a < nterms; ++a) {
+        center_push(&m->c[term_center[a]], term_tag[a], term_coef[a], term_npts[a], points + e);
+        e += term_npts[a];
+    }
+    m->iter = iteration;
+    return 0;
+}
+
 /* <C_j, C_j> = sum over all pairs of support points of coef*coef*K, directly. */
 static double center_sqnorm(orc_model *m, int j)
 {

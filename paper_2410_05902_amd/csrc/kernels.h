@@ -5,6 +5,8 @@
 
 namespace mbkk {
 
+// p[0 .. nwords) = v (32-bit words): the library's only way of clearing memory.
+void launch_fill32(void *p, uint32_t v, int64_t nwords, hipStream_t st);
 void launch_row_sqnorm(const float *X, int64_t n, int d, int64_t ld, float *sqn, unsigned int *sqmax,
                        hipStream_t st);
 // frag_mode 1 / 2: also write the rows (as batch rows 0..cnt-1) in MFMA
@@ -31,12 +33,12 @@ void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_ex
                    int gram_te, hipStream_t st);
 
 // Gram blocks of slot rr against the columns in col_mask: plan (when not made
-// by the update), then work and fold.  mfma: the Gaussian MFMA forms, with
-// the product arithmetic of `precision`; else VALU in FP64 or FP32.
+// by the update), then work and fold.  mfma: the Gaussian MFMA forms (FP32
+// MFMA products in every precision form); else VALU in FP64 or FP32.
 int gram_task_cols(int mfma, int fp64);  // te of the plan for the chosen Gram form
 void launch_gram_plan(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int te, hipStream_t st);
 void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param, int fp64,
-                 int mfma, int precision, bool fold, hipStream_t st);
+                 int mfma, bool fold, hipStream_t st);
 void launch_gram_fold(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, hipStream_t st);
 
 // Cross term P = <phi(x), C_j> for the staged batch rows [0, nb).
@@ -52,6 +54,9 @@ void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double pa
                   int precision, double tie_delta, double ymax2, double *D_out, int64_t ldD, bool with_rank,
                   hipStream_t st);
 void launch_sum_mind(const Buffers &B, int nb, int accumulate, hipStream_t st);
+// Bound on the error of a self norm N_j of the Gaussian MFMA forms (FP32
+// kernel values summed in FP64), for row stride dp, max ||y||^2 and kappa.
+double selfnorm_error_bound(int dp, double ymax2, double kappa);
 
 // Differentiation form (Gaussian, bandwidth s): self norms and their
 // s-derivative for every center, and the per-row gradient plus the summed

@@ -1290,8 +1290,10 @@ struct ScoreArgs {
     double *Dout;
     int64_t ldD;
     // FP64 re-scoring of near ties (BF16 forms): a fixed threshold (delta > 0)
-    // or the per-row bound from rel_dot and ymax2
-    double delta, kappa, rel_dot, ymax2;
+    // or the per-row bound from rel_dot, ymax2 and eN (the bound on the error
+    // of a self norm N_j); nresc counts the re-scored rows
+    double delta, kappa, rel_dot, ymax2, eN;
+    unsigned long long *nresc;
     int d, dp;
     const float *bat32, *pool32;
     const int32_t *sup_row;
@@ -1304,7 +1306,8 @@ struct ScoreArgs {
 // FP64 re-scoring of one batch row by one wave: candidates are the centers
 // whose approximate distance is within delta of the best; for them the cross
 // term is recomputed in FP64 from the FP32 coordinates (direct ||x - y||^2,
-// FP64 exp, FP64 weights).
+// FP64 exp, FP64 weights), and their distances (also in Dout when requested)
+// then carry only the error of N_j (FP32 kernel values summed in FP64).
 // best: the row's smallest approximate distance (from the scoring pass);
 // seg_off / Nv: the segment offsets and self norms (LDS copies when staged).
 __device__ void rescore_row(const ScoreArgs &A, int row, int RB, double delta, double best,
@@ -1351,6 +1354,8 @@ __device__ void rescore_row(const ScoreArgs &A, int row, int RB, double delta, d
             for (int o = 32; o > 0; o >>= 1)
                 p += __shfl_xor(p, o);
             const double D = 1.0 - 2.0 * p + Nv[j];
+            if (A.Dout && lane == 0)
+                A.Dout[(int64_t)row * A.ldD + j] = D;  // replaces the approximate value
             if (D < b64) {
                 s64 = b64;
                 b64 = D;
@@ -1378,7 +1383,7 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
     __shared__ int flab[64];
     __shared__ float fmin_[64], fmar[64];
     __shared__ double fdel[64], fbest[64];
-    __shared__ int smax_seg;
+    __shared__ int smax_seg, snresc;
     __shared__ int32_t lseg[LK ? kScoreLdsK + 1 : 1];
     __shared__ double lN[LK ? kScoreLdsK : 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1402,8 +1407,10 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
                                : (A.nranges > 0 ? bs_range_blocks(seg_off[A.k] / 32, A.nranges) : A.RB);
     if constexpr (RESCORE) {
         // longest center segment: the length of the FP32 sums in the error bound
-        if (threadIdx.x == 0)
+        if (threadIdx.x == 0) {
             smax_seg = 0;
+            snresc = 0;
+        }
         __syncthreads();
         int m = 0;
         for (int i = threadIdx.x; i < A.k; i += 64 * kScoreWaves)
@@ -1480,15 +1487,16 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
             // to at most 1 and kernel values at most 1
             //   |dP_j| <= e(x, Y) + S 2^-24,  |dN_j| <= e(Y, Y) + S 2^-24
             // (Y^2 = max |y|^2 over the data, S = longest segment: the FP32
-            // sums).  A margin above 2 (2 |dP| + |dN|) cannot hide a swap.
+            // sums).  N_j comes from FP32 kernel values summed in FP64: its
+            // bound eN is the host's.  A margin above 2 (2 |dP| + |dN|) cannot
+            // hide a swap.
             double dl = A.delta;
             if (!(dl > 0.0)) {
                 const double x2 = act ? A.batsq64[row] : 0.0, y2 = A.ymax2;
                 const double xn = sqrt(x2), yn = sqrt(y2);
                 const double gS = (double)smax_seg * 0x1p-24;
                 const double eP = (2.0 * A.rel_dot * xn * yn + 0x1p-22 * (x2 + y2)) / A.kappa + gS;
-                const double eN = (2.0 * A.rel_dot * y2 + 0x1p-22 * 2.0 * y2) / A.kappa + gS;
-                dl = 2.0 * (2.0 * eP + eN);
+                dl = 2.0 * (2.0 * eP + A.eN);
             }
             fdel[lane] = dl;
             fbest[lane] = b0;
@@ -1506,10 +1514,13 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
                     flab[r] = l;
                     fmin_[r] = m;
                     fmar[r] = g;
+                    atomicAdd(&snresc, 1);
                 }
             }
         }
         __syncthreads();
+        if (threadIdx.x == 0 && snresc > 0 && A.nresc)
+            atomicAdd(A.nresc, (unsigned long long)snresc);
     }
     if (w == 0 && act) {
         A.labels[row] = flab[lane];
@@ -1538,6 +1549,20 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
             }
         }
     }
+}
+
+// Bound on |N_j - <C_j, C_j>| for the Gaussian MFMA forms, whose Gram blocks
+// hold FP32 kernel values summed in FP64 (u = 2^-24):
+//  - a.e on FP32 MFMA over dp products: |d(a.e)| <= dp u |a||e| (+u: c2);
+//  - the exponent's FP32 norms, scalings and sum: 4u (|a|^2 + |e|^2);
+//  - so a kernel value has relative error <= (2 (dp+1) u Y^2 + 8u Y^2) / kappa
+//    with Y^2 = max |y|^2 over the data, plus 2u for exp2 and the rounding of
+//    its argument;
+//  - the weights' products sum to at most 1 (FP64 coefficients and sums).
+double selfnorm_error_bound(int dp, double ymax2, double kappa)
+{
+    const double u = 0x1p-24;
+    return (2.0 * (dp + 1) * u * ymax2 + 8.0 * u * ymax2) / kappa + 2.0 * u;
 }
 
 void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double param, int fp64, int mfma,
@@ -1572,6 +1597,8 @@ void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double pa
     A.rel_dot = precision == MBKK_BF16X1 ? 0x1p-7 + 0x1p-16 + (double)L.dp * 0x1p-24
                                          : 3.0 * 0x1p-16 + 3.0 * (double)L.dp * 0x1p-24;
     A.ymax2 = ymax2;
+    A.eN = selfnorm_error_bound(L.dp, ymax2, param);
+    A.nresc = B.nresc;
     A.d = L.d;
     A.dp = L.dp;
     A.bat32 = B.bat32;

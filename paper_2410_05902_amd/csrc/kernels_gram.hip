@@ -17,9 +17,11 @@
 // Every sum has a fixed order, so the blocks are bit-reproducible.
 //   k_gram_valu : any kernel, FP32 or FP64 arithmetic; a task is 32 slot
 //                 rows (wave-uniform) x 64 column rows (one per lane);
-//   k_gram_mfma : Gaussian MFMA forms, the form's own product arithmetic
-//                 (FP32 MFMA, or BF16 hi/lo split) and exp fused in
-//                 registers; a task is one 32 x 32 output block.
+//   k_gram_mfma : Gaussian MFMA forms; FP32 MFMA products and exp fused in
+//                 registers; a task is one 32 x 32 output block.  The BF16
+//                 forms take their Gram blocks here too: the self norms keep
+//                 FP32 kernel values (summed in FP64), so a row re-scored in
+//                 FP64 carries only the FP32 error of N_j.
 #include "dev_common.h"
 #include "kernels.h"
 
@@ -183,20 +185,16 @@ __global__ __launch_bounds__(kGramWG) void k_gram_valu(const GramWork A, int d, 
 
 // ---------------------------------------------------------------------------
 // MFMA tasks (Gaussian): exp(-(||a||^2 + ||e||^2 - 2 a.e) / kappa) with a.e
-// in the form's arithmetic; DP = 0 takes the row stride at run time.
-//   MODE 0: FP32 MFMA 32x32x2; MODE 1: BF16 hi.hi + hi.lo + lo.hi; MODE 2: BF16 hi.hi
+// on FP32 MFMA 32x32x2 (every MFMA form, the BF16 ones included); DP = 0
+// takes the row stride at run time.
 // ---------------------------------------------------------------------------
-template <int MODE, int DP>
+template <int DP>
 __global__ __launch_bounds__(kGramWG) void k_gram_mfma(const GramWork A, int dp_rt, int zero_row,
                                                        const float *__restrict__ pool32,
-                                                       const uint16_t *__restrict__ poolhi,
-                                                       const uint16_t *__restrict__ poollo,
                                                        const float *__restrict__ poolsq, float c2, float c1)
 {
-    constexpr bool F32 = MODE == 0;
-    constexpr bool X3 = MODE == 1;
     const int dp = DP > 0 ? DP : dp_rt;
-    const int KS = F32 ? dp / 2 : dp / 16;
+    const int KS = dp / 2;
     __shared__ float sqa[kGramWG / 64][32];
     const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
     gram_wave_loop<32>(A, [&](const GramCol &a, const GramCol &ec, int ab, int eb, double &lsum) {
@@ -211,43 +209,21 @@ __global__ __launch_bounds__(kGramWG) void k_gram_mfma(const GramWork A, int dp_
 #pragma unroll
         for (int i = 0; i < 16; ++i)
             acc[i] = 0.0f;
-        if constexpr (F32) {
-            const float *sa = pool32 + ra * dp + h * KS, *se = pool32 + re * dp + h * KS;
-            auto kstep = [&](int s4) {
-                const f32x4 av = *(const f32x4 *)(sa + s4), ev = *(const f32x4 *)(se + s4);
+        // lane half h takes the coordinates [h dp/2, (h+1) dp/2)
+        const float *sa = pool32 + ra * dp + h * KS, *se = pool32 + re * dp + h * KS;
+        auto kstep = [&](int s4) {
+            const f32x4 av = *(const f32x4 *)(sa + s4), ev = *(const f32x4 *)(se + s4);
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], ev[u], acc, 0, 0, 0);
-            };
-            if constexpr (DP > 0) {
+            for (int u = 0; u < 4; ++u)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], ev[u], acc, 0, 0, 0);
+        };
+        if constexpr (DP > 0) {
 #pragma unroll
-                for (int s4 = 0; s4 < DP / 2; s4 += 4)
-                    kstep(s4);
-            } else {
-                for (int s4 = 0; s4 < KS; s4 += 4)
-                    kstep(s4);
-            }
+            for (int s4 = 0; s4 < DP / 2; s4 += 4)
+                kstep(s4);
         } else {
-            auto kstep = [&](int ks) {
-                const int64_t oa16 = ra * dp + ks * 16 + h * 8, oe16 = re * dp + ks * 16 + h * 8;
-                const bf16x8 ah = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poolhi + oa16));
-                const bf16x8 eh = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poolhi + oe16));
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, eh, acc, 0, 0, 0);
-                if constexpr (X3) {
-                    const bf16x8 al = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poollo + oa16));
-                    const bf16x8 el = __builtin_bit_cast(bf16x8, *(const u16x8 *)(poollo + oe16));
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, el, acc, 0, 0, 0);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, eh, acc, 0, 0, 0);
-                }
-            };
-            if constexpr (DP > 0) {
-#pragma unroll
-                for (int ks = 0; ks < DP / 16; ++ks)
-                    kstep(ks);
-            } else {
-                for (int ks = 0; ks < KS; ++ks)
-                    kstep(ks);
-            }
+            for (int s4 = 0; s4 < KS; s4 += 4)
+                kstep(s4);
         }
         // lane: column n (e row), rows m = 8 (i/4) + 4 h + i%4 (a rows); the
         // row norms were written by this wave (in-order LDS access)
@@ -322,16 +298,14 @@ static void launch_gram_valu(const Layout &L, const Buffers &B, const GramWork &
 #undef MBKK_GV
 }
 
-template <int MODE>
 static void launch_gram_mfma(const Layout &L, const Buffers &B, const GramWork &A, double kappa, hipStream_t st)
 {
     const double l2e = 1.4426950408889634;
     const float c2 = (float)(2.0 * l2e / kappa), c1 = (float)(-l2e / kappa);
     const dim3 grid(kGramWaves / (kGramWG / 64));
     const int zr = (int)L.PR;
-#define MBKK_GM(DP)                                                                                          \
-    hipLaunchKernelGGL((k_gram_mfma<MODE, DP>), grid, dim3(kGramWG), 0, st, A, L.dp, zr, B.pool32, B.poolhi, \
-                       B.poollo, B.poolsq, c2, c1)
+#define MBKK_GM(DP) \
+    hipLaunchKernelGGL((k_gram_mfma<DP>), grid, dim3(kGramWG), 0, st, A, L.dp, zr, B.pool32, B.poolsq, c2, c1)
     switch (L.dp) {
     case 32: MBKK_GM(32); break;
     case 64: MBKK_GM(64); break;
@@ -343,7 +317,7 @@ static void launch_gram_mfma(const Layout &L, const Buffers &B, const GramWork &
 }
 
 void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t mask, int kind, double param, int fp64,
-                 int mfma, int precision, bool fold, hipStream_t st)
+                 int mfma, bool fold, hipStream_t st)
 {
     GramWork A;
     A.k = L.k;
@@ -355,12 +329,8 @@ void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t mask, int k
     A.goff = B.goff;
     A.gpart = B.gpart;
     if (mfma) {
-        if (precision == MBKK_FP32)
-            launch_gram_mfma<0>(L, B, A, param, st);
-        else if (precision == MBKK_BF16X3)
-            launch_gram_mfma<1>(L, B, A, param, st);
-        else
-            launch_gram_mfma<2>(L, B, A, param, st);
+        // every MFMA form: FP32 products (the BF16 forms' cross term alone is split)
+        launch_gram_mfma(L, B, A, param, st);
     } else if (fp64) {
         launch_gram_valu<double>(L, B, A, kind, param, st);
     } else {

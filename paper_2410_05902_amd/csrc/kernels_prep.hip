@@ -12,6 +12,26 @@
 namespace mbkk {
 
 // ---------------------------------------------------------------------------
+// Fill of n 32-bit words with one value: every clearing of device state goes
+// through this kernel rather than a runtime memset, so that a caller may
+// capture the library's calls in a HIP graph.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fill32(uint32_t *__restrict__ p, uint32_t v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        p[i] = v;
+}
+
+void launch_fill32(void *p, uint32_t v, int64_t nwords, hipStream_t st)
+{
+    if (nwords <= 0)
+        return;
+    int64_t blocks = (nwords + 255) / 256;
+    blocks = blocks < 1024 ? blocks : 1024;
+    hipLaunchKernelGGL(k_fill32, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t *)p, v, nwords);
+}
+
+// ---------------------------------------------------------------------------
 // ||x||^2 for every row of X, summed in FP64, stored as FP32 (data norms),
 // and their maximum over the finite ones (as FP32 bits in *sqmax, which the
 // caller zeroes first; non-negative floats order like their bit patterns).

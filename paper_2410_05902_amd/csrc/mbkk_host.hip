@@ -33,7 +33,7 @@ struct mbkk_ctx {
     uint32_t fold_mask = 0;
     // iteration whose support segment offsets the last update wrote to seg_next
     int64_t seg_next_iter = -1;
-    std::vector<int32_t> slot_b;  // points held by each physical slot
+    int32_t slot_b[kMaxSlots] = {};  // points held by each physical slot
     // timing of the cross-term kernel
     bool timing = false;
     std::vector<hipEvent_t> ev;  // pairs (start, stop)
@@ -159,9 +159,11 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.sup_w64 = (double *)take(8 * L.Mcap);
     B.sn_part = (double *)take(8 * 2 * (size_t)L.k * kSnSplit);
     B.blk_center = (int32_t *)take(4 * L.nblk);
-    size_t part_direct = (size_t)(L.k + kDirectWGs) * L.bmax * 8;  // runs of the direct kernel, FP64 worst case
-    size_t part_mfma = (size_t)L.nblk * L.bmax * 4;
-    B.part = take(L.untrunc ? 0 : (part_direct > part_mfma ? part_direct : part_mfma));
+    // cross-term partials of the kernel in use: runs of the direct kernel (FP32
+    // or FP64), or one FP32 value per (32-row block, batch row) on MFMA
+    const size_t part_direct = (size_t)(L.k + kDirectWGs) * L.bmax * L.tbytes;
+    const size_t part_mfma = (size_t)L.nblk * L.bmax * 4;
+    B.part = take(L.untrunc ? 0 : (L.pad == kMfmaPad ? part_mfma : part_direct));
     if (L.untrunc) {
         B.dp_T = take((size_t)L.tbytes * (size_t)L.k * (size_t)L.ldT);
         B.dp_tsel = take(8 * (size_t)L.bmax);
@@ -180,6 +182,7 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.margin = (float *)take(4 * (size_t)L.bmax);
     B.obj = (double *)take(8 * 4);
     B.flags = (int32_t *)take(4 * 4);
+    B.nresc = (unsigned long long *)take(8);
     B.Nsig = (double *)take(8 * (size_t)L.k);
     B.dNsig = (double *)take(8 * (size_t)L.k);
     B.rowds = (double *)take(8 * (size_t)L.bmax);
@@ -299,16 +302,15 @@ static uint32_t col_mask_of(const SlotList &s, bool init_alive)
     return m;
 }
 
-// Gram blocks of slot p against the live columns in `mask`: on MFMA with the
-// form's own arithmetic for the Gaussian MFMA forms, else VALU.  In a step
+// Gram blocks of slot p against the live columns in `mask`: on FP32 MFMA for
+// the Gaussian MFMA forms (BF16 ones included), else VALU.  In a step
 // (`in_step`) the update kernel already wrote the task plan and the fold is
 // left to the next support layout; elsewhere plan, work and fold run here.
 static void gram(mbkk_ctx *c, int p, uint32_t mask, bool in_step)
 {
     if (!in_step)
         launch_gram_plan(c->L, c->B, p, mask, gram_task_cols(c->use_mfma, c->fp64), c->stream);
-    launch_gram(c->L, c->B, p, mask, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->use_mfma, c->cfg.precision,
-                !in_step, c->stream);
+    launch_gram(c->L, c->B, p, mask, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->use_mfma, !in_step, c->stream);
     if (in_step) {
         c->fold_rr = p;
         c->fold_mask = mask;
@@ -338,7 +340,8 @@ static int check_flags(mbkk_ctx *c)
 
 static int clear_flags(mbkk_ctx *c)
 {
-    HIPCHK(c, hipMemsetAsync(c->B.flags, 0, 4 * sizeof(int32_t), c->stream));
+    launch_fill32(c->B.flags, 0, 4, c->stream);
+    HIPCHK(c, hipGetLastError());
     return MBKK_OK;
 }
 
@@ -440,6 +443,40 @@ int mbkk_workspace_size(const mbkk_config *cfg, size_t *bytes)
     return MBKK_OK;
 }
 
+// Sets up context c over the workspace (already checked): carves it and
+// writes the rows and sentinels that must start at fixed values.
+static int setup(mbkk_ctx *c, const mbkk_config *cfg, void *workspace, void *stream)
+{
+    const Layout L = make_layout(*cfg);
+    c->cfg = *cfg;
+    c->L = L;
+    carve(c->L, (char *)workspace, c->B);
+    c->stream = (hipStream_t)stream;
+    c->use_mfma = wants_mfma(*cfg);
+    c->fp64 = cfg->precision == MBKK_FP64;
+    std::fill(c->slot_b, c->slot_b + kMaxSlots, 0);
+    // zero row of the pool (segment padding target), sentinels, error flags,
+    // re-score count, ring offsets
+    const int64_t zr = L.PR;
+    launch_fill32(c->B.pool32 + zr * L.dp, 0, L.dp, c->stream);
+    if (L.bf16) {
+        launch_fill32(c->B.poolhi + zr * L.dp, 0, L.dp / 2, c->stream);
+        launch_fill32(c->B.poollo + zr * L.dp, 0, L.dp / 2, c->stream);
+    }
+    launch_fill32(c->B.poolsq + zr, 0, 1, c->stream);
+    launch_fill32(c->B.poolsq64 + zr, 0, 2, c->stream);
+    launch_fill32(c->B.sup_row + L.Mcap, (uint32_t)L.PR, 1, c->stream);
+    launch_fill32(c->B.sup_w + L.Mcap, 0, 1, c->stream);
+    launch_fill32(c->B.sup_ay + L.Mcap, 0, 1, c->stream);
+    launch_fill32(c->B.flags, 0, 4, c->stream);
+    launch_fill32(c->B.nresc, 0, 2, c->stream);
+    launch_fill32(c->B.ring_off, 0, (int64_t)L.P * (L.k + 1), c->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(nullptr, MBKK_E_HIP, std::string("workspace init: ") + hipGetErrorString(e));
+    return MBKK_OK;
+}
+
 int mbkk_create(const mbkk_config *cfg, void *workspace, size_t bytes, void *stream, mbkk_ctx **out)
 {
     std::string why;
@@ -454,37 +491,10 @@ int mbkk_create(const mbkk_config *cfg, void *workspace, size_t bytes, void *str
     if (!workspace || bytes < L.bytes || ((uintptr_t)workspace & 255))
         return fail(nullptr, MBKK_E_WORKSPACE, "workspace missing, smaller than mbkk_workspace_size or not 256-byte aligned");
     mbkk_ctx *c = new mbkk_ctx();
-    c->cfg = *cfg;
-    c->L = L;
-    carve(c->L, (char *)workspace, c->B);
-    c->stream = (hipStream_t)stream;
-    c->use_mfma = wants_mfma(*cfg);
-    c->fp64 = cfg->precision == MBKK_FP64;
-    c->slot_b.assign(L.P, 0);
-    // zero row of the pool (segment padding target) and error flags
-    const int64_t zr = L.PR;
-    hipError_t e = hipMemsetAsync(c->B.pool32 + zr * L.dp, 0, sizeof(float) * L.dp, c->stream);
-    if (e == hipSuccess && L.bf16)
-        e = hipMemsetAsync(c->B.poolhi + zr * L.dp, 0, 2 * L.dp, c->stream);
-    if (e == hipSuccess && L.bf16)
-        e = hipMemsetAsync(c->B.poollo + zr * L.dp, 0, 2 * L.dp, c->stream);
-    if (e == hipSuccess)
-        e = hipMemsetAsync(c->B.poolsq + zr, 0, sizeof(float), c->stream);
-    if (e == hipSuccess)
-        e = hipMemsetAsync(c->B.poolsq64 + zr, 0, sizeof(double), c->stream);
-    if (e == hipSuccess)
-        e = hipMemsetD32Async((hipDeviceptr_t)(c->B.sup_row + L.Mcap), (int)L.PR, 1, c->stream);
-    if (e == hipSuccess)
-        e = hipMemsetAsync(c->B.sup_w + L.Mcap, 0, sizeof(float), c->stream);
-    if (e == hipSuccess)
-        e = hipMemsetAsync(c->B.sup_ay + L.Mcap, 0, sizeof(float), c->stream);
-    if (e == hipSuccess)
-        e = hipMemsetAsync(c->B.flags, 0, 16, c->stream);
-    if (e == hipSuccess)
-        e = hipMemsetAsync(c->B.ring_off, 0, 4 * (size_t)L.P * (L.k + 1), c->stream);
-    if (e != hipSuccess) {
+    rc = setup(c, cfg, workspace, stream);
+    if (rc) {
         delete c;
-        return fail(nullptr, MBKK_E_HIP, std::string("workspace init: ") + hipGetErrorString(e));
+        return rc;
     }
     *out = c;
     return MBKK_OK;
@@ -510,7 +520,7 @@ int mbkk_set_data(mbkk_ctx *c, const float *X, int64_t ld)
         return fail(c, MBKK_E_INVALID, "X is NULL or ld < d");
     c->B.X = X;
     c->B.ld = ld;
-    HIPCHK(c, hipMemsetAsync(c->B.sqmax, 0, sizeof(unsigned int), c->stream));
+    launch_fill32(c->B.sqmax, 0, 1, c->stream);
     launch_row_sqnorm(X, c->L.n, c->L.d, ld, c->B.sqn, c->B.sqmax, c->stream);
     HIPCHK(c, hipGetLastError());
     unsigned int bits = 0;
@@ -538,14 +548,14 @@ static int init_common(mbkk_ctx *c, const int32_t *idx_dev)
         launch_dp_init(L, B, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->stream);
     } else {
         launch_init_state(L, B, c->cfg.kernel, c->cfg.kernel_param, c->fp64, 1, c->stream);
-        HIPCHK(c, hipMemsetAsync(B.ring_off, 0, 4 * (size_t)L.P * (L.k + 1), c->stream));
+        launch_fill32(B.ring_off, 0, (int64_t)L.P * (L.k + 1), c->stream);
     }
     HIPCHK(c, hipGetLastError());
     c->iter = 1;
     c->support_iter = -1;
     c->fold_rr = -1;
     c->seg_next_iter = -1;
-    std::fill(c->slot_b.begin(), c->slot_b.end(), 0);
+    std::fill(c->slot_b, c->slot_b + kMaxSlots, 0);
     if (c->cfg.validate) {
         int rc = check_flags(c);
         if (rc)
@@ -836,8 +846,8 @@ int mbkk_agreement(mbkk_ctx *c, const int32_t *labels_dev, const int32_t *truth_
     const int k = c->L.k;
     if (nc < 1 || (int64_t)k * nc > ((int64_t)1 << 26))
         return fail(c, MBKK_E_INVALID, "need 1 <= c and k * c <= 2^26");
-    HIPCHK(c, hipMemsetAsync(c->B.flags, 0, 4 * sizeof(int32_t), c->stream));
-    HIPCHK(c, hipMemsetAsync(table_dev, 0, sizeof(int64_t) * (size_t)k * nc, c->stream));
+    launch_fill32(c->B.flags, 0, 4, c->stream);
+    launch_fill32(table_dev, 0, 2 * (int64_t)k * nc, c->stream);
     launch_contingency(labels_dev, truth_dev, m, k, nc, table_dev, c->B.flags, c->stream);
     HIPCHK(c, hipGetLastError());
     std::vector<int64_t> n((size_t)k * nc);
@@ -1107,6 +1117,36 @@ int mbkk_set_state(mbkk_ctx *c, const mbkk_state *s)
     c->iter = i;
     c->support_iter = -1;
     c->inited = true;
+    return MBKK_OK;
+}
+
+int mbkk_rescore_count(mbkk_ctx *c, int64_t *rows_host, int32_t reset)
+{
+    if (!c)
+        return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (!rows_host)
+        return fail(c, MBKK_E_INVALID, "rows is NULL");
+    unsigned long long v = 0;
+    HIPCHK(c, hipMemcpyAsync(&v, c->B.nresc, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    if (reset)
+        launch_fill32(c->B.nresc, 0, 2, c->stream);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *rows_host = (int64_t)v;
+    return MBKK_OK;
+}
+
+int mbkk_selfnorm_error_bound(mbkk_ctx *c, double *bound_host)
+{
+    if (!c)
+        return fail(nullptr, MBKK_E_INVALID, "ctx is NULL");
+    if (!bound_host)
+        return fail(c, MBKK_E_INVALID, "bound is NULL");
+    if (!c->data_set)
+        return fail(c, MBKK_E_STATE, "set_data first");
+    if (!c->use_mfma || c->cfg.kernel != MBKK_GAUSS)
+        return fail(c, MBKK_E_STATE, "the bound covers the Gaussian MFMA forms");
+    *bound_host = selfnorm_error_bound(c->L.dp, c->ymax2, c->cfg.kernel_param);
     return MBKK_OK;
 }
 

@@ -113,6 +113,7 @@ struct Buffers {
     float *margin = nullptr;     // [bmax]
     double *obj = nullptr;       // [4] device scalars
     int32_t *flags = nullptr;    // [4] error flags (index, non-finite, label)
+    unsigned long long *nresc = nullptr;  // [1] rows re-scored in FP64 (BF16 forms)
     // differentiation form
     double *Nsig = nullptr;      // [k] self norms at the bandwidth of the call
     double *dNsig = nullptr;     // [k] their derivative

@@ -52,22 +52,26 @@ class Model:
         nbytes = C.c_size_t()
         L.check(lib.mbkk_workspace_size(C.byref(self.cfg), C.byref(nbytes)))
         self.workspace_bytes = int(nbytes.value)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        ctx = C.c_void_p()
         raw = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
         shift = (-raw.data_ptr()) % 256
         self._raw = raw
         self.workspace = raw[shift: shift + self.workspace_bytes]
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        ctx = C.c_void_p()
         L.check(lib.mbkk_create(C.byref(self.cfg), C.c_void_p(self.workspace.data_ptr()),
                                 self.workspace_bytes, C.c_void_p(self.stream.cuda_stream), C.byref(ctx)))
         self._ctx = ctx
         L.check(lib.mbkk_set_data(ctx, C.c_void_p(X.data_ptr()), X.stride(0)), ctx)
 
-    def __del__(self):
+    def close(self):
+        """Destroys the context (also done on garbage collection)."""
         ctx = getattr(self, "_ctx", None)
         if ctx is not None and L._lib is not None:
             L._lib.mbkk_destroy(ctx)
             self._ctx = None
+
+    def __del__(self):
+        self.close()
 
     # -- helpers ------------------------------------------------------------
     def _idx(self, idx) -> torch.Tensor:
@@ -204,6 +208,18 @@ class Model:
                     cum=np.ascontiguousarray(st["cum"], np.float64).reshape(k))
         s = self._state_struct(bufs, int(st["iteration"]), k, W, bm)
         self._chk(L.lib().mbkk_set_state(self._ctx, C.byref(s)))
+
+    def rescore_count(self, reset: bool = False) -> int:
+        """Rows re-scored in FP64 (BF16 forms) since creation or the last reset."""
+        n = C.c_int64()
+        self._chk(L.lib().mbkk_rescore_count(self._ctx, C.byref(n), 1 if reset else 0))
+        return int(n.value)
+
+    def selfnorm_error_bound(self) -> float:
+        """Bound on the error of a center's self norm (Gaussian MFMA forms)."""
+        v = C.c_double()
+        self._chk(L.lib().mbkk_selfnorm_error_bound(self._ctx, C.byref(v)))
+        return float(v.value)
 
     def set_timing(self, enable: bool):
         self._chk(L.lib().mbkk_set_timing(self._ctx, 1 if enable else 0))

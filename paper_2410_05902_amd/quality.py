@@ -64,8 +64,8 @@ def compare(wl: W.Workload, iterations: int, lrs: Iterable[str] = ("beta", "skle
     out = []
     for prec in precisions:
         for window in windows:
-            if window == 0 and prec not in ("fp32", "fp64"):
-                continue  # the table form runs in FP32 / FP64
+            if window == 0 and prec == "bf16x1":
+                continue  # the table form runs in FP32, FP64 or BF16X3
             for lr in lrs:
                 out.append(run_config(wl, X, lr, window, prec, iterations, b))
     return out

@@ -91,3 +91,28 @@ def oracle_from_gpu_state(orc, st, k, window):
         wts.append(coef[cj[keep], 1 + r])
     orc.set_centers(np.concatenate(cen), np.concatenate(pts), np.concatenate(wts))
     return int(sum(len(p) for p in pts))
+
+
+def state_image_to_oracle(st: dict, k: int, W: int) -> dict:
+    """The oracle's term list (Oracle.set_state) of a truncated-form state
+    image (mbkk_get_state): the initial term of every center whose coefficient
+    is not 0 (tag 0), then, oldest first, the part of each live batch
+    l = max(1, i-W) .. i-1 (ring slot (l-1) mod W) assigned to it (tag l).
+    For states of the window rule (tau = 0)."""
+    i = int(st["iteration"])
+    coef, off, sidx = st["coef"], st["slot_off"], st["slot_idx"]
+    tc, tt, tw, tn, pts = [], [], [], [], []
+    for j in range(k):
+        if coef[j, 0] != 0.0:
+            tc.append(j), tt.append(0), tw.append(coef[j, 0]), tn.append(1)
+            pts.append(np.array([st["init_idx"][j]], np.int32))
+        for l in range(max(1, i - W), i):
+            r = (l - 1) % W
+            seg = sidx[r, off[r][j]: off[r][j + 1]]
+            if seg.size and coef[j, 1 + r] != 0.0:
+                tc.append(j), tt.append(l), tw.append(coef[j, 1 + r]), tn.append(seg.size)
+                pts.append(seg.astype(np.int32))
+    return dict(iteration=i, term_center=np.array(tc, np.int32), term_tag=np.array(tt, np.int64),
+                term_coef=np.array(tw, np.float64), term_npts=np.array(tn, np.int32),
+                points=np.concatenate(pts) if pts else np.zeros(0, np.int32),
+                cum=np.asarray(st["cum"], np.float64))

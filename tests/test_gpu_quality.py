@@ -50,6 +50,5 @@ def test_compare_lists_every_configuration():
     wl = W.c1_blobs(seed=1)
     rows = compare(wl, 5, lrs=("beta", "sklearn"), windows=(2, 0), precisions=("fp32", "bf16x3"))
     keys = {(r["lr"], r["window"], r["precision"]) for r in rows}
-    # the table form (window 0) runs in FP32 only
-    assert keys == {("beta", 2, "fp32"), ("sklearn", 2, "fp32"), ("beta", 0, "fp32"), ("sklearn", 0, "fp32"),
-                    ("beta", 2, "bf16x3"), ("sklearn", 2, "bf16x3")}
+    # every rate, window and form: the table form (window 0) has FP32 and BF16X3 too
+    assert keys == {(lr, w, p) for lr in ("beta", "sklearn") for w in (2, 0) for p in ("fp32", "bf16x3")}

@@ -711,3 +711,51 @@ def test_fobj_coords_is_the_batch_objective(window, tau, steps):
         Dx = ((F[B][:, None, :] - Cx[None, :, :]) ** 2).sum(-1)
         assert f == pytest.approx(Dx.min(1).mean(), rel=1e-9)
         np.testing.assert_array_equal(lab, Dx.argmin(1))
+
+
+# --------------------------------------------------------------------------
+# state import: an exported state resumes the same run
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("window,lr", [(3, W.LR_BETA), (2, W.LR_SKLEARN), (0, W.LR_BETA)])
+def test_state_export_import_resumes_the_run(window, lr):
+    """Exporting the state after some steps and importing it into a fresh
+    oracle continues the run exactly (same labels, distances and states),
+    through the window's later truncations."""
+    X = small_data(seed=51, n=80, d=3)
+    batches = batches_for(80, 16, 9, seed=52)
+    a = O.Oracle(X, 3, window, O.GAUSS, 1.5, lr)
+    a.init_centers(np.array([3, 30, 60], np.int32))
+    for B in batches[:4]:
+        a.step(B)
+    b = O.Oracle(X, 3, window, O.GAUSS, 1.5, lr)
+    b.set_state(a.state())
+    assert b.iteration == a.iteration
+    for B in batches[4:]:
+        oa, ob = a.step(B), b.step(B)
+        np.testing.assert_array_equal(oa["labels"], ob["labels"])
+        np.testing.assert_array_equal(oa["D"], ob["D"])
+        sa, sb = a.state(), b.state()
+        for key in ("term_center", "term_tag", "term_coef", "term_npts", "points", "cum"):
+            np.testing.assert_array_equal(sa[key], sb[key])
+    with pytest.raises(ValueError):
+        bad = a.state()
+        bad["term_tag"] = bad["term_tag"] + 100   # a batch newer than the iteration
+        b.set_state(bad)
+
+
+def test_state_image_round_trip():
+    """The library's ring-slot state image of an oracle state converts back
+    to the same terms (the marshalling the benchmark's oracle leg uses)."""
+    from tests._parity import oracle_state_to_gpu, state_image_to_oracle
+    X = small_data(seed=53, n=90, d=2)
+    init = np.array([5, 40, 70], np.int32)
+    o = O.Oracle(X, 3, 3, O.GAUSS, 1.2)
+    o.init_centers(init)
+    for i, B in enumerate(batches_for(90, 20, 6, seed=54), start=1):
+        o.step(B)
+        st = o.state()
+        back = state_image_to_oracle(oracle_state_to_gpu(st, init, 3, 3, 20), 3, 3)
+        assert back["iteration"] == st["iteration"]
+        for key in ("term_center", "term_tag", "term_coef", "term_npts", "points", "cum"):
+            np.testing.assert_array_equal(back[key], st[key])
