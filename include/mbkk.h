@@ -160,6 +160,22 @@ int mbkk_create(const mbkk_config *cfg, void *workspace_dev, size_t bytes, void 
 int mbkk_destroy(mbkk_ctx *ctx);
 const char *mbkk_last_error(const mbkk_ctx *ctx);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): mbkk_create without a
+ * workspace argument.  The context's device state lives in a static device
+ * array of the library, 64 MiB (67108864 bytes) per GPU, held
+ * from the library's first use on a GPU until the process ends; the host-side
+ * context is static too, and neither call allocates device or heap memory.
+ * The context works on the current device (stream must belong to it) and is
+ * used with every other entry point exactly like one from mbkk_create.
+ * Limits: one such context per device at a time (a second call before
+ * mbkk_destroy of the first returns MBKK_E_STATE); a configuration whose
+ * mbkk_workspace_size exceeds the array returns MBKK_E_WORKSPACE.  The array
+ * keeps the previous context's contents; creation clears what must start at
+ * fixed values, and everything else is written before it is read.  Work of
+ * two contexts that overlaps in time on one device would race on the array,
+ * which the one-context rule excludes. */
+int mbkk_create_static(const mbkk_config *cfg, void *stream, mbkk_ctx **out);
 
 /* Borrows X_dev (n x d FP32, row stride ld >= d elements, 16-byte aligned
  * rows when ld % 4 == 0) and caches ||x||^2 for every row.  X_dev must stay

@@ -22,7 +22,7 @@ EXPORTS = [
     "mbkk_init_centers", "mbkk_init_kmeanspp", "mbkk_step", "mbkk_assign", "mbkk_objective",
     "mbkk_get_state", "mbkk_set_state", "mbkk_center_norms", "mbkk_set_timing", "mbkk_get_timing",
     "mbkk_objective_fwd", "mbkk_objective_bwd", "mbkk_last_batch_objective", "mbkk_agreement",
-    "mbkk_rescore_count", "mbkk_selfnorm_error_bound",
+    "mbkk_rescore_count", "mbkk_selfnorm_error_bound", "mbkk_create_static",
 ]
 
 
@@ -84,6 +84,7 @@ def lib():
         L.mbkk_objective_bwd.argtypes = [P, P, I32, D, P, D, P, C.POINTER(D)]
         L.mbkk_rescore_count.argtypes = [P, C.POINTER(I64), I32]
         L.mbkk_selfnorm_error_bound.argtypes = [P, C.POINTER(D)]
+        L.mbkk_create_static.argtypes = [C.POINTER(Config), P, C.POINTER(P)]
         for name in EXPORTS:
             if name != "mbkk_last_error":
                 getattr(L, name).restype = C.c_int

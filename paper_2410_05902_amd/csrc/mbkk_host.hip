@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -34,6 +35,7 @@ struct mbkk_ctx {
     // iteration whose support segment offsets the last update wrote to seg_next
     int64_t seg_next_iter = -1;
     int32_t slot_b[kMaxSlots] = {};  // points held by each physical slot
+    int device = -1;                 // static workspace: the device whose array it uses (-1: none)
     // timing of the cross-term kernel
     bool timing = false;
     std::vector<hipEvent_t> ev;  // pairs (start, stop)
@@ -500,12 +502,93 @@ int mbkk_create(const mbkk_config *cfg, void *workspace, size_t bytes, void *str
     return MBKK_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Workspace in a static device array, for callers that cannot allocate.
+// ---------------------------------------------------------------------------
+// `scratch` is the device array.  In host code its name is only a stand-in
+// for the symbol: the device address of each GPU's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// only that address is ever handed to kernels.  One context at a time may
+// use a device's array; its host-side context is static as well, so that
+// mbkk_create_static allocates nothing on the device or the host heap.
+constexpr size_t kStaticWorkspaceBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+static std::mutex g_static_mu;
+static void *g_scratch_dev[kMaxDevices];  // device address of `scratch` per device (nullptr: not looked up)
+static bool g_static_busy[kMaxDevices];
+static mbkk_ctx g_static_ctx[kMaxDevices];
+
+int mbkk_create_static(const mbkk_config *cfg, void *stream, mbkk_ctx **out)
+{
+    std::string why;
+    int rc = check_config(cfg, why);
+    if (rc)
+        return fail(nullptr, rc, why);
+    if (!out)
+        return fail(nullptr, MBKK_E_INVALID, "out is NULL");
+    Layout L = make_layout(*cfg);
+    Buffers B;
+    carve(L, nullptr, B);
+    if (L.bytes > kStaticWorkspaceBytes)
+        return fail(nullptr, MBKK_E_WORKSPACE,
+                    "configuration needs " + std::to_string(L.bytes) + " bytes of workspace; the static array holds " +
+                        std::to_string(kStaticWorkspaceBytes));
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return fail(nullptr, MBKK_E_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(nullptr, MBKK_E_INVALID, "device ordinal beyond the static table");
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (g_static_busy[dev])
+        return fail(nullptr, MBKK_E_STATE, "the static workspace of this device is in use by another context");
+    if (!g_scratch_dev[dev]) {
+        // once per device, with that device current
+        void *ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(nullptr, MBKK_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = ptr;
+    }
+    mbkk_ctx *c = &g_static_ctx[dev];
+    c->data_set = false;
+    c->inited = false;
+    c->iter = 1;
+    c->support_iter = -1;
+    c->fold_rr = -1;
+    c->fold_mask = 0;
+    c->seg_next_iter = -1;
+    c->ymax2 = 0.0;
+    c->timing = false;
+    c->ev_used = 0;
+    c->ms_acc = 0.0;
+    c->launches = 0;
+    c->err.clear();
+    rc = setup(c, cfg, g_scratch_dev[dev], stream);
+    if (rc)
+        return rc;
+    c->device = dev;
+    g_static_busy[dev] = true;
+    *out = c;
+    return MBKK_OK;
+}
+
 int mbkk_destroy(mbkk_ctx *c)
 {
     if (!c)
         return MBKK_OK;
     for (hipEvent_t e : c->ev)
         (void)hipEventDestroy(e);
+    c->ev.clear();
+    if (c->device >= 0) {
+        // a context over a static array: the array and the context go back to the device
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        g_static_busy[c->device] = false;
+        c->device = -1;
+        return MBKK_OK;
+    }
     delete c;
     return MBKK_OK;
 }

@@ -32,12 +32,15 @@ class Model:
     of cross terms <phi(x), C_j> of every point (Appendix A).
 
     X: (n, d) float32 CUDA tensor, borrowed for the lifetime of the model.
+    static_workspace: keep the device state in the library's static array
+    (mbkk_create_static: no allocation; one such model per device at a time)
+    instead of a workspace tensor.
     """
 
     def __init__(self, X: torch.Tensor, k: int, b_max: int, window: int, kernel="gauss",
                  kernel_param: float = 1.0, precision="fp32", lr="beta", cross_impl="auto",
                  tie_delta: float = 0.0, validate: bool = True, stream: Optional[torch.cuda.Stream] = None,
-                 tau: int = 0):
+                 tau: int = 0, static_workspace: bool = False):
         if not (X.is_cuda and X.dtype == torch.float32 and X.dim() == 2 and X.stride(1) == 1):
             raise ValueError("X must be a row-major float32 CUDA tensor")
         self.X = X
@@ -54,12 +57,18 @@ class Model:
         self.workspace_bytes = int(nbytes.value)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         ctx = C.c_void_p()
-        raw = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
-        shift = (-raw.data_ptr()) % 256
-        self._raw = raw
-        self.workspace = raw[shift: shift + self.workspace_bytes]
-        L.check(lib.mbkk_create(C.byref(self.cfg), C.c_void_p(self.workspace.data_ptr()),
-                                self.workspace_bytes, C.c_void_p(self.stream.cuda_stream), C.byref(ctx)))
+        if static_workspace:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                L.check(lib.mbkk_create_static(C.byref(self.cfg), C.c_void_p(self.stream.cuda_stream),
+                                               C.byref(ctx)))
+        else:
+            raw = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+            shift = (-raw.data_ptr()) % 256
+            self._raw = raw
+            self.workspace = raw[shift: shift + self.workspace_bytes]
+            L.check(lib.mbkk_create(C.byref(self.cfg), C.c_void_p(self.workspace.data_ptr()),
+                                    self.workspace_bytes, C.c_void_p(self.stream.cuda_stream), C.byref(ctx)))
         self._ctx = ctx
         L.check(lib.mbkk_set_data(ctx, C.c_void_p(X.data_ptr()), X.stride(0)), ctx)
 
