@@ -116,50 +116,19 @@ def measured_traffic(wl: str, src: str = CROSS_SRC):
     return t["traffic_bytes_per_launch"] if sha == source_sha(src) else None
 
 
-def differentiation(args, wl, X, batches, u, make, window, nsteps):
-    """Times the differentiation form: forward (objective and assignment of a
-    batch of coordinates at bandwidth sigma) and backward (gradient with
-    respect to the coordinates and sigma at the forward's labels), against the
-    centers after window + 2 steps of the FP32 form.  Both calls return host
-    scalars, so each is timed whole (launches and the read-back included)."""
-    import torch
-    model = make("fp32")
-    model.init_kmeanspp(u)
-    for i in range(window + 2):
-        model.step_noout(batches[i % nsteps])
-    torch.cuda.synchronize()
-    live = live_support(model.get_state())
-    xs = [X[batches[(window + 2 + i) % nsteps].long()].contiguous() for i in range(4)]
-    sigma = float(wl.sigma)
-    for i in range(args.warmup):
-        _, lab = model.objective_fwd(xs[i % 4], sigma)
-        model.objective_bwd(xs[i % 4], sigma, lab)
-    torch.cuda.synchronize()
-    tf = tb = 0.0
-    for i in range(args.steps):
-        x = xs[i % 4]
-        t0 = time.perf_counter()
-        _, lab = model.objective_fwd(x, sigma)
-        t1 = time.perf_counter()
-        dX, ds = model.objective_bwd(x, sigma, lab)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        tf += t1 - t0
-        tb += t2 - t1
-    ms_f, ms_b = tf * 1e3 / args.steps, tb * 1e3 / args.steps
-    b = xs[0].shape[0]
-    log(f"[bench] differentiation form: forward {ms_f:.4f} ms, backward {ms_b:.4f} ms, "
-        f"b={b}, support {live} entries")
+def differentiation(args, dev):
+    """--differentiation: the differentiation form alone (diff_leg), as the
+    benchmark line."""
+    out = diff_leg(dev, args.steps, args.warmup, unit_rates(dev))
     print(json.dumps({
         "metric": "differentiation form: objective and gradient (coordinates, bandwidth) per batch",
-        "value": b / ((ms_f + ms_b) * 1e-3), "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_f + ms_b, "ms_forward": ms_f, "ms_backward": ms_b,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": wl.name + "_differentiation", "n": wl.n, "d": wl.d, "k": wl.k, "b": b,
-                   "window": window, "kernel": "gauss", "sigma": sigma, "support_entries": live,
-                   "parallelism": "single GPU"},
-        "roofline": None, "cpu_baseline": None}), flush=True)
+        "value": out["rows_per_s"], "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": out["ms_per_step"], "ms_forward": out["ms_forward"],
+        "ms_backward": out["ms_backward"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": out["workload"], "b": out["b"], "support_entries": out["support_entries"],
+                   "kernel": "gauss", "parallelism": "single GPU"},
+        "roofline": out["roofline"], "vs_fp64_oracle": out["vs_fp64_oracle"], "cpu_baseline": None}), flush=True)
 
 
 def live_support(st):
@@ -169,6 +138,253 @@ def live_support(st):
     for r in range(coef.shape[1] - 1):
         m += int((np.diff(off[r]) * (coef[:, 1 + r] != 0.0)).sum())
     return m
+
+
+def unit_rates(dev):
+    """Attainable rates on this GPU (mbkk_microbench), one probe each at the
+    occupancy the kernels run at: FP32 sub + add-|.| and FMA lane ops/s, exp2/s,
+    BF16 and FP32 MFMA flop/s."""
+    import ctypes as C
+    import torch
+    from paper_2410_05902_amd import _lib as L
+    sink = torch.zeros(256, dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    out = {}
+    for name, kind, iters, w in [("fp32_subadd_lane_ops", L.PROBE_SUBADD, 50000, 8),
+                                 ("fp32_fma_lane_ops", L.PROBE_FMA, 50000, 8),
+                                 ("exp2", L.PROBE_EXP2, 25000, 8),
+                                 ("bf16_mfma_flops", L.PROBE_MFMA_BF16, 50000, 2),
+                                 ("fp32_mfma_flops", L.PROBE_MFMA_F32, 20000, 1)]:
+        ms, ops = C.c_double(), C.c_double()
+        rc = L.lib().mbkk_microbench(kind, iters, w, C.c_void_p(stream), C.c_void_p(sink.data_ptr()),
+                                     C.byref(ms), C.byref(ops))
+        if rc != 0:
+            raise SystemExit(f"mbkk_microbench({name}) failed: {rc}")
+        out[name] = ops.value / (ms.value * 1e-3)
+    return out
+
+
+# FP32 add / subtract lane operations: 128 per CU per clock (the issue rate the
+# 157.3 TFLOP/s vector figure implies, an FMA counting 2), 256 CUs at 2.4 GHz
+VALU_ADD_PEAK = 256 * 128 * 2.4e9
+
+
+def steady_support(st):
+    """Support entries with a nonzero weight and the pair count of the centers'
+    quadratic forms (sum over centers of their entries squared), from a state."""
+    coef, off = st["coef"], st["slot_off"]
+    seg = (coef[:, 0] != 0.0).astype(np.int64)
+    for r in range(coef.shape[1] - 1):
+        seg = seg + np.diff(off[r]) * (coef[:, 1 + r] != 0.0)
+    return int(seg.sum()), int((seg * seg).sum()), int(seg.max())
+
+
+def oracle_check(wl, model, st, rows_idx, pair_budget=1.2e10, threads=16):
+    """The FP64 oracle on the GPU's state (every term of every center) against
+    the GPU's assignment of the same rows: largest distance error (gated metric
+    and floored relative error) and label agreement.  Skipped, with the reason,
+    when the oracle's self norms would cost more than pair_budget pair
+    evaluations times d."""
+    import torch
+    import oracle as O
+    from tests._parity import state_image_to_oracle
+    _, pairs, _ = steady_support(st)
+    if pairs * wl.d > pair_budget:
+        return {"skipped": f"the oracle's self norms need {pairs:.3e} pair evaluations of d = {wl.d}; "
+                           "every row of a full batch is compared in tests/test_gpu_fullsize.py"}
+    orc = O.Oracle(wl.X, wl.k, wl.window, wl.kernel, wl.kernel_param)
+    orc.set_state(state_image_to_oracle(st, wl.k, wl.window))
+    t0 = time.perf_counter()
+    ref = orc.distances(rows_idx, threads=threads)
+    a = model.assign(torch.from_numpy(rows_idx).to(model.device), want_D=True)
+    Dg = a["D"].cpu().numpy()
+    scale = 1.0 + ref["N"][None, :]
+    err = np.abs(Dg - ref["D"]) / np.maximum(np.abs(ref["D"]), scale)
+    errf = np.abs(Dg - ref["D"]) / np.maximum(np.abs(ref["D"]), 1e-3 * scale)
+    lab = a["labels"].cpu().numpy()
+    return {"rows": int(len(rows_idx)), "max_distance_error": float(err.max()),
+            "max_floored_relative_error": float(errf.max()),
+            "assignment_agreement": float((lab == ref["labels"]).mean()),
+            "error_metric": "|D - D64| / max(|D64|, K(x,x) + N_j); floored: max(|D64|, 1e-3 (K(x,x) + N_j))",
+            "oracle_s": time.perf_counter() - t0}
+
+
+def leg(name, precision, dev, steps, warmup, rates, oracle_rows=256):
+    """One truncated-form workload at full size: k-means++ seeding on the GPU,
+    warm-up to the steady state, `steps` timed iterations, the cross kernel's
+    average from HIP events over further iterations, its roofline, and the
+    FP64 oracle on sampled rows of the next batch."""
+    import torch
+    from paper_2410_05902_amd import Model, workloads as W
+    wl = W.make(name)
+    warmup = max(warmup, wl.window + 2)  # a full window of batches before timing
+    gauss = wl.kernel == W.GAUSS
+    X = torch.from_numpy(wl.X).to(dev)
+    model = Model(X, k=wl.k, b_max=wl.b, window=wl.window, kernel="gauss" if gauss else "laplace",
+                  kernel_param=wl.kernel_param, precision=precision, validate=False)
+    model.init_kmeanspp(wl.kmeanspp_uniforms())
+    nb = warmup + steps + 20
+    batches = torch.from_numpy(np.stack([wl.batch(i) for i in range(1, nb + 1)])).to(dev)
+    for i in range(warmup):
+        model.step_noout(batches[i])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(warmup, warmup + steps):
+        model.step_noout(batches[i])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    live = []
+    model.set_timing(True)
+    for i in range(warmup + steps, nb):
+        live.append(steady_support(model.get_state())[0])
+        model.step_noout(batches[i])
+    kms, launches = model.get_timing()
+    model.set_timing(False)
+    kms /= max(launches, 1)
+    M = float(np.mean(live))
+    evals = wl.b * M
+    st = model.get_state()
+    out = {"workload": wl.name, "precision": precision, "n": wl.n, "d": wl.d, "k": wl.k, "b": wl.b,
+           "window": wl.window, "kernel": "gauss" if gauss else "laplace", "support_entries": M,
+           "ms_per_step": ms, "iters_per_s": 1e3 / ms, "kernel_evals_per_s": evals / (ms * 1e-3),
+           "cross_kernel_ms": kms}
+    if gauss:
+        flops = 2.0 * wl.d * evals * (3 if precision == "bf16x3" else 1)
+        pk = PEAK["bf16"] if precision.startswith("bf16") else PEAK["f32"]
+        att = rates["bf16_mfma_flops"] if precision.startswith("bf16") else rates["fp32_mfma_flops"]
+        out["roofline"] = {"bound": "mfma", "achieved": flops / (kms * 1e-3) / 1e12, "peak": pk / 1e12,
+                           "unit": "TFLOP/s", "frac": flops / (kms * 1e-3) / pk,
+                           "frac_of_measured_unit_rate": flops / (kms * 1e-3) / att,
+                           "work": f"{'3 x ' if precision == 'bf16x3' else ''}2 d b M flops per launch, "
+                                   f"b M = {wl.b} x {M:.0f} kernel evaluations"}
+    else:
+        ops = 2.0 * wl.d * evals
+        out["roofline"] = {"bound": "alu", "achieved": ops / (kms * 1e-3) / 1e12, "peak": VALU_ADD_PEAK / 1e12,
+                           "unit": "T lane-ops/s", "frac": ops / (kms * 1e-3) / VALU_ADD_PEAK,
+                           "frac_of_measured_unit_rate": ops / (kms * 1e-3) / rates["fp32_subadd_lane_ops"],
+                           "work": f"2 d b M FP32 lane operations (subtract, add |.|) per launch, "
+                                   f"b M = {wl.b} x {M:.0f}"}
+        algo_bytes = (wl.b + M) * wl.d * 4.0
+        out["algorithmic_hbm_GBps"] = algo_bytes / (kms * 1e-3) / 1e9
+        traffic = measured_traffic(name)
+        if traffic:
+            out["hbm_GBps"] = traffic / (kms * 1e-3) / 1e9
+            out["hbm_frac"] = traffic / (kms * 1e-3) / HBM_PEAK
+    rng = np.random.default_rng(80)
+    rows = wl.batch(nb + 1)[np.sort(rng.choice(wl.b, oracle_rows, replace=False))]
+    out["vs_fp64_oracle"] = oracle_check(wl, model, st, rows)
+    log(f"[bench] {name} {precision}: {ms:.4f} ms/step, cross kernel {kms:.4f} ms, "
+        f"frac {out['roofline']['frac']:.3f}, oracle {out['vs_fp64_oracle']}")
+    return out
+
+
+def diff_leg(dev, steps, warmup, rates):
+    """The differentiation form at full size (the 64-D mixture): forward
+    (objective and assignment at the bandwidth) and backward (gradient with
+    respect to the coordinates and the bandwidth) of one batch of
+    coordinates, against the centers after a full window; the roofline of the
+    forward's cross kernel; the oracle's objective and gradient on the same
+    centers."""
+    import torch
+    import oracle as O
+    from paper_2410_05902_amd import Model, workloads as W
+    from tests._parity import state_image_to_oracle
+    wl = W.make("c4")
+    X = torch.from_numpy(wl.X).to(dev)
+    model = Model(X, k=wl.k, b_max=wl.b, window=wl.window, kernel="gauss", kernel_param=wl.kernel_param,
+                  precision="fp32", validate=False)
+    model.init_kmeanspp(wl.kmeanspp_uniforms())
+    for i in range(1, wl.window + 3):
+        model.step_noout(torch.from_numpy(wl.batch(i)).to(dev))
+    st = model.get_state()
+    M, _, _ = steady_support(st)
+    xs = [X[torch.from_numpy(wl.batch(wl.window + 3 + i)).to(dev).long()].contiguous() for i in range(4)]
+    sigma = float(wl.sigma)
+    for i in range(warmup):
+        _, lab = model.objective_fwd(xs[i % 4], sigma)
+        model.objective_bwd(xs[i % 4], sigma, lab)
+    torch.cuda.synchronize()
+    tf = tb = 0.0
+    for i in range(steps):
+        x = xs[i % 4]
+        t0 = time.perf_counter()
+        _, lab = model.objective_fwd(x, sigma)
+        t1 = time.perf_counter()
+        model.objective_bwd(x, sigma, lab)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tf += t1 - t0
+        tb += t2 - t1
+    ms_f, ms_b = tf * 1e3 / steps, tb * 1e3 / steps
+    model.set_timing(True)
+    for i in range(10):
+        model.objective_fwd(xs[i % 4], sigma)
+    kms, launches = model.get_timing()
+    model.set_timing(False)
+    kms /= max(launches, 1)
+    b = wl.b
+    flops = 2.0 * wl.d * b * M
+    out = {"workload": wl.name + "_differentiation", "precision": "fp32", "b": b, "support_entries": M,
+           "ms_forward": ms_f, "ms_backward": ms_b, "ms_per_step": ms_f + ms_b,
+           "rows_per_s": b / ((ms_f + ms_b) * 1e-3), "forward_cross_kernel_ms": kms,
+           "roofline": {"bound": "mfma", "kernel": "forward cross term k_cross_bs<fp32>",
+                        "achieved": flops / (kms * 1e-3) / 1e12, "peak": PEAK["f32"] / 1e12, "unit": "TFLOP/s",
+                        "frac": flops / (kms * 1e-3) / PEAK["f32"],
+                        "frac_of_measured_unit_rate": flops / (kms * 1e-3) / rates["fp32_mfma_flops"],
+                        "work": f"2 d b M flops per launch, b M = {b} x {M}"}}
+    # the oracle on the same centers, the first batch of coordinates
+    orc = O.Oracle(wl.X, wl.k, wl.window, O.GAUSS, wl.kernel_param)
+    orc.set_state(state_image_to_oracle(st, wl.k, wl.window))
+    x64 = xs[0].cpu().numpy().astype(np.float64)
+    f, lab = model.objective_fwd(xs[0], sigma)
+    fo, labo = orc.fobj_coords(x64, sigma)
+    dXo, dso = orc.fobj_grad(x64, sigma, labo)
+    dX, ds = model.objective_bwd(xs[0], sigma, torch.from_numpy(labo).to(dev))
+    dX = dX.cpu().numpy().astype(np.float64)
+    out["vs_fp64_oracle"] = {"rows": b, "objective_rel_error": abs(f - fo) / abs(fo),
+                             "assignment_agreement": float((lab.cpu().numpy() == labo).mean()),
+                             "dX_error_rel_to_max": float(np.abs(dX - dXo).max() / np.abs(dXo).max()),
+                             "dsigma_rel_error": abs(ds - dso) / abs(dso)}
+    log(f"[bench] differentiation: forward {ms_f:.4f} ms, backward {ms_b:.4f} ms, cross {kms:.4f} ms; "
+        f"oracle {out['vs_fp64_oracle']}")
+    return out
+
+
+def oracle_steps(wl, model, batch_next, nsteps=3):
+    """The oracle as it stands, on one core: `nsteps` steady-state iterations
+    (assignment of every row of a full batch, then the update) resumed from
+    the GPU's final state, each timed; the first one's distances and labels
+    are set beside the GPU's assignment of the same batch on the same state."""
+    import torch
+    import oracle as O
+    from tests._parity import state_image_to_oracle
+    st = model.get_state()
+    M, pairs, _ = steady_support(st)
+    orc = O.Oracle(wl.X, wl.k, wl.window, wl.kernel, wl.kernel_param)
+    orc.set_state(state_image_to_oracle(st, wl.k, wl.window))
+    a = model.assign(torch.from_numpy(batch_next[0]).to(model.device), want_D=True)
+    times, first = [], None
+    for i in range(nsteps):
+        t0 = time.perf_counter()
+        r = orc.step(batch_next[i], threads=1)
+        times.append(time.perf_counter() - t0)
+        if first is None:
+            first = r
+    t = float(np.median(times))
+    Dg = a["D"].cpu().numpy()
+    scale = 1.0 + first["N"][None, :]
+    err = np.abs(Dg - first["D"]) / np.maximum(np.abs(first["D"]), scale)
+    errf = np.abs(Dg - first["D"]) / np.maximum(np.abs(first["D"]), 1e-3 * scale)
+    lab = a["labels"].cpu().numpy()
+    cpu = {"value": wl.b * M / t, "unit": "kernel evals/s", "cores": 1, "nproc": os.cpu_count(),
+           "kind": "oracle", "ms_per_step": t * 1e3, "iters_per_s": 1.0 / t,
+           "sample": (f"{nsteps} steady-state iterations of the oracle (assignment of all {wl.b} rows against "
+                      f"{M} support entries, self norms over {pairs} pairs, and the update), resumed from the "
+                      f"GPU's final state, FP64, 1 thread; median of {[round(x, 2) for x in times]} s")}
+    vs = {"rows": wl.b, "max_distance_error": float(err.max()), "max_floored_relative_error": float(errf.max()),
+          "assignment_agreement": float((lab == first["labels"]).mean()),
+          "error_metric": "|D - D64| / max(|D64|, K(x,x) + N_j); floored: max(|D64|, 1e-3 (K(x,x) + N_j))"}
+    return cpu, vs
 
 
 def main():
@@ -195,6 +411,12 @@ def main():
                     help="time the differentiation form (objective and gradient) on the 64-D mixture")
     ap.add_argument("--untruncated", action="store_true",
                     help="run the workload untruncated (window 0) on the table of cross terms")
+    ap.add_argument("--microbench", action="store_true",
+                    help="only measure the attainable VALU (sub/add, FMA), exp2 and MFMA rates")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the other workloads (784-D sparse prototypes, differentiation form, L1 mixture)")
+    ap.add_argument("--oracle-steps", type=int, default=3,
+                    help="steady-state oracle iterations timed for the CPU baseline")
     args = ap.parse_args()
     if args.traffic_summary:
         traffic_summary(args)
@@ -212,6 +434,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
 
+    if args.microbench:
+        microbench(dev)
+        return
+
     if args.copy_calibration:
         # a plain copy of known size: each launch reads and writes MIB MiB
         nel = args.copy_calibration * (1 << 20) // 4
@@ -223,8 +449,9 @@ def main():
         print(json.dumps({"copy_calibration_mib": args.copy_calibration, "launches": 5}), flush=True)
         return
 
-    if args.differentiation and args.workload == "c3":
-        args.workload = "c4"  # the workload the differentiation form is specified on
+    if args.differentiation:
+        differentiation(args, dev)
+        return
     t0 = time.time()
     wl = W.make(args.workload)
     log(f"[bench] workload {wl.name}: n={wl.n} d={wl.d} k={wl.k} b={wl.b} W={wl.window} "
@@ -243,12 +470,6 @@ def main():
         return Model(X, k=wl.k, b_max=wl.b, window=window,
                      kernel="gauss" if gauss else "laplace", kernel_param=wl.kernel_param,
                      precision=prec, validate=False, lr=args.lr, tau=args.tau)
-
-    if args.differentiation:
-        if not gauss or untrunc:
-            raise SystemExit("the differentiation form takes a Gaussian workload in the windowed form")
-        differentiation(args, wl, X, batches, u, make, window, nsteps)
-        return
 
     active = []  # untruncated form: centers with batch points in each kernel-timed step
     live = []    # truncated form: support entries with a nonzero weight in each kernel-timed step
@@ -387,65 +608,58 @@ def main():
 
     out["roofline"] = roof
 
-    # ---- CPU baseline: the FP64 oracle, one core, a bounded sample ----------
-    # Truncated form: the oracle takes the GPU's own final state (every term of
-    # every center, from mbkk_get_state) and scores a sample of the next
-    # batch; the same rows are scored on the GPU, which gives the GPU path's
-    # distance error and assignment agreement against FP64 at the benchmark
-    # state.  The untruncated form has no state image: a steady-state support
-    # of W generator batches stands in for the timing.
-    if not args.no_cpu_baseline:
+    # ---- CPU baseline: the FP64 oracle on one core ------------------------
+    # Truncated form: the oracle resumes from the GPU's own final state (every
+    # term of every center, from mbkk_get_state) and runs steady-state
+    # iterations on the next batches; the first one's distances are set beside
+    # the GPU's assignment of the same batch on the same state (the GPU path's
+    # distance error and assignment agreement against FP64).
+    rates = unit_rates(dev)
+    out["unit_rates_measured"] = rates
+    if "frac" in roof and roof.get("bound") == "mfma":
+        roof["frac_of_measured_unit_rate"] = roof["frac"] * roof["peak"] * 1e12 / (
+            rates["bf16_mfma_flops"] if precision.startswith("bf16") else rates["fp32_mfma_flops"])
+    elif roof.get("bound") == "alu":
+        roof["frac_of_measured_unit_rate"] = roof["achieved"] * 1e12 / rates["fp32_subadd_lane_ops"]
+    if not args.no_cpu_baseline and not untrunc:
+        nb_next = np.stack([wl.batch(nsteps + 1 + i) for i in range(max(1, args.oracle_steps))])
+        tc = time.perf_counter()
+        out["cpu_baseline"], out["vs_fp64_oracle"] = oracle_steps(wl, model, nb_next, max(1, args.oracle_steps))
+        log(f"[bench] cpu oracle: {out['cpu_baseline']['value']:.4e} evals/s, "
+            f"{out['cpu_baseline']['ms_per_step']:.0f} ms/step ({time.perf_counter() - tc:.1f}s); "
+            f"vs FP64 oracle: {out['vs_fp64_oracle']}")
+    elif not args.no_cpu_baseline:
+        # the untruncated form has no state image: a steady-state support of W
+        # generator batches stands in for the oracle's timing
         import oracle as O
         rows = min(args.cpu_rows, wl.b)
         orc = O.Oracle(wl.X, wl.k, wl.window, wl.kernel, wl.kernel_param)
         sample = wl.batch(nsteps + 1)[:rows]
-        if not untrunc:
-            st = model.get_state()
-            coef, off, sidx = st["coef"], st["slot_off"], st["slot_idx"]
-            cen, pts, wts = [], [], []
-            j0 = np.flatnonzero(coef[:, 0] != 0.0)
-            cen.append(j0)
-            pts.append(st["init_idx"][j0])
-            wts.append(coef[j0, 0])
-            for r in range(wl.window):
-                cnt = np.diff(off[r])
-                cj = np.repeat(np.arange(wl.k), cnt)
-                keep = coef[cj, 1 + r] != 0.0
-                cen.append(cj[keep])
-                pts.append(sidx[r, : off[r][-1]][keep])
-                wts.append(coef[cj[keep], 1 + r])
-            cen, pts, wts = np.concatenate(cen), np.concatenate(pts), np.concatenate(wts)
-            orc.set_centers(cen, pts, wts)
-            what = "the GPU's final state"
-        else:
-            comp = wl.comp % wl.k
-            pts = np.concatenate([wl.batch(i) for i in range(1, wl.window + 1)])
-            cen = comp[pts]
-            cnt = np.bincount(cen, minlength=wl.k).astype(np.float64)
-            orc.set_centers(cen, pts, 1.0 / cnt[cen])
-            what = f"a steady-state support of W={wl.window} generator batches"
+        comp = wl.comp % wl.k
+        pts = np.concatenate([wl.batch(i) for i in range(1, wl.window + 1)])
+        cen = comp[pts]
+        cnt = np.bincount(cen, minlength=wl.k).astype(np.float64)
+        orc.set_centers(cen, pts, 1.0 / cnt[cen])
         tc = time.perf_counter()
-        ref = orc.distances(sample, threads=1, want_D=not untrunc)
+        orc.distances(sample, threads=1, want_D=False)
         tcpu = time.perf_counter() - tc
         cpu_evals = rows * len(pts)
         out["cpu_baseline"] = {"value": cpu_evals / tcpu, "unit": "kernel evals/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": (f"one assignment pass (center norms + distances) of {rows} rows of the "
-                                          f"next batch against {what} ({len(pts)} support points, k={wl.k}), "
-                                          f"FP64, 1 thread, {tcpu:.1f}s")}
+                               "nproc": os.cpu_count(), "kind": "oracle",
+                               "sample": (f"one assignment pass (center norms + distances) of {rows} rows against "
+                                          f"a steady-state support of W={wl.window} generator batches "
+                                          f"({len(pts)} support points, k={wl.k}), FP64, 1 thread, {tcpu:.1f}s")}
         log(f"[bench] cpu oracle: {cpu_evals / tcpu:.4e} evals/s ({tcpu:.1f}s)")
-        if not untrunc:
-            a = model.assign(torch.from_numpy(sample).to(dev), want_D=True)
-            Dg = a["D"].cpu().numpy()
-            N = ref["N"]
-            scale = 1.0 + N[None, :]  # K(x, x) = 1 for the Gaussian and Laplacian kernels
-            err = np.abs(Dg - ref["D"]) / np.maximum(np.abs(ref["D"]), scale)
-            lab = a["labels"].cpu().numpy()
-            out["vs_fp64_oracle"] = {"rows": rows, "max_distance_error": float(err.max()),
-                                     "assignment_agreement": float((lab == ref["labels"]).mean()),
-                                     "error_metric": "|D - D64| / max(|D64|, K(x,x) + N_j)"}
-            log(f"[bench] vs FP64 oracle: max distance error {err.max():.3e}, agreement "
-                f"{(lab == ref['labels']).mean():.6f}")
+
+    # ---- the other workloads, each at full size in its own form ----------
+    if not args.no_legs and not untrunc and args.workload == "c3":
+        legs = {}
+        lsteps, lwarm = max(10, args.steps // 2), max(args.warmup, 6)
+        for name, prec in (("c2", "fp32"), ("c5", "fp32")):
+            legs[f"{name}_{prec}"] = leg(name, prec, dev, lsteps, lwarm, rates)
+            torch.cuda.empty_cache()
+        legs["c4_differentiation"] = diff_leg(dev, lsteps, 3, rates)
+        out["workloads"] = legs
 
     print(json.dumps(out), flush=True)
 

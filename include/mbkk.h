@@ -287,9 +287,11 @@ int mbkk_center_norms(mbkk_ctx *ctx, double *N_host);
 int mbkk_rescore_count(mbkk_ctx *ctx, int64_t *rows_host, int32_t reset);
 int mbkk_selfnorm_error_bound(mbkk_ctx *ctx, double *bound_host);
 
-/* Accumulated device time of the cross-term kernel (the dominant kernel) in
- * milliseconds and the number of launches since the last reset, measured
- * with HIP events on the context's stream when timing is enabled. */
+/* Accumulated device time of the cross-term kernel (the dominant kernel of
+ * mbkk_step, mbkk_assign, mbkk_objective and mbkk_objective_fwd; for window 0
+ * the table update) in milliseconds and the number of launches since the last
+ * reset, measured with HIP events on the context's stream when timing is
+ * enabled. */
 int mbkk_set_timing(mbkk_ctx *ctx, int32_t enable);
 int mbkk_get_timing(mbkk_ctx *ctx, double *ms_host, int64_t *launches_host);
 

@@ -23,7 +23,9 @@ EXPORTS = [
     "mbkk_get_state", "mbkk_set_state", "mbkk_center_norms", "mbkk_set_timing", "mbkk_get_timing",
     "mbkk_objective_fwd", "mbkk_objective_bwd", "mbkk_last_batch_objective", "mbkk_agreement",
     "mbkk_rescore_count", "mbkk_selfnorm_error_bound", "mbkk_create_static",
+    "mbkk_microbench",  # include/mbkk_microbench.h
 ]
+PROBE_SUBADD, PROBE_FMA, PROBE_EXP2, PROBE_MFMA_BF16, PROBE_MFMA_F32 = 0, 1, 2, 3, 4
 
 
 class MbkkError(RuntimeError):
@@ -85,6 +87,7 @@ def lib():
         L.mbkk_rescore_count.argtypes = [P, C.POINTER(I64), I32]
         L.mbkk_selfnorm_error_bound.argtypes = [P, C.POINTER(D)]
         L.mbkk_create_static.argtypes = [C.POINTER(Config), P, C.POINTER(P)]
+        L.mbkk_microbench.argtypes = [I32, I64, I32, P, P, C.POINTER(D), C.POINTER(D)]
         for name in EXPORTS:
             if name != "mbkk_last_error":
                 getattr(L, name).restype = C.c_int

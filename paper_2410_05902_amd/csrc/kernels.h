@@ -65,6 +65,14 @@ void launch_selfnorm_sigma(const Layout &L, const Buffers &B, double sigma, doub
 void launch_grad_rows(const Layout &L, const Buffers &B, const float *xb, int b, double sigma, const int32_t *labels,
                       double g, const double *dN, float *dX, double *rowds, double *out, hipStream_t st);
 int grad_max_dim();
+// The same on FP32 MFMA for the MFMA layouts (padded segments, row stride
+// 32, 64, 96 or 128): self norms and their derivative at s (task plan, work,
+// fold), and the backward (grouping of the rows by label, per-group tiles,
+// dsigma sum).  sigma_mfma_ok: whether the layout admits them.
+bool sigma_mfma_ok(const Layout &L);
+void launch_sigma_norms(const Layout &L, const Buffers &B, double sigma, double *N, double *dN, hipStream_t st);
+void launch_grad_mfma(const Layout &L, const Buffers &B, int b, double sigma, const int32_t *labels, double g,
+                      const double *dN, float *dX, double *rowds, double *out, hipStream_t st);
 
 // Untruncated form on the table of cross terms (window 0).  init: N and the
 // table of the initial centers (pool rows 0..k-1).  score: distances of rows

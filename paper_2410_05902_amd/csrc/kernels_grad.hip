@@ -6,8 +6,10 @@
 //   df/dx   = (2 / (b s^2)) sum_e w_e K_s(x, y_e) (x - y_e)
 //   df/ds   = (1/b) sum_x [-2 sum_e w_e K_s(x, y_e) ||x - y_e||^2 / s^3 + dN_j/ds]
 //   dN_j/ds = sum_{e, e'} w_e w_e' K_s(y_e, y_e') ||y_e - y_e'||^2 / s^3.
-// Kernel values are recomputed here (nothing of size b x M is stored); the
-// arithmetic is FP64 throughout.
+// Kernel values are recomputed here (nothing of size b x M is stored).  The
+// Gaussian MFMA forms (FP32 / BF16 contexts) take the MFMA kernels below the
+// VALU ones: FP32 products and kernel values, FP64 sums; the FP64 form (and
+// layouts without the MFMA padding) take the VALU kernels, in FP64.
 #include "dev_common.h"
 #include "kernels.h"
 
@@ -259,6 +261,449 @@ __global__ __launch_bounds__(1024) void k_sum_rows(const double *v, int n, doubl
     }
     if (tid == 0)
         *out = r[0];
+}
+
+// ===========================================================================
+// The same quantities on FP32 MFMA (Gaussian MFMA forms, row stride <= 128):
+// kernel tiles are recomputed from x.y products, as the forward's cross term
+// is; sums that leave a tile are FP64.  The support layout is the MFMA one
+// (every center's segment padded to a multiple of 32 with weight-0 entries of
+// the zero row), so tiles need no masks on the support side.
+//
+// 32 x 32 tiles on v_mfma_f32_32x32x2f32: lane l = 32 h + n supplies
+// A[n][h] and B[h][n] of a k-step, and holds C[m][n] for
+// m = 8 (i/4) + 4 h + i%4, i < 16.
+// ===========================================================================
+
+// Self norms at s: task (j, a, e) is the 32 x 32 block of entries a and e of
+// center j (all ordered block pairs: nb_j^2 tasks, offsets toff); kGramWaves
+// waves take equal contiguous task ranges and store one FP64 partial per
+// (wave, center) run at part[w + j] (N) and part2[w + j] (the d2-weighted
+// sum); the fold adds them in wave order (gram_fold_jc), as the Gram blocks.
+struct SigmaGramArgs {
+    int k, dp;
+    const int32_t *seg_off, *sup_row, *toff;
+    const double *sup_w64;
+    const float *pool32, *poolsq;
+    float c;             // -log2(e) / (2 s^2)
+    double inv_s3;
+    double *part, *part2;
+    double *N, *dN;
+};
+
+__global__ __launch_bounds__(1024) void k_sigma_plan(int k, const int32_t *__restrict__ seg_off,
+                                                    int32_t *__restrict__ toff)
+{
+    __shared__ int sint[16];
+    const int tid = threadIdx.x, per = (k + 1023) / 1024;
+    const int j0 = min(k, tid * per), j1 = min(k, j0 + per);
+    int local = 0;
+    for (int j = j0; j < j1; ++j) {
+        const int nb = (seg_off[j + 1] - seg_off[j]) / 32;
+        local += nb * nb;
+    }
+    int total;
+    int run = block_exclusive_scan(local, sint, &total);
+    for (int j = j0; j < j1; ++j) {
+        toff[j] = run;
+        const int nb = (seg_off[j + 1] - seg_off[j]) / 32;
+        run += nb * nb;
+    }
+    if (tid == 0)
+        toff[k] = total;
+}
+
+template <int DP>
+__global__ __launch_bounds__(256) void k_sigma_gram(const SigmaGramArgs A)
+{
+    __shared__ float sqa[4][32];
+    __shared__ double wa[4][32];
+    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
+    const int w = blockIdx.x * 4 + wl;
+    const int T = A.toff[A.k];
+    if (T == 0)
+        return;
+    const int chunk = (T + kGramWaves - 1) / kGramWaves;
+    const int64_t t0l = (int64_t)w * chunk;
+    if (t0l >= T)
+        return;  // wave uniform
+    const int t0 = (int)t0l, t1 = min(T, t0 + chunk);
+    constexpr int KS = DP / 2;
+    int j = wave_segment_of(A.toff, A.k, t0);
+    int t = t0;
+    while (t < t1) {  // wave uniform
+        const int g0 = A.toff[j], g1 = A.toff[j + 1];
+        const int e = min(t1, g1);
+        if (t < e) {
+            const int s0 = A.seg_off[j], nb = (A.seg_off[j + 1] - s0) / 32;
+            double ln = 0.0, ld = 0.0;
+            for (; t < e; ++t) {
+                const int u = t - g0, ab = u / nb, eb = u - ab * nb;
+                const int sa = s0 + 32 * ab + n, se = s0 + 32 * eb + n;
+                const int64_t ra = A.sup_row[sa], re = A.sup_row[se];
+                if (h == 0) {
+                    sqa[wl][n] = A.poolsq[ra];
+                    wa[wl][n] = A.sup_w64[sa];
+                }
+                const float sqe = A.poolsq[re];
+                const double we = A.sup_w64[se];
+                f32x16 acc;
+#pragma unroll
+                for (int i = 0; i < 16; ++i)
+                    acc[i] = 0.0f;
+                const float *pa = A.pool32 + ra * DP + h * KS, *pe = A.pool32 + re * DP + h * KS;
+#pragma unroll
+                for (int s4 = 0; s4 < KS; s4 += 4) {
+                    const f32x4 av = *(const f32x4 *)(pa + s4), ev = *(const f32x4 *)(pe + s4);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], ev[q], acc, 0, 0, 0);
+                }
+                __builtin_amdgcn_wave_barrier();  // sqa / wa of this task were written by this wave
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int m = 8 * (i >> 2) + 4 * h + (i & 3);
+                    const float d2 = fmaxf(fmaf(-2.0f, acc[i], sqa[wl][m] + sqe), 0.0f);
+                    const double pk = wa[wl][m] * we * (double)__builtin_amdgcn_exp2f(A.c * d2);
+                    ln += pk;
+                    ld = fma(pk, (double)d2, ld);
+                }
+                __builtin_amdgcn_wave_barrier();  // before the next task's sqa / wa
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                ln += __shfl_xor(ln, o);
+                ld += __shfl_xor(ld, o);
+            }
+            if (lane == 0) {
+                A.part[w + j] = ln;
+                A.part2[w + j] = ld;
+            }
+        }
+        ++j;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_sigma_fold(const SigmaGramArgs A)
+{
+    const int lane = threadIdx.x & 63;
+    const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= A.k)
+        return;
+    const double sn = gram_fold_jc(A.toff, A.part, A.k, j);
+    const double sd = gram_fold_jc(A.toff, A.part2, A.k, j);
+    if (lane == 0) {
+        A.N[j] = sn;
+        A.dN[j] = sd * A.inv_s3;
+    }
+}
+
+bool sigma_mfma_ok(const Layout &L)
+{
+    if (L.pad != kMfmaPad || !(L.dp == 32 || L.dp == 64 || L.dp == 96 || L.dp == 128))
+        return false;
+    const double nb = (double)L.Mcap / 32.0;  // at most this many blocks in one center
+    return nb * nb < 2147483647.0;
+}
+
+void launch_sigma_norms(const Layout &L, const Buffers &B, double sigma, double *N, double *dN, hipStream_t st)
+{
+    SigmaGramArgs A;
+    A.k = L.k;
+    A.dp = L.dp;
+    A.seg_off = B.seg_off;
+    A.sup_row = B.sup_row;
+    A.toff = B.sg_toff;
+    A.sup_w64 = B.sup_w64;
+    A.pool32 = B.pool32;
+    A.poolsq = B.poolsq;
+    A.c = (float)(-1.4426950408889634 / (2.0 * sigma * sigma));
+    A.inv_s3 = 1.0 / (sigma * sigma * sigma);
+    A.part = B.sg_part;
+    A.part2 = B.sg_part + kGramWaves + L.k;
+    A.N = N;
+    A.dN = dN;
+    hipLaunchKernelGGL(k_sigma_plan, dim3(1), dim3(1024), 0, st, L.k, (const int32_t *)B.seg_off, B.sg_toff);
+    const dim3 grid(kGramWaves / 4);
+    switch (L.dp) {
+    case 32: hipLaunchKernelGGL(k_sigma_gram<32>, grid, dim3(256), 0, st, A); break;
+    case 64: hipLaunchKernelGGL(k_sigma_gram<64>, grid, dim3(256), 0, st, A); break;
+    case 96: hipLaunchKernelGGL(k_sigma_gram<96>, grid, dim3(256), 0, st, A); break;
+    default: hipLaunchKernelGGL(k_sigma_gram<128>, grid, dim3(256), 0, st, A); break;
+    }
+    hipLaunchKernelGGL(k_sigma_fold, dim3((unsigned)((L.k + 3) / 4)), dim3(256), 0, st, A);
+}
+
+// ---------------------------------------------------------------------------
+// Backward on MFMA.  The rows are grouped by label (k_group_labels: counts,
+// offsets, a scatter; the order inside a group is immaterial, since every
+// row's result depends on its own row only), and task (j, r) takes rows
+// 32 r .. 32 r + 31 of center j's group against the whole support of j:
+//   per 32-entry block of the support (the block's owner among 4 waves):
+//     T   = X Y^T on MFMA, d2 = |x|^2 + |y|^2 - 2 T, P = w K(d2), Q = P d2,
+//     R  += P 1, S += Q 1  (row sums, FP64),
+//     G  += P Y            (32 x dp on MFMA, P through LDS into the A layout);
+//   then, summed over the 4 waves in order,
+//     dX  = (2 g / (b s^2)) (x R - G),
+//     row term of df/ds = (g / b) (-2 S / s^3 + dN_j).
+// ---------------------------------------------------------------------------
+struct GroupArgs {
+    int b, k, d;
+    const int32_t *labels;
+    int32_t *cnt, *cur;   // [k] counts and scatter cursors (cleared here)
+    int32_t *loff;        // [k+1] row offsets of the groups
+    int32_t *rtoff;       // [k+1] offsets of the 32-row tasks
+    int32_t *perm;        // [b] rows grouped by label
+    float *dX;            // rows with a bad label: zeroed
+    double *rowds;
+    int32_t *flags;       // flags[2]: a label outside [0, k)
+};
+
+// One workgroup: every phase is separated by a barrier, and the counters are
+// read back with atomic loads (they are updated with device atomics).
+__global__ __launch_bounds__(1024) void k_group_labels(const GroupArgs A)
+{
+    __shared__ int sint[16];
+    const int tid = threadIdx.x;
+    for (int j = tid; j < A.k; j += 1024) {
+        A.cnt[j] = 0;
+        A.cur[j] = 0;
+    }
+    __threadfence();
+    __syncthreads();
+    for (int r = tid; r < A.b; r += 1024) {
+        const int j = A.labels[r];
+        if (j >= 0 && j < A.k) {
+            atomicAdd(&A.cnt[j], 1);
+        } else {
+            atomicOr(&A.flags[2], 1);
+            A.rowds[r] = 0.0;
+            for (int t = 0; t < A.d; ++t)
+                A.dX[(int64_t)r * A.d + t] = 0.0f;
+        }
+    }
+    __threadfence();
+    __syncthreads();
+    const int per = (A.k + 1023) / 1024;
+    const int j0 = min(A.k, tid * per), j1 = min(A.k, j0 + per);
+    int lrow = 0, ltask = 0;
+    for (int j = j0; j < j1; ++j) {
+        const int c = __hip_atomic_load(&A.cnt[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        lrow += c;
+        ltask += (c + 31) / 32;
+    }
+    int trow, ttask;
+    int rrun = block_exclusive_scan(lrow, sint, &trow);
+    int trun = block_exclusive_scan(ltask, sint, &ttask);
+    for (int j = j0; j < j1; ++j) {
+        const int c = __hip_atomic_load(&A.cnt[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        A.loff[j] = rrun;
+        A.rtoff[j] = trun;
+        rrun += c;
+        trun += (c + 31) / 32;
+    }
+    if (tid == 0) {
+        A.loff[A.k] = trow;
+        A.rtoff[A.k] = ttask;
+    }
+    __threadfence();
+    __syncthreads();
+    for (int r = tid; r < A.b; r += 1024) {
+        const int j = A.labels[r];
+        if (j >= 0 && j < A.k) {
+            const int pos = __hip_atomic_load(&A.loff[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
+                            atomicAdd(&A.cur[j], 1);
+            A.perm[pos] = r;
+        }
+    }
+}
+
+struct GradMfmaArgs {
+    int b, d, k;
+    const int32_t *loff, *rtoff, *perm, *labels;
+    const int32_t *seg_off, *sup_row;
+    const float *sup_w;
+    const float *pool32, *poolsq;
+    const float *bat32, *batsq;  // the coordinates, gathered with row stride DP
+    int64_t zero_row;            // pool row of zeros (rows past a group's end)
+    const double *dN;
+    float c;                     // -log2(e) / (2 s^2)
+    double inv_s3, cx, cs;       // cx = 2 g / (b s^2), cs = g / b
+    float *dX;
+    double *rowds;
+};
+
+template <int DP>
+__global__ __launch_bounds__(256) void k_grad_mfma(const GradMfmaArgs A)
+{
+    constexpr int KS = DP / 2, NT = DP / 32;
+    __shared__ float Pl[4][32][33], Ql[4][32][33];
+    __shared__ float Gp[32][DP + 1];
+    __shared__ double Rp[4][32], Sp[4][32];
+    __shared__ float xsq[32];
+    __shared__ int rows[32];
+    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
+    const int task = blockIdx.x;
+    if (task >= A.rtoff[A.k])
+        return;  // block uniform
+    const int j = wave_segment_of(A.rtoff, A.k, task);
+    const int r0 = A.loff[j] + 32 * (task - A.rtoff[j]);
+    const int nr = min(32, A.loff[j + 1] - r0);
+    if (threadIdx.x < 32) {
+        const int row = threadIdx.x < nr ? A.perm[r0 + threadIdx.x] : -1;
+        rows[threadIdx.x] = row;
+        xsq[threadIdx.x] = row >= 0 ? A.batsq[row] : 0.0f;
+    }
+    __syncthreads();
+    // this lane's A fragments: row n of the task, coordinates [h KS, (h+1) KS)
+    const int myrow = rows[n];
+    const float *px = myrow >= 0 ? A.bat32 + (int64_t)myrow * DP + h * KS : A.pool32 + A.zero_row * DP + h * KS;
+    f32x4 xf[KS / 4];
+#pragma unroll
+    for (int s4 = 0; s4 < KS; s4 += 4)
+        xf[s4 / 4] = *(const f32x4 *)(px + s4);
+    f32x16 G[NT];
+#pragma unroll
+    for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            G[tb][i] = 0.0f;
+    double R = 0.0, S = 0.0;  // lanes < 32: row n's sum of P; lanes >= 32: of Q
+    const int s0 = A.seg_off[j], nb = (A.seg_off[j + 1] - s0) / 32;
+    for (int eb = wl; eb < nb; eb += 4) {  // wave uniform
+        const int se = s0 + 32 * eb + n;
+        const int64_t re = A.sup_row[se];
+        const float we = A.sup_w[se], sqe = A.poolsq[re];
+        const float *pe = A.pool32 + re * DP + h * KS;
+        f32x16 acc;
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            acc[i] = 0.0f;
+#pragma unroll
+        for (int s4 = 0; s4 < KS; s4 += 4) {
+            const f32x4 ev = *(const f32x4 *)(pe + s4);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xf[s4 / 4][q], ev[q], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int m = 8 * (i >> 2) + 4 * h + (i & 3);
+            const float d2 = fmaxf(fmaf(-2.0f, acc[i], xsq[m] + sqe), 0.0f);
+            const float p = we * __builtin_amdgcn_exp2f(A.c * d2);
+            Pl[wl][m][n] = p;
+            Ql[wl][m][n] = p * d2;
+        }
+        __builtin_amdgcn_wave_barrier();  // the tile is in LDS (one wave's in-order accesses)
+        {
+            const float *src = h == 0 ? &Pl[wl][n][0] : &Ql[wl][n][0];
+            double t = 0.0;
+#pragma unroll 8
+            for (int c = 0; c < 32; ++c)
+                t += (double)src[c];
+            if (h == 0)
+                R += t;
+            else
+                S += t;
+        }
+        // G += P Y: k-steps over the block's entries, two per step
+        const int32_t myre = (int32_t)re;
+#pragma unroll 4
+        for (int s = 0; s < 16; ++s) {
+            const float a = Pl[wl][n][2 * s + h];
+            const int64_t ry = __shfl(myre, 2 * s + h);
+            const float *py = A.pool32 + ry * DP + n;
+#pragma unroll
+            for (int tb = 0; tb < NT; ++tb)
+                G[tb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, py[32 * tb], G[tb], 0, 0, 0);
+        }
+        __builtin_amdgcn_wave_barrier();  // before the next block overwrites the tile
+    }
+    // the 4 waves' partial sums, added in wave order through one LDS tile
+    if (h == 0)
+        Rp[wl][n] = R;
+    else
+        Sp[wl][n] = S;
+    for (int q = 0; q < 4; ++q) {
+        if (wl == q) {
+#pragma unroll
+            for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const int m = 8 * (i >> 2) + 4 * h + (i & 3);
+                    float *gp = &Gp[m][32 * tb + n];
+                    *gp = q == 0 ? G[tb][i] : *gp + G[tb][i];
+                }
+        }
+        __syncthreads();
+    }
+    for (int idx = threadIdx.x; idx < 32 * A.d; idx += 256) {
+        const int m = idx / A.d, t = idx - m * A.d;
+        const int row = rows[m];
+        if (row < 0)
+            continue;
+        const double Rm = ((Rp[0][m] + Rp[1][m]) + Rp[2][m]) + Rp[3][m];
+        const double Gm = (double)Gp[m][t];
+        const double x = (double)A.bat32[(int64_t)row * DP + t];
+        A.dX[(int64_t)row * A.d + t] = (float)(A.cx * (x * Rm - Gm));
+    }
+    if (threadIdx.x < 32) {
+        const int m = threadIdx.x, row = rows[m];
+        if (row >= 0) {
+            const double Sm = ((Sp[0][m] + Sp[1][m]) + Sp[2][m]) + Sp[3][m];
+            A.rowds[row] = A.cs * (-2.0 * Sm * A.inv_s3 + A.dN[j]);
+        }
+    }
+}
+
+void launch_grad_mfma(const Layout &L, const Buffers &B, int b, double sigma, const int32_t *labels, double g,
+                      const double *dN, float *dX, double *rowds, double *out, hipStream_t st)
+{
+    GroupArgs Gq;
+    Gq.b = b;
+    Gq.k = L.k;
+    Gq.d = L.d;
+    Gq.labels = labels;
+    Gq.cnt = B.gr_cnt;
+    Gq.cur = B.gr_cnt + L.k;
+    Gq.loff = B.gr_loff;
+    Gq.rtoff = B.gr_rtoff;
+    Gq.perm = B.gr_perm;
+    Gq.dX = dX;
+    Gq.rowds = rowds;
+    Gq.flags = B.flags;
+    hipLaunchKernelGGL(k_group_labels, dim3(1), dim3(1024), 0, st, Gq);
+    GradMfmaArgs A;
+    A.b = b;
+    A.d = L.d;
+    A.k = L.k;
+    A.loff = B.gr_loff;
+    A.rtoff = B.gr_rtoff;
+    A.perm = B.gr_perm;
+    A.labels = labels;
+    A.seg_off = B.seg_off;
+    A.sup_row = B.sup_row;
+    A.sup_w = B.sup_w;
+    A.pool32 = B.pool32;
+    A.poolsq = B.poolsq;
+    A.bat32 = B.bat32;
+    A.batsq = B.batsq;
+    A.zero_row = L.PR;
+    A.dN = dN;
+    A.c = (float)(-1.4426950408889634 / (2.0 * sigma * sigma));
+    A.inv_s3 = 1.0 / (sigma * sigma * sigma);
+    A.cx = 2.0 * g / ((double)b * sigma * sigma);
+    A.cs = g / (double)b;
+    A.dX = dX;
+    A.rowds = rowds;
+    // at most ceil(b / 32) + k tasks (each group adds at most one partial block)
+    const dim3 grid((unsigned)((b + 31) / 32 + L.k));
+    switch (L.dp) {
+    case 32: hipLaunchKernelGGL(k_grad_mfma<32>, grid, dim3(256), 0, st, A); break;
+    case 64: hipLaunchKernelGGL(k_grad_mfma<64>, grid, dim3(256), 0, st, A); break;
+    case 96: hipLaunchKernelGGL(k_grad_mfma<96>, grid, dim3(256), 0, st, A); break;
+    default: hipLaunchKernelGGL(k_grad_mfma<128>, grid, dim3(256), 0, st, A); break;
+    }
+    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(1024), 0, st, (const double *)rowds, b, out);
 }
 
 int grad_max_dim() { return 64 * 16; }

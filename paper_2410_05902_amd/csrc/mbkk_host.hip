@@ -34,6 +34,13 @@ struct mbkk_ctx {
     uint32_t fold_mask = 0;
     // iteration whose support segment offsets the last update wrote to seg_next
     int64_t seg_next_iter = -1;
+    // state version: bumped by every change of the centers; the support layout
+    // (offsets, rows, weights) and the self norms at a bandwidth are valid for
+    // the version they were made at
+    int64_t version = 0;
+    int64_t layout_version = -1;
+    int64_t sig_version = -1;
+    double sig_sigma = 0.0;
     int32_t slot_b[kMaxSlots] = {};  // points held by each physical slot
     int device = -1;                 // static workspace: the device whose array it uses (-1: none)
     // timing of the cross-term kernel
@@ -188,6 +195,12 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.Nsig = (double *)take(8 * (size_t)L.k);
     B.dNsig = (double *)take(8 * (size_t)L.k);
     B.rowds = (double *)take(8 * (size_t)L.bmax);
+    B.sg_toff = (int32_t *)take(4 * ((size_t)L.k + 1));
+    B.sg_part = (double *)take(8 * 2 * ((size_t)kGramWaves + L.k));
+    B.gr_cnt = (int32_t *)take(4 * 2 * (size_t)L.k);
+    B.gr_loff = (int32_t *)take(4 * ((size_t)L.k + 1));
+    B.gr_rtoff = (int32_t *)take(4 * ((size_t)L.k + 1));
+    B.gr_perm = (int32_t *)take(4 * (size_t)L.bmax);
     B.D2 = (double *)take(8 * (size_t)L.n);
     B.kself = (double *)take(8 * (size_t)L.n);
     B.bsum = (double *)take(8 * (size_t)L.kpp_blocks);
@@ -380,8 +393,10 @@ static void prepare(mbkk_ctx *c, const int32_t *idx, int64_t cnt)
         fold_rr = take_fold(c, &fold_mask);
     launch_prepare(L, c->B, need, live, init_alive, idx, cnt, c->cfg.validate, ay_scale, fold_rr, fold_mask,
                    c->seg_next_iter == c->iter, c->stream);
-    if (need)
+    if (need) {
         c->support_iter = c->iter;
+        c->layout_version = c->version;
+    }
 }
 
 // The next (start, stop) pair of timing events.
@@ -560,6 +575,8 @@ int mbkk_create_static(const mbkk_config *cfg, void *stream, mbkk_ctx **out)
     c->fold_rr = -1;
     c->fold_mask = 0;
     c->seg_next_iter = -1;
+    c->layout_version = -1;
+    c->sig_version = -1;
     c->ymax2 = 0.0;
     c->timing = false;
     c->ev_used = 0;
@@ -612,6 +629,7 @@ int mbkk_set_data(mbkk_ctx *c, const float *X, int64_t ld)
     float f;
     memcpy(&f, &bits, sizeof(f));
     c->ymax2 = (double)f;
+    c->version++;
     c->data_set = true;
     c->inited = false;
     return MBKK_OK;
@@ -638,6 +656,7 @@ static int init_common(mbkk_ctx *c, const int32_t *idx_dev)
     c->support_iter = -1;
     c->fold_rr = -1;
     c->seg_next_iter = -1;
+    c->version++;
     std::fill(c->slot_b, c->slot_b + kMaxSlots, 0);
     if (c->cfg.validate) {
         int rc = check_flags(c);
@@ -714,6 +733,7 @@ static int dp_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels
     HIPCHK(c, hipGetLastError());
     c->slot_b[0] = b;
     c->iter += 1;
+    c->version++;
     if (labels_dev)
         HIPCHK(c, hipMemcpyAsync(labels_dev, B.labels, 4 * (size_t)b, hipMemcpyDeviceToDevice, c->stream));
     if (mind_dev)
@@ -774,6 +794,7 @@ int mbkk_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels_dev,
     HIPCHK(c, hipGetLastError());
     c->slot_b[p_new] = b;
     c->iter = i + 1;
+    c->version++;
     if (labels_dev)
         HIPCHK(c, hipMemcpyAsync(labels_dev, B.labels, 4 * (size_t)b, hipMemcpyDeviceToDevice, c->stream));
     if (mind_dev)
@@ -965,9 +986,9 @@ static int grad_args(mbkk_ctx *c, const float *xb, int32_t b, double sigma)
 }
 
 // Lays out the support of C_i with the exponent constants of bandwidth kappa
-// and evaluates the self norms at sigma (N) and their derivative (dN).  The
-// next call that scores at the model's own bandwidth lays the support out again.
-static void support_at_sigma(mbkk_ctx *c, double sigma)
+// (the cross term at sigma needs them); the next call that scores at the
+// model's own bandwidth lays the support out again.
+static void layout_at_sigma(mbkk_ctx *c, double sigma)
 {
     const Layout &L = c->L;
     const double kappa = 2.0 * sigma * sigma;
@@ -978,7 +999,21 @@ static void support_at_sigma(mbkk_ctx *c, double sigma)
     launch_prepare(L, c->B, true, live, init_alive, nullptr, 0, 0, (float)(-1.4426950408889634 / kappa), fold_rr,
                    fold_mask, c->seg_next_iter == c->iter, c->stream);
     c->support_iter = -1;
-    launch_selfnorm_sigma(L, c->B, sigma, c->B.Nsig, c->B.dNsig, c->stream);
+    c->layout_version = c->version;
+}
+
+// Self norms at sigma and their derivative, once per (state, sigma): the
+// backward that follows a forward at the same sigma reuses them.
+static void norms_at_sigma(mbkk_ctx *c, double sigma)
+{
+    if (c->sig_version == c->version && c->sig_sigma == sigma)
+        return;
+    if (sigma_mfma_ok(c->L))
+        launch_sigma_norms(c->L, c->B, sigma, c->B.Nsig, c->B.dNsig, c->stream);
+    else
+        launch_selfnorm_sigma(c->L, c->B, sigma, c->B.Nsig, c->B.dNsig, c->stream);
+    c->sig_version = c->version;
+    c->sig_sigma = sigma;
 }
 
 int mbkk_objective_fwd(mbkk_ctx *c, const float *xb_dev, int32_t b, double sigma, int32_t *labels_dev,
@@ -997,13 +1032,25 @@ int mbkk_objective_fwd(mbkk_ctx *c, const float *xb_dev, int32_t b, double sigma
     set_batch_view(c, phys_of(c->iter, L.P));
     launch_gather_rows(xb_dev, b, L.d, L.d, nullptr, b, L.dp, B.bat32, B.bathi, B.batlo, B.batsq, B.batsq64, nullptr,
                        B.flags, 1, c->stream, L.frag_mode, B.batfrag, 2 * (int64_t)frag_rows(L) * L.dp);
-    support_at_sigma(c, sigma);
+    layout_at_sigma(c, sigma);
+    norms_at_sigma(c, sigma);
     Buffers Bs = B;
     Bs.N = B.Nsig;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (c->timing) {
+        rc = timing_pair(c, &e0, &e1);
+        if (rc)
+            return rc;
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+    }
     if (c->use_mfma)
         launch_cross_mfma(L, Bs, b, cf.precision, kappa, c->stream);
     else
         launch_cross_direct(L, Bs, b, MBKK_GAUSS, kappa, c->fp64, c->stream);
+    if (c->timing) {
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        c->launches++;
+    }
     launch_score(L, Bs, b, MBKK_GAUSS, kappa, c->fp64, c->use_mfma, cf.precision, tie_delta(cf), c->ymax2, nullptr, 0,
                  false, c->stream);
     launch_sum_mind(B, b, 0, c->stream);
@@ -1038,8 +1085,20 @@ int mbkk_objective_bwd(mbkk_ctx *c, const float *xb_dev, int32_t b, double sigma
     Buffers &B = c->B;
     if (clear_flags(c))
         return MBKK_E_HIP;
-    support_at_sigma(c, sigma);
-    launch_grad_rows(L, B, xb_dev, b, sigma, labels_dev, g, B.dNsig, dX_dev, B.rowds, B.obj + 2, c->stream);
+    // the support layout and the self norms of a forward at this state and
+    // sigma are still valid; otherwise they are made here
+    if (c->layout_version != c->version)
+        layout_at_sigma(c, sigma);
+    norms_at_sigma(c, sigma);
+    if (sigma_mfma_ok(L)) {
+        // the coordinates go to the free slot, as in the forward
+        set_batch_view(c, phys_of(c->iter, L.P));
+        launch_gather_rows(xb_dev, b, L.d, L.d, nullptr, b, L.dp, B.bat32, nullptr, nullptr, B.batsq, B.batsq64,
+                           nullptr, B.flags, 0, c->stream);
+        launch_grad_mfma(L, B, b, sigma, labels_dev, g, B.dNsig, dX_dev, B.rowds, B.obj + 2, c->stream);
+    } else {
+        launch_grad_rows(L, B, xb_dev, b, sigma, labels_dev, g, B.dNsig, dX_dev, B.rowds, B.obj + 2, c->stream);
+    }
     HIPCHK(c, hipGetLastError());
     double s = 0.0;
     int32_t f[3] = {0, 0, 0};
@@ -1199,6 +1258,7 @@ int mbkk_set_state(mbkk_ctx *c, const mbkk_state *s)
         c->slot_b[p] = sb[p];
     c->iter = i;
     c->support_iter = -1;
+    c->version++;
     c->inited = true;
     return MBKK_OK;
 }

@@ -1,5 +1,5 @@
 """Host-side checks of the C-ABI library that need no GPU: it loads, exports
-every entry point declared in include/mbkk.h, and validates configurations
+every entry point declared in include/*.h, and validates configurations
 (mbkk_workspace_size touches no device)."""
 import ctypes as C
 import os
@@ -11,8 +11,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def declared_symbols():
-    text = open(os.path.join(ROOT, "include", "mbkk.h")).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(mbkk_\w+)\s*\(", text, re.M)))
+    """Every entry point declared in include/*.h."""
+    import glob
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        names |= set(re.findall(r"^\s*(?:int|const char \*)\s*(mbkk_\w+)\s*\(", text, re.M))
+    return sorted(names)
 
 
 def test_header_declares_the_abi():
