@@ -52,26 +52,63 @@ DP_SRC = os.path.join(ROOT, "paper_2410_05902_amd", "csrc", "kernels_dp.hip")
 
 
 def source_sha(path: str = CROSS_SRC) -> str:
+    """Hash of a kernel source's code: comments and blank space removed, so an
+    edit of the comments keeps the counters taken on the code valid."""
     import hashlib
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    import re
+    with open(path) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    text = " ".join(text.split())
+    return hashlib.sha256(text.encode()).hexdigest()[:16]
+
+
+def _kname(name: str) -> str:
+    import re
+    return re.sub(r"\(.*", "", name).replace("void ", "").strip()
 
 
 def _counter_means(d: str, counter: str):
-    """Mean per dispatch of `counter` (summed over its instances), per kernel name."""
+    """Mean per dispatch of `counter` (summed over its instances), per kernel
+    name, from a rocprofv3 counter-collection output (CSV or database)."""
+    import csv
     import glob
-    import re
     import sqlite3
-    dbs = glob.glob(os.path.join(d, "**", "*.db"), recursive=True)
-    if not dbs:
-        raise SystemExit(f"no rocprofv3 database under {d}")
-    con = sqlite3.connect(dbs[0])
-    rows = con.execute("select kernel_name, dispatch_id, sum(value) from counters_collection "
-                       "where counter_name = ? group by kernel_name, dispatch_id", (counter,)).fetchall()
+    per = {}
+    csvs = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if csvs:
+        for path in csvs:
+            with open(path) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] == counter:
+                        key = (_kname(r["Kernel_Name"]), int(r["Dispatch_Id"]))
+                        per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+    else:
+        dbs = glob.glob(os.path.join(d, "**", "*.db"), recursive=True)
+        if not dbs:
+            raise SystemExit(f"no rocprofv3 output under {d}")
+        con = sqlite3.connect(dbs[0])
+        rows = con.execute("select kernel_name, dispatch_id, sum(value) from counters_collection "
+                           "where counter_name = ? group by kernel_name, dispatch_id", (counter,)).fetchall()
+        for name, disp, v in rows:
+            per[(_kname(name), disp)] = v
     acc = {}
-    for name, _, v in rows:
-        acc.setdefault(re.sub(r"\(.*", "", name), []).append(v)
+    for (name, _), v in per.items():
+        acc.setdefault(name, []).append(v)
     return {k: (sum(v) / len(v), len(v)) for k, v in acc.items()}
+
+
+def _trace_means(d: str):
+    """Mean traced duration (us) per kernel name from a rocprofv3 kernel-stats CSV."""
+    import csv
+    import glob
+    out = {}
+    for path in glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True):
+        with open(path) as fh:
+            for r in csv.DictReader(fh):
+                out[_kname(r["Name"])] = float(r["AverageNs"]) / 1e3
+    return out
 
 
 def traffic_summary(args):
@@ -97,6 +134,20 @@ def traffic_summary(args):
            "fetch_scale": sf, "write_scale": sw,
            "traffic_bytes_per_launch": (f[0] * sf + w[0] * sw) * 1024.0,
            "source": os.path.basename(src), "source_sha": source_sha(src)}
+    # every kernel of the run: scaled bytes per dispatch, and with a kernel
+    # trace of the same command, GB/s against the 8 TB/s of HBM
+    tmeans = _trace_means(args.trace_dir) if args.trace_dir else {}
+    table = {}
+    for k in sorted(set(fetch) & set(write)):
+        byt = (fetch[k][0] * sf + write[k][0] * sw) * 1024.0
+        row = {"dispatches": fetch[k][1], "fetch_bytes": fetch[k][0] * sf * 1024.0,
+               "write_bytes": write[k][0] * sw * 1024.0, "bytes": byt}
+        if k in tmeans:
+            row["avg_us"] = tmeans[k]
+            row["GBps"] = byt / (tmeans[k] * 1e-6) / 1e9
+            row["frac_of_8TBps"] = row["GBps"] * 1e9 / HBM_PEAK
+        table[k] = row
+    out["kernels"] = table
     path = os.path.join(ROOT, "profiles", f"traffic_{wl}.json")
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
@@ -407,6 +458,9 @@ def main():
                     help="summarise rocprofv3 FETCH_SIZE / WRITE_SIZE runs of the workload and of the copy "
                          "calibration into profiles/traffic_<workload>.json (no GPU needed)")
     ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--trace-dir", default=None,
+                    help="with --traffic-summary: a rocprofv3 --kernel-trace --stats -f csv output of the same "
+                         "command, for each kernel's GB/s")
     ap.add_argument("--differentiation", action="store_true",
                     help="time the differentiation form (objective and gradient) on the 64-D mixture")
     ap.add_argument("--untruncated", action="store_true",
@@ -471,6 +525,7 @@ def main():
                      kernel="gauss" if gauss else "laplace", kernel_param=wl.kernel_param,
                      precision=prec, validate=False, lr=args.lr, tau=args.tau)
 
+    rescored = []  # rows re-scored in FP64 per step (BF16 forms), per timed form
     active = []  # untruncated form: centers with batch points in each kernel-timed step
     live = []    # truncated form: support entries with a nonzero weight in each kernel-timed step
 
@@ -495,6 +550,7 @@ def main():
         torch.cuda.synchronize()
         te = time.perf_counter()
         model.set_timing(True)
+        model.rescore_count(reset=True)
         for i in range(kernel_steps):
             if untrunc:
                 lab = model.step(batches[(warm + i) % nsteps])["labels"]
@@ -504,6 +560,7 @@ def main():
                 model.step_noout(batches[(warm + i) % nsteps])
         kms, launches = model.get_timing()
         model.set_timing(False)
+        rescored.append(model.rescore_count() / kernel_steps)
         return (te - ts) * 1e3 / timed_steps, kms / max(launches, 1)
 
     # ---- main form ---------------------------------------------------------
@@ -582,6 +639,8 @@ def main():
                       "tau": args.tau, "support_entries": None if untrunc else M,
                       "init": "kernel k-means++ (GPU)", "parallelism": "single GPU"},
            "iters_per_s": iters, ("table_kernel_ms" if untrunc else "cross_kernel_ms"): ms_cross}
+    if precision.startswith("bf16") and not untrunc:
+        out["rescored_rows_per_step"] = rescored[0]
 
     # ---- FP32 plain form, and assignment agreement -------------------------
     if gauss and precision.startswith("bf16") and not args.no_fp32 and not untrunc:

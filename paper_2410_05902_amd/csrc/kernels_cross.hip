@@ -638,13 +638,19 @@ __device__ __forceinline__ int bs_range_blocks(int Mb, int nranges)
     return (rb + kBsStageBlocks - 1) / kBsStageBlocks * kBsStageBlocks;
 }
 
+// Waves per SIMD: two in the BF16X3 form with row stride above 64, whose
+// two waves on a SIMD take turns, one issuing MFMAs while the other runs its
+// exp epilogue or waits on LDS; one elsewhere (the FP32 MFMAs are twice as
+// long, and at stride 64 the register file holds four N-blocks per wave).
+__host__ __device__ constexpr int bs_wps(int mode, int dp) { return mode == 1 && dp > 64 ? 2 : 1; }
 // Batch rows held in registers per wave, in 32-row N-blocks: as many as the
-// register file allows (one wave per SIMD: 256 VGPRs + 256 AGPRs) with two
-// accumulator sets (the pipelined epilogue) and few copies between the two
-// register kinds.  FP32 fragments are 2x larger and each FP32 MFMA is 2x
-// longer, so two N-blocks already amortise the support reads.
-__host__ __device__ constexpr int bs_nbk(int mode, int dp) { return mode == 0 ? 2 : (mode == 1 && dp > 64 ? 2 : 4); }
-static int bs_tile_rows(int mode, int dp) { return 4 * 32 * bs_nbk(mode, dp); }
+// register file allows (one wave per SIMD: 256 VGPRs + 256 AGPRs; two waves:
+// half each) with two accumulator sets (the pipelined epilogue) and few
+// copies between the two register kinds.  FP32 fragments are 2x larger and
+// each FP32 MFMA is 2x longer, so two N-blocks already amortise the support
+// reads.
+__host__ __device__ constexpr int bs_nbk(int mode, int dp) { return mode == 0 ? 2 : (mode == 1 && dp > 64 ? 1 : 4); }
+static int bs_tile_rows(int mode, int dp) { return 4 * bs_wps(mode, dp) * 32 * bs_nbk(mode, dp); }
 static int bs_mode(int precision) { return precision == MBKK_FP32 ? 0 : (precision == MBKK_BF16X3 ? 1 : 2); }
 // Ranges for nb batch rows: one round of workgroups (kBsOcc per compute unit).
 static int bs_nranges(int nb, int mode, int dp)
@@ -676,13 +682,14 @@ struct CrossBsArgs {
 typedef __attribute__((address_space(3))) void lds_void_t;
 
 template <int MODE, int DP>
-__global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
+__global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(const CrossBsArgs A)
 {
     // buffer resources exist in the device pass only; the host pass keeps the launch stub
 #if defined(__HIP_DEVICE_COMPILE__)
     constexpr bool F32 = MODE == 0;
     constexpr bool X3 = MODE == 1;
     constexpr int NBK = bs_nbk(MODE, DP);          // 32-row N-blocks (batch rows) per wave
+    constexpr int NW = 4 * bs_wps(MODE, DP);       // waves per workgroup
     constexpr int SB = kBsStageBlocks;
     constexpr int KS = F32 ? DP / 2 : DP / 16;     // MFMA k-steps over K = DP
     constexpr int ES = F32 ? 4 : 2;                // element bytes
@@ -691,7 +698,7 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
     constexpr int ROWS = 32 * SB;                  // support rows per stage
     constexpr int NPOS = ROWS * CPS;               // chunk positions per staged array
     constexpr int NINS = NPOS / 64;                // DMA instructions per array
-    constexpr int NT = (NINS + 3) / 4;             // per wave (waves take i = w, w+4, ...)
+    constexpr int NT = (NINS + NW - 1) / NW;       // per wave (waves take i = w, w+NW, ...)
     constexpr int NARR = X3 ? 2 : 1;
     constexpr int ABYTES = NPOS * 16;
     static_assert(NPOS % 64 == 0 && ROWS % 64 == 0 && ROWS / 64 * 2 == 4, "staging layout");
@@ -751,17 +758,17 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
         return;
     const int blk1 = min(Mb, blk0 + RB);
     const int nst = (blk1 - blk0 + SB - 1) / SB;
-    const int b0 = (bt * 4 + wu) * (32 * NBK);  // this wave's batch rows
+    const int b0 = (bt * NW + wu) * (32 * NBK);  // this wave's batch rows
     const int n = lane & 31, h = lane >> 5;
 
     // ---- staging ---------------------------------------------------------
-    // DMA slot q of this lane: instruction i = wave + 4 q writes chunk
+    // DMA slot q of this lane: instruction i = wave + NW q writes chunk
     // position 64 i + lane of a staged array, i.e. row dma_row(q), chunk
     // offset dma_coff(q) (recomputed when needed: registers are scarce)
-    __builtin_assume(wu >= 0 && wu < 4);
-    auto dma_row = [&](int q) { return min((64 * (wu + 4 * q) + lane) / CPS, ROWS - 1); };
+    __builtin_assume(wu >= 0 && wu < NW);
+    auto dma_row = [&](int q) { return min((64 * (wu + NW * q) + lane) / CPS, ROWS - 1); };
     auto dma_coff = [&](int q) {
-        const int c = (64 * (wu + 4 * q) + lane) % CPS;
+        const int c = (64 * (wu + NW * q) + lane) % CPS;
         return (c < CPR ? c : 0) * 16;  // the pad position loads any valid chunk
     };
     int pidx[NT];
@@ -816,8 +823,8 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
     auto issue_slot = [&](auto bc, int q) {  // DMA slot q of every staged array (pidx[q] holds its row)
 #pragma unroll
         for (int arr = 0; arr < NARR; ++arr) {
-            const int i = wu + 4 * q;
-            if (4 * q + 3 < NINS || i < NINS)
+            const int i = wu + NW * q;
+            if (NW * q + NW - 1 < NINS || i < NINS)
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(arr == 0 ? rs_p0 : rs_p1,
                                                          (lds_void_t *)(bufA(bc) + arr * ABYTES + i * 1024), 16,
                                                          pidx[q] * (DP * ES) + dma_coff(q), 0, 0, 0);
@@ -825,6 +832,8 @@ __global__ __launch_bounds__(256, kBsOcc) void k_cross_bs(const CrossBsArgs A)
     };
     auto issue_ayw = [&](int s, auto bc) {
         // exponent constants (waves 0, 1) and weights (waves 2, 3), 64 rows each
+        if (wu >= 4)
+            return;
         const int half = wu & 1;
         const int srow = (blk0 + SB * s) * 32 + half * 64 + lane;
         float *dst = (wu < 2 ? bufAy(bc) : bufW(bc)) + half * 64;
@@ -1168,7 +1177,7 @@ void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision,
         A.ldp = L.bmax;
         const int64_t tiles = (int64_t)A.nranges * A.nbt;
         const dim3 grid((unsigned)((tiles + 7) / 8 * 8));
-#define MBKK_BS(MODE, DP) hipLaunchKernelGGL((k_cross_bs<MODE, DP>), grid, dim3(256), 0, st, A)
+#define MBKK_BS(MODE, DP) hipLaunchKernelGGL((k_cross_bs<MODE, DP>), grid, dim3(256 * bs_wps(MODE, DP)), 0, st, A)
 #define MBKK_BS_DP(MODE)                      \
     switch (L.dp) {                           \
     case 32: MBKK_BS(MODE, 32); break;        \
@@ -1221,7 +1230,10 @@ void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision,
 
 // ===========================================================================
 // Distances, argmin and margin of each batch row:
-//   D_j = K(x,x) - 2 P_j + N_j  (FP64 assembly of the FP32/FP64 cross term)
+//   D_j = K(x,x) - 2 P_j + N_j, the FP32 cross term added to the FP64 self
+//   norm in FP64.  In a nearly orthogonal feature space (the Laplacian at
+//   sigma = 4 in 32-D: kernel values of 1e-8 and below) the centers' P_j
+//   differ far below an FP32 ulp of N_j, and an FP32 sum would tie them.
 // label = smallest j attaining the minimum; margin = second smallest - min.
 // LAYOUT 0: P[j][row]; LAYOUT 1: per-32-block partials of the MFMA kernel.
 // ===========================================================================
@@ -1243,6 +1255,7 @@ __device__ __forceinline__ double self_kernel(int kind, double param, double sq)
 // LAYOUT 1: the MFMA kernels write one partial per run of a center's blocks
 // inside a range of RB blocks, at the run's first block: the center's first
 // block and every range start inside the center.
+// The direct kernel's runs are summed in FP64, the MFMA kernels' in FP32.
 template <typename T, int LAYOUT>
 __device__ __forceinline__ double cross_of(const T *__restrict__ part, int ldp, int row, int j,
                                            const int32_t *__restrict__ seg_off, int RB, int k = 0)
@@ -1438,6 +1451,7 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
             for (int u = 0; u < NB; ++u) {
                 const int j = j0 + u * kScoreWaves;
                 if (j < A.k) {
+                    // in FP64, in the order K(x,x) - 2 P + N
                     const double D = kxx - 2.0 * P[u] + Nj[u];
                     if (A.Dout)
                         A.Dout[(int64_t)row * A.ldD + j] = D;

@@ -456,24 +456,41 @@ struct GroupArgs {
     float *dX;            // rows with a bad label: zeroed
     double *rowds;
     int32_t *flags;       // flags[2]: a label outside [0, k)
+    int32_t *ticket;      // cleared here for the grad kernel
 };
 
-// One workgroup: every phase is separated by a barrier, and the counters are
-// read back with atomic loads (they are updated with device atomics).
+// One workgroup.  With k <= kGroupLdsK the counters live in LDS (LDS
+// atomics); otherwise in the workspace (device atomics, read back with atomic
+// loads).  Every phase is separated by a barrier.
+constexpr int kGroupLdsK = 8192;
+
+template <bool LDS>
 __global__ __launch_bounds__(1024) void k_group_labels(const GroupArgs A)
 {
     __shared__ int sint[16];
+    __shared__ int lcnt[LDS ? kGroupLdsK : 1], lcur[LDS ? kGroupLdsK : 1];
+    int *cnt = LDS ? lcnt : A.cnt;
+    int *cur = LDS ? lcur : A.cur;
+    auto rd = [&](const int *p) -> int {
+        if constexpr (LDS)
+            return *p;
+        else
+            return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
     const int tid = threadIdx.x;
     for (int j = tid; j < A.k; j += 1024) {
-        A.cnt[j] = 0;
-        A.cur[j] = 0;
+        cnt[j] = 0;
+        cur[j] = 0;
     }
-    __threadfence();
+    if (tid == 0)
+        *A.ticket = 0;  // the grad kernel's count of finished tasks
+    if constexpr (!LDS)
+        __threadfence();
     __syncthreads();
     for (int r = tid; r < A.b; r += 1024) {
         const int j = A.labels[r];
         if (j >= 0 && j < A.k) {
-            atomicAdd(&A.cnt[j], 1);
+            atomicAdd(&cnt[j], 1);
         } else {
             atomicOr(&A.flags[2], 1);
             A.rowds[r] = 0.0;
@@ -481,13 +498,14 @@ __global__ __launch_bounds__(1024) void k_group_labels(const GroupArgs A)
                 A.dX[(int64_t)r * A.d + t] = 0.0f;
         }
     }
-    __threadfence();
+    if constexpr (!LDS)
+        __threadfence();
     __syncthreads();
     const int per = (A.k + 1023) / 1024;
     const int j0 = min(A.k, tid * per), j1 = min(A.k, j0 + per);
     int lrow = 0, ltask = 0;
     for (int j = j0; j < j1; ++j) {
-        const int c = __hip_atomic_load(&A.cnt[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int c = rd(&cnt[j]);
         lrow += c;
         ltask += (c + 31) / 32;
     }
@@ -495,9 +513,10 @@ __global__ __launch_bounds__(1024) void k_group_labels(const GroupArgs A)
     int rrun = block_exclusive_scan(lrow, sint, &trow);
     int trun = block_exclusive_scan(ltask, sint, &ttask);
     for (int j = j0; j < j1; ++j) {
-        const int c = __hip_atomic_load(&A.cnt[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int c = rd(&cnt[j]);
         A.loff[j] = rrun;
         A.rtoff[j] = trun;
+        cur[j] = rrun;  // (this thread's own centers: no other thread touched them yet)
         rrun += c;
         trun += (c + 31) / 32;
     }
@@ -505,15 +524,13 @@ __global__ __launch_bounds__(1024) void k_group_labels(const GroupArgs A)
         A.loff[A.k] = trow;
         A.rtoff[A.k] = ttask;
     }
-    __threadfence();
+    if constexpr (!LDS)
+        __threadfence();
     __syncthreads();
     for (int r = tid; r < A.b; r += 1024) {
         const int j = A.labels[r];
-        if (j >= 0 && j < A.k) {
-            const int pos = __hip_atomic_load(&A.loff[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) +
-                            atomicAdd(&A.cur[j], 1);
-            A.perm[pos] = r;
-        }
+        if (j >= 0 && j < A.k)
+            A.perm[atomicAdd(&cur[j], 1)] = r;
     }
 }
 
@@ -530,20 +547,40 @@ struct GradMfmaArgs {
     double inv_s3, cx, cs;       // cx = 2 g / (b s^2), cs = g / b
     float *dX;
     double *rowds;
+    int32_t *ticket;             // tasks finished (cleared by k_group_labels)
+    double *out;                 // df/ds: the sum of rowds, by the last task
 };
 
+// Each wave stages the 32 support rows of its block in LDS (row stride DP + 4
+// floats: 16-byte reads at the k-steps' offsets hit distinct banks); the
+// dot products read them there, and so does the contraction, whose operand
+// is the same rows read down the columns.  The rows of a wave's next block
+// are loaded into registers while the current one is multiplied, so one
+// block's global latency hides behind the previous block's matrix work.
+// NW waves per workgroup take the support blocks round robin.
 template <int DP>
-__global__ __launch_bounds__(256) void k_grad_mfma(const GradMfmaArgs A)
+__host__ __device__ constexpr int grad_waves()
 {
-    constexpr int KS = DP / 2, NT = DP / 32;
-    __shared__ float Pl[4][32][33], Ql[4][32][33];
+    return DP <= 64 ? 8 : 4;
+}
+
+template <int DP>
+__global__ __launch_bounds__(64 * grad_waves<DP>()) void k_grad_mfma(const GradMfmaArgs A)
+{
+    constexpr int NW = grad_waves<DP>();
+    constexpr int KS = DP / 2, NT = DP / 32, YS = DP + 4, NV = KS / 4;
+    __shared__ __attribute__((aligned(16))) float Yl[NW][32][YS];
+    __shared__ float Pl[NW][32][33];
     __shared__ float Gp[32][DP + 1];
-    __shared__ double Rp[4][32], Sp[4][32];
+    __shared__ double Rp[NW][32], Sp[NW][32];
+    __shared__ double red[16];
     __shared__ float xsq[32];
     __shared__ int rows[32];
+    __shared__ int last;
     const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
     const int task = blockIdx.x;
-    if (task >= A.rtoff[A.k])
+    const int ntask = A.rtoff[A.k];
+    if (task >= ntask)
         return;  // block uniform
     const int j = wave_segment_of(A.rtoff, A.k, task);
     const int r0 = A.loff[j] + 32 * (task - A.rtoff[j]);
@@ -557,73 +594,117 @@ __global__ __launch_bounds__(256) void k_grad_mfma(const GradMfmaArgs A)
     // this lane's A fragments: row n of the task, coordinates [h KS, (h+1) KS)
     const int myrow = rows[n];
     const float *px = myrow >= 0 ? A.bat32 + (int64_t)myrow * DP + h * KS : A.pool32 + A.zero_row * DP + h * KS;
-    f32x4 xf[KS / 4];
+    f32x4 xf[NV];
 #pragma unroll
-    for (int s4 = 0; s4 < KS; s4 += 4)
-        xf[s4 / 4] = *(const f32x4 *)(px + s4);
+    for (int q = 0; q < NV; ++q)
+        xf[q] = *(const f32x4 *)(px + 4 * q);
     f32x16 G[NT];
 #pragma unroll
     for (int tb = 0; tb < NT; ++tb)
 #pragma unroll
         for (int i = 0; i < 16; ++i)
             G[tb][i] = 0.0f;
-    double R = 0.0, S = 0.0;  // lanes < 32: row n's sum of P; lanes >= 32: of Q
+    double R = 0.0, S = 0.0;  // lanes < 32: row n's sum of P; lanes >= 32: of P d2
     const int s0 = A.seg_off[j], nb = (A.seg_off[j + 1] - s0) / 32;
-    for (int eb = wl; eb < nb; eb += 4) {  // wave uniform
+    float(*Y)[YS] = Yl[wl];
+    float(*P)[33] = Pl[wl];
+    // block eb's row n, half h (coordinates), weight and norm: loaded one block ahead
+    f32x4 yv[NV];
+    float we = 0.0f, sqe = 0.0f;
+    auto fetch = [&](int eb) {
         const int se = s0 + 32 * eb + n;
         const int64_t re = A.sup_row[se];
-        const float we = A.sup_w[se], sqe = A.poolsq[re];
+        we = A.sup_w[se];
+        sqe = A.poolsq[re];
         const float *pe = A.pool32 + re * DP + h * KS;
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            yv[q] = *(const f32x4 *)(pe + 4 * q);
+    };
+    if (wl < nb)
+        fetch(wl);
+    for (int eb = wl; eb < nb; eb += NW) {  // wave uniform
+        __builtin_amdgcn_wave_barrier();  // the previous block is done with the tiles
+#pragma unroll
+        for (int q = 0; q < NV; ++q)
+            *(f32x4 *)&Y[n][h * KS + 4 * q] = yv[q];
+        const float w_cur = we, sq_cur = sqe;
+        if (eb + NW < nb)
+            fetch(eb + NW);
+        __builtin_amdgcn_wave_barrier();
         f32x16 acc;
 #pragma unroll
         for (int i = 0; i < 16; ++i)
             acc[i] = 0.0f;
 #pragma unroll
-        for (int s4 = 0; s4 < KS; s4 += 4) {
-            const f32x4 ev = *(const f32x4 *)(pe + s4);
+        for (int q = 0; q < NV; ++q) {
+            const f32x4 ev = *(const f32x4 *)&Y[n][h * KS + 4 * q];
 #pragma unroll
-            for (int q = 0; q < 4; ++q)
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xf[s4 / 4][q], ev[q], acc, 0, 0, 0);
+            for (int u = 0; u < 4; ++u)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xf[q][u], ev[u], acc, 0, 0, 0);
         }
+        float qv[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
             const int m = 8 * (i >> 2) + 4 * h + (i & 3);
-            const float d2 = fmaxf(fmaf(-2.0f, acc[i], xsq[m] + sqe), 0.0f);
-            const float p = we * __builtin_amdgcn_exp2f(A.c * d2);
-            Pl[wl][m][n] = p;
-            Ql[wl][m][n] = p * d2;
+            const float d2 = fmaxf(fmaf(-2.0f, acc[i], xsq[m] + sq_cur), 0.0f);
+            const float p = w_cur * __builtin_amdgcn_exp2f(A.c * d2);
+            P[m][n] = p;
+            qv[i] = p * d2;
         }
-        __builtin_amdgcn_wave_barrier();  // the tile is in LDS (one wave's in-order accesses)
-        {
-            const float *src = h == 0 ? &Pl[wl][n][0] : &Ql[wl][n][0];
-            double t = 0.0;
-#pragma unroll 8
-            for (int c = 0; c < 32; ++c)
-                t += (double)src[c];
-            if (h == 0)
-                R += t;
-            else
-                S += t;
-        }
-        // G += P Y: k-steps over the block's entries, two per step
-        const int32_t myre = (int32_t)re;
-#pragma unroll 4
+        __builtin_amdgcn_wave_barrier();  // P is in LDS (one wave's in-order accesses)
+        // G += P Y: k-steps over the block's entries, two per step; all operands
+        // read first
+        float pa[16], yb[16][NT];
+#pragma unroll
         for (int s = 0; s < 16; ++s) {
-            const float a = Pl[wl][n][2 * s + h];
-            const int64_t ry = __shfl(myre, 2 * s + h);
-            const float *py = A.pool32 + ry * DP + n;
+            pa[s] = P[n][2 * s + h];
 #pragma unroll
             for (int tb = 0; tb < NT; ++tb)
-                G[tb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, py[32 * tb], G[tb], 0, 0, 0);
+                yb[s][tb] = Y[2 * s + h][32 * tb + n];
         }
-        __builtin_amdgcn_wave_barrier();  // before the next block overwrites the tile
+        if (h == 0) {  // row n's sum of P, four partial sums
+            double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+#pragma unroll
+            for (int c = 0; c < 32; c += 4) {
+                t0 += (double)P[n][c];
+                t1 += (double)P[n][c + 1];
+                t2 += (double)P[n][c + 2];
+                t3 += (double)P[n][c + 3];
+            }
+            R += (t0 + t1) + (t2 + t3);
+        }
+#pragma unroll
+        for (int s = 0; s < 16; ++s)
+#pragma unroll
+            for (int tb = 0; tb < NT; ++tb)
+                G[tb] = __builtin_amdgcn_mfma_f32_32x32x2f32(pa[s], yb[s][tb], G[tb], 0, 0, 0);
+        // P d2 into the tile (P's reads are done), then row n's sum of it
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int m = 8 * (i >> 2) + 4 * h + (i & 3);
+            P[m][n] = qv[i];
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (h == 1) {
+            double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+#pragma unroll
+            for (int c = 0; c < 32; c += 4) {
+                t0 += (double)P[n][c];
+                t1 += (double)P[n][c + 1];
+                t2 += (double)P[n][c + 2];
+                t3 += (double)P[n][c + 3];
+            }
+            S += (t0 + t1) + (t2 + t3);
+        }
     }
-    // the 4 waves' partial sums, added in wave order through one LDS tile
+    // the waves' partial sums, added in wave order through one LDS tile
     if (h == 0)
         Rp[wl][n] = R;
     else
         Sp[wl][n] = S;
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NW; ++q) {
         if (wl == q) {
 #pragma unroll
             for (int tb = 0; tb < NT; ++tb)
@@ -636,22 +717,42 @@ __global__ __launch_bounds__(256) void k_grad_mfma(const GradMfmaArgs A)
         }
         __syncthreads();
     }
-    for (int idx = threadIdx.x; idx < 32 * A.d; idx += 256) {
+    for (int idx = threadIdx.x; idx < 32 * A.d; idx += 64 * NW) {
         const int m = idx / A.d, t = idx - m * A.d;
         const int row = rows[m];
         if (row < 0)
             continue;
-        const double Rm = ((Rp[0][m] + Rp[1][m]) + Rp[2][m]) + Rp[3][m];
-        const double Gm = (double)Gp[m][t];
+        double Rm = 0.0;
+#pragma unroll
+        for (int q = 0; q < NW; ++q)
+            Rm += Rp[q][m];
         const double x = (double)A.bat32[(int64_t)row * DP + t];
-        A.dX[(int64_t)row * A.d + t] = (float)(A.cx * (x * Rm - Gm));
+        A.dX[(int64_t)row * A.d + t] = (float)(A.cx * (x * Rm - (double)Gp[m][t]));
     }
     if (threadIdx.x < 32) {
         const int m = threadIdx.x, row = rows[m];
         if (row >= 0) {
-            const double Sm = ((Sp[0][m] + Sp[1][m]) + Sp[2][m]) + Sp[3][m];
+            double Sm = 0.0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q)
+                Sm += Sp[q][m];
             A.rowds[row] = A.cs * (-2.0 * Sm * A.inv_s3 + A.dN[j]);
         }
+    }
+    // the last task to finish sums the row terms of df/ds in row order
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0)
+        last = atomicAdd(A.ticket, 1) == ntask - 1;
+    __syncthreads();
+    if (last) {
+        __threadfence();
+        double v = 0.0;
+        for (int r = threadIdx.x; r < A.b; r += 64 * NW)
+            v += __hip_atomic_load(&A.rowds[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v = block_sum(v, red);
+        if (threadIdx.x == 0)
+            *A.out = v;
     }
 }
 
@@ -671,7 +772,11 @@ void launch_grad_mfma(const Layout &L, const Buffers &B, int b, double sigma, co
     Gq.dX = dX;
     Gq.rowds = rowds;
     Gq.flags = B.flags;
-    hipLaunchKernelGGL(k_group_labels, dim3(1), dim3(1024), 0, st, Gq);
+    Gq.ticket = B.gr_cnt + 2 * L.k;
+    if (L.k <= kGroupLdsK)
+        hipLaunchKernelGGL(k_group_labels<true>, dim3(1), dim3(1024), 0, st, Gq);
+    else
+        hipLaunchKernelGGL(k_group_labels<false>, dim3(1), dim3(1024), 0, st, Gq);
     GradMfmaArgs A;
     A.b = b;
     A.d = L.d;
@@ -695,15 +800,16 @@ void launch_grad_mfma(const Layout &L, const Buffers &B, int b, double sigma, co
     A.cs = g / (double)b;
     A.dX = dX;
     A.rowds = rowds;
+    A.ticket = B.gr_cnt + 2 * L.k;
+    A.out = out;
     // at most ceil(b / 32) + k tasks (each group adds at most one partial block)
     const dim3 grid((unsigned)((b + 31) / 32 + L.k));
     switch (L.dp) {
-    case 32: hipLaunchKernelGGL(k_grad_mfma<32>, grid, dim3(256), 0, st, A); break;
-    case 64: hipLaunchKernelGGL(k_grad_mfma<64>, grid, dim3(256), 0, st, A); break;
-    case 96: hipLaunchKernelGGL(k_grad_mfma<96>, grid, dim3(256), 0, st, A); break;
-    default: hipLaunchKernelGGL(k_grad_mfma<128>, grid, dim3(256), 0, st, A); break;
+    case 32: hipLaunchKernelGGL(k_grad_mfma<32>, grid, dim3(64 * grad_waves<32>()), 0, st, A); break;
+    case 64: hipLaunchKernelGGL(k_grad_mfma<64>, grid, dim3(64 * grad_waves<64>()), 0, st, A); break;
+    case 96: hipLaunchKernelGGL(k_grad_mfma<96>, grid, dim3(64 * grad_waves<96>()), 0, st, A); break;
+    default: hipLaunchKernelGGL(k_grad_mfma<128>, grid, dim3(64 * grad_waves<128>()), 0, st, A); break;
     }
-    hipLaunchKernelGGL(k_sum_rows, dim3(1), dim3(1024), 0, st, (const double *)rowds, b, out);
 }
 
 int grad_max_dim() { return 64 * 16; }

@@ -189,15 +189,16 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.labels = (int32_t *)take(4 * (size_t)L.bmax);
     B.mind = (float *)take(4 * (size_t)L.bmax);
     B.margin = (float *)take(4 * (size_t)L.bmax);
-    B.obj = (double *)take(8 * 4);
-    B.flags = (int32_t *)take(4 * 4);
+    // device scalars and error flags, adjacent so that one copy reads both back
+    B.obj = (double *)take(8 * 4 + 4 * 4);
+    B.flags = (int32_t *)(B.obj + 4);
     B.nresc = (unsigned long long *)take(8);
     B.Nsig = (double *)take(8 * (size_t)L.k);
     B.dNsig = (double *)take(8 * (size_t)L.k);
     B.rowds = (double *)take(8 * (size_t)L.bmax);
     B.sg_toff = (int32_t *)take(4 * ((size_t)L.k + 1));
     B.sg_part = (double *)take(8 * 2 * ((size_t)kGramWaves + L.k));
-    B.gr_cnt = (int32_t *)take(4 * 2 * (size_t)L.k);
+    B.gr_cnt = (int32_t *)take(4 * (2 * (size_t)L.k + 1));  // counts, cursors, task ticket
     B.gr_loff = (int32_t *)take(4 * ((size_t)L.k + 1));
     B.gr_rtoff = (int32_t *)take(4 * ((size_t)L.k + 1));
     B.gr_perm = (int32_t *)take(4 * (size_t)L.bmax);
@@ -1057,15 +1058,16 @@ int mbkk_objective_fwd(mbkk_ctx *c, const float *xb_dev, int32_t b, double sigma
     HIPCHK(c, hipGetLastError());
     if (labels_dev)
         HIPCHK(c, hipMemcpyAsync(labels_dev, B.labels, 4 * (size_t)b, hipMemcpyDeviceToDevice, c->stream));
-    double s = 0.0;
-    int32_t f[2] = {0, 0};
-    HIPCHK(c, hipMemcpyAsync(&s, B.obj + 1, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(f, B.flags, sizeof(f), hipMemcpyDeviceToHost, c->stream));
+    // the device scalars and the flags in one read-back
+    double io[6];
+    HIPCHK(c, hipMemcpyAsync(io, B.obj, sizeof(io), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    int32_t f[4];
+    memcpy(f, io + 4, sizeof(f));
     if (f[1])
         return fail(c, MBKK_E_NONFINITE, "non-finite value in the coordinates");
     if (f_host)
-        *f_host = s / (double)b;
+        *f_host = io[1] / (double)b;
     return MBKK_OK;
 }
 
@@ -1100,14 +1102,14 @@ int mbkk_objective_bwd(mbkk_ctx *c, const float *xb_dev, int32_t b, double sigma
         launch_grad_rows(L, B, xb_dev, b, sigma, labels_dev, g, B.dNsig, dX_dev, B.rowds, B.obj + 2, c->stream);
     }
     HIPCHK(c, hipGetLastError());
-    double s = 0.0;
-    int32_t f[3] = {0, 0, 0};
-    HIPCHK(c, hipMemcpyAsync(&s, B.obj + 2, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(c, hipMemcpyAsync(f, B.flags, sizeof(f), hipMemcpyDeviceToHost, c->stream));
+    double io[6];
+    HIPCHK(c, hipMemcpyAsync(io, B.obj, sizeof(io), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    int32_t f[4];
+    memcpy(f, io + 4, sizeof(f));
     if (f[2])
         return fail(c, MBKK_E_INVALID, "label outside [0, k)");
-    *dsigma_host = s;
+    *dsigma_host = io[2];
     return MBKK_OK;
 }
 

@@ -120,7 +120,7 @@ struct Buffers {
     double *rowds = nullptr;     // [bmax] per-row terms of df/dsigma
     int32_t *sg_toff = nullptr;  // [k+1] task offsets of the self norms at a bandwidth (MFMA)
     double *sg_part = nullptr;   // [2 (kGramWaves + k)] their per-run partials (N, then d2-weighted)
-    int32_t *gr_cnt = nullptr;   // [2k] backward: group counts and scatter cursors
+    int32_t *gr_cnt = nullptr;   // [2k + 1] backward: group counts, scatter cursors, task ticket
     int32_t *gr_loff = nullptr;  // [k+1] row offsets of the groups
     int32_t *gr_rtoff = nullptr; // [k+1] offsets of the 32-row tasks
     int32_t *gr_perm = nullptr;  // [bmax] rows grouped by label
