@@ -117,11 +117,14 @@ def traffic_summary(args):
     copy_mib MiB to what the same counter reads for that copy."""
     fdir, wdir, cfdir, cwdir = args.traffic_summary
     wl = args.workload + ("u" if args.untruncated else "")
-    kern = ("k_dp_mfma" if args.workload == "c3" else "k_dp_table") if args.untruncated else ("k_cross_direct" if wl == "c5" else "k_cross_bs")
+    # the benchmark line's kernel: the BF16X3 cross kernel (template mode 1) on
+    # the Gaussian workloads, the VALU one on the L1 mixture
+    kern = ("k_dp_mfma" if args.workload == "c3" else "k_dp_table") if args.untruncated else (
+        "k_cross_direct" if wl == "c5" else "k_cross_bs<1,")
     src = DP_SRC if args.untruncated else CROSS_SRC
     fetch, write = _counter_means(fdir, "FETCH_SIZE"), _counter_means(wdir, "WRITE_SIZE")
     cf, cw = _counter_means(cfdir, "FETCH_SIZE"), _counter_means(cwdir, "WRITE_SIZE")
-    pick = lambda m, key: max(((v, n, k) for k, (v, n) in m.items() if key in k), default=None)
+    pick = lambda m, key: max(((v, n, k) for k, (v, n) in m.items() if key in k.replace(" ", "")), default=None)
     f, w = pick(fetch, kern), pick(write, kern)
     copy_f, copy_w = pick(cf, "copy"), pick(cw, "copy")
     if not (f and w and copy_f and copy_w):
