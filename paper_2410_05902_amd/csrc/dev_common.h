@@ -42,6 +42,47 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *lds, int *total)
     return res;
 }
 
+// Two exclusive scans (of a and of b) with one set of barriers; returns a's
+// scan, b's in *run_b, totals in *tot_a, *tot_b.  `lds` holds at least 32 ints.
+__device__ __forceinline__ int block_exclusive_scan2(int a, int b, int *lds, int *tot_a, int *run_b, int *tot_b)
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int x = a, y = b;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int xa = __shfl_up(x, o), yb = __shfl_up(y, o);
+        if (lane >= o) {
+            x += xa;
+            y += yb;
+        }
+    }
+    if (lane == 63) {
+        lds[wid] = x;
+        lds[16 + wid] = y;
+    }
+    __syncthreads();
+    if (wid == 0) {
+        int t = lane < nw ? lds[lane] : 0, u = lane < nw ? lds[16 + lane] : 0;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int ta = __shfl_up(t, o), ub = __shfl_up(u, o);
+            if (lane >= o) {
+                t += ta;
+                u += ub;
+            }
+        }
+        if (lane < nw) {
+            lds[lane] = t;
+            lds[16 + lane] = u;
+        }
+    }
+    __syncthreads();
+    const int ra = (wid > 0 ? lds[wid - 1] : 0) + x - a;
+    *run_b = (wid > 0 ? lds[16 + wid - 1] : 0) + y - b;
+    *tot_a = lds[nw - 1];
+    *tot_b = lds[16 + nw - 1];
+    __syncthreads();
+    return ra;
+}
+
 // Block-wide sum of one double per thread, in a fixed order (wave trees,
 // then the wave totals in order).  `lds` holds at least 16 doubles.
 __device__ __forceinline__ double block_sum(double v, double *lds)
@@ -194,34 +235,50 @@ __device__ __forceinline__ void gram_plan(int k, int C, int rr, uint32_t mask, i
 }
 
 // Block (j, c) of the Gram work just done (jc = j * C + c, njc = k * C): the
-// partials of the waves whose task ranges met jc (stored at gpart[w + jc]),
+// partials of the waves whose task ranges met jc (stored at gpart[w + jc];
+// nwaves: the wave count of the work kernel, which sets the ranges),
 // lane-strided with eight independent sums, then across the wave; every lane
-// returns the sum.  One fixed order, wherever the fold runs.
-__device__ __forceinline__ double gram_fold_jc(const int32_t *__restrict__ goff, const double *__restrict__ gpart,
-                                               int njc, int jc)
+// returns the sum.  One fixed order, wherever the fold runs.  Split in two so
+// that a caller can issue the offset loads early: the wave range [w0, w1]
+// (empty when the block has no tasks), then the sum over it.
+__device__ __forceinline__ void gram_fold_range(const int32_t *__restrict__ goff, int njc, int jc, int nwaves, int &w0,
+                                                int &w1)
+{
+    const int g0 = goff[jc], g1 = goff[jc + 1], T = goff[njc];
+    w0 = 1;
+    w1 = 0;
+    if (g1 > g0) {  // then T >= g1 > 0
+        const int chunk = (T + nwaves - 1) / nwaves;
+        w0 = g0 / chunk;
+        w1 = (g1 - 1) / chunk;
+    }
+}
+
+__device__ __forceinline__ double gram_fold_sum(const double *__restrict__ gpart, int jc, int w0, int w1)
 {
     const int lane = threadIdx.x & 63;
-    const int g0 = goff[jc], g1 = goff[jc + 1];
-    double s = 0.0;
-    if (g1 > g0) {
-        const int T = goff[njc];
-        const int chunk = (T + kGramWaves - 1) / kGramWaves;
-        const int w0 = g0 / chunk, w1 = (g1 - 1) / chunk;
-        const double *gp = gpart + jc;
-        double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        int w = w0 + lane;
-        for (; w + 7 * 64 <= w1; w += 8 * 64) {
+    const double *gp = gpart + jc;
+    double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int w = w0 + lane;
+    for (; w + 7 * 64 <= w1; w += 8 * 64) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                q[u] += gp[w + u * 64];
-        }
-        for (; w <= w1; w += 64)
-            q[0] += gp[w];
-        s = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
-        for (int o = 32; o > 0; o >>= 1)
-            s += __shfl_xor(s, o);
+        for (int u = 0; u < 8; ++u)
+            q[u] += gp[w + u * 64];
     }
+    for (; w <= w1; w += 64)
+        q[0] += gp[w];
+    double s = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
+    for (int o = 32; o > 0; o >>= 1)
+        s += __shfl_xor(s, o);
     return s;
+}
+
+__device__ __forceinline__ double gram_fold_jc(const int32_t *__restrict__ goff, const double *__restrict__ gpart,
+                                               int njc, int jc, int nwaves)
+{
+    int w0, w1;
+    gram_fold_range(goff, njc, jc, nwaves, w0, w1);
+    return gram_fold_sum(gpart, jc, w0, w1);
 }
 
 }  // namespace mbkk

@@ -39,7 +39,8 @@ int gram_task_cols(int mfma, int fp64);  // te of the plan for the chosen Gram f
 void launch_gram_plan(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int te, hipStream_t st);
 void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param, int fp64,
                  int mfma, bool fold, hipStream_t st);
-void launch_gram_fold(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, hipStream_t st);
+void launch_gram_fold(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int mfma, hipStream_t st);
+int gram_waves(int mfma);  // waves of the Gram work kernel of that form (its task ranges)
 
 // Cross term P = <phi(x), C_j> for the staged batch rows [0, nb).
 void launch_cross_direct(const Layout &L, const Buffers &B, int nb, int kind, double param, int fp64,

@@ -389,8 +389,8 @@ __global__ __launch_bounds__(256) void k_sigma_fold(const SigmaGramArgs A)
     const int j = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (j >= A.k)
         return;
-    const double sn = gram_fold_jc(A.toff, A.part, A.k, j);
-    const double sd = gram_fold_jc(A.toff, A.part2, A.k, j);
+    const double sn = gram_fold_jc(A.toff, A.part, A.k, j, kGramWaves);
+    const double sd = gram_fold_jc(A.toff, A.part2, A.k, j, kGramWaves);
     if (lane == 0) {
         A.N[j] = sn;
         A.dN[j] = sd * A.inv_s3;

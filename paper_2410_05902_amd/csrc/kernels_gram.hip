@@ -32,35 +32,74 @@ struct GramWork {
     const int32_t *ring_off, *ring_perm;
     const int32_t *goff;  // [k*C + 1] task offsets
     double *gpart;        // [kGramWaves + k*C] per-run partials
+    int nwaves;           // waves of the work kernel (sets the task ranges)
 };
 
 constexpr int kGramWG = 256;  // 4 waves per workgroup
+// LDS copy of the task offsets and the ring offsets (ints), when both fit
+constexpr int kGramStage = 4096;
+
+// gram_col with the offsets read once per wave into scalar registers.
+__device__ __forceinline__ GramCol gram_col_uniform(int k, int bmax, int j, int c, const int32_t *ring_off,
+                                                    const int32_t *__restrict__ ring_perm)
+{
+    GramCol g;
+    if (c == 0) {
+        g.n = 1;
+        g.perm = nullptr;
+        g.row0 = j;
+    } else {
+        const int32_t *o = ring_off + (int64_t)(c - 1) * (k + 1);
+        const int o0 = __builtin_amdgcn_readfirstlane(o[j]), o1 = __builtin_amdgcn_readfirstlane(o[j + 1]);
+        g.n = o1 - o0;
+        g.perm = ring_perm + (int64_t)(c - 1) * bmax + o0;
+        g.row0 = (int64_t)k + (int64_t)(c - 1) * bmax;
+    }
+    return g;
+}
 
 // Runs `task(a, e, ab, eb, lsum)` over this wave's task range; a = the slot's
 // rows of center j, e = column c's rows, (ab, eb) the task's row blocks.
+// Every thread of the workgroup calls it: when the task offsets and the ring
+// offsets fit in `stage`, the workgroup first copies them there with
+// coalesced loads, so the segment search and the column lookups read LDS.
 template <int TE, class Task>
-__device__ __forceinline__ void gram_wave_loop(const GramWork &A, Task &&task)
+__device__ __forceinline__ void gram_wave_loop(const GramWork &A, int32_t *stage, Task &&task)
 {
     const int lane = threadIdx.x & 63;
-    const int w = blockIdx.x * (kGramWG / 64) + (threadIdx.x >> 6);
+    // wave-uniform values are moved to scalar registers (readfirstlane)
+    const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * (kGramWG / 64) + (threadIdx.x >> 6));
     const int nJC = A.k * A.C;
+    const int nro = (A.C - 1) * (A.k + 1);
+    const int32_t *goff = A.goff, *ring_off = A.ring_off;
+    // the task count (a scalar load): a workgroup whose waves have no task
+    // leaves at once
     const int T = A.goff[nJC];
     if (T == 0)
         return;
-    const int chunk = (T + kGramWaves - 1) / kGramWaves;
+    const int chunk = (T + A.nwaves - 1) / A.nwaves;
+    if ((int64_t)blockIdx.x * (kGramWG / 64) * chunk >= T)
+        return;  // workgroup uniform
+    if (nJC + 1 + nro <= kGramStage) {  // workgroup uniform
+        for (int i = threadIdx.x; i < nJC + 1 + nro; i += kGramWG)
+            stage[i] = i <= nJC ? A.goff[i] : A.ring_off[i - (nJC + 1)];
+        __syncthreads();
+        goff = stage;
+        ring_off = stage + nJC + 1;
+    }
     const int64_t t0l = (int64_t)w * chunk;
     if (t0l >= T)
         return;  // wave uniform
     const int t0 = (int)t0l, t1 = min(T, t0 + chunk);
-    int jc = wave_segment_of(A.goff, nJC, t0);
+    int jc = __builtin_amdgcn_readfirstlane(wave_segment_of(goff, nJC, t0));
     int t = t0;
     while (t < t1) {  // wave uniform
-        const int g0 = A.goff[jc], g1 = A.goff[jc + 1];
+        const int g0 = __builtin_amdgcn_readfirstlane(goff[jc]), g1 = __builtin_amdgcn_readfirstlane(goff[jc + 1]);
         const int e = min(t1, g1);
         if (t < e) {
             const int j = jc / A.C, c = jc - j * A.C;
-            const GramCol a = gram_col(A.k, A.bmax, j, 1 + A.rr, A.ring_off, A.ring_perm);
-            const GramCol ec = gram_col(A.k, A.bmax, j, c, A.ring_off, A.ring_perm);
+            const GramCol a = gram_col_uniform(A.k, A.bmax, j, 1 + A.rr, ring_off, A.ring_perm);
+            const GramCol ec = gram_col_uniform(A.k, A.bmax, j, c, ring_off, A.ring_perm);
             const int nE = (ec.n + TE - 1) / TE;
             double lsum = 0.0;
             for (; t < e; ++t) {
@@ -125,7 +164,8 @@ __global__ __launch_bounds__(kGramWG) void k_gram_valu(const GramWork A, int d, 
     constexpr int DC = 32 / RPL;
     const int lane = threadIdx.x & 63;
     const KT prm = (KT)param;
-    gram_wave_loop<64 * RPL>(A, [&](const GramCol &a, const GramCol &ec, int ab, int eb, double &lsum) {
+    __shared__ int32_t stage[kGramStage];
+    gram_wave_loop<64 * RPL>(A, stage, [&](const GramCol &a, const GramCol &ec, int ab, int eb, double &lsum) {
         bool eok[RPL];
         int re[RPL];
 #pragma unroll
@@ -189,42 +229,59 @@ __global__ __launch_bounds__(kGramWG) void k_gram_valu(const GramWork A, int d, 
 // takes the row stride at run time.
 // ---------------------------------------------------------------------------
 template <int DP>
-__global__ __launch_bounds__(kGramWG) void k_gram_mfma(const GramWork A, int dp_rt, int zero_row,
+__global__ __launch_bounds__(kGramWG) __attribute__((amdgpu_waves_per_eu(3))) void k_gram_mfma(const GramWork A, int dp_rt, int zero_row,
                                                        const float *__restrict__ pool32,
                                                        const float *__restrict__ poolsq, float c2, float c1)
 {
     const int dp = DP > 0 ? DP : dp_rt;
     const int KS = dp / 2;
     __shared__ float sqa[kGramWG / 64][32];
+    __shared__ int32_t stage[kGramStage];
     const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
-    gram_wave_loop<32>(A, [&](const GramCol &a, const GramCol &ec, int ab, int eb, double &lsum) {
+    gram_wave_loop<32>(A, stage, [&](const GramCol &a, const GramCol &ec, int ab, int eb, double &lsum) {
         const int qa = ab * 32 + n, qe = eb * 32 + n;
-        const int64_t ra = qa < a.n ? gram_row(a, qa) : zero_row;
-        const int64_t re = qe < ec.n ? gram_row(ec, qe) : zero_row;
-        // lane n (h = 0) publishes the norm of a-row n for the output rows m
-        if (h == 0)
-            sqa[wl][n] = c1 * poolsq[ra];
-        const float se_ = c1 * poolsq[re];
+        // both permutation loads, then every row load, in flight together:
+        // clamped indices and selects, no branches (a is a slot column, so
+        // a.perm is set; column 0 of ec has no permutation and one row)
+        const int32_t *ep = ec.perm ? ec.perm : a.perm;
+        const int32_t pa = a.perm[min(qa, a.n - 1)];
+        const int32_t pe = ep[min(qe, ec.n - 1)];
+        const int64_t ra = qa < a.n ? a.row0 + pa : zero_row;
+        const int64_t re = qe < ec.n ? (ec.perm ? ec.row0 + pe : ec.row0) : zero_row;
+        const float sqa_v = poolsq[ra], sqe_v = poolsq[re];
         f32x16 acc;
 #pragma unroll
         for (int i = 0; i < 16; ++i)
             acc[i] = 0.0f;
         // lane half h takes the coordinates [h dp/2, (h+1) dp/2)
         const float *sa = pool32 + ra * dp + h * KS, *se = pool32 + re * dp + h * KS;
-        auto kstep = [&](int s4) {
-            const f32x4 av = *(const f32x4 *)(sa + s4), ev = *(const f32x4 *)(se + s4);
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], ev[u], acc, 0, 0, 0);
-        };
         if constexpr (DP > 0) {
+            // the task's coordinates are all loaded before the first product
+            constexpr int NS = DP / 8;
+            f32x4 av[NS], ev[NS];
 #pragma unroll
-            for (int s4 = 0; s4 < DP / 2; s4 += 4)
-                kstep(s4);
+            for (int q = 0; q < NS; ++q) {
+                av[q] = *(const f32x4 *)(sa + 4 * q);
+                ev[q] = *(const f32x4 *)(se + 4 * q);
+            }
+            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q][u], ev[q][u], acc, 0, 0, 0);
         } else {
-            for (int s4 = 0; s4 < KS; s4 += 4)
-                kstep(s4);
+            for (int s4 = 0; s4 < KS; s4 += 4) {
+                const f32x4 av = *(const f32x4 *)(sa + s4), ev = *(const f32x4 *)(se + s4);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], ev[u], acc, 0, 0, 0);
+            }
         }
+        // lane n (h = 0) publishes the norm of a-row n for the output rows m
+        if (h == 0)
+            sqa[wl][n] = c1 * sqa_v;
+        const float se_ = c1 * sqe_v;
         // lane: column n (e row), rows m = 8 (i/4) + 4 h + i%4 (a rows); the
         // row norms were written by this wave (in-order LDS access)
         if (qe < ec.n) {
@@ -251,7 +308,7 @@ __global__ __launch_bounds__(1024) void k_gram_plan(int k, int C, int rr, uint32
 
 // One wave per jc (gram_fold_jc).  In a step the fold runs instead inside
 // the next support layout (k_prepare), with the same summation.
-__global__ __launch_bounds__(256) void k_gram_fold(int k, int C, int rr, uint32_t mask,
+__global__ __launch_bounds__(256) void k_gram_fold(int k, int C, int rr, uint32_t mask, int nwaves,
                                                    const int32_t *__restrict__ goff,
                                                    const double *__restrict__ gpart, double *__restrict__ G)
 {
@@ -262,7 +319,7 @@ __global__ __launch_bounds__(256) void k_gram_fold(int k, int C, int rr, uint32_
     const int j = jc / C, c = jc - j * C;
     if (!((mask >> c) & 1u))
         return;
-    const double s = gram_fold_jc(goff, gpart, k * C, jc);
+    const double s = gram_fold_jc(goff, gpart, k * C, jc, nwaves);
     if (lane == 0) {
         double *g = G + (int64_t)j * C * C;
         g[(1 + rr) * C + c] = s;
@@ -302,7 +359,7 @@ static void launch_gram_mfma(const Layout &L, const Buffers &B, const GramWork &
 {
     const double l2e = 1.4426950408889634;
     const float c2 = (float)(2.0 * l2e / kappa), c1 = (float)(-l2e / kappa);
-    const dim3 grid(kGramWaves / (kGramWG / 64));
+    const dim3 grid(kGramWavesMfma / (kGramWG / 64));
     const int zr = (int)L.PR;
 #define MBKK_GM(DP) \
     hipLaunchKernelGGL((k_gram_mfma<DP>), grid, dim3(kGramWG), 0, st, A, L.dp, zr, B.pool32, B.poolsq, c2, c1)
@@ -328,6 +385,7 @@ void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t mask, int k
     A.ring_perm = B.ring_perm;
     A.goff = B.goff;
     A.gpart = B.gpart;
+    A.nwaves = gram_waves(mfma);
     if (mfma) {
         // every MFMA form: FP32 products (the BF16 forms' cross term alone is split)
         launch_gram_mfma(L, B, A, param, st);
@@ -337,14 +395,16 @@ void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t mask, int k
         launch_gram_valu<float>(L, B, A, kind, param, st);
     }
     if (fold)
-        launch_gram_fold(L, B, rr, mask, st);
+        launch_gram_fold(L, B, rr, mask, mfma, st);
 }
 
-void launch_gram_fold(const Layout &L, const Buffers &B, int rr, uint32_t mask, hipStream_t st)
+void launch_gram_fold(const Layout &L, const Buffers &B, int rr, uint32_t mask, int mfma, hipStream_t st)
 {
     const int njc = L.k * L.C;
-    hipLaunchKernelGGL(k_gram_fold, dim3((njc + 3) / 4), dim3(256), 0, st, L.k, L.C, rr, mask, B.goff, B.gpart,
-                       B.G);
+    hipLaunchKernelGGL(k_gram_fold, dim3((njc + 3) / 4), dim3(256), 0, st, L.k, L.C, rr, mask, gram_waves(mfma),
+                       B.goff, B.gpart, B.G);
 }
+
+int gram_waves(int mfma) { return mfma ? kGramWavesMfma : kGramWaves; }
 
 }  // namespace mbkk

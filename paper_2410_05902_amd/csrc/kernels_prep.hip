@@ -275,6 +275,7 @@ struct SupportArgs {
     uint32_t fold_mask;
     const int32_t *goff;
     const double *gpart;
+    int gram_waves;       // waves of the Gram work kernel that wrote gpart
     int32_t *seg_off, *sup_row;
     float *sup_w;
     double *sup_w64;
@@ -285,6 +286,13 @@ struct SupportArgs {
     float ay_scale;       // -log2(e) / kappa
 };
 
+// 256 threads.  Every load that depends on no other is issued first,
+// unconditionally at clamped indices (a load under a condition is waited on
+// before the next one goes out): the fold's task offsets, the coefficients,
+// the slot offsets of center j, the segment offsets and the old Gram blocks.
+// The fold then takes 16 lanes per column, so the partials of every column
+// are loaded in one round (before the barrier), every thread lays out
+// entries (permutations, then row norms), and N_j is taken from LDS.
 __device__ void support_fill_body(const SupportArgs &A, int j)
 {
     const int k = A.k, C = A.C, bmax = A.bmax, pad = A.pad;
@@ -300,39 +308,82 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
     float *__restrict__ sup_w = A.sup_w;
     double *__restrict__ sup_w64 = A.sup_w64;
     int32_t *__restrict__ blk_center = A.blk_center;
-    double *__restrict__ N = A.N;
     float *__restrict__ sup_ay = A.sup_ay;
     const float *__restrict__ poolsq = A.poolsq;
     const float ay_scale = A.ay_scale;
+    constexpr int MC = kMaxSlots + 1;  // columns at most
+    constexpr int FL = 16;             // fold lanes per column (columns [4 wv, 4 wv + 4) per wave)
     __shared__ int red[256];
     __shared__ int sh_start;
-    const int tid = threadIdx.x;
-    // Gram blocks of the last update's slot: one wave per column (the
-    // barriers of the prefix below publish them to the self norm)
-    if (A.fold_rr >= 0) {
-        const int rr = A.fold_rr;
-        for (int c = tid >> 6; c < C; c += 4) {  // wave uniform
-            if ((A.fold_mask >> c) & 1u) {
-                const double g = gram_fold_jc(A.goff, A.gpart, k * C, j * C + c);
-                if ((tid & 63) == 0) {
-                    double *gj = G + (int64_t)j * C * C;
-                    gj[(1 + rr) * C + c] = g;
-                    gj[c * C + 1 + rr] = g;
-                }
-            }
-        }
+    __shared__ double scf[MC];              // coef[j][c]
+    __shared__ double sG[MC * MC];          // G_j, with the folded blocks
+    __shared__ int sA0[kMaxSlots], sN[kMaxSlots];  // live slot s: first grouped row of j, rows (0: weight 0)
+    __shared__ int sSeg[2];
+    __shared__ int sBig[MC];                // column whose fold has more than FL partials
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const double *cfj = coef + (int64_t)j * C;
+    double *gj = G + (int64_t)j * C * C;
+    const int rr = A.fold_rr;
+    const bool fold = rr >= 0;
+    const bool lane_fold = C <= 4 * 4;  // every column in one 16-lane group
+    // ---- round 1
+    // the fold's task offsets: column fc of this 16-lane group
+    const int fcu = 4 * wv + lane / FL, fc = min(fcu, C - 1), fi = lane & (FL - 1);
+    const int fjc = j * C + fc;
+    const int fg0 = A.goff[fjc], fg1 = A.goff[fjc + 1], fT = A.goff[k * C];
+    // coefficient c = lane (wave 0)
+    const double v_cf = cfj[min(lane, C - 1)];
+    // live slot s = lane (wave 1): the offsets of center j and the weight
+    const int s1 = min(lane, max(live.n - 1, 0));
+    int p1 = 0;
+#pragma unroll
+    for (int s = 0; s < kMaxSlots; ++s)  // scalar reads of the slot list, then a select
+        p1 = s < live.n && s == s1 ? live.r[s] : p1;
+    const int32_t *o1p = ring_off + (int64_t)p1 * (k + 1);
+    const int a0v = o1p[j], a1v = o1p[j + 1];
+    const double w1v = cfj[1 + p1];
+    // segment offsets written by the update (seg_off itself when there are none)
+    const int32_t *snp = A.seg_next ? A.seg_next : seg_off;
+    const int sg0 = snp[j], sg1 = snp[j + 1];
+    // the old Gram blocks (waves 2-3)
+    const double v_g = gj[min(max(tid - 128, 0), C * C - 1)];
+    // ---- round 2 of the fold: its partials, one per lane
+    // wave range of the column (as gram_fold_range; branch-free, so that the
+    // task count's load is not sunk into a branch)
+    const int fchunk = max(1, (fT + A.gram_waves - 1) / A.gram_waves);
+    const bool fany = fg1 > fg0;
+    const int fw0 = fany ? fg0 / fchunk : 1, fw1 = fany ? (fg1 - 1) / fchunk : 0;
+    // (goff holds no plan before the first update: the index is formed only
+    // for a pending fold and kept inside the partials either way)
+    const int fwi = fold ? min(max(min(fw0 + fi, max(fw0, fw1)), 0), A.gram_waves - 1) : 0;
+    const double fv = A.gpart[fjc + fwi];
+    // ---- LDS
+    if (tid < C)
+        scf[tid] = v_cf;
+    if (tid >= 64 && tid < 64 + live.n) {
+        const int s = tid - 64;
+        sA0[s] = a0v;
+        sN[s] = w1v == 0.0 ? 0 : a1v - a0v;
     }
+    if (tid == 0) {
+        sSeg[0] = sg0;
+        sSeg[1] = sg1;
+    }
+    if (tid >= 128) {
+        if (tid - 128 < C * C)
+            sG[tid - 128] = v_g;
+        for (int q = tid; q < C * C; q += 128)  // C > 11
+            sG[q] = gj[q];
+    }
+    if (fi == 0 && fcu < C)
+        sBig[fcu] = fw1 - fw0 >= FL;
+    __syncthreads();
+    // ---- segment of center j
     int start, plen;
     if (A.seg_next) {
         // offsets written by the last update for this support
-        start = A.seg_next[j];
-        plen = A.seg_next[j + 1] - start;
-        if (tid == 0) {
-            seg_off[j] = start;
-            if (j == k - 1)
-                seg_off[k] = start + plen;
-        }
-        __syncthreads();
+        start = sSeg[0];
+        plen = sSeg[1] - start;
     } else {
         // exclusive prefix of the padded lengths of centers < j
         int acc = 0;
@@ -347,60 +398,88 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
                 red[tid] += red[tid + s];
             __syncthreads();
         }
-        const int len = seg_len(j, k, C, ring_off, coef, live, init_alive);
+        int len = init_alive && scf[0] != 0.0 ? 1 : 0;
+        for (int s = 0; s < live.n; ++s)
+            len += sN[s];
         plen = (len + pad - 1) / pad * pad;
-        if (tid == 0) {
+        if (tid == 0)
             sh_start = red[0];
-            seg_off[j] = red[0];
-            if (j == k - 1)
-                seg_off[k] = red[0] + plen;
-        }
         __syncthreads();
         start = sh_start;
     }
-    int pos = start;
-    if (init_alive && coef[(int64_t)j * C + 0] != 0.0) {
-        if (tid == 0) {
-            const double w = coef[(int64_t)j * C + 0];
-            sup_row[pos] = j;
-            sup_w[pos] = (float)w;
-            sup_w64[pos] = w;
+    if (tid == 0) {
+        seg_off[j] = start;
+        if (j == k - 1)
+            seg_off[k] = start + plen;
+    }
+    {
+        // ---- entries: the initial point (while alive, weight != 0), then the
+        // center's rows of every live slot with weight != 0, oldest first, then
+        // the zero row up to the padded length
+        const int ni = init_alive && scf[0] != 0.0 ? 1 : 0;
+        for (int q = tid; q < plen; q += 256) {
+            int64_t row = zero_row;
+            double w = 0.0;
+            if (q < ni) {
+                row = j;
+                w = scf[0];
+            } else {
+                int r = q - ni;
+                for (int s = 0; s < live.n; ++s) {
+                    const int ns = sN[s];
+                    if (r < ns) {
+                        const int p = live.r[s];
+                        row = (int64_t)k + (int64_t)p * bmax + ring_perm[(int64_t)p * bmax + sA0[s] + r];
+                        w = scf[1 + p];
+                        break;
+                    }
+                    r -= ns;
+                }
+            }
+            sup_row[start + q] = (int32_t)row;
+            sup_w[start + q] = (float)w;
+            sup_w64[start + q] = w;
             if (sup_ay)
-                sup_ay[pos] = ay_scale * poolsq[j];
+                sup_ay[start + q] = row == zero_row ? 0.0f : ay_scale * poolsq[row];
         }
-        ++pos;
-    }
-    for (int s = 0; s < live.n; ++s) {
-        const int p = live.r[s];
-        const int32_t *o = ring_off + (int64_t)p * (k + 1);
-        const int32_t *perm = ring_perm + (int64_t)p * bmax;
-        const double w = coef[(int64_t)j * C + 1 + p];
-        if (w == 0.0)
-            continue;  // (block uniform)
-        const int a0 = o[j], a1 = o[j + 1];
-        const int64_t row0 = (int64_t)k + (int64_t)p * bmax;
-        for (int q = tid; q < a1 - a0; q += 256) {
-            const int64_t row = row0 + perm[a0 + q];
-            sup_row[pos + q] = (int32_t)row;
-            sup_w[pos + q] = (float)w;
-            sup_w64[pos + q] = w;
-            if (sup_ay)
-                sup_ay[pos + q] = ay_scale * poolsq[row];
+        if (blk_center) {
+            for (int q = start / 32 + tid; q < (start + plen) / 32; q += 256)
+                blk_center[q] = j;
         }
-        pos += a1 - a0;
     }
-    for (int q = pos + tid; q < start + plen; q += 256) {
-        sup_row[q] = (int32_t)zero_row;
-        sup_w[q] = 0.0f;
-        sup_w64[q] = 0.0;
-        if (sup_ay)
-            sup_ay[q] = 0.0f;
+    // ---- Gram blocks of the last update's slot (gram_fold_jc's sums: up to
+    // FL partials in 16 lanes give the same additions as its 64-lane form,
+    // whose other lanes hold exact zeros)
+    if (fold) {
+        if (lane_fold) {
+            double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (fw0 + fi <= fw1)
+                q[0] += fv;
+            double sm = ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
+            for (int o = FL / 2; o > 0; o >>= 1)
+                sm += __shfl_xor(sm, o);
+            if (fi == 0 && fcu < C && ((A.fold_mask >> fcu) & 1u) && fw1 - fw0 < FL) {
+                sG[(1 + rr) * C + fcu] = sm;
+                sG[fcu * C + 1 + rr] = sm;
+                gj[(1 + rr) * C + fcu] = sm;
+                gj[fcu * C + 1 + rr] = sm;
+            }
+        }
+        // columns with more partials, or beyond the lane groups: one wave each
+        for (int c = wv; c < C; c += 4) {  // wave uniform
+            if (((A.fold_mask >> c) & 1u) && (!lane_fold || sBig[c])) {
+                const double g = gram_fold_jc(A.goff, A.gpart, k * C, j * C + c, A.gram_waves);
+                if (lane == 0) {
+                    sG[(1 + rr) * C + c] = g;
+                    sG[c * C + 1 + rr] = g;
+                    gj[(1 + rr) * C + c] = g;
+                    gj[c * C + 1 + rr] = g;
+                }
+            }
+        }
     }
-    if (blk_center) {
-        for (int q = start / 32 + tid; q < (start + plen) / 32; q += 256)
-            blk_center[q] = j;
-    }
-    // N_j from the Gram blocks (FP64), in a fixed order
+    __syncthreads();
+    // ---- N_j from the Gram blocks (FP64), in a fixed order
     if (tid == 0) {
         int cols[kMaxSlots + 1];
         int nc = 0;
@@ -408,13 +487,11 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
             cols[nc++] = 0;
         for (int s = 0; s < live.n; ++s)
             cols[nc++] = 1 + live.r[s];
-        const double *g = G + (int64_t)j * C * C;
-        const double *cf = coef + (int64_t)j * C;
         double nn = 0.0;
         for (int a = 0; a < nc; ++a)
             for (int e = 0; e < nc; ++e)
-                nn += cf[cols[a]] * cf[cols[e]] * g[cols[a] * C + cols[e]];
-        N[j] = nn;
+                nn += scf[cols[a]] * scf[cols[e]] * sG[cols[a] * C + cols[e]];
+        A.N[j] = nn;
     }
 }
 
@@ -449,6 +526,7 @@ void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const 
     S.fold_mask = fold_mask;
     S.goff = B.goff;
     S.gpart = B.gpart;
+    S.gram_waves = gram_waves(L.pad == kMfmaPad);
     S.seg_off = B.seg_off;
     S.sup_row = B.sup_row;
     S.sup_w = B.sup_w;
@@ -620,53 +698,76 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
     const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff, int pad, int32_t *__restrict__ seg_next)
 {
     constexpr int RPT = kMaxBatch / kGroupThreads;  // batch rows per thread
-    __shared__ int sint[16];
+    __shared__ int sint[32];
     __shared__ double sdbl[16];
-    __shared__ int scnt[kGroupLdsMax];    // per-(chunk, label) counts, then bases
+    __shared__ int scnt[kGroupLdsMax];    // per-(chunk, label) counts, then bases, then the grouped rows
+    __shared__ int sidx[kMaxBatch];       // the grouped rows' points
     __shared__ int spart[kGroupThreads];  // per-(slice, label) sums, then slice starts
     __shared__ int soff[kGroupSmallK];
     const int tid = threadIdx.x, nt = kGroupThreads;
-    // ---- independent loads
+    // ---- independent loads: unconditional, at clamped indices, and selected
+    // afterwards, so that none waits for another (a load under a condition
+    // is waited on before the next one is issued)
     int r_lab[RPT], r_rank[RPT], r_pt[RPT];
     float r_md[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
-        const int p = tid + i * nt;
-        const bool in = p < b;
-        r_lab[i] = in ? labels[p] : 0;
-        r_rank[i] = in ? rank[p] : 0;
-        r_pt[i] = in ? pts[p] : 0;
-        r_md[i] = in ? mind[p] : 0.0f;
+        const int pc = min(tid + i * nt, b - 1);  // b >= 1
+        r_lab[i] = labels[pc];
+        r_rank[i] = rank[pc];
+        r_pt[i] = pts[pc];
+        r_md[i] = mind[pc];
     }
     const bool own = tid < k;
-    const int j = tid;
+    const int j = tid, jc = min(tid, k - 1);
     double cf[kGroupSmallC];
+    int o0[kGroupSmallC], o1[kGroupSmallC];
+    double cumv = 0.0;
+    if ((tid & ~63) < k) {  // waves holding a center (one branch around every load)
+#pragma unroll
+        for (int c = 0; c < kGroupSmallC; ++c) {
+            const int cc = min(c, C - 1), sc = max(cc - 1, 0);
+            cf[c] = coef[(int64_t)jc * C + cc];
+            const int32_t *o = ring_off + (int64_t)sc * (k + 1);
+            o0[c] = o[jc];
+            o1[c] = o[jc + 1];
+        }
+        cumv = cum[jc];
+    } else {
+#pragma unroll
+        for (int c = 0; c < kGroupSmallC; ++c) {
+            cf[c] = 0.0;
+            o0[c] = o1[c] = 0;
+        }
+    }
+    constexpr int CPT = kGroupLdsMax / kGroupThreads;
+    int v[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q)
+        v[q] = gcnt[min(tid + q * nt, nchunk * k - 1)];
+    // ---- selections
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        if (tid + i * nt >= b) {
+            r_lab[i] = 0;
+            r_rank[i] = 0;
+            r_pt[i] = 0;
+            r_md[i] = 0.0f;
+        }
+    }
     int ne[kGroupSmallC];  // rows of center j in column c (other slots than the new one)
 #pragma unroll
     for (int c = 0; c < kGroupSmallC; ++c) {
-        cf[c] = own && c < C ? coef[(int64_t)j * C + c] : 0.0;
-        ne[c] = 0;
-        if (own && c >= 1 && c < C && c - 1 != p_new && ((gram_mask >> c) & 1u)) {
-            const int32_t *o = ring_off + (int64_t)(c - 1) * (k + 1);
-            ne[c] = o[j + 1] - o[j];
-        }
+        const bool colok = own && c < C;
+        cf[c] = colok ? cf[c] : 0.0;
+        ne[c] = colok && c >= 1 && c - 1 != p_new && ((gram_mask >> c) & 1u) ? o1[c] - o0[c] : 0;
     }
-    const double cumj = own && lr == MBKK_LR_SKLEARN ? cum[j] : 0.0;
-    {
-        // every count load in flight before the first LDS store
-        constexpr int CPT = kGroupLdsMax / kGroupThreads;
-        int v[CPT];
+    const double cumj = own && lr == MBKK_LR_SKLEARN ? cumv : 0.0;
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            const int i = tid + q * nt;
-            v[q] = i < nchunk * k ? gcnt[i] : 0;
-        }
-#pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            const int i = tid + q * nt;
-            if (i < nchunk * k)
-                scnt[i] = v[q];
-        }
+    for (int q = 0; q < CPT; ++q) {
+        const int i = tid + q * nt;
+        if (i < nchunk * k)
+            scnt[i] = v[q];
     }
     __syncthreads();
     // ---- label totals: slice sums over chunks, then per label over slices
@@ -787,14 +888,12 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
         }
         slen = (slen + pad - 1) / pad * pad;
     }
-    int stotal;
-    const int srun = block_exclusive_scan(slen, sint, &stotal);
+    int stotal, ttotal, trun;
+    const int srun = block_exclusive_scan2(slen, tasks, sint, &stotal, &trun, &ttotal);  // (its barriers also publish the bases)
     if (own)
         seg_next[j] = srun;
     if (tid == 0)
         seg_next[k] = stotal;
-    int ttotal;
-    int trun = block_exclusive_scan(tasks, sint, &ttotal);  // (its barriers also publish the bases)
     if (own) {
         const int nA = (bj + kGramTA - 1) / kGramTA;
 #pragma unroll
@@ -818,15 +917,31 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
     sm = block_sum(sm, sdbl);
     if (tid == 0)
         obj[0] = sm;
-    // ---- scatter: grouped position of every row = base of (chunk, label) + rank
+    // ---- scatter: grouped position of every row = base of (chunk, label) +
+    // rank, through LDS (the bases' array, then sidx), then written out in
+    // grouped order with coalesced stores
+    int pos[RPT];
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         const int p = tid + i * nt;
-        if (p < b) {
-            const int lab = min(max(r_lab[i], 0), k - 1);
-            const int pos = scnt[(p / kChunk) * k + lab] + r_rank[i];
-            ring_perm[pos] = p;
-            ring_idx[pos] = r_pt[i];
+        const int lab = min(max(r_lab[i], 0), k - 1);
+        pos[i] = p < b ? scnt[(p / kChunk) * k + lab] + r_rank[i] : -1;
+    }
+    __syncthreads();  // every base read before scnt is reused
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        if (pos[i] >= 0) {
+            scnt[pos[i]] = tid + i * nt;
+            sidx[pos[i]] = r_pt[i];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        const int q = tid + i * nt;
+        if (q < b) {
+            ring_perm[q] = scnt[q];
+            ring_idx[q] = sidx[q];
         }
     }
 }
