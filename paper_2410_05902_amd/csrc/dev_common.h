@@ -132,11 +132,12 @@ __device__ __forceinline__ int wave_segment_of(const int32_t *__restrict__ off, 
 //   G_j[c][c'] = sum_{a in column c of center j} sum_{e in column c' of center j} K(a, e)
 // (column 0: the initial point, 1 + p: the center's rows of slot p).  The
 // blocks of slot rr against a set of live columns are cut into tasks of
-// kGramTA rows of slot rr by `te` rows of the column:
-//   tasks(j, c) = ceil(na_j / kGramTA) * ceil(ne_jc / te),
+// `ta` rows of slot rr by `te` rows of the column:
+//   tasks(j, c) = ceil(na_j / ta) * ceil(ne_jc / te),
 // enumerated over jc = j * C + c with exclusive offsets goff[0 .. k*C].
 // ---------------------------------------------------------------------------
-constexpr int kGramTA = 32;
+constexpr int kGramTA = 32;      // slot rows per task of the VALU form
+constexpr int kGramTAMfma = 16;  // ... and of the MFMA form (16 x 16 tiles)
 
 // Rows of center j in column c: the slot rows through the grouping
 // permutation of their slot, column 0 the initial point (pool row j).
@@ -175,7 +176,7 @@ __device__ __forceinline__ int64_t gram_row(const GramCol &g, int q) { return g.
 // whose columns are `mask` (each center's rows over those columns, padded to
 // a multiple of pad): the layout of the next iteration when mask holds its
 // live columns.
-__device__ __forceinline__ void gram_plan(int k, int C, int rr, uint32_t mask, int te,
+__device__ __forceinline__ void gram_plan(int k, int C, int rr, uint32_t mask, int ta, int te,
                                           const int32_t *__restrict__ ring_off, const int32_t *na_own,
                                           const double *coef, int32_t *__restrict__ goff, int *sint,
                                           int pad = 1, int32_t *__restrict__ seg_next = nullptr)
@@ -195,7 +196,7 @@ __device__ __forceinline__ void gram_plan(int k, int C, int rr, uint32_t mask, i
         return o[j + 1] - o[j];
     };
     auto tasks = [&](int j, int c, int na) -> int {
-        return ((na + kGramTA - 1) / kGramTA) * ((rows(j, c, na) + te - 1) / te);
+        return ((na + ta - 1) / ta) * ((rows(j, c, na) + te - 1) / te);
     };
     int local = 0, slocal = 0;
     for (int j = j0; j < j1; ++j) {

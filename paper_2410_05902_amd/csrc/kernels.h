@@ -30,13 +30,14 @@ void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const 
 // each center, whose dropped columns get coefficient 0).
 void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
                    int init_keep, const SlotList &live, const WindowRank &win, int lr, uint32_t gram_mask,
-                   int gram_te, hipStream_t st);
+                   int gram_ta, int gram_te, hipStream_t st);
 
 // Gram blocks of slot rr against the columns in col_mask: plan (when not made
 // by the update), then work and fold.  mfma: the Gaussian MFMA forms (FP32
 // MFMA products in every precision form); else VALU in FP64 or FP32.
 int gram_task_cols(int mfma, int fp64);  // te of the plan for the chosen Gram form
-void launch_gram_plan(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int te, hipStream_t st);
+int gram_task_rows(int mfma);            // ta of the plan for the chosen Gram form
+void launch_gram_plan(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int ta, int te, hipStream_t st);
 void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param, int fp64,
                  int mfma, bool fold, hipStream_t st);
 void launch_gram_fold(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int mfma, hipStream_t st);

@@ -18,7 +18,7 @@
 //   k_gram_valu : any kernel, FP32 or FP64 arithmetic; a task is 32 slot
 //                 rows (wave-uniform) x 64 column rows (one per lane);
 //   k_gram_mfma : Gaussian MFMA forms; FP32 MFMA products and exp fused in
-//                 registers; a task is one 32 x 32 output block.  The BF16
+//                 registers; a task is one 16 x 16 output block.  The BF16
 //                 forms take their Gram blocks here too: the self norms keep
 //                 FP32 kernel values (summed in FP64), so a row re-scored in
 //                 FP64 carries only the FP32 error of N_j.
@@ -225,21 +225,25 @@ __global__ __launch_bounds__(kGramWG) void k_gram_valu(const GramWork A, int d, 
 
 // ---------------------------------------------------------------------------
 // MFMA tasks (Gaussian): exp(-(||a||^2 + ||e||^2 - 2 a.e) / kappa) with a.e
-// on FP32 MFMA 32x32x2 (every MFMA form, the BF16 ones included); DP = 0
-// takes the row stride at run time.
+// on FP32 MFMA 16x16x4 (every MFMA form, the BF16 ones included): a task is
+// a 16 x 16 block of (slot row, column row) pairs, so a cluster of b_j rows
+// pads to a multiple of 16 rather than 32.  Lane l = 16 g + n supplies
+// A[n][g] (slot row n) and B[g][n] (column row n) with g the quarter of the
+// coordinates it sums, [g dp/4, (g+1) dp/4); it holds D[4 g + i][n], i < 4.
+// DP = 0 takes the row stride at run time.
 // ---------------------------------------------------------------------------
 template <int DP>
-__global__ __launch_bounds__(kGramWG) __attribute__((amdgpu_waves_per_eu(3))) void k_gram_mfma(const GramWork A, int dp_rt, int zero_row,
-                                                       const float *__restrict__ pool32,
-                                                       const float *__restrict__ poolsq, float c2, float c1)
+__global__ __launch_bounds__(kGramWG) __attribute__((amdgpu_waves_per_eu(5))) void k_gram_mfma(
+    const GramWork A, int dp_rt, int zero_row, const float *__restrict__ pool32, const float *__restrict__ poolsq,
+    float c2, float c1)
 {
     const int dp = DP > 0 ? DP : dp_rt;
-    const int KS = dp / 2;
-    __shared__ float sqa[kGramWG / 64][32];
+    const int KQ = dp / 4;
+    __shared__ float sqa[kGramWG / 64][16];
     __shared__ int32_t stage[kGramStage];
-    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6, n = lane & 31, h = lane >> 5;
-    gram_wave_loop<32>(A, stage, [&](const GramCol &a, const GramCol &ec, int ab, int eb, double &lsum) {
-        const int qa = ab * 32 + n, qe = eb * 32 + n;
+    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6, n = lane & 15, g = lane >> 4;
+    gram_wave_loop<16>(A, stage, [&](const GramCol &a, const GramCol &ec, int ab, int eb, double &lsum) {
+        const int qa = ab * 16 + n, qe = eb * 16 + n;
         // both permutation loads, then every row load, in flight together:
         // clamped indices and selects, no branches (a is a slot column, so
         // a.perm is set; column 0 of ec has no permutation and one row)
@@ -249,15 +253,14 @@ __global__ __launch_bounds__(kGramWG) __attribute__((amdgpu_waves_per_eu(3))) vo
         const int64_t ra = qa < a.n ? a.row0 + pa : zero_row;
         const int64_t re = qe < ec.n ? (ec.perm ? ec.row0 + pe : ec.row0) : zero_row;
         const float sqa_v = poolsq[ra], sqe_v = poolsq[re];
-        f32x16 acc;
+        f32x4 acc;
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
+        for (int i = 0; i < 4; ++i)
             acc[i] = 0.0f;
-        // lane half h takes the coordinates [h dp/2, (h+1) dp/2)
-        const float *sa = pool32 + ra * dp + h * KS, *se = pool32 + re * dp + h * KS;
+        const float *sa = pool32 + ra * dp + g * KQ, *se = pool32 + re * dp + g * KQ;
         if constexpr (DP > 0) {
             // the task's coordinates are all loaded before the first product
-            constexpr int NS = DP / 8;
+            constexpr int NS = DP / 16;
             f32x4 av[NS], ev[NS];
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
@@ -269,26 +272,26 @@ __global__ __launch_bounds__(kGramWG) __attribute__((amdgpu_waves_per_eu(3))) vo
             for (int q = 0; q < NS; ++q)
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q][u], ev[q][u], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q][u], ev[q][u], acc, 0, 0, 0);
         } else {
-            for (int s4 = 0; s4 < KS; s4 += 4) {
+            for (int s4 = 0; s4 < KQ; s4 += 4) {
                 const f32x4 av = *(const f32x4 *)(sa + s4), ev = *(const f32x4 *)(se + s4);
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], ev[u], acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], ev[u], acc, 0, 0, 0);
             }
         }
-        // lane n (h = 0) publishes the norm of a-row n for the output rows m
-        if (h == 0)
+        // lane n (g = 0) publishes the norm of slot row n for the output rows m
+        if (g == 0)
             sqa[wl][n] = c1 * sqa_v;
         const float se_ = c1 * sqe_v;
-        // lane: column n (e row), rows m = 8 (i/4) + 4 h + i%4 (a rows); the
-        // row norms were written by this wave (in-order LDS access)
+        // lane: column n (column row), rows m = 4 g + i (slot rows); the row
+        // norms were written by this wave (in-order LDS access)
         if (qe < ec.n) {
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int m = 8 * (i >> 2) + 4 * h + (i & 3);
-                if (ab * 32 + m < a.n)
+            for (int i = 0; i < 4; ++i) {
+                const int m = 4 * g + i;
+                if (ab * 16 + m < a.n)
                     lsum += (double)__builtin_amdgcn_exp2f(fmaf(acc[i], c2, sqa[wl][m] + se_));
             }
         }
@@ -298,12 +301,12 @@ __global__ __launch_bounds__(kGramWG) __attribute__((amdgpu_waves_per_eu(3))) vo
 // ---------------------------------------------------------------------------
 // plan (outside a step) and fold
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void k_gram_plan(int k, int C, int rr, uint32_t mask, int te,
+__global__ __launch_bounds__(1024) void k_gram_plan(int k, int C, int rr, uint32_t mask, int ta, int te,
                                                     const int32_t *__restrict__ ring_off,
                                                     const double *__restrict__ coef, int32_t *__restrict__ goff)
 {
     __shared__ int sint[16];
-    gram_plan(k, C, rr, mask, te, ring_off, nullptr, coef, goff, sint);
+    gram_plan(k, C, rr, mask, ta, te, ring_off, nullptr, coef, goff, sint);
 }
 
 // One wave per jc (gram_fold_jc).  In a step the fold runs instead inside
@@ -329,12 +332,14 @@ __global__ __launch_bounds__(256) void k_gram_fold(int k, int C, int rr, uint32_
 
 int gram_task_cols(int mfma, int fp64)
 {
-    return mfma ? 32 : 64 * (fp64 ? gram_valu_rpl<double>() : gram_valu_rpl<float>());
+    return mfma ? 16 : 64 * (fp64 ? gram_valu_rpl<double>() : gram_valu_rpl<float>());
 }
 
-void launch_gram_plan(const Layout &L, const Buffers &B, int rr, uint32_t mask, int te, hipStream_t st)
+int gram_task_rows(int mfma) { return mfma ? kGramTAMfma : kGramTA; }
+
+void launch_gram_plan(const Layout &L, const Buffers &B, int rr, uint32_t mask, int ta, int te, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_gram_plan, dim3(1), dim3(1024), 0, st, L.k, L.C, rr, mask, te, B.ring_off, B.coef,
+    hipLaunchKernelGGL(k_gram_plan, dim3(1), dim3(1024), 0, st, L.k, L.C, rr, mask, ta, te, B.ring_off, B.coef,
                        B.goff);
 }
 

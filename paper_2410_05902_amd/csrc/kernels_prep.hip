@@ -567,7 +567,7 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
     double *__restrict__ coef, double *__restrict__ cum, int32_t *__restrict__ counts,
     double *__restrict__ alpha, int32_t *__restrict__ off, double *__restrict__ obj,
     const int32_t *__restrict__ labels, const int32_t *__restrict__ rank, const int32_t *__restrict__ pts,
-    int32_t *__restrict__ ring_idx, int32_t *__restrict__ ring_perm, uint32_t gram_mask, int gram_te,
+    int32_t *__restrict__ ring_idx, int32_t *__restrict__ ring_perm, uint32_t gram_mask, int gram_ta, int gram_te,
     const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff, int pad, int32_t *__restrict__ seg_next)
 {
     __shared__ int sint[16];
@@ -663,7 +663,7 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
         off[k] = b;
     // task offsets of the Gram blocks of the new slot (its counts are this
     // thread's b_i^j above; the other live slots' offsets are settled)
-    gram_plan(k, C, p_new, gram_mask, gram_te, ring_off, counts, coef, goff, sint, pad, seg_next);
+    gram_plan(k, C, p_new, gram_mask, gram_ta, gram_te, ring_off, counts, coef, goff, sint, pad, seg_next);
     // sum of min distances (FP64), fixed order
     double sm = 0.0;
     for (int p = tid; p < b; p += nt)
@@ -694,7 +694,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
     double *__restrict__ coef, double *__restrict__ cum, int32_t *__restrict__ counts,
     double *__restrict__ alpha, int32_t *__restrict__ off, double *__restrict__ obj,
     const int32_t *__restrict__ labels, const int32_t *__restrict__ rank, const int32_t *__restrict__ pts,
-    int32_t *__restrict__ ring_idx, int32_t *__restrict__ ring_perm, uint32_t gram_mask, int gram_te,
+    int32_t *__restrict__ ring_idx, int32_t *__restrict__ ring_perm, uint32_t gram_mask, int gram_ta, int gram_te,
     const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff, int pad, int32_t *__restrict__ seg_next)
 {
     constexpr int RPT = kMaxBatch / kGroupThreads;  // batch rows per thread
@@ -877,7 +877,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
                 coef[(int64_t)j * C + c] = cf[c];
         // Gram tasks of the new slot against the live columns that keep a
         // weight, and the padded segment of center j in the next support
-        const int nA = (bj + kGramTA - 1) / kGramTA;
+        const int nA = (bj + gram_ta - 1) / gram_ta;
 #pragma unroll
         for (int c = 0; c < kGroupSmallC; ++c) {
             if (c < C && ((gram_mask >> c) & 1u) && cf[c] != 0.0) {
@@ -895,7 +895,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
     if (tid == 0)
         seg_next[k] = stotal;
     if (own) {
-        const int nA = (bj + kGramTA - 1) / kGramTA;
+        const int nA = (bj + gram_ta - 1) / gram_ta;
 #pragma unroll
         for (int c = 0; c < kGroupSmallC; ++c) {
             if (c < C) {
@@ -948,7 +948,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
 
 void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
                    int init_keep, const SlotList &live, const WindowRank &win, int lr, uint32_t gram_mask,
-                   int gram_te, hipStream_t st)
+                   int gram_ta, int gram_te, hipStream_t st)
 {
     const int nchunk = (b + kChunk - 1) / kChunk;
 #define MBKK_GO(LDS)                                                                                             \
@@ -957,14 +957,14 @@ void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_ex
                        B.counts,                                                                                 \
                        B.alpha, B.ring_off + (int64_t)p_new * (L.k + 1), B.obj, B.labels, B.rank,                 \
                        B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,               \
-                       B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_te, B.ring_off, B.goff, L.pad,  \
+                       B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_ta, gram_te, B.ring_off, B.goff, L.pad,  \
                        B.seg_next)
     if (L.k <= kGroupSmallK && (int64_t)nchunk * L.k <= kGroupLdsMax && L.C <= kGroupSmallC)
         hipLaunchKernelGGL(k_group_offsets_small, dim3(1), dim3(kGroupThreads), 0, st, b, L.k, nchunk, L.C, p_new,
                            p_expired, init_alive_before, init_keep, live, win, lr, B.gcnt, B.mind, B.coef, B.cum,
                            B.counts, B.alpha, B.ring_off + (int64_t)p_new * (L.k + 1), B.obj, B.labels, B.rank,
                            B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,
-                           B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_te, B.ring_off, B.goff, L.pad,
+                           B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_ta, gram_te, B.ring_off, B.goff, L.pad,
                            B.seg_next);
     else if ((int64_t)nchunk * L.k <= kGroupLdsMax)
         MBKK_GO(true);

@@ -325,7 +325,8 @@ static uint32_t col_mask_of(const SlotList &s, bool init_alive)
 static void gram(mbkk_ctx *c, int p, uint32_t mask, bool in_step)
 {
     if (!in_step)
-        launch_gram_plan(c->L, c->B, p, mask, gram_task_cols(c->use_mfma, c->fp64), c->stream);
+        launch_gram_plan(c->L, c->B, p, mask, gram_task_rows(c->use_mfma), gram_task_cols(c->use_mfma, c->fp64),
+                         c->stream);
     launch_gram(c->L, c->B, p, mask, c->cfg.kernel, c->cfg.kernel_param, c->fp64, c->use_mfma, !in_step, c->stream);
     if (in_step) {
         c->fold_rr = p;
@@ -789,7 +790,7 @@ int mbkk_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels_dev,
     for (int q = 0; q < live_after.n; ++q)
         win.rank[live_after.r[q]] = q;
     launch_update(L, B, b, p_new, p_expired, init_alive_before, init_keep, live, win, c->cfg.lr, mask,
-                  gram_task_cols(c->use_mfma, c->fp64), c->stream);
+                  gram_task_rows(c->use_mfma), gram_task_cols(c->use_mfma, c->fp64), c->stream);
     gram(c, p_new, mask, true);
     c->seg_next_iter = i + 1;
     HIPCHK(c, hipGetLastError());

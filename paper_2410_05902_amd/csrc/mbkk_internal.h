@@ -32,7 +32,7 @@ constexpr int kNumCU = 256;
 constexpr int kDirectWGs = 2048;  // workgroups of the direct (VALU) cross kernel: ranges x row tiles (8 waves per SIMD)
 constexpr int kSnSplit = 64;      // workgroups per center of the self norms at a bandwidth (differentiation form)
 constexpr int kGramWaves = 5120;  // waves of the VALU Gram work kernel and the self norms at a bandwidth (5 per SIMD)
-constexpr int kGramWavesMfma = 3072;  // waves of the MFMA Gram work kernel (3 per SIMD: its occupancy)
+constexpr int kGramWavesMfma = 5120;  // waves of the MFMA Gram work kernel (5 per SIMD: its occupancy)
 
 // Physical slots of the live batches, oldest batch first.
 struct SlotList {
