@@ -1279,6 +1279,74 @@ __device__ __forceinline__ double cross_of(const T *__restrict__ part, int ldp, 
     }
 }
 
+// cross_of in two phases, so that the loads of several centers are in
+// flight together: cross_fetch issues the first two partials of the segment
+// at clamped indices (no branch), cross_finish adds them in cross_of's order
+// and, for a segment spanning more than two ranges, the rest in a loop.
+template <typename T>
+struct CrossFetch {
+    T a, b;
+    int lo, hi, next;  // LAYOUT 0: segment [lo, hi) in entries, next range r; 1: blocks [lo, hi), next block
+};
+
+// s0, s1: seg_off[j], seg_off[j + 1]; mtot: seg_off[k]
+template <typename T, int LAYOUT>
+__device__ __forceinline__ CrossFetch<T> cross_fetch_at(const T *__restrict__ part, int ldp, int row, int j, int s0,
+                                                        int s1, int mtot, int RB, int k)
+{
+    CrossFetch<T> f;
+    if constexpr (LAYOUT == 0) {
+        f.lo = s0;
+        f.hi = s1;
+        const int r1 = f.lo / RB + 1;
+        const int nr = (mtot + RB - 1) / RB;  // ranges that hold partials
+        f.a = part[(int64_t)j * ldp + row];
+        f.b = part[(int64_t)(k + max(min(r1, nr - 1), 0)) * ldp + row];
+        f.next = r1 * RB < f.hi ? r1 + 1 : -1;
+    } else {
+        f.lo = s0 / 32;
+        f.hi = s1 / 32;
+        const int b1 = (f.lo / RB + 1) * RB;
+        const int top = max(f.hi - 1, 0);
+        f.a = part[(int64_t)min(f.lo, top) * ldp + row];
+        f.b = part[(int64_t)min(b1, top) * ldp + row];
+        f.next = b1 < f.hi ? b1 + RB : -1;
+    }
+    return f;
+}
+
+template <typename T, int LAYOUT>
+__device__ __forceinline__ CrossFetch<T> cross_fetch(const T *__restrict__ part, int ldp, int row, int j,
+                                                     const int32_t *__restrict__ seg_off, int RB, int k)
+{
+    return cross_fetch_at<T, LAYOUT>(part, ldp, row, j, seg_off[j], seg_off[j + 1], seg_off[k], RB, k);
+}
+
+template <typename T, int LAYOUT>
+__device__ __forceinline__ double cross_finish(const CrossFetch<T> &f, const T *__restrict__ part, int ldp, int row,
+                                               int RB, int k)
+{
+    if (f.lo >= f.hi)
+        return 0.0;
+    if constexpr (LAYOUT == 0) {
+        double s = (double)f.a;
+        if (f.next >= 0) {
+            s += (double)f.b;
+            for (int r = f.next; r * RB < f.hi; ++r)
+                s += (double)part[(int64_t)(k + r) * ldp + row];
+        }
+        return s;
+    } else {
+        float s = f.a;
+        if (f.next >= 0) {
+            s += f.b;
+            for (int blk = f.next; blk < f.hi; blk += RB)
+                s += part[(int64_t)blk * ldp + row];
+        }
+        return (double)s;
+    }
+}
+
 // One workgroup per 64 batch rows; its 16 waves split the centers (wave w
 // takes j = w, w + 16, ...), each lane one row, then the 16 partial
 // (best, label, second) triples of a row are merged in LDS.  Ties go to the
@@ -1403,21 +1471,61 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
     const int row = blockIdx.x * 64 + lane;
     const bool act = row < A.nb;
     const T *part = (const T *)A.part;
-    const double kxx = act ? self_kernel(A.kind, A.param, A.batsq64[row]) : 0.0;
+    const double x2row = A.batsq64[min(row, A.nb - 1)];
+    // loads in issue order: the LDS copy's first pass, then the partials of
+    // the wave's first batch of centers (j = w, w + 16, ...), whose segment
+    // bounds are scalar loads (the center index is wave-uniform), so that
+    // the partials are requested before the barriers below.  Hoisted in the
+    // FP32 forms only (the FP64 form has no registers left for it).
+    constexpr int NB = 8;
+    constexpr bool HOIST = sizeof(T) == 4;
+    int sv0 = 0;
+    double nv0 = 0.0;
+    if constexpr (LK) {
+        const int i = min((int)threadIdx.x, A.k);
+        sv0 = A.seg_off[i];
+        nv0 = A.N[min(i, A.k - 1)];
+    }
+    const int mtot = A.seg_off[A.k];
+    const int RB = LAYOUT == 0 ? direct_range_rows(mtot, A.nranges)
+                               : (A.nranges > 0 ? bs_range_blocks(mtot / 32, A.nranges) : A.RB);
+    CrossFetch<T> fe0[HOIST ? NB : 1];
+    if constexpr (HOIST) {
+        int s0[NB], s1[NB];
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int j = min(w + u * kScoreWaves, A.k - 1);
+            s0[u] = A.seg_off[j];
+            s1[u] = A.seg_off[j + 1];
+        }
+        __builtin_amdgcn_sched_barrier(0);  // every bound requested before the first partial
+#pragma unroll
+        for (int u = 0; u < NB; ++u)
+            fe0[u] = cross_fetch_at<T, LAYOUT>(part, A.ldp, min(row, A.nb - 1), min(w + u * kScoreWaves, A.k - 1),
+                                               s0[u], s1[u], mtot, RB, A.k);
+    }
     const int32_t *seg_off = A.seg_off;
     const double *Nv = A.N;
     if constexpr (LK) {
-        for (int i = threadIdx.x; i <= A.k; i += 64 * kScoreWaves) {
-            lseg[i] = A.seg_off[i];
+        if ((int)threadIdx.x <= A.k) {
+            lseg[threadIdx.x] = sv0;
+            if ((int)threadIdx.x < A.k)
+                lN[threadIdx.x] = nv0;
+        }
+        __builtin_amdgcn_sched_barrier(0);  // (these stores wait for the copy's loads only)
+        for (int i = threadIdx.x + 64 * kScoreWaves; i <= A.k; i += 64 * kScoreWaves) {
+            const int sv = A.seg_off[i];
+            const double nv = A.N[min(i, A.k - 1)];
+            __builtin_amdgcn_sched_barrier(0);  // both loads before either store
+            lseg[i] = sv;
             if (i < A.k)
-                lN[i] = A.N[i];
+                lN[i] = nv;
         }
         __syncthreads();
         seg_off = lseg;
         Nv = lN;
     }
-    const int RB = LAYOUT == 0 ? direct_range_rows(seg_off[A.k], A.nranges)
-                               : (A.nranges > 0 ? bs_range_blocks(seg_off[A.k] / 32, A.nranges) : A.RB);
+    const double kxx = act ? self_kernel(A.kind, A.param, x2row) : 0.0;
     if constexpr (RESCORE) {
         // longest center segment: the length of the FP32 sums in the error bound
         if (threadIdx.x == 0) {
@@ -1437,14 +1545,24 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
     int lab = 0x7fffffff;
     if (act) {
         // the wave's centers j = w, w + 16, ... in batches of 8 whose loads
-        // are all in flight together
-        constexpr int NB = 8;
+        // are all in flight together (the first batch's since the start)
         for (int j0 = w; j0 < A.k; j0 += kScoreWaves * NB) {
             double P[NB], Nj[NB];
+            CrossFetch<T> fe[NB];
+            if (HOIST && j0 == w) {
+#pragma unroll
+                for (int u = 0; u < NB; ++u)
+                    fe[u] = fe0[HOIST ? u : 0];
+            } else {
+#pragma unroll
+                for (int u = 0; u < NB; ++u)
+                    fe[u] = cross_fetch<T, LAYOUT>(part, A.ldp, row, min(j0 + u * kScoreWaves, A.k - 1), seg_off, RB,
+                                                   A.k);
+            }
 #pragma unroll
             for (int u = 0; u < NB; ++u) {
                 const int j = j0 + u * kScoreWaves;
-                P[u] = j < A.k ? cross_of<T, LAYOUT>(part, A.ldp, row, j, seg_off, RB, A.k) : 0.0;
+                P[u] = j < A.k ? cross_finish<T, LAYOUT>(fe[u], part, A.ldp, row, RB, A.k) : 0.0;
                 Nj[u] = j < A.k ? Nv[j] : 0.0;
             }
 #pragma unroll

@@ -22,99 +22,10 @@
 //                 forms take their Gram blocks here too: the self norms keep
 //                 FP32 kernel values (summed in FP64), so a row re-scored in
 //                 FP64 carries only the FP32 error of N_j.
-#include "dev_common.h"
+#include "gram_body.h"
 #include "kernels.h"
 
 namespace mbkk {
-
-struct GramWork {
-    int k, C, bmax, rr;
-    const int32_t *ring_off, *ring_perm;
-    const int32_t *goff;  // [k*C + 1] task offsets
-    double *gpart;        // [kGramWaves + k*C] per-run partials
-    int nwaves;           // waves of the work kernel (sets the task ranges)
-};
-
-constexpr int kGramWG = 256;  // 4 waves per workgroup
-// LDS copy of the task offsets and the ring offsets (ints), when both fit
-constexpr int kGramStage = 4096;
-
-// gram_col with the offsets read once per wave into scalar registers.
-__device__ __forceinline__ GramCol gram_col_uniform(int k, int bmax, int j, int c, const int32_t *ring_off,
-                                                    const int32_t *__restrict__ ring_perm)
-{
-    GramCol g;
-    if (c == 0) {
-        g.n = 1;
-        g.perm = nullptr;
-        g.row0 = j;
-    } else {
-        const int32_t *o = ring_off + (int64_t)(c - 1) * (k + 1);
-        const int o0 = __builtin_amdgcn_readfirstlane(o[j]), o1 = __builtin_amdgcn_readfirstlane(o[j + 1]);
-        g.n = o1 - o0;
-        g.perm = ring_perm + (int64_t)(c - 1) * bmax + o0;
-        g.row0 = (int64_t)k + (int64_t)(c - 1) * bmax;
-    }
-    return g;
-}
-
-// Runs `task(a, e, ab, eb, lsum)` over this wave's task range; a = the slot's
-// rows of center j, e = column c's rows, (ab, eb) the task's row blocks.
-// Every thread of the workgroup calls it: when the task offsets and the ring
-// offsets fit in `stage`, the workgroup first copies them there with
-// coalesced loads, so the segment search and the column lookups read LDS.
-template <int TE, class Task>
-__device__ __forceinline__ void gram_wave_loop(const GramWork &A, int32_t *stage, Task &&task)
-{
-    const int lane = threadIdx.x & 63;
-    // wave-uniform values are moved to scalar registers (readfirstlane)
-    const int w = __builtin_amdgcn_readfirstlane(blockIdx.x * (kGramWG / 64) + (threadIdx.x >> 6));
-    const int nJC = A.k * A.C;
-    const int nro = (A.C - 1) * (A.k + 1);
-    const int32_t *goff = A.goff, *ring_off = A.ring_off;
-    // the task count (a scalar load): a workgroup whose waves have no task
-    // leaves at once
-    const int T = A.goff[nJC];
-    if (T == 0)
-        return;
-    const int chunk = (T + A.nwaves - 1) / A.nwaves;
-    if ((int64_t)blockIdx.x * (kGramWG / 64) * chunk >= T)
-        return;  // workgroup uniform
-    if (nJC + 1 + nro <= kGramStage) {  // workgroup uniform
-        for (int i = threadIdx.x; i < nJC + 1 + nro; i += kGramWG)
-            stage[i] = i <= nJC ? A.goff[i] : A.ring_off[i - (nJC + 1)];
-        __syncthreads();
-        goff = stage;
-        ring_off = stage + nJC + 1;
-    }
-    const int64_t t0l = (int64_t)w * chunk;
-    if (t0l >= T)
-        return;  // wave uniform
-    const int t0 = (int)t0l, t1 = min(T, t0 + chunk);
-    int jc = __builtin_amdgcn_readfirstlane(wave_segment_of(goff, nJC, t0));
-    int t = t0;
-    while (t < t1) {  // wave uniform
-        const int g0 = __builtin_amdgcn_readfirstlane(goff[jc]), g1 = __builtin_amdgcn_readfirstlane(goff[jc + 1]);
-        const int e = min(t1, g1);
-        if (t < e) {
-            const int j = jc / A.C, c = jc - j * A.C;
-            const GramCol a = gram_col_uniform(A.k, A.bmax, j, 1 + A.rr, ring_off, A.ring_perm);
-            const GramCol ec = gram_col_uniform(A.k, A.bmax, j, c, ring_off, A.ring_perm);
-            const int nE = (ec.n + TE - 1) / TE;
-            double lsum = 0.0;
-            for (; t < e; ++t) {
-                const int u = t - g0;
-                const int ab = u / nE, eb = u - ab * nE;
-                task(a, ec, ab, eb, lsum);
-            }
-            for (int o = 32; o > 0; o >>= 1)
-                lsum += __shfl_xor(lsum, o);
-            if (lane == 0)
-                A.gpart[w + jc] = lsum;
-        }
-        ++jc;
-    }
-}
 
 // ---------------------------------------------------------------------------
 // VALU tasks
@@ -165,7 +76,7 @@ __global__ __launch_bounds__(kGramWG) void k_gram_valu(const GramWork A, int d, 
     const int lane = threadIdx.x & 63;
     const KT prm = (KT)param;
     __shared__ int32_t stage[kGramStage];
-    gram_wave_loop<64 * RPL>(A, stage, [&](const GramCol &a, const GramCol &ec, int ab, int eb, double &lsum) {
+    gram_wave_loop<64 * RPL>(A, stage, blockIdx.x, [&](const GramCol &a, const GramCol &ec, int ab, int eb, double &lsum) {
         bool eok[RPL];
         int re[RPL];
 #pragma unroll
@@ -223,79 +134,13 @@ __global__ __launch_bounds__(kGramWG) void k_gram_valu(const GramWork A, int d, 
     });
 }
 
-// ---------------------------------------------------------------------------
-// MFMA tasks (Gaussian): exp(-(||a||^2 + ||e||^2 - 2 a.e) / kappa) with a.e
-// on FP32 MFMA 16x16x4 (every MFMA form, the BF16 ones included): a task is
-// a 16 x 16 block of (slot row, column row) pairs, so a cluster of b_j rows
-// pads to a multiple of 16 rather than 32.  Lane l = 16 g + n supplies
-// A[n][g] (slot row n) and B[g][n] (column row n) with g the quarter of the
-// coordinates it sums, [g dp/4, (g+1) dp/4); it holds D[4 g + i][n], i < 4.
-// DP = 0 takes the row stride at run time.
-// ---------------------------------------------------------------------------
+// MFMA tasks (Gaussian): gram_mfma_work, 5 waves per SIMD.
 template <int DP>
 __global__ __launch_bounds__(kGramWG) __attribute__((amdgpu_waves_per_eu(5))) void k_gram_mfma(
     const GramWork A, int dp_rt, int zero_row, const float *__restrict__ pool32, const float *__restrict__ poolsq,
     float c2, float c1)
 {
-    const int dp = DP > 0 ? DP : dp_rt;
-    const int KQ = dp / 4;
-    __shared__ float sqa[kGramWG / 64][16];
-    __shared__ int32_t stage[kGramStage];
-    const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6, n = lane & 15, g = lane >> 4;
-    gram_wave_loop<16>(A, stage, [&](const GramCol &a, const GramCol &ec, int ab, int eb, double &lsum) {
-        const int qa = ab * 16 + n, qe = eb * 16 + n;
-        // both permutation loads, then every row load, in flight together:
-        // clamped indices and selects, no branches (a is a slot column, so
-        // a.perm is set; column 0 of ec has no permutation and one row)
-        const int32_t *ep = ec.perm ? ec.perm : a.perm;
-        const int32_t pa = a.perm[min(qa, a.n - 1)];
-        const int32_t pe = ep[min(qe, ec.n - 1)];
-        const int64_t ra = qa < a.n ? a.row0 + pa : zero_row;
-        const int64_t re = qe < ec.n ? (ec.perm ? ec.row0 + pe : ec.row0) : zero_row;
-        const float sqa_v = poolsq[ra], sqe_v = poolsq[re];
-        f32x4 acc;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            acc[i] = 0.0f;
-        const float *sa = pool32 + ra * dp + g * KQ, *se = pool32 + re * dp + g * KQ;
-        if constexpr (DP > 0) {
-            // the task's coordinates are all loaded before the first product
-            constexpr int NS = DP / 16;
-            f32x4 av[NS], ev[NS];
-#pragma unroll
-            for (int q = 0; q < NS; ++q) {
-                av[q] = *(const f32x4 *)(sa + 4 * q);
-                ev[q] = *(const f32x4 *)(se + 4 * q);
-            }
-            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
-#pragma unroll
-            for (int q = 0; q < NS; ++q)
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q][u], ev[q][u], acc, 0, 0, 0);
-        } else {
-            for (int s4 = 0; s4 < KQ; s4 += 4) {
-                const f32x4 av = *(const f32x4 *)(sa + s4), ev = *(const f32x4 *)(se + s4);
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], ev[u], acc, 0, 0, 0);
-            }
-        }
-        // lane n (g = 0) publishes the norm of slot row n for the output rows m
-        if (g == 0)
-            sqa[wl][n] = c1 * sqa_v;
-        const float se_ = c1 * sqe_v;
-        // lane: column n (column row), rows m = 4 g + i (slot rows); the row
-        // norms were written by this wave (in-order LDS access)
-        if (qe < ec.n) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int m = 4 * g + i;
-                if (ab * 16 + m < a.n)
-                    lsum += (double)__builtin_amdgcn_exp2f(fmaf(acc[i], c2, sqa[wl][m] + se_));
-            }
-        }
-    });
+    gram_mfma_work<DP>(A, dp_rt, zero_row, pool32, poolsq, c2, c1, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------

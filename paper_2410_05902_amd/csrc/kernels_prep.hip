@@ -103,58 +103,135 @@ struct GatherArgs {
     int64_t frag_lo;  // byte offset of the lo fragments
 };
 
-// One wave per row; `blk` numbers groups of 4 rows.
+// Four rows per wave, 16 per workgroup (`blk` numbers groups of 16 rows):
+// the index loads of the four rows, then every coordinate load of a stretch
+// of 128 coordinates of the four rows, go out before the first store
+// (clamped indices, selects; restrict pointers, so the stores do not order
+// the loads).
+constexpr int kGatherRowsPerWave = 4;
+constexpr int kGatherRowsPerBlock = 4 * kGatherRowsPerWave;
+
 __device__ __forceinline__ void gather_rows_body(const GatherArgs &A, int64_t blk)
 {
+    constexpr int RW = kGatherRowsPerWave;
     const int lane = threadIdx.x & 63;
-    const int64_t row = blk * 4 + (threadIdx.x >> 6);
-    if (row >= A.cnt)
+    const int64_t row0 = blk * kGatherRowsPerBlock + (threadIdx.x >> 6) * RW;
+    if (row0 >= A.cnt)
         return;
-    const int64_t p = A.idx ? (int64_t)A.idx[row] : row;
-    const bool ok = p >= 0 && p < A.n;
-    if (!ok && lane == 0)
-        atomicOr(&A.flags[0], 1);
-    if (A.idx_copy && lane == 0)
-        A.idx_copy[row] = (int32_t)p;
-    const float *src = A.X + (ok ? p : 0) * A.ld;
-    double s = 0.0;
-    bool finite = true;
-    for (int t = lane; t < A.dp; t += 64) {
-        const float v = (ok && t < A.d) ? src[t] : 0.0f;
-        finite &= isfinite(v);
-        A.out32[row * A.dp + t] = v;
-        if (A.outhi) {
-            const uint16_t h = f32_to_bf16_rne(v);
-            const uint16_t l = f32_to_bf16_rne(v - bf16_to_f32(h));
-            A.outhi[row * A.dp + t] = h;
-            A.outlo[row * A.dp + t] = l;
-            if (A.frag_mode == 1) {
-                // 32x32x16 BF16 fragment order: k-step ks = t / 16 of block
-                // row / 32; lane 32 (t / 8 % 2) + row % 32, element t % 8
-                const int64_t f = ((((row >> 5) * (A.dp >> 4) + (t >> 4)) * 64 + ((t >> 3) & 1) * 32 + (row & 31))
-                                   << 3) + (t & 7);
-                ((uint16_t *)A.frag)[f] = h;
-                ((uint16_t *)(A.frag + A.frag_lo))[f] = l;
+    const float *__restrict__ X = A.X;
+    float *__restrict__ out32 = A.out32;
+    uint16_t *__restrict__ outhi = A.outhi;
+    uint16_t *__restrict__ outlo = A.outlo;
+    int64_t p[RW];
+    bool live[RW], ok[RW];
+    if (A.idx) {  // (uniform)
+        int32_t iv[RW];
+#pragma unroll
+        for (int q = 0; q < RW; ++q)
+            iv[q] = A.idx[min(row0 + q, A.cnt - 1)];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            asm volatile("" : "+v"(iv[q]));  // the value is used here: no load is sunk into a branch
+            p[q] = iv[q];
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < RW; ++q)
+            p[q] = min(row0 + q, A.cnt - 1);
+    }
+#pragma unroll
+    for (int q = 0; q < RW; ++q)
+        live[q] = row0 + q < A.cnt;
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+        ok[q] = p[q] >= 0 && p[q] < A.n;
+        if (live[q] && lane == 0) {
+            if (!ok[q])
+                atomicOr(&A.flags[0], 1);
+            if (A.idx_copy)
+                A.idx_copy[row0 + q] = (int32_t)p[q];
+        }
+    }
+    double s[RW];
+    bool finite[RW];
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+        s[q] = 0.0;
+        finite[q] = true;
+    }
+    for (int t0 = 0; t0 < A.dp; t0 += 128) {
+        float v[RW][2];
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            const float *src = X + (ok[q] ? p[q] : 0) * A.ld;
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+                v[q][u] = src[min(t0 + lane + 64 * u, A.d - 1)];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                asm volatile("" : "+v"(v[q][u]));  // (as above)
+                v[q][u] = ok[q] && t0 + lane + 64 * u < A.d ? v[q][u] : 0.0f;
             }
         }
-        if (A.frag_mode == 2) {
-            // 32x32x2 FP32 fragment order: lane half hh = t / (dp/2) holds the
-            // coordinates hh dp/2 + 4 q + e of row row % 32, chunk q
-            const int ks = A.dp >> 1, hh = t / ks, r2 = t - hh * ks;
-            const int64_t f =
-                ((((row >> 5) * (ks >> 2) + (r2 >> 2)) * 64 + hh * 32 + (row & 31)) << 2) + (r2 & 3);
-            ((float *)A.frag)[f] = v;
+#pragma unroll
+        for (int q = 0; q < RW; ++q) {
+            if (!live[q])
+                continue;  // (wave uniform)
+            const int64_t row = row0 + q;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int t = t0 + lane + 64 * u;
+                if (t >= A.dp)
+                    continue;
+                const float x = v[q][u];
+                finite[q] &= isfinite(x);
+                out32[row * A.dp + t] = x;
+                if (outhi) {
+                    const uint16_t h = f32_to_bf16_rne(x);
+                    const uint16_t l = f32_to_bf16_rne(x - bf16_to_f32(h));
+                    outhi[row * A.dp + t] = h;
+                    outlo[row * A.dp + t] = l;
+                    if (A.frag_mode == 1) {
+                        // 32x32x16 BF16 fragment order: k-step ks = t / 16 of block
+                        // row / 32; lane 32 (t / 8 % 2) + row % 32, element t % 8
+                        const int64_t f =
+                            ((((row >> 5) * (A.dp >> 4) + (t >> 4)) * 64 + ((t >> 3) & 1) * 32 + (row & 31)) << 3) +
+                            (t & 7);
+                        ((uint16_t *)A.frag)[f] = h;
+                        ((uint16_t *)(A.frag + A.frag_lo))[f] = l;
+                    }
+                }
+                if (A.frag_mode == 2) {
+                    // 32x32x2 FP32 fragment order: lane half hh = t / (dp/2) holds the
+                    // coordinates hh dp/2 + 4 q + e of row row % 32, chunk q
+                    const int ks = A.dp >> 1, hh = t / ks, r2 = t - hh * ks;
+                    const int64_t f =
+                        ((((row >> 5) * (ks >> 2) + (r2 >> 2)) * 64 + hh * 32 + (row & 31)) << 2) + (r2 & 3);
+                    ((float *)A.frag)[f] = x;
+                }
+                s[q] += (double)x * (double)x;
+            }
         }
-        s += (double)v * (double)v;
     }
-    if (A.check_finite && !finite)
-        atomicOr(&A.flags[1], 1);
-    for (int o = 32; o > 0; o >>= 1)
-        s += __shfl_xor(s, o);
-    if (lane == 0) {
-        A.outsq[row] = (float)s;
-        if (A.outsq64)
-            A.outsq64[row] = s;
+#pragma unroll
+    for (int q = 0; q < RW; ++q) {
+        if (!live[q])
+            continue;
+        if (A.check_finite && !finite[q])
+            atomicOr(&A.flags[1], 1);
+        double sq = s[q];
+        for (int o = 32; o > 0; o >>= 1)
+            sq += __shfl_xor(sq, o);
+        if (lane == 0) {
+            A.outsq[row0 + q] = (float)sq;
+            if (A.outsq64)
+                A.outsq64[row0 + q] = sq;
+        }
     }
 }
 
@@ -170,7 +247,7 @@ void launch_gather_rows(const float *X, int64_t n, int d, int64_t ld, const int3
     const GatherArgs A{X,        n,     d,         ld,    idx,          cnt,       dp,   out32,
                        outhi,    outlo, outsq,     outsq64, idx_copy,   flags,     check_finite,
                        frag_mode, frag, frag_lo};
-    const int64_t blocks = (cnt + 3) / 4;
+    const int64_t blocks = (cnt + kGatherRowsPerBlock - 1) / kGatherRowsPerBlock;
     hipLaunchKernelGGL(k_gather_rows, dim3((unsigned)blocks), dim3(256), 0, st, A);
 }
 
@@ -375,8 +452,9 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
         for (int q = tid; q < C * C; q += 128)  // C > 11
             sG[q] = gj[q];
     }
-    if (fi == 0 && fcu < C)
+    if (fi == 0 && fcu < C) {
         sBig[fcu] = fw1 - fw0 >= FL;
+    }
     __syncthreads();
     // ---- segment of center j
     int start, plen;
@@ -496,7 +574,7 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
 }
 
 // One launch prepares an iteration: workgroups [0, nsup) lay out the support
-// of C_i (one per center), the others stage the batch rows (4 per workgroup).
+// of C_i (one per center), the others stage the batch rows (16 per workgroup).
 __global__ __launch_bounds__(256) void k_prepare(const SupportArgs S, int nsup, const GatherArgs Gth)
 {
     if ((int)blockIdx.x < nsup)
@@ -541,7 +619,7 @@ void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const 
                          B.batidx,  B.flags,   check_finite, L.frag_mode, B.batfrag,
                          2 * (int64_t)frag_rows(L) * L.dp};
     const int nsup = with_support ? L.k : 0;
-    const int64_t ngat = cnt > 0 ? (cnt + 3) / 4 : 0;
+    const int64_t ngat = cnt > 0 ? (cnt + kGatherRowsPerBlock - 1) / kGatherRowsPerBlock : 0;
     if (nsup + ngat > 0)
         hipLaunchKernelGGL(k_prepare, dim3((unsigned)(nsup + ngat)), dim3(256), 0, st, S, nsup, Gth);
 }
