@@ -47,17 +47,22 @@ def log(*a):
 
 
 CROSS_SRC = os.path.join(ROOT, "paper_2410_05902_amd", "csrc", "kernels_cross.hip")
+# headers whose code the cross kernels compile (their hash covers these too)
+CROSS_DEPS = [os.path.join(ROOT, "paper_2410_05902_amd", "csrc", "cross_layout.h")]
 CROSS_KERNEL = {"gauss": "k_cross_bs", "laplace": "k_cross_direct"}
 DP_SRC = os.path.join(ROOT, "paper_2410_05902_amd", "csrc", "kernels_dp.hip")
 
 
 def source_sha(path: str = CROSS_SRC) -> str:
-    """Hash of a kernel source's code: comments and blank space removed, so an
-    edit of the comments keeps the counters taken on the code valid."""
+    """Hash of a kernel source's code (with the headers it depends on):
+    comments and blank space removed, so an edit of the comments keeps the
+    counters taken on the code valid."""
     import hashlib
     import re
-    with open(path) as f:
-        text = f.read()
+    text = ""
+    for p in [path] + (CROSS_DEPS if path == CROSS_SRC else []):
+        with open(p) as f:
+            text += f.read() + "\n"
     text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
     text = re.sub(r"//[^\n]*", " ", text)
     text = " ".join(text.split())

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 OUT = os.path.join(PKG, "libmbkk.so")
 BUILD_DIR = os.path.join(PKG, "_build")
-SOURCES = ["kernels_prep.hip", "kernels_cross.hip", "kernels_gram.hip", "kernels_init.hip", "kernels_grad.hip",
+SOURCES = ["kernels_prep.hip", "kernels_cross.hip", "kernels_score.hip", "kernels_gram.hip", "kernels_init.hip", "kernels_grad.hip",
            "microbench.hip",
            "kernels_metrics.hip", "kernels_dp.hip", "mbkk_host.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
