@@ -31,13 +31,9 @@ inline int direct_nranges(int nb, int rpl)
 
 constexpr int kBsStageBlocks = 4;  // support blocks (32 rows) per stage of the MFMA kernel
 
-// Blocks per range for Mb support blocks split over nranges ranges: a
-// multiple of the stage size.
-__host__ __device__ inline int bs_range_blocks(int Mb, int nranges)
-{
-    const int rb = (Mb + nranges - 1) / nranges;
-    return (rb + kBsStageBlocks - 1) / kBsStageBlocks * kBsStageBlocks;
-}
+// Blocks per range for Mb support blocks split over nranges ranges (the
+// kernel's last stage of a range skips the blocks past it).
+__host__ __device__ inline int bs_range_blocks(int Mb, int nranges) { return (Mb + nranges - 1) / nranges; }
 
 // Waves per SIMD: two in the BF16X3 form with row stride above 64, whose
 // two waves on a SIMD take turns, one issuing MFMAs while the other runs its

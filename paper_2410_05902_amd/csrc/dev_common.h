@@ -166,6 +166,21 @@ __device__ __forceinline__ GramCol gram_col(int k, int bmax, int j, int c, const
 
 __device__ __forceinline__ int64_t gram_row(const GramCol &g, int q) { return g.perm ? g.row0 + g.perm[q] : g.row0; }
 
+// Length of a center's segment holding len entries: a multiple of pad, or
+// (packed) the entries rounded up to a multiple of kPackAlign, at least pad
+// when there are any; and the end of the whole support (packed: rounded up
+// to a multiple of pad).
+constexpr int kPackAlign = 8;
+__host__ __device__ inline int seg_padded_len(int len, int pad, bool packed)
+{
+    return packed ? (len > 0 ? max((len + kPackAlign - 1) / kPackAlign * kPackAlign, pad) : 0)
+                  : (len + pad - 1) / pad * pad;
+}
+__host__ __device__ inline int seg_padded_end(int total, int pad, bool packed)
+{
+    return packed ? (total + pad - 1) / pad * pad : total;
+}
+
 // Task offsets of the blocks of slot rr against the columns in `mask`, by
 // one workgroup (blockDim.x a multiple of 64, at most 1024).  Thread t owns
 // the centers [t * per, (t + 1) * per), per = ceil(k / blockDim.x); na_own,
@@ -179,7 +194,8 @@ __device__ __forceinline__ int64_t gram_row(const GramCol &g, int q) { return g.
 __device__ __forceinline__ void gram_plan(int k, int C, int rr, uint32_t mask, int ta, int te,
                                           const int32_t *__restrict__ ring_off, const int32_t *na_own,
                                           const double *coef, int32_t *__restrict__ goff, int *sint,
-                                          int pad = 1, int32_t *__restrict__ seg_next = nullptr)
+                                          int pad = 1, int32_t *__restrict__ seg_next = nullptr,
+                                          bool packed = false)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int per = (k + nt - 1) / nt;
@@ -206,7 +222,7 @@ __device__ __forceinline__ void gram_plan(int k, int C, int rr, uint32_t mask, i
             local += tasks(j, c, na);
             len += rows(j, c, na);
         }
-        slocal += (len + pad - 1) / pad * pad;
+        slocal += seg_padded_len(len, pad, packed);
     }
     if (seg_next) {
         int stotal;
@@ -217,10 +233,10 @@ __device__ __forceinline__ void gram_plan(int k, int C, int rr, uint32_t mask, i
             for (int c = 0; c < C; ++c)
                 len += rows(j, c, na);
             seg_next[j] = srun;
-            srun += (len + pad - 1) / pad * pad;
+            srun += seg_padded_len(len, pad, packed);
         }
         if (threadIdx.x == 0)
-            seg_next[k] = stotal;
+            seg_next[k] = seg_padded_end(stotal, pad, packed);
     }
     int total;
     int run = block_exclusive_scan(local, sint, &total);

@@ -592,10 +592,14 @@ __global__ __launch_bounds__(256, 2) void k_cross_mfma(const CrossArgs A)
 //  - The exp epilogue of block b-1 is issued between the MFMAs of block b,
 //    in program order, each MFMA with its share of VALU work fenced off from
 //    the scheduler: the VALU work then issues while the matrix core is busy.
-//  - Consecutive blocks of one center are summed in registers; a run is
-//    written once, at its first block ("run head": the first block of a
-//    center or of a range), so the partial buffer holds one value per
-//    (run, batch row).
+//  - Segments are packed (a center's entries rounded up to a multiple of 8,
+//    at least 32 when it has any), so a block holds at most one row where a
+//    center starts (blk_split), a multiple of 8.  Consecutive rows of one
+//    center are summed in registers; the epilogue of a block where a center
+//    starts inside moves the finishing run's sums aside at that row group.  A run is written once, at slot 2 b of
+//    the block b it starts at (a range start, or a center starting at the
+//    block's first row) or at slot 2 b + 1 (a center starting inside block
+//    b), so the partial buffer holds one value per (run, batch row).
 // Grid: (#ranges x #batch tiles of 128 NBK rows), one round of workgroups
 // (one per compute unit), XCD-aware: the workgroups of one XCD share support
 // ranges.
@@ -619,7 +623,7 @@ struct CrossBsArgs {
     const uint16_t *poolhi, *poollo;
     const int32_t *sup_row;
     const float *sup_w, *sup_ay;
-    const int32_t *blk_center;
+    const int32_t *blk_split;  // row of each block where a center starts (32: none)
     const char *batfrag;  // the batch in fragment order (see gather_rows_body), hi then lo
     int64_t frag_lo;      // byte offset of the lo fragments
     const float *batsq;
@@ -762,12 +766,14 @@ __global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(con
         for (int q = 0; q < NT; ++q)
             pidx[q] = bufIdx(bi)[dma_row(q)];
     };
-    // centers of the range's blocks: lane l of cen_win holds block blk0 + cw0 + l
-    // (blocks past the range take the range's last block: they never end a run)
-    int cw0 = 0, cen_win = 0;
-    auto load_cen_win = [&](int base) {
+    // where centers start in the range's blocks: lane l of spl_win holds the
+    // row of block blk0 + cw0 + l where a center starts, 32 for none (blocks
+    // past the range: none)
+    int cw0 = 0, spl_win = 32;
+    auto load_spl_win = [&](int base) {
         cw0 = base;
-        cen_win = A.blk_center[min(blk0 + base + lane, blk1 - 1)];
+        const int b = blk0 + base + lane;
+        spl_win = b < blk1 ? A.blk_split[b] : 32;
     };
     auto issue_slot = [&](auto bc, int q) {  // DMA slot q of every staged array (pidx[q] holds its row)
 #pragma unroll
@@ -830,7 +836,7 @@ __global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(con
     {
         constexpr int QPB = F32 ? KS / 4 : KS;
         load_idx(0);
-        load_cen_win(0);
+        load_spl_win(0);
 #pragma unroll
         for (int nbk = 0; nbk < NBK; ++nbk) {
             const int row = b0 + nbk * 32 + n;
@@ -875,10 +881,14 @@ __global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(con
     // running epilogue is done with them (rows 0-7 at half time, rows 8-15 at
     // the end).  The first support fragments of the next block of the stage
     // are read during the last k-step.
-    float run[NBK];
+    // run: the running center's sums; hold: those of the center that ended
+    // inside the block whose epilogue ran last (a center started there)
+    float run[NBK], hold[NBK];
 #pragma unroll
-    for (int nbk = 0; nbk < NBK; ++nbk)
+    for (int nbk = 0; nbk < NBK; ++nbk) {
         run[nbk] = 0.0f;
+        hold[nbk] = 0.0f;
+    }
     const float c2 = A.c2;
     f32x4 eay[4], ew[4];
 #pragma unroll
@@ -898,12 +908,23 @@ __global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(con
     constexpr int NEL = 16 * NBK;                 // epilogue elements per lane
     constexpr int HALF = NMF / 2;                 // after it, rows 0-7 of the epilogue are done
     static_assert(NEL * HALF / NMF >= 8 * NBK || true, "");
-    auto epi_range = [&](const f32x16 (&accP)[NBK], int e0, int e1) {
+    // rs: the block's row where a center starts (wave-uniform; 8, 16, 24 inside
+    // the block).  The elements run in row-group order (e < 4 g NBK: rows below
+    // 8 g, in both lane halves), so at the group where the new center starts
+    // the finished center's sums move to hold and run restarts.
+    auto epi_range = [&](const f32x16 (&accP)[NBK], int e0, int e1, int rs) {
 #pragma unroll
         for (int e = e0; e < e1; ++e) {
+            if (e > 0 && e % (4 * NBK) == 0 && rs == 2 * e / NBK) {  // rows 8 g .. : e = 4 g NBK
+#pragma unroll
+                for (int q = 0; q < NBK; ++q) {
+                    hold[q] = run[q];
+                    run[q] = 0.0f;
+                }
+            }
             const int i = e / NBK, nbk = e % NBK;
-            run[nbk] = fmaf(ew[i / 4][i % 4],
-                            __builtin_amdgcn_exp2f(fmaf(accP[nbk][i], c2, eay[i / 4][i % 4])), run[nbk]);
+            run[nbk] = fmaf(ew[i / 4][i % 4], __builtin_amdgcn_exp2f(fmaf(accP[nbk][i], c2, eay[i / 4][i % 4])),
+                            run[nbk]);
         }
     };
     // Carried support fragments of the next block: k-step 0 (a0h / a0l) and,
@@ -931,7 +952,7 @@ __global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(con
     };
     // The element range of MFMA mi: the epilogue is spread evenly; rows 0-7
     // (elements < 8 NBK) are finished by MFMA HALF - 1.
-    auto share = [&](const f32x16 (&accP)[NBK], int mi, auto bc, int sub) {
+    auto share = [&](const f32x16 (&accP)[NBK], int mi, auto bc, int sub, int rs) {
         int e0 = mi * NEL / NMF, e1 = (mi + 1) * NEL / NMF;
         if (mi < HALF) {
             e1 = min(e1, 8 * NBK);
@@ -941,7 +962,7 @@ __global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(con
         } else {
             e0 = max(e0, 8 * NBK);
         }
-        epi_range(accP, e0, e1);
+        epi_range(accP, e0, e1, rs);
         if (mi == HALF - 1)
             load_ayw(bc, sub, 0, 2);
         if (mi == NMF - 1)
@@ -951,7 +972,7 @@ __global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(con
     // a0h / a0l), with the epilogue of the previous block (accP) spread
     // between them; reads the next block's k-step 0 fragments when `nsub` >= 0.
     auto fused_block = [&](f32x16 (&accN)[NBK], const f32x16 (&accP)[NBK], auto bc, int sub, int nsub,
-                           auto hook) {
+                           auto hook, int rs) {
 #pragma unroll
         for (int nbk = 0; nbk < NBK; ++nbk)
 #pragma unroll
@@ -972,7 +993,7 @@ __global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(con
                     for (int nbk = 0; nbk < NBK; ++nbk) {
                         const int mi = ((s4 + u) * NBK + nbk);
                         accN[nbk] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[u], bh[nbk][s4 + u], accN[nbk], 0, 0, 0);
-                        share(accP, mi, bc, sub);
+                        share(accP, mi, bc, sub, rs);
                         hook(mi);
                         __builtin_amdgcn_sched_barrier(0);
                     }
@@ -1003,7 +1024,7 @@ __global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(con
                         const bf16x8 aa = pr == 2 ? al : ah;
                         const bf16x8 bb = pr == 1 ? bl[nbk][ks] : bh[nbk][ks];
                         accN[nbk] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aa, bb, accN[nbk], 0, 0, 0);
-                        share(accP, mi, bc, sub);
+                        share(accP, mi, bc, sub, rs);
                         hook(mi);
                         __builtin_amdgcn_sched_barrier(0);
                     }
@@ -1016,9 +1037,10 @@ __global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(con
             }
         }
     };
-    int run_head = blk0;
-    int run_center = __builtin_amdgcn_readlane(cen_win, 0);
-    auto flush = [&]() {
+    // partial slots: 2 b for the run from block b's start, 2 b + 1 for the run
+    // of a center that starts inside block b
+    int run_slot = 2 * blk0;
+    auto flush_vals = [&](float (&vals)[NBK]) {
         // lane l holds the half-sum (over rows with m % 8 in 4h..4h+3) of
         // column n of every N-block; swapping lanes 32-63 of block p with
         // lanes 0-31 of block p+1 puts both halves of block p in lanes < 32
@@ -1026,16 +1048,27 @@ __global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(con
 #pragma unroll
         for (int p = 0; p < NBK; p += 2) {
             const int q = p + 1 < NBK ? p + 1 : p;  // an unpaired last block pairs with itself
-            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(run[p]), __float_as_uint(run[q]), false,
+            const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(vals[p]), __float_as_uint(vals[q]), false,
                                                              false);
             const float tot = __uint_as_float(sw[0]) + __uint_as_float(sw[1]);
             const int col = b0 + (p + h) * 32 + n;
             if ((q != p || h == 0) && col < A.nb)
-                A.part[(int64_t)run_head * A.ldp + col] = tot;
+                A.part[(int64_t)run_slot * A.ldp + col] = tot;
         }
 #pragma unroll
         for (int nbk = 0; nbk < NBK; ++nbk)
-            run[nbk] = 0.0f;
+            vals[nbk] = 0.0f;
+    };
+    auto flush = [&]() { flush_vals(run); };
+
+    // the block whose epilogue runs next, and its row where a center starts
+    int prev_blk = blk0, prev_rs = 32;
+    bool last_odd = false;
+    auto split_over = [&]() {
+        if (prev_rs > 0 && prev_rs < 32) {
+            flush_vals(hold);  // the finished center, at its slot
+            run_slot = 2 * prev_blk + 1;
+        }
     };
 
     // ---- pipeline ----------------------------------------------------------
@@ -1050,11 +1083,11 @@ __global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(con
     auto stage = [&](int s, auto bc, auto bn) {
         const int bp = blk0 + SB * s;
         if (SB * s + SB - 1 - cw0 >= 64)
-            load_cen_win(SB * s);  // ranges of more than 64 blocks: next window
-        int cen[SB];
+            load_spl_win(SB * s);  // ranges of more than 64 blocks: next window
+        int spl[SB];
 #pragma unroll
         for (int k = 0; k < SB; ++k)
-            cen[k] = __builtin_amdgcn_readlane(cen_win, SB * s + k - cw0);
+            spl[k] = __builtin_amdgcn_readlane(spl_win, SB * s + k - cw0);
         if (s + 1 < nst)
             read_idx(bn);  // pool rows of stage s+1, staged during stage s-1
         if constexpr (!kBsSpreadStaging) {
@@ -1070,20 +1103,28 @@ __global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(con
 #pragma unroll
         for (int k = 0; k < SB; ++k) {
             // block bp + k; epilogue of block bp + k - 1; staging items of the next stage
+            if (bp + k >= blk1)
+                continue;  // past the range (its last stage, which stages nothing more)
             const int nsub = k + 1 < SB ? k + 1 : -1;
             auto hook = [&](int mi) {
                 if constexpr (kBsSpreadStaging)
                     stage_item(s, bc, bn, k * NMF + mi);
             };
             if (k % 2 == 0)
-                fused_block(acc0, acc1, bc, k, nsub, hook);
+                fused_block(acc0, acc1, bc, k, nsub, hook, prev_rs);
             else
-                fused_block(acc1, acc0, bc, k, nsub, hook);
-            if (cen[k] != run_center) {
+                fused_block(acc1, acc0, bc, k, nsub, hook, prev_rs);
+            last_odd = k % 2 == 1;
+            // the previous block's epilogue is done: a center that started
+            // inside it takes over (the finished center's sums are in hold)
+            split_over();
+            // a center that starts at this block's first row
+            if (spl[k] == 0 && bp + k != blk0) {
                 flush();
-                run_head = bp + k;
-                run_center = cen[k];
+                run_slot = 2 * (bp + k);
             }
+            prev_blk = bp + k;
+            prev_rs = spl[k];
         }
         __syncthreads();
     };
@@ -1092,7 +1133,12 @@ __global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(con
         if (s + 1 < nst)
             stage(s + 1, IC1{}, IC0{});
     }
-    epi_range(acc1, 0, NEL);
+    // the last block's epilogue (its accumulator set by its parity)
+    if (last_odd)
+        epi_range(acc1, 0, NEL, prev_rs);
+    else
+        epi_range(acc0, 0, NEL, prev_rs);
+    split_over();
     flush();
 #endif
 }
@@ -1117,7 +1163,7 @@ void launch_cross_mfma(const Layout &L, const Buffers &B, int nb, int precision,
         A.sup_row = B.sup_row;
         A.sup_w = B.sup_w;
         A.sup_ay = B.sup_ay;
-        A.blk_center = B.blk_center;
+        A.blk_split = B.blk_split;
         A.batfrag = (const char *)B.batfrag;
         A.frag_lo = 2 * (int64_t)frag_rows(L) * L.dp;
         A.batsq = B.batsq;

@@ -266,9 +266,9 @@ __global__ __launch_bounds__(1024) void k_sum_rows(const double *v, int n, doubl
 // ===========================================================================
 // The same quantities on FP32 MFMA (Gaussian MFMA forms, row stride <= 128):
 // kernel tiles are recomputed from x.y products, as the forward's cross term
-// is; sums that leave a tile are FP64.  The support layout is the MFMA one
-// (every center's segment padded to a multiple of 32 with weight-0 entries of
-// the zero row), so tiles need no masks on the support side.
+// is; sums that leave a tile are FP64.  A center's segment is cut into
+// blocks of 32 entries; entries of the last block past the segment's end
+// (packed segments are not multiples of 32) take weight 0 and the zero row.
 //
 // 32 x 32 tiles on v_mfma_f32_32x32x2f32: lane l = 32 h + n supplies
 // A[n][h] and B[h][n] of a k-step, and holds C[m][n] for
@@ -282,6 +282,7 @@ __global__ __launch_bounds__(1024) void k_sum_rows(const double *v, int n, doubl
 // sum); the fold adds them in wave order (gram_fold_jc), as the Gram blocks.
 struct SigmaGramArgs {
     int k, dp;
+    int sup_cap;         // sup_row[sup_cap] is the zero pool row
     const int32_t *seg_off, *sup_row, *toff;
     const double *sup_w64;
     const float *pool32, *poolsq;
@@ -299,14 +300,14 @@ __global__ __launch_bounds__(1024) void k_sigma_plan(int k, const int32_t *__res
     const int j0 = min(k, tid * per), j1 = min(k, j0 + per);
     int local = 0;
     for (int j = j0; j < j1; ++j) {
-        const int nb = (seg_off[j + 1] - seg_off[j]) / 32;
+        const int nb = (seg_off[j + 1] - seg_off[j] + 31) / 32;
         local += nb * nb;
     }
     int total;
     int run = block_exclusive_scan(local, sint, &total);
     for (int j = j0; j < j1; ++j) {
         toff[j] = run;
-        const int nb = (seg_off[j + 1] - seg_off[j]) / 32;
+        const int nb = (seg_off[j + 1] - seg_off[j] + 31) / 32;
         run += nb * nb;
     }
     if (tid == 0)
@@ -335,18 +336,19 @@ __global__ __launch_bounds__(256) void k_sigma_gram(const SigmaGramArgs A)
         const int g0 = A.toff[j], g1 = A.toff[j + 1];
         const int e = min(t1, g1);
         if (t < e) {
-            const int s0 = A.seg_off[j], nb = (A.seg_off[j + 1] - s0) / 32;
+            const int s0 = A.seg_off[j], s1 = A.seg_off[j + 1], nb = (s1 - s0 + 31) / 32;
             double ln = 0.0, ld = 0.0;
             for (; t < e; ++t) {
                 const int u = t - g0, ab = u / nb, eb = u - ab * nb;
                 const int sa = s0 + 32 * ab + n, se = s0 + 32 * eb + n;
-                const int64_t ra = A.sup_row[sa], re = A.sup_row[se];
+                const bool oka = sa < s1, oke = se < s1;  // past the segment: weight 0, zero row
+                const int64_t ra = A.sup_row[oka ? sa : A.sup_cap], re = A.sup_row[oke ? se : A.sup_cap];
                 if (h == 0) {
                     sqa[wl][n] = A.poolsq[ra];
-                    wa[wl][n] = A.sup_w64[sa];
+                    wa[wl][n] = oka ? A.sup_w64[sa] : 0.0;
                 }
                 const float sqe = A.poolsq[re];
-                const double we = A.sup_w64[se];
+                const double we = oke ? A.sup_w64[se] : 0.0;
                 f32x16 acc;
 #pragma unroll
                 for (int i = 0; i < 16; ++i)
@@ -410,6 +412,7 @@ void launch_sigma_norms(const Layout &L, const Buffers &B, double sigma, double 
     SigmaGramArgs A;
     A.k = L.k;
     A.dp = L.dp;
+    A.sup_cap = (int)L.Mcap;
     A.seg_off = B.seg_off;
     A.sup_row = B.sup_row;
     A.toff = B.sg_toff;
@@ -542,6 +545,7 @@ struct GradMfmaArgs {
     const float *pool32, *poolsq;
     const float *bat32, *batsq;  // the coordinates, gathered with row stride DP
     int64_t zero_row;            // pool row of zeros (rows past a group's end)
+    int sup_cap;                 // sup_row[sup_cap] is the zero pool row, sup_w[sup_cap] = 0
     const double *dN;
     float c;                     // -log2(e) / (2 s^2)
     double inv_s3, cx, cs;       // cx = 2 g / (b s^2), cs = g / b
@@ -605,14 +609,15 @@ __global__ __launch_bounds__(64 * grad_waves<DP>()) void k_grad_mfma(const GradM
         for (int i = 0; i < 16; ++i)
             G[tb][i] = 0.0f;
     double R = 0.0, S = 0.0;  // lanes < 32: row n's sum of P; lanes >= 32: of P d2
-    const int s0 = A.seg_off[j], nb = (A.seg_off[j + 1] - s0) / 32;
+    const int s0 = A.seg_off[j], s1 = A.seg_off[j + 1], nb = (s1 - s0 + 31) / 32;
     float(*Y)[YS] = Yl[wl];
     float(*P)[33] = Pl[wl];
     // block eb's row n, half h (coordinates), weight and norm: loaded one block ahead
     f32x4 yv[NV];
     float we = 0.0f, sqe = 0.0f;
     auto fetch = [&](int eb) {
-        const int se = s0 + 32 * eb + n;
+        const int se0 = s0 + 32 * eb + n;
+        const int se = se0 < s1 ? se0 : A.sup_cap;  // past the segment: weight 0, zero row
         const int64_t re = A.sup_row[se];
         we = A.sup_w[se];
         sqe = A.poolsq[re];
@@ -793,6 +798,7 @@ void launch_grad_mfma(const Layout &L, const Buffers &B, int b, double sigma, co
     A.bat32 = B.bat32;
     A.batsq = B.batsq;
     A.zero_row = L.PR;
+    A.sup_cap = (int)L.Mcap;
     A.dN = dN;
     A.c = (float)(-1.4426950408889634 / (2.0 * sigma * sigma));
     A.inv_s3 = 1.0 / (sigma * sigma * sigma);

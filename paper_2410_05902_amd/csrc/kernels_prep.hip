@@ -356,7 +356,9 @@ struct SupportArgs {
     int32_t *seg_off, *sup_row;
     float *sup_w;
     double *sup_w64;
-    int32_t *blk_center;
+    int32_t *blk_center;  // padded segments: the center of each block (else null)
+    int32_t *blk_split;   // packed segments: the row of each block where a center starts, 32 for none (else null)
+    int packed;
     double *N;
     float *sup_ay;        // MFMA path only (else null)
     const float *poolsq;
@@ -385,6 +387,7 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
     float *__restrict__ sup_w = A.sup_w;
     double *__restrict__ sup_w64 = A.sup_w64;
     int32_t *__restrict__ blk_center = A.blk_center;
+    int32_t *__restrict__ blk_split = A.blk_split;
     float *__restrict__ sup_ay = A.sup_ay;
     const float *__restrict__ poolsq = A.poolsq;
     const float ay_scale = A.ay_scale;
@@ -467,7 +470,7 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
         int acc = 0;
         for (int q = tid; q < j; q += 256) {
             const int l = seg_len(q, k, C, ring_off, coef, live, init_alive);
-            acc += (l + pad - 1) / pad * pad;
+            acc += seg_padded_len(l, pad, A.packed);
         }
         red[tid] = acc;
         __syncthreads();
@@ -479,11 +482,13 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
         int len = init_alive && scf[0] != 0.0 ? 1 : 0;
         for (int s = 0; s < live.n; ++s)
             len += sN[s];
-        plen = (len + pad - 1) / pad * pad;
+        plen = seg_padded_len(len, pad, A.packed);
         if (tid == 0)
             sh_start = red[0];
         __syncthreads();
         start = sh_start;
+        if (j == k - 1)  // the last segment reaches the support's end
+            plen = seg_padded_end(start + plen, pad, A.packed) - start;
     }
     if (tid == 0) {
         seg_off[j] = start;
@@ -523,6 +528,15 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
         if (blk_center) {
             for (int q = start / 32 + tid; q < (start + plen) / 32; q += 256)
                 blk_center[q] = j;
+        }
+        if (blk_split && plen > 0) {
+            // the block holding the segment's first entry records where it
+            // starts; the blocks wholly inside the segment record no start
+            // (every block gets one writer: a segment is at least 32 entries)
+            if (tid == 0)
+                blk_split[start / 32] = start % 32;
+            for (int q = start / 32 + 1 + tid; 32 * q + 32 <= start + plen; q += 256)
+                blk_split[q] = 32;
         }
     }
     // ---- Gram blocks of the last update's slot (gram_fold_jc's sums: up to
@@ -609,7 +623,9 @@ void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const 
     S.sup_row = B.sup_row;
     S.sup_w = B.sup_w;
     S.sup_w64 = B.sup_w64;
-    S.blk_center = L.pad == kMfmaPad ? B.blk_center : nullptr;
+    S.blk_center = L.pad == kMfmaPad && !L.packed ? B.blk_center : nullptr;
+    S.blk_split = L.packed ? B.blk_split : nullptr;
+    S.packed = L.packed;
     S.N = B.N;
     S.sup_ay = L.pad == kMfmaPad ? B.sup_ay : nullptr;
     S.poolsq = B.poolsq;
@@ -646,7 +662,8 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
     double *__restrict__ alpha, int32_t *__restrict__ off, double *__restrict__ obj,
     const int32_t *__restrict__ labels, const int32_t *__restrict__ rank, const int32_t *__restrict__ pts,
     int32_t *__restrict__ ring_idx, int32_t *__restrict__ ring_perm, uint32_t gram_mask, int gram_ta, int gram_te,
-    const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff, int pad, int32_t *__restrict__ seg_next)
+    const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff, int pad, int packed,
+    int32_t *__restrict__ seg_next)
 {
     __shared__ int sint[16];
     __shared__ double sdbl[16];
@@ -741,7 +758,7 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
         off[k] = b;
     // task offsets of the Gram blocks of the new slot (its counts are this
     // thread's b_i^j above; the other live slots' offsets are settled)
-    gram_plan(k, C, p_new, gram_mask, gram_ta, gram_te, ring_off, counts, coef, goff, sint, pad, seg_next);
+    gram_plan(k, C, p_new, gram_mask, gram_ta, gram_te, ring_off, counts, coef, goff, sint, pad, seg_next, packed);
     // sum of min distances (FP64), fixed order
     double sm = 0.0;
     for (int p = tid; p < b; p += nt)
@@ -773,7 +790,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
     double *__restrict__ alpha, int32_t *__restrict__ off, double *__restrict__ obj,
     const int32_t *__restrict__ labels, const int32_t *__restrict__ rank, const int32_t *__restrict__ pts,
     int32_t *__restrict__ ring_idx, int32_t *__restrict__ ring_perm, uint32_t gram_mask, int gram_ta, int gram_te,
-    const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff, int pad, int32_t *__restrict__ seg_next)
+    const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff, int pad, int packed,
+    int32_t *__restrict__ seg_next)
 {
     constexpr int RPT = kMaxBatch / kGroupThreads;  // batch rows per thread
     __shared__ int sint[32];
@@ -964,14 +982,14 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
                 slen += nec;
             }
         }
-        slen = (slen + pad - 1) / pad * pad;
+        slen = seg_padded_len(slen, pad, packed);
     }
     int stotal, ttotal, trun;
     const int srun = block_exclusive_scan2(slen, tasks, sint, &stotal, &trun, &ttotal);  // (its barriers also publish the bases)
     if (own)
         seg_next[j] = srun;
     if (tid == 0)
-        seg_next[k] = stotal;
+        seg_next[k] = seg_padded_end(stotal, pad, packed);
     if (own) {
         const int nA = (bj + gram_ta - 1) / gram_ta;
 #pragma unroll
@@ -1036,14 +1054,14 @@ void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_ex
                        B.alpha, B.ring_off + (int64_t)p_new * (L.k + 1), B.obj, B.labels, B.rank,                 \
                        B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,               \
                        B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_ta, gram_te, B.ring_off, B.goff, L.pad,  \
-                       B.seg_next)
+                       (int)L.packed, B.seg_next)
     if (L.k <= kGroupSmallK && (int64_t)nchunk * L.k <= kGroupLdsMax && L.C <= kGroupSmallC)
         hipLaunchKernelGGL(k_group_offsets_small, dim3(1), dim3(kGroupThreads), 0, st, b, L.k, nchunk, L.C, p_new,
                            p_expired, init_alive_before, init_keep, live, win, lr, B.gcnt, B.mind, B.coef, B.cum,
                            B.counts, B.alpha, B.ring_off + (int64_t)p_new * (L.k + 1), B.obj, B.labels, B.rank,
                            B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,
                            B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_ta, gram_te, B.ring_off, B.goff, L.pad,
-                           B.seg_next);
+                           (int)L.packed, B.seg_next);
     else if ((int64_t)nchunk * L.k <= kGroupLdsMax)
         MBKK_GO(true);
     else

@@ -18,7 +18,7 @@ namespace mbkk {
 //   sigma = 4 in 32-D: kernel values of 1e-8 and below) the centers' P_j
 //   differ far below an FP32 ulp of N_j, and an FP32 sum would tie them.
 // label = smallest j attaining the minimum; margin = second smallest - min.
-// LAYOUT 0: P[j][row]; LAYOUT 1: per-32-block partials of the MFMA kernel.
+// LAYOUT 0: runs of the direct kernel; 1, 2: runs of the MFMA kernels (below).
 // ===========================================================================
 __device__ __forceinline__ double self_kernel(int kind, double param, double sq)
 {
@@ -35,6 +35,11 @@ __device__ __forceinline__ double self_kernel(int kind, double param, double sq)
 // LAYOUT 1: the MFMA kernels write one partial per run of a center's blocks
 // inside a range of RB blocks, at the run's first block: the center's first
 // block and every range start inside the center.
+// LAYOUT 2 (packed segments, which may start inside a block): two slots per
+// block, 2 b for the run from block b's first row (a range start, or a center
+// starting there) and 2 b + 1 for a center starting inside block b; a
+// center's partials are its first slot and slot 2 b of every range start b
+// after its first block and inside its segment.
 // The direct kernel's runs are summed in FP64, the MFMA kernels' in FP32.
 template <typename T, int LAYOUT>
 __device__ __forceinline__ double cross_of(const T *__restrict__ part, int ldp, int row, int j,
@@ -48,13 +53,22 @@ __device__ __forceinline__ double cross_of(const T *__restrict__ part, int ldp, 
         for (int r = s0 / RB + 1; r * RB < s1; ++r)
             s += (double)part[(int64_t)(k + r) * ldp + row];
         return s;
-    } else {
+    } else if constexpr (LAYOUT == 1) {
         const int bs = seg_off[j] / 32, be = seg_off[j + 1] / 32;
         if (bs >= be)
             return 0.0;
         float s = part[(int64_t)bs * ldp + row];
         for (int blk = (bs / RB + 1) * RB; blk < be; blk += RB)
             s += part[(int64_t)blk * ldp + row];
+        return (double)s;
+    } else {
+        const int s0 = seg_off[j], s1 = seg_off[j + 1];
+        if (s0 >= s1)
+            return 0.0;
+        const int b0 = s0 / 32;
+        float s = part[(int64_t)(2 * b0 + (s0 % 32 != 0)) * ldp + row];
+        for (int blk = (b0 / RB + 1) * RB; 32 * blk < s1; blk += RB)
+            s += part[(int64_t)(2 * blk) * ldp + row];
         return (double)s;
     }
 }
@@ -66,7 +80,7 @@ __device__ __forceinline__ double cross_of(const T *__restrict__ part, int ldp, 
 template <typename T>
 struct CrossFetch {
     T a, b;
-    int lo, hi, next;  // LAYOUT 0: segment [lo, hi) in entries, next range r; 1: blocks [lo, hi), next block
+    int lo, hi, next;  // LAYOUT 0, 2: segment [lo, hi) in entries; 1: blocks [lo, hi); next range or block
 };
 
 // s0, s1: seg_off[j], seg_off[j + 1]; mtot: seg_off[k]
@@ -83,7 +97,7 @@ __device__ __forceinline__ CrossFetch<T> cross_fetch_at(const T *__restrict__ pa
         f.a = part[(int64_t)j * ldp + row];
         f.b = part[(int64_t)(k + max(min(r1, nr - 1), 0)) * ldp + row];
         f.next = r1 * RB < f.hi ? r1 + 1 : -1;
-    } else {
+    } else if constexpr (LAYOUT == 1) {
         f.lo = s0 / 32;
         f.hi = s1 / 32;
         const int b1 = (f.lo / RB + 1) * RB;
@@ -91,6 +105,14 @@ __device__ __forceinline__ CrossFetch<T> cross_fetch_at(const T *__restrict__ pa
         f.a = part[(int64_t)min(f.lo, top) * ldp + row];
         f.b = part[(int64_t)min(b1, top) * ldp + row];
         f.next = b1 < f.hi ? b1 + RB : -1;
+    } else {
+        f.lo = s0;
+        f.hi = s1;
+        const int b0 = s0 / 32, b1 = (b0 / RB + 1) * RB;
+        const int top = max(2 * (mtot / 32) - 1, 0);  // last slot of the support
+        f.a = part[(int64_t)min(2 * b0 + (s0 % 32 != 0), top) * ldp + row];
+        f.b = part[(int64_t)min(2 * b1, top) * ldp + row];
+        f.next = 32 * b1 < s1 ? b1 + RB : -1;
     }
     return f;
 }
@@ -116,12 +138,20 @@ __device__ __forceinline__ double cross_finish(const CrossFetch<T> &f, const T *
                 s += (double)part[(int64_t)(k + r) * ldp + row];
         }
         return s;
-    } else {
+    } else if constexpr (LAYOUT == 1) {
         float s = f.a;
         if (f.next >= 0) {
             s += f.b;
             for (int blk = f.next; blk < f.hi; blk += RB)
                 s += part[(int64_t)blk * ldp + row];
+        }
+        return (double)s;
+    } else {
+        float s = f.a;
+        if (f.next >= 0) {
+            s += f.b;
+            for (int blk = f.next; 32 * blk < f.hi; blk += RB)
+                s += part[(int64_t)(2 * blk) * ldp + row];
         }
         return (double)s;
     }
@@ -171,6 +201,7 @@ struct ScoreArgs {
 // then carry only the error of N_j (FP32 kernel values summed in FP64).
 // best: the row's smallest approximate distance (from the scoring pass);
 // seg_off / Nv: the segment offsets and self norms (LDS copies when staged).
+template <int LAYOUT>
 __device__ void rescore_row(const ScoreArgs &A, int row, int RB, double delta, double best,
                             const int32_t *__restrict__ seg_off, const double *__restrict__ Nv, int &lab_io,
                             float &mind_io, float &margin_io)
@@ -183,7 +214,7 @@ __device__ void rescore_row(const ScoreArgs &A, int row, int RB, double delta, d
     for (int j0 = 0; j0 < A.k; j0 += 64) {
         const int jl = j0 + lane;
         const double Dap =
-            jl < A.k ? 1.0 - 2.0 * cross_of<float, 1>(part, A.ldp, row, jl, seg_off, RB) + Nv[jl] : INFINITY;
+            jl < A.k ? 1.0 - 2.0 * cross_of<float, LAYOUT>(part, A.ldp, row, jl, seg_off, RB) + Nv[jl] : INFINITY;
         const bool cand = Dap <= best + delta;
         if (!cand)
             outside = fmin(outside, Dap);
@@ -421,7 +452,7 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
             if (rw < A.nb && (double)fmar[r] < fdel[r]) {
                 int l;
                 float m, g;
-                rescore_row(A, rw, RB, fdel[r], fbest[r], seg_off, Nv, l, m, g);
+                rescore_row<LAYOUT>(A, rw, RB, fdel[r], fbest[r], seg_off, Nv, l, m, g);
                 if (lane == 0) {
                     flab[r] = l;
                     fmin_[r] = m;
@@ -525,8 +556,12 @@ void launch_score(const Layout &L, const Buffers &B, int nb, int kind, double pa
     do {                                                                            \
         if (fp64)                                                                   \
             hipLaunchKernelGGL((k_score<double, 0, false, LK>), grid, block, 0, st, A); \
+        else if (mfma && L.packed && rescore)                                       \
+            hipLaunchKernelGGL((k_score<float, 2, true, LK>), grid, block, 0, st, A);   \
         else if (mfma && rescore)                                                   \
             hipLaunchKernelGGL((k_score<float, 1, true, LK>), grid, block, 0, st, A);   \
+        else if (mfma && L.packed)                                                  \
+            hipLaunchKernelGGL((k_score<float, 2, false, LK>), grid, block, 0, st, A);  \
         else if (mfma)                                                              \
             hipLaunchKernelGGL((k_score<float, 1, false, LK>), grid, block, 0, st, A);  \
         else                                                                        \

@@ -99,6 +99,7 @@ Layout make_layout(const mbkk_config &c)
     L.C = L.P + 1;
     L.bmax = c.b_max;
     L.pad = wants_mfma(c) ? kMfmaPad : 1;
+    L.packed = wants_mfma(c) && L.dp <= 128;
     L.bf16 = c.precision == MBKK_BF16X3 || c.precision == MBKK_BF16X1;
     // the batch-stationary MFMA cross kernel (row stride <= 128) reads the
     // batch from a fragment-order copy
@@ -168,10 +169,13 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.sup_w64 = (double *)take(8 * L.Mcap);
     B.sn_part = (double *)take(8 * 2 * (size_t)L.k * kSnSplit);
     B.blk_center = (int32_t *)take(4 * L.nblk);
+    B.blk_split = (int32_t *)take(4 * L.nblk);
     // cross-term partials of the kernel in use: runs of the direct kernel (FP32
-    // or FP64), or one FP32 value per (32-row block, batch row) on MFMA
+    // or FP64), or FP32 values per (32-row block, batch row) on MFMA: one, or
+    // two with packed segments (the run from the block's start, and the run of
+    // a center that starts inside the block)
     const size_t part_direct = (size_t)(L.k + kDirectWGs) * L.bmax * L.tbytes;
-    const size_t part_mfma = (size_t)L.nblk * L.bmax * 4;
+    const size_t part_mfma = (size_t)L.nblk * (L.packed ? 2 : 1) * L.bmax * 4;
     B.part = take(L.untrunc ? 0 : (L.pad == kMfmaPad ? part_mfma : part_direct));
     if (L.untrunc) {
         B.dp_T = take((size_t)L.tbytes * (size_t)L.k * (size_t)L.ldT);

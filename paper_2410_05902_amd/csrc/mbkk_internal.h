@@ -106,7 +106,8 @@ struct Buffers {
     float *sup_ay = nullptr;     // [Mcap + 1], [Mcap] = 0; MFMA path: -log2(e) ||y||^2 / kappa of the entry's row
     double *sup_w64 = nullptr;   // [Mcap]
     double *sn_part = nullptr;   // [k][kSnSplit][2] partial sums of the self norms at a bandwidth
-    int32_t *blk_center = nullptr;  // [Mcap/32]
+    int32_t *blk_center = nullptr;  // [Mcap/32] center of each 32-entry block (segments padded to 32)
+    int32_t *blk_split = nullptr;   // [Mcap/32] packed segments: row of the block where a center starts (32: none)
     // cross-term output and assignment
     void *part = nullptr;        // P[k][bmax] (direct) or per-run partials [Mcap/32][bmax]
     int32_t *labels = nullptr;   // [bmax]
@@ -148,6 +149,10 @@ struct Buffers {
 struct Layout {
     int64_t n;
     int d, dp, k, W, P, C, bmax, pad;
+    // packed segments (the batch-stationary MFMA kernel): a center's segment is
+    // its entries, at least `pad` when it has any, the support's end rounded
+    // up to a multiple of pad; else every segment is a multiple of pad
+    bool packed;
     int64_t PR;        // pool rows excluding the zero row: k + P * bmax
     int64_t Mcap;      // max padded support entries (multiple of 128)
     int64_t nblk;      // Mcap / 32
