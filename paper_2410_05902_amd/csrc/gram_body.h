@@ -48,18 +48,26 @@ __device__ __forceinline__ GramCol gram_col_uniform(int k, int bmax, int j, int 
     return g;
 }
 
+// XCD-aware order of the work workgroups (on by default)
+#ifndef MBKK_GRAM_XCD
+#define MBKK_GRAM_XCD 1
+#endif
+
 // Runs `task(a, e, ab, eb, lsum)` over the task range of wave w = blk * 4 +
 // (wave in the workgroup); a = the slot's rows of center j, e = column c's
 // rows, (ab, eb) the task's row blocks.  Every thread of the workgroup calls
 // it: when the task offsets and the ring offsets fit in `stage`, the
 // workgroup first copies them there with coalesced loads, so the segment
 // search and the column lookups read LDS.
+// pblk: the physical workgroup index of a grid of nwaves / 4 workgroups
+// (a multiple of 8).  Workgroups are handed to the 8 XCDs round robin
+// (pblk % 8); the workgroups that have tasks are cut into 8 contiguous
+// shares, share x taken by the workgroups of XCD x, so that the tasks of a
+// center, which are contiguous, read their rows through one XCD's L2.
 template <int TE, class Task>
-__device__ __forceinline__ void gram_wave_loop(const GramWork &A, int32_t *stage, int blk, Task &&task)
+__device__ __forceinline__ void gram_wave_loop(const GramWork &A, int32_t *stage, int pblk, Task &&task)
 {
     const int lane = threadIdx.x & 63;
-    // wave-uniform values are moved to scalar registers (readfirstlane)
-    const int w = __builtin_amdgcn_readfirstlane(blk * (kGramWG / 64) + (threadIdx.x >> 6));
     const int nJC = A.k * A.C;
     const int nro = (A.C - 1) * (A.k + 1);
     const int32_t *goff = A.goff, *ring_off = A.ring_off;
@@ -69,8 +77,18 @@ __device__ __forceinline__ void gram_wave_loop(const GramWork &A, int32_t *stage
     if (T == 0)
         return;
     const int chunk = (T + A.nwaves - 1) / A.nwaves;
+    int blk = pblk;
+    if constexpr (MBKK_GRAM_XCD != 0) {
+        const int awg = ((T + chunk - 1) / chunk + kGramWG / 64 - 1) / (kGramWG / 64);  // workgroups with tasks
+        const int share = (awg + 7) / 8;
+        if (pblk / 8 >= share)
+            return;  // workgroup uniform
+        blk = (pblk % 8) * share + pblk / 8;
+    }
     if ((int64_t)blk * (kGramWG / 64) * chunk >= T)
         return;  // workgroup uniform
+    // wave-uniform values are moved to scalar registers (readfirstlane)
+    const int w = __builtin_amdgcn_readfirstlane(blk * (kGramWG / 64) + (threadIdx.x >> 6));
     if (nJC + 1 + nro <= kGramStage) {  // workgroup uniform
         // every load first (one address select each, no branch), then the stores
         constexpr int SQ = kGramStage / kGramWG;
@@ -127,7 +145,7 @@ __device__ __forceinline__ void gram_wave_loop(const GramWork &A, int32_t *stage
 // pads to a multiple of 16 rather than 32.  Lane l = 16 g + n supplies
 // A[n][g] (slot row n) and B[g][n] (column row n) with g the quarter of the
 // coordinates it sums, [g dp/4, (g+1) dp/4); it holds D[4 g + i][n], i < 4.
-// DP = 0 takes the row stride at run time.  blk: the work block's index.
+// DP = 0 takes the row stride at run time.  blk: the physical workgroup index.
 // ---------------------------------------------------------------------------
 template <int DP>
 __device__ __forceinline__ void gram_mfma_work(const GramWork &A, int dp_rt, int zero_row,

@@ -11,6 +11,7 @@
 //     (any kernel, FP32 or FP64; the Laplacian L1 path);
 //   - k_cross_mfma  : Gaussian only, x.y on MFMA (FP32, or BF16 hi/lo split),
 //     exp fused in registers, segmented weighted sums over the support rows.
+#include <algorithm>
 #include <type_traits>
 
 #include "cross_layout.h"
@@ -605,7 +606,8 @@ __global__ __launch_bounds__(256, 2) void k_cross_mfma(const CrossArgs A)
 // ranges.
 // ===========================================================================
 // Where the staging of the next stage is issued: spread between the MFMAs of
-// the stage's first block, or all at the start of the stage.
+// the stage (one item every MBKK_BS_ITEM_STRIDE MFMAs, from the first), or
+// all at the start of the stage.
 #ifndef MBKK_BS_SPREAD
 #define MBKK_BS_SPREAD 1
 #endif
@@ -613,6 +615,18 @@ __global__ __launch_bounds__(256, 2) void k_cross_mfma(const CrossArgs A)
 #define MBKK_BS_XCD_BY_TILE 1
 #endif
 constexpr bool kBsSpreadStaging = MBKK_BS_SPREAD != 0;
+// MFMA positions between two staging items of the next stage
+#ifndef MBKK_BS_ITEM_STRIDE
+#define MBKK_BS_ITEM_STRIDE 10
+#endif
+// Wave priority by progress through the stage: priority 3 - k in block k,
+// so that of the two waves of a SIMD the one behind issues first and both
+// reach the end-of-stage barrier together (unprioritised, the older wave
+// ran a block ahead and then idled at the barrier while the other ran
+// alone)
+#ifndef MBKK_BS_PRIO
+#define MBKK_BS_PRIO 1
+#endif
 
 struct CrossBsArgs {
     int nb, nbt, nranges;
@@ -801,16 +815,17 @@ __global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(con
             issue_slot(bc, q);
         issue_ayw(s, bc);
     };
-    // The staging of stage s+1 and the index loads of stage s+2, as NT + 2
-    // items placed after every fourth MFMA of stage s (one per k * NMF + mi
-    // position), so that their issue overlaps matrix-core work.
     // The staging of stage s+1 (pool rows already in pidx) and the index
-    // staging of stage s+2, as NT + 2 items placed after every fourth MFMA of
-    // stage s, so that their issue overlaps matrix-core work.
+    // staging of stage s+2, as NT + 2 items placed after every IST-th MFMA of
+    // stage s (positions k * NMF + mi), so that their issue overlaps
+    // matrix-core work; all are issued before the end-of-stage barrier.
     auto stage_item = [&](int s, auto bc, auto bn, int pos) {  // bc / bn: the buffers of stages s / s+1
-        if (pos % 4 != 0)
+        // the stride, capped so that every item falls inside the stage
+        constexpr int IST = std::min(MBKK_BS_ITEM_STRIDE, (SB * KS * NBK * (X3 ? 3 : 1) - 1) / (NT + 1));
+        static_assert(IST >= 1, "staging items");
+        if (pos % IST != 0)
             return;
-        const int j = pos / 4;
+        const int j = pos / IST;
         if (j < NT) {
             if (s + 1 < nst)
                 issue_slot(bn, j);
@@ -1106,6 +1121,14 @@ __global__ __launch_bounds__(256 * bs_wps(MODE, DP), kBsOcc) void k_cross_bs(con
             if (bp + k >= blk1)
                 continue;  // past the range (its last stage, which stages nothing more)
             const int nsub = k + 1 < SB ? k + 1 : -1;
+            if constexpr (MBKK_BS_PRIO != 0) {
+                switch (k) {  // (k is a constant once the loop is unrolled)
+                case 0: __builtin_amdgcn_s_setprio(3); break;
+                case 1: __builtin_amdgcn_s_setprio(2); break;
+                case 2: __builtin_amdgcn_s_setprio(1); break;
+                default: __builtin_amdgcn_s_setprio(0); break;
+                }
+            }
             auto hook = [&](int mi) {
                 if constexpr (kBsSpreadStaging)
                     stage_item(s, bc, bn, k * NMF + mi);
