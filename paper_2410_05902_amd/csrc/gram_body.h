@@ -71,10 +71,28 @@ __device__ __forceinline__ void gram_wave_loop(const GramWork &A, int32_t *stage
     const int nJC = A.k * A.C;
     const int nro = (A.C - 1) * (A.k + 1);
     const int32_t *goff = A.goff, *ring_off = A.ring_off;
-    // the task count (a scalar load): a workgroup whose waves have no task
-    // leaves at once
+    // the task count (a scalar load), and the loads of the LDS copy of the
+    // offsets, which do not depend on it, in flight together; a workgroup
+    // whose waves have no task leaves once they have arrived
     const int T = A.goff[nJC];
-    if (T == 0)
+    const bool staged = nJC + 1 + nro <= kGramStage;  // workgroup uniform
+    constexpr int SQ = kGramStage / kGramWG;
+    const int tot = nJC + 1 + nro;
+    int v[SQ];
+    int vor = 0;
+    if (staged) {
+        // one address select each, no branch
+#pragma unroll
+        for (int q = 0; q < SQ; ++q) {
+            const int i = min((int)threadIdx.x + q * kGramWG, tot - 1);
+            v[q] = *(i <= nJC ? A.goff + i : A.ring_off + (i - (nJC + 1)));
+            vor |= v[q];
+        }
+    }
+    // (offsets are never negative, so the second test is false in every
+    // thread and the exit stays workgroup uniform; it keeps the copy's loads
+    // ahead of the exits below instead of sunk past them)
+    if (T == 0 || vor < 0)
         return;
     const int chunk = (T + A.nwaves - 1) / A.nwaves;
     int blk = pblk;
@@ -89,16 +107,7 @@ __device__ __forceinline__ void gram_wave_loop(const GramWork &A, int32_t *stage
         return;  // workgroup uniform
     // wave-uniform values are moved to scalar registers (readfirstlane)
     const int w = __builtin_amdgcn_readfirstlane(blk * (kGramWG / 64) + (threadIdx.x >> 6));
-    if (nJC + 1 + nro <= kGramStage) {  // workgroup uniform
-        // every load first (one address select each, no branch), then the stores
-        constexpr int SQ = kGramStage / kGramWG;
-        const int tot = nJC + 1 + nro;
-        int v[SQ];
-#pragma unroll
-        for (int q = 0; q < SQ; ++q) {
-            const int i = min((int)threadIdx.x + q * kGramWG, tot - 1);
-            v[q] = *(i <= nJC ? A.goff + i : A.ring_off + (i - (nJC + 1)));
-        }
+    if (staged) {
 #pragma unroll
         for (int q = 0; q < SQ; ++q) {
             const int i = threadIdx.x + q * kGramWG;
