@@ -199,28 +199,50 @@ def live_support(st):
     return m
 
 
-def unit_rates(dev):
-    """Attainable rates on this GPU (mbkk_microbench), one probe each at the
-    occupancy the kernels run at: FP32 sub + add-|.| and FMA lane ops/s, exp2/s,
-    BF16 and FP32 MFMA flop/s."""
+def _probe_rate(dev, name, kind, iters, waves_per_simd):
+    """One mbkk_microbench probe: operations (lane ops or flops) per second."""
     import ctypes as C
     import torch
     from paper_2410_05902_amd import _lib as L
     sink = torch.zeros(256, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream(dev).cuda_stream
-    out = {}
-    for name, kind, iters, w in [("fp32_subadd_lane_ops", L.PROBE_SUBADD, 50000, 8),
-                                 ("fp32_fma_lane_ops", L.PROBE_FMA, 50000, 8),
-                                 ("exp2", L.PROBE_EXP2, 25000, 8),
-                                 ("bf16_mfma_flops", L.PROBE_MFMA_BF16, 50000, 2),
-                                 ("fp32_mfma_flops", L.PROBE_MFMA_F32, 20000, 1)]:
-        ms, ops = C.c_double(), C.c_double()
-        rc = L.lib().mbkk_microbench(kind, iters, w, C.c_void_p(stream), C.c_void_p(sink.data_ptr()),
-                                     C.byref(ms), C.byref(ops))
-        if rc != 0:
-            raise SystemExit(f"mbkk_microbench({name}) failed: {rc}")
-        out[name] = ops.value / (ms.value * 1e-3)
-    return out
+    ms, ops = C.c_double(), C.c_double()
+    rc = L.lib().mbkk_microbench(kind, iters, waves_per_simd, C.c_void_p(stream), C.c_void_p(sink.data_ptr()),
+                                 C.byref(ms), C.byref(ops))
+    if rc != 0:
+        raise SystemExit(f"mbkk_microbench({name}) failed: {rc}")
+    return ops.value / (ms.value * 1e-3)
+
+
+def _probes():
+    from paper_2410_05902_amd import _lib as L
+    # name, kind, iterations, waves per SIMD the kernels run at
+    return [("fp32_subadd_lane_ops", L.PROBE_SUBADD, 50000, 8),
+            ("fp32_fma_lane_ops", L.PROBE_FMA, 50000, 8),
+            ("exp2", L.PROBE_EXP2, 25000, 8),
+            ("bf16_mfma_flops", L.PROBE_MFMA_BF16, 50000, 2),
+            ("bf16_mfma_one_chain_per_wave_flops", L.PROBE_MFMA_BF16_CHAIN, 50000, 2),
+            ("fp32_mfma_flops", L.PROBE_MFMA_F32, 20000, 1)]
+
+
+def unit_rates(dev):
+    """Attainable rates on this GPU (mbkk_microbench), one probe each at the
+    occupancy the kernels run at: FP32 sub + add-|.| and FMA lane ops/s, exp2/s,
+    BF16 MFMA flop/s (independent accumulators, and one dependent chain per
+    wave as in the batch-stationary cross kernel) and FP32 MFMA flop/s."""
+    return {name: _probe_rate(dev, name, kind, iters, w) for name, kind, iters, w in _probes()}
+
+
+def microbench(dev):
+    """--microbench: every probe at 1, 2, 4 and 8 waves per SIMD, one JSON line
+    (rates per second, and per CU per clock at 2.4 GHz)."""
+    table = {}
+    for name, kind, iters, _ in _probes():
+        for w in (1, 2, 4, 8):
+            r = _probe_rate(dev, name, kind, iters, w)
+            table[f"{name}@{w}"] = {"rate": r, "per_cu_per_clock_2p4GHz": r / (256 * 2.4e9)}
+            log(f"[microbench] {name:36s} {w} waves/SIMD: {r:.4e}/s")
+    print(json.dumps({"microbench": table}), flush=True)
 
 
 # FP32 add / subtract lane operations: 128 per CU per clock (the issue rate the

@@ -10,7 +10,8 @@
  *
  * mbkk_microbench runs one probe kernel grid-wide (256 workgroups of 4 waves
  * per wave level, waves_per_simd in [1, 8] waves on every SIMD), each lane
- * running 16 independent dependency chains for `iters` steps, once to warm up
+ * running 16 independent dependency chains (the MFMA probes: 4 accumulators
+ * per wave, the chain probe 1) for `iters` steps, once to warm up
  * and once timed with HIP events on `stream` (a hipStream_t, NULL = default).
  *   kind MBKK_PROBE_SUBADD   : s += |x - y| (v_sub_f32, v_add_f32 with |.|),
  *                              2 lane operations per pair + 1 FMA per step
@@ -18,6 +19,9 @@
  *   kind MBKK_PROBE_EXP2     : a = 2^-a (v_exp_f32), 1 lane operation
  *   kind MBKK_PROBE_MFMA_BF16: v_mfma_f32_32x32x16_bf16, 32768 flops each
  *   kind MBKK_PROBE_MFMA_F32 : v_mfma_f32_32x32x2_f32, 4096 flops each
+ *   kind MBKK_PROBE_MFMA_BF16_CHAIN: v_mfma_f32_32x32x16_bf16 with ONE
+ *                              accumulator per wave (every product depends
+ *                              on the one before it in the wave)
  * sink_dev: a device float array of at least 256 elements (never written in
  * practice; it keeps the work observable).  Writes the timed launch's
  * duration (ms_host) and the lane operations or flops it performed
@@ -38,6 +42,7 @@ extern "C" {
 #define MBKK_PROBE_EXP2 2
 #define MBKK_PROBE_MFMA_BF16 3
 #define MBKK_PROBE_MFMA_F32 4
+#define MBKK_PROBE_MFMA_BF16_CHAIN 5
 
 int mbkk_microbench(int32_t kind, int64_t iters, int32_t waves_per_simd, void *stream, float *sink_dev,
                     double *ms_host, double *ops_host);

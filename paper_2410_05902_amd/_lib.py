@@ -25,7 +25,7 @@ EXPORTS = [
     "mbkk_rescore_count", "mbkk_selfnorm_error_bound", "mbkk_create_static",
     "mbkk_microbench",  # include/mbkk_microbench.h
 ]
-PROBE_SUBADD, PROBE_FMA, PROBE_EXP2, PROBE_MFMA_BF16, PROBE_MFMA_F32 = 0, 1, 2, 3, 4
+PROBE_SUBADD, PROBE_FMA, PROBE_EXP2, PROBE_MFMA_BF16, PROBE_MFMA_F32, PROBE_MFMA_BF16_CHAIN = 0, 1, 2, 3, 4, 5
 
 
 class MbkkError(RuntimeError):

@@ -1,6 +1,7 @@
 // Throughput probes of the gfx950 units the hot path is bound by: FP32
 // subtract + add-|.| (the Laplacian distance's inner pair), FP32 FMA, the
-// exp2 transcendental, and BF16 / FP32 MFMA.  They give the attainable rates
+// exp2 transcendental, and BF16 / FP32 MFMA (BF16 also as one dependent
+// chain per wave).  They give the attainable rates
 // that the roofline fractions of the VALU-bound and MFMA-bound kernels are set
 // beside (include/mbkk_microbench.h).
 //
@@ -125,6 +126,33 @@ __global__ __launch_bounds__(256) void k_probe_mfma(int64_t iters, float *sink)
     sink_if(t, sink);
 }
 
+// MFMA, one dependent chain per wave: every product of the wave accumulates
+// into the same 32x32 block, as a batch-stationary kernel holding one block
+// of batch rows per wave does (the matrix core then overlaps only the
+// products of different waves).
+__global__ __launch_bounds__(256) void k_probe_mfma_chain(int64_t iters, float *sink)
+{
+    f32x16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        acc[i] = 0.0f;
+    const float av = (float)(threadIdx.x & 7) * 1e-3f;
+    bf16x8 ab;
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        ab[i] = (__bf16)(av + (float)i * 1e-3f);
+    for (int64_t it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ab, ab, acc, 0, 0, 0);
+    }
+    float t = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        t += acc[i];
+    sink_if(t, sink);
+}
+
 }  // namespace
 
 extern "C" int mbkk_microbench(int32_t kind, int64_t iters, int32_t waves_per_simd, void *stream, float *sink_dev,
@@ -161,6 +189,10 @@ extern "C" int mbkk_microbench(int32_t kind, int64_t iters, int32_t waves_per_si
             break;
         case MBKK_PROBE_MFMA_BF16:
             hipLaunchKernelGGL(k_probe_mfma<true>, dim3(blocks), dim3(256), 0, st, iters, sink_dev);
+            ops = (double)blocks * 4.0 * (double)iters * 4.0 * 32.0 * 32.0 * 16.0 * 2.0;
+            break;
+        case MBKK_PROBE_MFMA_BF16_CHAIN:
+            hipLaunchKernelGGL(k_probe_mfma_chain, dim3(blocks), dim3(256), 0, st, iters, sink_dev);
             ops = (double)blocks * 4.0 * (double)iters * 4.0 * 32.0 * 32.0 * 16.0 * 2.0;
             break;
         case MBKK_PROBE_MFMA_F32:
