@@ -83,6 +83,58 @@ __device__ __forceinline__ int block_exclusive_scan2(int a, int b, int *lds, int
     return ra;
 }
 
+// N exclusive scans with one set of barriers: run[q] = the scan of v[q],
+// tot[q] its total.  `lds` holds at least 16 N ints (at most 16 waves).
+template <int N>
+__device__ __forceinline__ void block_exclusive_scan_n(const int (&v)[N], int *lds, int (&run)[N], int (&tot)[N])
+{
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int x[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+        x[q] = v[q];
+    for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            const int y = __shfl_up(x[q], o);
+            if (lane >= o)
+                x[q] += y;
+        }
+    }
+    if (lane == 63) {
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+            lds[16 * q + wid] = x[q];
+    }
+    __syncthreads();
+    if (wid == 0) {
+        int t[N];
+#pragma unroll
+        for (int q = 0; q < N; ++q)
+            t[q] = lane < nw ? lds[16 * q + lane] : 0;
+        for (int o = 1; o < 64; o <<= 1) {
+#pragma unroll
+            for (int q = 0; q < N; ++q) {
+                const int y = __shfl_up(t[q], o);
+                if (lane >= o)
+                    t[q] += y;
+            }
+        }
+        if (lane < nw) {
+#pragma unroll
+            for (int q = 0; q < N; ++q)
+                lds[16 * q + lane] = t[q];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        run[q] = (wid > 0 ? lds[16 * q + wid - 1] : 0) + x[q] - v[q];
+        tot[q] = lds[16 * q + nw - 1];
+    }
+    __syncthreads();
+}
+
 // Block-wide sum of one double per thread, in a fixed order (wave trees,
 // then the wave totals in order).  `lds` holds at least 16 doubles.
 __device__ __forceinline__ double block_sum(double v, double *lds)
@@ -138,6 +190,10 @@ __device__ __forceinline__ int wave_segment_of(const int32_t *__restrict__ off, 
 // ---------------------------------------------------------------------------
 constexpr int kGramTA = 32;      // slot rows per task of the VALU form
 constexpr int kGramTAMfma = 16;  // ... and of the MFMA form (16 x 16 tiles)
+// Column tiles per task that a plan may choose: 1, 2, ..., 2^(steps - 1).
+// A plan whose tasks outnumber the work kernel's waves takes more tiles per
+// task, so that a task's slot rows are loaded once for several tiles.
+constexpr int kGramTileSteps = 4;
 
 // Rows of center j in column c: the slot rows through the grouping
 // permutation of their slot, column 0 the initial point (pool row j).
@@ -247,8 +303,10 @@ __device__ __forceinline__ void gram_plan(int k, int C, int rr, uint32_t mask, i
             run += tasks(j, c, na);
         }
     }
-    if (tid == 0)
+    if (tid == 0) {
         goff[(int64_t)k * C] = total;
+        goff[(int64_t)k * C + 1] = 1;  // column tiles per task
+    }
 }
 
 // Block (j, c) of the Gram work just done (jc = j * C + c, njc = k * C): the

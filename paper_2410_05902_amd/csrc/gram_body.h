@@ -53,9 +53,11 @@ __device__ __forceinline__ GramCol gram_col_uniform(int k, int bmax, int j, int 
 #define MBKK_GRAM_XCD 1
 #endif
 
-// Runs `task(a, e, ab, eb, lsum)` over the task range of wave w = blk * 4 +
+// Runs `task(a, e, ab, eb, Q, lsum)` over the task range of wave w = blk * 4 +
 // (wave in the workgroup); a = the slot's rows of center j, e = column c's
-// rows, (ab, eb) the task's row blocks.  Every thread of the workgroup calls
+// rows, (ab, eb) the task's row blocks: slot rows ab TA.., column tiles
+// eb Q .. eb Q + Q - 1 of TE rows (Q, the plan's column tiles per task, is
+// read after the task total when TQ, else 1).  Every thread of the workgroup calls
 // it: when the task offsets and the ring offsets fit in `stage`, the
 // workgroup first copies them there with coalesced loads, so the segment
 // search and the column lookups read LDS.
@@ -64,7 +66,7 @@ __device__ __forceinline__ GramCol gram_col_uniform(int k, int bmax, int j, int 
 // (pblk % 8); the workgroups that have tasks are cut into 8 contiguous
 // shares, share x taken by the workgroups of XCD x, so that the tasks of a
 // center, which are contiguous, read their rows through one XCD's L2.
-template <int TE, class Task>
+template <int TE, bool TQ, class Task>
 __device__ __forceinline__ void gram_wave_loop(const GramWork &A, int32_t *stage, int pblk, Task &&task)
 {
     const int lane = threadIdx.x & 63;
@@ -75,6 +77,7 @@ __device__ __forceinline__ void gram_wave_loop(const GramWork &A, int32_t *stage
     // offsets, which do not depend on it, in flight together; a workgroup
     // whose waves have no task leaves once they have arrived
     const int T = A.goff[nJC];
+    const int Q = TQ ? A.goff[nJC + 1] : 1;
     const bool staged = nJC + 1 + nro <= kGramStage;  // workgroup uniform
     constexpr int SQ = kGramStage / kGramWG;
     const int tot = nJC + 1 + nro;
@@ -131,12 +134,12 @@ __device__ __forceinline__ void gram_wave_loop(const GramWork &A, int32_t *stage
             const int j = jc / A.C, c = jc - j * A.C;
             const GramCol a = gram_col_uniform(A.k, A.bmax, j, 1 + A.rr, ring_off, A.ring_perm);
             const GramCol ec = gram_col_uniform(A.k, A.bmax, j, c, ring_off, A.ring_perm);
-            const int nE = (ec.n + TE - 1) / TE;
+            const int nE = ((ec.n + TE - 1) / TE + Q - 1) / Q;
             double lsum = 0.0;
             for (; t < e; ++t) {
                 const int u = t - g0;
                 const int ab = u / nE, eb = u - ab * nE;
-                task(a, ec, ab, eb, lsum);
+                task(a, ec, ab, eb, Q, lsum);
             }
             for (int o = 32; o > 0; o >>= 1)
                 lsum += __shfl_xor(lsum, o);
@@ -150,8 +153,10 @@ __device__ __forceinline__ void gram_wave_loop(const GramWork &A, int32_t *stage
 // ---------------------------------------------------------------------------
 // MFMA tasks (Gaussian): exp(-(||a||^2 + ||e||^2 - 2 a.e) / kappa) with a.e
 // on FP32 MFMA 16x16x4 (every MFMA form, the BF16 ones included): a task is
-// a 16 x 16 block of (slot row, column row) pairs, so a cluster of b_j rows
-// pads to a multiple of 16 rather than 32.  Lane l = 16 g + n supplies
+// 16 slot rows by Q tiles of 16 column rows (the plan's Q: 1 unless the
+// tasks would outnumber the waves), so a cluster of b_j rows pads to a
+// multiple of 16 rather than 32, and a large one loads its slot rows once
+// for up to 8 tiles.  Lane l = 16 g + n supplies
 // A[n][g] (slot row n) and B[g][n] (column row n) with g the quarter of the
 // coordinates it sums, [g dp/4, (g+1) dp/4); it holds D[4 g + i][n], i < 4.
 // DP = 0 takes the row stride at run time.  blk: the physical workgroup index.
@@ -166,57 +171,76 @@ __device__ __forceinline__ void gram_mfma_work(const GramWork &A, int dp_rt, int
     __shared__ float sqa[kGramWG / 64][16];
     __shared__ int32_t stage[kGramStage];
     const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6, n = lane & 15, g = lane >> 4;
-    gram_wave_loop<16>(A, stage, blk, [&](const GramCol &a, const GramCol &ec, int ab, int eb, double &lsum) {
-        const int qa = ab * 16 + n, qe = eb * 16 + n;
-        // both permutation loads, then every row load, in flight together:
-        // clamped indices and selects, no branches (a is a slot column, so
-        // a.perm is set; column 0 of ec has no permutation and one row)
+    gram_wave_loop<16, true>(A, stage, blk, [&](const GramCol &a, const GramCol &ec, int ab, int eb, int Q,
+                                                 double &lsum) {
+        // the task: slot rows ab*16.., column tiles tile0 .. tile1-1 (wave uniform)
+        const int qa = ab * 16 + n;
+        const int tile0 = eb * Q, tile1 = min((ec.n + 15) / 16, tile0 + Q);
+        // both permutation loads of the first tile, then every row load, in
+        // flight together: clamped indices and selects, no branches (a is a
+        // slot column, so a.perm is set; column 0 of ec has no permutation
+        // and one row)
         const int32_t *ep = ec.perm ? ec.perm : a.perm;
         const int32_t pa = a.perm[min(qa, a.n - 1)];
-        const int32_t pe = ep[min(qe, ec.n - 1)];
+        int qe = tile0 * 16 + n;
+        int32_t pe = ep[min(qe, ec.n - 1)];
         const int64_t ra = qa < a.n ? a.row0 + pa : zero_row;
-        const int64_t re = qe < ec.n ? (ec.perm ? ec.row0 + pe : ec.row0) : zero_row;
-        const float sqa_v = poolsq[ra], sqe_v = poolsq[re];
-        f32x4 acc;
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-            acc[i] = 0.0f;
-        const float *sa = pool32 + ra * dp + g * KQ, *se = pool32 + re * dp + g * KQ;
+        const float sqa_v = poolsq[ra];
+        const float *sa = pool32 + ra * dp + g * KQ;
+        // the slot rows' coordinates, loaded once for every tile of the task
+        constexpr int NS = DP > 0 ? DP / 16 : 1;
+        f32x4 av[NS];
         if constexpr (DP > 0) {
-            // the task's coordinates are all loaded before the first product
-            constexpr int NS = DP / 16;
-            f32x4 av[NS], ev[NS];
-#pragma unroll
-            for (int q = 0; q < NS; ++q) {
-                av[q] = *(const f32x4 *)(sa + 4 * q);
-                ev[q] = *(const f32x4 *)(se + 4 * q);
-            }
-            __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
 #pragma unroll
             for (int q = 0; q < NS; ++q)
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q][u], ev[q][u], acc, 0, 0, 0);
-        } else {
-            for (int s4 = 0; s4 < KQ; s4 += 4) {
-                const f32x4 av = *(const f32x4 *)(sa + s4), ev = *(const f32x4 *)(se + s4);
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[u], ev[u], acc, 0, 0, 0);
-            }
+                av[q] = *(const f32x4 *)(sa + 4 * q);
         }
-        // lane n (g = 0) publishes the norm of slot row n for the output rows m
-        if (g == 0)
-            sqa[wl][n] = c1 * sqa_v;
-        const float se_ = c1 * sqe_v;
-        // lane: column n (column row), rows m = 4 g + i (slot rows); the row
-        // norms were written by this wave (in-order LDS access)
-        if (qe < ec.n) {
+        for (int tile = tile0; tile < tile1; ++tile) {
+            if (tile != tile0) {
+                qe = tile * 16 + n;
+                pe = ep[min(qe, ec.n - 1)];
+            }
+            const int64_t re = qe < ec.n ? (ec.perm ? ec.row0 + pe : ec.row0) : zero_row;
+            const float sqe_v = poolsq[re];
+            const float *se = pool32 + re * dp + g * KQ;
+            f32x4 acc;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int m = 4 * g + i;
-                if (ab * 16 + m < a.n)
-                    lsum += (double)__builtin_amdgcn_exp2f(fmaf(acc[i], c2, sqa[wl][m] + se_));
+            for (int i = 0; i < 4; ++i)
+                acc[i] = 0.0f;
+            if constexpr (DP > 0) {
+                // the tile's coordinates are all loaded before its first product
+                f32x4 ev[NS];
+#pragma unroll
+                for (int q = 0; q < NS; ++q)
+                    ev[q] = *(const f32x4 *)(se + 4 * q);
+                __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+#pragma unroll
+                for (int q = 0; q < NS; ++q)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q][u], ev[q][u], acc, 0, 0, 0);
+            } else {
+                for (int s4 = 0; s4 < KQ; s4 += 4) {
+                    const f32x4 a4 = *(const f32x4 *)(sa + s4), e4 = *(const f32x4 *)(se + s4);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[u], e4[u], acc, 0, 0, 0);
+                }
+            }
+            // lane n (g = 0) publishes the norm of slot row n for the output
+            // rows m, once per task
+            if (tile == tile0 && g == 0)
+                sqa[wl][n] = c1 * sqa_v;
+            const float se_ = c1 * sqe_v;
+            // lane: column n (column row), rows m = 4 g + i (slot rows); the
+            // row norms were written by this wave (in-order LDS access)
+            if (qe < ec.n) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int m = 4 * g + i;
+                    if (ab * 16 + m < a.n)
+                        lsum += (double)__builtin_amdgcn_exp2f(fmaf(acc[i], c2, sqa[wl][m] + se_));
+                }
             }
         }
     });

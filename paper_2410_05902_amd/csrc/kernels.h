@@ -24,19 +24,21 @@ void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const 
                     const int32_t *idx, int64_t cnt, int check_finite, float ay_scale, int fold_rr,
                     uint32_t fold_mask, bool seg_ready, hipStream_t st);
 // The update also writes the task plan of the new slot's Gram blocks against
-// the columns in gram_mask (tasks gram_te column rows wide), and the
-// segment offsets of the support over those columns into B.seg_next.
-// win: the window after the update and tau (> 0: the count truncation of
-// each center, whose dropped columns get coefficient 0).
+// the columns in gram_mask (tasks gram_ta slot rows by 1..gram_qmax tiles of
+// gram_te column rows: the fewest tiles whose tasks fit in gram_nwaves
+// waves), and the segment offsets of the support over those columns into
+// B.seg_next.  win: the window after the update and tau (> 0: the count
+// truncation of each center, whose dropped columns get coefficient 0).
 void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
                    int init_keep, const SlotList &live, const WindowRank &win, int lr, uint32_t gram_mask,
-                   int gram_ta, int gram_te, hipStream_t st);
+                   int gram_ta, int gram_te, int gram_qmax, int gram_nwaves, hipStream_t st);
 
 // Gram blocks of slot rr against the columns in col_mask: plan (when not made
 // by the update), then work and fold.  mfma: the Gaussian MFMA forms (FP32
 // MFMA products in every precision form); else VALU in FP64 or FP32.
 int gram_task_cols(int mfma, int fp64);  // te of the plan for the chosen Gram form
 int gram_task_rows(int mfma);            // ta of the plan for the chosen Gram form
+int gram_task_qmax(int mfma);            // most column tiles per task the Gram form takes
 void launch_gram_plan(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int ta, int te, hipStream_t st);
 void launch_gram(const Layout &L, const Buffers &B, int rr, uint32_t col_mask, int kind, double param, int fp64,
                  int mfma, bool fold, hipStream_t st);

@@ -76,7 +76,9 @@ __global__ __launch_bounds__(kGramWG) void k_gram_valu(const GramWork A, int d, 
     const int lane = threadIdx.x & 63;
     const KT prm = (KT)param;
     __shared__ int32_t stage[kGramStage];
-    gram_wave_loop<64 * RPL>(A, stage, blockIdx.x, [&](const GramCol &a, const GramCol &ec, int ab, int eb, double &lsum) {
+    // (one column set per task: the VALU plan takes Q = 1)
+    gram_wave_loop<64 * RPL, false>(A, stage, blockIdx.x, [&](const GramCol &a, const GramCol &ec, int ab, int eb, int,
+                                                              double &lsum) {
         bool eok[RPL];
         int re[RPL];
 #pragma unroll
@@ -181,6 +183,14 @@ int gram_task_cols(int mfma, int fp64)
 }
 
 int gram_task_rows(int mfma) { return mfma ? kGramTAMfma : kGramTA; }
+// the MFMA task loads its 16 slot rows once for up to MBKK_GRAM_QMAX column
+// tiles (a power of two, at most 2^(kGramTileSteps - 1)); the VALU task
+// takes one column set
+#ifndef MBKK_GRAM_QMAX
+#define MBKK_GRAM_QMAX 8
+#endif
+static_assert(MBKK_GRAM_QMAX >= 1 && MBKK_GRAM_QMAX <= 1 << (kGramTileSteps - 1), "column tiles per task");
+int gram_task_qmax(int mfma) { return mfma ? MBKK_GRAM_QMAX : 1; }
 
 void launch_gram_plan(const Layout &L, const Buffers &B, int rr, uint32_t mask, int ta, int te, hipStream_t st)
 {

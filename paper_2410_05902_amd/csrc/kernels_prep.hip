@@ -790,11 +790,11 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
     double *__restrict__ alpha, int32_t *__restrict__ off, double *__restrict__ obj,
     const int32_t *__restrict__ labels, const int32_t *__restrict__ rank, const int32_t *__restrict__ pts,
     int32_t *__restrict__ ring_idx, int32_t *__restrict__ ring_perm, uint32_t gram_mask, int gram_ta, int gram_te,
-    const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff, int pad, int packed,
-    int32_t *__restrict__ seg_next)
+    int gram_qmax, int gram_nwaves, const int32_t *__restrict__ ring_off, int32_t *__restrict__ goff, int pad,
+    int packed, int32_t *__restrict__ seg_next)
 {
     constexpr int RPT = kMaxBatch / kGroupThreads;  // batch rows per thread
-    __shared__ int sint[32];
+    __shared__ int sint[16 * (1 + kGramTileSteps)];
     __shared__ double sdbl[16];
     __shared__ int scnt[kGroupLdsMax];    // per-(chunk, label) counts, then bases, then the grouped rows
     __shared__ int sidx[kMaxBatch];       // the grouped rows' points
@@ -908,7 +908,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
         }
     }
     // ---- learning rate and the coefficient update of center j
-    int tasks = 0, slen = 0;
+    int tasks[kGramTileSteps] = {};  // Gram tasks of 1, 2, 4, ... column tiles
+    int slen = 0;
     if (own) {
         double a;
         if (lr == MBKK_LR_FULL)
@@ -972,39 +973,56 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
             if (c < C)
                 coef[(int64_t)j * C + c] = cf[c];
         // Gram tasks of the new slot against the live columns that keep a
-        // weight, and the padded segment of center j in the next support
+        // weight (for each number of column tiles per task), and the padded
+        // segment of center j in the next support
         const int nA = (bj + gram_ta - 1) / gram_ta;
 #pragma unroll
         for (int c = 0; c < kGroupSmallC; ++c) {
             if (c < C && ((gram_mask >> c) & 1u) && cf[c] != 0.0) {
                 const int nec = c == 0 ? 1 : (c - 1 == p_new ? bj : ne[c]);
-                tasks += nA * ((nec + gram_te - 1) / gram_te);
+                const int ntile = (nec + gram_te - 1) / gram_te;
+#pragma unroll
+                for (int qi = 0; qi < kGramTileSteps; ++qi)
+                    tasks[qi] += nA * ((ntile + (1 << qi) - 1) >> qi);
                 slen += nec;
             }
         }
         slen = seg_padded_len(slen, pad, packed);
     }
-    int stotal, ttotal, trun;
-    const int srun = block_exclusive_scan2(slen, tasks, sint, &stotal, &trun, &ttotal);  // (its barriers also publish the bases)
+    int sv[1 + kGramTileSteps], srun_[1 + kGramTileSteps], stot[1 + kGramTileSteps];
+    sv[0] = slen;
+#pragma unroll
+    for (int qi = 0; qi < kGramTileSteps; ++qi)
+        sv[1 + qi] = tasks[qi];
+    block_exclusive_scan_n<1 + kGramTileSteps>(sv, sint, srun_, stot);  // (its barriers also publish the bases)
+    // column tiles per task: the fewest (a power of two up to gram_qmax) whose
+    // tasks fit in the work kernel's waves, else the most (workgroup uniform)
+    int qi = 0;
+    while (qi + 1 < kGramTileSteps && (2 << qi) <= gram_qmax && stot[1 + qi] > gram_nwaves)
+        ++qi;
+    const int Q = 1 << qi;
     if (own)
-        seg_next[j] = srun;
+        seg_next[j] = srun_[0];
     if (tid == 0)
-        seg_next[k] = seg_padded_end(stotal, pad, packed);
+        seg_next[k] = seg_padded_end(stot[0], pad, packed);
     if (own) {
         const int nA = (bj + gram_ta - 1) / gram_ta;
+        int trun = srun_[1 + qi];
 #pragma unroll
         for (int c = 0; c < kGroupSmallC; ++c) {
             if (c < C) {
                 goff[(int64_t)j * C + c] = trun;
                 if (((gram_mask >> c) & 1u) && cf[c] != 0.0) {
                     const int nec = c == 0 ? 1 : (c - 1 == p_new ? bj : ne[c]);
-                    trun += nA * ((nec + gram_te - 1) / gram_te);
+                    trun += nA * (((nec + gram_te - 1) / gram_te + Q - 1) / Q);
                 }
             }
         }
     }
-    if (tid == 0)
-        goff[(int64_t)k * C] = ttotal;
+    if (tid == 0) {
+        goff[(int64_t)k * C] = stot[1 + qi];
+        goff[(int64_t)k * C + 1] = Q;
+    }
     // ---- sum of min distances (FP64), in the order of the general variant
     double sm = 0.0;
 #pragma unroll
@@ -1044,7 +1062,7 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
 
 void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_expired, int init_alive_before,
                    int init_keep, const SlotList &live, const WindowRank &win, int lr, uint32_t gram_mask,
-                   int gram_ta, int gram_te, hipStream_t st)
+                   int gram_ta, int gram_te, int gram_qmax, int gram_nwaves, hipStream_t st)
 {
     const int nchunk = (b + kChunk - 1) / kChunk;
 #define MBKK_GO(LDS)                                                                                             \
@@ -1060,8 +1078,8 @@ void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_ex
                            p_expired, init_alive_before, init_keep, live, win, lr, B.gcnt, B.mind, B.coef, B.cum,
                            B.counts, B.alpha, B.ring_off + (int64_t)p_new * (L.k + 1), B.obj, B.labels, B.rank,
                            B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,
-                           B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_ta, gram_te, B.ring_off, B.goff, L.pad,
-                           (int)L.packed, B.seg_next);
+                           B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_ta, gram_te, gram_qmax,
+                           gram_nwaves, B.ring_off, B.goff, L.pad, (int)L.packed, B.seg_next);
     else if ((int64_t)nchunk * L.k <= kGroupLdsMax)
         MBKK_GO(true);
     else

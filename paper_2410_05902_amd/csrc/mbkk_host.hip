@@ -153,7 +153,7 @@ void carve(const Layout &Lc, char *base, Buffers &B)
     B.coef = (double *)take(8 * (size_t)L.k * C);
     B.cum = (double *)take(8 * (size_t)L.k);
     B.G = (double *)take(8 * (size_t)L.k * C * C);
-    B.goff = (int32_t *)take(4 * ((size_t)L.k * C + 1));
+    B.goff = (int32_t *)take(4 * ((size_t)L.k * C + 2));
     B.gpart = (double *)take(8 * ((size_t)kGramWaves + (size_t)L.k * C));
     B.N = (double *)take(8 * (size_t)L.k);
     B.counts = (int32_t *)take(4 * (size_t)L.k);
@@ -794,7 +794,8 @@ int mbkk_step(mbkk_ctx *c, const int32_t *batch, int32_t b, int32_t *labels_dev,
     for (int q = 0; q < live_after.n; ++q)
         win.rank[live_after.r[q]] = q;
     launch_update(L, B, b, p_new, p_expired, init_alive_before, init_keep, live, win, c->cfg.lr, mask,
-                  gram_task_rows(c->use_mfma), gram_task_cols(c->use_mfma, c->fp64), c->stream);
+                  gram_task_rows(c->use_mfma), gram_task_cols(c->use_mfma, c->fp64), gram_task_qmax(c->use_mfma),
+                  gram_waves(c->use_mfma), c->stream);
     gram(c, p_new, mask, true);
     c->seg_next_iter = i + 1;
     HIPCHK(c, hipGetLastError());

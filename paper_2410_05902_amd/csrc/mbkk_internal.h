@@ -89,7 +89,7 @@ struct Buffers {
     double *coef = nullptr;       // [k * C], C = P + 1
     double *cum = nullptr;        // [k]
     double *G = nullptr;          // [k * C * C]
-    int32_t *goff = nullptr;      // [k * C + 1] task offsets of the Gram blocks being computed
+    int32_t *goff = nullptr;      // [k * C + 2] task offsets of the Gram blocks being computed, their total, column tiles per task
     double *gpart = nullptr;      // [kGramWaves + k * C] their per-run partial sums
     double *N = nullptr;          // [k]
     int32_t *counts = nullptr;    // [k]

@@ -365,6 +365,21 @@ def test_free_running_mfma(precision):
     assert same == 8
 
 
+@pytest.mark.parametrize("k,b,window,steps", [(3, 2048, 3, 6), (2, 4096, 2, 4)])
+def test_free_running_mfma_large_clusters(k, b, window, steps):
+    """Clusters of 650-2100 rows: the Gram plan's 16 x 16 tasks outnumber the
+    work kernel's 5120 waves, so the plan takes 2-4 (first case) or 8 (second)
+    column tiles per task and each task loads its slot rows once for all of
+    them; the self norms after the last step against the oracle's."""
+    X, comp = _small_gmm(20000, 32, k, 0.3, seed=36, with_comp=True)
+    sigma = W.median_pairwise_distance(X, 0)
+    rng = np.random.default_rng(37)
+    batches = [rng.integers(0, 20000, b).astype(np.int32) for _ in range(steps)]
+    same = free_run(X, k, window, O.GAUSS, 2 * sigma * sigma, _one_per_component(comp, k), batches, "fp32",
+                    "mfma")
+    assert same == steps
+
+
 def test_free_running_fp64_direct():
     X, comp = _small_gmm(3000, 8, 6, 0.4, seed=34, with_comp=True)
     rng = np.random.default_rng(35)
