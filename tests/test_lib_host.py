@@ -35,6 +35,16 @@ def test_library_exports_every_declared_symbol():
     assert set(declared_symbols()) <= set(_lib.EXPORTS) | {"mbkk_last_error"}
 
 
+def test_probe_kinds_match_the_header():
+    """The binding's probe constants are the header's MBKK_PROBE_* values."""
+    from paper_2410_05902_amd import _lib
+    text = open(os.path.join(ROOT, "include", "mbkk_microbench.h")).read()
+    hdr = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define MBKK_PROBE_(\w+) (\d+)", text)}
+    assert hdr == {"SUBADD": _lib.PROBE_SUBADD, "FMA": _lib.PROBE_FMA, "EXP2": _lib.PROBE_EXP2,
+                   "MFMA_BF16": _lib.PROBE_MFMA_BF16, "MFMA_F32": _lib.PROBE_MFMA_F32,
+                   "MFMA_BF16_CHAIN": _lib.PROBE_MFMA_BF16_CHAIN}
+
+
 def _cfg(**kw):
     from paper_2410_05902_amd import _lib
     base = dict(n=1000, d=16, k=8, b_max=256, window=4, kernel=_lib.GAUSS, kernel_param=1.0,
