@@ -220,11 +220,25 @@ __device__ __forceinline__ void gram_mfma_work(const GramWork &A, int dp_rt, int
                     for (int u = 0; u < 4; ++u)
                         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q][u], ev[q][u], acc, 0, 0, 0);
             } else {
-                for (int s4 = 0; s4 < KQ; s4 += 4) {
-                    const f32x4 a4 = *(const f32x4 *)(sa + s4), e4 = *(const f32x4 *)(se + s4);
+                // row stride at run time: 8 steps of 4 coordinates per round
+                // of loads, all in flight before their products (clamped
+                // indices; the steps past the row skip their products)
+                constexpr int U = 8;
+                for (int s0 = 0; s0 < KQ; s0 += 4 * U) {
+                    f32x4 a4[U], e4[U];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[u], e4[u], acc, 0, 0, 0);
+                    for (int q = 0; q < U; ++q) {
+                        const int s4 = min(s0 + 4 * q, KQ - 4);
+                        a4[q] = *(const f32x4 *)(sa + s4);
+                        e4[q] = *(const f32x4 *)(se + s4);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+#pragma unroll
+                    for (int q = 0; q < U; ++q)
+                        if (s0 + 4 * q < KQ)  // wave uniform
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[q][u], e4[q][u], acc, 0, 0, 0);
                 }
             }
             // lane n (g = 0) publishes the norm of slot row n for the output
