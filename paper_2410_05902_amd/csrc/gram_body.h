@@ -157,8 +157,10 @@ __device__ __forceinline__ void gram_wave_loop(const GramWork &A, int32_t *stage
 // tasks would outnumber the waves), so a cluster of b_j rows pads to a
 // multiple of 16 rather than 32, and a large one loads its slot rows once
 // for up to 8 tiles.  Lane l = 16 g + n supplies
-// A[n][g] (slot row n) and B[g][n] (column row n) with g the quarter of the
-// coordinates it sums, [g dp/4, (g+1) dp/4); it holds D[4 g + i][n], i < 4.
+// A[n][g] (slot row n) and B[g][n] (column row n); the u-th MFMA of step t
+// takes coordinate 16 t + 4 g + u, so one 16-byte load per lane and step
+// serves four MFMAs and the four lanes of a row read 64 contiguous bytes
+// (16 cache lines per wave load, not 64).  The lane holds D[4 g + i][n], i < 4.
 // DP = 0 takes the row stride at run time.  blk: the physical workgroup index.
 // ---------------------------------------------------------------------------
 template <int DP>
@@ -186,14 +188,14 @@ __device__ __forceinline__ void gram_mfma_work(const GramWork &A, int dp_rt, int
         int32_t pe = ep[min(qe, ec.n - 1)];
         const int64_t ra = qa < a.n ? a.row0 + pa : zero_row;
         const float sqa_v = poolsq[ra];
-        const float *sa = pool32 + ra * dp + g * KQ;
+        const float *sa = pool32 + ra * dp + 4 * g;
         // the slot rows' coordinates, loaded once for every tile of the task
         constexpr int NS = DP > 0 ? DP / 16 : 1;
         f32x4 av[NS];
         if constexpr (DP > 0) {
 #pragma unroll
             for (int q = 0; q < NS; ++q)
-                av[q] = *(const f32x4 *)(sa + 4 * q);
+                av[q] = *(const f32x4 *)(sa + 16 * q);
         }
         for (int tile = tile0; tile < tile1; ++tile) {
             if (tile != tile0) {
@@ -202,7 +204,7 @@ __device__ __forceinline__ void gram_mfma_work(const GramWork &A, int dp_rt, int
             }
             const int64_t re = qe < ec.n ? (ec.perm ? ec.row0 + pe : ec.row0) : zero_row;
             const float sqe_v = poolsq[re];
-            const float *se = pool32 + re * dp + g * KQ;
+            const float *se = pool32 + re * dp + 4 * g;
             f32x4 acc;
 #pragma unroll
             for (int i = 0; i < 4; ++i)
@@ -212,7 +214,7 @@ __device__ __forceinline__ void gram_mfma_work(const GramWork &A, int dp_rt, int
                 f32x4 ev[NS];
 #pragma unroll
                 for (int q = 0; q < NS; ++q)
-                    ev[q] = *(const f32x4 *)(se + 4 * q);
+                    ev[q] = *(const f32x4 *)(se + 16 * q);
                 __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
 #pragma unroll
                 for (int q = 0; q < NS; ++q)
@@ -229,8 +231,8 @@ __device__ __forceinline__ void gram_mfma_work(const GramWork &A, int dp_rt, int
 #pragma unroll
                     for (int q = 0; q < U; ++q) {
                         const int s4 = min(s0 + 4 * q, KQ - 4);
-                        a4[q] = *(const f32x4 *)(sa + s4);
-                        e4[q] = *(const f32x4 *)(se + s4);
+                        a4[q] = *(const f32x4 *)(sa + 4 * s4);
+                        e4[q] = *(const f32x4 *)(se + 4 * s4);
                     }
                     __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
 #pragma unroll
