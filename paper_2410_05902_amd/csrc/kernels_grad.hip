@@ -353,10 +353,12 @@ __global__ __launch_bounds__(256) void k_sigma_gram(const SigmaGramArgs A)
 #pragma unroll
                 for (int i = 0; i < 16; ++i)
                     acc[i] = 0.0f;
-                const float *pa = A.pool32 + ra * DP + h * KS, *pe = A.pool32 + re * DP + h * KS;
+                // the u-th MFMA of step q takes coordinate 8 q + 4 h + u: the
+                // two lanes of a row read 32 contiguous bytes per step
+                const float *pa = A.pool32 + ra * DP + 4 * h, *pe = A.pool32 + re * DP + 4 * h;
 #pragma unroll
                 for (int s4 = 0; s4 < KS; s4 += 4) {
-                    const f32x4 av = *(const f32x4 *)(pa + s4), ev = *(const f32x4 *)(pe + s4);
+                    const f32x4 av = *(const f32x4 *)(pa + 2 * s4), ev = *(const f32x4 *)(pe + 2 * s4);
 #pragma unroll
                     for (int q = 0; q < 4; ++q)
                         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av[q], ev[q], acc, 0, 0, 0);
@@ -595,13 +597,15 @@ __global__ __launch_bounds__(64 * grad_waves<DP>()) void k_grad_mfma(const GradM
         xsq[threadIdx.x] = row >= 0 ? A.batsq[row] : 0.0f;
     }
     __syncthreads();
-    // this lane's A fragments: row n of the task, coordinates [h KS, (h+1) KS)
+    // this lane's A fragments: row n of the task, coordinates 8 q + 4 h + u
+    // (the u-th MFMA of step q), so the two lanes of a row read 32
+    // contiguous bytes per step
     const int myrow = rows[n];
-    const float *px = myrow >= 0 ? A.bat32 + (int64_t)myrow * DP + h * KS : A.pool32 + A.zero_row * DP + h * KS;
+    const float *px = myrow >= 0 ? A.bat32 + (int64_t)myrow * DP + 4 * h : A.pool32 + A.zero_row * DP + 4 * h;
     f32x4 xf[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q)
-        xf[q] = *(const f32x4 *)(px + 4 * q);
+        xf[q] = *(const f32x4 *)(px + 8 * q);
     f32x16 G[NT];
 #pragma unroll
     for (int tb = 0; tb < NT; ++tb)
@@ -612,7 +616,7 @@ __global__ __launch_bounds__(64 * grad_waves<DP>()) void k_grad_mfma(const GradM
     const int s0 = A.seg_off[j], s1 = A.seg_off[j + 1], nb = (s1 - s0 + 31) / 32;
     float(*Y)[YS] = Yl[wl];
     float(*P)[33] = Pl[wl];
-    // block eb's row n, half h (coordinates), weight and norm: loaded one block ahead
+    // block eb's row n (this lane's coordinates 8 q + 4 h + u), weight and norm: loaded one block ahead
     f32x4 yv[NV];
     float we = 0.0f, sqe = 0.0f;
     auto fetch = [&](int eb) {
@@ -621,10 +625,10 @@ __global__ __launch_bounds__(64 * grad_waves<DP>()) void k_grad_mfma(const GradM
         const int64_t re = A.sup_row[se];
         we = A.sup_w[se];
         sqe = A.poolsq[re];
-        const float *pe = A.pool32 + re * DP + h * KS;
+        const float *pe = A.pool32 + re * DP + 4 * h;
 #pragma unroll
         for (int q = 0; q < NV; ++q)
-            yv[q] = *(const f32x4 *)(pe + 4 * q);
+            yv[q] = *(const f32x4 *)(pe + 8 * q);
     };
     if (wl < nb)
         fetch(wl);
@@ -632,7 +636,7 @@ __global__ __launch_bounds__(64 * grad_waves<DP>()) void k_grad_mfma(const GradM
         __builtin_amdgcn_wave_barrier();  // the previous block is done with the tiles
 #pragma unroll
         for (int q = 0; q < NV; ++q)
-            *(f32x4 *)&Y[n][h * KS + 4 * q] = yv[q];
+            *(f32x4 *)&Y[n][8 * q + 4 * h] = yv[q];
         const float w_cur = we, sq_cur = sqe;
         if (eb + NW < nb)
             fetch(eb + NW);
@@ -643,7 +647,7 @@ __global__ __launch_bounds__(64 * grad_waves<DP>()) void k_grad_mfma(const GradM
             acc[i] = 0.0f;
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
-            const f32x4 ev = *(const f32x4 *)&Y[n][h * KS + 4 * q];
+            const f32x4 ev = *(const f32x4 *)&Y[n][8 * q + 4 * h];
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 acc = __builtin_amdgcn_mfma_f32_32x32x2f32(xf[q][u], ev[u], acc, 0, 0, 0);
