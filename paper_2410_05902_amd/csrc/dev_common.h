@@ -10,28 +10,85 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
+// Lane i of the result takes x from lane i - n of its row of 16 lanes, 0
+// where there is none (DPP row_shr; CTRL = 0x110 + n), or, for the row
+// broadcasts (CTRL 0x142: lane 15 of each row, 0x143: lane 31), the
+// broadcast value in the rows of ROWS and 0 in the others.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ int dpp_or_zero(int x)
+{
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, ROWS, 0xf, false);
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave (every lane active), on
+// the DPP paths of the register file: shifts by 1, 2, 4 and 8 inside each row
+// of 16 lanes, then row 0's total into row 1 and row 2's into row 3, then
+// the first two rows' total into rows 2 and 3.  No LDS round trips.
+__device__ __forceinline__ int wave_inclusive_sum(int x)
+{
+    x += dpp_or_zero<0x111>(x);
+    x += dpp_or_zero<0x112>(x);
+    x += dpp_or_zero<0x114>(x);
+    x += dpp_or_zero<0x118>(x);
+    x += dpp_or_zero<0x142, 0xa>(x);
+    x += dpp_or_zero<0x143, 0xc>(x);
+    return x;
+}
+
+// Maximum over the 64 lanes of a wave (every lane active), the same in every
+// lane: exchanges inside quads and rows by DPP (partners 1 and 2 apart, then
+// the mirrored half-row and row, whose lanes all hold the same value by then),
+// then the four rows' maxima read as scalars.
+__device__ __forceinline__ int wave_max(int x)
+{
+    x = max(x, __builtin_amdgcn_update_dpp(x, x, 0xb1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
+    x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x4e, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
+    x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x141, 0xf, 0xf, false));  // row_half_mirror
+    x = max(x, __builtin_amdgcn_update_dpp(x, x, 0x140, 0xf, 0xf, false));  // row_mirror
+    return max(max(__builtin_amdgcn_readlane(x, 0), __builtin_amdgcn_readlane(x, 16)),
+               max(__builtin_amdgcn_readlane(x, 32), __builtin_amdgcn_readlane(x, 48)));
+}
+
+// Sum over the 64 lanes of a wave (every lane active), the same in every
+// lane and in a fixed order: lane pairs 1 and 2 apart inside quads, then the
+// mirrored half-row and row (whose lanes hold equal values by then), all by
+// DPP, then the four row sums as ((row 0 + row 1) + (row 2 + row 3)).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+    v += dpp_f64<0xb1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4e>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
 // Block-wide exclusive scan of one int per thread (blockDim.x a multiple of
-// 64, at most 1024): wave scans with shuffles, then a scan of the wave totals.
-// `lds` holds at least 16 ints.  Returns the exclusive prefix; *total gets the sum.
+// 64, at most 1024): wave scans, then a scan of the wave totals.  `lds` holds
+// at least 16 ints.  Returns the exclusive prefix; *total gets the sum.
 __device__ __forceinline__ int block_exclusive_scan(int v, int *lds, int *total)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    int x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o);
-        if (lane >= o)
-            x += y;
-    }
+    const int x = wave_inclusive_sum(v);
     if (lane == 63)
         lds[wid] = x;
     __syncthreads();
     if (wid == 0) {
-        int t = lane < nw ? lds[lane] : 0;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(t, o);
-            if (lane >= o)
-                t += y;
-        }
+        const int t = wave_inclusive_sum(lane < nw ? lds[lane] : 0);
         if (lane < nw)
             lds[lane] = t;
     }
@@ -47,28 +104,15 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int *lds, int *total)
 __device__ __forceinline__ int block_exclusive_scan2(int a, int b, int *lds, int *tot_a, int *run_b, int *tot_b)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    int x = a, y = b;
-    for (int o = 1; o < 64; o <<= 1) {
-        const int xa = __shfl_up(x, o), yb = __shfl_up(y, o);
-        if (lane >= o) {
-            x += xa;
-            y += yb;
-        }
-    }
+    const int x = wave_inclusive_sum(a), y = wave_inclusive_sum(b);
     if (lane == 63) {
         lds[wid] = x;
         lds[16 + wid] = y;
     }
     __syncthreads();
     if (wid == 0) {
-        int t = lane < nw ? lds[lane] : 0, u = lane < nw ? lds[16 + lane] : 0;
-        for (int o = 1; o < 64; o <<= 1) {
-            const int ta = __shfl_up(t, o), ub = __shfl_up(u, o);
-            if (lane >= o) {
-                t += ta;
-                u += ub;
-            }
-        }
+        const int t = wave_inclusive_sum(lane < nw ? lds[lane] : 0);
+        const int u = wave_inclusive_sum(lane < nw ? lds[16 + lane] : 0);
         if (lane < nw) {
             lds[lane] = t;
             lds[16 + lane] = u;
@@ -92,15 +136,7 @@ __device__ __forceinline__ void block_exclusive_scan_n(const int (&v)[N], int *l
     int x[N];
 #pragma unroll
     for (int q = 0; q < N; ++q)
-        x[q] = v[q];
-    for (int o = 1; o < 64; o <<= 1) {
-#pragma unroll
-        for (int q = 0; q < N; ++q) {
-            const int y = __shfl_up(x[q], o);
-            if (lane >= o)
-                x[q] += y;
-        }
-    }
+        x[q] = wave_inclusive_sum(v[q]);
     if (lane == 63) {
 #pragma unroll
         for (int q = 0; q < N; ++q)
@@ -111,15 +147,7 @@ __device__ __forceinline__ void block_exclusive_scan_n(const int (&v)[N], int *l
         int t[N];
 #pragma unroll
         for (int q = 0; q < N; ++q)
-            t[q] = lane < nw ? lds[16 * q + lane] : 0;
-        for (int o = 1; o < 64; o <<= 1) {
-#pragma unroll
-            for (int q = 0; q < N; ++q) {
-                const int y = __shfl_up(t[q], o);
-                if (lane >= o)
-                    t[q] += y;
-            }
-        }
+            t[q] = wave_inclusive_sum(lane < nw ? lds[16 * q + lane] : 0);
         if (lane < nw) {
 #pragma unroll
             for (int q = 0; q < N; ++q)
@@ -135,13 +163,12 @@ __device__ __forceinline__ void block_exclusive_scan_n(const int (&v)[N], int *l
     __syncthreads();
 }
 
-// Block-wide sum of one double per thread, in a fixed order (wave trees,
+// Block-wide sum of one double per thread, in a fixed order (wave sums,
 // then the wave totals in order).  `lds` holds at least 16 doubles.
 __device__ __forceinline__ double block_sum(double v, double *lds)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int o = 32; o > 0; o >>= 1)
-        v += __shfl_xor(v, o);
+    v = wave_sum_f64(v);
     if (lane == 0)
         lds[wid] = v;
     __syncthreads();

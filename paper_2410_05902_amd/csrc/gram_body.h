@@ -141,8 +141,7 @@ __device__ __forceinline__ void gram_wave_loop(const GramWork &A, int32_t *stage
                 const int ab = u / nE, eb = u - ab * nE;
                 task(a, ec, ab, eb, Q, lsum);
             }
-            for (int o = 32; o > 0; o >>= 1)
-                lsum += __shfl_xor(lsum, o);
+            lsum = wave_sum_f64(lsum);
             if (lane == 0)
                 A.gpart[w + jc] = lsum;
         }

@@ -400,6 +400,7 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
     __shared__ int sA0[kMaxSlots], sN[kMaxSlots];  // live slot s: first grouped row of j, rows (0: weight 0)
     __shared__ int sSeg[2];
     __shared__ int sBig[MC];                // column whose fold has more than FL partials
+    __shared__ double sNt[MC * MC];         // the terms of N_j
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const double *cfj = coef + (int64_t)j * C;
     double *gj = G + (int64_t)j * C * C;
@@ -499,31 +500,65 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
         // ---- entries: the initial point (while alive, weight != 0), then the
         // center's rows of every live slot with weight != 0, oldest first, then
         // the zero row up to the padded length
+        // (FU entries per thread per round, whose permutation and norm loads
+        // are issued together at clamped indices: a large center's entries
+        // then cost two load round trips, not two per 256 entries)
+        constexpr int FU = 4;
         const int ni = init_alive && scf[0] != 0.0 ? 1 : 0;
-        for (int q = tid; q < plen; q += 256) {
-            int64_t row = zero_row;
-            double w = 0.0;
-            if (q < ni) {
-                row = j;
-                w = scf[0];
-            } else {
-                int r = q - ni;
-                for (int s = 0; s < live.n; ++s) {
-                    const int ns = sN[s];
-                    if (r < ns) {
-                        const int p = live.r[s];
-                        row = (int64_t)k + (int64_t)p * bmax + ring_perm[(int64_t)p * bmax + sA0[s] + r];
-                        w = scf[1 + p];
-                        break;
+        for (int qb = tid; qb < plen; qb += 256 * FU) {
+            int64_t row[FU];
+            double w[FU];
+            int64_t pidx[FU];  // index into ring_perm, -1 for the initial point and padding
+#pragma unroll
+            for (int u = 0; u < FU; ++u) {
+                const int q = qb + 256 * u;
+                row[u] = zero_row;
+                w[u] = 0.0;
+                pidx[u] = -1;
+                if (q < plen) {
+                    if (q < ni) {
+                        row[u] = j;
+                        w[u] = scf[0];
+                    } else {
+                        int r = q - ni;
+                        for (int s = 0; s < live.n; ++s) {
+                            const int ns = sN[s];
+                            if (r < ns) {
+                                const int p = live.r[s];
+                                row[u] = (int64_t)k + (int64_t)p * bmax;
+                                pidx[u] = (int64_t)p * bmax + sA0[s] + r;
+                                w[u] = scf[1 + p];
+                                break;
+                            }
+                            r -= ns;
+                        }
                     }
-                    r -= ns;
                 }
             }
-            sup_row[start + q] = (int32_t)row;
-            sup_w[start + q] = (float)w;
-            sup_w64[start + q] = w;
-            if (sup_ay)
-                sup_ay[start + q] = row == zero_row ? 0.0f : ay_scale * poolsq[row];
+            int pv[FU];
+#pragma unroll
+            for (int u = 0; u < FU; ++u)
+                pv[u] = ring_perm[max(pidx[u], (int64_t)0)];
+#pragma unroll
+            for (int u = 0; u < FU; ++u)
+                row[u] += pidx[u] >= 0 ? pv[u] : 0;
+            float ya[FU];
+            if (sup_ay) {
+#pragma unroll
+                for (int u = 0; u < FU; ++u)
+                    ya[u] = poolsq[row[u]];  // the zero row's entry exists (and is 0)
+            }
+#pragma unroll
+            for (int u = 0; u < FU; ++u) {
+                const int q = qb + 256 * u;
+                if (q < plen) {
+                    sup_row[start + q] = (int32_t)row[u];
+                    sup_w[start + q] = (float)w[u];
+                    sup_w64[start + q] = w[u];
+                    if (sup_ay)
+                        sup_ay[start + q] = row[u] == zero_row ? 0.0f : ay_scale * ya[u];
+                }
+            }
         }
         if (blk_center) {
             for (int q = start / 32 + tid; q < (start + plen) / 32; q += 256)
@@ -571,18 +606,20 @@ __device__ void support_fill_body(const SupportArgs &A, int j)
         }
     }
     __syncthreads();
-    // ---- N_j from the Gram blocks (FP64), in a fixed order
+    // ---- N_j from the Gram blocks (FP64), in a fixed order: the products of
+    // the live columns' pairs (a, e) by one thread each, then their sum, a
+    // major and e minor, by one thread
+    const int nc = (init_alive ? 1 : 0) + live.n;
+    auto col_of = [&](int i) { return init_alive ? (i == 0 ? 0 : 1 + live.r[i - 1]) : 1 + live.r[i]; };
+    for (int t = tid; t < nc * nc; t += 256) {
+        const int ca = col_of(t / nc), ce = col_of(t % nc);
+        sNt[t] = scf[ca] * scf[ce] * sG[ca * C + ce];
+    }
+    __syncthreads();
     if (tid == 0) {
-        int cols[kMaxSlots + 1];
-        int nc = 0;
-        if (init_alive)
-            cols[nc++] = 0;
-        for (int s = 0; s < live.n; ++s)
-            cols[nc++] = 1 + live.r[s];
         double nn = 0.0;
-        for (int a = 0; a < nc; ++a)
-            for (int e = 0; e < nc; ++e)
-                nn += scf[cols[a]] * scf[cols[e]] * sG[cols[a] * C + cols[e]];
+        for (int t = 0; t < nc * nc; ++t)
+            nn += sNt[t];
         A.N[j] = nn;
     }
 }
@@ -775,8 +812,10 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
     }
 }
 
-// Variant for k <= kGroupSmallK, nchunk * k <= kGroupLdsMax and C <= kGroupSmallC
-// (each thread owns at most one center): every global load that does not
+// Variant for k <= kGroupSmallK, nchunk * k <= kGroupLdsMax, C <= kGroupSmallC
+// and Gram task shapes that are powers of two (each thread owns at most one
+// center; one workgroup, so the per-center work is a serial chain of a wave's
+// instructions, and divisions are shifts): every global load that does not
 // depend on a result of this kernel is issued at its start (the rows' labels,
 // ranks, points and distances, the center's coefficient row and the ring
 // offsets the Gram plan needs), so the phases below wait on LDS only.  The
@@ -794,6 +833,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
     int packed, int32_t *__restrict__ seg_next)
 {
     constexpr int RPT = kMaxBatch / kGroupThreads;  // batch rows per thread
+    // the task rows and columns are powers of two (the launch checks it)
+    const int lta = __builtin_ctz((unsigned)gram_ta), lte = __builtin_ctz((unsigned)gram_te);
     __shared__ int sint[16 * (1 + kGramTileSteps)];
     __shared__ double sdbl[16];
     __shared__ int scnt[kGroupLdsMax];    // per-(chunk, label) counts, then bases, then the grouped rows
@@ -910,6 +951,10 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
     // ---- learning rate and the coefficient update of center j
     int tasks[kGramTileSteps] = {};  // Gram tasks of 1, 2, 4, ... column tiles
     int slen = 0;
+    int nA = 0, ntl[kGroupSmallC];  // slot-row tiles, and column tiles of the counted columns (else 0)
+#pragma unroll
+    for (int c = 0; c < kGroupSmallC; ++c)
+        ntl[c] = 0;
     if (own) {
         double a;
         if (lr == MBKK_LR_FULL)
@@ -975,15 +1020,15 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
         // Gram tasks of the new slot against the live columns that keep a
         // weight (for each number of column tiles per task), and the padded
         // segment of center j in the next support
-        const int nA = (bj + gram_ta - 1) / gram_ta;
+        nA = (bj + gram_ta - 1) >> lta;
 #pragma unroll
         for (int c = 0; c < kGroupSmallC; ++c) {
             if (c < C && ((gram_mask >> c) & 1u) && cf[c] != 0.0) {
                 const int nec = c == 0 ? 1 : (c - 1 == p_new ? bj : ne[c]);
-                const int ntile = (nec + gram_te - 1) / gram_te;
+                ntl[c] = (nec + gram_te - 1) >> lte;
 #pragma unroll
                 for (int qi = 0; qi < kGramTileSteps; ++qi)
-                    tasks[qi] += nA * ((ntile + (1 << qi) - 1) >> qi);
+                    tasks[qi] += nA * ((ntl[c] + (1 << qi) - 1) >> qi);
                 slen += nec;
             }
         }
@@ -1006,16 +1051,12 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
     if (tid == 0)
         seg_next[k] = seg_padded_end(stot[0], pad, packed);
     if (own) {
-        const int nA = (bj + gram_ta - 1) / gram_ta;
         int trun = srun_[1 + qi];
 #pragma unroll
         for (int c = 0; c < kGroupSmallC; ++c) {
             if (c < C) {
                 goff[(int64_t)j * C + c] = trun;
-                if (((gram_mask >> c) & 1u) && cf[c] != 0.0) {
-                    const int nec = c == 0 ? 1 : (c - 1 == p_new ? bj : ne[c]);
-                    trun += nA * (((nec + gram_te - 1) / gram_te + Q - 1) / Q);
-                }
+                trun += nA * ((ntl[c] + Q - 1) >> qi);
             }
         }
     }
@@ -1073,7 +1114,8 @@ void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_ex
                        B.slot_pts + (int64_t)p_new * L.bmax, B.ring_idx + (int64_t)p_new * L.bmax,               \
                        B.ring_perm + (int64_t)p_new * L.bmax, gram_mask, gram_ta, gram_te, B.ring_off, B.goff, L.pad,  \
                        (int)L.packed, B.seg_next)
-    if (L.k <= kGroupSmallK && (int64_t)nchunk * L.k <= kGroupLdsMax && L.C <= kGroupSmallC)
+    const bool pow2 = (gram_ta & (gram_ta - 1)) == 0 && (gram_te & (gram_te - 1)) == 0;
+    if (L.k <= kGroupSmallK && (int64_t)nchunk * L.k <= kGroupLdsMax && L.C <= kGroupSmallC && pow2)
         hipLaunchKernelGGL(k_group_offsets_small, dim3(1), dim3(kGroupThreads), 0, st, b, L.k, nchunk, L.C, p_new,
                            p_expired, init_alive_before, init_keep, live, win, lr, B.gcnt, B.mind, B.coef, B.cum,
                            B.counts, B.alpha, B.ring_off + (int64_t)p_new * (L.k + 1), B.obj, B.labels, B.rank,

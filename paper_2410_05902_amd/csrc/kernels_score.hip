@@ -168,6 +168,23 @@ __device__ __forceinline__ bool lex_less(double a, int la, double b, int lb)
     return a < b || (a == b && la < lb);
 }
 
+// One butterfly step of the per-row merge: the partner lane's (best, label,
+// second) by the DPP pattern CTRL, then the lexicographically smaller best
+// and the smallest remaining value as the second.
+template <int CTRL>
+__device__ __forceinline__ void score_merge_step(double &b0, int &l0, double &s0)
+{
+    const double bq = dpp_f64<CTRL>(b0), sq = dpp_f64<CTRL>(s0);
+    const int lq = __builtin_amdgcn_update_dpp(0, l0, CTRL, 0xf, 0xf, false);
+    if (lex_less(bq, lq, b0, l0)) {
+        s0 = fmin(b0, sq);
+        b0 = bq;
+        l0 = lq;
+    } else {
+        s0 = fmin(s0, bq);
+    }
+}
+
 struct ScoreArgs {
     int nb, k, ldp, RB, kind;
     int nranges;  // > 0: RB of the batch-stationary kernel, derived from the support size
@@ -270,11 +287,13 @@ constexpr int kScoreLdsK = 2048;
 template <typename T, int LAYOUT, bool RESCORE, bool LK>
 __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
 {
-    __shared__ double sb[kScoreWaves][64], ss[kScoreWaves][64];
-    __shared__ int sl[kScoreWaves][64];
+    // per-wave (best, second, label) of each row, row-major with one pad entry
+    // so that neither the waves' stores nor the merge's loads share banks
+    __shared__ double sb[64][kScoreWaves + 1], ss[64][kScoreWaves + 1];
+    __shared__ int sl[64][kScoreWaves + 1];
     __shared__ int flab[64];
     __shared__ float fmin_[64], fmar[64];
-    __shared__ double fdel[64], fbest[64];
+    __shared__ double fdel[64], fbest[64], sep0[64];
     __shared__ int smax_seg, snresc;
     __shared__ int32_t lseg[LK ? kScoreLdsK + 1 : 1];
     __shared__ double lN[LK ? kScoreLdsK : 1];
@@ -283,6 +302,9 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
     const bool act = row < A.nb;
     const T *part = (const T *)A.part;
     const double x2row = A.batsq64[min(row, A.nb - 1)];
+    // the merge below gives wave w rows 4w .. 4w + 3, 16 lanes each
+    static_assert(kScoreWaves == 16, "16 partial triples per row, one per lane of a DPP row");
+    const int mrow = w * 4 + (lane >> 4), mq = lane & 15;
     // loads in issue order: the LDS copy's first pass, then the partials of
     // the wave's first batch of centers (j = w, w + 16, ...), whose segment
     // bounds are scalar loads (the center index is wave-uniform), so that
@@ -337,6 +359,13 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
         Nv = lN;
     }
     const double kxx = act ? self_kernel(A.kind, A.param, x2row) : 0.0;
+    if (RESCORE && w == kScoreWaves - 1 && !(A.delta > 0.0)) {
+        // the row's part of the error bound below that needs no other wave,
+        // taken while the partials are in flight
+        const double x2 = act ? x2row : 0.0, y2 = A.ymax2;
+        const double xn = sqrt(x2), yn = sqrt(y2);
+        sep0[lane] = (2.0 * A.rel_dot * xn * yn + 0x1p-22 * (x2 + y2)) / A.kappa;
+    }
     if constexpr (RESCORE) {
         // longest center segment: the length of the FP32 sums in the error bound
         if (threadIdx.x == 0) {
@@ -347,8 +376,7 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
         int m = 0;
         for (int i = threadIdx.x; i < A.k; i += 64 * kScoreWaves)
             m = max(m, seg_off[i + 1] - seg_off[i]);
-        for (int o = 32; o > 0; o >>= 1)
-            m = max(m, __shfl_xor(m, o));
+        m = wave_max(m);
         if (lane == 0)
             atomicMax(&smax_seg, m);
     }
@@ -395,61 +423,63 @@ __global__ __launch_bounds__(64 * kScoreWaves) void k_score(const ScoreArgs A)
             }
         }
     }
-    sb[w][lane] = best;
-    ss[w][lane] = second;
-    sl[w][lane] = lab;
+    sb[lane][w] = best;
+    ss[lane][w] = second;
+    sl[lane][w] = lab;
     __syncthreads();
-    if (w == 0) {
-        double b0 = sb[0][lane], s0 = ss[0][lane];
-        int l0 = sl[0][lane];
-        for (int q = 1; q < kScoreWaves; ++q) {
-            const double bq = sb[q][lane], sq = ss[q][lane];
-            const int lq = sl[q][lane];
-            if (lex_less(bq, lq, b0, l0)) {
-                s0 = fmin(b0, sq);
-                b0 = bq;
-                l0 = lq;
-            } else {
-                s0 = fmin(s0, bq);
+    {
+        // the 16 triples of row mrow, one per lane of a DPP row, merged by a
+        // butterfly; the merge is an exact selection (the lexicographic
+        // minimum of (distance, label), then the smallest other value), so
+        // every order gives the sequential result
+        double b0 = sb[mrow][mq], s0 = ss[mrow][mq];
+        int l0 = sl[mrow][mq];
+        score_merge_step<0xb1>(b0, l0, s0);   // quad_perm [1,0,3,2]
+        score_merge_step<0x4e>(b0, l0, s0);   // quad_perm [2,3,0,1]
+        score_merge_step<0x141>(b0, l0, s0);  // row_half_mirror
+        score_merge_step<0x140>(b0, l0, s0);  // row_mirror
+        if (mq == 0) {
+            // a row whose distances are all NaN (non-finite input) matched no
+            // center: it is assigned to center 0 so that every label is in range
+            if (!(l0 >= 0 && l0 < A.k))
+                l0 = 0;
+            flab[mrow] = l0;
+            fmin_[mrow] = (float)b0;
+            fmar[mrow] = (float)(s0 - b0);
+            if constexpr (RESCORE) {
+                // Error bound of an approximate distance D_j (Gaussian, BF16 form):
+                // the exponent a = (2 x.y - |x|^2 - |y|^2) / kappa has
+                // |da| <= (2 rel_dot |x||y| + 2^-22 (|x|^2 + |y|^2)) / kappa = e(x, y)
+                // (rel_dot: relative error of x.y against sum |x_t y_t| <= |x||y|;
+                // 2^-22: the FP32 roundings of the norms and of the FMA), so a
+                // kernel value has relative error <= e, and with weights summing
+                // to at most 1 and kernel values at most 1
+                //   |dP_j| <= e(x, Y) + S 2^-24,  |dN_j| <= e(Y, Y) + S 2^-24
+                // (Y^2 = max |y|^2 over the data, S = longest segment: the FP32
+                // sums).  N_j comes from FP32 kernel values summed in FP64: its
+                // bound eN is the host's.  A margin above 2 (2 |dP| + |dN|) cannot
+                // hide a swap.
+                double dl = A.delta;
+                if (!(dl > 0.0)) {
+                    const double gS = (double)smax_seg * 0x1p-24;
+                    const double eP = sep0[mrow] + gS;  // e(x, Y) from before the main loop
+                    dl = 2.0 * (2.0 * eP + A.eN);
+                }
+                fdel[mrow] = dl;
+                fbest[mrow] = b0;
             }
-        }
-        // a row whose distances are all NaN (non-finite input) matched no
-        // center: it is assigned to center 0 so that every label is in range
-        if (!(l0 >= 0 && l0 < A.k))
-            l0 = 0;
-        flab[lane] = l0;
-        fmin_[lane] = (float)b0;
-        fmar[lane] = (float)(s0 - b0);
-        if constexpr (RESCORE) {
-            // Error bound of an approximate distance D_j (Gaussian, BF16 form):
-            // the exponent a = (2 x.y - |x|^2 - |y|^2) / kappa has
-            // |da| <= (2 rel_dot |x||y| + 2^-22 (|x|^2 + |y|^2)) / kappa = e(x, y)
-            // (rel_dot: relative error of x.y against sum |x_t y_t| <= |x||y|;
-            // 2^-22: the FP32 roundings of the norms and of the FMA), so a
-            // kernel value has relative error <= e, and with weights summing
-            // to at most 1 and kernel values at most 1
-            //   |dP_j| <= e(x, Y) + S 2^-24,  |dN_j| <= e(Y, Y) + S 2^-24
-            // (Y^2 = max |y|^2 over the data, S = longest segment: the FP32
-            // sums).  N_j comes from FP32 kernel values summed in FP64: its
-            // bound eN is the host's.  A margin above 2 (2 |dP| + |dN|) cannot
-            // hide a swap.
-            double dl = A.delta;
-            if (!(dl > 0.0)) {
-                const double x2 = act ? A.batsq64[row] : 0.0, y2 = A.ymax2;
-                const double xn = sqrt(x2), yn = sqrt(y2);
-                const double gS = (double)smax_seg * 0x1p-24;
-                const double eP = (2.0 * A.rel_dot * xn * yn + 0x1p-22 * (x2 + y2)) / A.kappa + gS;
-                dl = 2.0 * (2.0 * eP + A.eN);
-            }
-            fdel[lane] = dl;
-            fbest[lane] = b0;
         }
     }
     __syncthreads();
     if constexpr (RESCORE) {
-        for (int r = w; r < 64; r += kScoreWaves) {  // wave-uniform row loop
+        // the wave's rows w, w + 16, w + 32, w + 48, tested by lanes 0-3 at once
+        const int rt = w + kScoreWaves * (lane & 3);
+        uint64_t todo = __ballot(lane < 4 && blockIdx.x * 64 + rt < A.nb && (double)fmar[rt] < fdel[rt]);
+        while (todo) {  // wave-uniform row loop
+            const int r = w + kScoreWaves * (__ffsll((unsigned long long)todo) - 1);
+            todo &= todo - 1;
             const int rw = blockIdx.x * 64 + r;
-            if (rw < A.nb && (double)fmar[r] < fdel[r]) {
+            {
                 int l;
                 float m, g;
                 rescore_row<LAYOUT>(A, rw, RB, fdel[r], fbest[r], seg_off, Nv, l, m, g);
