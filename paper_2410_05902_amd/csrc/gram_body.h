@@ -169,7 +169,7 @@ __device__ __forceinline__ void gram_mfma_work(const GramWork &A, int dp_rt, int
 {
     const int dp = DP > 0 ? DP : dp_rt;
     const int KQ = dp / 4;
-    __shared__ float sqa[kGramWG / 64][16];
+    __shared__ __attribute__((aligned(16))) float sqa[kGramWG / 64][16];
     __shared__ int32_t stage[kGramStage];
     const int lane = threadIdx.x & 63, wl = threadIdx.x >> 6, n = lane & 15, g = lane >> 4;
     gram_wave_loop<16, true>(A, stage, blk, [&](const GramCol &a, const GramCol &ec, int ab, int eb, int Q,
@@ -215,6 +215,10 @@ __device__ __forceinline__ void gram_mfma_work(const GramWork &A, int dp_rt, int
                 for (int q = 0; q < NS; ++q)
                     ev[q] = *(const f32x4 *)(se + 16 * q);
                 __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+                // the slot row's norm is needed by this point (the products
+                // wait for the later row loads anyway), so its load is not
+                // sunk into the branch that publishes it below
+                asm volatile("" ::"v"(sqa_v));
 #pragma unroll
                 for (int q = 0; q < NS; ++q)
 #pragma unroll
@@ -248,13 +252,16 @@ __device__ __forceinline__ void gram_mfma_work(const GramWork &A, int dp_rt, int
                 sqa[wl][n] = c1 * sqa_v;
             const float se_ = c1 * sqe_v;
             // lane: column n (column row), rows m = 4 g + i (slot rows); the
-            // row norms were written by this wave (in-order LDS access)
+            // row norms were written by this wave (in-order LDS access) and
+            // are read as one 16-byte load; rows past the cluster add an
+            // exact 0 (the sum is positive, so no sign of zero changes)
             if (qe < ec.n) {
+                const f32x4 sq4 = *(const f32x4 *)&sqa[wl][4 * g];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const int m = 4 * g + i;
-                    if (ab * 16 + m < a.n)
-                        lsum += (double)__builtin_amdgcn_exp2f(fmaf(acc[i], c2, sqa[wl][m] + se_));
+                    const double t = (double)__builtin_amdgcn_exp2f(fmaf(acc[i], c2, sq4[i] + se_));
+                    lsum += ab * 16 + m < a.n ? t : 0.0;
                 }
             }
         }
