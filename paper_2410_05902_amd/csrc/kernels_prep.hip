@@ -1043,6 +1043,8 @@ __global__ __launch_bounds__(kGroupThreads) void k_group_offsets_small(
     // column tiles per task: the fewest (a power of two up to gram_qmax) whose
     // tasks fit in the work kernel's waves, else the most (workgroup uniform)
     int qi = 0;
+    while (qi + 1 < kGramTileSteps && (2 << qi) <= min(kGramQMin, gram_qmax))
+        ++qi;
     while (qi + 1 < kGramTileSteps && (2 << qi) <= gram_qmax && stot[1 + qi] > gram_nwaves)
         ++qi;
     const int Q = 1 << qi;

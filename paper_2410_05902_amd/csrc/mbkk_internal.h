@@ -32,6 +32,10 @@ constexpr int kNumCU = 256;
 constexpr int kDirectWGs = 2048;  // workgroups of the direct (VALU) cross kernel: ranges x row tiles (8 waves per SIMD)
 constexpr int kSnSplit = 64;      // workgroups per center of the self norms at a bandwidth (differentiation form)
 constexpr int kGramWaves = 5120;  // waves of the VALU Gram work kernel and the self norms at a bandwidth (5 per SIMD)
+// fewest column tiles per task of the MFMA Gram form (the plan raises it to
+// fit the waves): a task loads its slot rows once for all its tiles, and a
+// compute unit's L1 traffic bounds the Gram work more than the task count
+constexpr int kGramQMin = 4;
 constexpr int kGramWavesMfma = 5120;  // waves of the MFMA Gram work kernel (5 per SIMD: its occupancy)
 
 // Physical slots of the live batches, oldest batch first.
