@@ -196,35 +196,81 @@ __device__ __forceinline__ void gram_mfma_work(const GramWork &A, int dp_rt, int
             for (int q = 0; q < NS; ++q)
                 av[q] = *(const f32x4 *)(sa + 16 * q);
         }
-        for (int tile = tile0; tile < tile1; ++tile) {
-            if (tile != tile0) {
-                qe = tile * 16 + n;
-                pe = ep[min(qe, ec.n - 1)];
-            }
-            const int64_t re = qe < ec.n ? (ec.perm ? ec.row0 + pe : ec.row0) : zero_row;
-            const float sqe_v = poolsq[re];
-            const float *se = pool32 + re * dp + 4 * g;
-            f32x4 acc;
+        // lane: column n (column row), rows m = 4 g + i (slot rows); the
+        // row norms were written by this wave (in-order LDS access) and are
+        // read as one 16-byte load; rows past the cluster add an exact 0 (the
+        // sum is positive, so no sign of zero changes)
+        auto tile_sum = [&](int tile, const f32x4 &acc, float sqe_v) {
+            const int qe_t = tile * 16 + n;
+            if (tile == tile0 && g == 0)
+                sqa[wl][n] = c1 * sqa_v;  // slot row n's norm for the output rows m, once per task
+            const float se_ = c1 * sqe_v;
+            if (qe_t < ec.n) {
+                const f32x4 sq4 = *(const f32x4 *)&sqa[wl][4 * g];
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                acc[i] = 0.0f;
-            if constexpr (DP > 0) {
-                // the tile's coordinates are all loaded before its first product
-                f32x4 ev[NS];
+                for (int i = 0; i < 4; ++i) {
+                    const int m = 4 * g + i;
+                    const double t = (double)__builtin_amdgcn_exp2f(fmaf(acc[i], c2, sq4[i] + se_));
+                    lsum += ab * 16 + m < a.n ? t : 0.0;
+                }
+            }
+        };
+        auto col_row = [&](int tile, int32_t pe_t) -> int64_t {
+            const int qe_t = tile * 16 + n;
+            return qe_t < ec.n ? (ec.perm ? ec.row0 + pe_t : ec.row0) : zero_row;
+        };
+        if constexpr (DP > 0) {
+            // every tile's permutation entry at the start, then each tile's
+            // rows requested before the previous tile's products (clamped
+            // to the last tile, which then loads its rows twice)
+            constexpr int QX = 1 << (kGramTileSteps - 1);
+            int32_t pes[QX];
+            pes[0] = pe;
+#pragma unroll
+            for (int q = 1; q < QX; ++q)
+                pes[q] = ep[min(min(tile0 + q, tile1 - 1) * 16 + n, ec.n - 1)];
+            int64_t re = col_row(tile0, pes[0]);
+            float sqe_v = poolsq[re];
+            f32x4 ev[NS];
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+                ev[q] = *(const f32x4 *)(pool32 + re * dp + 4 * g + 16 * q);
+#pragma unroll
+            for (int t = 0; t < QX; ++t) {
+                const int tile = tile0 + t;
+                if (tile >= tile1)
+                    break;  // wave uniform
+                const int tn = min(tile + 1, tile1 - 1);
+                const int64_t rn = col_row(tn, pes[t + 1 < QX ? t + 1 : t]);
+                const float sqn = poolsq[rn];
+                f32x4 en[NS];
 #pragma unroll
                 for (int q = 0; q < NS; ++q)
-                    ev[q] = *(const f32x4 *)(se + 16 * q);
-                __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the products
+                    en[q] = *(const f32x4 *)(pool32 + rn * dp + 4 * g + 16 * q);
                 // the slot row's norm is needed by this point (the products
-                // wait for the later row loads anyway), so its load is not
-                // sunk into the branch that publishes it below
+                // wait for the row loads anyway), so its load is not sunk into
+                // the branch that publishes it
                 asm volatile("" ::"v"(sqa_v));
+                f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
                 for (int q = 0; q < NS; ++q)
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
                         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[q][u], ev[q][u], acc, 0, 0, 0);
-            } else {
+                tile_sum(tile, acc, sqe_v);
+#pragma unroll
+                for (int q = 0; q < NS; ++q)
+                    ev[q] = en[q];
+                sqe_v = sqn;
+            }
+        } else {
+            for (int tile = tile0; tile < tile1; ++tile) {
+                if (tile != tile0)
+                    pe = ep[min(tile * 16 + n, ec.n - 1)];
+                const int64_t re = col_row(tile, pe);
+                const float sqe_v = poolsq[re];
+                const float *se = pool32 + re * dp + 4 * g;
+                f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
                 // row stride at run time: 8 steps of 4 coordinates per round
                 // of loads, all in flight before their products (clamped
                 // indices; the steps past the row skip their products)
@@ -245,24 +291,7 @@ __device__ __forceinline__ void gram_mfma_work(const GramWork &A, int dp_rt, int
                             for (int u = 0; u < 4; ++u)
                                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[q][u], e4[q][u], acc, 0, 0, 0);
                 }
-            }
-            // lane n (g = 0) publishes the norm of slot row n for the output
-            // rows m, once per task
-            if (tile == tile0 && g == 0)
-                sqa[wl][n] = c1 * sqa_v;
-            const float se_ = c1 * sqe_v;
-            // lane: column n (column row), rows m = 4 g + i (slot rows); the
-            // row norms were written by this wave (in-order LDS access) and
-            // are read as one 16-byte load; rows past the cluster add an
-            // exact 0 (the sum is positive, so no sign of zero changes)
-            if (qe < ec.n) {
-                const f32x4 sq4 = *(const f32x4 *)&sqa[wl][4 * g];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int m = 4 * g + i;
-                    const double t = (double)__builtin_amdgcn_exp2f(fmaf(acc[i], c2, sq4[i] + se_));
-                    lsum += ab * 16 + m < a.n ? t : 0.0;
-                }
+                tile_sum(tile, acc, sqe_v);
             }
         }
     });
