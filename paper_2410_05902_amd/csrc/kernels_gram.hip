@@ -139,8 +139,8 @@ __global__ __launch_bounds__(kGramWG) void k_gram_valu(const GramWork A, int d, 
 // MFMA tasks (Gaussian): gram_mfma_work, 5 waves per SIMD.
 template <int DP>
 // (fixed row stride: a task's next column tile is loaded during the current
-// one's products, and the registers allow 3 waves per SIMD; the tasks seldom
-// fill more, since a task takes at least 4 tiles)
+// one's products, so the register budget asks only for 3 waves per SIMD; the
+// tasks seldom fill more, since a task takes at least 4 tiles)
 __global__ __launch_bounds__(kGramWG) __attribute__((amdgpu_waves_per_eu(DP > 0 ? 3 : 5))) void k_gram_mfma(
     const GramWork A, int dp_rt, int zero_row, const float *__restrict__ pool32, const float *__restrict__ poolsq,
     float c2, float c1)
