@@ -152,10 +152,10 @@ __device__ __forceinline__ void gram_wave_loop(const GramWork &A, int32_t *stage
 // ---------------------------------------------------------------------------
 // MFMA tasks (Gaussian): exp(-(||a||^2 + ||e||^2 - 2 a.e) / kappa) with a.e
 // on FP32 MFMA 16x16x4 (every MFMA form, the BF16 ones included): a task is
-// 16 slot rows by Q tiles of 16 column rows (the plan's Q: 1 unless the
-// tasks would outnumber the waves), so a cluster of b_j rows pads to a
-// multiple of 16 rather than 32, and a large one loads its slot rows once
-// for up to 8 tiles.  Lane l = 16 g + n supplies
+// 16 slot rows by Q tiles of 16 column rows (the plan's Q: at least 4, more
+// when the tasks would outnumber the waves), so a cluster of b_j rows pads
+// to a multiple of 16 rather than 32, and a task loads its slot rows once
+// for all its tiles.  Lane l = 16 g + n supplies
 // A[n][g] (slot row n) and B[g][n] (column row n); the u-th MFMA of step t
 // takes coordinate 16 t + 4 g + u, so one 16-byte load per lane and step
 // serves four MFMAs and the four lanes of a row read 64 contiguous bytes
@@ -183,8 +183,7 @@ __device__ __forceinline__ void gram_mfma_work(const GramWork &A, int dp_rt, int
         // and one row)
         const int32_t *ep = ec.perm ? ec.perm : a.perm;
         const int32_t pa = a.perm[min(qa, a.n - 1)];
-        int qe = tile0 * 16 + n;
-        int32_t pe = ep[min(qe, ec.n - 1)];
+        int32_t pe = ep[min(tile0 * 16 + n, ec.n - 1)];
         const int64_t ra = qa < a.n ? a.row0 + pa : zero_row;
         const float sqa_v = poolsq[ra];
         const float *sa = pool32 + ra * dp + 4 * g;
