@@ -690,6 +690,35 @@ void launch_prepare(const Layout &L, const Buffers &B, bool with_support, const 
 // LDS variant (per-chunk counts held in LDS) when nchunk * k is at most this.
 constexpr int kGroupLdsMax = 8192;
 
+// For the variant with counts in global memory: per label j (one thread
+// each, over as many workgroups as the labels need), the exclusive prefix of
+// its counts over the chunks, in gbase (the base of (chunk, label) within the
+// label), and its total b_j in counts.  The chunk loads of a thread are issued
+// kLabelU at a time; consecutive threads read consecutive labels.
+constexpr int kLabelU = 32;
+__global__ __launch_bounds__(64) void k_label_bases(int k, int nchunk, const int32_t *__restrict__ gcnt,
+                                                     int32_t *__restrict__ gbase, int32_t *__restrict__ counts)
+{
+    const int j = blockIdx.x * 64 + threadIdx.x;
+    if (j >= k)
+        return;
+    int run = 0;
+    for (int g0 = 0; g0 < nchunk; g0 += kLabelU) {
+        int c[kLabelU];
+#pragma unroll
+        for (int u = 0; u < kLabelU; ++u)
+            c[u] = gcnt[(int64_t)min(g0 + u, nchunk - 1) * k + j];
+#pragma unroll
+        for (int u = 0; u < kLabelU; ++u) {
+            if (g0 + u < nchunk) {
+                gbase[(int64_t)(g0 + u) * k + j] = run;
+                run += c[u];
+            }
+        }
+    }
+    counts[j] = run;
+}
+
 template <bool LDS>
 __global__ __launch_bounds__(1024) void k_group_offsets(
     int b, int k, int nchunk, int C, int p_new, int p_expired, int init_alive_before, int init_keep,
@@ -730,24 +759,35 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
     const int per = (k + nt - 1) / nt;
     const int j0 = tid * per, j1 = min(k, j0 + per);
     // totals of this thread's labels, block-wide exclusive scan -> offsets
+    // (counts in global memory: k_label_bases has put the totals in counts
+    // and the bases within each label in gbase)
     int local = 0;
     for (int j = j0; j < j1; ++j) {
+        if constexpr (LDS) {
 #pragma unroll 8
-        for (int g = 0; g < nchunk; ++g)
-            local += cnt[(int64_t)g * k + j];
+            for (int g = 0; g < nchunk; ++g)
+                local += cnt[(int64_t)g * k + j];
+        } else {
+            local += counts[j];
+        }
     }
     int total;
     int run = block_exclusive_scan(local, sint, &total);
     for (int j = j0; j < j1; ++j) {
         off[j] = run;
-        int gb = run;
+        int bj;
+        if constexpr (LDS) {
+            int gb = run;
 #pragma unroll 8
-        for (int g = 0; g < nchunk; ++g) {
-            base[(int64_t)g * k + j] = gb;  // base of label j in chunk g
-            gb += cnt[(int64_t)g * k + j];
+            for (int g = 0; g < nchunk; ++g) {
+                base[(int64_t)g * k + j] = gb;  // base of label j in chunk g
+                gb += cnt[(int64_t)g * k + j];
+            }
+            bj = gb - run;
+        } else {
+            bj = counts[j];
         }
-        const int bj = gb - run;
-        run = gb;
+        run += bj;
         counts[j] = bj;
         double a;
         if (lr == MBKK_LR_FULL)
@@ -806,7 +846,7 @@ __global__ __launch_bounds__(1024) void k_group_offsets(
     // scatter: grouped position of every row = base of (chunk, label) + rank
     for (int p = tid; p < b; p += nt) {
         const int lab = min(max(labels[p], 0), k - 1);
-        const int pos = base[(int64_t)(p / kChunk) * k + lab] + rank[p];
+        const int pos = base[(int64_t)(p / kChunk) * k + lab] + (LDS ? 0 : off[lab]) + rank[p];
         ring_perm[pos] = p;
         ring_idx[pos] = pts[p];
     }
@@ -1126,8 +1166,11 @@ void launch_update(const Layout &L, const Buffers &B, int b, int p_new, int p_ex
                            gram_nwaves, B.ring_off, B.goff, L.pad, (int)L.packed, B.seg_next);
     else if ((int64_t)nchunk * L.k <= kGroupLdsMax)
         MBKK_GO(true);
-    else
+    else {
+        hipLaunchKernelGGL(k_label_bases, dim3((unsigned)((L.k + 63) / 64)), dim3(64), 0, st, L.k, nchunk, B.gcnt,
+                           B.gbase, B.counts);
         MBKK_GO(false);
+    }
 #undef MBKK_GO
 }
 
